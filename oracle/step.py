@@ -1,0 +1,404 @@
+"""Oracle time step: the inner projective-dynamics iteration with subspace
+reuse, the non-distance barrier and partial CCD, and the per-block full CCD
+filter, in FP64 on the CPU (TEST INFRASTRUCTURE ONLY).
+
+Paper passages followed, in the order the step takes them:
+  * predictor z = x* + h v* + h^2 g ............................ Eq. (z)
+  * initial full CCD and filter on (x*, z) .............. Algorithm 1 (start)
+  * per outer block, I inner iterations of:
+      local step: triangle strain projection, hinge bending target,
+        collision targets weighted by w = k K^a (K = 2) ... Eq. (local), (exp)
+      residual r0 = b - (H + diag W) x ....................... Eq. (global)
+      subspace reuse (Lambda~ + U^T diag W U) q = U^T r0,
+        x~ = x + U q ......... Eq. (subspace_collision), Eq. (uu), section 5.1
+      Jacobi sweep on the residual of x~ ..... Eq. (high_frequency_residual)
+        with Chebyshev acceleration (the semi-iterative weights of Wang 2015)
+      partial CCD on (x-, x^{k+1}) -> life spans a_p ....... Eq. (query)
+    then full CCD on (x-, x+), constraint set update and the filter
+      x = x- + s (x+ - x-), s = alpha t_TOI or 1 ......... section 6, 7
+  * v = (x - x*) / h.
+
+Readings where the paper is silent are listed in the repository's design
+notes (strain model, collision target, life-span cap, sample set, filter).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import native
+from .model import Model
+
+NO_HIT = 2.0
+VT_SAMPLES = np.array([[1 / 6, 1 / 6], [2 / 3, 1 / 6], [1 / 6, 2 / 3]])
+EE_SAMPLES = np.array([[0.25, 0.25], [0.5, 0.5], [0.75, 0.75]])
+
+
+@dataclass
+class Params:
+    iters_outer: int
+    iters_inner: int
+    cheb_rho: float
+    cheb_gamma: float = 1.0
+    cheb_delay: int = 3
+    d_hat: float = 1e-3
+    alpha: float = 0.8
+    K_base: float = 2.0
+    a_max: int = 20
+    self_contact: bool = True
+
+
+@dataclass
+class Obst:
+    kind: int          # 0 sphere, 1 cylinder (infinite along its axis)
+    center: np.ndarray
+    radius: float
+    axis: np.ndarray
+
+
+@dataclass
+class Constraints:
+    """Constraint set C of one outer block (sorted lists, life spans a)."""
+    vt: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))
+    ee: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))
+    ob: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))  # (vertex, obstacle)
+    a_vt: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    a_ee: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    a_ob: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    # frozen at x- of the block
+    lam_vt: np.ndarray = None
+    n_vt: np.ndarray = None
+    lam_ee: np.ndarray = None
+    n_ee: np.ndarray = None
+
+
+@dataclass
+class StepStats:
+    dx: List[float] = field(default_factory=list)
+    min_toi: float = NO_HIT
+    n_candidates: int = 0
+    n_constraints: int = 0
+    fallbacks: int = 0
+
+
+def chebyshev_weights(n: int, rho: float, delay: int) -> np.ndarray:
+    """omega_{k+1} for k = 0..n-1: 1 before the delay S, 2/(2 - rho^2) at S,
+    then 4/(4 - rho^2 omega_k)."""
+    w = np.ones(n)
+    for k in range(n):
+        if k < delay:
+            w[k] = 1.0
+        elif k == delay:
+            w[k] = 2.0 / (2.0 - rho * rho)
+        else:
+            w[k] = 4.0 / (4.0 - rho * rho * w[k - 1])
+    return w
+
+
+def polar_3x2(F: np.ndarray) -> np.ndarray:
+    """Closest matrix with orthonormal columns to each 3x2 F (rows of a
+    stack): T = F (F^T F)^{-1/2}, with the 2x2 square root in closed form
+    sqrt(S) = (S + sqrt(det S) I) / sqrt(tr S + 2 sqrt(det S)).
+    Near-degenerate F (det S <= 1e-20) is returned unchanged."""
+    S = np.einsum("tdi,tdj->tij", F, F)
+    det = S[:, 0, 0] * S[:, 1, 1] - S[:, 0, 1] * S[:, 1, 0]
+    ok = det > 1e-20
+    sd = np.sqrt(np.where(ok, det, 1.0))
+    den = np.sqrt(S[:, 0, 0] + S[:, 1, 1] + 2 * sd)
+    R = (S + sd[:, None, None] * np.eye(2)) / den[:, None, None]
+    detR = sd  # det sqrt(S) = sqrt(det S)
+    Rinv = np.empty_like(R)
+    Rinv[:, 0, 0] = R[:, 1, 1] / detR
+    Rinv[:, 1, 1] = R[:, 0, 0] / detR
+    Rinv[:, 0, 1] = -R[:, 0, 1] / detR
+    Rinv[:, 1, 0] = -R[:, 1, 0] / detR
+    T = np.einsum("tdi,tij->tdj", F, Rinv)
+    T[~ok] = F[~ok]
+    return T
+
+
+def elastic_rhs(model: Model, x: np.ndarray) -> np.ndarray:
+    """sum_t w_t G_t^T T_t^T + sum_e w_e K_e y_e (local step, Eq. (local)) as
+    a per-vertex 3-vector."""
+    xs = x[model.tris]                                      # (T,3,3) corners x xyz
+    F = np.einsum("tcd,tci->tdi", xs, model.g)              # (T,3,2)
+    T = polar_3x2(F)
+    contrib = np.einsum("tdi,tci->tcd", T, model.g) * model.w_tri[:, None, None]
+    rhs = np.zeros_like(x)
+    np.add.at(rhs, model.tris.ravel(), contrib.reshape(-1, 3))
+    curved = model.rest_bend > 0
+    if curved.any():
+        hg = model.hinges[curved]
+        K = model.K[curved]
+        s = np.einsum("ek,ekd->ed", K, x[hg])
+        sn = np.linalg.norm(s, axis=1)
+        y = np.where(sn[:, None] > 0, s * (model.rest_bend[curved] / np.where(sn > 0, sn, 1))[:, None], 0)
+        c = K[:, :, None] * (model.w_hinge[curved][:, None] * 1.0)[:, :, None] * y[:, None, :]
+        np.add.at(rhs, hg.ravel(), c.reshape(-1, 3))
+    return rhs
+
+
+def query_vt(xm, xp, v, tri, lam):
+    """Q(lambda) = (p2^1(lambda) - p1^1) . (p2^0(lambda) - p1^0), Eq. (query),
+    for a vertex p1 = x_v and the triangle point p2 = x1 + l1 (x2-x1) + l2 (x3-x1);
+    lam has shape (P, S, 2); returns (P, S)."""
+    def p2(x):
+        a, b, c = x[tri[:, 0]], x[tri[:, 1]], x[tri[:, 2]]
+        return a[:, None] + lam[..., :1] * (b - a)[:, None] + lam[..., 1:] * (c - a)[:, None]
+    return np.einsum("psd,psd->ps", p2(xp) - xp[v][:, None], p2(xm) - xm[v][:, None])
+
+
+def query_ee(xm, xp, e1, e2, lam):
+    """Q(lambda) for edges p1 = x1 + l1 (x2 - x1), p2 = x3 + l2 (x4 - x3)."""
+    def diff(x):
+        p1 = x[e1[:, 0]][:, None] + lam[..., :1] * (x[e1[:, 1]] - x[e1[:, 0]])[:, None]
+        p2 = x[e2[:, 0]][:, None] + lam[..., 1:] * (x[e2[:, 1]] - x[e2[:, 0]])[:, None]
+        return p2 - p1
+    return np.einsum("psd,psd->ps", diff(xp), diff(xm))
+
+
+def obstacle_phi(ob: Obst, x: np.ndarray):
+    """Signed distance to the obstacle surface and the radial vector used by
+    the projection (sphere: x - c; cylinder: its component normal to the axis)."""
+    o = x - ob.center
+    if ob.kind == 1:
+        o = o - np.outer(o @ ob.axis, ob.axis)
+    rad = np.linalg.norm(o, axis=1)
+    return rad - ob.radius, o, rad
+
+
+def obstacle_toi(ob: Obst, xm: np.ndarray, xp: np.ndarray) -> np.ndarray:
+    """Entering root in [0,1] of |radial(x- + t (x+ - x-))| = R; NO_HIT for
+    vertices already inside or never reaching the surface."""
+    d = xp - xm
+    o = xm - ob.center
+    if ob.kind == 1:
+        d = d - np.outer(d @ ob.axis, ob.axis)
+        o = o - np.outer(o @ ob.axis, ob.axis)
+    a = np.einsum("ij,ij->i", d, d)
+    b = 2 * np.einsum("ij,ij->i", o, d)
+    c = np.einsum("ij,ij->i", o, o) - ob.radius ** 2
+    disc = b * b - 4 * a * c
+    toi = np.full(xm.shape[0], NO_HIT)
+    ok = (c > 0) & (b < 0) & (disc >= 0) & (a > 0)
+    q = 0.5 * (-b[ok] + np.sqrt(disc[ok]))
+    t = c[ok] / q
+    t = np.where(t <= 1.0, t, NO_HIT)
+    toi[ok] = t
+    return toi
+
+
+class Oracle:
+    """FP64 reference solver for one scene; state is (x, v)."""
+
+    def __init__(self, model: Model, Us: np.ndarray, params: Params, gravity,
+                 obstacles: Optional[List[Obst]] = None):
+        self.m = model
+        self.U = np.asarray(Us, np.float64)
+        self.p = params
+        self.g = np.asarray(gravity, np.float64)
+        self.obs = obstacles or []
+        self.Lam = self.U.T @ (model.H @ self.U)
+        self.x = model.rest.copy()
+        self.v = np.zeros_like(self.x)
+        self.free = ~model.pinned
+        self.pin_pos = model.rest.copy()
+        self.omega = chebyshev_weights(max(params.iters_inner, 1), params.cheb_rho,
+                                       params.cheb_delay)
+        self.last = StepStats()
+
+    # ---- state
+    def set_state(self, x, v):
+        self.x = np.array(x, np.float64)
+        self.v = np.array(v, np.float64)
+        self.pin_pos = self.x.copy()
+
+    # ---- constraint bookkeeping
+    def _weights(self, a: np.ndarray) -> np.ndarray:
+        return np.ldexp(self.m.k_contact, a.astype(np.int64)) if self.p.K_base == 2.0 else \
+            self.m.k_contact * self.p.K_base ** a
+
+    def _collision_terms(self, C: Constraints, x: np.ndarray):
+        """Per-vertex W = sum w_p and WY = sum w_p y_{p,v} over constraints.
+        VT/EE: half-space projection with the normal and closest-point
+        parameters frozen at x-; obstacles: projection onto the surface offset
+        by d_hat."""
+        nv = self.m.nv
+        W = np.zeros(nv)
+        WY = np.zeros((nv, 3))
+        dh = self.p.d_hat
+        mov = self.free.astype(np.float64)
+        if len(C.vt):
+            tri = self.m.tris[C.vt[:, 1]]
+            ids = np.concatenate([C.vt[:, :1], tri], axis=1)          # (P,4)
+            l1, l2 = C.lam_vt[:, 0], C.lam_vt[:, 1]
+            coef = np.stack([np.ones_like(l1), -(1 - l1 - l2), -l1, -l2], 1)
+            self._half_space(ids, coef, C.n_vt, self._weights(C.a_vt), x, mov, dh, W, WY)
+        if len(C.ee):
+            ids = np.concatenate([self.m.edges[C.ee[:, 0]], self.m.edges[C.ee[:, 1]]], axis=1)
+            s, t = C.lam_ee[:, 0], C.lam_ee[:, 1]
+            coef = np.stack([-(1 - s), -s, 1 - t, t], 1)
+            self._half_space(ids, coef, C.n_ee, self._weights(C.a_ee), x, mov, dh, W, WY)
+        if len(C.ob):
+            w = self._weights(C.a_ob)
+            for j, ob in enumerate(self.obs):
+                sel = C.ob[:, 1] == j
+                if not sel.any():
+                    continue
+                v = C.ob[sel, 0]
+                phi, o, rad = obstacle_phi(ob, x[v])
+                y = x[v].copy()
+                inside = (phi < dh) & (rad > 0)
+                y[inside] = x[v][inside] - o[inside] + \
+                    o[inside] * ((ob.radius + dh) / rad[inside])[:, None]
+                np.add.at(W, v, w[sel])
+                np.add.at(WY, v, w[sel][:, None] * y)
+        return W, WY
+
+    @staticmethod
+    def _half_space(ids, coef, nrm, w, x, mov, dh, W, WY):
+        # g(y) = sum_k c_k n . y_k - d_hat >= 0; minimum-norm correction over movable vertices
+        cm = coef * mov[ids]
+        gx = np.einsum("pk,pkd,pd->p", coef, x[ids], nrm) - dh
+        den = np.einsum("pk,pk->p", cm, cm)
+        delta = np.where((gx < 0) & (den > 0), -gx / np.where(den > 0, den, 1.0), 0.0)
+        y = x[ids] + cm[:, :, None] * delta[:, None, None] * nrm[:, None, :]
+        np.add.at(W, ids.ravel(), np.repeat(w, 4))
+        np.add.at(WY, ids.ravel(), (w[:, None, None] * y).reshape(-1, 3))
+
+    def _partial_ccd(self, C: Constraints, xm: np.ndarray, xp: np.ndarray):
+        """Life-span update a <- active ? min(a+1, a_max) : 0, active when
+        Q(lambda) <= 0 at some sample (Eq. (query)); obstacles: active when
+        the end position is closer than d_hat."""
+        amax = self.p.a_max
+        if len(C.vt):
+            lam = np.concatenate([np.broadcast_to(VT_SAMPLES, (len(C.vt), 3, 2)),
+                                  C.lam_vt[:, None, :]], axis=1)          # (P,4,2)
+            Q = query_vt(xm, xp, C.vt[:, 0], self.m.tris[C.vt[:, 1]], lam)
+            act = (Q <= 0).any(1)
+            C.a_vt = np.where(act, np.minimum(C.a_vt + 1, amax), 0).astype(np.int32)
+        if len(C.ee):
+            lam = np.concatenate([np.broadcast_to(EE_SAMPLES, (len(C.ee), 3, 2)),
+                                  C.lam_ee[:, None, :]], axis=1)
+            Q = query_ee(xm, xp, self.m.edges[C.ee[:, 0]], self.m.edges[C.ee[:, 1]], lam)
+            act = (Q <= 0).any(1)
+            C.a_ee = np.where(act, np.minimum(C.a_ee + 1, amax), 0).astype(np.int32)
+        if len(C.ob):
+            act = np.zeros(len(C.ob), bool)
+            for j, ob in enumerate(self.obs):
+                sel = C.ob[:, 1] == j
+                phi, _, _ = obstacle_phi(ob, xp[C.ob[sel, 0]])
+                act[sel] = phi < self.p.d_hat
+            C.a_ob = np.where(act, np.minimum(C.a_ob + 1, amax), 0).astype(np.int32)
+
+    def _outer_ccd(self, xm: np.ndarray, xp: np.ndarray, prev: Constraints, st: StepStats):
+        """Broad phase + full CCD on (x-, x+): returns (s, new constraint set).
+        C_o = {candidates with TOI <= 1} U (C_{o-1} intersect candidates);
+        surviving entries keep their life span, new ones start at 0."""
+        m = self.m
+        xm32 = xm.astype(np.float32)
+        xp32 = xp.astype(np.float32)
+        vt, ee = native.broad_phase(xm32, xp32, m.edges, m.tris, self.p.d_hat, self.p.self_contact)
+        tv, te, nf = native.toi_pairs(xm, xp, m.tris, m.edges, vt, ee)
+        st.fallbacks += nf
+        st.n_candidates = len(vt) + len(ee)
+        tmin = min(tv.min(initial=NO_HIT), te.min(initial=NO_HIT))
+        C = Constraints()
+        C.vt, C.a_vt = _merge(vt, tv <= 1.0, prev.vt, prev.a_vt)
+        C.ee, C.a_ee = _merge(ee, te <= 1.0, prev.ee, prev.a_ee)
+        obs_rows = []
+        for j, ob in enumerate(self.obs):
+            toi = obstacle_toi(ob, xm, xp)
+            tmin = min(tmin, toi.min(initial=NO_HIT))
+            phim, _, _ = obstacle_phi(ob, xm)
+            phip, _, _ = obstacle_phi(ob, xp)
+            mem = (toi <= 1.0) | (phim < self.p.d_hat) | (phip < self.p.d_hat)
+            mem &= self.free
+            v = np.flatnonzero(mem).astype(np.int32)
+            obs_rows.append(np.stack([v, np.full_like(v, j)], 1))
+        ob = np.concatenate(obs_rows) if obs_rows else np.zeros((0, 2), np.int32)
+        ob = ob[np.lexsort((ob[:, 1], ob[:, 0]))] if len(ob) else ob
+        cand_ob = np.ones(len(ob), bool)
+        C.ob, C.a_ob = _merge(ob, cand_ob, prev.ob, prev.a_ob)
+        st.min_toi = min(st.min_toi, tmin)
+        s = 1.0 if tmin > 1.0 else self.p.alpha * tmin
+        return s, C
+
+    def _freeze(self, C: Constraints, xm: np.ndarray):
+        C.lam_vt, C.n_vt = native.frozen_vt(xm, self.m.tris, C.vt)
+        C.lam_ee, C.n_ee = native.frozen_ee(xm, self.m.edges, C.ee)
+
+    # ---- one implicit step
+    def step(self) -> StepStats:
+        m, p = self.m, self.p
+        h = m.h
+        st = StepStats()
+        xs = self.x
+        z = xs + h * self.v + h * h * self.g
+        z[m.pinned] = self.pin_pos[m.pinned]
+        xm = xs.copy()
+        s, C = self._outer_ccd(xm, z, Constraints(), st)
+        x = xm + s * (z - xm)
+        xm = x.copy()
+        self._freeze(C, xm)
+        inertia = (m.mass / (h * h))[:, None] * z
+        for o in range(p.iters_outer):
+            xk = x.copy()
+            xkm1 = x.copy()
+            for k in range(p.iters_inner):
+                xk1 = self.iterate(xk, xkm1, k, C, inertia, xm)
+                self._partial_ccd(C, xm, xk1)
+                st.dx.append(float(np.linalg.norm(xk1 - xk, axis=1).max()))
+                xkm1, xk = xk, xk1
+            xp = xk
+            s, C = self._outer_ccd(xm, xp, C, st)
+            x = xm + s * (xp - xm)
+            xm = x.copy()
+            self._freeze(C, xm)
+        st.n_constraints = len(C.vt) + len(C.ee) + len(C.ob)
+        self.v = (x - xs) / h
+        self.x = x
+        self.last = st
+        return st
+
+    def iterate(self, xk, xkm1, k, C, inertia, xm, frozen=None):
+        """One inner PD iteration from x^k (history x^{k-1}) -> x^{k+1}.
+        `frozen` = (b, W) replaces the local step by a fixed right-hand side
+        and diagonal (used to check the global solve on its own)."""
+        m, p = self.m, self.p
+        free = self.free
+        if frozen is None:
+            W, WY = self._collision_terms(C, xk)
+            b = inertia + elastic_rhs(m, xk) + WY
+        else:
+            b, W = frozen
+        r0 = b - m.H @ xk - W[:, None] * xk
+        r0[~free] = 0
+        g = self.U.T @ r0
+        A = self.Lam + self.U.T @ (W[:, None] * self.U)
+        Q = sla.cho_solve(sla.cho_factor(A), g)
+        xt = xk + self.U @ Q
+        r1 = b - m.H @ xt - W[:, None] * xt
+        r1[~free] = 0
+        xhat = xt + r1 / (m.diagH + W)[:, None]
+        om = self.omega[min(k, len(self.omega) - 1)]
+        self.trace = dict(r0=r0, g=g, A=A, Q=Q, xt=xt, r1=r1, xhat=xhat, b=b, W=W)
+        return om * (p.cheb_gamma * (xhat - xk) + xk - xkm1) + xkm1
+
+
+def _merge(cand: np.ndarray, hit: np.ndarray, prev: np.ndarray, prev_a: np.ndarray):
+    """Rows of `cand` (sorted) kept when hit or present in `prev`; life spans
+    carried over from `prev`, 0 for new rows."""
+    if len(cand) == 0:
+        return np.zeros((0, 2), np.int32), np.zeros(0, np.int32)
+    key = cand[:, 0].astype(np.int64) * (1 << 31) + cand[:, 1]
+    pkey = prev[:, 0].astype(np.int64) * (1 << 31) + prev[:, 1] if len(prev) else np.zeros(0, np.int64)
+    pos = np.searchsorted(pkey, key)
+    pos_c = np.minimum(pos, max(len(pkey) - 1, 0))
+    inprev = (len(pkey) > 0) & (pkey[pos_c] == key) if len(pkey) else np.zeros(len(key), bool)
+    keep = hit | inprev
+    a = np.where(inprev, prev_a[pos_c] if len(pkey) else 0, 0)
+    return cand[keep].astype(np.int32), a[keep].astype(np.int32)
