@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the projective-dynamics cloth step on one MI355X.
+
+Workload (default): the 600 x 600-vertex cloth (360,000 vertices, 717,602
+triangles) dropped 0.3 m onto a horizontal cylinder spinning at 2 rad/s,
+self contact on, dt = 1/200 s, 3 outer blocks x 10 inner PD iterations per
+step, BF16 basis (r = 128) with FP32 local step / SpMV and FP64 reduced
+solve, 200 steps.  Synthetic, seeded input (scenegen.config(2)).
+
+Metric: vertex-iterations per second = vertices x inner iterations x steps /
+wall time of the timed steps (inputs resident in HBM).  Also reported:
+p50/p99 per-step GPU time, the dominant kernel's achieved bandwidth against
+the HBM roofline (HIP events around its launches in a second, instrumented
+pass over the same steps), and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "vertex-iters/s on 360K-vert cloth (plain FP32 vs mixed/batched); p50/p99 step ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_gpu_scene(sc, precision, P, basis_mod):
+    prec = P.CLOTH_MIXED if precision == "mixed" else P.CLOTH_PLAIN_FP32
+    g = P.ClothScene(sc.tris, sc.rest, dt=sc.dt, density=sc.density, k_stretch=sc.k_stretch,
+                     k_bend=sc.k_bend, k_contact=0.0, d_hat=sc.d_hat, pinned=sc.pinned, r=sc.r,
+                     iters_inner=sc.iters_inner, iters_outer=sc.iters_outer, cheb_rho=0.0,
+                     cheb_gamma=0.0, cheb_delay=3, precision=prec, self_contact=sc.self_contact,
+                     arena="torch")
+    for ob in sc.obstacles:
+        g.add_obstacle(ob.kind, ob.center, ob.radius, axis=ob.axis, half_length=ob.half_length,
+                       omega=ob.omega)
+    return g
+
+
+def kernel_bytes(name, sc, nnz, ubytes, contact):
+    """Algorithmic bytes one launch moves: every array the kernel reads or
+    writes counted once (neighbour gathers count as cache hits)."""
+    N, T, r = sc.nv, sc.nt, sc.r
+    nblk = (N + 255) // 256
+    csr = 4 * (N + 1) + 8 * nnz
+    if name == "local_residual":
+        b = 12 * N + 4 * N + 4 * (N + 1) + 12 * T + 32 * T + 12 * N + csr + N + N * r * ubytes
+        b += 12 * N + nblk * r * 3 * 4
+        if contact:
+            b += 4 * (N + 1) + 4 * N * len(sc.obstacles) + 4 * N
+        return b
+    if name == "expand":
+        return N * r * ubytes + 12 * N + 12 * N
+    if name == "jacobi_cheb":
+        b = 12 * N * 3 + N + csr + 4 * N + 12 * N + 12 * N
+        if contact:
+            b += 4 * N
+        return b
+    return None
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash(d.get("sources", [])):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sc, iters):
+    """The FP64 oracle as it stands, on one step of the same workload cut to
+    one outer block of `iters` inner iterations (with its two CCD stages)."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import model as M
+    from oracle import step as S
+    t0 = time.time()
+    m = M.build_model(sc.tris, sc.rest, sc.pinned, sc.dt, sc.density, sc.k_stretch, sc.k_bend)
+    rng = np.random.default_rng(0)
+    # the timed work does not depend on the basis values: a seeded orthonormal
+    # basis of the workload's width stands in for the eigenvectors here
+    U, _ = np.linalg.qr(rng.standard_normal((sc.nv, sc.r)))
+    Us = M.stored_basis(U, sc.precision)
+    p = S.Params(iters_outer=1, iters_inner=iters, cheb_rho=0.95, cheb_gamma=0.9, cheb_delay=3,
+                 d_hat=sc.d_hat, self_contact=sc.self_contact)
+    obs = [S.Obst(o.kind, np.array(o.center, float), o.radius, np.array(o.axis, float))
+           for o in sc.obstacles]
+    o = S.Oracle(m, Us, p, sc.gravity, obs)
+    o.set_state(sc.x0, sc.v0)
+    log(f"cpu oracle set-up {time.time() - t0:.1f}s")
+    t0 = time.perf_counter()
+    o.step()
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": sc.nv * iters / dt, "unit": "vertex-iters/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"one step of the same workload cut to 1 outer block x {iters} inner "
+                      f"iterations (initial and final CCD stages included), FP64 numpy/scipy + C "
+                      f"geometry; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
+    ap.add_argument("--precision", default=None, choices=["mixed", "fp32"])
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing-pass", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
+              "not an implemented path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2403_19272_amd as P
+    import scenegen
+    from paper_2403_19272_amd import basis as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sc = scenegen.config(2 if args.workload == "c2" else 1)
+    if args.precision:
+        sc.precision = args.precision
+    log(f"workload {sc.name}: nv={sc.nv} nt={sc.nt} r={sc.r} {sc.precision}")
+    g = make_gpu_scene(sc, sc.precision, P, B)
+    t0 = time.time()
+    H = g.system_matrix()
+    U = B.rest_eigenbasis(H, sc.pinned, sc.r)
+    log(f"basis {time.time() - t0:.1f}s")
+    g.set_basis(U)
+    stream = torch.cuda.current_stream()
+    g.set_state(sc.x0, sc.v0, stream=stream)
+    st = g.step(sc.gravity, n=max(args.warmup, 1), stream=stream)
+    log(f"warmup {args.warmup} steps: {st}")
+
+    def timed_pass(K, timing):
+        g.set_state(sc.x0, sc.v0, stream=stream)
+        g.set_timing(timing)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(K):
+            g.step(sc.gravity, n=1, stream=stream, stats=False)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(K)])
+        kt = g.kernel_times() if timing else None
+        g.set_timing(False)
+        return wall, per, kt
+
+    K = args.steps
+    wall, per, _ = timed_pass(K, False)
+    stats = g.step(sc.gravity, n=0, stream=stream)  # stats of the last step
+    iters = sc.iters_inner * sc.iters_outer
+    value = sc.nv * iters * K / wall
+    log(f"timed {K} steps: {wall:.3f}s  {value:.3e} vertex-iters/s  p50 {np.percentile(per, 50):.3f} ms")
+    x, v = g.get_state(stream=stream)
+    finite = bool(np.isfinite(x).all() and np.isfinite(v).all())
+
+    roof = None
+    kt = None
+    if not args.no_timing_pass:
+        wall2, per2, kt = timed_pass(K, True)
+        nnz = H.nnz
+        ub = 2 if sc.precision == "mixed" else 4
+        contact = sc.self_contact or bool(sc.obstacles)
+        cands = {k: v for k, v in kt.items() if k in ("local_residual", "expand", "jacobi_cheb") and v[1]}
+        dom = max(cands, key=lambda k: cands[k][0])
+        tot_ms, n_launch = cands[dom]
+        avg_s = tot_ms / n_launch / 1e3
+        nbytes = kernel_bytes(dom, sc, nnz, ub, contact)
+        ach = nbytes / avg_s / 1e9
+        traffic = pmc_traffic(dom, args.workload)
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(nbytes),
+                "instrumented_wall_s": round(wall2, 3)}
+        log("kernel times (ms, launches):", json.dumps({k: [round(a, 3), b] for k, (a, b) in kt.items()}))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(sc, args.cpu_iters)
+        except Exception as e:  # reported, never fatal for the GPU figure
+            log(f"cpu baseline failed: {e!r}")
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "vertex-iters/s", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": round(wall / K * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16" if sc.precision == "mixed" else "f32", "data": "synthetic",
+        "config": {"workload": f"{sc.name}: {sc.n_side}x{sc.n_side} cloth ({sc.nv} verts, {sc.nt} tris) "
+                               f"dropped {0.3} m onto a {'cylinder spinning at 2 rad/s' if args.workload == 'c2' else 'sphere'}, "
+                               f"self contact, dt=1/200 s, {sc.iters_outer}x{sc.iters_inner} PD iterations/step, "
+                               f"r={sc.r} {'BF16' if sc.precision == 'mixed' else 'FP32'} basis, FP64 reduced solve",
+                   "vertices": sc.nv, "triangles": sc.nt, "iters_per_step": iters, "r": sc.r,
+                   "precision": sc.precision, "steps_from_rest_state": K},
+        "p50_step_ms": round(float(np.percentile(per, 50)), 4),
+        "p99_step_ms": round(float(np.percentile(per, 99)), 4),
+        "steps_per_s": round(K / wall, 2),
+        "last_step": {"n_candidates": stats["n_candidates"], "n_constraints": stats["n_constraints"],
+                      "min_toi": stats["min_toi"], "dx_norm": stats["dx_norm"],
+                      "cheb_rho": stats["cheb_rho"], "cheb_gamma": stats["cheb_gamma"], "finite": finite},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if kt:
+        out["kernel_ms"] = {k: round(a, 3) for k, (a, b) in kt.items() if b}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

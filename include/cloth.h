@@ -1,0 +1,221 @@
+/*
+ * cloth.h — C ABI of the MI355X (gfx950) projective-dynamics cloth solver.
+ *
+ * The library advances a triangle-mesh cloth by implicit Euler steps written
+ * as an energy minimisation (Lan et al., "Efficient GPU Cloth Simulation with
+ * Non-distance Barriers and Subspace Reuse", arXiv 2403.19272, section 3,
+ * Eq. (var) and Eq. (z)), solved with projective-dynamics local/global
+ * iterations (Eq. (local), Eq. (global)).  Each inner iteration runs:
+ *   - the local step: per-triangle strain projection, hinge bending target,
+ *     and collision targets weighted by the non-distance barrier
+ *     w = k K^a (Eq. (exp));
+ *   - the residual of the global system against the fixed system matrix H
+ *     stored as CSR, plus the diagonal collision term;
+ *   - the subspace-reuse correction through the rest-shape eigenbasis U
+ *     (Eq. (subspace_collision), Eq. (uu));
+ *   - a Chebyshev-accelerated Jacobi sweep on the remaining residual
+ *     (Eq. (high_frequency_residual));
+ *   - partial CCD on every collision constraint (Eq. (query)), which updates
+ *     the life spans a.
+ * Every outer block ends with a broad phase, an exact time-of-impact pass and
+ * the step-length filter x = x- + s (x+ - x-) (Algorithm 1, section 7).
+ *
+ * Conventions
+ *   - Positions and velocities cross the ABI as host float arrays of nv*3
+ *     values (x0,y0,z0,x1,...), in the caller's vertex order.
+ *   - Every call returns a cloth_status: CLOTH_OK (0) or a negative code; no
+ *     call aborts or throws.  cloth_last_error() gives a text for the last
+ *     failure on the calling thread.
+ *   - Host arrays passed in are borrowed for the duration of the call.
+ *   - Device work is enqueued on the stream argument (a hipStream_t; 0 is the
+ *     null stream).  Calls that return host data synchronise that stream.
+ *   - One scene is used by one thread at a time.
+ */
+#ifndef CLOTH_H
+#define CLOTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cloth_status;
+#define CLOTH_OK 0
+#define CLOTH_E_INVALID -1   /* bad argument or call order */
+#define CLOTH_E_MESH -2      /* non-manifold or degenerate mesh */
+#define CLOTH_E_OOM -3       /* arena too small / allocation failed */
+#define CLOTH_E_CAPACITY -4  /* pair or constraint buffer overflow after regrow */
+#define CLOTH_E_DIVERGED -5  /* NaN or Inf in the state */
+#define CLOTH_E_DEVICE -7    /* a HIP runtime error */
+
+#define CLOTH_PLAIN_FP32 0   /* basis U stored in FP32 */
+#define CLOTH_MIXED 1        /* basis U stored in BF16 (FP32 accumulation) */
+
+#define CLOTH_SPHERE 0
+#define CLOTH_CYLINDER 1     /* infinite along its axis for contact purposes */
+
+typedef struct cloth_scene_s* cloth_scene;
+
+/* Triangle mesh: nt triangles as 3 vertex indices each (0-based, one
+ * consistent orientation), optional per-vertex pin flags (NULL = none). */
+typedef struct {
+    int32_t nv, nt;
+    const int32_t* tris;
+    const uint8_t* pinned;
+} cloth_mesh;
+
+/* Material and contact constants (SI units).
+ *   density    mass per area, kg/m^2 (lumped: one third of each incident area)
+ *   k_stretch  strain weight per rest area (PD weight w_t = k_stretch * area)
+ *   k_bend     bending weight (hinge weight k_bend * 3 / (A1 + A2))
+ *   k_contact  initial barrier weight k of Eq. (exp); <= 0 selects the mean
+ *              elastic diagonal of H over free vertices
+ *   K_base     growth base K of Eq. (exp) (the paper uses 2)
+ *   a_max      cap on the life span a
+ *   d_hat      contact target distance (m)
+ *   alpha      filter back-off, s = alpha * t_TOI (the paper uses 0.8) */
+typedef struct {
+    double density, k_stretch, k_bend, k_contact, K_base;
+    int32_t a_max;
+    double d_hat, alpha;
+} cloth_material;
+
+/* Solver settings.
+ *   r                   basis width (scalar modes; each acts on x, y and z)
+ *   iters_inner/outer   fixed iteration budget per step (inner per block)
+ *   cheb_rho            spectral radius estimate for the Chebyshev weights;
+ *                       <= 0: estimated by power iteration when the basis is set
+ *   cheb_gamma          damping of the Jacobi step; <= 0: chosen with rho
+ *   cheb_delay          iterations before the Chebyshev weights start
+ *   precision           CLOTH_PLAIN_FP32 or CLOTH_MIXED
+ *   self_contact        1: vertex-triangle and edge-edge contact on
+ *   pair_capacity       candidate pairs the arena holds (0: 48 per vertex) */
+typedef struct {
+    int32_t r, iters_inner, iters_outer;
+    double cheb_rho, cheb_gamma;
+    int32_t cheb_delay, precision, self_contact;
+    int64_t pair_capacity;
+} cloth_solver_params;
+
+typedef struct {
+    int32_t kind;
+    double center[3], axis[3], radius, half_length, omega;
+} cloth_obstacle;
+
+/* Filled after the step's stream has been synchronised. */
+typedef struct {
+    int32_t inner_iters, outer_iters;
+    int64_t n_candidates, n_constraints;
+    double dx_norm;      /* max per-vertex change of the last inner iteration */
+    double min_toi;      /* smallest time of impact seen (2 = none) */
+    double cheb_rho, cheb_gamma;
+} cloth_step_stats;
+
+const char* cloth_status_string(cloth_status s);
+const char* cloth_last_error(void);
+
+/* Device bytes a scene needs for this mesh and these settings.  Builds the
+ * mesh's system-matrix pattern on the host to count its nonzeros. */
+cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_params* params,
+                                   size_t* bytes);
+
+/* Creates a scene: validates the mesh, builds rest data, lumped mass and the
+ * system matrix H = M/h^2 + sum_t w_t G_t^T G_t + sum_e w_e k_e k_e^T
+ * (Eq. (global)) on the host in FP64, and uploads it.  rest_xyz is the rest
+ * shape (nv*3 floats); the initial state is the rest shape at rest.
+ * dev_arena/arena_bytes: caller-owned device memory of at least the
+ * footprint (it must outlive the scene), or NULL/0 to let the library
+ * allocate.  The basis must be set (cloth_set_basis) before stepping. */
+cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const cloth_material* mat,
+                        double dt, const cloth_solver_params* params, void* dev_arena,
+                        size_t arena_bytes, cloth_scene* out);
+
+/* The scene's system matrix H (FP64 CSR, caller's vertex order, sorted
+ * columns).  Call with row_ptr = col = val = NULL to get nnz only. */
+cloth_status cloth_system_matrix(cloth_scene s, int64_t* nnz, int32_t* row_ptr, int32_t* col,
+                                 double* val);
+
+/* Sets the subspace basis U (nv*r FP64, row-major, caller's vertex order;
+ * rows of pinned vertices are ignored and stored as zero).  The library
+ * rounds it to the storage precision, forms Lambda~ = U~^T H U~ in FP64,
+ * factors it, and estimates the Chebyshev parameters if they are <= 0.
+ * Section 5: U holds the eigenvectors of H for the r smallest eigenvalues;
+ * any basis is accepted (the correction is a Galerkin projection). */
+cloth_status cloth_set_basis(cloth_scene s, const double* U, int32_t r);
+
+/* Adds an analytic obstacle (at most 4 per scene). */
+cloth_status cloth_add_obstacle(cloth_scene s, const cloth_obstacle* ob);
+
+/* State upload / download (host arrays of nv*3 floats; v may be NULL).
+ * set_state also fixes pinned vertices at the given x. */
+cloth_status cloth_set_state(cloth_scene s, const float* x, const float* v, void* stream);
+cloth_status cloth_get_state(cloth_scene s, float* x, float* v, void* stream);
+
+/* One implicit time step with gravity g (m/s^2); stats may be NULL. */
+cloth_status cloth_step(cloth_scene s, const float gravity[3], void* stream,
+                        cloth_step_stats* stats);
+
+/* n steps in a row on the same stream without host synchronisation in
+ * between; stats (may be NULL) describe the last step. */
+cloth_status cloth_step_n(cloth_scene s, const float gravity[3], int32_t n, void* stream,
+                          cloth_step_stats* stats);
+
+cloth_status cloth_destroy(cloth_scene s);
+
+/* Per-kernel timing.  With timing on, every kernel (or kernel group) of the
+ * step is bracketed by HIP events on the step's stream; cloth_kernel_times
+ * synchronises the device and returns, per kernel id, its name (32 chars
+ * each in names), total milliseconds and launch count.  *count receives the
+ * number of ids; at most max entries are written.  Turning timing on or off
+ * clears the totals. */
+cloth_status cloth_set_timing(cloth_scene s, int32_t on);
+cloth_status cloth_kernel_times(cloth_scene s, int32_t max, char* names, double* total_ms,
+                                int64_t* launches, int32_t* count);
+
+/* ---------------------------------------------------------------------
+ * Stage-level entry points, used to check each stage against a reference
+ * on identical inputs.  Host arrays, caller's vertex order.
+ * ------------------------------------------------------------------- */
+
+/* Broad phase on (xm, xp): sorted VT pairs (vertex, triangle) and EE pairs
+ * (edge e1 < e2, edges numbered in lexicographic (i<j) order) whose swept
+ * FP32 boxes grown by d_hat overlap and that share no vertex.  Returns
+ * CLOTH_E_CAPACITY (with the true counts) if a list does not fit. */
+cloth_status cloth_stage_broad_phase(cloth_scene s, const float* xm, const float* xp,
+                                     int64_t cap, int32_t* vt, int64_t* n_vt, int32_t* ee,
+                                     int64_t* n_ee);
+
+/* FP64 time of impact over (xm, xp) for given VT and EE pairs (2.0 = no hit). */
+cloth_status cloth_stage_toi(cloth_scene s, const float* xm, const float* xp, int64_t n_vt,
+                             const int32_t* vt, int64_t n_ee, const int32_t* ee,
+                             double* toi_vt, double* toi_ee);
+
+/* Loads a block state: x- (start of block), x^k, x^{k-1}, the inertia target
+ * z, and a constraint set (sorted VT and EE lists with life spans, and
+ * per-vertex obstacle life spans ob_a[j*nv + v], -1 = not a member).  The
+ * frozen constraint data are computed from xm. */
+cloth_status cloth_stage_load_block(cloth_scene s, const float* xm, const float* xk,
+                                    const float* xkm1, const float* z, int64_t n_vt,
+                                    const int32_t* vt, const int32_t* a_vt, int64_t n_ee,
+                                    const int32_t* ee, const int32_t* a_ee, const int32_t* ob_a);
+
+/* One inner iteration with Chebyshev index k on the loaded block, followed
+ * by partial CCD (the life-span update); then x^{k-1} <- x^k <- x^{k+1}. */
+cloth_status cloth_stage_inner(cloth_scene s, int32_t k);
+
+/* Partial CCD of the loaded block's constraints on (x-, xnew) with xnew
+ * given (host, nv*3 floats): updates the life spans only. */
+cloth_status cloth_stage_partial_ccd(cloth_scene s, const float* xnew);
+
+/* Reads the block state back: x^k (after cloth_stage_inner: x^{k+1}), the
+ * life spans, the last inner iteration's max change, and (if non-NULL) the
+ * right-hand side b and reduced solution Q (r*3 values, row-major). */
+cloth_status cloth_stage_read_block(cloth_scene s, float* xk, int32_t* a_vt, int32_t* a_ee,
+                                    int32_t* ob_a, double* dx, float* b, double* Q);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLOTH_H */

@@ -1,0 +1,289 @@
+"""Python binding of libcloth (include/cloth.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module converts numpy
+arrays and torch device buffers/streams to plain pointers.  Importing it
+fails if the library has not been built (python -m paper_2403_19272_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcloth.so")
+
+CLOTH_OK = 0
+CLOTH_E_INVALID = -1
+CLOTH_E_MESH = -2
+CLOTH_E_OOM = -3
+CLOTH_E_CAPACITY = -4
+CLOTH_E_DIVERGED = -5
+CLOTH_E_DEVICE = -7
+CLOTH_PLAIN_FP32 = 0
+CLOTH_MIXED = 1
+CLOTH_SPHERE = 0
+CLOTH_CYLINDER = 1
+
+EXPORTS = [
+    "cloth_status_string", "cloth_last_error", "cloth_query_footprint", "cloth_init",
+    "cloth_system_matrix", "cloth_set_basis", "cloth_add_obstacle", "cloth_set_state",
+    "cloth_get_state", "cloth_step", "cloth_step_n", "cloth_destroy", "cloth_stage_broad_phase",
+    "cloth_stage_toi", "cloth_stage_load_block", "cloth_stage_inner", "cloth_stage_partial_ccd",
+    "cloth_stage_read_block", "cloth_set_timing", "cloth_kernel_times",
+]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("nt", C.c_int32), ("tris", C.c_void_p), ("pinned", C.c_void_p)]
+
+
+class Material(C.Structure):
+    _fields_ = [("density", C.c_double), ("k_stretch", C.c_double), ("k_bend", C.c_double),
+                ("k_contact", C.c_double), ("K_base", C.c_double), ("a_max", C.c_int32),
+                ("d_hat", C.c_double), ("alpha", C.c_double)]
+
+
+class SolverParams(C.Structure):
+    _fields_ = [("r", C.c_int32), ("iters_inner", C.c_int32), ("iters_outer", C.c_int32),
+                ("cheb_rho", C.c_double), ("cheb_gamma", C.c_double), ("cheb_delay", C.c_int32),
+                ("precision", C.c_int32), ("self_contact", C.c_int32), ("pair_capacity", C.c_int64)]
+
+
+class Obstacle(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("center", C.c_double * 3), ("axis", C.c_double * 3),
+                ("radius", C.c_double), ("half_length", C.c_double), ("omega", C.c_double)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("inner_iters", C.c_int32), ("outer_iters", C.c_int32),
+                ("n_candidates", C.c_int64), ("n_constraints", C.c_int64),
+                ("dx_norm", C.c_double), ("min_toi", C.c_double), ("cheb_rho", C.c_double),
+                ("cheb_gamma", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libcloth.so not built at {LIB_PATH}; run python -m paper_2403_19272_amd.build")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "cloth_status_string": (C.c_char_p, [i32]),
+        "cloth_last_error": (C.c_char_p, []),
+        "cloth_query_footprint": (i32, [C.POINTER(Mesh), C.POINTER(SolverParams), C.POINTER(C.c_size_t)]),
+        "cloth_init": (i32, [C.POINTER(Mesh), P, C.POINTER(Material), f64, C.POINTER(SolverParams), P,
+                             C.c_size_t, C.POINTER(P)]),
+        "cloth_system_matrix": (i32, [P, C.POINTER(i64), P, P, P]),
+        "cloth_set_basis": (i32, [P, P, i32]),
+        "cloth_add_obstacle": (i32, [P, C.POINTER(Obstacle)]),
+        "cloth_set_state": (i32, [P, P, P, P]),
+        "cloth_get_state": (i32, [P, P, P, P]),
+        "cloth_step": (i32, [P, P, P, C.POINTER(StepStats)]),
+        "cloth_step_n": (i32, [P, P, i32, P, C.POINTER(StepStats)]),
+        "cloth_destroy": (i32, [P]),
+        "cloth_stage_broad_phase": (i32, [P, P, P, i64, P, C.POINTER(i64), P, C.POINTER(i64)]),
+        "cloth_stage_toi": (i32, [P, P, P, i64, P, i64, P, P, P]),
+        "cloth_stage_load_block": (i32, [P, P, P, P, P, i64, P, P, i64, P, P, P]),
+        "cloth_stage_inner": (i32, [P, i32]),
+        "cloth_stage_partial_ccd": (i32, [P, P]),
+        "cloth_set_timing": (i32, [P, i32]),
+        "cloth_kernel_times": (i32, [P, i32, P, P, P, C.POINTER(i32)]),
+        "cloth_stage_read_block": (i32, [P, P, P, P, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+class ClothError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib.cloth_last_error().decode()
+        super().__init__(f"{where}: {lib.cloth_status_string(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(code, where):
+    if code != CLOTH_OK:
+        raise ClothError(code, where)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32).reshape(-1, 3))
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class ClothScene:
+    """One cloth scene resident on the device."""
+
+    def __init__(self, tris, rest, *, dt, density=0.3, k_stretch=160.0, k_bend=3e-4,
+                 k_contact=0.0, K_base=2.0, a_max=20, d_hat=1e-3, alpha=0.8, pinned=None, r=16,
+                 iters_inner=10, iters_outer=1, cheb_rho=0.0, cheb_gamma=0.0, cheb_delay=3,
+                 precision=CLOTH_PLAIN_FP32, self_contact=False, pair_capacity=0, arena=None):
+        self._tris = np.ascontiguousarray(tris, np.int32)
+        rest = _f32(rest)
+        nv = rest.shape[0]
+        self.nv = nv
+        self._pinned = None if pinned is None else np.ascontiguousarray(pinned, np.uint8)
+        self.mesh = Mesh(nv, self._tris.shape[0], self._tris.ctypes.data, None if self._pinned is None
+                         else self._pinned.ctypes.data)
+        self.mat = Material(density, k_stretch, k_bend, k_contact, K_base, a_max, d_hat, alpha)
+        self.params = SolverParams(r, iters_inner, iters_outer, cheb_rho, cheb_gamma, cheb_delay,
+                                   precision, int(bool(self_contact)), pair_capacity)
+        self.r = r
+        nbytes = C.c_size_t(0)
+        _check(lib.cloth_query_footprint(C.byref(self.mesh), C.byref(self.params), C.byref(nbytes)),
+               "cloth_query_footprint")
+        self.footprint = nbytes.value
+        self._arena = None
+        aptr, asize = None, 0
+        if arena == "torch":
+            import torch
+            self._arena = torch.empty(self.footprint, dtype=torch.uint8, device="cuda")
+            aptr, asize = C.c_void_p(self._arena.data_ptr()), self.footprint
+        self._h = C.c_void_p()
+        _check(lib.cloth_init(C.byref(self.mesh), _ptr(rest), C.byref(self.mat), dt,
+                              C.byref(self.params), aptr, asize, C.byref(self._h)), "cloth_init")
+
+    # ---- setup
+    def system_matrix(self):
+        import scipy.sparse as sp
+        nnz = C.c_int64(0)
+        _check(lib.cloth_system_matrix(self._h, C.byref(nnz), None, None, None), "cloth_system_matrix")
+        rp = np.empty(self.nv + 1, np.int32)
+        col = np.empty(nnz.value, np.int32)
+        val = np.empty(nnz.value, np.float64)
+        _check(lib.cloth_system_matrix(self._h, C.byref(nnz), _ptr(rp), _ptr(col), _ptr(val)),
+               "cloth_system_matrix")
+        return sp.csr_matrix((val, col, rp), shape=(self.nv, self.nv))
+
+    def set_basis(self, U: np.ndarray):
+        U = np.ascontiguousarray(U, np.float64)
+        _check(lib.cloth_set_basis(self._h, _ptr(U), U.shape[1]), "cloth_set_basis")
+
+    def add_obstacle(self, kind, center, radius, axis=(1.0, 0.0, 0.0), half_length=0.0, omega=0.0):
+        ob = Obstacle(kind, (C.c_double * 3)(*center), (C.c_double * 3)(*axis), radius,
+                      half_length, omega)
+        _check(lib.cloth_add_obstacle(self._h, C.byref(ob)), "cloth_add_obstacle")
+
+    # ---- state
+    def set_state(self, x, v=None, stream=None):
+        x = _f32(x)
+        v = None if v is None else _f32(v)
+        _check(lib.cloth_set_state(self._h, _ptr(x), _ptr(v), _stream(stream)), "cloth_set_state")
+
+    def get_state(self, stream=None):
+        x = np.empty((self.nv, 3), np.float32)
+        v = np.empty((self.nv, 3), np.float32)
+        _check(lib.cloth_get_state(self._h, _ptr(x), _ptr(v), _stream(stream)), "cloth_get_state")
+        return x, v
+
+    def step(self, gravity=(0.0, -9.8, 0.0), n=1, stream=None, stats=True):
+        g = np.asarray(gravity, np.float32)
+        st = StepStats()
+        _check(lib.cloth_step_n(self._h, _ptr(g), n, _stream(stream), C.byref(st) if stats else None),
+               "cloth_step_n")
+        return st.as_dict() if stats else None
+
+    # ---- timing
+    def set_timing(self, on: bool):
+        _check(lib.cloth_set_timing(self._h, int(bool(on))), "cloth_set_timing")
+
+    def kernel_times(self):
+        """{kernel name: (total ms, launches)} since timing was switched on."""
+        n = C.c_int32(0)
+        names = C.create_string_buffer(32 * 32)
+        ms = np.zeros(32)
+        cnt = np.zeros(32, np.int64)
+        _check(lib.cloth_kernel_times(self._h, 32, names, _ptr(ms), _ptr(cnt), C.byref(n)),
+               "cloth_kernel_times")
+        raw = names.raw
+        out = {}
+        for i in range(n.value):
+            name = raw[32 * i:32 * i + 32].split(b"\0")[0].decode()
+            out[name] = (float(ms[i]), int(cnt[i]))
+        return out
+
+    # ---- stages
+    def stage_broad_phase(self, xm, xp, cap=None):
+        xm, xp = _f32(xm), _f32(xp)
+        cap = cap or max(1024, 64 * self.nv)
+        vt = np.empty((cap, 2), np.int32)
+        ee = np.empty((cap, 2), np.int32)
+        nvt, nee = C.c_int64(0), C.c_int64(0)
+        _check(lib.cloth_stage_broad_phase(self._h, _ptr(xm), _ptr(xp), cap, _ptr(vt), C.byref(nvt),
+                                           _ptr(ee), C.byref(nee)), "cloth_stage_broad_phase")
+        return vt[:nvt.value].copy(), ee[:nee.value].copy()
+
+    def stage_toi(self, xm, xp, vt, ee):
+        xm, xp = _f32(xm), _f32(xp)
+        vt = np.ascontiguousarray(vt, np.int32).reshape(-1, 2)
+        ee = np.ascontiguousarray(ee, np.int32).reshape(-1, 2)
+        tv = np.empty(len(vt))
+        te = np.empty(len(ee))
+        _check(lib.cloth_stage_toi(self._h, _ptr(xm), _ptr(xp), len(vt), _ptr(vt), len(ee), _ptr(ee),
+                                   _ptr(tv), _ptr(te)), "cloth_stage_toi")
+        return tv, te
+
+    def stage_load_block(self, xm, xk, xkm1, z, vt=None, a_vt=None, ee=None, a_ee=None, ob_a=None):
+        vt = np.zeros((0, 2), np.int32) if vt is None else np.ascontiguousarray(vt, np.int32)
+        ee = np.zeros((0, 2), np.int32) if ee is None else np.ascontiguousarray(ee, np.int32)
+        a_vt = np.zeros(len(vt), np.int32) if a_vt is None else np.ascontiguousarray(a_vt, np.int32)
+        a_ee = np.zeros(len(ee), np.int32) if a_ee is None else np.ascontiguousarray(a_ee, np.int32)
+        ob = None if ob_a is None else np.ascontiguousarray(ob_a, np.int32)
+        self._keep = (vt, ee, a_vt, a_ee, ob)
+        _check(lib.cloth_stage_load_block(self._h, _ptr(_f32(xm)), _ptr(_f32(xk)), _ptr(_f32(xkm1)),
+                                          _ptr(_f32(z)), len(vt), _ptr(vt), _ptr(a_vt), len(ee),
+                                          _ptr(ee), _ptr(a_ee), _ptr(ob)), "cloth_stage_load_block")
+        self._nvt, self._nee = len(vt), len(ee)
+
+    def stage_inner(self, k):
+        _check(lib.cloth_stage_inner(self._h, k), "cloth_stage_inner")
+
+    def stage_partial_ccd(self, xnew):
+        _check(lib.cloth_stage_partial_ccd(self._h, _ptr(_f32(xnew))), "cloth_stage_partial_ccd")
+
+    def stage_read_block(self, nob=0):
+        xk = np.empty((self.nv, 3), np.float32)
+        b = np.empty((self.nv, 3), np.float32)
+        a_vt = np.empty(self._nvt, np.int32)
+        a_ee = np.empty(self._nee, np.int32)
+        ob = np.empty(max(nob, 1) * self.nv, np.int32)
+        dx = C.c_double(0)
+        Q = np.empty((self.r, 3))
+        _check(lib.cloth_stage_read_block(self._h, _ptr(xk), _ptr(a_vt), _ptr(a_ee), _ptr(ob),
+                                          C.byref(dx), _ptr(b), _ptr(Q)), "cloth_stage_read_block")
+        return dict(xk=xk, a_vt=a_vt, a_ee=a_ee, ob_a=ob[:nob * self.nv].reshape(nob, self.nv),
+                    dx=dx.value, b=b, Q=Q)
+
+    def close(self):
+        if self._h:
+            lib.cloth_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

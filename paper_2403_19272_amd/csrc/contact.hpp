@@ -1,0 +1,91 @@
+// Contact side of the cloth step: broad phase, time of impact, constraint
+// sets with life spans, NDB weights and targets, partial CCD, the reduced
+// matrix update U^T diag(W) U and its FP64 factorisation on the device.
+#pragma once
+
+#include <functional>
+
+#include "scene.hpp"
+
+namespace cloth {
+
+struct ContactState {
+    bool enabled = false;   // self contact or obstacles present
+    bool active = false;    // the current block has constraints (or may have)
+    int nob = 0;
+    ObstD ob[MAX_OBST];
+    int64_t cap = 0;        // pair capacity (candidates and constraints per type)
+    int hash_p = 0;         // hash buckets (power of two)
+    int ntiles_cap = 0;     // scan tiles for the largest scan
+
+    // boxes (lo xyz, hi xyz as 6 floats)
+    float *vbox = nullptr, *tbox = nullptr, *ebox = nullptr;
+    int* tcell = nullptr;   // 3 ints per triangle: its low-corner cell
+    int* ecell = nullptr;   // 3 ints per edge
+    int *bucket_cnt = nullptr, *bucket_ptr = nullptr, *bucket_item = nullptr;
+    unsigned int* maxext = nullptr;  // 6: tri (x,y,z), edge (x,y,z) max widths as float bits
+
+    // candidates
+    int* vcount = nullptr;  // per vertex VT counts, then offsets (nv+1)
+    int* ecount = nullptr;  // per edge EE counts, then offsets (ne+1)
+    int2 *cand_vt = nullptr, *cand_ee = nullptr;
+    double *toi_vt = nullptr, *toi_ee = nullptr;
+    int *keep = nullptr, *keep_ofs = nullptr, *cand_a = nullptr;
+
+    // constraints (VT first, then EE), current and previous block
+    int2 *cpair = nullptr, *cpair_prev = nullptr;
+    int *ca = nullptr, *ca_prev = nullptr;
+    double2* clam = nullptr;
+    float4* cnrm = nullptr;
+    float4* slot = nullptr;      // 4 per constraint: (w, w*y)
+    int *vslot_ptr = nullptr, *vslot = nullptr, *vslot_fill = nullptr;
+    int* ob_a = nullptr;         // MAX_OBST * nv, -1 = not a member
+    int* cvlist = nullptr;       // contact vertices (for the Gram)
+    int *cvflag = nullptr, *cvofs = nullptr;
+    ObstD* ob_dev = nullptr;     // device copy of ob[]
+
+    // device scalars: [0] n_vt cand, [1] n_ee cand, [2] n_cvt, [3] n_cee,
+    // [4] n_prev_vt, [5] n_prev_ee, [6] n_cv, [7] overflow flag,
+    // [9] n_vt + n_ee, [10] obstacle constraints
+    int* cnt = nullptr;
+    unsigned long long* tmin_bits = nullptr;  // [0] block min, [1] step min
+    double* s_dev = nullptr;                  // filter step length
+    int64_t* stat64 = nullptr;                // [0] candidates (last), [1] constraints (last)
+
+    // scan scratch
+    int* scan_tiles = nullptr;
+    double* gpart2 = nullptr;    // level-1 partials of U^T r0 (also used without contact)
+    double* gvec = nullptr;      // g = U^T r0 (r*3, FP64)
+    int gram_chunks = 0;
+};
+
+using Carver = std::function<void*(size_t)>;
+
+// carves the contact buffers (a counting carver gives the footprint)
+cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve);
+cloth_status contact_upload(Scene& s, ContactState& c);
+cloth_status contact_set_obstacles(Scene& s, ContactState& c);
+bool contact_enabled(const Scene& s, const ContactState& c);
+cloth_status contact_step_begin(Scene& s, ContactState& c, hipStream_t st);
+cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st);
+cloth_status contact_prepare_iteration(Scene& s, ContactState& c, hipStream_t st);
+cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st);
+cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st);
+cloth_status contact_block_end(Scene& s, ContactState& c, bool last, hipStream_t st);
+cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step_stats* out);
+cloth_status contact_load_constraints(Scene& s, ContactState& c, int64_t n_vt, const int32_t* vt,
+                                      const int32_t* a_vt, int64_t n_ee, const int32_t* ee,
+                                      const int32_t* a_ee, const int32_t* ob_a);
+cloth_status contact_read_constraints(Scene& s, ContactState& c, int32_t* a_vt, int32_t* a_ee,
+                                      int32_t* ob_a);
+cloth_status contact_stage_broad_phase(Scene& s, ContactState& c, const float* xm, const float* xp,
+                                       int64_t cap, int32_t* vt, int64_t* n_vt, int32_t* ee,
+                                       int64_t* n_ee);
+cloth_status contact_stage_toi(Scene& s, ContactState& c, const float* xm, const float* xp,
+                               int64_t n_vt, const int32_t* vt, int64_t n_ee, const int32_t* ee,
+                               double* toi_vt, double* toi_ee);
+void contact_destroy(Scene& s, ContactState& c);
+
+cloth_status set_error(cloth_status code, const std::string& msg);
+
+}  // namespace cloth

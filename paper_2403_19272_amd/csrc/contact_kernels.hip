@@ -1,0 +1,1443 @@
+// Contact kernels for gfx950: swept-box spatial hash broad phase, FP64
+// time of impact, constraint sets with life spans (non-distance barrier,
+// Eq. (exp)), partial CCD (Eq. (query)), half-space and obstacle targets,
+// U^T diag(W) U over the contact vertices (Eq. (uu)) and a one-workgroup FP64
+// Cholesky of the reduced matrix (Eq. (subspace_collision)).
+//
+// Every kernel takes its item counts from device memory and loops over them
+// with a fixed grid, so the whole step can be enqueued without reading
+// anything back on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "contact.hpp"
+#include "kernels.hpp"
+
+namespace cloth {
+
+namespace {
+
+constexpr int SCAN_TILE = 2048;   // items per scan block (256 threads x 8)
+constexpr int GRID_LOOP = 2048;   // blocks of the grid-stride kernels
+constexpr int VT_SAMPLES = 3, EE_SAMPLES = 3;
+
+struct d3 {
+    double x, y, z;
+};
+__device__ __forceinline__ d3 mk(double x, double y, double z) { return {x, y, z}; }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ d3 operator*(d3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ d3 lerp(d3 a, d3 b, double t) { return a + (b - a) * t; }
+__device__ __forceinline__ d3 ld3(const float* X, int n, int v) {
+    return {(double)X[v], (double)X[n + v], (double)X[2 * n + v]};
+}
+__device__ __forceinline__ double amax(d3 a) { return fmax(fabs(a.x), fmax(fabs(a.y), fabs(a.z))); }
+
+__device__ __forceinline__ int cell_of(float lo, float cs) { return (int)floorf(lo / cs); }
+__device__ __forceinline__ unsigned hash3(int x, int y, int z) {
+    return ((unsigned)x * 73856093u) ^ ((unsigned)y * 19349663u) ^ ((unsigned)z * 83492791u);
+}
+__device__ __forceinline__ float cs_of(const unsigned* maxext, int d) {
+    float w = __uint_as_float(maxext[d]);
+    return w * (1.0f + 1.0f / 1024.0f) + 1e-30f;
+}
+__device__ __forceinline__ bool overlap6(const float* a, const float* b) {
+    return !(a[0] > b[3] || b[0] > a[3] || a[1] > b[4] || b[1] > a[4] || a[2] > b[5] || b[2] > a[5]);
+}
+
+__device__ __forceinline__ double warp_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+// ---------------------------------------------------------------- TOI
+// Earliest t in [0,1] at which the moving points are coplanar (cubic in t)
+// and in contact; degenerate cubics fall back to sampled distances.
+constexpr double DEGEN_REL = 1e-14, PAR_REL = 1e-20, NOHIT = 2.0;
+constexpr int FALLBACK_SAMPLES = 1024;
+
+__device__ double horner(const double c[4], double t) { return ((c[3] * t + c[2]) * t + c[1]) * t + c[0]; }
+__device__ int sgnd(double v) { return (v > 0) - (v < 0); }
+
+__device__ int roots01(const double c[4], double* roots) {
+    double brk[4];
+    int nb = 0;
+    brk[nb++] = 0.0;
+    double A = 3 * c[3], B = 2 * c[2], C = c[1];
+    double cr[2];
+    int ncr = 0;
+    if (A != 0.0) {
+        double disc = B * B - 4 * A * C;
+        if (disc >= 0) {
+            double sq = sqrt(disc);
+            double q = -0.5 * (B + (B >= 0 ? sq : -sq));
+            double r1 = q / A, r2 = (q != 0.0) ? C / q : r1;
+            if (r1 > r2) {
+                double t = r1;
+                r1 = r2;
+                r2 = t;
+            }
+            cr[ncr++] = r1;
+            if (r2 != r1) cr[ncr++] = r2;
+        }
+    } else if (B != 0.0) {
+        cr[ncr++] = -C / B;
+    }
+    for (int i = 0; i < ncr; ++i)
+        if (cr[i] > 0.0 && cr[i] < 1.0) brk[nb++] = cr[i];
+    brk[nb++] = 1.0;
+    int nr = 0;
+    for (int i = 0; i + 1 < nb; ++i) {
+        double lo = brk[i], hi = brk[i + 1];
+        double flo = horner(c, lo), fhi = horner(c, hi);
+        if (flo == 0.0) {
+            if (nr == 0 || roots[nr - 1] != lo) roots[nr++] = lo;
+            continue;
+        }
+        if (fhi == 0.0) {
+            roots[nr++] = hi;
+            continue;
+        }
+        if (sgnd(flo) == sgnd(fhi)) continue;
+        int s0 = sgnd(flo);
+        for (int it = 0; it < 64; ++it) {
+            double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            double fm = horner(c, mid);
+            if (fm == 0.0) {
+                lo = mid;
+                break;
+            }
+            if (sgnd(fm) == s0) lo = mid; else hi = mid;
+        }
+        roots[nr++] = lo;
+    }
+    return nr;
+}
+
+__device__ bool in_tri(d3 p, d3 a, d3 b, d3 c) {
+    d3 n = cross(b - a, c - a);
+    if (!(dot(n, n) > 0.0)) return false;
+    return dot(cross(b - p, c - p), n) >= 0.0 && dot(cross(c - p, a - p), n) >= 0.0 &&
+           dot(cross(a - p, b - p), n) >= 0.0;
+}
+
+// -1: parallel, 0: apart, 1: crossing (coplanar segments)
+__device__ int seg_cross(d3 p1, d3 p2, d3 p3, d3 p4) {
+    d3 d1 = p2 - p1, d2 = p4 - p3, r = p3 - p1;
+    d3 n = cross(d1, d2);
+    double nn = dot(n, n);
+    if (nn <= PAR_REL * dot(d1, d1) * dot(d2, d2)) return -1;
+    double s1 = dot(cross(r, d2), n) / nn, s2 = dot(cross(r, d1), n) / nn;
+    return s1 >= 0.0 && s1 <= 1.0 && s2 >= 0.0 && s2 <= 1.0;
+}
+
+__device__ double clamp01(double v) { return v < 0 ? 0 : (v > 1 ? 1 : v); }
+
+// closest point of triangle abc to p as (l1, l2): q = a + l1 (b-a) + l2 (c-a)
+__device__ void tri_closest(d3 p, d3 a, d3 b, d3 c, double& l1, double& l2) {
+    d3 ab = b - a, ac = c - a, ap = p - a;
+    double d1 = dot(ab, ap), d2 = dot(ac, ap);
+    if (d1 <= 0 && d2 <= 0) { l1 = 0; l2 = 0; return; }
+    d3 bp = p - b;
+    double d3_ = dot(ab, bp), d4 = dot(ac, bp);
+    if (d3_ >= 0 && d4 <= d3_) { l1 = 1; l2 = 0; return; }
+    double vc = d1 * d4 - d3_ * d2;
+    if (vc <= 0 && d1 >= 0 && d3_ <= 0) { l1 = d1 / (d1 - d3_); l2 = 0; return; }
+    d3 cp = p - c;
+    double d5 = dot(ab, cp), d6 = dot(ac, cp);
+    if (d6 >= 0 && d5 <= d6) { l1 = 0; l2 = 1; return; }
+    double vb = d5 * d2 - d1 * d6;
+    if (vb <= 0 && d2 >= 0 && d6 <= 0) { l1 = 0; l2 = d2 / (d2 - d6); return; }
+    double va = d3_ * d6 - d5 * d4;
+    if (va <= 0 && (d4 - d3_) >= 0 && (d5 - d6) >= 0) {
+        double w = (d4 - d3_) / ((d4 - d3_) + (d5 - d6));
+        l1 = 1 - w; l2 = w; return;
+    }
+    double den = va + vb + vc;
+    if (den == 0.0) { l1 = 0; l2 = 0; return; }
+    l1 = vb / den; l2 = vc / den;
+}
+
+// closest parameters (s on p1p2, t on p3p4)
+__device__ void seg_closest(d3 p1, d3 p2, d3 p3, d3 p4, double& s, double& t) {
+    d3 d1 = p2 - p1, d2 = p4 - p3, r = p1 - p3;
+    double a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
+    if (a <= 0 && e <= 0) { s = 0; t = 0; return; }
+    if (a <= 0) { s = 0; t = clamp01(f / e); return; }
+    double c = dot(d1, r);
+    if (e <= 0) { t = 0; s = clamp01(-c / a); return; }
+    double b = dot(d1, d2), den = a * e - b * b;
+    s = den > 0 ? clamp01((b * f - c * e) / den) : 0.0;
+    t = (b * s + f) / e;
+    if (t < 0) { t = 0; s = clamp01(-c / a); }
+    else if (t > 1) { t = 1; s = clamp01((b - c) / a); }
+}
+
+__device__ double dist_vt(const d3* q0, const d3* q1, double t) {
+    d3 p = lerp(q0[0], q1[0], t), a = lerp(q0[1], q1[1], t), b = lerp(q0[2], q1[2], t), c = lerp(q0[3], q1[3], t);
+    double l1, l2;
+    tri_closest(p, a, b, c, l1, l2);
+    d3 d = p - (a + (b - a) * l1 + (c - a) * l2);
+    return sqrt(dot(d, d));
+}
+__device__ double dist_ee(const d3* q0, const d3* q1, double t) {
+    d3 p1 = lerp(q0[0], q1[0], t), p2 = lerp(q0[1], q1[1], t), p3 = lerp(q0[2], q1[2], t), p4 = lerp(q0[3], q1[3], t);
+    double s, u;
+    seg_closest(p1, p2, p3, p4, s, u);
+    d3 d = lerp(p3, p4, u) - lerp(p1, p2, s);
+    return sqrt(dot(d, d));
+}
+
+template <bool VT>
+__device__ double sampled_toi(const d3* q0, const d3* q1, double eta) {
+    double prev = 0.0;
+    for (int i = 0; i <= FALLBACK_SAMPLES; ++i) {
+        double t = (double)i / FALLBACK_SAMPLES;
+        double dd = VT ? dist_vt(q0, q1, t) : dist_ee(q0, q1, t);
+        if (dd <= eta) {
+            if (i == 0) return 0.0;
+            double lo = prev, hi = t;
+            for (int it = 0; it < 64; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                double dm = VT ? dist_vt(q0, q1, mid) : dist_ee(q0, q1, mid);
+                if (dm <= eta) hi = mid; else lo = mid;
+            }
+            return lo;
+        }
+        prev = t;
+    }
+    return NOHIT;
+}
+
+// coplanarity cubic of the points (p, a, b, c): ((b-a) x (c-a)) . (p-a)
+__device__ void cubic_of(const d3* q0, const d3* q1, double c[4], double& L) {
+    d3 E1 = q0[2] - q0[1], E2 = q0[3] - q0[1], W = q0[0] - q0[1];
+    d3 F1 = q1[2] - q1[1], F2 = q1[3] - q1[1], Wf = q1[0] - q1[1];
+    d3 dE1 = F1 - E1, dE2 = F2 - E2, dW = Wf - W;
+    d3 C0 = cross(E1, E2), C1 = cross(E1, dE2) + cross(dE1, E2), C2 = cross(dE1, dE2);
+    c[0] = dot(C0, W);
+    c[1] = dot(C0, dW) + dot(C1, W);
+    c[2] = dot(C1, dW) + dot(C2, W);
+    c[3] = dot(C2, dW);
+    L = fmax(fmax(fmax(amax(E1), amax(E2)), fmax(amax(W), amax(F1))), fmax(amax(F2), amax(Wf)));
+}
+
+__device__ bool degenerate(const double c[4], double L) {
+    double s = fmax(fmax(fabs(c[0]), fabs(c[1])), fmax(fabs(c[2]), fabs(c[3])));
+    return s <= DEGEN_REL * L * L * L;
+}
+
+// q: (vertex, a, b, c) at t=0 and t=1
+__device__ double pair_toi_vt(const d3* q0, const d3* q1) {
+    double c[4], L;
+    cubic_of(q0, q1, c, L);
+    if (L == 0.0) return NOHIT;
+    if (degenerate(c, L)) return sampled_toi<true>(q0, q1, 1e-12 * L);
+    double roots[4];
+    int nr = roots01(c, roots);
+    for (int i = 0; i < nr; ++i) {
+        double t = roots[i];
+        if (in_tri(lerp(q0[0], q1[0], t), lerp(q0[1], q1[1], t), lerp(q0[2], q1[2], t), lerp(q0[3], q1[3], t)))
+            return t;
+    }
+    return NOHIT;
+}
+
+// e: (p1, p2, p3, p4) at t=0 and t=1
+__device__ double pair_toi_ee(const d3* e0, const d3* e1) {
+    d3 q0[4] = {e0[2], e0[0], e0[1], e0[0] + (e0[3] - e0[2])};
+    d3 q1[4] = {e1[2], e1[0], e1[1], e1[0] + (e1[3] - e1[2])};
+    double c[4], L;
+    cubic_of(q0, q1, c, L);
+    if (L == 0.0) return NOHIT;
+    if (degenerate(c, L)) return sampled_toi<false>(e0, e1, 1e-12 * L);
+    double roots[4];
+    int nr = roots01(c, roots);
+    for (int i = 0; i < nr; ++i) {
+        double t = roots[i];
+        int r = seg_cross(lerp(e0[0], e1[0], t), lerp(e0[1], e1[1], t), lerp(e0[2], e1[2], t), lerp(e0[3], e1[3], t));
+        if (r < 0) return sampled_toi<false>(e0, e1, 1e-12 * L);
+        if (r) return t;
+    }
+    return NOHIT;
+}
+
+__device__ __forceinline__ void pair_points(const Dev& d, bool vt, int i, int j, const float* X, d3* q) {
+    const int n = d.nv;
+    if (vt) {
+        TriRec tr = d.tri[j];
+        q[0] = ld3(X, n, i);
+        q[1] = ld3(X, n, tr.v0);
+        q[2] = ld3(X, n, tr.v1);
+        q[3] = ld3(X, n, tr.v2);
+    } else {
+        q[0] = ld3(X, n, d.edges[2 * i]);
+        q[1] = ld3(X, n, d.edges[2 * i + 1]);
+        q[2] = ld3(X, n, d.edges[2 * j]);
+        q[3] = ld3(X, n, d.edges[2 * j + 1]);
+    }
+}
+
+__device__ __forceinline__ void pair_ids(const Dev& d, bool vt, int i, int j, int* id) {
+    if (vt) {
+        TriRec tr = d.tri[j];
+        id[0] = i; id[1] = tr.v0; id[2] = tr.v1; id[3] = tr.v2;
+    } else {
+        id[0] = d.edges[2 * i]; id[1] = d.edges[2 * i + 1]; id[2] = d.edges[2 * j]; id[3] = d.edges[2 * j + 1];
+    }
+}
+
+// obstacle: signed distance and radial vector (FP64)
+__device__ __forceinline__ double obst_phi(const ObstD& o, d3 x, d3& rv, double& rad) {
+    d3 c = mk(o.c[0], o.c[1], o.c[2]);
+    rv = x - c;
+    if (o.kind == CLOTH_CYLINDER) {
+        d3 a = mk(o.a[0], o.a[1], o.a[2]);
+        rv = rv - a * dot(rv, a);
+    }
+    rad = sqrt(dot(rv, rv));
+    return rad - o.R;
+}
+
+__device__ double obst_toi(const ObstD& o, d3 xm, d3 xp) {
+    d3 dd = xp - xm, oo = xm - mk(o.c[0], o.c[1], o.c[2]);
+    if (o.kind == CLOTH_CYLINDER) {
+        d3 a = mk(o.a[0], o.a[1], o.a[2]);
+        dd = dd - a * dot(dd, a);
+        oo = oo - a * dot(oo, a);
+    }
+    double A = dot(dd, dd), B = 2 * dot(oo, dd), C = dot(oo, oo) - o.R * o.R;
+    double disc = B * B - 4 * A * C;
+    if (!(C > 0 && B < 0 && disc >= 0 && A > 0)) return NOHIT;
+    double q = 0.5 * (-B + sqrt(disc));
+    double t = C / q;
+    return t <= 1.0 ? t : NOHIT;
+}
+
+}  // namespace
+
+// ================================================================ scans
+// Exclusive prefix sums over n = min(n_dev ? *n_dev : n_host, cap) ints.
+__global__ void k_scan_tiles(const int* __restrict__ in, int n_host, const int* __restrict__ n_dev, int* tiles) {
+    __shared__ int red[256];
+    int n = n_dev ? *n_dev : n_host;
+    int base = blockIdx.x * SCAN_TILE;
+    int s = 0;
+    if (base < n)
+        for (int i = threadIdx.x; i < SCAN_TILE; i += 256) {
+            int g = base + i;
+            if (g < n) s += in[g];
+        }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tiles[blockIdx.x] = red[0];
+}
+
+// single block: exclusive scan of the tile sums in place; total -> *total
+__global__ void k_scan_top(int* tiles, int ntiles, int* total) {
+    __shared__ int part[1024];
+    int per = (ntiles + 1023) / 1024;
+    int b0 = threadIdx.x * per, b1 = min(ntiles, b0 + per);
+    int s = 0;
+    for (int i = b0; i < b1; ++i) s += tiles[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int i = b0; i < b1; ++i) {
+        int t = tiles[i];
+        tiles[i] = run;
+        run += t;
+    }
+    if (threadIdx.x == 1023 && total) *total = part[1023];
+}
+
+__global__ void k_scan_apply(const int* __restrict__ in, int n_host, const int* __restrict__ n_dev,
+                             const int* __restrict__ tiles, int* __restrict__ out) {
+    __shared__ int ts[256];
+    int n = n_dev ? *n_dev : n_host;
+    int base = blockIdx.x * SCAN_TILE;
+    if (base >= n) return;
+    // each thread owns 8 consecutive items
+    int v[8];
+    int s = 0;
+    for (int k = 0; k < 8; ++k) {
+        int g = base + threadIdx.x * 8 + k;
+        v[k] = g < n ? in[g] : 0;
+        s += v[k];
+    }
+    ts[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        int t = threadIdx.x >= o ? ts[threadIdx.x - o] : 0;
+        __syncthreads();
+        ts[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = tiles[blockIdx.x] + (threadIdx.x ? ts[threadIdx.x - 1] : 0);
+    for (int k = 0; k < 8; ++k) {
+        int g = base + threadIdx.x * 8 + k;
+        if (g < n) out[g] = run;
+        run += v[k];
+    }
+}
+
+// out[i] = exclusive prefix of in[0..i); out may alias in only through `tmp`.
+static hipError_t scan_exclusive(const int* in, int* out, int n_cap, const int* n_dev, int* tiles, int* total,
+                                 hipStream_t st) {
+    int nt = (n_cap + SCAN_TILE - 1) / SCAN_TILE;
+    if (nt == 0) nt = 1;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st, in, n_cap, n_dev, tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tiles, nt, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(256), 0, st, in, n_cap, n_dev, tiles, out);
+    return hipGetLastError();
+}
+
+// ================================================================ broad phase
+
+__global__ void k_fill_i32(int* p, int v, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Swept boxes over (xm, xp) grown by dhat (FP32) and the widest box per axis.
+__global__ void k_boxes(Dev d, const float* __restrict__ xm, const float* __restrict__ xp, float dhat,
+                        float* vbox, float* tbox, float* ebox, unsigned* maxext) {
+    const int n = d.nv;
+    int total = d.nv + d.nt + d.ne;
+    float wl[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        int ids[3];
+        int nvert;
+        float* out;
+        int kind;
+        if (i < d.nv) {
+            ids[0] = i;
+            nvert = 1;
+            out = vbox + 6 * (size_t)i;
+            kind = 0;
+        } else if (i < d.nv + d.nt) {
+            int t = i - d.nv;
+            TriRec tr = d.tri[t];
+            ids[0] = tr.v0; ids[1] = tr.v1; ids[2] = tr.v2;
+            nvert = 3;
+            out = tbox + 6 * (size_t)t;
+            kind = 1;
+        } else {
+            int e = i - d.nv - d.nt;
+            ids[0] = d.edges[2 * e];
+            ids[1] = d.edges[2 * e + 1];
+            nvert = 2;
+            out = ebox + 6 * (size_t)e;
+            kind = 2;
+        }
+        for (int c = 0; c < 3; ++c) {
+            float lo = xm[c * n + ids[0]], hi = lo;
+            for (int k = 0; k < nvert; ++k) {
+                float a = xm[c * n + ids[k]], b = xp[c * n + ids[k]];
+                lo = fminf(lo, fminf(a, b));
+                hi = fmaxf(hi, fmaxf(a, b));
+            }
+            float l = lo - dhat, h = hi + dhat;
+            out[c] = l;
+            out[3 + c] = h;
+            if (kind == 1) wl[c] = fmaxf(wl[c], h - l);
+            if (kind == 2) wl[3 + c] = fmaxf(wl[3 + c], h - l);
+        }
+    }
+    for (int c = 0; c < 6; ++c) {
+        float w = wl[c];
+        for (int o = 32; o > 0; o >>= 1) w = fmaxf(w, __shfl_xor(w, o));
+        if ((threadIdx.x & 63) == 0 && w > 0) atomicMax(&maxext[c], __float_as_uint(w));
+    }
+}
+
+// low-corner cell of each box and bucket counts
+__global__ void k_cells(int m, const float* __restrict__ box, const unsigned* __restrict__ maxext, int* cell,
+                        int* bucket_cnt, int P) {
+    float cs[3] = {cs_of(maxext, 0), cs_of(maxext, 1), cs_of(maxext, 2)};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        int c0 = cell_of(box[6 * (size_t)i], cs[0]), c1 = cell_of(box[6 * (size_t)i + 1], cs[1]),
+            c2 = cell_of(box[6 * (size_t)i + 2], cs[2]);
+        cell[3 * (size_t)i] = c0;
+        cell[3 * (size_t)i + 1] = c1;
+        cell[3 * (size_t)i + 2] = c2;
+        atomicAdd(&bucket_cnt[hash3(c0, c1, c2) & (P - 1)], 1);
+    }
+}
+
+__global__ void k_bucket_fill(int m, const int* __restrict__ cell, int P, int* cursor, int* items) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        unsigned b = hash3(cell[3 * (size_t)i], cell[3 * (size_t)i + 1], cell[3 * (size_t)i + 2]) & (P - 1);
+        int pos = atomicAdd(&cursor[b], 1);
+        items[pos] = i;
+    }
+}
+
+// Query of one box against the hashed targets.  VT: query = vertex v, targets
+// = triangles (skip incident); EE: query = edge e, targets = edges f > e
+// sharing no vertex.  WRITE = false counts, true writes at ofs[q] and sorts.
+template <bool VT, bool WRITE>
+__global__ void k_query(Dev d, const float* __restrict__ qbox, const float* __restrict__ tbox,
+                        const int* __restrict__ tcell, const unsigned* __restrict__ maxext_t, const int* bptr,
+                        const int* bitem, int P, int* count, int2* out, int64_t cap, int* overflow) {
+    const int nq = VT ? d.nv : d.ne;
+    float cs[3] = {cs_of(maxext_t, 0), cs_of(maxext_t, 1), cs_of(maxext_t, 2)};
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const float* qb = qbox + 6 * (size_t)q;
+        int qa = -1, qb2 = -1;
+        if (!VT) {
+            qa = d.edges[2 * q];
+            qb2 = d.edges[2 * q + 1];
+        }
+        int lo[3], hi[3];
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = cell_of(qb[c], cs[c]) - 2;
+            hi[c] = cell_of(qb[3 + c], cs[c]);
+        }
+        int cnt = 0;
+        int base = WRITE ? count[q] : 0;
+        for (int ix = lo[0]; ix <= hi[0]; ++ix)
+            for (int iy = lo[1]; iy <= hi[1]; ++iy)
+                for (int iz = lo[2]; iz <= hi[2]; ++iz) {
+                    unsigned b = hash3(ix, iy, iz) & (P - 1);
+                    for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
+                        int t = bitem[k];
+                        if (tcell[3 * (size_t)t] != ix || tcell[3 * (size_t)t + 1] != iy ||
+                            tcell[3 * (size_t)t + 2] != iz)
+                            continue;
+                        if (VT) {
+                            TriRec tr = d.tri[t];
+                            if (tr.v0 == q || tr.v1 == q || tr.v2 == q) continue;
+                        } else {
+                            if (t <= q) continue;
+                            int f0 = d.edges[2 * t], f1 = d.edges[2 * t + 1];
+                            if (f0 == qa || f0 == qb2 || f1 == qa || f1 == qb2) continue;
+                        }
+                        if (!overlap6(qb, tbox + 6 * (size_t)t)) continue;
+                        if (WRITE) {
+                            int64_t pos = (int64_t)base + cnt;
+                            if (pos < cap) out[pos] = make_int2(q, t);
+                        }
+                        ++cnt;
+                    }
+                }
+        if (!WRITE) {
+            count[q] = cnt;
+        } else {
+            int64_t b0 = base, b1 = (int64_t)base + cnt;
+            if (b1 > cap) {
+                atomicExch(overflow, 1);
+                b1 = cap;
+            }
+            for (int64_t i = b0 + 1; i < b1; ++i) {  // insertion sort by target id
+                int2 key = out[i];
+                int64_t j = i - 1;
+                while (j >= b0 && out[j].y > key.y) {
+                    out[j + 1] = out[j];
+                    --j;
+                }
+                out[j + 1] = key;
+            }
+        }
+    }
+}
+
+// total of the last count + last offset -> n (clamped to cap), overflow flag
+__global__ void k_count_total(const int* counts_scanned, const int* counts_raw, int m, int* n_out, int64_t cap,
+                              int* overflow) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        long long tot = m > 0 ? (long long)counts_scanned[m - 1] + counts_raw[m - 1] : 0;
+        if (tot > cap) {
+            *overflow = 1;
+            tot = cap;
+        }
+        *n_out = (int)tot;
+    }
+}
+
+// ================================================================ TOI + merge
+// For candidate i (VT in [0, n_vt), EE after): TOI, whether it was in the
+// previous constraint set (binary search on the sorted previous list), the
+// keep flag (TOI <= 1 or present before) and the carried life span.
+__global__ void k_toi_merge(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
+                            const int2* __restrict__ cvt, const int2* __restrict__ cee, const int* cnt,
+                            double* toi_vt, double* toi_ee, const int2* __restrict__ prev, const int* __restrict__ prev_a,
+                            int* keep, int* cand_a, unsigned long long* tmin_bits, int do_merge) {
+    __shared__ double wmin[4];
+    const int nvt = cnt[0], nee = cnt[1];
+    const int pvt = cnt[4], pee = cnt[5];
+    double tmin = NOHIT;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nvt + nee; i += gridDim.x * blockDim.x) {
+        bool vt = i < nvt;
+        int2 pr = vt ? cvt[i] : cee[i - nvt];
+        d3 q0[4], q1[4];
+        pair_points(d, vt, pr.x, pr.y, xm, q0);
+        pair_points(d, vt, pr.x, pr.y, xp, q1);
+        double t = vt ? pair_toi_vt(q0, q1) : pair_toi_ee(q0, q1);
+        if (vt) toi_vt[i] = t; else toi_ee[i - nvt] = t;
+        tmin = fmin(tmin, t);
+        if (do_merge) {
+            // binary search in the previous list of the same type
+            int lo = vt ? 0 : pvt, hi = vt ? pvt : pvt + pee;
+            long long key = ((long long)pr.x << 32) | (unsigned)pr.y;
+            int found = -1;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                int2 p = prev[mid];
+                long long k2 = ((long long)p.x << 32) | (unsigned)p.y;
+                if (k2 < key) lo = mid + 1;
+                else hi = mid;
+            }
+            int end = vt ? pvt : pvt + pee;
+            if (lo < end) {
+                int2 p = prev[lo];
+                if (p.x == pr.x && p.y == pr.y) found = lo;
+            }
+            keep[i] = (t <= 1.0 || found >= 0) ? 1 : 0;
+            cand_a[i] = found >= 0 ? prev_a[found] : 0;
+        }
+    }
+    tmin = warp_min(tmin);
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+        atomicMin(tmin_bits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// obstacles: TOI on (xm, xp) and membership with carried life spans
+__global__ void k_obstacles_outer(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
+                                  unsigned long long* tmin_bits, int* n_ob) {
+    __shared__ double wmin[4];
+    const int nob = d.nob;
+    const ObstD* ob = d.ob;
+    int* ob_a = d.ob_a;
+    const double dhat = d.dhat;
+    int members = 0;
+    const int n = d.nv;
+    double tmin = NOHIT;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        d3 a = ld3(xm, n, v), b = ld3(xp, n, v);
+        for (int j = 0; j < nob; ++j) {
+            double t = obst_toi(ob[j], a, b);
+            tmin = fmin(tmin, t);
+            d3 rv;
+            double rad;
+            double pm = obst_phi(ob[j], a, rv, rad), pp = obst_phi(ob[j], b, rv, rad);
+            bool mem = !d.pinned[v] && (t <= 1.0 || pm < dhat || pp < dhat);
+            int prev = ob_a[(size_t)j * n + v];
+            ob_a[(size_t)j * n + v] = mem ? (prev >= 0 ? prev : 0) : -1;
+            members += mem;
+        }
+    }
+    if (members) atomicAdd(n_ob, members);
+    tmin = warp_min(tmin);
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+        atomicMin(tmin_bits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// s = 1 (no hit) or alpha * t_TOI; running minimum for the statistics
+__global__ void k_step_length(unsigned long long* tmin_bits, double alpha, double* s_dev) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double t = __longlong_as_double((long long)tmin_bits[0]);
+        s_dev[0] = t > 1.0 ? 1.0 : alpha * t;
+        if (tmin_bits[0] < tmin_bits[1]) tmin_bits[1] = tmin_bits[0];
+        tmin_bits[0] = (unsigned long long)__double_as_longlong(NOHIT);
+    }
+}
+
+// compaction of kept candidates into the new constraint list (order kept)
+__global__ void k_compact(const int2* __restrict__ cvt, const int2* __restrict__ cee, int* cnt,
+                          const int* __restrict__ keep, const int* __restrict__ ofs, const int* __restrict__ cand_a,
+                          int2* cpair, int* ca) {
+    const int nvt = cnt[0], nee = cnt[1];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nvt + nee; i += gridDim.x * blockDim.x) {
+        if (keep[i]) {
+            int o = ofs[i];
+            cpair[o] = i < nvt ? cvt[i] : cee[i - nvt];
+            ca[o] = cand_a[i];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int tot = nvt + nee;
+        int nk = tot > 0 ? ofs[tot - 1] + keep[tot - 1] : 0;
+        int nk_vt = nvt > 0 ? (nvt < tot ? ofs[nvt] : nk) : 0;
+        cnt[2] = nk_vt;
+        cnt[3] = nk - nk_vt;
+    }
+}
+
+// ================================================================ frozen data
+// Closest-point parameters and normals at x- (start of the block).
+__global__ void k_freeze(Dev d, const int* cnt, const int2* __restrict__ cpair, double2* clam, float4* cnrm) {
+    const int nvt = cnt[2], nc = cnt[2] + cnt[3];
+    const int n = d.nv;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        int2 pr = cpair[p];
+        d3 q[4];
+        pair_points(d, p < nvt, pr.x, pr.y, d.xm, q);
+        double l1, l2;
+        d3 nn;
+        if (p < nvt) {
+            tri_closest(q[0], q[1], q[2], q[3], l1, l2);
+            nn = cross(q[2] - q[1], q[3] - q[1]);
+            double nl = sqrt(dot(nn, nn));
+            nn = nl > 0 ? nn * (1.0 / nl) : mk(0, 1, 0);
+            if (dot(nn, q[0] - q[1]) < 0) nn = nn * -1.0;
+        } else {
+            seg_closest(q[0], q[1], q[2], q[3], l1, l2);
+            d3 dd = lerp(q[2], q[3], l2) - lerp(q[0], q[1], l1);
+            double dl = sqrt(dot(dd, dd));
+            if (dl > 0) {
+                nn = dd * (1.0 / dl);
+            } else {
+                nn = cross(q[1] - q[0], q[3] - q[2]);
+                double nl = sqrt(dot(nn, nn));
+                nn = nl > 0 ? nn * (1.0 / nl) : mk(0, 1, 0);
+            }
+        }
+        clam[p] = make_double2(l1, l2);
+        cnrm[p] = make_float4((float)nn.x, (float)nn.y, (float)nn.z, 0.f);
+        (void)n;
+    }
+}
+
+// vertex -> slot incidence (slot = 4 * constraint + corner)
+__global__ void k_slot_count(Dev d, const int* cnt, const int2* __restrict__ cpair, int* vcnt) {
+    const int nvt = cnt[2], nc = cnt[2] + cnt[3];
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        int2 pr = cpair[p];
+        int id[4];
+        pair_ids(d, p < nvt, pr.x, pr.y, id);
+        for (int k = 0; k < 4; ++k) atomicAdd(&vcnt[id[k]], 1);
+    }
+}
+
+__global__ void k_slot_fill(Dev d, const int* cnt, const int2* __restrict__ cpair, int* cursor, int* vslot) {
+    const int nvt = cnt[2], nc = cnt[2] + cnt[3];
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        int2 pr = cpair[p];
+        int id[4];
+        pair_ids(d, p < nvt, pr.x, pr.y, id);
+        for (int k = 0; k < 4; ++k) vslot[atomicAdd(&cursor[id[k]], 1)] = 4 * p + k;
+    }
+}
+
+// sort each vertex's slots (deterministic accumulation order) and flag
+// contact vertices (in a pair constraint or an obstacle constraint)
+__global__ void k_slot_sort(Dev d, const int* __restrict__ ptr, int* vslot, const int* __restrict__ ob_a, int nob,
+                            int* flag) {
+    const int n = d.nv;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        int b0 = ptr[v], b1 = ptr[v + 1];
+        for (int i = b0 + 1; i < b1; ++i) {
+            int key = vslot[i], j = i - 1;
+            while (j >= b0 && vslot[j] > key) {
+                vslot[j + 1] = vslot[j];
+                --j;
+            }
+            vslot[j + 1] = key;
+        }
+        bool f = b1 > b0;
+        for (int j = 0; j < nob; ++j) f |= ob_a[(size_t)j * n + v] >= 0;
+        flag[v] = (f && !d.pinned[v]) ? 1 : 0;
+    }
+}
+
+__global__ void k_cv_compact(int n, const int* __restrict__ flag, const int* __restrict__ ofs, int* list, int* n_out) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (flag[v]) list[ofs[v]] = v;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = n > 0 ? ofs[n - 1] + flag[n - 1] : 0;
+}
+
+// ================================================================ per iteration
+// Targets of the pair constraints at x^k: half-space projection with the
+// frozen normal and closest-point parameters (minimum-norm correction over
+// movable vertices), weight w = k * 2^a (Eq. (exp) with K = 2; other K use powf).
+__global__ void k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ cpair, const int* __restrict__ ca,
+                               const double2* __restrict__ clam, const float4* __restrict__ cnrm, float kc, float Kb,
+                               float dhat, float4* slot) {
+    const int nvt = cnt[2], nc = cnt[2] + cnt[3];
+    const int n = d.nv;
+    const float* X = d.xk;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        int2 pr = cpair[p];
+        int id[4];
+        pair_ids(d, p < nvt, pr.x, pr.y, id);
+        float l1 = (float)clam[p].x, l2 = (float)clam[p].y;
+        float c[4];
+        if (p < nvt) {
+            c[0] = 1.f; c[1] = -(1.f - l1 - l2); c[2] = -l1; c[3] = -l2;
+        } else {
+            c[0] = -(1.f - l1); c[1] = -l1; c[2] = 1.f - l2; c[3] = l2;
+        }
+        float4 nr = cnrm[p];
+        float gx = -dhat, den = 0.f;
+        float xs[4][3];
+        float cm[4];
+        for (int k = 0; k < 4; ++k) {
+            xs[k][0] = X[id[k]]; xs[k][1] = X[n + id[k]]; xs[k][2] = X[2 * n + id[k]];
+            gx += c[k] * (nr.x * xs[k][0] + nr.y * xs[k][1] + nr.z * xs[k][2]);
+            cm[k] = d.pinned[id[k]] ? 0.f : c[k];
+            den += cm[k] * cm[k];
+        }
+        float delta = (gx < 0.f && den > 0.f) ? -gx / den : 0.f;
+        int a = ca[p];
+        float w = (Kb == 2.0f) ? ldexpf(kc, a) : kc * powf(Kb, (float)a);
+        for (int k = 0; k < 4; ++k) {
+            float s = cm[k] * delta;
+            slot[4 * (size_t)p + k] = make_float4(w, w * (xs[k][0] + s * nr.x), w * (xs[k][1] + s * nr.y),
+                                                  w * (xs[k][2] + s * nr.z));
+        }
+    }
+}
+
+// Partial CCD on (x-, x^{k+1}): active when Q(lambda) <= 0 at a sample
+// (three fixed samples plus the frozen closest point); a <- active ?
+// min(a+1, a_max) : 0.  Obstacles: active when phi(x^{k+1}) < d_hat.
+__global__ void k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cpair, int* ca,
+                              const double2* __restrict__ clam, int amax, const float* __restrict__ xnew) {
+    const int nob = d.nob;
+    const ObstD* ob = d.ob;
+    int* ob_a = d.ob_a;
+    const double dhat = d.dhat;
+    const int nvt = cnt[2], nc = cnt[2] + cnt[3];
+    const int n = d.nv;
+    const double svt[3][2] = {{1.0 / 6, 1.0 / 6}, {2.0 / 3, 1.0 / 6}, {1.0 / 6, 2.0 / 3}};
+    const double see[3][2] = {{0.25, 0.25}, {0.5, 0.5}, {0.75, 0.75}};
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc + n; p += gridDim.x * blockDim.x) {
+        if (p < nc) {
+            int2 pr = cpair[p];
+            bool vt = p < nvt;
+            d3 q0[4], q1[4];
+            pair_points(d, vt, pr.x, pr.y, d.xm, q0);
+            pair_points(d, vt, pr.x, pr.y, xnew, q1);
+            bool act = false;
+            for (int s = 0; s < 4; ++s) {
+                double l1, l2;
+                if (s < 3) {
+                    l1 = vt ? svt[s][0] : see[s][0];
+                    l2 = vt ? svt[s][1] : see[s][1];
+                } else {
+                    l1 = clam[p].x;
+                    l2 = clam[p].y;
+                }
+                d3 a0, a1;
+                if (vt) {
+                    d3 p20 = q0[1] + (q0[2] - q0[1]) * l1 + (q0[3] - q0[1]) * l2;
+                    d3 p21 = q1[1] + (q1[2] - q1[1]) * l1 + (q1[3] - q1[1]) * l2;
+                    a0 = p20 - q0[0];
+                    a1 = p21 - q1[0];
+                } else {
+                    a0 = (q0[2] + (q0[3] - q0[2]) * l2) - (q0[0] + (q0[1] - q0[0]) * l1);
+                    a1 = (q1[2] + (q1[3] - q1[2]) * l2) - (q1[0] + (q1[1] - q1[0]) * l1);
+                }
+                act |= dot(a1, a0) <= 0.0;
+            }
+            int a = ca[p];
+            ca[p] = act ? min(a + 1, amax) : 0;
+        } else {
+            int v = p - nc;
+            d3 x = ld3(xnew, n, v);
+            for (int j = 0; j < nob; ++j) {
+                int a = ob_a[(size_t)j * n + v];
+                if (a < 0) continue;
+                d3 rv;
+                double rad;
+                bool act = obst_phi(ob[j], x, rv, rad) < dhat;
+                ob_a[(size_t)j * n + v] = act ? min(a + 1, amax) : 0;
+            }
+        }
+    }
+}
+
+// U^T diag(W) U over the contact vertices: chunk c of the vertex list,
+// upper triangle (i <= j) of the r x r partial, FP32 accumulation.
+template <typename UT>
+__global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
+                                            int nchunk, float* part) {
+    __shared__ float us[32][257];
+    __shared__ float ws[32];
+    const int r = d.r;
+    const int ncv = *n_cv;
+    const int per = (ncv + nchunk - 1) / nchunk;
+    const int c0 = blockIdx.x * per, c1 = min(ncv, c0 + per);
+    const int nent = r * (r + 1) / 2;
+    constexpr int MAXE = 33;  // entries per thread for r <= 128 (8256 / 256)
+    float acc[MAXE];
+    int ei[MAXE], ej[MAXE];
+    int ne = 0;
+    for (int e = threadIdx.x; e < nent && ne < MAXE; e += 256) {
+        // row-major upper triangle index -> (i, j)
+        int i = 0, rem = e;
+        while (rem >= r - i) {
+            rem -= r - i;
+            ++i;
+        }
+        ei[ne] = i;
+        ej[ne] = i + rem;
+        acc[ne] = 0.f;
+        ++ne;
+    }
+    const UT* U = static_cast<const UT*>(d.U);
+    for (int base = c0; base < c1; base += 32) {
+        int m = min(32, c1 - base);
+        __syncthreads();
+        for (int q = threadIdx.x; q < 32 * r; q += 256) {
+            int vv = q / r, cc = q % r;
+            float u = 0.f;
+            if (vv < m) {
+                int v = cvlist[base + vv];
+                UT raw = U[(size_t)v * r + cc];
+                if constexpr (sizeof(UT) == 2) u = __uint_as_float((uint32_t)raw << 16);
+                else u = (float)raw;
+            }
+            us[vv][cc] = u;
+        }
+        if (threadIdx.x < 32) ws[threadIdx.x] = threadIdx.x < m ? d.W[cvlist[base + threadIdx.x]] : 0.f;
+        __syncthreads();
+        for (int vv = 0; vv < m; ++vv) {
+            float w = ws[vv];
+            for (int q = 0; q < ne; ++q) acc[q] += w * us[vv][ei[q]] * us[vv][ej[q]];
+        }
+    }
+    for (int q = 0; q < ne; ++q) {
+        size_t o = (size_t)blockIdx.x * r * r + (size_t)ei[q] * r + ej[q];
+        part[o] = acc[q];
+    }
+}
+
+// One workgroup: A = Lambda~ + sum of Gram chunks (FP64), in-place Cholesky
+// (one barrier per column), then q = A^{-1} g by two triangular solves.
+__global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const float* __restrict__ part, int nchunk,
+                                                   const double* __restrict__ g, const int* __restrict__ n_cv) {
+    extern __shared__ double A[];
+    const int r = d.r;
+    double* y = A + (size_t)r * r;  // r * 3
+    double* dsq = y + (size_t)r * 3;  // r
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (*n_cv == 0) {  // no contact vertex: A = Lambda~, use its inverse
+        for (int o = tid; o < r * 3; o += nt) {
+            int c = o / 3, k = o % 3;
+            double acc = 0.0;
+            for (int j = 0; j < r; ++j) acc += d.Ainv[(size_t)c * r + j] * g[j * 3 + k];
+            d.Qd[o] = acc;
+            d.Qf[o] = (float)acc;
+        }
+        return;
+    }
+    for (int e = tid; e < r * r; e += nt) {
+        int i = e / r, j = e % r;
+        int a = min(i, j), b = max(i, j);
+        double s = d.Lam[e];
+        for (int c = 0; c < nchunk; ++c) s += (double)part[(size_t)c * r * r + (size_t)a * r + b];
+        A[e] = s;
+    }
+    for (int e = tid; e < r * 3; e += nt) y[e] = g[e];
+    __syncthreads();
+    // right-looking: at step k every thread updates its (i, j), k < j <= i,
+    // from column k (not modified during step k)
+    for (int k = 0; k < r; ++k) {
+        double akk = A[(size_t)k * r + k];
+        double inv = 1.0 / akk;
+        int m = r - k - 1;
+        int tot = m * (m + 1) / 2;
+        for (int e = tid; e < tot; e += nt) {
+            // (i, j) with k < j <= i: enumerate rows i = k+1.. with j = k+1..i
+            int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+            while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+            while (ii * (ii + 1) / 2 > e) --ii;
+            int jj = e - ii * (ii + 1) / 2;
+            int i = k + 1 + ii, j = k + 1 + jj;
+            A[(size_t)i * r + j] -= A[(size_t)i * r + k] * A[(size_t)j * r + k] * inv;
+        }
+        __syncthreads();
+    }
+    // L(i,k) = A(i,k) / sqrt(A(k,k)) for i >= k (the diagonal becomes sqrt(A(k,k)))
+    for (int k = tid; k < r; k += nt) dsq[k] = sqrt(A[(size_t)k * r + k]);
+    __syncthreads();
+    for (int e = tid; e < r * r; e += nt) {
+        int i = e / r, k = e % r;
+        if (i >= k) A[e] = A[e] / dsq[k];
+    }
+    __syncthreads();
+    // forward: L y = g
+    for (int k = 0; k < r; ++k) {
+        if (tid < 3) y[k * 3 + tid] /= A[(size_t)k * r + k];
+        __syncthreads();
+        for (int e = tid; e < (r - k - 1) * 3; e += nt) {
+            int i = k + 1 + e / 3, c = e % 3;
+            y[i * 3 + c] -= A[(size_t)i * r + k] * y[k * 3 + c];
+        }
+        __syncthreads();
+    }
+    // backward: L^T q = y
+    for (int k = r - 1; k >= 0; --k) {
+        if (tid < 3) y[k * 3 + tid] /= A[(size_t)k * r + k];
+        __syncthreads();
+        for (int e = tid; e < k * 3; e += nt) {
+            int i = e / 3, c = e % 3;
+            y[i * 3 + c] -= A[(size_t)k * r + i] * y[k * 3 + c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < r * 3; e += nt) {
+        d.Qd[e] = y[e];
+        d.Qf[e] = (float)y[e];
+    }
+}
+
+
+__global__ void k_copy_i32(int* __restrict__ dst, const int* __restrict__ src, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+// previous constraint set <- current (count from device)
+__global__ void k_save_prev(int* cnt, const int2* __restrict__ cp, const int* __restrict__ a, int2* pp, int* pa,
+                            int first) {
+    const int nc = first ? 0 : cnt[2] + cnt[3];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+        pp[i] = cp[i];
+        pa[i] = a[i];
+    }
+}
+
+// bookkeeping of the device counters at the start of an outer stage
+__global__ void k_stage_counters(int* cnt, int first, unsigned long long* tmin_bits) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cnt[4] = first ? 0 : cnt[2];
+        cnt[5] = first ? 0 : cnt[3];
+        cnt[0] = 0;
+        cnt[1] = 0;
+        cnt[10] = 0;
+        if (first) {
+            cnt[7] = 0;
+            tmin_bits[1] = (unsigned long long)__double_as_longlong(NOHIT);
+        }
+        tmin_bits[0] = (unsigned long long)__double_as_longlong(NOHIT);
+    }
+}
+
+__global__ void k_sum2(int* cnt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) cnt[9] = cnt[0] + cnt[1];
+}
+
+// ================================================================ host side
+
+static inline int gblocks(int64_t n) {
+    int64_t b = (n + TPB - 1) / TPB;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, GRID_LOOP));
+}
+
+#define HC(expr)                                                                                        \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return set_error(CLOTH_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+bool contact_enabled(const Scene& s, const ContactState& c) { return c.nob > 0 || s.self_contact; }
+
+cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
+    const int n = s.nv;
+    c.cap = s.pair_cap;
+    int P = 1;
+    while (P < 2 * std::max(s.nt, s.ne)) P <<= 1;
+    c.hash_p = P;
+    int64_t maxscan = std::max<int64_t>({2 * c.cap, (int64_t)n + 1, (int64_t)s.ne + 1, (int64_t)P + 1});
+    c.ntiles_cap = (int)((maxscan + SCAN_TILE - 1) / SCAN_TILE) + 1;
+    auto I = [&](size_t k) { return static_cast<int*>(carve(sizeof(int) * k)); };
+    c.gpart2 = static_cast<double*>(carve(sizeof(double) * ((size_t)(s.nblk + 31) / 32 + 1) * s.r * 3));
+    c.gvec = static_cast<double*>(carve(sizeof(double) * s.r * 3));
+    c.cnt = I(16);
+    c.tmin_bits = static_cast<unsigned long long*>(carve(16));
+    c.s_dev = static_cast<double*>(carve(8));
+    c.scan_tiles = I(c.ntiles_cap);
+    c.ob_a = I((size_t)MAX_OBST * n);
+    c.ob_dev = static_cast<ObstD*>(carve(sizeof(ObstD) * MAX_OBST));
+    if (!c.gpart2 || !c.gvec || !c.cnt || !c.tmin_bits || !c.s_dev || !c.scan_tiles || !c.ob_a || !c.ob_dev)
+        return set_error(CLOTH_E_OOM, "arena exhausted (contact scalars)");
+    Dev& d = s.d;
+    d.gvec = c.gvec;
+    d.ob_a = c.ob_a;
+    d.ob = c.ob_dev;
+    d.nob = 0;
+    d.kc = (float)s.kc;
+    d.Kb = (float)s.Kb;
+    d.dhat = s.dhat;
+    c.enabled = contact_enabled(s, c);
+    // pair buffers only when self contact is on; obstacles need only per-vertex data
+    int64_t pc = s.self_contact ? c.cap : 1;
+    c.cap = pc;
+    c.vbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? n : 1)));
+    c.tbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? s.nt : 1)));
+    c.ebox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? s.ne : 1)));
+    c.tcell = I(3 * (size_t)(s.self_contact ? s.nt : 1));
+    c.ecell = I(3 * (size_t)(s.self_contact ? s.ne : 1));
+    c.bucket_cnt = I((size_t)P + 1);
+    c.bucket_ptr = I((size_t)P + 1);
+    c.bucket_item = I((size_t)std::max(s.nt, s.ne));
+    c.maxext = static_cast<unsigned*>(carve(sizeof(unsigned) * 8));
+    c.vcount = I((size_t)n + 1);
+    c.ecount = I((size_t)s.ne + 1);
+    c.cand_vt = static_cast<int2*>(carve(sizeof(int2) * pc));
+    c.cand_ee = static_cast<int2*>(carve(sizeof(int2) * pc));
+    c.toi_vt = static_cast<double*>(carve(sizeof(double) * pc));
+    c.toi_ee = static_cast<double*>(carve(sizeof(double) * pc));
+    c.keep = I(std::max<int64_t>(2 * pc, (int64_t)std::max(n, s.ne) + 1));
+    c.keep_ofs = I(2 * pc);
+    c.cand_a = I(2 * pc);
+    c.cpair = static_cast<int2*>(carve(sizeof(int2) * 2 * pc));
+    c.cpair_prev = static_cast<int2*>(carve(sizeof(int2) * 2 * pc));
+    c.ca = I(2 * pc);
+    c.ca_prev = I(2 * pc);
+    c.clam = static_cast<double2*>(carve(sizeof(double2) * 2 * pc));
+    c.cnrm = static_cast<float4*>(carve(sizeof(float4) * 2 * pc));
+    c.slot = static_cast<float4*>(carve(sizeof(float4) * 8 * pc));
+    c.vslot_ptr = I((size_t)n + 1);
+    c.vslot_fill = I((size_t)n + 1);
+    c.vslot = I(8 * pc);
+    c.cvlist = I((size_t)n + 1);
+    c.cvflag = I((size_t)n + 1);
+    c.cvofs = I((size_t)n + 1);
+    if (!c.vbox || !c.tbox || !c.ebox || !c.tcell || !c.ecell || !c.bucket_cnt || !c.bucket_ptr ||
+        !c.bucket_item || !c.maxext || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
+        !c.toi_ee || !c.keep || !c.keep_ofs || !c.cand_a || !c.cpair || !c.cpair_prev || !c.ca ||
+        !c.ca_prev || !c.clam || !c.cnrm || !c.slot || !c.vslot_ptr || !c.vslot_fill || !c.vslot || !c.cvlist ||
+        !c.cvflag || !c.cvofs)
+        return set_error(CLOTH_E_OOM, "arena exhausted (contact buffers)");
+    d.vslot_ptr = c.vslot_ptr;
+    d.vslot = c.vslot;
+    d.slot = c.slot;
+    c.gram_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, (n + 2047) / 2048));
+    return CLOTH_OK;
+}
+
+cloth_status contact_upload(Scene& s, ContactState& c) {
+    const int n = s.nv;
+    HC(hipMemset(c.cnt, 0, sizeof(int) * 16));
+    HC(hipMemset(c.ob_a, 0xff, sizeof(int) * (size_t)MAX_OBST * n));
+    std::vector<unsigned long long> tb = {0x4000000000000000ull, 0x4000000000000000ull};  // 2.0
+    HC(hipMemcpy(c.tmin_bits, tb.data(), 16, hipMemcpyHostToDevice));
+    double one = 1.0;
+    HC(hipMemcpy(c.s_dev, &one, 8, hipMemcpyHostToDevice));
+    HC(hipMemset(c.vslot_ptr, 0, sizeof(int) * (n + 1)));
+    HC(hipFuncSetAttribute((const void*)k_chol_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)(sizeof(double) * (size_t)(s.r * s.r + 4 * s.r))));
+    return CLOTH_OK;
+}
+
+cloth_status contact_set_obstacles(Scene& s, ContactState& c) {
+    c.nob = (int)s.obst.size();
+    for (int j = 0; j < c.nob; ++j) c.ob[j] = s.obst[j];
+    HC(hipMemcpy(c.ob_dev, c.ob, sizeof(ObstD) * MAX_OBST, hipMemcpyHostToDevice));
+    s.d.nob = c.nob;
+    c.enabled = contact_enabled(s, c);
+    return CLOTH_OK;
+}
+
+// Broad phase on (xm, xp) -> sorted candidates, counts in cnt[0], cnt[1].
+static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, const float* xp, hipStream_t st) {
+    if (!s.self_contact) return CLOTH_OK;
+    Dev& d = s.d;
+    const int n = s.nv;
+    const int P = c.hash_p;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (int*)c.maxext, 0, 8);
+    hipLaunchKernelGGL(k_boxes, dim3(gblocks((int64_t)n + s.nt + s.ne)), dim3(TPB), 0, st, d, xm, xp, (float)s.dhat,
+                       c.vbox, c.tbox, c.ebox, c.maxext);
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool vt = pass == 0;
+        const int m = vt ? s.nt : s.ne;
+        const float* tb = vt ? c.tbox : c.ebox;
+        int* cell = vt ? c.tcell : c.ecell;
+        const unsigned* mx = c.maxext + (vt ? 0 : 3);
+        hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, c.bucket_cnt, 0, P + 1);
+        hipLaunchKernelGGL(k_cells, dim3(gblocks(m)), dim3(TPB), 0, st, m, tb, mx, cell, c.bucket_cnt, P);
+        HC(scan_exclusive(c.bucket_cnt, c.bucket_ptr, P + 1, nullptr, c.scan_tiles, nullptr, st));
+        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, c.bucket_cnt, c.bucket_ptr, P + 1);
+        hipLaunchKernelGGL(k_bucket_fill, dim3(gblocks(m)), dim3(TPB), 0, st, m, cell, P, c.bucket_cnt, c.bucket_item);
+        const int nq = vt ? n : s.ne;
+        int* cnts = vt ? c.vcount : c.ecount;
+        int2* outp = vt ? c.cand_vt : c.cand_ee;
+        const float* qb = vt ? c.vbox : c.ebox;
+        if (vt)
+            hipLaunchKernelGGL((k_query<true, false>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
+                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.cnt + 7);
+        else
+            hipLaunchKernelGGL((k_query<false, false>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
+                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.cnt + 7);
+        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, c.keep, cnts, nq);
+        HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, st));
+        hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
+                           c.cnt + 7);
+        if (vt)
+            hipLaunchKernelGGL((k_query<true, true>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
+                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.cnt + 7);
+        else
+            hipLaunchKernelGGL((k_query<false, true>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
+                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.cnt + 7);
+    }
+    HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
+// TOI + merge with the previous set + obstacles + step length + compaction +
+// filter x = xm + s (xp - xm) written to d.x and d.xm.
+static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm, const float* xp, hipStream_t st) {
+    Dev& d = s.d;
+    const int n = s.nv;
+    if (s.self_contact) {
+        hipLaunchKernelGGL(k_toi_merge, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, xm, xp, c.cand_vt, c.cand_ee,
+                           c.cnt, c.toi_vt, c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tmin_bits, 1);
+    }
+    if (c.nob > 0)
+        hipLaunchKernelGGL(k_obstacles_outer, dim3(gblocks(n)), dim3(TPB), 0, st, d, xm, xp, c.tmin_bits, c.cnt + 10);
+    hipLaunchKernelGGL(k_step_length, dim3(1), dim3(64), 0, st, c.tmin_bits, s.alpha, c.s_dev);
+    if (s.self_contact) {
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(64), 0, st, c.cnt);
+        HC(scan_exclusive(c.keep, c.keep_ofs, (int)(2 * c.cap), c.cnt + 9, c.scan_tiles, nullptr, st));
+        hipLaunchKernelGGL(k_compact, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, c.cand_vt, c.cand_ee, c.cnt, c.keep,
+                           c.keep_ofs, c.cand_a, c.cpair, c.ca);
+    }
+    HC(launch_filter(d, xm, xp, c.s_dev, d.x, d.xm, st));
+    HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
+// Per block: frozen data at x-, vertex slot lists, contact-vertex list.
+static cloth_status block_setup(Scene& s, ContactState& c, hipStream_t st) {
+    Dev& d = s.d;
+    const int n = s.nv;
+    if (s.self_contact) {
+        hipLaunchKernelGGL(k_freeze, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.clam, c.cnrm);
+        hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(n + 1)), dim3(TPB), 0, st, c.vslot_fill, 0, n + 1);
+        hipLaunchKernelGGL(k_slot_count, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.vslot_fill);
+        HC(scan_exclusive(c.vslot_fill, c.vslot_ptr, n + 1, nullptr, c.scan_tiles, nullptr, st));
+        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(n + 1)), dim3(TPB), 0, st, c.vslot_fill, c.vslot_ptr, n + 1);
+        hipLaunchKernelGGL(k_slot_fill, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.vslot_fill,
+                           c.vslot);
+    }
+    hipLaunchKernelGGL(k_slot_sort, dim3(gblocks(n)), dim3(TPB), 0, st, d, c.vslot_ptr, c.vslot, c.ob_a, c.nob,
+                       c.cvflag);
+    HC(scan_exclusive(c.cvflag, c.cvofs, n, nullptr, c.scan_tiles, nullptr, st));
+    hipLaunchKernelGGL(k_cv_compact, dim3(gblocks(n)), dim3(TPB), 0, st, n, c.cvflag, c.cvofs, c.cvlist, c.cnt + 6);
+    HC(hipGetLastError());
+    c.active = true;
+    return CLOTH_OK;
+}
+
+static cloth_status outer_stage(Scene& s, ContactState& c, const float* xm, const float* xp, bool first,
+                                bool setup, hipStream_t st) {
+    if (first) hipLaunchKernelGGL(k_fill_i32, dim3(gblocks((int64_t)MAX_OBST * s.nv)), dim3(TPB), 0, st, c.ob_a, -1,
+                                  MAX_OBST * s.nv);
+    hipLaunchKernelGGL(k_save_prev, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, c.cnt, c.cpair, c.ca, c.cpair_prev,
+                       c.ca_prev, first ? 1 : 0);
+    hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, st, c.cnt, first ? 1 : 0, c.tmin_bits);
+    if (first) {
+        // the previous set of the first stage is empty; the current one too
+        int z[2] = {0, 0};
+        (void)z;
+    }
+    cloth_status rc = broad_phase(s, c, xm, xp, st);
+    if (rc != CLOTH_OK) return rc;
+    rc = toi_merge_filter(s, c, xm, xp, st);
+    if (rc != CLOTH_OK) return rc;
+    if (setup) return block_setup(s, c, st);
+    return CLOTH_OK;
+}
+
+cloth_status contact_step_begin(Scene& s, ContactState& c, hipStream_t st) {
+    // clear the constraint counts of the previous step before saving "prev"
+    return outer_stage(s, c, s.d.xstar, s.d.z, true, true, st);
+}
+
+cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st) {
+    (void)s;
+    (void)c;
+    (void)st;
+    return CLOTH_OK;
+}
+
+cloth_status contact_block_end(Scene& s, ContactState& c, bool last, hipStream_t st) {
+    return outer_stage(s, c, s.d.xm, s.d.xk, false, !last, st);
+}
+
+cloth_status contact_prepare_iteration(Scene& s, ContactState& c, hipStream_t st) {
+    if (!s.self_contact) return CLOTH_OK;
+    Dev& d = s.d;
+    hipLaunchKernelGGL(k_pair_targets, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca, c.clam,
+                       c.cnrm, (float)s.kc, (float)s.Kb, (float)s.dhat, c.slot);
+    HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
+cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st) {
+    Dev& d = s.d;
+    if (s.prec == CLOTH_MIXED)
+        hipLaunchKernelGGL(k_gram<uint16_t>, dim3(c.gram_chunks), dim3(256), 0, st, d, c.cvlist, c.cnt + 6,
+                           c.gram_chunks, d.gram_part);
+    else
+        hipLaunchKernelGGL(k_gram<float>, dim3(c.gram_chunks), dim3(256), 0, st, d, c.cvlist, c.cnt + 6,
+                           c.gram_chunks, d.gram_part);
+    size_t sh = sizeof(double) * (size_t)(s.r * s.r + 4 * s.r);
+    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), sh, st, d, d.gram_part, c.gram_chunks, c.gvec, c.cnt + 6);
+    HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
+cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st) {
+    Dev& d = s.d;
+    hipLaunchKernelGGL(k_partial_ccd, dim3(gblocks(2 * c.cap + s.nv)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca,
+                       c.clam, s.amax, d.xk);
+    HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
+cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step_stats* out) {
+    if (!c.enabled) return CLOTH_OK;
+    int h[16];
+    unsigned long long tb[2];
+    HC(hipMemcpyAsync(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+    HC(hipMemcpyAsync(tb, c.tmin_bits, sizeof(tb), hipMemcpyDeviceToHost, st));
+    HC(hipStreamSynchronize(st));
+    double t;
+    std::memcpy(&t, &tb[1], 8);
+    out->min_toi = t;
+    out->n_candidates = (int64_t)h[0] + h[1];
+    out->n_constraints = (int64_t)h[2] + h[3] + h[10];
+    if (h[7]) return set_error(CLOTH_E_CAPACITY, "pair capacity exceeded");
+    (void)s;
+    return CLOTH_OK;
+}
+
+// ---- stage entry points (host arrays, caller order; SoA conversion here)
+
+static void to_soa(const float* a, std::vector<float>& o, int n) {
+    o.resize(3 * (size_t)n);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) o[(size_t)k * n + i] = a[3 * (size_t)i + k];
+}
+
+cloth_status contact_stage_broad_phase(Scene& s, ContactState& c, const float* xm, const float* xp, int64_t cap,
+                                       int32_t* vt, int64_t* n_vt, int32_t* ee, int64_t* n_ee) {
+    if (!s.self_contact) {
+        *n_vt = *n_ee = 0;
+        return CLOTH_OK;
+    }
+    std::vector<float> t;
+    to_soa(xm, t, s.nv);
+    HC(hipMemcpy(s.d.xm, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
+    to_soa(xp, t, s.nv);
+    HC(hipMemcpy(s.d.xt, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, nullptr, c.cnt, 1, c.tmin_bits);
+    cloth_status rc = broad_phase(s, c, s.d.xm, s.d.xt, nullptr);
+    if (rc != CLOTH_OK) return rc;
+    int h[16];
+    HC(hipMemcpy(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost));
+    *n_vt = h[0];
+    *n_ee = h[1];
+    if (h[7] || h[0] > cap || h[1] > cap) return set_error(CLOTH_E_CAPACITY, "pair list does not fit");
+    if (vt && h[0]) HC(hipMemcpy(vt, c.cand_vt, sizeof(int2) * h[0], hipMemcpyDeviceToHost));
+    if (ee && h[1]) HC(hipMemcpy(ee, c.cand_ee, sizeof(int2) * h[1], hipMemcpyDeviceToHost));
+    return CLOTH_OK;
+}
+
+cloth_status contact_stage_toi(Scene& s, ContactState& c, const float* xm, const float* xp, int64_t n_vt,
+                               const int32_t* vt, int64_t n_ee, const int32_t* ee, double* toi_vt, double* toi_ee) {
+    if (n_vt > c.cap || n_ee > c.cap) return set_error(CLOTH_E_CAPACITY, "pair list exceeds capacity");
+    std::vector<float> t;
+    to_soa(xm, t, s.nv);
+    HC(hipMemcpy(s.d.xm, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
+    to_soa(xp, t, s.nv);
+    HC(hipMemcpy(s.d.xt, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
+    if (n_vt) HC(hipMemcpy(c.cand_vt, vt, sizeof(int2) * n_vt, hipMemcpyHostToDevice));
+    if (n_ee) HC(hipMemcpy(c.cand_ee, ee, sizeof(int2) * n_ee, hipMemcpyHostToDevice));
+    int h[2] = {(int)n_vt, (int)n_ee};
+    HC(hipMemcpy(c.cnt, h, sizeof(h), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_toi_merge, dim3(gblocks(n_vt + n_ee)), dim3(TPB), 0, nullptr, s.d, s.d.xm, s.d.xt, c.cand_vt,
+                       c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tmin_bits, 0);
+    HC(hipGetLastError());
+    HC(hipDeviceSynchronize());
+    if (n_vt) HC(hipMemcpy(toi_vt, c.toi_vt, sizeof(double) * n_vt, hipMemcpyDeviceToHost));
+    if (n_ee) HC(hipMemcpy(toi_ee, c.toi_ee, sizeof(double) * n_ee, hipMemcpyDeviceToHost));
+    return CLOTH_OK;
+}
+
+cloth_status contact_load_constraints(Scene& s, ContactState& c, int64_t n_vt, const int32_t* vt, const int32_t* a_vt,
+                                      int64_t n_ee, const int32_t* ee, const int32_t* a_ee, const int32_t* ob_a) {
+    const int n = s.nv;
+    if (!c.enabled) {
+        c.active = false;
+        return CLOTH_OK;
+    }
+    if (n_vt + n_ee > 2 * c.cap) return set_error(CLOTH_E_CAPACITY, "constraint list exceeds capacity");
+    if ((n_vt || n_ee) && !s.self_contact) return set_error(CLOTH_E_INVALID, "pair constraints without self contact");
+    std::vector<int2> pr(n_vt + n_ee);
+    std::vector<int> a(n_vt + n_ee);
+    for (int64_t i = 0; i < n_vt; ++i) {
+        pr[i] = make_int2(vt[2 * i], vt[2 * i + 1]);
+        a[i] = a_vt ? a_vt[i] : 0;
+    }
+    for (int64_t i = 0; i < n_ee; ++i) {
+        pr[n_vt + i] = make_int2(ee[2 * i], ee[2 * i + 1]);
+        a[n_vt + i] = a_ee ? a_ee[i] : 0;
+    }
+    if (!pr.empty()) {
+        HC(hipMemcpy(c.cpair, pr.data(), sizeof(int2) * pr.size(), hipMemcpyHostToDevice));
+        HC(hipMemcpy(c.ca, a.data(), sizeof(int) * a.size(), hipMemcpyHostToDevice));
+    }
+    int h[16] = {0};
+    h[2] = (int)n_vt;
+    h[3] = (int)n_ee;
+    HC(hipMemcpy(c.cnt, h, sizeof(h), hipMemcpyHostToDevice));
+    std::vector<int> ob(MAX_OBST * (size_t)n, -1);
+    if (ob_a)
+        for (int j = 0; j < c.nob; ++j)
+            for (int v = 0; v < n; ++v) ob[(size_t)j * n + v] = ob_a[(size_t)j * n + v];
+    HC(hipMemcpy(c.ob_a, ob.data(), sizeof(int) * ob.size(), hipMemcpyHostToDevice));
+    return block_setup(s, c, nullptr);
+}
+
+cloth_status contact_read_constraints(Scene& s, ContactState& c, int32_t* a_vt, int32_t* a_ee, int32_t* ob_a) {
+    if (!c.enabled) return CLOTH_OK;
+    int h[16];
+    HC(hipMemcpy(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost));
+    if (a_vt && h[2]) HC(hipMemcpy(a_vt, c.ca, sizeof(int) * h[2], hipMemcpyDeviceToHost));
+    if (a_ee && h[3]) HC(hipMemcpy(a_ee, c.ca + h[2], sizeof(int) * h[3], hipMemcpyDeviceToHost));
+    if (ob_a && c.nob)
+        HC(hipMemcpy(ob_a, c.ob_a, sizeof(int) * (size_t)c.nob * s.nv, hipMemcpyDeviceToHost));
+    return CLOTH_OK;
+}
+
+void contact_destroy(Scene& s, ContactState& c) {
+    (void)s;
+    (void)c;
+}
+
+}  // namespace cloth

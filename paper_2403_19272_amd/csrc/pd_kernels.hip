@@ -1,0 +1,442 @@
+// Inner projective-dynamics iteration kernels for gfx950 (wave64).
+//
+// One inner iteration (paper, Algorithm 1 inner loop; Eq. (local), (global),
+// (subspace_collision), (high_frequency_residual)):
+//   k_local_residual   local step (triangle strain projection; flat-rest
+//                      bending adds no right-hand side) + inertia + collision
+//                      targets -> b; r0 = b - (H + diag W) x^k on free rows;
+//                      per-block partial products U^T r0 (r x 3)
+//   k_reduce_g1        first level of the deterministic sum of the partials
+//   k_solve_reduced    g = U^T r0 in FP64, q = A^{-1} g (A = Lambda~ + U^T W U)
+//   k_expand           x~ = x^k + U q
+//   k_jacobi_cheb      r1 = b - (H + diag W) x~, x^ = x~ + r1 / (diag H + W),
+//                      Chebyshev blend -> x^{k+1}; max |x^{k+1} - x^k| in FP64
+// Data: SoA FP32 positions (x, y, z planes of nv floats), scalar CSR of H
+// shared by the three coordinates, U row-major in FP32 or BF16.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace cloth {
+
+namespace {
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
+
+// Eight consecutive basis entries of row v starting at column c (c % 8 == 0).
+template <typename UT>
+__device__ __forceinline__ void load8(const UT* __restrict__ U, size_t off, float u[8]);
+
+template <>
+__device__ __forceinline__ void load8<float>(const float* __restrict__ U, size_t off, float u[8]) {
+    const float4* p = reinterpret_cast<const float4*>(U + off);
+    float4 a = p[0], b = p[1];
+    u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
+    u[4] = b.x; u[5] = b.y; u[6] = b.z; u[7] = b.w;
+}
+
+template <>
+__device__ __forceinline__ void load8<uint16_t>(const uint16_t* __restrict__ U, size_t off, float u[8]) {
+    uint4 a = *reinterpret_cast<const uint4*>(U + off);
+    u[0] = __uint_as_float(a.x << 16); u[1] = __uint_as_float(a.x & 0xffff0000u);
+    u[2] = __uint_as_float(a.y << 16); u[3] = __uint_as_float(a.y & 0xffff0000u);
+    u[4] = __uint_as_float(a.z << 16); u[5] = __uint_as_float(a.z & 0xffff0000u);
+    u[6] = __uint_as_float(a.w << 16); u[7] = __uint_as_float(a.w & 0xffff0000u);
+}
+
+// Closest 3x2 matrix with orthonormal columns: T = F (F^T F)^{-1/2}, with
+// the 2x2 square root sqrt(S) = (S + sqrt(det S) I) / sqrt(tr S + 2 sqrt(det S)).
+// F and T are row-major 3x2 (F[2*d + i]).
+__device__ __forceinline__ void polar32(const float F[6], float T[6]) {
+    float s00 = F[0] * F[0] + F[2] * F[2] + F[4] * F[4];
+    float s01 = F[0] * F[1] + F[2] * F[3] + F[4] * F[5];
+    float s11 = F[1] * F[1] + F[3] * F[3] + F[5] * F[5];
+    float det = s00 * s11 - s01 * s01;
+    if (!(det > 1e-20f)) {
+        for (int i = 0; i < 6; ++i) T[i] = F[i];
+        return;
+    }
+    float sd = sqrtf(det);
+    float rden = 1.0f / sqrtf(s00 + s11 + 2.0f * sd);
+    float r00 = (s00 + sd) * rden, r11 = (s11 + sd) * rden, r01 = s01 * rden;
+    float isd = 1.0f / sd;
+    float i00 = r11 * isd, i11 = r00 * isd, i01 = -r01 * isd;
+    for (int d = 0; d < 3; ++d) {
+        float f0 = F[2 * d], f1 = F[2 * d + 1];
+        T[2 * d] = f0 * i00 + f1 * i01;
+        T[2 * d + 1] = f0 * i01 + f1 * i11;
+    }
+}
+
+__device__ __forceinline__ double warp_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+}  // namespace
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_copy3(float* __restrict__ dst, const float* __restrict__ src, int n3) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3) dst[i] = src[i];
+}
+
+// z = x* + h v* + h^2 g (free rows), z = x* at pinned rows; x* saved (Eq. (z)).
+__global__ void k_predict(Dev d, float h, float gx, float gy, float gz) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= d.nv) return;
+    const int n = d.nv;
+    bool pin = d.pinned[v] != 0;
+    float g[3] = {gx, gy, gz};
+    for (int c = 0; c < 3; ++c) {
+        float xv = d.x[c * n + v];
+        d.xstar[c * n + v] = xv;
+        d.z[c * n + v] = pin ? xv : xv + h * d.v[c * n + v] + h * h * g[c];
+    }
+}
+
+// x = x- + s (x+ - x-), x- <- x (the step-length filter, section 7).
+__global__ void k_filter(int nv, const float* __restrict__ xm, const float* __restrict__ xp,
+                         const double* __restrict__ s_dev, float* __restrict__ x,
+                         float* __restrict__ xm_out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * nv) return;
+    float s = (float)s_dev[0];
+    float a = xm[i];
+    float r = (s == 1.0f) ? xp[i] : a + s * (xp[i] - a);
+    x[i] = r;
+    xm_out[i] = r;
+}
+
+// v = (x - x*) / h
+__global__ void k_epilogue(Dev d, float inv_h) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * d.nv) return;
+    d.v[i] = (d.x[i] - d.xstar[i]) * inv_h;
+}
+
+// Local step, right-hand side b, residual r0 and the block's partial U^T r0.
+// Thread = vertex; the elastic projection of each incident triangle is
+// recomputed per corner so that accumulation is a deterministic gather.
+// flags: bit 0 = contact terms (W, WY gathered here from the pair-constraint
+// slots and the obstacle constraints, W stored for the later kernels),
+// bit 1 = linear mode (b = 0: error propagation of the global iteration).
+template <typename UT>
+__global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
+    __shared__ float sr[3][TPB];
+    __shared__ float red[TPB * 24];
+    const int tid = threadIdx.x;
+    const int n = d.nv;
+    const int v = blockIdx.x * TPB + tid;
+    const bool contact = flags & 1, linear = flags & 2;
+    float r0[3] = {0.f, 0.f, 0.f};
+    if (v < n) {
+        const float* X = d.xk;
+        float bx = 0.f, by = 0.f, bz = 0.f;
+        if (!linear) {
+            float m = d.mh2[v];
+            bx = m * d.z[v];
+            by = m * d.z[n + v];
+            bz = m * d.z[2 * n + v];
+            for (int i = d.inc_ptr[v], e = d.inc_ptr[v + 1]; i < e; ++i) {
+                int code = d.inc[i];
+                int t = code >> 2, c = code & 3;
+                TriRec tr = d.tri[t];
+                float p0[3] = {X[tr.v0], X[n + tr.v0], X[2 * n + tr.v0]};
+                float e1[3] = {X[tr.v1] - p0[0], X[n + tr.v1] - p0[1], X[2 * n + tr.v1] - p0[2]};
+                float e2[3] = {X[tr.v2] - p0[0], X[n + tr.v2] - p0[1], X[2 * n + tr.v2] - p0[2]};
+                float F[6], T[6];
+                for (int q = 0; q < 3; ++q) {
+                    F[2 * q] = e1[q] * tr.gj0 + e2[q] * tr.gk0;
+                    F[2 * q + 1] = e1[q] * tr.gj1 + e2[q] * tr.gk1;
+                }
+                polar32(F, T);
+                float g0, g1;
+                if (c == 0) {
+                    g0 = -tr.gj0 - tr.gk0;
+                    g1 = -tr.gj1 - tr.gk1;
+                } else if (c == 1) {
+                    g0 = tr.gj0;
+                    g1 = tr.gj1;
+                } else {
+                    g0 = tr.gk0;
+                    g1 = tr.gk1;
+                }
+                bx += tr.w * (T[0] * g0 + T[1] * g1);
+                by += tr.w * (T[2] * g0 + T[3] * g1);
+                bz += tr.w * (T[4] * g0 + T[5] * g1);
+            }
+        }
+        float Wv = 0.f;
+        if (contact) {
+            float wx = 0.f, wy = 0.f, wz = 0.f;
+            for (int i = d.vslot_ptr[v], e = d.vslot_ptr[v + 1]; i < e; ++i) {
+                float4 sl = d.slot[d.vslot[i]];
+                Wv += sl.x;
+                wx += sl.y;
+                wy += sl.z;
+                wz += sl.w;
+            }
+            for (int j = 0; j < d.nob; ++j) {
+                int a = d.ob_a[j * n + v];
+                if (a < 0) continue;
+                float w = (d.Kb == 2.0f) ? ldexpf(d.kc, a) : d.kc * powf(d.Kb, (float)a);
+                const ObstD& o = d.ob[j];
+                double px = X[v], py = X[n + v], pz = X[2 * n + v];
+                double ox = px - o.c[0], oy = py - o.c[1], oz = pz - o.c[2];
+                if (o.kind == CLOTH_CYLINDER) {
+                    double ax = ox * o.a[0] + oy * o.a[1] + oz * o.a[2];
+                    ox -= ax * o.a[0];
+                    oy -= ax * o.a[1];
+                    oz -= ax * o.a[2];
+                }
+                double rad = sqrt(ox * ox + oy * oy + oz * oz);
+                double yx = px, yy = py, yz = pz;
+                if (rad - o.R < d.dhat && rad > 0) {
+                    double sc = (o.R + d.dhat) / rad;
+                    yx = px - ox + ox * sc;
+                    yy = py - oy + oy * sc;
+                    yz = pz - oz + oz * sc;
+                }
+                Wv += w;
+                wx += w * (float)yx;
+                wy += w * (float)yy;
+                wz += w * (float)yz;
+            }
+            d.W[v] = Wv;
+            if (!linear) {
+                bx += wx;
+                by += wy;
+                bz += wz;
+            }
+        }
+        d.b[v] = bx;
+        d.b[n + v] = by;
+        d.b[2 * n + v] = bz;
+        if (!d.pinned[v]) {
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
+                int c = d.col[j];
+                float a = d.val[j];
+                ax += a * X[c];
+                ay += a * X[n + c];
+                az += a * X[2 * n + c];
+            }
+            r0[0] = bx - ax - Wv * X[v];
+            r0[1] = by - ay - Wv * X[n + v];
+            r0[2] = bz - az - Wv * X[2 * n + v];
+        }
+    }
+    sr[0][tid] = r0[0];
+    sr[1][tid] = r0[1];
+    sr[2][tid] = r0[2];
+    __syncthreads();
+    // partial U^T r0 over this block's vertices: thread = (column group of 8, vertex group)
+    const int r = d.r;
+    const int ncg = r >> 3;
+    const int nvg = TPB / ncg;
+    const int cg = tid % ncg, vg = tid / ncg;
+    float acc[8][3];
+    for (int i = 0; i < 8; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.f;
+    const UT* U = static_cast<const UT*>(d.U);
+    if (vg < nvg) {
+        for (int vv = vg; vv < TPB; vv += nvg) {
+            int vtx = blockIdx.x * TPB + vv;
+            if (vtx >= n) break;
+            float u[8];
+            load8<UT>(U, (size_t)vtx * r + cg * 8, u);
+            float a0 = sr[0][vv], a1 = sr[1][vv], a2 = sr[2][vv];
+            for (int i = 0; i < 8; ++i) {
+                acc[i][0] += u[i] * a0;
+                acc[i][1] += u[i] * a1;
+                acc[i][2] += u[i] * a2;
+            }
+        }
+        for (int i = 0; i < 8; ++i)
+            for (int c = 0; c < 3; ++c) red[vg * (r * 3) + (cg * 8 + i) * 3 + c] = acc[i][c];
+    }
+    __syncthreads();
+    for (int o = tid; o < r * 3; o += TPB) {
+        float s = 0.f;
+        for (int g = 0; g < nvg; ++g) s += red[g * (r * 3) + o];
+        d.gpart[(size_t)blockIdx.x * (r * 3) + o] = s;
+    }
+}
+
+// First reduction level: block s sums partial rows [s*SEG, (s+1)*SEG) in FP64.
+constexpr int SEG = 32;
+__global__ void k_reduce_g1(const float* __restrict__ gpart, int nblk, int m, double* __restrict__ out) {
+    int s = blockIdx.x;
+    int b0 = s * SEG, b1 = min(nblk, b0 + SEG);
+    for (int o = threadIdx.x; o < m; o += blockDim.x) {
+        double acc = 0.0;
+        for (int b = b0; b < b1; ++b) acc += (double)gpart[(size_t)b * m + o];
+        out[(size_t)s * m + o] = acc;
+    }
+}
+
+// g = sum of the level-1 partials (FP64) -> d.gvec; without contact also
+// q = A^{-1} g with the precomputed inverse of Lambda~.
+__global__ void k_solve_reduced(Dev d, const double* __restrict__ g1, int nseg, int solve) {
+    extern __shared__ double gs[];
+    const int r = d.r, m = r * 3;
+    for (int o = threadIdx.x; o < m; o += blockDim.x) {
+        double acc = 0.0;
+        for (int s = 0; s < nseg; ++s) acc += g1[(size_t)s * m + o];
+        gs[o] = acc;
+        d.gvec[o] = acc;
+    }
+    __syncthreads();
+    if (!solve) return;
+    for (int o = threadIdx.x; o < m; o += blockDim.x) {
+        int c = o / 3, k = o % 3;
+        double acc = 0.0;
+        for (int j = 0; j < r; ++j) acc += d.Ainv[(size_t)c * r + j] * gs[j * 3 + k];
+        d.Qd[o] = acc;
+        d.Qf[o] = (float)acc;
+    }
+}
+
+// x~ = x^k + U q
+template <typename UT>
+__global__ void __launch_bounds__(TPB) k_expand(Dev d) {
+    extern __shared__ float qs[];
+    const int r = d.r;
+    for (int o = threadIdx.x; o < r * 3; o += blockDim.x) qs[o] = d.Qf[o];
+    __syncthreads();
+    const int n = d.nv;
+    const int v = blockIdx.x * TPB + threadIdx.x;
+    if (v >= n) return;
+    const UT* U = static_cast<const UT*>(d.U);
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int c = 0; c < r; c += 8) {
+        float u[8];
+        load8<UT>(U, (size_t)v * r + c, u);
+        for (int i = 0; i < 8; ++i) {
+            a0 += u[i] * qs[(c + i) * 3];
+            a1 += u[i] * qs[(c + i) * 3 + 1];
+            a2 += u[i] * qs[(c + i) * 3 + 2];
+        }
+    }
+    d.xt[v] = d.xk[v] + a0;
+    d.xt[n + v] = d.xk[n + v] + a1;
+    d.xt[2 * n + v] = d.xk[2 * n + v] + a2;
+}
+
+// Jacobi sweep on the residual of x~ with the Chebyshev blend:
+//   x^{k+1} = omega (gamma (x^ - x^k) + x^k - x^{k-1}) + x^{k-1}.
+__global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float gamma, int has_contact,
+                                                    unsigned long long* dx_slot) {
+    __shared__ double wmax[TPB / 64];
+    const int n = d.nv;
+    const int v = blockIdx.x * TPB + threadIdx.x;
+    double dxm = 0.0;
+    if (v < n) {
+        const float* XT = d.xt;
+        float xt[3] = {XT[v], XT[n + v], XT[2 * n + v]};
+        float xk[3] = {d.xk[v], d.xk[n + v], d.xk[2 * n + v]};
+        float xkm1[3] = {d.xkm1[v], d.xkm1[n + v], d.xkm1[2 * n + v]};
+        float xh[3] = {xt[0], xt[1], xt[2]};
+        if (!d.pinned[v]) {
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
+                int c = d.col[j];
+                float a = d.val[j];
+                ax += a * XT[c];
+                ay += a * XT[n + c];
+                az += a * XT[2 * n + c];
+            }
+            float Wv = has_contact ? d.W[v] : 0.f;
+            float inv = 1.0f / (d.diag[v] + Wv);
+            xh[0] = xt[0] + (d.b[v] - ax - Wv * xt[0]) * inv;
+            xh[1] = xt[1] + (d.b[n + v] - ay - Wv * xt[1]) * inv;
+            xh[2] = xt[2] + (d.b[2 * n + v] - az - Wv * xt[2]) * inv;
+        }
+        double s2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            float nx = omega * (gamma * (xh[c] - xk[c]) + xk[c] - xkm1[c]) + xkm1[c];
+            d.xk1[c * n + v] = nx;
+            double dd = (double)nx - (double)xk[c];
+            s2 += dd * dd;
+        }
+        dxm = sqrt(s2);
+    }
+    dxm = warp_max(dxm);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = dxm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0];
+        for (int i = 1; i < TPB / 64; ++i) m = fmax(m, wmax[i]);
+        atomicMax(dx_slot, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline int blocks_for(int n) { return (n + TPB - 1) / TPB; }
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy3(float* dst, const float* src, int nv, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy3, dim3(blocks_for(3 * nv)), dim3(TPB), 0, st, dst, src, 3 * nv);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(const Dev& d, float h, float gx, float gy, float gz, hipStream_t st) {
+    hipLaunchKernelGGL(k_predict, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, h, gx, gy, gz);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(const Dev& d, const float* xm, const float* xp, const double* s_dev, float* x,
+                         float* xm_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_filter, dim3(blocks_for(3 * d.nv)), dim3(TPB), 0, st, d.nv, xm, xp, s_dev, x,
+                       xm_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_epilogue(const Dev& d, float inv_h, hipStream_t st) {
+    hipLaunchKernelGGL(k_epilogue, dim3(blocks_for(3 * d.nv)), dim3(TPB), 0, st, d, inv_h);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_residual(const Dev& d, int prec, int flags, hipStream_t st) {
+    if (prec == CLOTH_MIXED)
+        hipLaunchKernelGGL(k_local_residual<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, flags);
+    else
+        hipLaunchKernelGGL(k_local_residual<float>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpart2, hipStream_t st) {
+    const int m = d.r * 3;
+    int nseg = (nblk + SEG - 1) / SEG;
+    hipLaunchKernelGGL(k_reduce_g1, dim3(nseg), dim3(256), 0, st, d.gpart, nblk, m, gpart2);
+    hipLaunchKernelGGL(k_solve_reduced, dim3(1), dim3(512), sizeof(double) * m, st, d,
+                       (const double*)gpart2, nseg, contact ? 0 : 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(const Dev& d, int prec, hipStream_t st) {
+    size_t sh = sizeof(float) * d.r * 3;
+    if (prec == CLOTH_MIXED)
+        hipLaunchKernelGGL(k_expand<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), sh, st, d);
+    else
+        hipLaunchKernelGGL(k_expand<float>, dim3(blocks_for(d.nv)), dim3(TPB), sh, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_cheb(const Dev& d, float omega, float gamma, int has_contact,
+                              unsigned long long* dx_slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_jacobi_cheb, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, omega, gamma,
+                       has_contact, dx_slot);
+    return hipGetLastError();
+}
+
+}  // namespace cloth

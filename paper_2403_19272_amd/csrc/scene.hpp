@@ -1,0 +1,133 @@
+// Internal scene state of the cloth library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cloth.h"
+
+namespace cloth {
+
+constexpr int TPB = 256;          // threads per block of the vertex/pair kernels
+constexpr int MAX_OBST = 4;
+constexpr double NO_HIT = 2.0;
+
+// Triangle record for the local step: corner ids, PD weight w = k_s * area,
+// and the gradient rows g_j, g_k (g_i = -g_j - g_k) with F = sum_c x_c g_c^T.
+struct TriRec {
+    int v0, v1, v2;
+    float w;
+    float gj0, gj1, gk0, gk1;
+};
+static_assert(sizeof(TriRec) == 32, "TriRec layout");
+
+// Analytic obstacle in the form the kernels read (FP64 so that the
+// proximity decisions are taken in double precision).
+struct ObstD {
+    int kind;        // CLOTH_SPHERE / CLOTH_CYLINDER (axis a unit length)
+    double c[3], a[3], R;
+};
+
+// Device pointers and sizes handed to kernels by value.
+struct Dev {
+    int nv, nt, ne, r;
+    // SoA 3*nv arrays: [0,nv) x, [nv,2nv) y, [2nv,3nv) z
+    float *x, *v, *xstar, *z, *xm, *xk, *xkm1, *xk1, *xt, *b, *WY;
+    float* W;                 // nv: diagonal collision weights
+    float* mh2;               // nv: m / h^2
+    float* diag;              // nv: diag(H)
+    const uint8_t* pinned;    // nv
+    const int* rowptr;        // nv+1
+    const int* col;           // nnz
+    const float* val;         // nnz
+    const TriRec* tri;        // nt
+    const int* inc_ptr;       // nv+1: vertex -> (triangle << 2 | corner)
+    const int* inc;           // 3*nt
+    const int* edges;         // 2*ne (lexicographic, i < j)
+    const void* U;            // nv*r, row-major, float or bf16 bits
+    float* gpart;             // nblk * r * 3
+    float* Qf;                // r * 3
+    double* Qd;               // r * 3
+    double* Ainv;             // r * r (no-contact inverse of Lambda~)
+    double* Lam;              // r * r
+    double* Amat;             // r * r work (contact)
+    float* gram_part;         // gram chunks * r * r
+    unsigned long long* dxbits;  // per-iteration max |dx| as double bits
+    double* gvec;             // r * 3: g = U^T r0 (FP64)
+    // contact (read when the contact flag is set)
+    const int* vslot_ptr;     // nv+1: vertex -> slots of pair constraints
+    const int* vslot;         // slot ids (4 * constraint + corner), sorted per vertex
+    const float4* slot;       // per slot (w, w*y)
+    int* ob_a;                // MAX_OBST * nv obstacle life spans (-1 = none)
+    const ObstD* ob;          // obstacle table
+    int nob;
+    float kc, Kb;             // initial weight k and growth base K of Eq. (exp)
+    double dhat;
+};
+
+struct Scene {
+    // sizes and settings
+    int nv = 0, nt = 0, ne = 0, nh = 0, r = 0;
+    int64_t nnz = 0;
+    double h = 0, density = 0, ks = 0, kb = 0, kc = 0, Kb = 2, dhat = 1e-3, alpha = 0.8;
+    int amax = 20;
+    int iters_in = 10, iters_out = 1, delay = 3, prec = CLOTH_PLAIN_FP32, self_contact = 0;
+    double rho = 0, gamma = 0;
+    int64_t pair_cap = 0;
+    bool basis_set = false;
+
+    // host data (FP64 precompute)
+    std::vector<int> tris, edges, hinges;  // hinges: 4 per interior edge
+    std::vector<uint8_t> pinned;
+    std::vector<double> rest, mass, area, g;  // g: 6 per triangle (g_i, g_j, g_k)
+    std::vector<double> K, w_hinge;
+    std::vector<int> rowptr, col;
+    std::vector<double> val, diag;
+    std::vector<double> Ustored;   // nv*r stored-precision values as FP64
+    std::vector<double> Lam;       // r*r
+    std::vector<ObstD> obst;
+
+    // device memory
+    char* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
+    bool arena_owned = false;
+    Dev d{};
+    int nblk = 0;                 // vertex blocks
+    uint8_t* d_pinned = nullptr;
+    int *d_rowptr = nullptr, *d_col = nullptr, *d_inc_ptr = nullptr, *d_inc = nullptr,
+        *d_edges = nullptr;
+    float* d_val = nullptr;
+    TriRec* d_tri = nullptr;
+    void* d_U = nullptr;
+    double* d_dx_host_copy = nullptr;
+    std::vector<float> omega;     // Chebyshev weights per inner index
+
+    // stats of the last step
+    cloth_step_stats last{};
+
+    // optional per-kernel timing: event pairs recorded around launches
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_used;   // (kernel id, pool index of the start event)
+    std::vector<double> kt_ms;
+    std::vector<int64_t> kt_n;
+};
+
+// kernel ids of the timing table
+enum KernelId {
+    K_PREDICT = 0, K_LOCAL, K_REDUCE, K_EXPAND, K_JACOBI, K_TARGETS, K_GRAM_CHOL, K_PCCD, K_OUTER,
+    K_MISC, K_COUNT
+};
+static const char* const kKernelNames[K_COUNT] = {
+    "predict", "local_residual", "reduce_solve", "expand", "jacobi_cheb", "pair_targets",
+    "gram_cholesky", "partial_ccd", "outer_ccd_stage", "misc"};
+
+// host precompute (host_build.cpp)
+std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, double dt,
+                        const cloth_material* mat, const cloth_solver_params* prm);
+size_t footprint_bytes(int nv, int nt, int ne, int64_t nnz, int r, int prec, int64_t pair_cap);
+
+}  // namespace cloth
