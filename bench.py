@@ -160,6 +160,7 @@ def main():
     U = B.rest_eigenbasis(H, sc.pinned, sc.r)
     log(f"basis {time.time() - t0:.1f}s")
     g.set_basis(U)
+    log("basis set (Chebyshev parameters estimated on the device)")
     stream = torch.cuda.current_stream()
     g.set_state(sc.x0, sc.v0, stream=stream)
     st = g.step(sc.gravity, n=max(args.warmup, 1), stream=stream)

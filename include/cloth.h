@@ -164,6 +164,43 @@ cloth_status cloth_step_n(cloth_scene s, const float gravity[3], int32_t n, void
 
 cloth_status cloth_destroy(cloth_scene s);
 
+/* Steps n distinct scenes (same device) once each with gravity g, their
+ * work overlapping on the device: the stream forks to a pool of streams,
+ * each scene's recorded step graph runs on its own stream, and the stream
+ * joins them.  stats: n entries or NULL (then no synchronisation). */
+cloth_status cloth_step_batch(cloth_scene* scenes, int32_t n, const float gravity[3], void* stream,
+                              cloth_step_stats* stats);
+
+/* Continuous-batching step server.  A host thread keeps up to `slots` steps
+ * in flight (one stream each), starts queued requests as slots and their
+ * scenes free up (two steps of one scene never overlap; requests of a scene
+ * run in submission order), and admits scenes while the sum of their device
+ * footprints stays within hbm_budget bytes (0 = no limit).  A scene in a
+ * server must not be stepped or modified by the caller until it is released.
+ *   admit:   *admitted = 1 if the scene fits (or is already in), else 0
+ *   release: waits for the scene's queued steps, then frees its budget
+ *   submit:  queues one step of the scene; returns a ticket
+ *   poll / wait: completion of a ticket, with latency (submission to
+ *            completion, host clock) and service time (device, ms)
+ *   destroy: finishes queued work and stops the thread */
+typedef struct cloth_server_s* cloth_server;
+cloth_status cloth_server_create(int32_t slots, size_t hbm_budget, cloth_server* out);
+cloth_status cloth_server_admit(cloth_server sv, cloth_scene s, int32_t* admitted);
+cloth_status cloth_server_release(cloth_server sv, cloth_scene s);
+cloth_status cloth_server_submit(cloth_server sv, cloth_scene s, const float gravity[3],
+                                 int64_t* ticket);
+cloth_status cloth_server_poll(cloth_server sv, int64_t ticket, int32_t* done, double* latency_ms,
+                               double* service_ms);
+cloth_status cloth_server_wait(cloth_server sv, int64_t ticket, double* latency_ms,
+                               double* service_ms);
+cloth_status cloth_server_destroy(cloth_server sv);
+
+/* Whole-step graph replay (on by default): the first cloth_step / cloth_step_n
+ * records one step's launches into a HIP graph on a private stream and
+ * replays it on the caller's stream; a new gravity vector re-records it.
+ * Steps run with timing on are launched directly. */
+cloth_status cloth_set_graph(cloth_scene s, int32_t on);
+
 /* Per-kernel timing.  With timing on, every kernel (or kernel group) of the
  * step is bracketed by HIP events on the step's stream; cloth_kernel_times
  * synchronises the device and returns, per kernel id, its name (32 chars
@@ -208,6 +245,22 @@ cloth_status cloth_stage_inner(cloth_scene s, int32_t k);
 /* Partial CCD of the loaded block's constraints on (x-, xnew) with xnew
  * given (host, nv*3 floats): updates the life spans only. */
 cloth_status cloth_stage_partial_ccd(cloth_scene s, const float* xnew);
+
+/* One outer CCD stage on (xm, xp) (host arrays): broad phase, time of impact,
+ * new constraint set = {candidates with TOI <= 1} U (loaded set intersected
+ * with the candidates) with carried life spans (first != 0: the loaded set is
+ * ignored and obstacle spans restart), step length s = 1 or alpha t_TOI, and
+ * the filtered positions x = xm + s (xp - xm) (written to x_out, nv*3).
+ * The new set becomes the loaded block (read it with cloth_stage_read_set). */
+cloth_status cloth_stage_outer(cloth_scene s, const float* xm, const float* xp, int32_t first,
+                               float* x_out, double* s_out);
+
+/* The loaded constraint set: sorted VT and EE pairs with life spans (each
+ * list holds at most cap pairs; the counts are returned either way) and the
+ * per-vertex obstacle spans ob_a[j*nv + v] (NULL to skip). */
+cloth_status cloth_stage_read_set(cloth_scene s, int64_t cap, int32_t* vt, int32_t* a_vt,
+                                  int64_t* n_vt, int32_t* ee, int32_t* a_ee, int64_t* n_ee,
+                                  int32_t* ob_a);
 
 /* Reads the block state back: x^k (after cloth_stage_inner: x^{k+1}), the
  * life spans, the last inner iteration's max change, and (if non-NULL) the

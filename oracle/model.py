@@ -35,65 +35,65 @@ def hinges(tris: np.ndarray) -> np.ndarray:
     """Interior edges as rows (x0, x1, x2, x3): the edge (x0 < x1) and the
     opposite vertices of its two triangles, x2 in the lower-index triangle.
     Sorted by edge."""
-    d = {}
-    for t, (a, b, c) in enumerate(tris.tolist()):
-        for (i, j, k) in ((a, b, c), (b, c, a), (c, a, b)):
-            key = (min(i, j), max(i, j))
-            d.setdefault(key, []).append(k)
-    rows = []
-    for key in sorted(d):
-        opp = d[key]
-        if len(opp) == 2:
-            rows.append((key[0], key[1], opp[0], opp[1]))
-        elif len(opp) > 2:
-            raise ValueError("non-manifold edge %s" % (key,))
-    return np.array(rows, dtype=np.int64).reshape(-1, 4)
+    tris = np.asarray(tris, np.int64)
+    T = tris.shape[0]
+    a = np.concatenate([tris[:, 0], tris[:, 1], tris[:, 2]])
+    b = np.concatenate([tris[:, 1], tris[:, 2], tris[:, 0]])
+    o = np.concatenate([tris[:, 2], tris[:, 0], tris[:, 1]])
+    t = np.concatenate([np.arange(T)] * 3)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    order = np.lexsort((t, hi, lo))
+    lo, hi, o = lo[order], hi[order], o[order]
+    same = (lo[1:] == lo[:-1]) & (hi[1:] == hi[:-1])
+    if np.any(same[1:] & same[:-1]):
+        raise ValueError("non-manifold edge")
+    i = np.flatnonzero(same)
+    return np.stack([lo[i], hi[i], o[i], o[i + 1]], 1).astype(np.int64).reshape(-1, 4)
 
 
 def triangle_rest(X: np.ndarray, tris: np.ndarray):
     """Per triangle: rest area and the corner gradient vectors g_c (2-vectors)
     with F = sum_c x_c g_c^T = D_s D_m^{-1}, D_m holding the rest edges in an
-    in-plane orthonormal frame."""
-    T = tris.shape[0]
-    area = np.empty(T)
-    g = np.empty((T, 3, 2))
-    for t in range(T):
-        i, j, k = tris[t]
-        e1 = X[j] - X[i]
-        e2 = X[k] - X[i]
-        u1 = e1 / np.linalg.norm(e1)
-        nrm = np.cross(e1, e2)
-        area[t] = 0.5 * np.linalg.norm(nrm)
-        n = nrm / np.linalg.norm(nrm)
-        u2 = np.cross(n, u1)
-        Dm = np.array([[e1 @ u1, e2 @ u1], [e1 @ u2, e2 @ u2]])
-        Dminv = np.linalg.inv(Dm)
-        g[t, 1] = Dminv[0]
-        g[t, 2] = Dminv[1]
-        g[t, 0] = -Dminv[0] - Dminv[1]
+    in-plane orthonormal frame (u1 along the first edge, u2 = n x u1)."""
+    P = X[tris]
+    e1 = P[:, 1] - P[:, 0]
+    e2 = P[:, 2] - P[:, 0]
+    nrm = np.cross(e1, e2)
+    a2 = np.linalg.norm(nrm, axis=1)
+    area = 0.5 * a2
+    n = nrm / a2[:, None]
+    u1 = e1 / np.linalg.norm(e1, axis=1)[:, None]
+    u2 = np.cross(n, u1)
+    Dm = np.empty((len(tris), 2, 2))
+    Dm[:, 0, 0] = np.einsum("ij,ij->i", e1, u1)
+    Dm[:, 0, 1] = np.einsum("ij,ij->i", e2, u1)
+    Dm[:, 1, 0] = np.einsum("ij,ij->i", e1, u2)
+    Dm[:, 1, 1] = np.einsum("ij,ij->i", e2, u2)
+    Dminv = np.linalg.inv(Dm)
+    g = np.empty((len(tris), 3, 2))
+    g[:, 1] = Dminv[:, 0]
+    g[:, 2] = Dminv[:, 1]
+    g[:, 0] = -Dminv[:, 0] - Dminv[:, 1]
     return area, g
 
 
-def _cot(a: np.ndarray, b: np.ndarray) -> float:
-    return float(a @ b) / float(np.linalg.norm(np.cross(a, b)))
+def _cot(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """cot of the angle between rows of a and b."""
+    return np.einsum("ij,ij->i", a, b) / np.linalg.norm(np.cross(a, b), axis=1)
 
 
-def hinge_rest(X: np.ndarray, hg: np.ndarray, area_of_pair):
+def hinge_rest(X: np.ndarray, hg: np.ndarray, area_of_pair=None):
     """Cotangent stencil K (4 coefficients on x0..x3) and rest areas sum per
     hinge; K annihilates affine fields of the flat rest hinge."""
-    K = np.empty((hg.shape[0], 4))
-    asum = np.empty(hg.shape[0])
-    for e, (x0, x1, x2, x3) in enumerate(hg):
-        p0, p1, p2, p3 = X[x0], X[x1], X[x2], X[x3]
-        cA0 = _cot(p1 - p0, p2 - p0)   # angle at x0 in triangle (x0, x1, x2)
-        cA1 = _cot(p0 - p1, p2 - p1)   # angle at x1 in triangle (x0, x1, x2)
-        cB0 = _cot(p1 - p0, p3 - p0)
-        cB1 = _cot(p0 - p1, p3 - p1)
-        K[e] = [cA1 + cB1, cA0 + cB0, -cA0 - cA1, -cB0 - cB1]
-        aA = 0.5 * np.linalg.norm(np.cross(p1 - p0, p2 - p0))
-        aB = 0.5 * np.linalg.norm(np.cross(p1 - p0, p3 - p0))
-        asum[e] = aA + aB
-    return K, asum
+    p0, p1, p2, p3 = X[hg[:, 0]], X[hg[:, 1]], X[hg[:, 2]], X[hg[:, 3]]
+    cA0 = _cot(p1 - p0, p2 - p0)   # angle at x0 in triangle (x0, x1, x2)
+    cA1 = _cot(p0 - p1, p2 - p1)   # angle at x1 in triangle (x0, x1, x2)
+    cB0 = _cot(p1 - p0, p3 - p0)
+    cB1 = _cot(p0 - p1, p3 - p1)
+    K = np.stack([cA1 + cB1, cA0 + cB0, -cA0 - cA1, -cB0 - cB1], 1)
+    aA = 0.5 * np.linalg.norm(np.cross(p1 - p0, p2 - p0), axis=1)
+    aB = 0.5 * np.linalg.norm(np.cross(p1 - p0, p3 - p0), axis=1)
+    return K, aA + aB
 
 
 @dataclass

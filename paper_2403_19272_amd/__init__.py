@@ -32,7 +32,10 @@ EXPORTS = [
     "cloth_system_matrix", "cloth_set_basis", "cloth_add_obstacle", "cloth_set_state",
     "cloth_get_state", "cloth_step", "cloth_step_n", "cloth_destroy", "cloth_stage_broad_phase",
     "cloth_stage_toi", "cloth_stage_load_block", "cloth_stage_inner", "cloth_stage_partial_ccd",
-    "cloth_stage_read_block", "cloth_set_timing", "cloth_kernel_times",
+    "cloth_stage_read_block", "cloth_set_timing", "cloth_kernel_times", "cloth_set_graph",
+    "cloth_stage_outer", "cloth_stage_read_set", "cloth_step_batch", "cloth_server_create",
+    "cloth_server_admit", "cloth_server_release", "cloth_server_submit", "cloth_server_poll",
+    "cloth_server_wait", "cloth_server_destroy",
 ]
 
 
@@ -93,6 +96,17 @@ def _load():
         "cloth_stage_inner": (i32, [P, i32]),
         "cloth_stage_partial_ccd": (i32, [P, P]),
         "cloth_set_timing": (i32, [P, i32]),
+        "cloth_set_graph": (i32, [P, i32]),
+        "cloth_stage_outer": (i32, [P, P, P, i32, P, C.POINTER(f64)]),
+        "cloth_stage_read_set": (i32, [P, i64, P, P, C.POINTER(i64), P, P, C.POINTER(i64), P]),
+        "cloth_step_batch": (i32, [P, i32, P, P, P]),
+        "cloth_server_create": (i32, [i32, C.c_size_t, C.POINTER(P)]),
+        "cloth_server_admit": (i32, [P, P, C.POINTER(i32)]),
+        "cloth_server_release": (i32, [P, P]),
+        "cloth_server_submit": (i32, [P, P, P, C.POINTER(i64)]),
+        "cloth_server_poll": (i32, [P, i64, C.POINTER(i32), C.POINTER(f64), C.POINTER(f64)]),
+        "cloth_server_wait": (i32, [P, i64, C.POINTER(f64), C.POINTER(f64)]),
+        "cloth_server_destroy": (i32, [P]),
         "cloth_kernel_times": (i32, [P, i32, P, P, P, C.POINTER(i32)]),
         "cloth_stage_read_block": (i32, [P, P, P, P, P, P, P, P]),
     }
@@ -206,6 +220,9 @@ class ClothScene:
                "cloth_step_n")
         return st.as_dict() if stats else None
 
+    def set_graph(self, on: bool):
+        _check(lib.cloth_set_graph(self._h, int(bool(on))), "cloth_set_graph")
+
     # ---- timing
     def set_timing(self, on: bool):
         _check(lib.cloth_set_timing(self._h, int(bool(on))), "cloth_set_timing")
@@ -261,6 +278,27 @@ class ClothScene:
     def stage_inner(self, k):
         _check(lib.cloth_stage_inner(self._h, k), "cloth_stage_inner")
 
+    def stage_outer(self, xm, xp, first=False):
+        x = np.empty((self.nv, 3), np.float32)
+        s = C.c_double(0)
+        _check(lib.cloth_stage_outer(self._h, _ptr(_f32(xm)), _ptr(_f32(xp)), int(bool(first)), _ptr(x),
+                                     C.byref(s)), "cloth_stage_outer")
+        return x, s.value
+
+    def stage_read_set(self, nob=0, cap=None):
+        cap = cap or max(1024, 32 * self.nv)
+        vt = np.empty((cap, 2), np.int32)
+        ee = np.empty((cap, 2), np.int32)
+        avt = np.empty(cap, np.int32)
+        aee = np.empty(cap, np.int32)
+        ob = np.empty(max(nob, 1) * self.nv, np.int32)
+        nvt, nee = C.c_int64(0), C.c_int64(0)
+        _check(lib.cloth_stage_read_set(self._h, cap, _ptr(vt), _ptr(avt), C.byref(nvt), _ptr(ee), _ptr(aee),
+                                        C.byref(nee), _ptr(ob)), "cloth_stage_read_set")
+        self._nvt, self._nee = nvt.value, nee.value
+        return dict(vt=vt[:nvt.value].copy(), a_vt=avt[:nvt.value].copy(), ee=ee[:nee.value].copy(),
+                    a_ee=aee[:nee.value].copy(), ob_a=ob[:nob * self.nv].reshape(nob, self.nv).copy())
+
     def stage_partial_ccd(self, xnew):
         _check(lib.cloth_stage_partial_ccd(self._h, _ptr(_f32(xnew))), "cloth_stage_partial_ccd")
 
@@ -280,6 +318,62 @@ class ClothScene:
     def close(self):
         if self._h:
             lib.cloth_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def step_batch(scenes, gravity=(0.0, -9.8, 0.0), stream=None, stats=True):
+    """One step of every scene in `scenes`, overlapping on the device."""
+    n = len(scenes)
+    hs = (C.c_void_p * n)(*[sc._h.value for sc in scenes])
+    g = np.asarray(gravity, np.float32)
+    st = (StepStats * n)()
+    _check(lib.cloth_step_batch(hs, n, _ptr(g), _stream(stream), st if stats else None),
+           "cloth_step_batch")
+    return [s.as_dict() for s in st] if stats else None
+
+
+class StepServer:
+    """Continuous-batching step server (see cloth_server_* in cloth.h)."""
+
+    def __init__(self, slots=8, hbm_budget=0):
+        self._h = C.c_void_p()
+        _check(lib.cloth_server_create(slots, hbm_budget, C.byref(self._h)), "cloth_server_create")
+
+    def admit(self, scene) -> bool:
+        ok = C.c_int32(0)
+        _check(lib.cloth_server_admit(self._h, scene._h, C.byref(ok)), "cloth_server_admit")
+        return bool(ok.value)
+
+    def release(self, scene):
+        _check(lib.cloth_server_release(self._h, scene._h), "cloth_server_release")
+
+    def submit(self, scene, gravity=(0.0, -9.8, 0.0)) -> int:
+        g = np.asarray(gravity, np.float32)
+        t = C.c_int64(0)
+        _check(lib.cloth_server_submit(self._h, scene._h, _ptr(g), C.byref(t)), "cloth_server_submit")
+        return t.value
+
+    def poll(self, ticket):
+        done = C.c_int32(0)
+        lat, svc = C.c_double(0), C.c_double(0)
+        _check(lib.cloth_server_poll(self._h, ticket, C.byref(done), C.byref(lat), C.byref(svc)),
+               "cloth_server_poll")
+        return (lat.value, svc.value) if done.value else None
+
+    def wait(self, ticket):
+        lat, svc = C.c_double(0), C.c_double(0)
+        _check(lib.cloth_server_wait(self._h, ticket, C.byref(lat), C.byref(svc)), "cloth_server_wait")
+        return lat.value, svc.value
+
+    def close(self):
+        if self._h:
+            lib.cloth_server_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

@@ -21,6 +21,7 @@ SOURCES = [
     # (source, extra flags)
     ("host_build.cpp", []),
     ("api.cpp", ["-fopenmp"]),
+    ("serve.cpp", []),
     ("pd_kernels.hip", []),
     # FP64 geometric predicates: keep the written operation order
     ("contact_kernels.hip", ["-ffp-contract=off"]),
@@ -39,7 +40,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(out)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fopenmp", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fopenmp", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

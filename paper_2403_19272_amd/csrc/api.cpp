@@ -18,11 +18,6 @@
 
 using namespace cloth;
 
-struct cloth_scene_s {
-    Scene s;
-    ContactState c;
-};
-
 namespace {
 
 thread_local std::string g_err;
@@ -611,6 +606,46 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
     return CLOTH_OK;
 }
 
+// Records one step's launches into a graph (every count the kernels need is
+// read from device memory, so the launch sequence of a step never changes).
+static cloth_status capture_step(cloth_scene sc, const float g[3]) {
+    Scene& s = sc->s;
+    if (!s.cap_stream) HIPCHECK(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
+    if (s.graph_exec) {
+        HIPCHECK(hipGraphExecDestroy(s.graph_exec));
+        s.graph_exec = nullptr;
+    }
+    HIPCHECK(hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal));
+    cloth_status rc = step_enqueue(sc, g, s.cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s.cap_stream, &graph);
+    if (rc != CLOTH_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(CLOTH_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&s.graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(CLOTH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    for (int i = 0; i < 3; ++i) s.graph_g[i] = g[i];
+    return CLOTH_OK;
+}
+
+}  // extern "C"
+
+namespace cloth {
+// the scene's step graph, recorded for gravity g if needed
+cloth_status prepare_step_graph(cloth_scene_s* sc, const float g[3]) {
+    Scene& s = sc->s;
+    if (!s.graph_exec || g[0] != s.graph_g[0] || g[1] != s.graph_g[1] || g[2] != s.graph_g[2])
+        return capture_step(sc, g);
+    return CLOTH_OK;
+}
+cloth_status scene_stats(cloth_scene_s* sc, hipStream_t st, cloth_step_stats* out);
+}  // namespace cloth
+
+extern "C" {
+
 static cloth_status collect_stats(cloth_scene sc, hipStream_t st, cloth_step_stats* stats) {
     Scene& s = sc->s;
     int last = s.iters_out * s.iters_in - 1;
@@ -634,6 +669,16 @@ static cloth_status collect_stats(cloth_scene sc, hipStream_t st, cloth_step_sta
     return CLOTH_OK;
 }
 
+}  // extern "C"
+
+namespace cloth {
+cloth_status scene_stats(cloth_scene_s* sc, hipStream_t st, cloth_step_stats* out) {
+    return collect_stats(sc, st, out);
+}
+}  // namespace cloth
+
+extern "C" {
+
 cloth_status cloth_step(cloth_scene sc, const float gravity[3], void* stream, cloth_step_stats* stats) {
     return cloth_step_n(sc, gravity, 1, stream, stats);
 }
@@ -644,9 +689,20 @@ cloth_status cloth_step_n(cloth_scene sc, const float gravity[3], int32_t n, voi
     if (!sc->s.basis_set) return fail(CLOTH_E_INVALID, "basis not set");
     if (n < 0) return fail(CLOTH_E_INVALID, "negative step count");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < n; ++i) {
-        cloth_status rc = step_enqueue(sc, gravity, st);
+    Scene& s = sc->s;
+    bool graph = s.use_graph && !s.timing && n > 0;
+    if (graph && (!s.graph_exec || gravity[0] != s.graph_g[0] || gravity[1] != s.graph_g[1] ||
+                  gravity[2] != s.graph_g[2])) {
+        cloth_status rc = capture_step(sc, gravity);
         if (rc != CLOTH_OK) return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (graph) {
+            HIPCHECK(hipGraphLaunch(s.graph_exec, st));
+        } else {
+            cloth_status rc = step_enqueue(sc, gravity, st);
+            if (rc != CLOTH_OK) return rc;
+        }
     }
     if (stats) return collect_stats(sc, st, stats);
     return CLOTH_OK;
@@ -681,8 +737,16 @@ cloth_status cloth_kernel_times(cloth_scene sc, int32_t max, char* names, double
     return CLOTH_OK;
 }
 
+cloth_status cloth_set_graph(cloth_scene sc, int32_t on) {
+    if (!sc) return fail(CLOTH_E_INVALID, "null argument");
+    sc->s.use_graph = on != 0;
+    return CLOTH_OK;
+}
+
 cloth_status cloth_destroy(cloth_scene sc) {
     if (!sc) return CLOTH_OK;
+    if (sc->s.graph_exec) (void)hipGraphExecDestroy(sc->s.graph_exec);
+    if (sc->s.cap_stream) (void)hipStreamDestroy(sc->s.cap_stream);
     for (hipEvent_t e : sc->s.ev_pool) (void)hipEventDestroy(e);
     contact_destroy(sc->s, sc->c);
     if (sc->s.arena_owned) (void)hipFree(sc->s.arena);
@@ -690,18 +754,61 @@ cloth_status cloth_destroy(cloth_scene sc) {
     return CLOTH_OK;
 }
 
-// Chebyshev parameters from the device iteration itself: for each damping
-// gamma in a small set, the growth rate of the error of the coarse-corrected
-// damped Jacobi sweep (b = 0, no contact, omega = 1) by power iteration; the
-// gamma with the smallest rate is kept and rho = 0.999 * rate.
+// Largest eigenvalue of D^{-1} H on the free rows (FP64 power iteration on
+// the host copy of H): damped Jacobi x <- x + gamma D^{-1} r converges only
+// for gamma < 2 / lambda_max.
+static double jacobi_lambda_max(const Scene& s) {
+    const int n = s.nv;
+    std::vector<double> e(n), f(n);
+    uint64_t st64 = 0x2545F4914F6CDD1Dull;
+    for (int v = 0; v < n; ++v) {
+        st64 ^= st64 << 13;
+        st64 ^= st64 >> 7;
+        st64 ^= st64 << 17;
+        e[v] = s.pinned[v] ? 0.0 : (double)(st64 >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    double lam = 0.0;
+    for (int it = 0; it < 150; ++it) {
+        double nrm = 0.0;
+#pragma omp parallel for reduction(+ : nrm) schedule(static)
+        for (int v = 0; v < n; ++v) {
+            double acc = 0.0;
+            if (!s.pinned[v]) {
+                for (int j = s.rowptr[v]; j < s.rowptr[v + 1]; ++j) acc += s.val[j] * e[s.col[j]];
+                acc /= s.diag[v];
+            }
+            f[v] = acc;
+            nrm += acc * acc;
+        }
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0)) break;
+        lam = nrm;
+        for (int v = 0; v < n; ++v) e[v] = f[v] / nrm;
+    }
+    return lam;
+}
+
+// Chebyshev parameters from the device iteration itself.  The damping
+// candidates are fractions of the Jacobi stability limit 2 / lambda_max; for
+// each, the growth rate of the error of the coarse-corrected damped Jacobi
+// sweep (b = 0, no contact, omega = 1) is measured by power iteration on the
+// device; the fastest converging gamma is kept and rho is set slightly above
+// the measured rate (underestimating rho makes the Chebyshev iteration
+// diverge, overestimating only slows it).
 cloth_status cloth_estimate_chebyshev(cloth_scene sc, void* stream) {
     Scene& s = sc->s;
     Dev& d = s.d;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int n = s.nv;
-    const int warm = 60, meas = 60;
-    const double gammas[] = {1.0, 0.9, 0.8, 0.7, 0.6};
-    bool save_active = sc->c.active;
+    const int warm = 100, meas = 100;
+    double lmax = jacobi_lambda_max(s);
+    double gmax = lmax > 0 ? 2.0 / lmax : 1.0;
+    std::vector<double> cands;
+    if (s.gamma > 0) {
+        cands.push_back(s.gamma);
+    } else {
+        for (double f : {0.95, 0.85, 0.75, 0.65, 0.55}) cands.push_back(std::min(1.0, f * gmax));
+    }
     std::vector<float> e(3 * (size_t)n);
     uint64_t st64 = 0x9E3779B97F4A7C15ull;
     for (size_t i = 0; i < e.size(); ++i) {
@@ -711,11 +818,8 @@ cloth_status cloth_estimate_chebyshev(cloth_scene sc, void* stream) {
         int v = (int)(i % n);
         e[i] = s.pinned[v] ? 0.f : (float)((double)(st64 >> 11) * (1.0 / 9007199254740992.0) - 0.5);
     }
-    float* save_x = d.xk;
-    double best_rate = 1e300, best_gamma = 1.0;
-    double user_gamma = s.gamma;
-    for (double gm : (user_gamma > 0 ? std::vector<double>{user_gamma}
-                                      : std::vector<double>(std::begin(gammas), std::end(gammas)))) {
+    double best_rate = 1e300, best_gamma = cands[0];
+    for (double gm : cands) {
         s.gamma = gm;
         HIPCHECK(hipMemcpyAsync(d.xk, e.data(), sizeof(float) * e.size(), hipMemcpyHostToDevice, st));
         HIPCHECK(launch_copy3(d.xkm1, d.xk, n, st));
@@ -730,17 +834,18 @@ cloth_status cloth_estimate_chebyshev(cloth_scene sc, void* stream) {
         double a, b;
         std::memcpy(&a, &bits[warm - 1], 8);
         std::memcpy(&b, &bits[warm + meas - 1], 8);
-        double rate = (a > 0 && b > 0) ? std::pow(b / a, 1.0 / meas) : 1.0;
+        double rate = (a > 0 && b >= 0) ? std::pow(b / a, 1.0 / meas) : 1e300;
         if (!std::isfinite(rate)) rate = 1e300;
         if (rate < best_rate) {
             best_rate = rate;
             best_gamma = gm;
         }
     }
-    (void)save_x;
-    sc->c.active = save_active;
     s.gamma = best_gamma;
-    if (s.rho <= 0) s.rho = std::min(0.999 * best_rate, 0.9999);
+    if (!(best_rate < 0.9999))
+        return fail(CLOTH_E_DIVERGED, "no damping gives a converging Jacobi sweep (rate " +
+                                          std::to_string(best_rate) + ", lambda_max " + std::to_string(lmax) + ")");
+    if (s.rho <= 0) s.rho = std::min(0.9999, 1.0 - 0.8 * (1.0 - best_rate));
     return CLOTH_OK;
 }
 
@@ -817,6 +922,18 @@ cloth_status cloth_stage_read_block(cloth_scene sc, float* xk, int32_t* a_vt, in
         std::memcpy(dx, &bits, 8);
     }
     return contact_read_constraints(s, sc->c, a_vt, a_ee, ob_a);
+}
+
+cloth_status cloth_stage_outer(cloth_scene sc, const float* xm, const float* xp, int32_t first, float* x_out,
+                               double* s_out) {
+    if (!sc || !xm || !xp) return fail(CLOTH_E_INVALID, "null argument");
+    return contact_stage_outer(sc->s, sc->c, xm, xp, first, x_out, s_out);
+}
+
+cloth_status cloth_stage_read_set(cloth_scene sc, int64_t cap, int32_t* vt, int32_t* a_vt, int64_t* n_vt,
+                                  int32_t* ee, int32_t* a_ee, int64_t* n_ee, int32_t* ob_a) {
+    if (!sc) return fail(CLOTH_E_INVALID, "null argument");
+    return contact_stage_read_set(sc->s, sc->c, cap, vt, a_vt, n_vt, ee, a_ee, n_ee, ob_a);
 }
 
 cloth_status cloth_stage_broad_phase(cloth_scene sc, const float* xm, const float* xp, int64_t cap, int32_t* vt,

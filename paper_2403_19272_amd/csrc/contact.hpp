@@ -16,6 +16,7 @@ struct ContactState {
     ObstD ob[MAX_OBST];
     int64_t cap = 0;        // pair capacity (candidates and constraints per type)
     int hash_p = 0;         // hash buckets (power of two)
+    int max_out = 1024;     // candidate pairs one query may produce
     int ntiles_cap = 0;     // scan tiles for the largest scan
 
     // boxes (lo xyz, hi xyz as 6 floats)
@@ -84,8 +85,18 @@ cloth_status contact_stage_broad_phase(Scene& s, ContactState& c, const float* x
 cloth_status contact_stage_toi(Scene& s, ContactState& c, const float* xm, const float* xp,
                                int64_t n_vt, const int32_t* vt, int64_t n_ee, const int32_t* ee,
                                double* toi_vt, double* toi_ee);
+cloth_status contact_stage_outer(Scene& s, ContactState& c, const float* xm, const float* xp, int first,
+                                 float* x_out, double* s_out);
+cloth_status contact_stage_read_set(Scene& s, ContactState& c, int64_t cap, int32_t* vt, int32_t* a_vt,
+                                    int64_t* n_vt, int32_t* ee, int32_t* a_ee, int64_t* n_ee, int32_t* ob_a);
 void contact_destroy(Scene& s, ContactState& c);
 
 cloth_status set_error(cloth_status code, const std::string& msg);
 
 }  // namespace cloth
+
+// the opaque scene handle of the ABI
+struct cloth_scene_s {
+    cloth::Scene s;
+    cloth::ContactState c;
+};

@@ -497,12 +497,21 @@ __global__ void k_bucket_fill(int m, const int* __restrict__ cell, int P, int* c
 // Query of one box against the hashed targets.  VT: query = vertex v, targets
 // = triangles (skip incident); EE: query = edge e, targets = edges f > e
 // sharing no vertex.  WRITE = false counts, true writes at ofs[q] and sorts.
+// Query of one box against the hashed targets.  VT: query = vertex v, targets
+// = triangles (skip incident); EE: query = edge e, targets = edges f > e
+// sharing no vertex.  WRITE = false counts, true writes at ofs[q] and sorts.
+// Work and output per query are bounded (MAX_VISIT bucket entries, max_out
+// pairs, at most 8 cells per axis, finite boxes only); hitting a bound sets
+// the overflow flag and the step reports a capacity error instead of
+// running away on a diverged state.
+constexpr int MAX_VISIT = 1 << 16;
 template <bool VT, bool WRITE>
 __global__ void k_query(Dev d, const float* __restrict__ qbox, const float* __restrict__ tbox,
                         const int* __restrict__ tcell, const unsigned* __restrict__ maxext_t, const int* bptr,
-                        const int* bitem, int P, int* count, int2* out, int64_t cap, int* overflow) {
+                        const int* bitem, int P, int* count, int2* out, int64_t cap, int max_out, int* overflow) {
     const int nq = VT ? d.nv : d.ne;
     float cs[3] = {cs_of(maxext_t, 0), cs_of(maxext_t, 1), cs_of(maxext_t, 2)};
+    const bool cs_ok = isfinite(cs[0]) && isfinite(cs[1]) && isfinite(cs[2]);
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const float* qb = qbox + 6 * (size_t)q;
         int qa = -1, qb2 = -1;
@@ -510,41 +519,55 @@ __global__ void k_query(Dev d, const float* __restrict__ qbox, const float* __re
             qa = d.edges[2 * q];
             qb2 = d.edges[2 * q + 1];
         }
+        bool ok = cs_ok;
         int lo[3], hi[3];
         for (int c = 0; c < 3; ++c) {
-            lo[c] = cell_of(qb[c], cs[c]) - 2;
-            hi[c] = cell_of(qb[3 + c], cs[c]);
+            ok = ok && isfinite(qb[c]) && isfinite(qb[3 + c]) && fabsf(qb[c] / cs[c]) < 1e9f &&
+                 fabsf(qb[3 + c] / cs[c]) < 1e9f;
+            if (ok) {
+                lo[c] = cell_of(qb[c], cs[c]) - 2;
+                hi[c] = cell_of(qb[3 + c], cs[c]);
+                if (hi[c] - lo[c] > 8) ok = false;
+            }
         }
-        int cnt = 0;
+        int cnt = 0, visits = 0;
+        bool full = !ok;
         int base = WRITE ? count[q] : 0;
-        for (int ix = lo[0]; ix <= hi[0]; ++ix)
-            for (int iy = lo[1]; iy <= hi[1]; ++iy)
-                for (int iz = lo[2]; iz <= hi[2]; ++iz) {
-                    unsigned b = hash3(ix, iy, iz) & (P - 1);
-                    for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
-                        int t = bitem[k];
-                        if (tcell[3 * (size_t)t] != ix || tcell[3 * (size_t)t + 1] != iy ||
-                            tcell[3 * (size_t)t + 2] != iz)
-                            continue;
-                        if (VT) {
-                            TriRec tr = d.tri[t];
-                            if (tr.v0 == q || tr.v1 == q || tr.v2 == q) continue;
-                        } else {
-                            if (t <= q) continue;
-                            int f0 = d.edges[2 * t], f1 = d.edges[2 * t + 1];
-                            if (f0 == qa || f0 == qb2 || f1 == qa || f1 == qb2) continue;
+        if (ok) {
+            for (int ix = lo[0]; ix <= hi[0] && !full; ++ix)
+                for (int iy = lo[1]; iy <= hi[1] && !full; ++iy)
+                    for (int iz = lo[2]; iz <= hi[2] && !full; ++iz) {
+                        unsigned b = hash3(ix, iy, iz) & (P - 1);
+                        for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
+                            if (++visits > MAX_VISIT || cnt >= max_out) {
+                                full = true;
+                                break;
+                            }
+                            int t = bitem[k];
+                            if (tcell[3 * (size_t)t] != ix || tcell[3 * (size_t)t + 1] != iy ||
+                                tcell[3 * (size_t)t + 2] != iz)
+                                continue;
+                            if (VT) {
+                                TriRec tr = d.tri[t];
+                                if (tr.v0 == q || tr.v1 == q || tr.v2 == q) continue;
+                            } else {
+                                if (t <= q) continue;
+                                int f0 = d.edges[2 * t], f1 = d.edges[2 * t + 1];
+                                if (f0 == qa || f0 == qb2 || f1 == qa || f1 == qb2) continue;
+                            }
+                            if (!overlap6(qb, tbox + 6 * (size_t)t)) continue;
+                            if (WRITE) {
+                                int64_t pos = (int64_t)base + cnt;
+                                if (pos >= 0 && pos < cap) out[pos] = make_int2(q, t);
+                            }
+                            ++cnt;
                         }
-                        if (!overlap6(qb, tbox + 6 * (size_t)t)) continue;
-                        if (WRITE) {
-                            int64_t pos = (int64_t)base + cnt;
-                            if (pos < cap) out[pos] = make_int2(q, t);
-                        }
-                        ++cnt;
                     }
-                }
+        }
+        if (full) atomicExch(overflow, 1);
         if (!WRITE) {
             count[q] = cnt;
-        } else {
+        } else if (base >= 0) {
             int64_t b0 = base, b1 = (int64_t)base + cnt;
             if (b1 > cap) {
                 atomicExch(overflow, 1);
@@ -1070,6 +1093,8 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     int P = 1;
     while (P < 2 * std::max(s.nt, s.ne)) P <<= 1;
     c.hash_p = P;
+    // per-query output bound: the int prefix sums over queries cannot overflow
+    c.max_out = (int)std::min<int64_t>(1024, (int64_t)0x7fffffff / std::max<int64_t>(1, std::max(n, s.ne)) - 1);
     int64_t maxscan = std::max<int64_t>({2 * c.cap, (int64_t)n + 1, (int64_t)s.ne + 1, (int64_t)P + 1});
     c.ntiles_cap = (int)((maxscan + SCAN_TILE - 1) / SCAN_TILE) + 1;
     auto I = [&](size_t k) { return static_cast<int*>(carve(sizeof(int) * k)); };
@@ -1188,20 +1213,20 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
         const float* qb = vt ? c.vbox : c.ebox;
         if (vt)
             hipLaunchKernelGGL((k_query<true, false>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
-                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.cnt + 7);
+                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.max_out, c.cnt + 7);
         else
             hipLaunchKernelGGL((k_query<false, false>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
-                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.cnt + 7);
+                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.max_out, c.cnt + 7);
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, c.keep, cnts, nq);
         HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, st));
         hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
                            c.cnt + 7);
         if (vt)
             hipLaunchKernelGGL((k_query<true, true>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
-                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.cnt + 7);
+                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.max_out, c.cnt + 7);
         else
             hipLaunchKernelGGL((k_query<false, true>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
-                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.cnt + 7);
+                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.max_out, c.cnt + 7);
     }
     HC(hipGetLastError());
     return CLOTH_OK;
@@ -1432,6 +1457,46 @@ cloth_status contact_read_constraints(Scene& s, ContactState& c, int32_t* a_vt, 
     if (a_ee && h[3]) HC(hipMemcpy(a_ee, c.ca + h[2], sizeof(int) * h[3], hipMemcpyDeviceToHost));
     if (ob_a && c.nob)
         HC(hipMemcpy(ob_a, c.ob_a, sizeof(int) * (size_t)c.nob * s.nv, hipMemcpyDeviceToHost));
+    return CLOTH_OK;
+}
+
+cloth_status contact_stage_outer(Scene& s, ContactState& c, const float* xm, const float* xp, int first,
+                                 float* x_out, double* s_out) {
+    if (!c.enabled) return set_error(CLOTH_E_INVALID, "no contact in this scene");
+    const int n = s.nv;
+    std::vector<float> t;
+    to_soa(xm, t, n);
+    HC(hipMemcpy(s.d.xm, t.data(), 12 * (size_t)n, hipMemcpyHostToDevice));
+    to_soa(xp, t, n);
+    HC(hipMemcpy(s.d.xt, t.data(), 12 * (size_t)n, hipMemcpyHostToDevice));
+    cloth_status rc = outer_stage(s, c, s.d.xm, s.d.xt, first != 0, true, nullptr);
+    if (rc != CLOTH_OK) return rc;
+    HC(hipDeviceSynchronize());
+    int h[16];
+    HC(hipMemcpy(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost));
+    if (h[7]) return set_error(CLOTH_E_CAPACITY, "pair capacity exceeded");
+    if (s_out) HC(hipMemcpy(s_out, c.s_dev, 8, hipMemcpyDeviceToHost));
+    if (x_out) {
+        HC(hipMemcpy(t.data(), s.d.x, 12 * (size_t)n, hipMemcpyDeviceToHost));
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k) x_out[3 * (size_t)i + k] = t[(size_t)k * n + i];
+    }
+    return CLOTH_OK;
+}
+
+cloth_status contact_stage_read_set(Scene& s, ContactState& c, int64_t cap, int32_t* vt, int32_t* a_vt,
+                                    int64_t* n_vt, int32_t* ee, int32_t* a_ee, int64_t* n_ee, int32_t* ob_a) {
+    int h[16];
+    HC(hipMemcpy(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost));
+    if (n_vt) *n_vt = h[2];
+    if (n_ee) *n_ee = h[3];
+    int64_t mv = std::min<int64_t>(h[2], cap), me = std::min<int64_t>(h[3], cap);
+    if (vt && mv) HC(hipMemcpy(vt, c.cpair, sizeof(int2) * mv, hipMemcpyDeviceToHost));
+    if (a_vt && mv) HC(hipMemcpy(a_vt, c.ca, sizeof(int) * mv, hipMemcpyDeviceToHost));
+    if (ee && me) HC(hipMemcpy(ee, c.cpair + h[2], sizeof(int2) * me, hipMemcpyDeviceToHost));
+    if (a_ee && me) HC(hipMemcpy(a_ee, c.ca + h[2], sizeof(int) * me, hipMemcpyDeviceToHost));
+    if (ob_a && c.nob) HC(hipMemcpy(ob_a, c.ob_a, sizeof(int) * (size_t)c.nob * s.nv, hipMemcpyDeviceToHost));
+    if (h[2] > cap || h[3] > cap) return set_error(CLOTH_E_CAPACITY, "constraint list does not fit");
     return CLOTH_OK;
 }
 

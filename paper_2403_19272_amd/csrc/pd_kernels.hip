@@ -68,6 +68,17 @@ __device__ __forceinline__ void polar32(const float F[6], float T[6]) {
     }
 }
 
+// Workgroups are dealt round-robin over the 8 XCDs; this maps workgroup b to
+// a vertex tile so that each XCD (and its L2) works on one contiguous range,
+// where the neighbour gathers of the SpMV and of the triangle stencils hit.
+// It is a bijection of [0, nblk).
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+    constexpr int X = 8;
+    int x = b % X, i = b / X;
+    int q = nblk / X, rem = nblk % X;
+    return x * q + min(x, rem) + i;
+}
+
 __device__ __forceinline__ double warp_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
@@ -131,7 +142,8 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     __shared__ float red[TPB * 24];
     const int tid = threadIdx.x;
     const int n = d.nv;
-    const int v = blockIdx.x * TPB + tid;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int v = tile * TPB + tid;
     const bool contact = flags & 1, linear = flags & 2;
     float r0[3] = {0.f, 0.f, 0.f};
     if (v < n) {
@@ -245,7 +257,7 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     const UT* U = static_cast<const UT*>(d.U);
     if (vg < nvg) {
         for (int vv = vg; vv < TPB; vv += nvg) {
-            int vtx = blockIdx.x * TPB + vv;
+            int vtx = tile * TPB + vv;
             if (vtx >= n) break;
             float u[8];
             load8<UT>(U, (size_t)vtx * r + cg * 8, u);
@@ -263,7 +275,7 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     for (int o = tid; o < r * 3; o += TPB) {
         float s = 0.f;
         for (int g = 0; g < nvg; ++g) s += red[g * (r * 3) + o];
-        d.gpart[(size_t)blockIdx.x * (r * 3) + o] = s;
+        d.gpart[(size_t)tile * (r * 3) + o] = s;
     }
 }
 
@@ -309,7 +321,7 @@ __global__ void __launch_bounds__(TPB) k_expand(Dev d) {
     for (int o = threadIdx.x; o < r * 3; o += blockDim.x) qs[o] = d.Qf[o];
     __syncthreads();
     const int n = d.nv;
-    const int v = blockIdx.x * TPB + threadIdx.x;
+    const int v = xcd_tile(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     if (v >= n) return;
     const UT* U = static_cast<const UT*>(d.U);
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
@@ -333,7 +345,7 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
                                                     unsigned long long* dx_slot) {
     __shared__ double wmax[TPB / 64];
     const int n = d.nv;
-    const int v = blockIdx.x * TPB + threadIdx.x;
+    const int v = xcd_tile(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     double dxm = 0.0;
     if (v < n) {
         const float* XT = d.xt;

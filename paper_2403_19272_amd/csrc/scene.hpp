@@ -108,6 +108,12 @@ struct Scene {
     // stats of the last step
     cloth_step_stats last{};
 
+    // whole-step graph: captured on a private stream, replayed on the caller's
+    bool use_graph = true;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    float graph_g[3] = {0, 0, 0};
+
     // optional per-kernel timing: event pairs recorded around launches
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;

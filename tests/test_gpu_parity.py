@@ -136,3 +136,234 @@ def test_inner_iteration_with_contact(precision):
     print(f"[inner {precision}] err/diag={err:.3e} update/diag={upd:.3e} Q rel={qerr:.2e}", flush=True)
     assert upd > 1e-4
     assert err <= 1e-5
+
+
+def test_graph_replay_matches_eager_steps():
+    """The recorded whole-step graph, replayed with eager work and host
+    synchronisations in between, gives bitwise the eager result every step."""
+    sc = scenegen.drop_cloth(24, seed=7, obstacle="sphere", r=16, steps=6, drop=0.003, d_hat=1e-3)
+    o, U, rho = oracle_side(sc, "mixed", rho=0.95)
+    a = gpu_side(sc, U, "mixed", 0.95)
+    b = gpu_side(sc, U, "mixed", 0.95)
+    a.set_graph(False)
+    b.set_graph(True)
+    for s in range(sc.steps):
+        sa = a.step(sc.gravity)
+        sb = b.step(sc.gravity)
+        xa, va = a.get_state()
+        xb, vb = b.get_state()
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb), s
+        assert sa["n_constraints"] == sb["n_constraints"]
+    print(f"[graph] constraints={sb['n_constraints']} candidates={sb['n_candidates']}", flush=True)
+
+
+def test_auto_chebyshev_damping_is_stable_on_fine_grid():
+    """Regression: on a bending-dominated fine grid the Jacobi stability limit
+    2 / lambda_max(D^-1 H) is below 0.65; the library's own choice of the
+    damping must respect it and stepping must stay finite."""
+    sc = scenegen.drop_cloth(256, seed=1, obstacle="sphere", r=64, steps=4, d_hat=1e-3)
+    m = M.build_model(sc.tris, sc.rest, sc.pinned, sc.dt, sc.density, sc.k_stretch, sc.k_bend)
+    rng = np.random.default_rng(0)
+    e = rng.standard_normal(m.nv)
+    lam = 0.0
+    for _ in range(200):
+        e = (m.H @ e) / m.diagH
+        lam = np.linalg.norm(e)
+        e /= lam
+    _, U = M.eigenbasis(m, sc.r)
+    import paper_2403_19272_amd as P
+    g = P.ClothScene(sc.tris, sc.rest, dt=sc.dt, density=sc.density, k_stretch=sc.k_stretch,
+                     k_bend=sc.k_bend, d_hat=sc.d_hat, r=sc.r, iters_inner=10, iters_outer=3,
+                     precision=P.CLOTH_MIXED, self_contact=True)
+    g.add_obstacle(P.CLOTH_SPHERE, sc.obstacles[0].center, sc.obstacles[0].radius)
+    g.set_basis(U)
+    g.set_state(sc.x0, sc.v0)
+    st = g.step(sc.gravity, n=sc.steps)
+    print(f"[auto] lambda_max={lam:.3f} gamma={st['cheb_gamma']:.3f} rho={st['cheb_rho']:.4f} dx={st['dx_norm']:.2e}", flush=True)
+    assert lam > 2.5 and st["cheb_gamma"] * lam < 2.0
+    assert 0 < st["cheb_rho"] < 1
+    x, v = g.get_state()
+    assert np.isfinite(x).all() and np.isfinite(v).all()
+    assert np.abs(x - sc.x0).max() < 0.05
+
+
+@pytest.mark.parametrize("first", [True, False])
+def test_outer_stage_set_spans_and_filter(first):
+    """Outer stage on identical FP32 inputs: the new constraint set and carried
+    life spans bit-exact, the step length within 1e-6, the filtered positions
+    within FP32 rounding."""
+    sc, o, U, blk = contact_block(n=24, seed=5)
+    g = gpu_side(sc, U, "fp32", 0.95)
+    g.stage_load_block(blk["xm"], blk["xk"], blk["xkm1"], blk["z"], blk["vt"], blk["a_vt"], blk["ee"],
+                       blk["a_ee"], blk["ob_a"])
+    x_gpu, s_gpu = g.stage_outer(blk["xm"], blk["xp"], first)
+    got = g.stage_read_set(nob=1)
+    prev = S.Constraints() if first else oracle_constraints(o, blk)
+    xm64, xp64 = blk["xm"].astype(np.float64), blk["xp"].astype(np.float64)
+    s_or, C = o._outer_ccd(xm64, xp64, prev, S.StepStats())
+    print(f"[outer first={first}] s={s_gpu:.6f}/{s_or:.6f} vt={len(C.vt)} ee={len(C.ee)} ob={len(C.ob)} "
+          f"carried={int((C.a_vt > 0).sum() + (C.a_ee > 0).sum())}", flush=True)
+    assert len(C.vt) + len(C.ee) > 0
+    assert np.array_equal(got["vt"], C.vt) and np.array_equal(got["a_vt"], C.a_vt)
+    assert np.array_equal(got["ee"], C.ee) and np.array_equal(got["a_ee"], C.a_ee)
+    ob = np.full(sc.nv, -1, np.int32)
+    ob[C.ob[:, 0]] = C.a_ob
+    assert np.array_equal(got["ob_a"][0], ob)
+    assert abs(s_gpu - s_or) <= 1e-6
+    x_or = xm64 + s_or * (xp64 - xm64)
+    assert vertex_err(x_gpu, x_or) <= 1e-6 * bbox_diag(x_or)
+
+
+def full_size_scene():
+    sc = scenegen.config(2)
+    rng = np.random.default_rng(11)
+    U, _ = np.linalg.qr(rng.standard_normal((sc.nv, sc.r)))   # any basis is a valid input here
+    return sc, U
+
+
+def test_full_size_broad_phase_and_sampled_toi():
+    """600 x 600 cloth: pair lists bit-exact, TOI within 1e-6 on a sample."""
+    sc, U = full_size_scene()
+    rng = np.random.default_rng(12)
+    xm = (sc.x0 + rng.normal(0, 2e-4, sc.x0.shape)).astype(np.float32)
+    xp = (xm + rng.normal(0, 5e-4, xm.shape) + np.array([0, -0.01, 0])).astype(np.float32)
+    g = gpu_side(sc, U, "mixed", 0.95)
+    vt, ee = g.stage_broad_phase(xm, xp, cap=48 * sc.nv)
+    edges = M.unique_edges(sc.tris)
+    ovt, oee = native.broad_phase(xm, xp, edges, sc.tris, sc.d_hat, cap=48 * sc.nv)
+    print(f"[full bp] vt={len(vt)} ee={len(ee)}", flush=True)
+    assert len(vt) > 100000 and len(ee) > 100000
+    assert np.array_equal(vt, ovt) and np.array_equal(ee, oee)
+    svt = vt[rng.choice(len(vt), 20000, replace=False)]
+    see = ee[rng.choice(len(ee), 20000, replace=False)]
+    tv, te = g.stage_toi(xm, xp, svt, see)
+    otv, ote, _ = native.toi_pairs(xm.astype(np.float64), xp.astype(np.float64), sc.tris, edges, svt, see)
+    assert np.array_equal(tv <= 1, otv <= 1) and np.array_equal(te <= 1, ote <= 1)
+    h = otv <= 1
+    assert np.abs(tv[h] - otv[h]).max(initial=0) <= 1e-6
+    h = ote <= 1
+    assert np.abs(te[h] - ote[h]).max(initial=0) <= 1e-6
+
+
+def test_full_size_inner_iteration():
+    """600 x 600 cloth, r = 128 BF16 basis: one inner iteration with pair and
+    obstacle constraints from a shared state, against the oracle."""
+    sc, U = full_size_scene()
+    rng = np.random.default_rng(13)
+    xm = (sc.x0 + rng.normal(0, 2e-4, sc.x0.shape)).astype(np.float32)
+    xp = (xm + rng.normal(0, 5e-4, xm.shape)).astype(np.float32)
+    o, _, rho = oracle_side(sc, "mixed", rho=0.98, gamma=0.5, U=U)
+    vt, ee = native.broad_phase(xm, xp, o.m.edges, o.m.tris, sc.d_hat, cap=48 * sc.nv)
+    vt = vt[rng.random(len(vt)) < 0.05]
+    ee = ee[rng.random(len(ee)) < 0.05]
+    blk = dict(xm=xm, xk=(xm + rng.normal(0, 1e-4, xm.shape)).astype(np.float32), vt=vt, ee=ee,
+               a_vt=rng.integers(0, 6, len(vt)).astype(np.int32), a_ee=rng.integers(0, 6, len(ee)).astype(np.int32),
+               ob_a=np.where(rng.random(sc.nv) < 0.1, rng.integers(0, 6, sc.nv), -1).astype(np.int32)[None])
+    blk["xkm1"] = (blk["xk"] + rng.normal(0, 5e-5, xm.shape)).astype(np.float32)
+    blk["z"] = (blk["xk"] + rng.normal(0, 2e-4, xm.shape)).astype(np.float32)
+    g = gpu_side(sc, U, "mixed", rho, gamma=0.5)
+    g.stage_load_block(blk["xm"], blk["xk"], blk["xkm1"], blk["z"], blk["vt"], blk["a_vt"], blk["ee"],
+                       blk["a_ee"], blk["ob_a"])
+    k = 5
+    g.stage_inner(k)
+    got = g.stage_read_block(nob=1)
+    C = oracle_constraints(o, blk)
+    inertia = (o.m.mass / o.m.h ** 2)[:, None] * blk["z"].astype(np.float64)
+    xk1 = o.iterate(blk["xk"].astype(np.float64), blk["xkm1"].astype(np.float64), k, C, inertia, xm.astype(np.float64))
+    diag = bbox_diag(xk1)
+    err = vertex_err(got["xk"], xk1) / diag
+    upd = vertex_err(xk1, blk["xk"]) / diag
+    dx_or = float(np.linalg.norm(xk1 - blk["xk"], axis=1).max())
+    print(f"[full inner] constraints={len(vt) + len(ee)} err/diag={err:.3e} update/diag={upd:.3e} "
+          f"dx={got['dx']:.4e}/{dx_or:.4e}", flush=True)
+    assert upd > 1e-5
+    assert err <= 1e-5
+    assert abs(got["dx"] - dx_or) <= 1e-5 * diag
+
+
+def test_full_size_steps_stay_tangle_free():
+    """600 x 600 cloth starting 5 mm above the cylinder, the bench's solver
+    settings (library basis and Chebyshev estimate): finite and free of
+    intersecting triangles after every step."""
+    from oracle import exact
+    import paper_2403_19272_amd as P
+    from paper_2403_19272_amd import basis as B
+    sc = scenegen.drop_cloth(600, seed=2, obstacle="cylinder", r=128, steps=8, drop=0.005, precision="mixed")
+    g = P.ClothScene(sc.tris, sc.rest, dt=sc.dt, density=sc.density, k_stretch=sc.k_stretch,
+                     k_bend=sc.k_bend, d_hat=sc.d_hat, r=sc.r, iters_inner=10, iters_outer=3,
+                     precision=P.CLOTH_MIXED, self_contact=True)
+    ob = sc.obstacles[0]
+    g.add_obstacle(ob.kind, ob.center, ob.radius, axis=ob.axis, half_length=ob.half_length, omega=ob.omega)
+    g.set_basis(B.rest_eigenbasis(g.system_matrix(), sc.pinned, sc.r))
+    g.set_state(sc.x0, sc.v0)
+    assert exact.count_tangles(sc.x0, sc.tris) == 0
+    for s in range(sc.steps):
+        st = g.step(sc.gravity)
+        x, v = g.get_state()
+        assert np.isfinite(x).all()
+        nt = exact.count_tangles(x, sc.tris)
+        print(f"[full steps] step {s} constraints={st['n_constraints']} min_toi={st['min_toi']:.3f} "
+              f"tangles={nt}", flush=True)
+        assert nt == 0
+    assert st["n_constraints"] > 0
+
+
+def uneven_scenes(count=4, seed=21):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(16, 49))
+        sc = scenegen.drop_cloth(n, seed=int(rng.integers(1 << 20)), obstacle="sphere", r=16, steps=5,
+                                 drop=0.004, d_hat=1e-3, side=(n - 1) / 127.0)
+        o, U, rho = oracle_side(sc, "mixed", rho=0.95, gamma=0.6)
+        out.append((sc, U))
+    return out
+
+
+def test_batch_equals_scenes_stepped_alone():
+    """Batched (overlapping) stepping gives each scene bitwise its alone result."""
+    import paper_2403_19272_amd as P
+    specs = uneven_scenes()
+    alone = [gpu_side(sc, U, "mixed", 0.95, gamma=0.6) for sc, U in specs]
+    batch = [gpu_side(sc, U, "mixed", 0.95, gamma=0.6) for sc, U in specs]
+    g = specs[0][0].gravity
+    for s in range(4):
+        for a in alone:
+            a.step(g)
+        P.step_batch(batch, g)
+        for a, b in zip(alone, batch):
+            xa, va = a.get_state()
+            xb, vb = b.get_state()
+            assert np.array_equal(xa, xb) and np.array_equal(va, vb), s
+
+
+def test_server_results_equal_alone_runs():
+    """Requests from several scenes, submitted interleaved while others run,
+    give every scene bitwise the state it reaches stepped alone; latencies
+    are recorded."""
+    import paper_2403_19272_amd as P
+    specs = uneven_scenes(5, seed=22)
+    alone = [gpu_side(sc, U, "mixed", 0.95, gamma=0.6) for sc, U in specs]
+    served = [gpu_side(sc, U, "mixed", 0.95, gamma=0.6) for sc, U in specs]
+    g = specs[0][0].gravity
+    steps = [3, 1, 4, 2, 3]
+    for a, k in zip(alone, steps):
+        for _ in range(k):
+            a.step(g)
+    srv = P.StepServer(slots=3, hbm_budget=0)
+    for sc in served:
+        assert srv.admit(sc)
+    order = [i for i, k in enumerate(steps) for _ in range(k)]
+    rng = np.random.default_rng(0)
+    rng.shuffle(order)
+    tickets = [srv.submit(served[i], g) for i in order]
+    lat = [srv.wait(t) for t in tickets]
+    srv.close()
+    for a, b in zip(alone, served):
+        xa, va = a.get_state()
+        xb, vb = b.get_state()
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    assert all(l >= s >= 0 for l, s in lat)
+    small = P.StepServer(slots=2, hbm_budget=served[0].footprint + served[1].footprint)
+    assert small.admit(served[0]) and small.admit(served[1]) and not small.admit(served[2])
+    small.close()
