@@ -163,8 +163,11 @@ def main():
     log("basis set (Chebyshev parameters estimated on the device)")
     stream = torch.cuda.current_stream()
     g.set_state(sc.x0, sc.v0, stream=stream)
-    st = g.step(sc.gravity, n=max(args.warmup, 1), stream=stream)
-    log(f"warmup {args.warmup} steps: {st}")
+    for i in range(max(args.warmup, 1)):
+        st = g.step(sc.gravity, n=1, stream=stream)
+        log(f"warmup step {i}: dx={st['dx_norm']:.3e} candidates={st['n_candidates']} "
+            f"constraints={st['n_constraints']} min_toi={st['min_toi']:.4f} "
+            f"rho={st['cheb_rho']:.4f} gamma={st['cheb_gamma']:.4f}")
 
     def timed_pass(K, timing):
         g.set_state(sc.x0, sc.v0, stream=stream)

@@ -145,6 +145,18 @@ cloth_status cloth_system_matrix(cloth_scene s, int64_t* nnz, int32_t* row_ptr, 
  * any basis is accepted (the correction is a Galerkin projection). */
 cloth_status cloth_set_basis(cloth_scene s, const double* U, int32_t r);
 
+/* Computes the basis on the device and sets it (as cloth_set_basis): the r
+ * lowest eigenvectors of H on the free vertices by Chebyshev-filtered
+ * subspace iteration (polynomial degree `degree` per pass, at most
+ * max_passes passes, until the largest relative Ritz residual
+ * |H u - theta u| / theta of the r wanted pairs is below tol).  Block
+ * products run in FP32, the small eigenproblems in FP64 on the host.
+ * Optional outputs: U (nv*r FP64, caller order), the Ritz values (r), the
+ * passes used and the final residual.  Section 5 (U from the rest H). */
+cloth_status cloth_compute_basis(cloth_scene s, int32_t r, int32_t degree, int32_t max_passes,
+                                 double tol, double* U, double* ritz, int32_t* passes,
+                                 double* residual);
+
 /* Adds an analytic obstacle (at most 4 per scene). */
 cloth_status cloth_add_obstacle(cloth_scene s, const cloth_obstacle* ob);
 
@@ -194,6 +206,24 @@ cloth_status cloth_server_poll(cloth_server sv, int64_t ticket, int32_t* done, d
 cloth_status cloth_server_wait(cloth_server sv, int64_t ticket, double* latency_ms,
                                double* service_ms);
 cloth_status cloth_server_destroy(cloth_server sv);
+
+/* Optional parts of Algorithm 1 around the inner loop:
+ *   warm_iters  modal warm start: that many local/global iterations in
+ *               span(U) from z, collisions ignored, before the first full CCD
+ *               (the same basis serves the warm start and the reuse)
+ *   rf_iters    residual forwarding (section 6): after the exiting filter,
+ *               that many inner iterations with every collision weight at k
+ *               and no filter; if the exiting t_TOI was below rf_toi their
+ *               displacement dx is forwarded, the next step's z gaining
+ *               h^2 M^{-1} delta f = 2 dx (Eq. (z_rf), delta f = 2 M dx / h^2).
+ *               The iterations run every step and their result is applied
+ *               on the device only when the condition holds.
+ * Both default to 0 (off).  Changing them re-records the step graph. */
+cloth_status cloth_set_step_options(cloth_scene s, int32_t warm_iters, int32_t rf_iters,
+                                    double rf_toi);
+
+/* The residual currently forwarded to the next step (nv*3 host floats). */
+cloth_status cloth_get_forwarded(cloth_scene s, float* dx);
 
 /* Whole-step graph replay (on by default): the first cloth_step / cloth_step_n
  * records one step's launches into a HIP graph on a private stream and

@@ -49,6 +49,9 @@ class Params:
     K_base: float = 2.0
     a_max: int = 20
     self_contact: bool = True
+    warm_iters: int = 0        # modal warm-start iterations (0 = start from z)
+    rf_iters: int = 0          # residual-forwarding iterations (0 = off)
+    rf_toi: float = 0.5        # forward the residual when the exiting t_TOI is below this
 
 
 @dataclass
@@ -82,6 +85,7 @@ class StepStats:
     n_candidates: int = 0
     n_constraints: int = 0
     fallbacks: int = 0
+    t_exit: float = NO_HIT     # t_TOI of the step's last (exiting) filter
 
 
 def chebyshev_weights(n: int, rho: float, delay: int) -> np.ndarray:
@@ -206,8 +210,9 @@ class Oracle:
         self.v = np.zeros_like(self.x)
         self.free = ~model.pinned
         self.pin_pos = model.rest.copy()
-        self.omega = chebyshev_weights(max(params.iters_inner, 1), params.cheb_rho,
+        self.omega = chebyshev_weights(max(params.iters_inner, params.rf_iters, 1), params.cheb_rho,
                                        params.cheb_delay)
+        self.rf_dx = np.zeros_like(self.x)   # residual forwarded to the next step (2 dx term of z)
         self.last = StepStats()
 
     # ---- state
@@ -215,6 +220,7 @@ class Oracle:
         self.x = np.array(x, np.float64)
         self.v = np.array(v, np.float64)
         self.pin_pos = self.x.copy()
+        self.rf_dx = np.zeros_like(self.x)
 
     # ---- constraint bookkeeping
     def _weights(self, a: np.ndarray) -> np.ndarray:
@@ -337,14 +343,19 @@ class Oracle:
         h = m.h
         st = StepStats()
         xs = self.x
-        z = xs + h * self.v + h * h * self.g
+        # Eq. (z_rf): z = x* + h v* + h^2 (M^{-1} f_ext + M^{-1} delta f), with
+        # h^2 M^{-1} delta f = 2 dx forwarded by the previous step
+        z = xs + h * self.v + h * h * self.g + 2.0 * self.rf_dx
         z[m.pinned] = self.pin_pos[m.pinned]
+        self.rf_dx = np.zeros_like(xs)
+        inertia = (m.mass / (h * h))[:, None] * z
+        xw = self.warm_start(z, inertia) if p.warm_iters > 0 else z
         xm = xs.copy()
-        s, C = self._outer_ccd(xm, z, Constraints(), st)
-        x = xm + s * (z - xm)
+        s, C = self._outer_ccd(xm, xw, Constraints(), st)
+        x = xm + s * (xw - xm)
         xm = x.copy()
         self._freeze(C, xm)
-        inertia = (m.mass / (h * h))[:, None] * z
+        t_exit = NO_HIT
         for o in range(p.iters_outer):
             xk = x.copy()
             xkm1 = x.copy()
@@ -354,15 +365,55 @@ class Oracle:
                 st.dx.append(float(np.linalg.norm(xk1 - xk, axis=1).max()))
                 xkm1, xk = xk, xk1
             xp = xk
-            s, C = self._outer_ccd(xm, xp, C, st)
+            st_o = StepStats()
+            s, C = self._outer_ccd(xm, xp, C, st_o)
+            st.min_toi = min(st.min_toi, st_o.min_toi)
+            st.n_candidates = st_o.n_candidates
+            st.fallbacks += st_o.fallbacks
+            t_exit = st_o.min_toi
             x = xm + s * (xp - xm)
             xm = x.copy()
             self._freeze(C, xm)
         st.n_constraints = len(C.vt) + len(C.ee) + len(C.ob)
+        st.t_exit = t_exit
+        if p.rf_iters > 0 and t_exit < p.rf_toi:
+            self.rf_dx = self.residual_forward(x, C, inertia)
         self.v = (x - xs) / h
         self.x = x
         self.last = st
         return st
+
+    def warm_start(self, z, inertia):
+        """Modal warm start (Algorithm 1 before the first full CCD): local
+        projections of the elastic terms and the global solve restricted to
+        span(U), collisions ignored: q = Lambda~^{-1} U^T (b - H x), x += U q,
+        warm_iters times from x = z."""
+        m = self.m
+        cf = sla.cho_factor(self.Lam)
+        x = z.copy()
+        for _ in range(self.p.warm_iters):
+            b = inertia + elastic_rhs(m, x)
+            r = b - m.H @ x
+            r[~self.free] = 0
+            x = x + self.U @ sla.cho_solve(cf, self.U.T @ r)
+        return x
+
+    def residual_forward(self, x, C, inertia):
+        """Residual forwarding (section 6): with every collision weight at k
+        (a = 0, the quadratic approximation of the barrier) and no CCD filter,
+        rf_iters inner iterations from x approximate one more Newton-like
+        solve; their displacement dx is forwarded as delta f = 2 M dx / h^2,
+        i.e. z of the next step gains 2 dx."""
+        Crf = Constraints(vt=C.vt, ee=C.ee, ob=C.ob, a_vt=np.zeros_like(C.a_vt), a_ee=np.zeros_like(C.a_ee),
+                          a_ob=np.zeros_like(C.a_ob), lam_vt=C.lam_vt, n_vt=C.n_vt, lam_ee=C.lam_ee, n_ee=C.n_ee)
+        xk = x.copy()
+        xkm1 = x.copy()
+        for k in range(self.p.rf_iters):
+            xk1 = self.iterate(xk, xkm1, k, Crf, inertia, x)
+            xkm1, xk = xk, xk1
+        dx = xk - x
+        dx[~self.free] = 0
+        return dx
 
     def iterate(self, xk, xkm1, k, C, inertia, xm, frozen=None):
         """One inner PD iteration from x^k (history x^{k-1}) -> x^{k+1}.

@@ -35,7 +35,8 @@ EXPORTS = [
     "cloth_stage_read_block", "cloth_set_timing", "cloth_kernel_times", "cloth_set_graph",
     "cloth_stage_outer", "cloth_stage_read_set", "cloth_step_batch", "cloth_server_create",
     "cloth_server_admit", "cloth_server_release", "cloth_server_submit", "cloth_server_poll",
-    "cloth_server_wait", "cloth_server_destroy",
+    "cloth_server_wait", "cloth_server_destroy", "cloth_compute_basis", "cloth_set_step_options",
+    "cloth_get_forwarded",
 ]
 
 
@@ -107,6 +108,9 @@ def _load():
         "cloth_server_poll": (i32, [P, i64, C.POINTER(i32), C.POINTER(f64), C.POINTER(f64)]),
         "cloth_server_wait": (i32, [P, i64, C.POINTER(f64), C.POINTER(f64)]),
         "cloth_server_destroy": (i32, [P]),
+        "cloth_compute_basis": (i32, [P, i32, i32, i32, f64, P, P, C.POINTER(i32), C.POINTER(f64)]),
+        "cloth_set_step_options": (i32, [P, i32, i32, f64]),
+        "cloth_get_forwarded": (i32, [P, P]),
         "cloth_kernel_times": (i32, [P, i32, P, P, P, C.POINTER(i32)]),
         "cloth_stage_read_block": (i32, [P, P, P, P, P, P, P, P]),
     }
@@ -196,6 +200,16 @@ class ClothScene:
         U = np.ascontiguousarray(U, np.float64)
         _check(lib.cloth_set_basis(self._h, _ptr(U), U.shape[1]), "cloth_set_basis")
 
+    def compute_basis(self, degree=300, max_passes=12, tol=2e-2, return_basis=False):
+        """Device eigenbasis (Chebyshev-filtered subspace iteration), then set."""
+        U = np.empty((self.nv, self.r)) if return_basis else None
+        w = np.empty(self.r)
+        npass = C.c_int32(0)
+        res = C.c_double(0)
+        _check(lib.cloth_compute_basis(self._h, self.r, degree, max_passes, tol, _ptr(U), _ptr(w),
+                                       C.byref(npass), C.byref(res)), "cloth_compute_basis")
+        return dict(U=U, ritz=w, passes=npass.value, residual=res.value)
+
     def add_obstacle(self, kind, center, radius, axis=(1.0, 0.0, 0.0), half_length=0.0, omega=0.0):
         ob = Obstacle(kind, (C.c_double * 3)(*center), (C.c_double * 3)(*axis), radius,
                       half_length, omega)
@@ -219,6 +233,14 @@ class ClothScene:
         _check(lib.cloth_step_n(self._h, _ptr(g), n, _stream(stream), C.byref(st) if stats else None),
                "cloth_step_n")
         return st.as_dict() if stats else None
+
+    def set_step_options(self, warm_iters=0, rf_iters=0, rf_toi=0.5):
+        _check(lib.cloth_set_step_options(self._h, warm_iters, rf_iters, rf_toi), "cloth_set_step_options")
+
+    def forwarded(self):
+        dx = np.empty((self.nv, 3), np.float32)
+        _check(lib.cloth_get_forwarded(self._h, _ptr(dx)), "cloth_get_forwarded")
+        return dx
 
     def set_graph(self, on: bool):
         _check(lib.cloth_set_graph(self._h, int(bool(on))), "cloth_set_graph")

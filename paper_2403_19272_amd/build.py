@@ -23,6 +23,7 @@ SOURCES = [
     ("api.cpp", ["-fopenmp"]),
     ("serve.cpp", []),
     ("pd_kernels.hip", []),
+    ("eig.hip", []),
     # FP64 geometric predicates: keep the written operation order
     ("contact_kernels.hip", ["-ffp-contract=off"]),
 ]

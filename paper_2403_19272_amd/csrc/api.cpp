@@ -165,9 +165,10 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     d.Amat = cv<double>(carve_fn, (size_t)s.r * s.r);
     d.gram_part = cv<float>(carve_fn, (size_t)64 * s.r * s.r);
     d.dxbits = cv<unsigned long long>(carve_fn, 4096);
+    s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);
     if (!d.W || !d.mh2 || !d.diag || !s.d_pinned || !s.d_rowptr || !s.d_col || !s.d_val || !s.d_tri ||
         !s.d_inc_ptr || !s.d_inc || !s.d_edges || !s.d_U || !d.gpart || !d.Qf || !d.Qd || !d.Ainv ||
-        !d.Lam || !d.Amat || !d.gram_part || !d.dxbits)
+        !d.Lam || !d.Amat || !d.gram_part || !d.dxbits || !s.d_rfdx)
         return fail(CLOTH_E_OOM, "arena exhausted");
     return contact_layout(s, c, carve_fn);
 }
@@ -249,22 +250,38 @@ static cloth_status fail_any(cloth_status c, const char*) { return c; }
 // One inner iteration on the device state: x^k = d.xk, x^{k-1} = d.xkm1 ->
 // d.xk1; then buffers rotate so that d.xk holds x^{k+1}.
 static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStream_t st, bool linear,
-                                    float omega_override) {
+                                    float omega_override, bool force_k = false) {
     Scene& s = sc->s;
     ContactState& c = sc->c;
     Dev& d = s.d;
     int has_contact = (c.active && !linear) ? 1 : 0;
-    if (has_contact) TIMED(K_TARGETS, contact_prepare_iteration(s, c, st));
-    TIMED(K_LOCAL, launch_local_residual(d, s.prec, has_contact | (linear ? 2 : 0), st));
+    if (has_contact) TIMED(K_TARGETS, contact_prepare_iteration(s, c, force_k, st));
+    TIMED(K_LOCAL, launch_local_residual(d, s.prec, has_contact | (linear ? 2 : 0) | (force_k ? 4 : 0), st));
     TIMED(K_REDUCE, launch_reduce_solve(d, s.nblk, has_contact, c.gpart2, st));
     if (has_contact) TIMED(K_GRAM_CHOL, contact_dynamic_solve(s, c, st));
-    TIMED(K_EXPAND, launch_expand(d, s.prec, st));
+    TIMED(K_EXPAND, launch_expand(d, s.prec, 0, st));
     float om = omega_override > 0 ? omega_override : s.omega[std::min(k, (int)s.omega.size() - 1)];
     TIMED(K_JACOBI, launch_jacobi_cheb(d, om, (float)s.gamma, has_contact, s.d.dxbits + slot, st));
     float* t = d.xkm1;
     d.xkm1 = d.xk;
     d.xk = d.xk1;
     d.xk1 = t;
+    return CLOTH_OK;
+}
+
+// One modal warm-start iteration on d.xk (collisions ignored): local step,
+// q = Lambda~^{-1} U^T (b - H x), x <- x + U q (Algorithm 1, before the
+// first full CCD).
+static cloth_status modal_iteration(cloth_scene_s* sc, hipStream_t st) {
+    Scene& s = sc->s;
+    ContactState& c = sc->c;
+    Dev& d = s.d;
+    TIMED(K_LOCAL, launch_local_residual(d, s.prec, 0, st));
+    TIMED(K_REDUCE, launch_reduce_solve(d, s.nblk, 0, c.gpart2, st));
+    TIMED(K_EXPAND, launch_expand(d, s.prec, 1, st));
+    float* t = d.xk;
+    d.xk = d.xt;
+    d.xt = t;
     return CLOTH_OK;
 }
 
@@ -431,6 +448,7 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     HIPCHECK(hipMemset(d.v, 0, sizeof(float) * 3 * n));
     HIPCHECK(hipMemset(d.W, 0, sizeof(float) * n));
     HIPCHECK(hipMemset(d.WY, 0, sizeof(float) * 3 * n));
+    HIPCHECK(hipMemset(s.d_rfdx, 0, sizeof(float) * 3 * n));
     cloth_status rc = contact_upload(s, sc->c);
     if (rc != CLOTH_OK) return rc;
     HIPCHECK(hipDeviceSynchronize());
@@ -515,8 +533,51 @@ cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
         cloth_status rc = cloth_estimate_chebyshev(sc, nullptr);
         if (rc != CLOTH_OK) return rc;
     }
-    s.omega = cheb_weights(s.iters_in, s.rho, s.delay);
+    s.omega = cheb_weights(std::max(s.iters_in, s.rf_iters), s.rho, s.delay);
     return CLOTH_OK;
+}
+
+cloth_status cloth_set_step_options(cloth_scene sc, int32_t warm_iters, int32_t rf_iters, double rf_toi) {
+    if (!sc || warm_iters < 0 || rf_iters < 0) return fail(CLOTH_E_INVALID, "bad step options");
+    Scene& s = sc->s;
+    s.warm_iters = warm_iters;
+    s.rf_iters = rf_iters;
+    s.rf_toi = rf_toi;
+    if (s.basis_set) s.omega = cheb_weights(std::max(s.iters_in, s.rf_iters), s.rho, s.delay);
+    if (s.graph_exec) {
+        HIPCHECK(hipGraphExecDestroy(s.graph_exec));
+        s.graph_exec = nullptr;
+    }
+    return CLOTH_OK;
+}
+
+cloth_status cloth_get_forwarded(cloth_scene sc, float* dx) {
+    if (!sc || !dx) return fail(CLOTH_E_INVALID, "null argument");
+    Scene& s = sc->s;
+    std::vector<float> t(3 * (size_t)s.nv);
+    HIPCHECK(hipDeviceSynchronize());
+    HIPCHECK(hipMemcpy(t.data(), s.d_rfdx, 12 * (size_t)s.nv, hipMemcpyDeviceToHost));
+    soa_to_aos(t, dx, s.nv);
+    return CLOTH_OK;
+}
+
+cloth_status cloth_compute_basis(cloth_scene sc, int32_t r, int32_t degree, int32_t max_passes, double tol,
+                                 double* U, double* ritz, int32_t* passes, double* residual) {
+    if (!sc) return fail(CLOTH_E_INVALID, "null argument");
+    Scene& s = sc->s;
+    if (r != s.r) return fail(CLOTH_E_INVALID, "basis width differs from params.r");
+    if (degree < 1 || max_passes < 1) return fail(CLOTH_E_INVALID, "degree and passes must be positive");
+    std::vector<double> Uh, w;
+    std::string err;
+    int p = 0;
+    double res = 0;
+    cloth_status rc = device_eigenbasis(s, r, degree, max_passes, tol, Uh, w, &p, &res, err);
+    if (rc != CLOTH_OK) return fail(rc, err);
+    if (U) std::copy(Uh.begin(), Uh.end(), U);
+    if (ritz) std::copy(w.begin(), w.end(), ritz);
+    if (passes) *passes = p;
+    if (residual) *residual = res;
+    return cloth_set_basis(sc, Uh.data(), r);
 }
 
 cloth_status cloth_add_obstacle(cloth_scene sc, const cloth_obstacle* ob) {
@@ -581,12 +642,22 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
     const int n = s.nv;
     const int nslots = s.iters_out * s.iters_in;
     TIMED(K_MISC, launch_fill_u64(d.dxbits, 0ull, nslots + 1, st));
-    TIMED(K_PREDICT, launch_predict(d, (float)s.h, g[0], g[1], g[2], st));
-    bool contact = contact_enabled(s, c);
+    const bool contact = contact_enabled(s, c);
+    const bool rf = s.rf_iters > 0 && contact;
+    TIMED(K_PREDICT, launch_predict(d, (float)s.h, g[0], g[1], g[2], rf ? s.d_rfdx : nullptr, st));
+    const float* xplus = d.z;
+    if (s.warm_iters > 0) {
+        TIMED(K_MISC, launch_copy3(d.xk, d.z, n, st));
+        for (int i = 0; i < s.warm_iters; ++i) {
+            cloth_status rc = modal_iteration(sc, st);
+            if (rc != CLOTH_OK) return rc;
+        }
+        xplus = d.xk;
+    }
     if (contact) {
-        TIMED(K_OUTER, contact_step_begin(s, c, st));   // x- = x*, x+ = z: CCD, filter -> x, x-
+        TIMED(K_OUTER, contact_step_begin(s, c, xplus, st));   // x- = x*, x+: CCD, filter -> x, x-
     } else {
-        TIMED(K_MISC, launch_copy3(d.x, d.z, n, st));
+        TIMED(K_MISC, launch_copy3(d.x, xplus, n, st));
     }
     for (int o = 0; o < s.iters_out; ++o) {
         TIMED(K_MISC, launch_copy3(d.xk, d.x, n, st));
@@ -597,10 +668,22 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
             if (contact) TIMED(K_PCCD, contact_partial_ccd(s, c, st));
         }
         if (contact) {
-            TIMED(K_OUTER, contact_block_end(s, c, o == s.iters_out - 1, st));  // x+ = x^k -> x, x-
+            bool last = o == s.iters_out - 1;
+            TIMED(K_OUTER, contact_block_end(s, c, !last || rf, st));  // x+ = x^k -> x, x-
         } else {
             TIMED(K_MISC, launch_copy3(d.x, d.xk, n, st));
         }
+    }
+    if (rf) {
+        // residual forwarding (section 6): collision weights at k, no filter;
+        // the displacement is kept only if the exiting t_TOI was small
+        TIMED(K_MISC, launch_copy3(d.xk, d.x, n, st));
+        TIMED(K_MISC, launch_copy3(d.xkm1, d.x, n, st));
+        for (int k = 0; k < s.rf_iters; ++k) {
+            cloth_status rc = inner_iteration(sc, k, nslots, st, false, 0.f, true);
+            if (rc != CLOTH_OK) return rc;
+        }
+        TIMED(K_MISC, launch_rf_finish(d, d.xk, d.x, s.d_rfdx, c.tmin_bits + 2, s.rf_toi, st));
     }
     TIMED(K_MISC, launch_epilogue(d, (float)(1.0 / s.h), st));
     return CLOTH_OK;

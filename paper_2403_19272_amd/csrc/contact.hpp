@@ -49,7 +49,7 @@ struct ContactState {
     // [4] n_prev_vt, [5] n_prev_ee, [6] n_cv, [7] overflow flag,
     // [9] n_vt + n_ee, [10] obstacle constraints
     int* cnt = nullptr;
-    unsigned long long* tmin_bits = nullptr;  // [0] block min, [1] step min
+    unsigned long long* tmin_bits = nullptr;  // [0] stage min, [1] step min, [2] last stage's t_TOI
     double* s_dev = nullptr;                  // filter step length
     int64_t* stat64 = nullptr;                // [0] candidates (last), [1] constraints (last)
 
@@ -67,12 +67,12 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve);
 cloth_status contact_upload(Scene& s, ContactState& c);
 cloth_status contact_set_obstacles(Scene& s, ContactState& c);
 bool contact_enabled(const Scene& s, const ContactState& c);
-cloth_status contact_step_begin(Scene& s, ContactState& c, hipStream_t st);
+cloth_status contact_step_begin(Scene& s, ContactState& c, const float* xp, hipStream_t st);
 cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st);
-cloth_status contact_prepare_iteration(Scene& s, ContactState& c, hipStream_t st);
+cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, hipStream_t st);
 cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st);
-cloth_status contact_block_end(Scene& s, ContactState& c, bool last, hipStream_t st);
+cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, hipStream_t st);
 cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step_stats* out);
 cloth_status contact_load_constraints(Scene& s, ContactState& c, int64_t n_vt, const int32_t* vt,
                                       const int32_t* a_vt, int64_t n_ee, const int32_t* ee,

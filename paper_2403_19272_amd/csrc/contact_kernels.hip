@@ -685,11 +685,13 @@ __global__ void k_obstacles_outer(Dev d, const float* __restrict__ xm, const flo
     }
 }
 
-// s = 1 (no hit) or alpha * t_TOI; running minimum for the statistics
+// s = 1 (no hit) or alpha * t_TOI; running minimum for the statistics and
+// the stage's own t_TOI (the exiting one after the last stage)
 __global__ void k_step_length(unsigned long long* tmin_bits, double alpha, double* s_dev) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double t = __longlong_as_double((long long)tmin_bits[0]);
         s_dev[0] = t > 1.0 ? 1.0 : alpha * t;
+        tmin_bits[2] = tmin_bits[0];
         if (tmin_bits[0] < tmin_bits[1]) tmin_bits[1] = tmin_bits[0];
         tmin_bits[0] = (unsigned long long)__double_as_longlong(NOHIT);
     }
@@ -800,12 +802,13 @@ __global__ void k_cv_compact(int n, const int* __restrict__ flag, const int* __r
 }
 
 // ================================================================ per iteration
-// Targets of the pair constraints at x^k: half-space projection with the
+// Targets of the pair constraints at x^k, stored per slot as (w, w (y - x)):
+// half-space projection with the
 // frozen normal and closest-point parameters (minimum-norm correction over
 // movable vertices), weight w = k * 2^a (Eq. (exp) with K = 2; other K use powf).
 __global__ void k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ cpair, const int* __restrict__ ca,
                                const double2* __restrict__ clam, const float4* __restrict__ cnrm, float kc, float Kb,
-                               float dhat, float4* slot) {
+                               float dhat, float4* slot, int force_k) {
     const int nvt = cnt[2], nc = cnt[2] + cnt[3];
     const int n = d.nv;
     const float* X = d.xk;
@@ -831,12 +834,11 @@ __global__ void k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ c
             den += cm[k] * cm[k];
         }
         float delta = (gx < 0.f && den > 0.f) ? -gx / den : 0.f;
-        int a = ca[p];
+        int a = force_k ? 0 : ca[p];
         float w = (Kb == 2.0f) ? ldexpf(kc, a) : kc * powf(Kb, (float)a);
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 4; ++k) {   // (w, w (y - x)) with y - x = c_k delta n
             float s = cm[k] * delta;
-            slot[4 * (size_t)p + k] = make_float4(w, w * (xs[k][0] + s * nr.x), w * (xs[k][1] + s * nr.y),
-                                                  w * (xs[k][2] + s * nr.z));
+            slot[4 * (size_t)p + k] = make_float4(w, w * s * nr.x, w * s * nr.y, w * s * nr.z);
         }
     }
 }
@@ -1101,7 +1103,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.gpart2 = static_cast<double*>(carve(sizeof(double) * ((size_t)(s.nblk + 31) / 32 + 1) * s.r * 3));
     c.gvec = static_cast<double*>(carve(sizeof(double) * s.r * 3));
     c.cnt = I(16);
-    c.tmin_bits = static_cast<unsigned long long*>(carve(16));
+    c.tmin_bits = static_cast<unsigned long long*>(carve(32));
     c.s_dev = static_cast<double*>(carve(8));
     c.scan_tiles = I(c.ntiles_cap);
     c.ob_a = I((size_t)MAX_OBST * n);
@@ -1168,8 +1170,8 @@ cloth_status contact_upload(Scene& s, ContactState& c) {
     const int n = s.nv;
     HC(hipMemset(c.cnt, 0, sizeof(int) * 16));
     HC(hipMemset(c.ob_a, 0xff, sizeof(int) * (size_t)MAX_OBST * n));
-    std::vector<unsigned long long> tb = {0x4000000000000000ull, 0x4000000000000000ull};  // 2.0
-    HC(hipMemcpy(c.tmin_bits, tb.data(), 16, hipMemcpyHostToDevice));
+    std::vector<unsigned long long> tb(4, 0x4000000000000000ull);  // 2.0
+    HC(hipMemcpy(c.tmin_bits, tb.data(), 32, hipMemcpyHostToDevice));
     double one = 1.0;
     HC(hipMemcpy(c.s_dev, &one, 8, hipMemcpyHostToDevice));
     HC(hipMemset(c.vslot_ptr, 0, sizeof(int) * (n + 1)));
@@ -1297,9 +1299,8 @@ static cloth_status outer_stage(Scene& s, ContactState& c, const float* xm, cons
     return CLOTH_OK;
 }
 
-cloth_status contact_step_begin(Scene& s, ContactState& c, hipStream_t st) {
-    // clear the constraint counts of the previous step before saving "prev"
-    return outer_stage(s, c, s.d.xstar, s.d.z, true, true, st);
+cloth_status contact_step_begin(Scene& s, ContactState& c, const float* xp, hipStream_t st) {
+    return outer_stage(s, c, s.d.xstar, xp, true, true, st);
 }
 
 cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st) {
@@ -1309,15 +1310,15 @@ cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st) {
     return CLOTH_OK;
 }
 
-cloth_status contact_block_end(Scene& s, ContactState& c, bool last, hipStream_t st) {
-    return outer_stage(s, c, s.d.xm, s.d.xk, false, !last, st);
+cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, hipStream_t st) {
+    return outer_stage(s, c, s.d.xm, s.d.xk, false, setup, st);
 }
 
-cloth_status contact_prepare_iteration(Scene& s, ContactState& c, hipStream_t st) {
+cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, hipStream_t st) {
     if (!s.self_contact) return CLOTH_OK;
     Dev& d = s.d;
     hipLaunchKernelGGL(k_pair_targets, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca, c.clam,
-                       c.cnrm, (float)s.kc, (float)s.Kb, (float)s.dhat, c.slot);
+                       c.cnrm, (float)s.kc, (float)s.Kb, (float)s.dhat, c.slot, force_k ? 1 : 0);
     HC(hipGetLastError());
     return CLOTH_OK;
 }

@@ -9,17 +9,20 @@ namespace cloth {
 // ---- PD iteration (pd_kernels.hip)
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);
 hipError_t launch_copy3(float* dst, const float* src, int nv, hipStream_t st);
-hipError_t launch_predict(const Dev& d, float h, float gx, float gy, float gz, hipStream_t st);
+hipError_t launch_predict(const Dev& d, float h, float gx, float gy, float gz, const float* rfdx, hipStream_t st);
+hipError_t launch_rf_finish(const Dev& d, const float* xrf, const float* x, float* rfdx,
+                            const unsigned long long* t_last_bits, double rf_toi, hipStream_t st);
 hipError_t launch_filter(const Dev& d, const float* xm, const float* xp, const double* s_dev,
                          float* x, float* xm_out, hipStream_t st);
 hipError_t launch_epilogue(const Dev& d, float inv_h, hipStream_t st);
 // local step + residual r0 + U^T r0 partials (contact: W, WY read when has_contact)
-// flags: bit 0 contact terms, bit 1 linear mode (b = 0)
+// flags: bit 0 contact terms, bit 1 linear mode (b = 0), bit 2 obstacle weights k
 hipError_t launch_local_residual(const Dev& d, int prec, int flags, hipStream_t st);
 // sum of U^T r0 partials -> d.gvec; without contact also Q = A^{-1} g
 hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpart2,
                                hipStream_t st);
-hipError_t launch_expand(const Dev& d, int prec, hipStream_t st);
+// delta = U q into d.xt (add: d.xt = x^k + U q)
+hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st);
 hipError_t launch_jacobi_cheb(const Dev& d, float omega, float gamma, int has_contact,
                               unsigned long long* dx_slot, hipStream_t st);
 

@@ -4,12 +4,13 @@
 // (subspace_collision), (high_frequency_residual)):
 //   k_local_residual   local step (triangle strain projection; flat-rest
 //                      bending adds no right-hand side) + inertia + collision
-//                      targets -> b; r0 = b - (H + diag W) x^k on free rows;
-//                      per-block partial products U^T r0 (r x 3)
+//                      targets; r0 = b - (H + diag W) x^k on free rows,
+//                      evaluated in difference form; per-block partial
+//                      products U^T r0 (r x 3)
 //   k_reduce_g1        first level of the deterministic sum of the partials
 //   k_solve_reduced    g = U^T r0 in FP64, q = A^{-1} g (A = Lambda~ + U^T W U)
-//   k_expand           x~ = x^k + U q
-//   k_jacobi_cheb      r1 = b - (H + diag W) x~, x^ = x~ + r1 / (diag H + W),
+//   k_expand           delta = U q  (x~ = x^k + delta)
+//   k_jacobi_cheb      r1 = r0 - (H + diag W) delta, x^ = x~ + r1 / (diag H + W),
 //                      Chebyshev blend -> x^{k+1}; max |x^{k+1} - x^k| in FP64
 // Data: SoA FP32 positions (x, y, z planes of nv floats), scalar CSR of H
 // shared by the three coordinates, U row-major in FP32 or BF16.
@@ -96,8 +97,10 @@ __global__ void k_copy3(float* __restrict__ dst, const float* __restrict__ src, 
     if (i < n3) dst[i] = src[i];
 }
 
-// z = x* + h v* + h^2 g (free rows), z = x* at pinned rows; x* saved (Eq. (z)).
-__global__ void k_predict(Dev d, float h, float gx, float gy, float gz) {
+// z = x* + h v* + h^2 g + 2 dx_rf (free rows), z = x* at pinned rows; x*
+// saved.  Eq. (z) and, with a forwarded residual, Eq. (z_rf): the previous
+// step's delta f = 2 M dx_rf / h^2 contributes h^2 M^{-1} delta f = 2 dx_rf.
+__global__ void k_predict(Dev d, float h, float gx, float gy, float gz, const float* __restrict__ rfdx) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= d.nv) return;
     const int n = d.nv;
@@ -106,8 +109,21 @@ __global__ void k_predict(Dev d, float h, float gx, float gy, float gz) {
     for (int c = 0; c < 3; ++c) {
         float xv = d.x[c * n + v];
         d.xstar[c * n + v] = xv;
-        d.z[c * n + v] = pin ? xv : xv + h * d.v[c * n + v] + h * h * g[c];
+        float zz = xv + h * d.v[c * n + v] + h * h * g[c];
+        if (rfdx) zz += 2.0f * rfdx[c * n + v];
+        d.z[c * n + v] = pin ? xv : zz;
     }
+}
+
+// Residual forwarding result: dx_rf = x_rf - x on free rows when the step's
+// exiting t_TOI is below the threshold, else 0 (section 6).
+__global__ void k_rf_finish(Dev d, const float* __restrict__ xrf, const float* __restrict__ x, float* rfdx,
+                            const unsigned long long* __restrict__ t_last_bits, double rf_toi) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * d.nv) return;
+    double t = __longlong_as_double((long long)t_last_bits[0]);
+    int v = i % d.nv;
+    rfdx[i] = (t < rf_toi && !d.pinned[v]) ? xrf[i] - x[i] : 0.0f;
 }
 
 // x = x- + s (x+ - x-), x- <- x (the step-length filter, section 7).
@@ -135,7 +151,8 @@ __global__ void k_epilogue(Dev d, float inv_h) {
 // recomputed per corner so that accumulation is a deterministic gather.
 // flags: bit 0 = contact terms (W, WY gathered here from the pair-constraint
 // slots and the obstacle constraints, W stored for the later kernels),
-// bit 1 = linear mode (b = 0: error propagation of the global iteration).
+// bit 1 = linear mode (b = 0: error propagation of the global iteration),
+// bit 2 = every obstacle weight at k (a = 0; residual forwarding).
 template <typename UT>
 __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     __shared__ float sr[3][TPB];
@@ -144,16 +161,21 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     const int n = d.nv;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int v = tile * TPB + tid;
-    const bool contact = flags & 1, linear = flags & 2;
+    const bool contact = flags & 1, linear = flags & 2, force_k = flags & 4;
     float r0[3] = {0.f, 0.f, 0.f};
     if (v < n) {
         const float* X = d.xk;
+        const float x0 = X[v], x1 = X[n + v], x2 = X[2 * n + v];
+        // right-hand side minus the diagonal terms, accumulated as differences
+        // (b - (M/h^2 + W) x) so that no large, nearly cancelling products
+        // appear in FP32: inertia (m/h^2)(z - x), elastic projections, and the
+        // collision corrections w (y - x)
         float bx = 0.f, by = 0.f, bz = 0.f;
         if (!linear) {
             float m = d.mh2[v];
-            bx = m * d.z[v];
-            by = m * d.z[n + v];
-            bz = m * d.z[2 * n + v];
+            bx = m * (d.z[v] - x0);
+            by = m * (d.z[n + v] - x1);
+            bz = m * (d.z[2 * n + v] - x2);
             for (int i = d.inc_ptr[v], e = d.inc_ptr[v + 1]; i < e; ++i) {
                 int code = d.inc[i];
                 int t = code >> 2, c = code & 3;
@@ -187,7 +209,7 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
         if (contact) {
             float wx = 0.f, wy = 0.f, wz = 0.f;
             for (int i = d.vslot_ptr[v], e = d.vslot_ptr[v + 1]; i < e; ++i) {
-                float4 sl = d.slot[d.vslot[i]];
+                float4 sl = d.slot[d.vslot[i]];   // (w, w (y - x))
                 Wv += sl.x;
                 wx += sl.y;
                 wy += sl.z;
@@ -196,10 +218,10 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
             for (int j = 0; j < d.nob; ++j) {
                 int a = d.ob_a[j * n + v];
                 if (a < 0) continue;
+                if (force_k) a = 0;
                 float w = (d.Kb == 2.0f) ? ldexpf(d.kc, a) : d.kc * powf(d.Kb, (float)a);
                 const ObstD& o = d.ob[j];
-                double px = X[v], py = X[n + v], pz = X[2 * n + v];
-                double ox = px - o.c[0], oy = py - o.c[1], oz = pz - o.c[2];
+                double ox = x0 - o.c[0], oy = x1 - o.c[1], oz = x2 - o.c[2];
                 if (o.kind == CLOTH_CYLINDER) {
                     double ax = ox * o.a[0] + oy * o.a[1] + oz * o.a[2];
                     ox -= ax * o.a[0];
@@ -207,17 +229,12 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
                     oz -= ax * o.a[2];
                 }
                 double rad = sqrt(ox * ox + oy * oy + oz * oz);
-                double yx = px, yy = py, yz = pz;
-                if (rad - o.R < d.dhat && rad > 0) {
-                    double sc = (o.R + d.dhat) / rad;
-                    yx = px - ox + ox * sc;
-                    yy = py - oy + oy * sc;
-                    yz = pz - oz + oz * sc;
-                }
+                double sc = 0.0;   // y - x = (sc - 1) * radial
+                if (rad - o.R < d.dhat && rad > 0) sc = (o.R + d.dhat) / rad - 1.0;
                 Wv += w;
-                wx += w * (float)yx;
-                wy += w * (float)yy;
-                wz += w * (float)yz;
+                wx += w * (float)(sc * ox);
+                wy += w * (float)(sc * oy);
+                wz += w * (float)(sc * oz);
             }
             d.W[v] = Wv;
             if (!linear) {
@@ -226,22 +243,39 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
                 bz += wz;
             }
         }
-        d.b[v] = bx;
-        d.b[n + v] = by;
-        d.b[2 * n + v] = bz;
         if (!d.pinned[v]) {
-            float ax = 0.f, ay = 0.f, az = 0.f;
-            for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
-                int c = d.col[j];
-                float a = d.val[j];
-                ax += a * X[c];
-                ay += a * X[n + c];
-                az += a * X[2 * n + c];
+            if (!linear) {
+                // elastic rows sum to zero: H x = (m/h^2) x + sum_{j != v} H_vj (x_j - x_v)
+                float ax = 0.f, ay = 0.f, az = 0.f;
+                for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
+                    int c = d.col[j];
+                    if (c == v) continue;
+                    float a = d.val[j];
+                    ax += a * (X[c] - x0);
+                    ay += a * (X[n + c] - x1);
+                    az += a * (X[2 * n + c] - x2);
+                }
+                r0[0] = bx - ax;
+                r0[1] = by - ay;
+                r0[2] = bz - az;
+            } else {
+                float ax = 0.f, ay = 0.f, az = 0.f;
+                for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
+                    int c = d.col[j];
+                    float a = d.val[j];
+                    ax += a * X[c];
+                    ay += a * X[n + c];
+                    az += a * X[2 * n + c];
+                }
+                r0[0] = -ax - Wv * x0;
+                r0[1] = -ay - Wv * x1;
+                r0[2] = -az - Wv * x2;
             }
-            r0[0] = bx - ax - Wv * X[v];
-            r0[1] = by - ay - Wv * X[n + v];
-            r0[2] = bz - az - Wv * X[2 * n + v];
         }
+        // d.b holds r0 = b - (H + diag W) x^k for the Jacobi sweep
+        d.b[v] = r0[0];
+        d.b[n + v] = r0[1];
+        d.b[2 * n + v] = r0[2];
     }
     sr[0][tid] = r0[0];
     sr[1][tid] = r0[1];
@@ -313,9 +347,9 @@ __global__ void k_solve_reduced(Dev d, const double* __restrict__ g1, int nseg, 
     }
 }
 
-// x~ = x^k + U q
+// delta = U q into d.xt (add = 1: d.xt = x^k + U q)
 template <typename UT>
-__global__ void __launch_bounds__(TPB) k_expand(Dev d) {
+__global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
     extern __shared__ float qs[];
     const int r = d.r;
     for (int o = threadIdx.x; o < r * 3; o += blockDim.x) qs[o] = d.Qf[o];
@@ -334,13 +368,22 @@ __global__ void __launch_bounds__(TPB) k_expand(Dev d) {
             a2 += u[i] * qs[(c + i) * 3 + 2];
         }
     }
-    d.xt[v] = d.xk[v] + a0;
-    d.xt[n + v] = d.xk[n + v] + a1;
-    d.xt[2 * n + v] = d.xk[2 * n + v] + a2;
+    if (add) {
+        d.xt[v] = d.xk[v] + a0;
+        d.xt[n + v] = d.xk[n + v] + a1;
+        d.xt[2 * n + v] = d.xk[2 * n + v] + a2;
+    } else {
+        d.xt[v] = a0;
+        d.xt[n + v] = a1;
+        d.xt[2 * n + v] = a2;
+    }
 }
 
-// Jacobi sweep on the residual of x~ with the Chebyshev blend:
-//   x^{k+1} = omega (gamma (x^ - x^k) + x^k - x^{k-1}) + x^{k-1}.
+// Jacobi sweep on the residual of x~ = x^k + delta with the Chebyshev blend:
+//   r1 = r0 - (H + diag W) delta   (= b - (H + diag W) x~, by linearity),
+//   x^ - x^k = delta + r1 / (diag H + W),
+//   x^{k+1} = x^{k-1} + omega (gamma (x^ - x^k) + x^k - x^{k-1}).
+// d.b holds r0 and d.xt holds delta = U q.
 __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float gamma, int has_contact,
                                                     unsigned long long* dx_slot) {
     __shared__ double wmax[TPB / 64];
@@ -348,29 +391,29 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
     const int v = xcd_tile(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     double dxm = 0.0;
     if (v < n) {
-        const float* XT = d.xt;
-        float xt[3] = {XT[v], XT[n + v], XT[2 * n + v]};
+        const float* DL = d.xt;
         float xk[3] = {d.xk[v], d.xk[n + v], d.xk[2 * n + v]};
         float xkm1[3] = {d.xkm1[v], d.xkm1[n + v], d.xkm1[2 * n + v]};
-        float xh[3] = {xt[0], xt[1], xt[2]};
+        float dh[3] = {0.f, 0.f, 0.f};
         if (!d.pinned[v]) {
             float ax = 0.f, ay = 0.f, az = 0.f;
             for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
                 int c = d.col[j];
                 float a = d.val[j];
-                ax += a * XT[c];
-                ay += a * XT[n + c];
-                az += a * XT[2 * n + c];
+                ax += a * DL[c];
+                ay += a * DL[n + c];
+                az += a * DL[2 * n + c];
             }
             float Wv = has_contact ? d.W[v] : 0.f;
             float inv = 1.0f / (d.diag[v] + Wv);
-            xh[0] = xt[0] + (d.b[v] - ax - Wv * xt[0]) * inv;
-            xh[1] = xt[1] + (d.b[n + v] - ay - Wv * xt[1]) * inv;
-            xh[2] = xt[2] + (d.b[2 * n + v] - az - Wv * xt[2]) * inv;
+            float dl[3] = {DL[v], DL[n + v], DL[2 * n + v]};
+            dh[0] = dl[0] + (d.b[v] - ax - Wv * dl[0]) * inv;
+            dh[1] = dl[1] + (d.b[n + v] - ay - Wv * dl[1]) * inv;
+            dh[2] = dl[2] + (d.b[2 * n + v] - az - Wv * dl[2]) * inv;
         }
         double s2 = 0.0;
         for (int c = 0; c < 3; ++c) {
-            float nx = omega * (gamma * (xh[c] - xk[c]) + xk[c] - xkm1[c]) + xkm1[c];
+            float nx = xkm1[c] + omega * (gamma * dh[c] + (xk[c] - xkm1[c]));
             d.xk1[c * n + v] = nx;
             double dd = (double)nx - (double)xk[c];
             s2 += dd * dd;
@@ -401,8 +444,15 @@ hipError_t launch_copy3(float* dst, const float* src, int nv, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_predict(const Dev& d, float h, float gx, float gy, float gz, hipStream_t st) {
-    hipLaunchKernelGGL(k_predict, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, h, gx, gy, gz);
+hipError_t launch_predict(const Dev& d, float h, float gx, float gy, float gz, const float* rfdx, hipStream_t st) {
+    hipLaunchKernelGGL(k_predict, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, h, gx, gy, gz, rfdx);
+    return hipGetLastError();
+}
+
+hipError_t launch_rf_finish(const Dev& d, const float* xrf, const float* x, float* rfdx,
+                            const unsigned long long* t_last_bits, double rf_toi, hipStream_t st) {
+    hipLaunchKernelGGL(k_rf_finish, dim3(blocks_for(3 * d.nv)), dim3(TPB), 0, st, d, xrf, x, rfdx, t_last_bits,
+                       rf_toi);
     return hipGetLastError();
 }
 
@@ -435,12 +485,12 @@ hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpar
     return hipGetLastError();
 }
 
-hipError_t launch_expand(const Dev& d, int prec, hipStream_t st) {
+hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st) {
     size_t sh = sizeof(float) * d.r * 3;
     if (prec == CLOTH_MIXED)
-        hipLaunchKernelGGL(k_expand<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), sh, st, d);
+        hipLaunchKernelGGL(k_expand<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), sh, st, d, add);
     else
-        hipLaunchKernelGGL(k_expand<float>, dim3(blocks_for(d.nv)), dim3(TPB), sh, st, d);
+        hipLaunchKernelGGL(k_expand<float>, dim3(blocks_for(d.nv)), dim3(TPB), sh, st, d, add);
     return hipGetLastError();
 }
 

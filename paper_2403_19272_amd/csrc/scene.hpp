@@ -78,6 +78,8 @@ struct Scene {
     double rho = 0, gamma = 0;
     int64_t pair_cap = 0;
     bool basis_set = false;
+    int warm_iters = 0, rf_iters = 0;   // modal warm start / residual forwarding iterations
+    double rf_toi = 0.5;                // forward when the exiting t_TOI is below this
 
     // host data (FP64 precompute)
     std::vector<int> tris, edges, hinges;  // hinges: 4 per interior edge
@@ -97,6 +99,7 @@ struct Scene {
     Dev d{};
     int nblk = 0;                 // vertex blocks
     uint8_t* d_pinned = nullptr;
+    float* d_rfdx = nullptr;      // forwarded residual dx (3*nv)
     int *d_rowptr = nullptr, *d_col = nullptr, *d_inc_ptr = nullptr, *d_inc = nullptr,
         *d_edges = nullptr;
     float* d_val = nullptr;
@@ -135,5 +138,8 @@ static const char* const kKernelNames[K_COUNT] = {
 std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, double dt,
                         const cloth_material* mat, const cloth_solver_params* prm);
 size_t footprint_bytes(int nv, int nt, int ne, int64_t nnz, int r, int prec, int64_t pair_cap);
+// device eigenbasis (eig.hip)
+cloth_status device_eigenbasis(Scene& s, int r, int degree, int max_passes, double tol, std::vector<double>& U,
+                               std::vector<double>& w, int* passes, double* max_res, std::string& err);
 
 }  // namespace cloth

@@ -69,11 +69,11 @@ def test_broad_phase_and_toi_bit_exact(n, seed):
     assert np.abs(te[hit] - ote[hit]).max(initial=0) <= 1e-6
 
 
-def contact_block(n=20, seed=3, precision="fp32"):
+def contact_block(n=20, seed=3, precision="fp32", step=0.1):
     """A block state with pair and obstacle constraints on identical FP32 inputs."""
     sc = scenegen.drop_cloth(n, seed=seed, obstacle="sphere", r=8, steps=1, d_hat=2e-3, drop=0.002)
     rng = np.random.default_rng(seed)
-    xm, xp = crumpled(sc, seed, amp=0.2 / n, step=0.1 / n)
+    xm, xp = crumpled(sc, seed, amp=0.2 / n, step=step / n)
     o, U, rho = oracle_side(sc, precision, rho=0.95)
     vt, ee = native.broad_phase(xm, xp, o.m.edges, o.m.tris, sc.d_hat)
     vt = vt[rng.random(len(vt)) < 0.3]
@@ -192,7 +192,7 @@ def test_outer_stage_set_spans_and_filter(first):
     """Outer stage on identical FP32 inputs: the new constraint set and carried
     life spans bit-exact, the step length within 1e-6, the filtered positions
     within FP32 rounding."""
-    sc, o, U, blk = contact_block(n=24, seed=5)
+    sc, o, U, blk = contact_block(n=24, seed=5, step=0.6)
     g = gpu_side(sc, U, "fp32", 0.95)
     g.stage_load_block(blk["xm"], blk["xk"], blk["xkm1"], blk["z"], blk["vt"], blk["a_vt"], blk["ee"],
                        blk["a_ee"], blk["ob_a"])
