@@ -136,6 +136,15 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing-pass", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch each kernel from the host instead of replaying the step graph "
+                         "(for counter collection)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times and exit "
+                         "(the known-size kernel that calibrates the HBM byte counters)")
+    ap.add_argument("--basis-cache", default=None, metavar="NPY",
+                    help="load the rest eigenbasis from this .npy file if it holds one of the right "
+                         "shape, else compute it and save it there")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -150,14 +159,33 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 5 x {args.copy_probe} MiB read + {args.copy_probe} MiB written")
+        return
     sc = scenegen.config(2 if args.workload == "c2" else 1)
     if args.precision:
         sc.precision = args.precision
     log(f"workload {sc.name}: nv={sc.nv} nt={sc.nt} r={sc.r} {sc.precision}")
     g = make_gpu_scene(sc, sc.precision, P, B)
+    if args.eager:
+        g.set_graph(False)
     t0 = time.time()
     H = g.system_matrix()
-    U = B.rest_eigenbasis(H, sc.pinned, sc.r)
+    U = None
+    if args.basis_cache and os.path.exists(args.basis_cache):
+        U = np.load(args.basis_cache)
+        if U.shape != (sc.nv, sc.r):
+            U = None
+    if U is None:
+        U = B.rest_eigenbasis(H, sc.pinned, sc.r)
+        if args.basis_cache:
+            np.save(args.basis_cache, U)
     log(f"basis {time.time() - t0:.1f}s")
     g.set_basis(U)
     log("basis set (Chebyshev parameters estimated on the device)")
@@ -238,6 +266,7 @@ def main():
         "last_step": {"n_candidates": stats["n_candidates"], "n_constraints": stats["n_constraints"],
                       "min_toi": stats["min_toi"], "dx_norm": stats["dx_norm"],
                       "cheb_rho": stats["cheb_rho"], "cheb_gamma": stats["cheb_gamma"], "finite": finite},
+        "launch": "eager" if args.eager else "graph replay",
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -83,7 +83,8 @@ typedef struct {
 } cloth_material;
 
 /* Solver settings.
- *   r                   basis width (scalar modes; each acts on x, y and z)
+ *   r                   basis width (scalar modes; each acts on x, y and z), a
+ *                       multiple of 8 in [8, 192]
  *   iters_inner/outer   fixed iteration budget per step (inner per block)
  *   cheb_rho            spectral radius estimate for the Chebyshev weights;
  *                       <= 0: estimated by power iteration when the basis is set
@@ -147,10 +148,12 @@ cloth_status cloth_set_basis(cloth_scene s, const double* U, int32_t r);
 
 /* Computes the basis on the device and sets it (as cloth_set_basis): the r
  * lowest eigenvectors of H on the free vertices by Chebyshev-filtered
- * subspace iteration (polynomial degree `degree` per pass, at most
- * max_passes passes, until the largest relative Ritz residual
- * |H u - theta u| / theta of the r wanted pairs is below tol).  Block
- * products run in FP32, the small eigenproblems in FP64 on the host.
+ * subspace iteration (polynomial degree at most `degree` per pass, lowered
+ * where the filter would amplify the lowest wanted Ritz direction more than
+ * 1e4 times over the r-th; at most max_passes passes, until the largest
+ * relative Ritz residual |H u - theta u| / theta of the r wanted pairs is
+ * below tol).  Block products run in FP32 with FP64 Gram accumulation, the
+ * small eigenproblems in FP64 on the host.
  * Optional outputs: U (nv*r FP64, caller order), the Ritz values (r), the
  * passes used and the final residual.  Section 5 (U from the rest H). */
 cloth_status cloth_compute_basis(cloth_scene s, int32_t r, int32_t degree, int32_t max_passes,

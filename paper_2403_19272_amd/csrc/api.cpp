@@ -151,6 +151,11 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     s.d_rowptr = cv<int>(carve_fn, n + 1);
     s.d_col = cv<int>(carve_fn, (size_t)s.nnz);
     s.d_val = cv<float>(carve_fn, (size_t)s.nnz);
+    const int nsl = (n + 63) / 64;
+    const size_t nsell = (size_t)s.nsell;
+    s.d_sell_ptr = cv<int>(carve_fn, nsl + 1);
+    s.d_sell_col = cv<int>(carve_fn, nsell + 1);
+    s.d_sell_val = cv<float>(carve_fn, nsell + 1);
     s.d_tri = cv<TriRec>(carve_fn, s.nt);
     s.d_inc_ptr = cv<int>(carve_fn, n + 1);
     s.d_inc = cv<int>(carve_fn, 3 * (size_t)s.nt);
@@ -163,10 +168,11 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     d.Ainv = cv<double>(carve_fn, (size_t)s.r * s.r);
     d.Lam = cv<double>(carve_fn, (size_t)s.r * s.r);
     d.Amat = cv<double>(carve_fn, (size_t)s.r * s.r);
-    d.gram_part = cv<float>(carve_fn, (size_t)64 * s.r * s.r);
+    d.gram_part = cv<float>(carve_fn, (size_t)GRAM_CHUNKS * s.r * s.r);
     d.dxbits = cv<unsigned long long>(carve_fn, 4096);
     s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);
     if (!d.W || !d.mh2 || !d.diag || !s.d_pinned || !s.d_rowptr || !s.d_col || !s.d_val || !s.d_tri ||
+        !s.d_sell_ptr || !s.d_sell_col || !s.d_sell_val ||
         !s.d_inc_ptr || !s.d_inc || !s.d_edges || !s.d_U || !d.gpart || !d.Qf || !d.Qd || !d.Ainv ||
         !d.Lam || !d.Amat || !d.gram_part || !d.dxbits || !s.d_rfdx)
         return fail(CLOTH_E_OOM, "arena exhausted");
@@ -179,6 +185,7 @@ static size_t dry_footprint(const Scene& src) {
     s.nt = src.nt;
     s.ne = src.ne;
     s.nnz = src.nnz;
+    s.nsell = src.nsell;
     s.r = src.r;
     s.prec = src.prec;
     s.self_contact = src.self_contact;
@@ -309,11 +316,8 @@ const char* cloth_last_error(void) { return g_err.c_str(); }
 cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_params* params, size_t* bytes) {
     if (!mesh || !params || !bytes) return fail(CLOTH_E_INVALID, "null argument");
     if (!mesh->tris || mesh->nv <= 0 || mesh->nt <= 0) return fail(CLOTH_E_INVALID, "empty mesh");
-    // count the nonzero pattern: diagonal + triangle corners + hinge stencils
-    Scene tmp;
-    std::vector<float> rest(3 * (size_t)mesh->nv, 0.f);
-    // pattern only depends on connectivity; use a dummy planar layout is not
-    // valid for degeneracy checks, so count from connectivity directly
+    // count the nonzero pattern (diagonal + triangle corners + hinge
+    // stencils) from the connectivity alone
     std::vector<std::vector<int>> nb(mesh->nv);
     std::vector<std::pair<int, int>> ed;
     std::vector<std::vector<int>> opp;
@@ -343,18 +347,26 @@ cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_pa
             i = j;
         }
     }
-    int64_t nnz = 0;
+    int64_t nnz = 0, nsell = 0;
+    int slice_w = 0;
     for (int v = 0; v < mesh->nv; ++v) {
         auto& l = nb[v];
         l.push_back(v);
         std::sort(l.begin(), l.end());
-        nnz += (int64_t)(std::unique(l.begin(), l.end()) - l.begin());
+        int len = (int)(std::unique(l.begin(), l.end()) - l.begin());
+        nnz += len;
+        slice_w = std::max(slice_w, len - 1);
+        if (v % 64 == 63 || v == mesh->nv - 1) {
+            nsell += 64 * (int64_t)slice_w;
+            slice_w = 0;
+        }
     }
     Scene ds;
     ds.nv = mesh->nv;
     ds.nt = mesh->nt;
     ds.ne = (int)ed.size();
     ds.nnz = nnz;
+    ds.nsell = nsell;
     ds.r = params->r;
     ds.prec = params->precision;
     ds.self_contact = params->self_contact;
@@ -368,8 +380,8 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
                         const cloth_solver_params* params, void* dev_arena, size_t arena_bytes,
                         cloth_scene* out) {
     if (!mesh || !rest_xyz || !mat || !params || !out) return fail(CLOTH_E_INVALID, "null argument");
-    if (params->r < 8 || params->r > 256 || params->r % 8 != 0)
-        return fail(CLOTH_E_INVALID, "r must be a multiple of 8 in [8, 256]");
+    if (params->r < 8 || params->r > MAX_R || params->r % 8 != 0)
+        return fail(CLOTH_E_INVALID, "r must be a multiple of 8 in [8, " + std::to_string(MAX_R) + "]");
     if (params->iters_inner <= 0 || params->iters_outer <= 0)
         return fail(CLOTH_E_INVALID, "iteration budgets must be positive");
     if (params->precision != CLOTH_PLAIN_FP32 && params->precision != CLOTH_MIXED)
@@ -402,6 +414,9 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     d.rowptr = s.d_rowptr;
     d.col = s.d_col;
     d.val = s.d_val;
+    d.sell_ptr = s.d_sell_ptr;
+    d.sell_col = s.d_sell_col;
+    d.sell_val = s.d_sell_val;
     d.tri = s.d_tri;
     d.inc_ptr = s.d_inc_ptr;
     d.inc = s.d_inc;
@@ -421,6 +436,12 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     {
         std::vector<float> vf(s.val.begin(), s.val.end());
         HIPCHECK(hipMemcpy(s.d_val, vf.data(), sizeof(float) * s.nnz, hipMemcpyHostToDevice));
+    }
+    HIPCHECK(hipMemcpy(s.d_sell_ptr, s.sell_ptr.data(), sizeof(int) * s.sell_ptr.size(), hipMemcpyHostToDevice));
+    if (!s.sell_col.empty()) {
+        HIPCHECK(hipMemcpy(s.d_sell_col, s.sell_col.data(), sizeof(int) * s.sell_col.size(), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(s.d_sell_val, s.sell_val.data(), sizeof(float) * s.sell_val.size(),
+                           hipMemcpyHostToDevice));
     }
     {
         std::vector<TriRec> tr(s.nt);

@@ -904,69 +904,111 @@ __global__ void k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cp
 
 // U^T diag(W) U over the contact vertices: chunk c of the vertex list,
 // upper triangle (i <= j) of the r x r partial, FP32 accumulation.
+// Gram of the contact rows, Eq. (uu): sum over contact vertices j of
+// W_j U_j U_j^T (r x r, FP32 partial per chunk of vertices).  Thread = one
+// 8 x 8 tile of the upper block triangle; blockIdx.y picks a group of 256
+// tiles, blockIdx.x a chunk of the contact-vertex list.  Vertices are staged
+// 32 at a time in LDS as W-scaled and plain FP32 rows.
+constexpr int GRAM_MIN_PER_CHUNK = 32;
+__device__ __forceinline__ int gram_per_chunk(int ncv, int nchunk) {
+    return max(GRAM_MIN_PER_CHUNK, (ncv + nchunk - 1) / nchunk);
+}
+
 template <typename UT>
 __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
                                             int nchunk, float* part) {
-    __shared__ float us[32][257];
-    __shared__ float ws[32];
-    const int r = d.r;
+    __shared__ float us[32][MAX_R];
+    __shared__ float ws[32][MAX_R];
+    const int r = d.r, T = r >> 3;
     const int ncv = *n_cv;
-    const int per = (ncv + nchunk - 1) / nchunk;
+    const int per = gram_per_chunk(ncv, nchunk);
     const int c0 = blockIdx.x * per, c1 = min(ncv, c0 + per);
-    const int nent = r * (r + 1) / 2;
-    constexpr int MAXE = 33;  // entries per thread for r <= 128 (8256 / 256)
-    float acc[MAXE];
-    int ei[MAXE], ej[MAXE];
-    int ne = 0;
-    for (int e = threadIdx.x; e < nent && ne < MAXE; e += 256) {
-        // row-major upper triangle index -> (i, j)
-        int i = 0, rem = e;
-        while (rem >= r - i) {
-            rem -= r - i;
-            ++i;
+    if (c0 >= c1) return;
+    // tile -> (ti, tj), ti <= tj, row-major over the upper block triangle
+    int tile = blockIdx.y * 256 + threadIdx.x;
+    const bool active = tile < T * (T + 1) / 2;
+    int ti = 0, tj = 0;
+    if (active) {
+        int rem = tile;
+        while (rem >= T - ti) {
+            rem -= T - ti;
+            ++ti;
         }
-        ei[ne] = i;
-        ej[ne] = i + rem;
-        acc[ne] = 0.f;
-        ++ne;
+        tj = ti + rem;
     }
+    float acc[8][8];
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) acc[a][b] = 0.f;
     const UT* U = static_cast<const UT*>(d.U);
     for (int base = c0; base < c1; base += 32) {
-        int m = min(32, c1 - base);
+        const int m = min(32, c1 - base);
         __syncthreads();
         for (int q = threadIdx.x; q < 32 * r; q += 256) {
             int vv = q / r, cc = q % r;
-            float u = 0.f;
+            float u = 0.f, w = 0.f;
             if (vv < m) {
                 int v = cvlist[base + vv];
                 UT raw = U[(size_t)v * r + cc];
                 if constexpr (sizeof(UT) == 2) u = __uint_as_float((uint32_t)raw << 16);
                 else u = (float)raw;
+                w = d.W[v];
             }
             us[vv][cc] = u;
+            ws[vv][cc] = w * u;
         }
-        if (threadIdx.x < 32) ws[threadIdx.x] = threadIdx.x < m ? d.W[cvlist[base + threadIdx.x]] : 0.f;
         __syncthreads();
-        for (int vv = 0; vv < m; ++vv) {
-            float w = ws[vv];
-            for (int q = 0; q < ne; ++q) acc[q] += w * us[vv][ei[q]] * us[vv][ej[q]];
+        if (active) {
+            for (int vv = 0; vv < m; ++vv) {
+                float wa[8], ub[8];
+                for (int a = 0; a < 8; ++a) wa[a] = ws[vv][ti * 8 + a];
+                for (int b = 0; b < 8; ++b) ub[b] = us[vv][tj * 8 + b];
+                for (int a = 0; a < 8; ++a)
+                    for (int b = 0; b < 8; ++b) acc[a][b] += wa[a] * ub[b];
+            }
         }
     }
-    for (int q = 0; q < ne; ++q) {
-        size_t o = (size_t)blockIdx.x * r * r + (size_t)ei[q] * r + ej[q];
-        part[o] = acc[q];
+    if (!active) return;
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b)
+            part[((size_t)blockIdx.x * r + ti * 8 + a) * r + tj * 8 + b] = acc[a][b];
+}
+
+// A = Lambda~ + sum of the Gram chunks, in FP64, packed lower triangle
+// (A(i, j), j <= i, at i (i + 1) / 2 + j).  The chunk sums read the upper
+// triangle of the partials: A(i, j) = part(j, i).
+__global__ void k_gram_reduce(Dev d, const float* __restrict__ part, int nchunk, const int* __restrict__ n_cv,
+                              double* __restrict__ Apk) {
+    const int r = d.r;
+    const int ncv = *n_cv;
+    if (ncv == 0) return;
+    const int per = gram_per_chunk(ncv, nchunk);
+    const int used = min(nchunk, (ncv + per - 1) / per);
+    const int tot = r * (r + 1) / 2;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        while (i * (i + 1) / 2 > e) --i;
+        int j = e - i * (i + 1) / 2;
+        double acc = d.Lam[(size_t)i * r + j];
+        for (int c = 0; c < used; ++c) acc += (double)part[((size_t)c * r + j) * r + i];
+        Apk[e] = acc;
     }
 }
 
-// One workgroup: A = Lambda~ + sum of Gram chunks (FP64), in-place Cholesky
-// (one barrier per column), then q = A^{-1} g by two triangular solves.
-__global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const float* __restrict__ part, int nchunk,
+// One workgroup: Cholesky of the packed A (FP64, in LDS) and q = A^{-1} g by
+// two triangular solves.  Right-looking elimination without square roots
+// (A(i, j) -= A(i, k) A(j, k) / A(k, k) for k < j <= i, one barrier per
+// column; each thread owns fixed entries), then L(i, k) = A(i, k) / s_k with
+// s_k = sqrt(A(k, k)).  The solves run in wavefront 0 with the right-hand
+// sides in registers (lane l holds rows l, l + 64, l + 128).
+constexpr int CHOL_OWN = (MAX_R * (MAX_R + 1) / 2 + 1023) / 1024;
+__global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __restrict__ Apk,
                                                    const double* __restrict__ g, const int* __restrict__ n_cv) {
     extern __shared__ double A[];
     const int r = d.r;
-    double* y = A + (size_t)r * r;  // r * 3
-    double* dsq = y + (size_t)r * 3;  // r
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tot = r * (r + 1) / 2;
+    double* sq = A + tot;   // r
+    const int tid = threadIdx.x, nt = 1024;
     if (*n_cv == 0) {  // no contact vertex: A = Lambda~, use its inverse
         for (int o = tid; o < r * 3; o += nt) {
             int c = o / 3, k = o % 3;
@@ -977,64 +1019,93 @@ __global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const float* __restr
         }
         return;
     }
-    for (int e = tid; e < r * r; e += nt) {
-        int i = e / r, j = e % r;
-        int a = min(i, j), b = max(i, j);
-        double s = d.Lam[e];
-        for (int c = 0; c < nchunk; ++c) s += (double)part[(size_t)c * r * r + (size_t)a * r + b];
-        A[e] = s;
+    // entries owned by this thread: e = tid + 1024 q, as (row i, column j)
+    int own[CHOL_OWN];
+#pragma unroll
+    for (int q = 0; q < CHOL_OWN; ++q) {
+        const int e = tid + q * 1024;
+        own[q] = -1;
+        if (e < tot) {
+            A[e] = Apk[e];
+            int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+            while ((i + 1) * (i + 2) / 2 <= e) ++i;
+            while (i * (i + 1) / 2 > e) --i;
+            own[q] = (i << 16) | (e - i * (i + 1) / 2);
+        }
     }
-    for (int e = tid; e < r * 3; e += nt) y[e] = g[e];
     __syncthreads();
-    // right-looking: at step k every thread updates its (i, j), k < j <= i,
-    // from column k (not modified during step k)
     for (int k = 0; k < r; ++k) {
-        double akk = A[(size_t)k * r + k];
-        double inv = 1.0 / akk;
-        int m = r - k - 1;
-        int tot = m * (m + 1) / 2;
-        for (int e = tid; e < tot; e += nt) {
-            // (i, j) with k < j <= i: enumerate rows i = k+1.. with j = k+1..i
-            int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-            while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-            while (ii * (ii + 1) / 2 > e) --ii;
-            int jj = e - ii * (ii + 1) / 2;
-            int i = k + 1 + ii, j = k + 1 + jj;
-            A[(size_t)i * r + j] -= A[(size_t)i * r + k] * A[(size_t)j * r + k] * inv;
+        const double inv = 1.0 / A[k * (k + 1) / 2 + k];
+#pragma unroll
+        for (int q = 0; q < CHOL_OWN; ++q) {
+            const int i = own[q] >> 16, j = own[q] & 0xffff;
+            if (own[q] >= 0 && j > k)
+                A[i * (i + 1) / 2 + j] -= A[i * (i + 1) / 2 + k] * A[j * (j + 1) / 2 + k] * inv;
         }
         __syncthreads();
     }
-    // L(i,k) = A(i,k) / sqrt(A(k,k)) for i >= k (the diagonal becomes sqrt(A(k,k)))
-    for (int k = tid; k < r; k += nt) dsq[k] = sqrt(A[(size_t)k * r + k]);
+    for (int k = tid; k < r; k += nt) sq[k] = sqrt(A[k * (k + 1) / 2 + k]);
     __syncthreads();
-    for (int e = tid; e < r * r; e += nt) {
-        int i = e / r, k = e % r;
-        if (i >= k) A[e] = A[e] / dsq[k];
+    if (tid >= 64) return;
+    constexpr int RPL = (MAX_R + 63) / 64;   // rows per lane
+    double y[RPL][3];
+    for (int q = 0; q < RPL; ++q) {
+        int i = tid + 64 * q;
+        for (int c = 0; c < 3; ++c) y[q][c] = i < r ? g[i * 3 + c] : 0.0;
     }
-    __syncthreads();
-    // forward: L y = g
+    auto bcast = [](double v, int lane) {
+        long long b = __double_as_longlong(v);
+        int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+        int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    };
+    // forward: L y' = g, L(i, k) = A(i, k) / s_k
     for (int k = 0; k < r; ++k) {
-        if (tid < 3) y[k * 3 + tid] /= A[(size_t)k * r + k];
-        __syncthreads();
-        for (int e = tid; e < (r - k - 1) * 3; e += nt) {
-            int i = k + 1 + e / 3, c = e % 3;
-            y[i * 3 + c] -= A[(size_t)i * r + k] * y[k * 3 + c];
+        const int ql = k >> 6, lk = k & 63;
+        double yk[3];
+        for (int c = 0; c < 3; ++c) {
+            double mine = 0.0;
+            for (int q = 0; q < RPL; ++q)
+                if (q == ql) mine = y[q][c];
+            yk[c] = bcast(mine, lk) / sq[k];
         }
-        __syncthreads();
+        for (int q = 0; q < RPL; ++q) {
+            int i = tid + 64 * q;
+            if (i == k)
+                for (int c = 0; c < 3; ++c) y[q][c] = yk[c];
+            else if (i > k && i < r) {
+                double l = A[i * (i + 1) / 2 + k] / sq[k];
+                for (int c = 0; c < 3; ++c) y[q][c] -= l * yk[c];
+            }
+        }
     }
-    // backward: L^T q = y
+    // backward: L^T q = y', L^T(i, k) = L(k, i) = A(k, i) / s_i
     for (int k = r - 1; k >= 0; --k) {
-        if (tid < 3) y[k * 3 + tid] /= A[(size_t)k * r + k];
-        __syncthreads();
-        for (int e = tid; e < k * 3; e += nt) {
-            int i = e / 3, c = e % 3;
-            y[i * 3 + c] -= A[(size_t)k * r + i] * y[k * 3 + c];
+        const int ql = k >> 6, lk = k & 63;
+        double qk[3];
+        for (int c = 0; c < 3; ++c) {
+            double mine = 0.0;
+            for (int q = 0; q < RPL; ++q)
+                if (q == ql) mine = y[q][c];
+            qk[c] = bcast(mine, lk) / sq[k];
         }
-        __syncthreads();
+        for (int q = 0; q < RPL; ++q) {
+            int i = tid + 64 * q;
+            if (i == k)
+                for (int c = 0; c < 3; ++c) y[q][c] = qk[c];
+            else if (i < k) {
+                double l = A[k * (k + 1) / 2 + i] / sq[i];
+                for (int c = 0; c < 3; ++c) y[q][c] -= l * qk[c];
+            }
+        }
     }
-    for (int e = tid; e < r * 3; e += nt) {
-        d.Qd[e] = y[e];
-        d.Qf[e] = (float)y[e];
+    for (int q = 0; q < RPL; ++q) {
+        int i = tid + 64 * q;
+        if (i < r)
+            for (int c = 0; c < 3; ++c) {
+                d.Qd[i * 3 + c] = y[q][c];
+                d.Qf[i * 3 + c] = (float)y[q][c];
+            }
     }
 }
 
@@ -1162,7 +1233,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     d.vslot_ptr = c.vslot_ptr;
     d.vslot = c.vslot;
     d.slot = c.slot;
-    c.gram_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, (n + 2047) / 2048));
+    c.gram_chunks = GRAM_CHUNKS;
     return CLOTH_OK;
 }
 
@@ -1176,7 +1247,7 @@ cloth_status contact_upload(Scene& s, ContactState& c) {
     HC(hipMemcpy(c.s_dev, &one, 8, hipMemcpyHostToDevice));
     HC(hipMemset(c.vslot_ptr, 0, sizeof(int) * (n + 1)));
     HC(hipFuncSetAttribute((const void*)k_chol_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                           (int)(sizeof(double) * (size_t)(s.r * s.r + 4 * s.r))));
+                           (int)chol_lds_bytes(s.r)));
     return CLOTH_OK;
 }
 
@@ -1325,14 +1396,18 @@ cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, 
 
 cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st) {
     Dev& d = s.d;
+    const int T = s.r / 8;
+    dim3 grid(c.gram_chunks, (T * (T + 1) / 2 + 255) / 256);
     if (s.prec == CLOTH_MIXED)
-        hipLaunchKernelGGL(k_gram<uint16_t>, dim3(c.gram_chunks), dim3(256), 0, st, d, c.cvlist, c.cnt + 6,
-                           c.gram_chunks, d.gram_part);
+        hipLaunchKernelGGL(k_gram<uint16_t>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
+                           d.gram_part);
     else
-        hipLaunchKernelGGL(k_gram<float>, dim3(c.gram_chunks), dim3(256), 0, st, d, c.cvlist, c.cnt + 6,
-                           c.gram_chunks, d.gram_part);
-    size_t sh = sizeof(double) * (size_t)(s.r * s.r + 4 * s.r);
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), sh, st, d, d.gram_part, c.gram_chunks, c.gvec, c.cnt + 6);
+        hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
+                           d.gram_part);
+    const int tot = s.r * (s.r + 1) / 2;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((tot + 255) / 256), dim3(256), 0, st, d, d.gram_part, c.gram_chunks,
+                       c.cnt + 6, d.Amat);
+    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, d.Amat, c.gvec, c.cnt + 6);
     HC(hipGetLastError());
     return CLOTH_OK;
 }

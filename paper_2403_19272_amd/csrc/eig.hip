@@ -63,10 +63,12 @@ __global__ void k_blk_cheb(int n, int m, const int* __restrict__ rp, const int* 
     }
 }
 
-// part[chunk][i][j] = sum over the chunk's rows of A[v][i] B[v][j]; block =
-// (tile i, tile j, chunk), 32 x 32 outputs, 4 per thread.
+// part[chunk][i][j] = sum over the chunk's rows of A[v][i] B[v][j] (FP64
+// accumulation: the filtered blocks are ill-conditioned by design, and their
+// Gram matrices must stay positive definite); block = (tile i, tile j,
+// chunk), 32 x 32 outputs, 4 per thread.
 __global__ void __launch_bounds__(256) k_blk_gram(int n, int m, const float* __restrict__ A,
-                                                  const float* __restrict__ B, int nchunk, float* part) {
+                                                  const float* __restrict__ B, int nchunk, double* part) {
     __shared__ float as[GT][GT + 1];
     __shared__ float bs[GT][GT + 1];
     const int ti = blockIdx.x, tj = blockIdx.y, ch = blockIdx.z;
@@ -74,7 +76,7 @@ __global__ void __launch_bounds__(256) k_blk_gram(int n, int m, const float* __r
     const int r0 = ch * per, r1 = min(n, r0 + per);
     const int tid = threadIdx.x;
     const int oy = (tid / 16) * 2, ox = (tid % 16) * 2;
-    float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     for (int base = r0; base < r1; base += GT) {
         __syncthreads();
         for (int e = tid; e < GT * GT; e += 256) {
@@ -86,7 +88,7 @@ __global__ void __launch_bounds__(256) k_blk_gram(int n, int m, const float* __r
         }
         __syncthreads();
         for (int rr = 0; rr < GT; ++rr) {
-            float a0 = as[rr][oy], a1 = as[rr][oy + 1], b0 = bs[rr][ox], b1 = bs[rr][ox + 1];
+            double a0 = as[rr][oy], a1 = as[rr][oy + 1], b0 = bs[rr][ox], b1 = bs[rr][ox + 1];
             acc[0][0] += a0 * b0;
             acc[0][1] += a0 * b1;
             acc[1][0] += a1 * b0;
@@ -212,12 +214,28 @@ void jacobi_eig(std::vector<double> A, int m, std::vector<double>& V, std::vecto
     } while (0)
 
 struct Work {
-    float *Y = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z = nullptr, *M = nullptr, *part = nullptr;
+    float *Y = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z = nullptr, *M = nullptr;
+    double* part = nullptr;
     ~Work() {
-        for (float* p : {Y, Y0, Y1, Z, M, part})
+        for (float* p : {Y, Y0, Y1, Z, M})
             if (p) (void)hipFree(p);
+        if (part) (void)hipFree(part);
     }
 };
+
+// Largest filter degree for which the scaled Chebyshev polynomial on [a, b]
+// amplifies the lowest Ritz value theta_0 at most `growth` times more than
+// the r-th one (|T_d(x)| grows as (x + sqrt(x^2 - 1))^d outside [-1, 1]):
+// beyond that the wanted directions of the block collapse onto the lowest
+// ones below the FP32 resolution of the block.
+int filter_degree(double theta0, double thetar, double a, double b, int dmax, double growth) {
+    const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+    auto g = [](double x) { return std::log(x + std::sqrt(std::max(0.0, x * x - 1.0))); };
+    const double x0 = (c - theta0) / e, xr = (c - thetar) / e;
+    if (!(x0 > 1.0) || !(xr >= 1.0) || !(g(x0) > g(xr))) return dmax;
+    const double d = std::log(growth) / (g(x0) - g(xr));
+    return (int)std::max(4.0, std::min((double)dmax, std::floor(d)));
+}
 
 }  // namespace
 
@@ -235,7 +253,7 @@ cloth_status device_eigenbasis(Scene& s, int r, int degree, int max_passes, doub
     HC(hipMalloc(&w.Y1, blk));
     HC(hipMalloc(&w.Z, blk));
     HC(hipMalloc(&w.M, sizeof(float) * (size_t)m * m));
-    HC(hipMalloc(&w.part, sizeof(float) * (size_t)nchunk * m * m));
+    HC(hipMalloc(&w.part, sizeof(double) * (size_t)nchunk * m * m));
     const int* rp = s.d.rowptr;
     const int* col = s.d.col;
     const float* val = s.d.val;
@@ -249,11 +267,11 @@ cloth_status device_eigenbasis(Scene& s, int r, int degree, int max_passes, doub
         bmax = std::max(bmax, acc);
     }
     dim3 gg((m + GT - 1) / GT, (m + GT - 1) / GT, nchunk);
-    std::vector<float> part((size_t)nchunk * m * m);
+    std::vector<double> part((size_t)nchunk * m * m);
     auto gram = [&](const float* A, const float* B, std::vector<double>& G) -> cloth_status {
         hipLaunchKernelGGL(k_blk_gram, gg, dim3(256), 0, nullptr, n, m, A, B, nchunk, w.part);
         HC(hipGetLastError());
-        HC(hipMemcpy(part.data(), w.part, sizeof(float) * part.size(), hipMemcpyDeviceToHost));
+        HC(hipMemcpy(part.data(), w.part, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
         G.assign((size_t)m * m, 0.0);
         for (int c = 0; c < nchunk; ++c)
             for (size_t e = 0; e < (size_t)m * m; ++e) G[e] += part[(size_t)c * m * m + e];
@@ -326,6 +344,7 @@ cloth_status device_eigenbasis(Scene& s, int r, int degree, int max_passes, doub
     for (; p < max_passes; ++p) {
         // scaled Chebyshev filter on [a, b], normalised at 0
         const double a = theta[m - 1], b = bmax;
+        const int deg = filter_degree(theta[0], theta[r - 1], a, b, degree, 1e4);
         const double e = 0.5 * (b - a), c = 0.5 * (b + a);
         double sig = e / (0.0 - c);
         const double tau = 2.0 / sig;
@@ -336,7 +355,7 @@ cloth_status device_eigenbasis(Scene& s, int r, int degree, int max_passes, doub
         float* y0 = w.Y;
         float* y1 = w.Y1;
         float* y2 = w.Z;
-        for (int i = 2; i <= degree; ++i) {
+        for (int i = 2; i <= deg; ++i) {
             double sn = 1.0 / (tau - sig);
             hipLaunchKernelGGL(k_blk_cheb, dim3(grid), dim3(tpb), 0, nullptr, n, m, rp, col, val, pin, y1, y0, y2,
                                (float)(2.0 * sn / e), (float)c, (float)(-sig * sn));

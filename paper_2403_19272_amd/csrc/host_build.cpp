@@ -183,6 +183,41 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     }
     s.nnz = (int64_t)s.col.size();
 
+    // Sliced ELLPACK copy of the off-diagonal entries for the sweeps: slices
+    // of 64 rows (one wavefront), each as wide as its longest row; entry j of
+    // row v sits at sell_ptr[v / 64] + 64 j + v % 64, so that every load of a
+    // wavefront is one contiguous 256-byte run.  Padding points at the row
+    // itself with value 0.
+    {
+        const int ns = (nv + 63) / 64;
+        s.sell_ptr.assign(ns + 1, 0);
+        for (int sl = 0; sl < ns; ++sl) {
+            int w = 0;
+            for (int v = sl * 64; v < std::min(nv, sl * 64 + 64); ++v)
+                w = std::max(w, s.rowptr[v + 1] - s.rowptr[v] - 1);
+            s.sell_ptr[sl + 1] = s.sell_ptr[sl] + 64 * w;
+        }
+        s.nsell = s.sell_ptr[ns];
+        s.sell_col.assign(s.sell_ptr[ns], 0);
+        s.sell_val.assign(s.sell_ptr[ns], 0.0f);
+        for (int sl = 0; sl < ns; ++sl) {
+            int w = (s.sell_ptr[sl + 1] - s.sell_ptr[sl]) / 64;
+            for (int lane = 0; lane < 64; ++lane) {
+                int v = sl * 64 + lane;
+                int j = 0;
+                if (v < nv)
+                    for (int k = s.rowptr[v]; k < s.rowptr[v + 1]; ++k) {
+                        if (s.col[k] == v) continue;
+                        size_t at = (size_t)s.sell_ptr[sl] + 64 * j + lane;
+                        s.sell_col[at] = s.col[k];
+                        s.sell_val[at] = (float)s.val[k];
+                        ++j;
+                    }
+                for (; j < w; ++j) s.sell_col[(size_t)s.sell_ptr[sl] + 64 * j + lane] = v < nv ? v : 0;
+            }
+        }
+    }
+
     // contact constant k
     if (mat->k_contact > 0) {
         s.kc = mat->k_contact;
@@ -207,37 +242,6 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     s.self_contact = prm->self_contact;
     s.pair_cap = prm->pair_capacity > 0 ? prm->pair_capacity : (int64_t)48 * nv;
     return "";
-}
-
-size_t footprint_bytes(int nv, int nt, int ne, int64_t nnz, int r, int prec, int64_t pair_cap) {
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    size_t nblk = (nv + TPB - 1) / TPB;
-    size_t b = 0;
-    b += 14 * al(3 * sizeof(float) * (size_t)nv);           // state vectors
-    b += 4 * al(sizeof(float) * (size_t)nv);                // W, mh2, diag, spare
-    b += al(nv) + 2 * al(sizeof(int) * (size_t)(nv + 1));   // pinned, rowptr, inc_ptr
-    b += al(sizeof(int) * (size_t)nnz) + al(sizeof(float) * (size_t)nnz);
-    b += al(sizeof(TriRec) * (size_t)nt) + al(sizeof(int) * 3 * (size_t)nt);
-    b += al(sizeof(int) * 2 * (size_t)ne);
-    b += al((prec == CLOTH_MIXED ? 2 : 4) * (size_t)nv * r);
-    b += al(sizeof(float) * nblk * r * 3) + al(sizeof(float) * r * 3) + al(sizeof(double) * r * 3);
-    b += 3 * al(sizeof(double) * (size_t)r * r);
-    b += al(sizeof(float) * 64 * (size_t)r * r);            // gram partials
-    b += al(sizeof(unsigned long long) * 4096);
-    // contact: candidate pairs (VT + EE) with TOI, constraints, incidence
-    size_t pc = (size_t)pair_cap;
-    b += 2 * al(sizeof(int) * 2 * pc) + 2 * al(sizeof(double) * pc);      // candidates + toi
-    b += 2 * al(sizeof(int) * 2 * pc) + 2 * al(sizeof(int) * pc);         // constraints + a
-    b += 2 * al(sizeof(int) * 2 * pc) + 2 * al(sizeof(int) * pc);         // previous set
-    b += 2 * al(sizeof(double) * 5 * pc);                                   // frozen data
-    b += al(sizeof(float) * 4 * 4 * pc) + al(sizeof(int) * 4 * pc);        // slot contributions
-    b += al(sizeof(int) * (size_t)(nv + 1)) + al(sizeof(int) * (size_t)nv);  // slot incidence
-    b += 2 * al(sizeof(int) * 2 * pc);                                      // sort scratch
-    b += al(sizeof(int) * (size_t)(3 * nv + 2 * nt + 2 * ne + 16)) * 4;      // boxes/hash
-    b += al(sizeof(float) * 6 * (size_t)(nv + nt + ne));                    // boxes
-    b += al((size_t)MAX_OBST * nv * sizeof(int));                          // obstacle spans
-    b += 1 << 20;                                                            // misc
-    return b;
 }
 
 }  // namespace cloth

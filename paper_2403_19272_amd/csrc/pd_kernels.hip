@@ -12,8 +12,9 @@
 //   k_expand           delta = U q  (x~ = x^k + delta)
 //   k_jacobi_cheb      r1 = r0 - (H + diag W) delta, x^ = x~ + r1 / (diag H + W),
 //                      Chebyshev blend -> x^{k+1}; max |x^{k+1} - x^k| in FP64
-// Data: SoA FP32 positions (x, y, z planes of nv floats), scalar CSR of H
-// shared by the three coordinates, U row-major in FP32 or BF16.
+// Data: SoA FP32 positions (x, y, z planes of nv floats); the off-diagonal
+// part of H in SELL-64 slices (one slice per wavefront, shared by the three
+// coordinates) plus diag(H); U row-major in FP32 or BF16.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -244,13 +245,15 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
             }
         }
         if (!d.pinned[v]) {
+            // off-diagonal part of H from the SELL-64 slices; elastic rows
+            // sum to zero, so H x = (m/h^2) x + sum_{j != v} H_vj (x_j - x_v)
+            const int lane = v & 63;
+            const int p0 = d.sell_ptr[v >> 6], p1 = d.sell_ptr[(v >> 6) + 1];
+            float ax = 0.f, ay = 0.f, az = 0.f;
             if (!linear) {
-                // elastic rows sum to zero: H x = (m/h^2) x + sum_{j != v} H_vj (x_j - x_v)
-                float ax = 0.f, ay = 0.f, az = 0.f;
-                for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
-                    int c = d.col[j];
-                    if (c == v) continue;
-                    float a = d.val[j];
+                for (int j = p0 + lane; j < p1; j += 64) {
+                    int c = d.sell_col[j];
+                    float a = d.sell_val[j];
                     ax += a * (X[c] - x0);
                     ay += a * (X[n + c] - x1);
                     az += a * (X[2 * n + c] - x2);
@@ -259,17 +262,17 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
                 r0[1] = by - ay;
                 r0[2] = bz - az;
             } else {
-                float ax = 0.f, ay = 0.f, az = 0.f;
-                for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
-                    int c = d.col[j];
-                    float a = d.val[j];
+                for (int j = p0 + lane; j < p1; j += 64) {
+                    int c = d.sell_col[j];
+                    float a = d.sell_val[j];
                     ax += a * X[c];
                     ay += a * X[n + c];
                     az += a * X[2 * n + c];
                 }
-                r0[0] = -ax - Wv * x0;
-                r0[1] = -ay - Wv * x1;
-                r0[2] = -az - Wv * x2;
+                const float dv = d.diag[v] + Wv;
+                r0[0] = -ax - dv * x0;
+                r0[1] = -ay - dv * x1;
+                r0[2] = -az - dv * x2;
             }
         }
         // d.b holds r0 = b - (H + diag W) x^k for the Jacobi sweep
@@ -347,41 +350,69 @@ __global__ void k_solve_reduced(Dev d, const double* __restrict__ g1, int nseg, 
     }
 }
 
-// delta = U q into d.xt (add = 1: d.xt = x^k + U q)
+// delta = U q into d.xt (add = 1: d.xt = x^k + U q).
+// G lanes share one row of U (G = r/8 rounded up to a power of two), each
+// lane holding the q entries of its 8 columns in registers, so that a
+// wavefront reads 64/G whole rows per load: contiguous runs of U instead of
+// one 16-byte piece of 64 different rows.  The per-row sums are reduced
+// across the G lanes and staged in LDS for a coalesced store.
 template <typename UT>
 __global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
-    extern __shared__ float qs[];
-    const int r = d.r;
-    for (int o = threadIdx.x; o < r * 3; o += blockDim.x) qs[o] = d.Qf[o];
-    __syncthreads();
+    __shared__ float res[3][TPB];
+    const int r = d.r, ncg = r >> 3;
+    int G = 1;
+    while (G < ncg) G <<= 1;               // r <= 256: G <= 32
+    const int per = 64 / G;                // rows per wavefront per round
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cg = lane % G, vs = lane / G;
+    const bool active = cg < ncg;
+    float q[8][3];
+    for (int i = 0; i < 8; ++i)
+        for (int k = 0; k < 3; ++k) q[i][k] = active ? d.Qf[(cg * 8 + i) * 3 + k] : 0.f;
     const int n = d.nv;
-    const int v = xcd_tile(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
-    if (v >= n) return;
+    const int base = xcd_tile(blockIdx.x, gridDim.x) * TPB + wave * 64;
     const UT* U = static_cast<const UT*>(d.U);
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    for (int c = 0; c < r; c += 8) {
-        float u[8];
-        load8<UT>(U, (size_t)v * r + c, u);
-        for (int i = 0; i < 8; ++i) {
-            a0 += u[i] * qs[(c + i) * 3];
-            a1 += u[i] * qs[(c + i) * 3 + 1];
-            a2 += u[i] * qs[(c + i) * 3 + 2];
+    for (int rnd = 0; rnd < G; ++rnd) {
+        const int lv = rnd * per + vs;
+        const int v = base + lv;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        if (active && v < n) {
+            float u[8];
+            load8<UT>(U, (size_t)v * r + cg * 8, u);
+            for (int i = 0; i < 8; ++i) {
+                a0 += u[i] * q[i][0];
+                a1 += u[i] * q[i][1];
+                a2 += u[i] * q[i][2];
+            }
+        }
+        for (int o = 1; o < G; o <<= 1) {
+            a0 += __shfl_xor(a0, o);
+            a1 += __shfl_xor(a1, o);
+            a2 += __shfl_xor(a2, o);
+        }
+        if (cg == 0) {
+            res[0][wave * 64 + lv] = a0;
+            res[1][wave * 64 + lv] = a1;
+            res[2][wave * 64 + lv] = a2;
         }
     }
+    __syncthreads();
+    const int v = base - wave * 64 + tid;
+    if (v >= n) return;
     if (add) {
-        d.xt[v] = d.xk[v] + a0;
-        d.xt[n + v] = d.xk[n + v] + a1;
-        d.xt[2 * n + v] = d.xk[2 * n + v] + a2;
+        d.xt[v] = d.xk[v] + res[0][tid];
+        d.xt[n + v] = d.xk[n + v] + res[1][tid];
+        d.xt[2 * n + v] = d.xk[2 * n + v] + res[2][tid];
     } else {
-        d.xt[v] = a0;
-        d.xt[n + v] = a1;
-        d.xt[2 * n + v] = a2;
+        d.xt[v] = res[0][tid];
+        d.xt[n + v] = res[1][tid];
+        d.xt[2 * n + v] = res[2][tid];
     }
 }
 
 // Jacobi sweep on the residual of x~ = x^k + delta with the Chebyshev blend:
 //   r1 = r0 - (H + diag W) delta   (= b - (H + diag W) x~, by linearity),
-//   x^ - x^k = delta + r1 / (diag H + W),
+//   x^ - x^k = delta + r1 / (diag H + W) = (r0 - offdiag(H) delta) / (diag H + W),
 //   x^{k+1} = x^{k-1} + omega (gamma (x^ - x^k) + x^k - x^{k-1}).
 // d.b holds r0 and d.xt holds delta = U q.
 __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float gamma, int has_contact,
@@ -397,19 +428,22 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
         float dh[3] = {0.f, 0.f, 0.f};
         if (!d.pinned[v]) {
             float ax = 0.f, ay = 0.f, az = 0.f;
-            for (int j = d.rowptr[v], e = d.rowptr[v + 1]; j < e; ++j) {
-                int c = d.col[j];
-                float a = d.val[j];
+            const int lane = v & 63;
+            const int p1 = d.sell_ptr[(v >> 6) + 1];
+            for (int j = d.sell_ptr[v >> 6] + lane; j < p1; j += 64) {
+                int c = d.sell_col[j];
+                float a = d.sell_val[j];
                 ax += a * DL[c];
                 ay += a * DL[n + c];
                 az += a * DL[2 * n + c];
             }
             float Wv = has_contact ? d.W[v] : 0.f;
             float inv = 1.0f / (d.diag[v] + Wv);
-            float dl[3] = {DL[v], DL[n + v], DL[2 * n + v]};
-            dh[0] = dl[0] + (d.b[v] - ax - Wv * dl[0]) * inv;
-            dh[1] = dl[1] + (d.b[n + v] - ay - Wv * dl[1]) * inv;
-            dh[2] = dl[2] + (d.b[2 * n + v] - az - Wv * dl[2]) * inv;
+            // x^ - x^k = delta + (r0 - (H + diag W) delta) / (diag H + W)
+            //          = (r0 - offdiag(H) delta) / (diag H + W)
+            dh[0] = (d.b[v] - ax) * inv;
+            dh[1] = (d.b[n + v] - ay) * inv;
+            dh[2] = (d.b[2 * n + v] - az) * inv;
         }
         double s2 = 0.0;
         for (int c = 0; c < 3; ++c) {
@@ -486,11 +520,10 @@ hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpar
 }
 
 hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st) {
-    size_t sh = sizeof(float) * d.r * 3;
     if (prec == CLOTH_MIXED)
-        hipLaunchKernelGGL(k_expand<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), sh, st, d, add);
+        hipLaunchKernelGGL(k_expand<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
     else
-        hipLaunchKernelGGL(k_expand<float>, dim3(blocks_for(d.nv)), dim3(TPB), sh, st, d, add);
+        hipLaunchKernelGGL(k_expand<float>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
     return hipGetLastError();
 }
 

@@ -14,6 +14,11 @@ namespace cloth {
 constexpr int TPB = 256;          // threads per block of the vertex/pair kernels
 constexpr int MAX_OBST = 4;
 constexpr double NO_HIT = 2.0;
+constexpr int MAX_R = 192;        // widest basis: the packed FP64 Cholesky factor lives in LDS
+constexpr int GRAM_CHUNKS = 128;  // contact-vertex chunks of the Gram partials
+
+// LDS of the contact-solve Cholesky: packed lower triangle + r pivots roots
+inline size_t chol_lds_bytes(int r) { return sizeof(double) * ((size_t)r * (r + 1) / 2 + r); }
 
 // Triangle record for the local step: corner ids, PD weight w = k_s * area,
 // and the gradient rows g_j, g_k (g_i = -g_j - g_k) with F = sum_c x_c g_c^T.
@@ -43,6 +48,9 @@ struct Dev {
     const int* rowptr;        // nv+1
     const int* col;           // nnz
     const float* val;         // nnz
+    const int* sell_ptr;      // nv/64 slices + 1: SELL-64 off-diagonal part of H
+    const int* sell_col;
+    const float* sell_val;
     const TriRec* tri;        // nt
     const int* inc_ptr;       // nv+1: vertex -> (triangle << 2 | corner)
     const int* inc;           // 3*nt
@@ -53,8 +61,8 @@ struct Dev {
     double* Qd;               // r * 3
     double* Ainv;             // r * r (no-contact inverse of Lambda~)
     double* Lam;              // r * r
-    double* Amat;             // r * r work (contact)
-    float* gram_part;         // gram chunks * r * r
+    double* Amat;             // r (r + 1) / 2: packed Lambda~ + U^T W U (contact)
+    float* gram_part;         // GRAM_CHUNKS * r * r Gram partials
     unsigned long long* dxbits;  // per-iteration max |dx| as double bits
     double* gvec;             // r * 3: g = U^T r0 (FP64)
     // contact (read when the contact flag is set)
@@ -71,7 +79,7 @@ struct Dev {
 struct Scene {
     // sizes and settings
     int nv = 0, nt = 0, ne = 0, nh = 0, r = 0;
-    int64_t nnz = 0;
+    int64_t nnz = 0, nsell = 0;   // CSR nonzeros, SELL-64 entries
     double h = 0, density = 0, ks = 0, kb = 0, kc = 0, Kb = 2, dhat = 1e-3, alpha = 0.8;
     int amax = 20;
     int iters_in = 10, iters_out = 1, delay = 3, prec = CLOTH_PLAIN_FP32, self_contact = 0;
@@ -88,6 +96,8 @@ struct Scene {
     std::vector<double> K, w_hinge;
     std::vector<int> rowptr, col;
     std::vector<double> val, diag;
+    std::vector<int> sell_ptr, sell_col;   // off-diagonal SELL-64 copy of H (see host_build.cpp)
+    std::vector<float> sell_val;
     std::vector<double> Ustored;   // nv*r stored-precision values as FP64
     std::vector<double> Lam;       // r*r
     std::vector<ObstD> obst;
@@ -103,6 +113,8 @@ struct Scene {
     int *d_rowptr = nullptr, *d_col = nullptr, *d_inc_ptr = nullptr, *d_inc = nullptr,
         *d_edges = nullptr;
     float* d_val = nullptr;
+    int *d_sell_ptr = nullptr, *d_sell_col = nullptr;
+    float* d_sell_val = nullptr;
     TriRec* d_tri = nullptr;
     void* d_U = nullptr;
     double* d_dx_host_copy = nullptr;
@@ -137,7 +149,6 @@ static const char* const kKernelNames[K_COUNT] = {
 // host precompute (host_build.cpp)
 std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, double dt,
                         const cloth_material* mat, const cloth_solver_params* prm);
-size_t footprint_bytes(int nv, int nt, int ne, int64_t nnz, int r, int prec, int64_t pair_cap);
 // device eigenbasis (eig.hip)
 cloth_status device_eigenbasis(Scene& s, int r, int degree, int max_passes, double tol, std::vector<double>& U,
                                std::vector<double>& w, int* passes, double* max_res, std::string& err);

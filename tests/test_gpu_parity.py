@@ -227,10 +227,13 @@ def test_full_size_broad_phase_and_sampled_toi():
     rng = np.random.default_rng(12)
     xm = (sc.x0 + rng.normal(0, 2e-4, sc.x0.shape)).astype(np.float32)
     xp = (xm + rng.normal(0, 5e-4, xm.shape) + np.array([0, -0.01, 0])).astype(np.float32)
-    g = gpu_side(sc, U, "mixed", 0.95)
-    vt, ee = g.stage_broad_phase(xm, xp, cap=48 * sc.nv)
+    # about 6.6M VT and 17.4M EE candidates: above the default capacity of
+    # 48 per vertex for the EE list, so the scene is given 64 per vertex
+    cap = 64 * sc.nv
+    g = gpu_side(sc, U, "mixed", 0.95, pair_capacity=cap)
+    vt, ee = g.stage_broad_phase(xm, xp, cap=cap)
     edges = M.unique_edges(sc.tris)
-    ovt, oee = native.broad_phase(xm, xp, edges, sc.tris, sc.d_hat, cap=48 * sc.nv)
+    ovt, oee = native.broad_phase(xm, xp, edges, sc.tris, sc.d_hat, cap=cap)
     print(f"[full bp] vt={len(vt)} ee={len(ee)}", flush=True)
     assert len(vt) > 100000 and len(ee) > 100000
     assert np.array_equal(vt, ovt) and np.array_equal(ee, oee)
