@@ -205,6 +205,12 @@ static size_t dry_footprint(const Scene& src) {
 
 namespace cloth {
 
+// Timing pairs: the single-kernel operations (local residual, expand,
+// Jacobi sweep) get the kernel's own start/end time (the launcher passes the
+// events to hipExtLaunchKernelGGL); the other operations, which may launch
+// several kernels, are bracketed by two recorded events.
+static bool single_kernel_op(int id) { return id == K_LOCAL || id == K_EXPAND || id == K_JACOBI; }
+
 static void t_begin(Scene& s, int id, hipStream_t st) {
     if (!s.timing) return;
     size_t k = s.ev_used.size() * 2;
@@ -216,13 +222,19 @@ static void t_begin(Scene& s, int id, hipStream_t st) {
         }
         s.ev_pool.push_back(e);
     }
-    (void)hipEventRecord(s.ev_pool[k], st);
+    if (single_kernel_op(id))
+        set_kernel_events(s.ev_pool[k], s.ev_pool[k + 1]);
+    else
+        (void)hipEventRecord(s.ev_pool[k], st);
     s.ev_used.push_back({id, (int)k});
 }
 
 static void t_end(Scene& s, hipStream_t st) {
     if (!s.timing || s.ev_used.empty()) return;
-    (void)hipEventRecord(s.ev_pool[s.ev_used.back().second + 1], st);
+    if (single_kernel_op(s.ev_used.back().first))
+        clear_kernel_events();
+    else
+        (void)hipEventRecord(s.ev_pool[s.ev_used.back().second + 1], st);
 }
 
 // folds the recorded pairs into the per-kernel totals (after a sync)

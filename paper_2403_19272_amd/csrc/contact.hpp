@@ -9,6 +9,21 @@
 
 namespace cloth {
 
+// Broad-phase grid of one target family (cell widths, column axes) and the
+// inline record of a target in its column bucket.
+struct BpGrid {
+    double cs[3];   // cell width per axis
+    int au, av;     // column axes (the third axis runs inside a column)
+    int ok;         // all extents finite
+    int pad;
+};
+
+struct BpRec {
+    int cu, cv, id, a, b, c;   // column, target id, its vertices (c = -1 for edges)
+    float lo[3], hi[3];
+};
+static_assert(sizeof(BpRec) == 48, "BpRec layout");
+
 struct ContactState {
     bool enabled = false;   // self contact or obstacles present
     bool active = false;    // the current block has constraints (or may have)
@@ -21,10 +36,12 @@ struct ContactState {
 
     // boxes (lo xyz, hi xyz as 6 floats)
     float *vbox = nullptr, *tbox = nullptr, *ebox = nullptr;
-    int* tcell = nullptr;   // 3 ints per triangle: its low-corner cell
-    int* ecell = nullptr;   // 3 ints per edge
-    int *bucket_cnt = nullptr, *bucket_ptr = nullptr, *bucket_item = nullptr;
-    unsigned int* maxext = nullptr;  // 6: tri (x,y,z), edge (x,y,z) max widths as float bits
+    int2* tcol = nullptr;   // column of each target's low corner
+    int *bucket_cnt = nullptr, *bucket_ptr = nullptr;
+    BpRec* rec = nullptr;   // targets in column-bucket order
+    int* qscratch = nullptr;  // per query: up to QK target ids from the counting pass
+    float* bpart = nullptr;   // per-block box extents
+    BpGrid* grid = nullptr;   // [0] triangles, [1] edges
 
     // candidates
     int* vcount = nullptr;  // per vertex VT counts, then offsets (nv+1)
@@ -50,6 +67,7 @@ struct ContactState {
     // [9] n_vt + n_ee, [10] obstacle constraints
     int* cnt = nullptr;
     unsigned long long* tmin_bits = nullptr;  // [0] stage min, [1] step min, [2] last stage's t_TOI
+    double* tpart = nullptr;                  // per-block TOI minima of a stage (TOI, then obstacle blocks)
     double* s_dev = nullptr;                  // filter step length
     int64_t* stat64 = nullptr;                // [0] candidates (last), [1] constraints (last)
 

@@ -43,18 +43,6 @@ __device__ __forceinline__ d3 ld3(const float* X, int n, int v) {
 }
 __device__ __forceinline__ double amax(d3 a) { return fmax(fabs(a.x), fmax(fabs(a.y), fabs(a.z))); }
 
-__device__ __forceinline__ int cell_of(float lo, float cs) { return (int)floorf(lo / cs); }
-__device__ __forceinline__ unsigned hash3(int x, int y, int z) {
-    return ((unsigned)x * 73856093u) ^ ((unsigned)y * 19349663u) ^ ((unsigned)z * 83492791u);
-}
-__device__ __forceinline__ float cs_of(const unsigned* maxext, int d) {
-    float w = __uint_as_float(maxext[d]);
-    return w * (1.0f + 1.0f / 1024.0f) + 1e-30f;
-}
-__device__ __forceinline__ bool overlap6(const float* a, const float* b) {
-    return !(a[0] > b[3] || b[0] > a[3] || a[1] > b[4] || b[1] > a[4] || a[2] > b[5] || b[2] > a[5]);
-}
-
 __device__ __forceinline__ double warp_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
     return v;
@@ -69,12 +57,22 @@ constexpr int FALLBACK_SAMPLES = 1024;
 __device__ double horner(const double c[4], double t) { return ((c[3] * t + c[2]) * t + c[1]) * t + c[0]; }
 __device__ int sgnd(double v) { return (v > 0) - (v < 0); }
 
-__device__ int roots01(const double c[4], double* roots) {
+// Roots of the cubic in [0, 1] in increasing order: the interval is split
+// at the critical points inside it; on each piece an endpoint value of 0 is
+// a root, and a sign change is refined by bisection.  Each root is handed to
+// `accept` in turn; the first one it accepts is returned (NOHIT if none).
+// may_have_root01 runs the same bracketing without the refinement: false
+// means the cubic has no root there, so the pair cannot hit.
+struct Brackets {
     double brk[4];
-    int nb = 0;
-    brk[nb++] = 0.0;
+    int nb;
+};
+
+__device__ __forceinline__ Brackets brackets01(const double c[4]) {
+    Brackets r;
+    r.brk[0] = 0.0;
     double A = 3 * c[3], B = 2 * c[2], C = c[1];
-    double cr[2];
+    double cr0 = 2.0, cr1 = 2.0;
     int ncr = 0;
     if (A != 0.0) {
         double disc = B * B - 4 * A * C;
@@ -87,42 +85,78 @@ __device__ int roots01(const double c[4], double* roots) {
                 r1 = r2;
                 r2 = t;
             }
-            cr[ncr++] = r1;
-            if (r2 != r1) cr[ncr++] = r2;
+            cr0 = r1;
+            ncr = 1;
+            if (r2 != r1) {
+                cr1 = r2;
+                ncr = 2;
+            }
         }
     } else if (B != 0.0) {
-        cr[ncr++] = -C / B;
+        cr0 = -C / B;
+        ncr = 1;
     }
-    for (int i = 0; i < ncr; ++i)
-        if (cr[i] > 0.0 && cr[i] < 1.0) brk[nb++] = cr[i];
-    brk[nb++] = 1.0;
-    int nr = 0;
-    for (int i = 0; i + 1 < nb; ++i) {
-        double lo = brk[i], hi = brk[i + 1];
+    // breakpoints 0 < (critical points inside (0, 1), in order) < 1, written
+    // with fixed indices so that they stay in registers
+    const bool in0 = ncr >= 1 && cr0 > 0.0 && cr0 < 1.0, in1 = ncr >= 2 && cr1 > 0.0 && cr1 < 1.0;
+    const int k = (int)in0 + (int)in1;
+    const double e1 = in0 ? cr0 : cr1;
+    r.brk[1] = k >= 1 ? e1 : 1.0;
+    r.brk[2] = k >= 2 ? cr1 : 1.0;
+    r.brk[3] = 1.0;
+    r.nb = k + 2;
+    return r;
+}
+
+__device__ bool may_have_root01(const double c[4]) {
+    const Brackets br = brackets01(c);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (i + 1 >= br.nb) break;
+        double flo = horner(c, br.brk[i]), fhi = horner(c, br.brk[i + 1]);
+        if (flo == 0.0 || fhi == 0.0 || sgnd(flo) != sgnd(fhi)) return true;
+    }
+    return false;
+}
+
+template <typename Accept>
+__device__ double first_root01(const double c[4], Accept accept) {
+    const Brackets br = brackets01(c);
+    bool have_last = false;
+    double last = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (i + 1 >= br.nb) break;
+        double lo = br.brk[i], hi = br.brk[i + 1];
         double flo = horner(c, lo), fhi = horner(c, hi);
+        double root;
         if (flo == 0.0) {
-            if (nr == 0 || roots[nr - 1] != lo) roots[nr++] = lo;
+            if (have_last && last == lo) continue;
+            root = lo;
+        } else if (fhi == 0.0) {
+            root = hi;
+        } else if (sgnd(flo) == sgnd(fhi)) {
             continue;
-        }
-        if (fhi == 0.0) {
-            roots[nr++] = hi;
-            continue;
-        }
-        if (sgnd(flo) == sgnd(fhi)) continue;
-        int s0 = sgnd(flo);
-        for (int it = 0; it < 64; ++it) {
-            double mid = 0.5 * (lo + hi);
-            if (mid <= lo || mid >= hi) break;
-            double fm = horner(c, mid);
-            if (fm == 0.0) {
-                lo = mid;
-                break;
+        } else {
+            int s0 = sgnd(flo);
+            for (int it = 0; it < 64; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                double fm = horner(c, mid);
+                if (fm == 0.0) {
+                    lo = mid;
+                    break;
+                }
+                if (sgnd(fm) == s0) lo = mid; else hi = mid;
             }
-            if (sgnd(fm) == s0) lo = mid; else hi = mid;
+            root = lo;
         }
-        roots[nr++] = lo;
+        have_last = true;
+        last = root;
+        int verdict = accept(root);   // 1: hit at root, -1: stop (fallback taken), 0: next root
+        if (verdict != 0) return verdict > 0 ? root : -1.0;
     }
-    return nr;
+    return NOHIT;
 }
 
 __device__ bool in_tri(d3 p, d3 a, d3 b, d3 c) {
@@ -245,33 +279,55 @@ __device__ double pair_toi_vt(const d3* q0, const d3* q1) {
     cubic_of(q0, q1, c, L);
     if (L == 0.0) return NOHIT;
     if (degenerate(c, L)) return sampled_toi<true>(q0, q1, 1e-12 * L);
-    double roots[4];
-    int nr = roots01(c, roots);
-    for (int i = 0; i < nr; ++i) {
-        double t = roots[i];
-        if (in_tri(lerp(q0[0], q1[0], t), lerp(q0[1], q1[1], t), lerp(q0[2], q1[2], t), lerp(q0[3], q1[3], t)))
-            return t;
-    }
-    return NOHIT;
+    return first_root01(c, [&](double t) {
+        return in_tri(lerp(q0[0], q1[0], t), lerp(q0[1], q1[1], t), lerp(q0[2], q1[2], t), lerp(q0[3], q1[3], t))
+                   ? 1
+                   : 0;
+    });
+}
+
+__device__ __forceinline__ void ee_as_vt(const d3* e, d3* q) {
+    q[0] = e[2];
+    q[1] = e[0];
+    q[2] = e[1];
+    q[3] = e[0] + (e[3] - e[2]);
 }
 
 // e: (p1, p2, p3, p4) at t=0 and t=1
 __device__ double pair_toi_ee(const d3* e0, const d3* e1) {
-    d3 q0[4] = {e0[2], e0[0], e0[1], e0[0] + (e0[3] - e0[2])};
-    d3 q1[4] = {e1[2], e1[0], e1[1], e1[0] + (e1[3] - e1[2])};
+    d3 q0[4], q1[4];
+    ee_as_vt(e0, q0);
+    ee_as_vt(e1, q1);
     double c[4], L;
     cubic_of(q0, q1, c, L);
     if (L == 0.0) return NOHIT;
     if (degenerate(c, L)) return sampled_toi<false>(e0, e1, 1e-12 * L);
-    double roots[4];
-    int nr = roots01(c, roots);
-    for (int i = 0; i < nr; ++i) {
-        double t = roots[i];
+    double t = first_root01(c, [&](double t) {
         int r = seg_cross(lerp(e0[0], e1[0], t), lerp(e0[1], e1[1], t), lerp(e0[2], e1[2], t), lerp(e0[3], e1[3], t));
-        if (r < 0) return sampled_toi<false>(e0, e1, 1e-12 * L);
-        if (r) return t;
+        return r < 0 ? -1 : (r ? 1 : 0);
+    });
+    if (t < 0.0) return sampled_toi<false>(e0, e1, 1e-12 * L);
+    return t;
+}
+
+// true when the pair certainly does not hit (the cubic has no root in
+// [0, 1] and is not degenerate): the result is NOHIT without refinement
+__device__ bool pair_no_hit(bool vt, const d3* p0, const d3* p1) {
+    d3 q0[4], q1[4];
+    if (vt) {
+        for (int k = 0; k < 4; ++k) {
+            q0[k] = p0[k];
+            q1[k] = p1[k];
+        }
+    } else {
+        ee_as_vt(p0, q0);
+        ee_as_vt(p1, q1);
     }
-    return NOHIT;
+    double c[4], L;
+    cubic_of(q0, q1, c, L);
+    if (L == 0.0) return true;
+    if (degenerate(c, L)) return false;
+    return !may_have_root01(c);
 }
 
 __device__ __forceinline__ void pair_points(const Dev& d, bool vt, int i, int j, const float* X, d3* q) {
@@ -415,17 +471,49 @@ static hipError_t scan_exclusive(const int* in, int* out, int n_cap, const int* 
 }
 
 // ================================================================ broad phase
+//
+// Candidate pairs are the pairs whose FP32 swept boxes (grown by d^) overlap;
+// the structure below only has to find each of them once.  Targets
+// (triangles for VT, edges for EE) are filed by the grid column of their low
+// corner on the two axes with the most cells (cell width = widest target box
+// on that axis, plus a margin); a query box looks at the columns from one
+// below its low corner to its high corner on those axes, so every
+// overlapping target is seen exactly once.  Each target is stored inline in
+// its column bucket (column, ids, box), so a query reads contiguous records.
 
 __global__ void k_fill_i32(int* p, int v, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
-// Swept boxes over (xm, xp) grown by dhat (FP32) and the widest box per axis.
-__global__ void k_boxes(Dev d, const float* __restrict__ xm, const float* __restrict__ xp, float dhat,
-                        float* vbox, float* tbox, float* ebox, unsigned* maxext) {
+constexpr int BP_PART = 18;   // per block: tri (maxw, lo, hi) x 3 axes, edge (maxw, lo, hi) x 3 axes
+constexpr int QK = 32;        // candidates per query kept from the counting pass
+
+__device__ __forceinline__ unsigned hash2(int u, int v) { return ((unsigned)u * 73856093u) ^ ((unsigned)v * 19349663u); }
+
+// cell index along one axis, in FP64 so that the one-cell margin of the
+// query range cannot be eaten by rounding; false for non-finite or far-away
+// coordinates
+__device__ __forceinline__ bool cell_d(float x, double cs, int& c) {
+    double q = (double)x / cs;
+    if (!(fabs(q) < 1e9)) return false;
+    c = (int)floor(q);
+    return true;
+}
+
+// Swept boxes over (xm, xp) grown by dhat (FP32); per block the widest box
+// and the extent per axis of the triangle and edge boxes (reduced by k_grid).
+__global__ void __launch_bounds__(256) k_boxes(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
+                                               float dhat, float* vbox, float* tbox, float* ebox, float* bpart) {
+    __shared__ float red[4][BP_PART];
     const int n = d.nv;
-    int total = d.nv + d.nt + d.ne;
-    float wl[6] = {0, 0, 0, 0, 0, 0};
+    const int total = d.nv + d.nt + d.ne;
+    float acc[BP_PART];
+    for (int f = 0; f < 2; ++f)
+        for (int c = 0; c < 3; ++c) {
+            acc[f * 9 + c] = 0.f;                 // widest box
+            acc[f * 9 + 3 + c] = INFINITY;        // lowest corner
+            acc[f * 9 + 6 + c] = -INFINITY;       // highest corner
+        }
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         int ids[3];
         int nvert;
@@ -461,119 +549,222 @@ __global__ void k_boxes(Dev d, const float* __restrict__ xm, const float* __rest
             float l = lo - dhat, h = hi + dhat;
             out[c] = l;
             out[3 + c] = h;
-            if (kind == 1) wl[c] = fmaxf(wl[c], h - l);
-            if (kind == 2) wl[3 + c] = fmaxf(wl[3 + c], h - l);
+            if (kind) {
+                const int f = (kind - 1) * 9;
+                acc[f + c] = fmaxf(acc[f + c], h - l);
+                acc[f + 3 + c] = fminf(acc[f + 3 + c], l);
+                acc[f + 6 + c] = fmaxf(acc[f + 6 + c], h);
+            }
         }
     }
-    for (int c = 0; c < 6; ++c) {
-        float w = wl[c];
-        for (int o = 32; o > 0; o >>= 1) w = fmaxf(w, __shfl_xor(w, o));
-        if ((threadIdx.x & 63) == 0 && w > 0) atomicMax(&maxext[c], __float_as_uint(w));
+    for (int k = 0; k < BP_PART; ++k) {
+        const bool is_min = (k % 9) >= 3 && (k % 9) < 6;
+        float w = acc[k];
+        for (int o = 32; o > 0; o >>= 1) {
+            float u = __shfl_xor(w, o);
+            w = is_min ? fminf(w, u) : fmaxf(w, u);
+        }
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < BP_PART) {
+        const int k = threadIdx.x;
+        const bool is_min = (k % 9) >= 3 && (k % 9) < 6;
+        float w = red[0][k];
+        for (int q = 1; q < 4; ++q) w = is_min ? fminf(w, red[q][k]) : fmaxf(w, red[q][k]);
+        bpart[(size_t)blockIdx.x * BP_PART + k] = w;
     }
 }
 
-// low-corner cell of each box and bucket counts
-__global__ void k_cells(int m, const float* __restrict__ box, const unsigned* __restrict__ maxext, int* cell,
-                        int* bucket_cnt, int P) {
-    float cs[3] = {cs_of(maxext, 0), cs_of(maxext, 1), cs_of(maxext, 2)};
+// One block: reduce the box partials; per family (0 = triangles, 1 = edges)
+// the cell widths and the column axes (the two with the most cells).
+__global__ void k_grid(const float* __restrict__ bpart, int nblk, BpGrid* grid) {
+    __shared__ float red[256][BP_PART];
+    for (int q = 0; q < BP_PART; ++q) {
+        const bool is_min = (q % 9) >= 3 && (q % 9) < 6;
+        float w = is_min ? INFINITY : (q % 9 < 3 ? 0.f : -INFINITY);
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+            float u = bpart[(size_t)b * BP_PART + q];
+            w = is_min ? fminf(w, u) : fmaxf(w, u);
+        }
+        red[threadIdx.x][q] = w;
+    }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int q = 0; q < BP_PART; ++q) {
+                const bool is_min = (q % 9) >= 3 && (q % 9) < 6;
+                float a = red[threadIdx.x][q], b = red[threadIdx.x + o][q];
+                red[threadIdx.x][q] = is_min ? fminf(a, b) : fmaxf(a, b);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) {
+        const int f = threadIdx.x;
+        const float* r = red[0] + f * 9;
+        BpGrid g;
+        g.ok = 1;
+        double cells[3];
+        for (int c = 0; c < 3; ++c) {
+            g.cs[c] = (double)r[c] * (1.0 + 1.0 / 1024.0) + 1e-30;
+            double ext = (double)r[6 + c] - (double)r[3 + c];
+            if (!isfinite(g.cs[c]) || !isfinite(ext)) g.ok = 0;
+            cells[c] = ext > 0 ? ext / g.cs[c] : 0.0;
+        }
+        int run = 0;
+        for (int c = 1; c < 3; ++c)
+            if (cells[c] < cells[run]) run = c;
+        g.au = run == 0 ? 1 : 0;
+        g.av = run == 2 ? 1 : 2;
+        g.pad = 0;
+        grid[f] = g;
+    }
+}
+
+// column of each target's low corner and bucket counts
+__global__ void __launch_bounds__(256) k_cols(int m, const float* __restrict__ box, const BpGrid* __restrict__ gp, int2* col,
+                       int* bucket_cnt, int P, int* overflow) {
+    const BpGrid g = *gp;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        int c0 = cell_of(box[6 * (size_t)i], cs[0]), c1 = cell_of(box[6 * (size_t)i + 1], cs[1]),
-            c2 = cell_of(box[6 * (size_t)i + 2], cs[2]);
-        cell[3 * (size_t)i] = c0;
-        cell[3 * (size_t)i + 1] = c1;
-        cell[3 * (size_t)i + 2] = c2;
-        atomicAdd(&bucket_cnt[hash3(c0, c1, c2) & (P - 1)], 1);
+        int cu = 0, cv = 0;
+        bool ok = g.ok && cell_d(box[6 * (size_t)i + g.au], g.cs[g.au], cu) &&
+                  cell_d(box[6 * (size_t)i + g.av], g.cs[g.av], cv);
+        if (!ok) {   // counted and filed in column (0, 0); the step reports the overflow
+            atomicExch(overflow, 1);
+            cu = cv = 0;
+        }
+        col[i] = make_int2(cu, cv);
+        atomicAdd(&bucket_cnt[hash2(cu, cv) & (P - 1)], 1);
     }
 }
 
-__global__ void k_bucket_fill(int m, const int* __restrict__ cell, int P, int* cursor, int* items) {
+// targets into their column buckets as inline records (order inside a
+// bucket is arbitrary: query outputs are sorted by target id)
+__global__ void __launch_bounds__(256) k_bucket_fill(Dev d, int vt, int m, const float* __restrict__ box, const int2* __restrict__ col,
+                              int P, int* cursor, BpRec* rec) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        unsigned b = hash3(cell[3 * (size_t)i], cell[3 * (size_t)i + 1], cell[3 * (size_t)i + 2]) & (P - 1);
-        int pos = atomicAdd(&cursor[b], 1);
-        items[pos] = i;
+        int2 cc = col[i];
+        int pos = atomicAdd(&cursor[hash2(cc.x, cc.y) & (P - 1)], 1);
+        BpRec r;
+        r.cu = cc.x;
+        r.cv = cc.y;
+        r.id = i;
+        if (vt) {
+            TriRec tr = d.tri[i];
+            r.a = tr.v0;
+            r.b = tr.v1;
+            r.c = tr.v2;
+        } else {
+            r.a = d.edges[2 * i];
+            r.b = d.edges[2 * i + 1];
+            r.c = -1;
+        }
+        for (int c = 0; c < 3; ++c) {
+            r.lo[c] = box[6 * (size_t)i + c];
+            r.hi[c] = box[6 * (size_t)i + 3 + c];
+        }
+        rec[pos] = r;
     }
 }
 
-// Query of one box against the hashed targets.  VT: query = vertex v, targets
-// = triangles (skip incident); EE: query = edge e, targets = edges f > e
-// sharing no vertex.  WRITE = false counts, true writes at ofs[q] and sorts.
-// Query of one box against the hashed targets.  VT: query = vertex v, targets
-// = triangles (skip incident); EE: query = edge e, targets = edges f > e
-// sharing no vertex.  WRITE = false counts, true writes at ofs[q] and sorts.
-// Work and output per query are bounded (MAX_VISIT bucket entries, max_out
-// pairs, at most 8 cells per axis, finite boxes only); hitting a bound sets
-// the overflow flag and the step reports a capacity error instead of
-// running away on a diverged state.
+// Query of one box against the column buckets.  VT: query = vertex v,
+// targets = triangles not incident to v; EE: query = edge e, targets = edges
+// f > e sharing no vertex.
+//   PASS 0: count, keep up to QK target ids per query in `scratch`, sorted.
+//   PASS 1: write the query's sorted pairs at ofs[q] (copied from the
+//           scratch when they fit there, else found again and sorted in
+//           place).
+// Work and output per query are bounded (MAX_VISIT records, max_out pairs,
+// at most 8 columns per axis, finite boxes only); hitting a bound sets the
+// overflow flag and the step reports a capacity error instead of running
+// away on a diverged state.
 constexpr int MAX_VISIT = 1 << 16;
-template <bool VT, bool WRITE>
-__global__ void k_query(Dev d, const float* __restrict__ qbox, const float* __restrict__ tbox,
-                        const int* __restrict__ tcell, const unsigned* __restrict__ maxext_t, const int* bptr,
-                        const int* bitem, int P, int* count, int2* out, int64_t cap, int max_out, int* overflow) {
+template <bool VT, int PASS>
+__global__ void __launch_bounds__(256) k_query(Dev d, const float* __restrict__ qbox, const BpGrid* __restrict__ gp,
+                        const int* __restrict__ bptr, const BpRec* __restrict__ rec, int P, int* count,
+                        const int* __restrict__ raw, int* scratch, int2* out, int64_t cap, int max_out,
+                        int* overflow) {
     const int nq = VT ? d.nv : d.ne;
-    float cs[3] = {cs_of(maxext_t, 0), cs_of(maxext_t, 1), cs_of(maxext_t, 2)};
-    const bool cs_ok = isfinite(cs[0]) && isfinite(cs[1]) && isfinite(cs[2]);
+    const BpGrid g = *gp;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        int* sq = scratch + (size_t)q * QK;
+        int base = 0;
+        if (PASS == 1) {
+            base = count[q];
+            const int k = raw[q];
+            if (base < 0) continue;
+            if (k <= QK) {
+                for (int i = 0; i < k; ++i) {
+                    int64_t pos = (int64_t)base + i;
+                    if (pos < cap) out[pos] = make_int2(q, sq[i]);
+                }
+                continue;
+            }
+        }
         const float* qb = qbox + 6 * (size_t)q;
         int qa = -1, qb2 = -1;
         if (!VT) {
             qa = d.edges[2 * q];
             qb2 = d.edges[2 * q + 1];
         }
-        bool ok = cs_ok;
-        int lo[3], hi[3];
-        for (int c = 0; c < 3; ++c) {
-            ok = ok && isfinite(qb[c]) && isfinite(qb[3 + c]) && fabsf(qb[c] / cs[c]) < 1e9f &&
-                 fabsf(qb[3 + c] / cs[c]) < 1e9f;
-            if (ok) {
-                lo[c] = cell_of(qb[c], cs[c]) - 2;
-                hi[c] = cell_of(qb[3 + c], cs[c]);
-                if (hi[c] - lo[c] > 8) ok = false;
-            }
-        }
+        float ql[3] = {qb[0], qb[1], qb[2]}, qh[3] = {qb[3], qb[4], qb[5]};
+        int lu = 0, hu = 0, lv = 0, hv = 0;
+        bool ok = g.ok && cell_d(ql[g.au], g.cs[g.au], lu) && cell_d(qh[g.au], g.cs[g.au], hu) &&
+                  cell_d(ql[g.av], g.cs[g.av], lv) && cell_d(qh[g.av], g.cs[g.av], hv) &&
+                  isfinite(ql[0] + ql[1] + ql[2] + qh[0] + qh[1] + qh[2]);
+        lu -= 1;
+        lv -= 1;
+        if (ok && (hu - lu > 8 || hv - lv > 8)) ok = false;
         int cnt = 0, visits = 0;
         bool full = !ok;
-        int base = WRITE ? count[q] : 0;
         if (ok) {
-            for (int ix = lo[0]; ix <= hi[0] && !full; ++ix)
-                for (int iy = lo[1]; iy <= hi[1] && !full; ++iy)
-                    for (int iz = lo[2]; iz <= hi[2] && !full; ++iz) {
-                        unsigned b = hash3(ix, iy, iz) & (P - 1);
-                        for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
-                            if (++visits > MAX_VISIT || cnt >= max_out) {
-                                full = true;
-                                break;
-                            }
-                            int t = bitem[k];
-                            if (tcell[3 * (size_t)t] != ix || tcell[3 * (size_t)t + 1] != iy ||
-                                tcell[3 * (size_t)t + 2] != iz)
-                                continue;
-                            if (VT) {
-                                TriRec tr = d.tri[t];
-                                if (tr.v0 == q || tr.v1 == q || tr.v2 == q) continue;
-                            } else {
-                                if (t <= q) continue;
-                                int f0 = d.edges[2 * t], f1 = d.edges[2 * t + 1];
-                                if (f0 == qa || f0 == qb2 || f1 == qa || f1 == qb2) continue;
-                            }
-                            if (!overlap6(qb, tbox + 6 * (size_t)t)) continue;
-                            if (WRITE) {
-                                int64_t pos = (int64_t)base + cnt;
-                                if (pos >= 0 && pos < cap) out[pos] = make_int2(q, t);
-                            }
-                            ++cnt;
+            for (int cu = lu; cu <= hu && !full; ++cu)
+                for (int cv = lv; cv <= hv && !full; ++cv) {
+                    const unsigned b = hash2(cu, cv) & (P - 1);
+                    for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
+                        if (++visits > MAX_VISIT || cnt >= max_out) {
+                            full = true;
+                            break;
                         }
+                        const BpRec r = rec[k];
+                        if (r.cu != cu || r.cv != cv) continue;
+                        if (VT) {
+                            if (r.a == q || r.b == q || r.c == q) continue;
+                        } else {
+                            if (r.id <= q || r.a == qa || r.a == qb2 || r.b == qa || r.b == qb2) continue;
+                        }
+                        if (ql[0] > r.hi[0] || r.lo[0] > qh[0] || ql[1] > r.hi[1] || r.lo[1] > qh[1] ||
+                            ql[2] > r.hi[2] || r.lo[2] > qh[2])
+                            continue;
+                        if (PASS == 0) {
+                            if (cnt < QK) sq[cnt] = r.id;
+                        } else {
+                            int64_t pos = (int64_t)base + cnt;
+                            if (pos < cap) out[pos] = make_int2(q, r.id);
+                        }
+                        ++cnt;
                     }
+                }
         }
         if (full) atomicExch(overflow, 1);
-        if (!WRITE) {
+        if (PASS == 0) {
+            for (int i = 1; i < min(cnt, QK); ++i) {  // insertion sort by target id
+                int key = sq[i];
+                int j = i - 1;
+                while (j >= 0 && sq[j] > key) {
+                    sq[j + 1] = sq[j];
+                    --j;
+                }
+                sq[j + 1] = key;
+            }
             count[q] = cnt;
-        } else if (base >= 0) {
+        } else {
             int64_t b0 = base, b1 = (int64_t)base + cnt;
             if (b1 > cap) {
                 atomicExch(overflow, 1);
                 b1 = cap;
             }
-            for (int64_t i = b0 + 1; i < b1; ++i) {  // insertion sort by target id
+            for (int64_t i = b0 + 1; i < b1; ++i) {
                 int2 key = out[i];
                 int64_t j = i - 1;
                 while (j >= b0 && out[j].y > key.y) {
@@ -603,56 +794,90 @@ __global__ void k_count_total(const int* counts_scanned, const int* counts_raw, 
 // For candidate i (VT in [0, n_vt), EE after): TOI, whether it was in the
 // previous constraint set (binary search on the sorted previous list), the
 // keep flag (TOI <= 1 or present before) and the carried life span.
-__global__ void k_toi_merge(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
-                            const int2* __restrict__ cvt, const int2* __restrict__ cee, const int* cnt,
-                            double* toi_vt, double* toi_ee, const int2* __restrict__ prev, const int* __restrict__ prev_a,
-                            int* keep, int* cand_a, unsigned long long* tmin_bits, int do_merge) {
+// Work is taken in chunks of TOI_CHUNK candidates per block: every lane first
+// settles the pairs that cannot hit (no root of the coplanarity cubic in
+// [0, 1]); the rest go to an LDS queue that all lanes then drain, so the
+// root refinement and the inside tests run on full wavefronts.
+constexpr int TOI_CHUNK = 1024;
+
+__device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, int2 pr, double t, double* toi_vt,
+                                           double* toi_ee, const int2* __restrict__ prev,
+                                           const int* __restrict__ prev_a, int pvt, int pee, int* keep,
+                                           int* cand_a, int do_merge) {
+    if (vt) toi_vt[i] = t; else toi_ee[i - nvt] = t;
+    if (!do_merge) return;
+    // binary search in the previous list of the same type
+    int lo = vt ? 0 : pvt, hi = vt ? pvt : pvt + pee;
+    long long key = ((long long)pr.x << 32) | (unsigned)pr.y;
+    int found = -1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        int2 p = prev[mid];
+        long long k2 = ((long long)p.x << 32) | (unsigned)p.y;
+        if (k2 < key) lo = mid + 1;
+        else hi = mid;
+    }
+    int end = vt ? pvt : pvt + pee;
+    if (lo < end) {
+        int2 p = prev[lo];
+        if (p.x == pr.x && p.y == pr.y) found = lo;
+    }
+    keep[i] = (t <= 1.0 || found >= 0) ? 1 : 0;
+    cand_a[i] = found >= 0 ? prev_a[found] : 0;
+}
+
+__global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
+                                                   const int2* __restrict__ cvt, const int2* __restrict__ cee,
+                                                   const int* cnt, double* toi_vt, double* toi_ee,
+                                                   const int2* __restrict__ prev, const int* __restrict__ prev_a,
+                                                   int* keep, int* cand_a, double* tpart, int do_merge) {
     __shared__ double wmin[4];
+    __shared__ int queue[TOI_CHUNK];
+    __shared__ int qn;
     const int nvt = cnt[0], nee = cnt[1];
     const int pvt = cnt[4], pee = cnt[5];
+    const int total = nvt + nee;
     double tmin = NOHIT;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nvt + nee; i += gridDim.x * blockDim.x) {
-        bool vt = i < nvt;
-        int2 pr = vt ? cvt[i] : cee[i - nvt];
-        d3 q0[4], q1[4];
-        pair_points(d, vt, pr.x, pr.y, xm, q0);
-        pair_points(d, vt, pr.x, pr.y, xp, q1);
-        double t = vt ? pair_toi_vt(q0, q1) : pair_toi_ee(q0, q1);
-        if (vt) toi_vt[i] = t; else toi_ee[i - nvt] = t;
-        tmin = fmin(tmin, t);
-        if (do_merge) {
-            // binary search in the previous list of the same type
-            int lo = vt ? 0 : pvt, hi = vt ? pvt : pvt + pee;
-            long long key = ((long long)pr.x << 32) | (unsigned)pr.y;
-            int found = -1;
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                int2 p = prev[mid];
-                long long k2 = ((long long)p.x << 32) | (unsigned)p.y;
-                if (k2 < key) lo = mid + 1;
-                else hi = mid;
-            }
-            int end = vt ? pvt : pvt + pee;
-            if (lo < end) {
-                int2 p = prev[lo];
-                if (p.x == pr.x && p.y == pr.y) found = lo;
-            }
-            keep[i] = (t <= 1.0 || found >= 0) ? 1 : 0;
-            cand_a[i] = found >= 0 ? prev_a[found] : 0;
+    for (int base = blockIdx.x * TOI_CHUNK; base < total; base += gridDim.x * TOI_CHUNK) {
+        if (threadIdx.x == 0) qn = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < TOI_CHUNK; k += blockDim.x) {
+            const int i = base + k;
+            if (i >= total) break;
+            const bool vt = i < nvt;
+            const int2 pr = vt ? cvt[i] : cee[i - nvt];
+            d3 q0[4], q1[4];
+            pair_points(d, vt, pr.x, pr.y, xm, q0);
+            pair_points(d, vt, pr.x, pr.y, xp, q1);
+            if (pair_no_hit(vt, q0, q1))
+                toi_finish(i, vt, nvt, pr, NOHIT, toi_vt, toi_ee, prev, prev_a, pvt, pee, keep, cand_a, do_merge);
+            else
+                queue[atomicAdd(&qn, 1)] = i;
         }
+        __syncthreads();
+        const int nq = qn;
+        for (int k = threadIdx.x; k < nq; k += blockDim.x) {
+            const int i = queue[k];
+            const bool vt = i < nvt;
+            const int2 pr = vt ? cvt[i] : cee[i - nvt];
+            d3 q0[4], q1[4];
+            pair_points(d, vt, pr.x, pr.y, xm, q0);
+            pair_points(d, vt, pr.x, pr.y, xp, q1);
+            const double t = vt ? pair_toi_vt(q0, q1) : pair_toi_ee(q0, q1);
+            tmin = fmin(tmin, t);
+            toi_finish(i, vt, nvt, pr, t, toi_vt, toi_ee, prev, prev_a, pvt, pee, keep, cand_a, do_merge);
+        }
+        __syncthreads();   // the queue is reused by the next chunk
     }
     tmin = warp_min(tmin);
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
-        atomicMin(tmin_bits, (unsigned long long)__double_as_longlong(m));
-    }
+    if (threadIdx.x == 0) tpart[blockIdx.x] = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
 }
 
 // obstacles: TOI on (xm, xp) and membership with carried life spans
-__global__ void k_obstacles_outer(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
-                                  unsigned long long* tmin_bits, int* n_ob) {
+__global__ void __launch_bounds__(256) k_obstacles_outer(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
+                                  double* tpart, int* n_ob) {
     __shared__ double wmin[4];
     const int nob = d.nob;
     const ObstD* ob = d.ob;
@@ -679,17 +904,27 @@ __global__ void k_obstacles_outer(Dev d, const float* __restrict__ xm, const flo
     tmin = warp_min(tmin);
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
-        atomicMin(tmin_bits, (unsigned long long)__double_as_longlong(m));
-    }
+    if (threadIdx.x == 0) tpart[blockIdx.x] = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
 }
 
-// s = 1 (no hit) or alpha * t_TOI; running minimum for the statistics and
-// the stage's own t_TOI (the exiting one after the last stage)
-__global__ void k_step_length(unsigned long long* tmin_bits, double alpha, double* s_dev) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double t = __longlong_as_double((long long)tmin_bits[0]);
+// Stage t_TOI = minimum of the per-block partials of the TOI and obstacle
+// kernels (npart of them) and tmin_bits[0]; s = 1 (no hit) or alpha t_TOI;
+// running minimum for the statistics and the stage's own t_TOI (the exiting
+// one after the last stage).  One block of 256 threads.
+__global__ void k_step_length(const double* __restrict__ tpart, int npart, unsigned long long* tmin_bits,
+                              double alpha, double* s_dev) {
+    __shared__ double red[256];
+    double m = NOHIT;
+    for (int i = threadIdx.x; i < npart; i += blockDim.x) m = fmin(m, tpart[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double t = fmin(red[0], __longlong_as_double((long long)tmin_bits[0]));
+        tmin_bits[0] = (unsigned long long)__double_as_longlong(t);
         s_dev[0] = t > 1.0 ? 1.0 : alpha * t;
         tmin_bits[2] = tmin_bits[0];
         if (tmin_bits[0] < tmin_bits[1]) tmin_bits[1] = tmin_bits[0];
@@ -720,7 +955,7 @@ __global__ void k_compact(const int2* __restrict__ cvt, const int2* __restrict__
 
 // ================================================================ frozen data
 // Closest-point parameters and normals at x- (start of the block).
-__global__ void k_freeze(Dev d, const int* cnt, const int2* __restrict__ cpair, double2* clam, float4* cnrm) {
+__global__ void __launch_bounds__(256) k_freeze(Dev d, const int* cnt, const int2* __restrict__ cpair, double2* clam, float4* cnrm) {
     const int nvt = cnt[2], nc = cnt[2] + cnt[3];
     const int n = d.nv;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
@@ -776,7 +1011,7 @@ __global__ void k_slot_fill(Dev d, const int* cnt, const int2* __restrict__ cpai
 
 // sort each vertex's slots (deterministic accumulation order) and flag
 // contact vertices (in a pair constraint or an obstacle constraint)
-__global__ void k_slot_sort(Dev d, const int* __restrict__ ptr, int* vslot, const int* __restrict__ ob_a, int nob,
+__global__ void __launch_bounds__(256) k_slot_sort(Dev d, const int* __restrict__ ptr, int* vslot, const int* __restrict__ ob_a, int nob,
                             int* flag) {
     const int n = d.nv;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
@@ -806,7 +1041,7 @@ __global__ void k_cv_compact(int n, const int* __restrict__ flag, const int* __r
 // half-space projection with the
 // frozen normal and closest-point parameters (minimum-norm correction over
 // movable vertices), weight w = k * 2^a (Eq. (exp) with K = 2; other K use powf).
-__global__ void k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ cpair, const int* __restrict__ ca,
+__global__ void __launch_bounds__(256) k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ cpair, const int* __restrict__ ca,
                                const double2* __restrict__ clam, const float4* __restrict__ cnrm, float kc, float Kb,
                                float dhat, float4* slot, int force_k) {
     const int nvt = cnt[2], nc = cnt[2] + cnt[3];
@@ -846,7 +1081,7 @@ __global__ void k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ c
 // Partial CCD on (x-, x^{k+1}): active when Q(lambda) <= 0 at a sample
 // (three fixed samples plus the frozen closest point); a <- active ?
 // min(a+1, a_max) : 0.  Obstacles: active when phi(x^{k+1}) < d_hat.
-__global__ void k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cpair, int* ca,
+__global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cpair, int* ca,
                               const double2* __restrict__ clam, int amax, const float* __restrict__ xnew) {
     const int nob = d.nob;
     const ObstD* ob = d.ob;
@@ -854,8 +1089,6 @@ __global__ void k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cp
     const double dhat = d.dhat;
     const int nvt = cnt[2], nc = cnt[2] + cnt[3];
     const int n = d.nv;
-    const double svt[3][2] = {{1.0 / 6, 1.0 / 6}, {2.0 / 3, 1.0 / 6}, {1.0 / 6, 2.0 / 3}};
-    const double see[3][2] = {{0.25, 0.25}, {0.5, 0.5}, {0.75, 0.75}};
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc + n; p += gridDim.x * blockDim.x) {
         if (p < nc) {
             int2 pr = cpair[p];
@@ -864,14 +1097,25 @@ __global__ void k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cp
             pair_points(d, vt, pr.x, pr.y, d.xm, q0);
             pair_points(d, vt, pr.x, pr.y, xnew, q1);
             bool act = false;
+            const double2 lf = clam[p];
+#pragma unroll
             for (int s = 0; s < 4; ++s) {
+                // samples: VT barycentrics (1/6, 1/6), (2/3, 1/6), (1/6, 2/3);
+                // EE parameters (1/4, 1/4), (1/2, 1/2), (3/4, 3/4); then the
+                // frozen closest point
                 double l1, l2;
-                if (s < 3) {
-                    l1 = vt ? svt[s][0] : see[s][0];
-                    l2 = vt ? svt[s][1] : see[s][1];
+                if (s == 0) {
+                    l1 = vt ? 1.0 / 6 : 0.25;
+                    l2 = vt ? 1.0 / 6 : 0.25;
+                } else if (s == 1) {
+                    l1 = vt ? 2.0 / 3 : 0.5;
+                    l2 = vt ? 1.0 / 6 : 0.5;
+                } else if (s == 2) {
+                    l1 = vt ? 1.0 / 6 : 0.75;
+                    l2 = vt ? 2.0 / 3 : 0.75;
                 } else {
-                    l1 = clam[p].x;
-                    l2 = clam[p].y;
+                    l1 = lf.x;
+                    l2 = lf.y;
                 }
                 d3 a0, a1;
                 if (vt) {
@@ -1175,11 +1419,12 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.gvec = static_cast<double*>(carve(sizeof(double) * s.r * 3));
     c.cnt = I(16);
     c.tmin_bits = static_cast<unsigned long long*>(carve(32));
+    c.tpart = static_cast<double*>(carve(sizeof(double) * 2 * GRID_LOOP));
     c.s_dev = static_cast<double*>(carve(8));
     c.scan_tiles = I(c.ntiles_cap);
     c.ob_a = I((size_t)MAX_OBST * n);
     c.ob_dev = static_cast<ObstD*>(carve(sizeof(ObstD) * MAX_OBST));
-    if (!c.gpart2 || !c.gvec || !c.cnt || !c.tmin_bits || !c.s_dev || !c.scan_tiles || !c.ob_a || !c.ob_dev)
+    if (!c.gpart2 || !c.gvec || !c.cnt || !c.tmin_bits || !c.tpart || !c.s_dev || !c.scan_tiles || !c.ob_a || !c.ob_dev)
         return set_error(CLOTH_E_OOM, "arena exhausted (contact scalars)");
     Dev& d = s.d;
     d.gvec = c.gvec;
@@ -1196,12 +1441,14 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.vbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? n : 1)));
     c.tbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? s.nt : 1)));
     c.ebox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? s.ne : 1)));
-    c.tcell = I(3 * (size_t)(s.self_contact ? s.nt : 1));
-    c.ecell = I(3 * (size_t)(s.self_contact ? s.ne : 1));
+    const size_t mt = s.self_contact ? (size_t)std::max(s.nt, s.ne) : 1;
+    c.tcol = static_cast<int2*>(carve(sizeof(int2) * mt));
     c.bucket_cnt = I((size_t)P + 1);
     c.bucket_ptr = I((size_t)P + 1);
-    c.bucket_item = I((size_t)std::max(s.nt, s.ne));
-    c.maxext = static_cast<unsigned*>(carve(sizeof(unsigned) * 8));
+    c.rec = static_cast<BpRec*>(carve(sizeof(BpRec) * mt));
+    c.qscratch = I((size_t)QK * (s.self_contact ? (size_t)std::max(n, s.ne) : 1));
+    c.bpart = static_cast<float*>(carve(sizeof(float) * BP_PART * GRID_LOOP));
+    c.grid = static_cast<BpGrid*>(carve(sizeof(BpGrid) * 2));
     c.vcount = I((size_t)n + 1);
     c.ecount = I((size_t)s.ne + 1);
     c.cand_vt = static_cast<int2*>(carve(sizeof(int2) * pc));
@@ -1224,8 +1471,8 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.cvlist = I((size_t)n + 1);
     c.cvflag = I((size_t)n + 1);
     c.cvofs = I((size_t)n + 1);
-    if (!c.vbox || !c.tbox || !c.ebox || !c.tcell || !c.ecell || !c.bucket_cnt || !c.bucket_ptr ||
-        !c.bucket_item || !c.maxext || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
+    if (!c.vbox || !c.tbox || !c.ebox || !c.tcol || !c.bucket_cnt || !c.bucket_ptr || !c.rec || !c.qscratch ||
+        !c.bpart || !c.grid || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
         !c.toi_ee || !c.keep || !c.keep_ofs || !c.cand_a || !c.cpair || !c.cpair_prev || !c.ca ||
         !c.ca_prev || !c.clam || !c.cnrm || !c.slot || !c.vslot_ptr || !c.vslot_fill || !c.vslot || !c.cvlist ||
         !c.cvflag || !c.cvofs)
@@ -1266,40 +1513,41 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
     Dev& d = s.d;
     const int n = s.nv;
     const int P = c.hash_p;
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (int*)c.maxext, 0, 8);
-    hipLaunchKernelGGL(k_boxes, dim3(gblocks((int64_t)n + s.nt + s.ne)), dim3(TPB), 0, st, d, xm, xp, (float)s.dhat,
-                       c.vbox, c.tbox, c.ebox, c.maxext);
+    const int nbb = gblocks((int64_t)n + s.nt + s.ne);
+    hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, xm, xp, (float)s.dhat, c.vbox, c.tbox, c.ebox,
+                       c.bpart);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, (const float*)c.bpart, nbb, c.grid);
     for (int pass = 0; pass < 2; ++pass) {
         const bool vt = pass == 0;
         const int m = vt ? s.nt : s.ne;
         const float* tb = vt ? c.tbox : c.ebox;
-        int* cell = vt ? c.tcell : c.ecell;
-        const unsigned* mx = c.maxext + (vt ? 0 : 3);
+        const BpGrid* g = c.grid + (vt ? 0 : 1);
         hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, c.bucket_cnt, 0, P + 1);
-        hipLaunchKernelGGL(k_cells, dim3(gblocks(m)), dim3(TPB), 0, st, m, tb, mx, cell, c.bucket_cnt, P);
+        hipLaunchKernelGGL(k_cols, dim3(gblocks(m)), dim3(TPB), 0, st, m, tb, g, c.tcol, c.bucket_cnt, P, c.cnt + 7);
         HC(scan_exclusive(c.bucket_cnt, c.bucket_ptr, P + 1, nullptr, c.scan_tiles, nullptr, st));
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, c.bucket_cnt, c.bucket_ptr, P + 1);
-        hipLaunchKernelGGL(k_bucket_fill, dim3(gblocks(m)), dim3(TPB), 0, st, m, cell, P, c.bucket_cnt, c.bucket_item);
+        hipLaunchKernelGGL(k_bucket_fill, dim3(gblocks(m)), dim3(TPB), 0, st, d, vt ? 1 : 0, m, tb,
+                           (const int2*)c.tcol, P, c.bucket_cnt, c.rec);
         const int nq = vt ? n : s.ne;
         int* cnts = vt ? c.vcount : c.ecount;
         int2* outp = vt ? c.cand_vt : c.cand_ee;
         const float* qb = vt ? c.vbox : c.ebox;
         if (vt)
-            hipLaunchKernelGGL((k_query<true, false>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
-                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.max_out, c.cnt + 7);
+            hipLaunchKernelGGL((k_query<true, 0>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr, c.rec,
+                               P, cnts, (const int*)nullptr, c.qscratch, outp, c.cap, c.max_out, c.cnt + 7);
         else
-            hipLaunchKernelGGL((k_query<false, false>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
-                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.max_out, c.cnt + 7);
+            hipLaunchKernelGGL((k_query<false, 0>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
+                               c.rec, P, cnts, (const int*)nullptr, c.qscratch, outp, c.cap, c.max_out, c.cnt + 7);
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, c.keep, cnts, nq);
         HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, st));
         hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
                            c.cnt + 7);
         if (vt)
-            hipLaunchKernelGGL((k_query<true, true>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
-                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.max_out, c.cnt + 7);
+            hipLaunchKernelGGL((k_query<true, 1>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr, c.rec,
+                               P, cnts, (const int*)c.keep, c.qscratch, outp, c.cap, c.max_out, c.cnt + 7);
         else
-            hipLaunchKernelGGL((k_query<false, true>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, tb, cell, mx,
-                               c.bucket_ptr, c.bucket_item, P, cnts, outp, c.cap, c.max_out, c.cnt + 7);
+            hipLaunchKernelGGL((k_query<false, 1>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
+                               c.rec, P, cnts, (const int*)c.keep, c.qscratch, outp, c.cap, c.max_out, c.cnt + 7);
     }
     HC(hipGetLastError());
     return CLOTH_OK;
@@ -1310,13 +1558,20 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
 static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm, const float* xp, hipStream_t st) {
     Dev& d = s.d;
     const int n = s.nv;
+    int npart = 0;
     if (s.self_contact) {
-        hipLaunchKernelGGL(k_toi_merge, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, xm, xp, c.cand_vt, c.cand_ee,
-                           c.cnt, c.toi_vt, c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tmin_bits, 1);
+        const int nb = gblocks(2 * c.cap);
+        hipLaunchKernelGGL(k_toi_merge, dim3(nb), dim3(TPB), 0, st, d, xm, xp, c.cand_vt, c.cand_ee, c.cnt, c.toi_vt,
+                           c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tpart, 1);
+        npart = nb;
     }
-    if (c.nob > 0)
-        hipLaunchKernelGGL(k_obstacles_outer, dim3(gblocks(n)), dim3(TPB), 0, st, d, xm, xp, c.tmin_bits, c.cnt + 10);
-    hipLaunchKernelGGL(k_step_length, dim3(1), dim3(64), 0, st, c.tmin_bits, s.alpha, c.s_dev);
+    if (c.nob > 0) {
+        const int nb = gblocks(n);
+        hipLaunchKernelGGL(k_obstacles_outer, dim3(nb), dim3(TPB), 0, st, d, xm, xp, c.tpart + npart, c.cnt + 10);
+        npart += nb;
+    }
+    hipLaunchKernelGGL(k_step_length, dim3(1), dim3(256), 0, st, (const double*)c.tpart, npart, c.tmin_bits, s.alpha,
+                       c.s_dev);
     if (s.self_contact) {
         hipLaunchKernelGGL(k_sum2, dim3(1), dim3(64), 0, st, c.cnt);
         HC(scan_exclusive(c.keep, c.keep_ofs, (int)(2 * c.cap), c.cnt + 9, c.scan_tiles, nullptr, st));
@@ -1482,7 +1737,7 @@ cloth_status contact_stage_toi(Scene& s, ContactState& c, const float* xm, const
     int h[2] = {(int)n_vt, (int)n_ee};
     HC(hipMemcpy(c.cnt, h, sizeof(h), hipMemcpyHostToDevice));
     hipLaunchKernelGGL(k_toi_merge, dim3(gblocks(n_vt + n_ee)), dim3(TPB), 0, nullptr, s.d, s.d.xm, s.d.xt, c.cand_vt,
-                       c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tmin_bits, 0);
+                       c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tpart, 0);
     HC(hipGetLastError());
     HC(hipDeviceSynchronize());
     if (n_vt) HC(hipMemcpy(toi_vt, c.toi_vt, sizeof(double) * n_vt, hipMemcpyDeviceToHost));

@@ -6,6 +6,13 @@
 
 namespace cloth {
 
+// Kernel-level timing: while a pair is set (on this host thread), the
+// single-kernel launchers below (local residual, expand, Jacobi sweep)
+// launch through hipExtLaunchKernelGGL with these events, which then carry
+// the kernel's own start and end time instead of a marker around it.
+void set_kernel_events(hipEvent_t start, hipEvent_t stop);
+void clear_kernel_events();
+
 // ---- PD iteration (pd_kernels.hip)
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);
 hipError_t launch_copy3(float* dst, const float* src, int nv, hipStream_t st);

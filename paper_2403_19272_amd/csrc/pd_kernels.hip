@@ -15,6 +15,7 @@
 // Data: SoA FP32 positions (x, y, z planes of nv floats); the off-diagonal
 // part of H in SELL-64 slices (one slice per wavefront, shared by the three
 // coordinates) plus diag(H); U row-major in FP32 or BF16.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -293,16 +294,29 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     for (int i = 0; i < 8; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.f;
     const UT* U = static_cast<const UT*>(d.U);
     if (vg < nvg) {
-        for (int vv = vg; vv < TPB; vv += nvg) {
-            int vtx = tile * TPB + vv;
-            if (vtx >= n) break;
-            float u[8];
-            load8<UT>(U, (size_t)vtx * r + cg * 8, u);
-            float a0 = sr[0][vv], a1 = sr[1][vv], a2 = sr[2][vv];
-            for (int i = 0; i < 8; ++i) {
-                acc[i][0] += u[i] * a0;
-                acc[i][1] += u[i] * a1;
-                acc[i][2] += u[i] * a2;
+        // vertices in batches of 4: the batch's loads are issued together
+        for (int vv0 = vg; vv0 < TPB; vv0 += 4 * nvg) {
+            float u[4][8];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int vv = vv0 + b * nvg;
+                const int vtx = tile * TPB + vv;
+                if (vv < TPB && vtx < n) {
+                    load8<UT>(U, (size_t)vtx * r + cg * 8, u[b]);
+                } else {
+                    for (int i = 0; i < 8; ++i) u[b][i] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int vv = vv0 + b * nvg;
+                if (vv >= TPB) break;
+                float a0 = sr[0][vv], a1 = sr[1][vv], a2 = sr[2][vv];
+                for (int i = 0; i < 8; ++i) {
+                    acc[i][0] += u[b][i] * a0;
+                    acc[i][1] += u[b][i] * a1;
+                    acc[i][2] += u[b][i] * a2;
+                }
             }
         }
         for (int i = 0; i < 8; ++i)
@@ -323,30 +337,50 @@ __global__ void k_reduce_g1(const float* __restrict__ gpart, int nblk, int m, do
     int b0 = s * SEG, b1 = min(nblk, b0 + SEG);
     for (int o = threadIdx.x; o < m; o += blockDim.x) {
         double acc = 0.0;
+#pragma unroll 8
         for (int b = b0; b < b1; ++b) acc += (double)gpart[(size_t)b * m + o];
         out[(size_t)s * m + o] = acc;
     }
 }
 
 // g = sum of the level-1 partials (FP64) -> d.gvec; without contact also
-// q = A^{-1} g with the precomputed inverse of Lambda~.
-__global__ void k_solve_reduced(Dev d, const double* __restrict__ g1, int nseg, int solve) {
+// q = A^{-1} g with the precomputed inverse of Lambda~: one wavefront per
+// row of A^{-1} at a time, lanes over its columns (coalesced), three
+// right-hand sides reduced across the wavefront.
+__global__ void __launch_bounds__(1024) k_solve_reduced(Dev d, const double* __restrict__ g1, int nseg, int solve) {
     extern __shared__ double gs[];
     const int r = d.r, m = r * 3;
     for (int o = threadIdx.x; o < m; o += blockDim.x) {
         double acc = 0.0;
+#pragma unroll 8
         for (int s = 0; s < nseg; ++s) acc += g1[(size_t)s * m + o];
         gs[o] = acc;
         d.gvec[o] = acc;
     }
     __syncthreads();
     if (!solve) return;
-    for (int o = threadIdx.x; o < m; o += blockDim.x) {
-        int c = o / 3, k = o % 3;
-        double acc = 0.0;
-        for (int j = 0; j < r; ++j) acc += d.Ainv[(size_t)c * r + j] * gs[j * 3 + k];
-        d.Qd[o] = acc;
-        d.Qf[o] = (float)acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = wave; c < r; c += nw) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int j = lane; j < r; j += 64) {
+            double a = d.Ainv[(size_t)c * r + j];
+            a0 += a * gs[j * 3];
+            a1 += a * gs[j * 3 + 1];
+            a2 += a * gs[j * 3 + 2];
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o);
+            a1 += __shfl_xor(a1, o);
+            a2 += __shfl_xor(a2, o);
+        }
+        if (lane == 0) {
+            d.Qd[c * 3] = a0;
+            d.Qd[c * 3 + 1] = a1;
+            d.Qd[c * 3 + 2] = a2;
+            d.Qf[c * 3] = (float)a0;
+            d.Qf[c * 3 + 1] = (float)a1;
+            d.Qf[c * 3 + 2] = (float)a2;
+        }
     }
 }
 
@@ -372,28 +406,40 @@ __global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
     const int n = d.nv;
     const int base = xcd_tile(blockIdx.x, gridDim.x) * TPB + wave * 64;
     const UT* U = static_cast<const UT*>(d.U);
-    for (int rnd = 0; rnd < G; ++rnd) {
-        const int lv = rnd * per + vs;
-        const int v = base + lv;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-        if (active && v < n) {
-            float u[8];
-            load8<UT>(U, (size_t)v * r + cg * 8, u);
-            for (int i = 0; i < 8; ++i) {
-                a0 += u[i] * q[i][0];
-                a1 += u[i] * q[i][1];
-                a2 += u[i] * q[i][2];
+    // rounds in batches of EXP_BATCH: all loads of a batch are issued before
+    // their products, so that each lane keeps several rows in flight
+    constexpr int EXP_BATCH = 4;
+    for (int rnd0 = 0; rnd0 < G; rnd0 += EXP_BATCH) {
+        float u[EXP_BATCH][8];
+#pragma unroll
+        for (int b = 0; b < EXP_BATCH; ++b) {
+            const int v = base + (rnd0 + b) * per + vs;
+            if (rnd0 + b < G && active && v < n) {
+                load8<UT>(U, (size_t)v * r + cg * 8, u[b]);
+            } else {
+                for (int i = 0; i < 8; ++i) u[b][i] = 0.f;
             }
         }
-        for (int o = 1; o < G; o <<= 1) {
-            a0 += __shfl_xor(a0, o);
-            a1 += __shfl_xor(a1, o);
-            a2 += __shfl_xor(a2, o);
-        }
-        if (cg == 0) {
-            res[0][wave * 64 + lv] = a0;
-            res[1][wave * 64 + lv] = a1;
-            res[2][wave * 64 + lv] = a2;
+#pragma unroll
+        for (int b = 0; b < EXP_BATCH; ++b) {
+            if (rnd0 + b >= G) break;
+            const int lv = (rnd0 + b) * per + vs;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+            for (int i = 0; i < 8; ++i) {
+                a0 += u[b][i] * q[i][0];
+                a1 += u[b][i] * q[i][1];
+                a2 += u[b][i] * q[i][2];
+            }
+            for (int o = 1; o < G; o <<= 1) {
+                a0 += __shfl_xor(a0, o);
+                a1 += __shfl_xor(a1, o);
+                a2 += __shfl_xor(a2, o);
+            }
+            if (cg == 0) {
+                res[0][wave * 64 + lv] = a0;
+                res[1][wave * 64 + lv] = a1;
+                res[2][wave * 64 + lv] = a2;
+            }
         }
     }
     __syncthreads();
@@ -468,6 +514,28 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
 
 static inline int blocks_for(int n) { return (n + TPB - 1) / TPB; }
 
+namespace {
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+template <typename... KArgs, typename... Args>
+void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shm, hipStream_t st, Args... args) {
+    if (t_ev_start && t_ev_stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, st, t_ev_start, t_ev_stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+}
+}  // namespace
+
+void set_kernel_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+void clear_kernel_events() {
+    t_ev_start = nullptr;
+    t_ev_stop = nullptr;
+}
+
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
     return hipGetLastError();
@@ -504,9 +572,9 @@ hipError_t launch_epilogue(const Dev& d, float inv_h, hipStream_t st) {
 
 hipError_t launch_local_residual(const Dev& d, int prec, int flags, hipStream_t st) {
     if (prec == CLOTH_MIXED)
-        hipLaunchKernelGGL(k_local_residual<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, flags);
+        launch_timed(k_local_residual<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, flags);
     else
-        hipLaunchKernelGGL(k_local_residual<float>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, flags);
+        launch_timed(k_local_residual<float>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, flags);
     return hipGetLastError();
 }
 
@@ -514,23 +582,22 @@ hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpar
     const int m = d.r * 3;
     int nseg = (nblk + SEG - 1) / SEG;
     hipLaunchKernelGGL(k_reduce_g1, dim3(nseg), dim3(256), 0, st, d.gpart, nblk, m, gpart2);
-    hipLaunchKernelGGL(k_solve_reduced, dim3(1), dim3(512), sizeof(double) * m, st, d,
+    hipLaunchKernelGGL(k_solve_reduced, dim3(1), dim3(1024), sizeof(double) * m, st, d,
                        (const double*)gpart2, nseg, contact ? 0 : 1);
     return hipGetLastError();
 }
 
 hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st) {
     if (prec == CLOTH_MIXED)
-        hipLaunchKernelGGL(k_expand<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
+        launch_timed(k_expand<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
     else
-        hipLaunchKernelGGL(k_expand<float>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
+        launch_timed(k_expand<float>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
     return hipGetLastError();
 }
 
 hipError_t launch_jacobi_cheb(const Dev& d, float omega, float gamma, int has_contact,
                               unsigned long long* dx_slot, hipStream_t st) {
-    hipLaunchKernelGGL(k_jacobi_cheb, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, omega, gamma,
-                       has_contact, dx_slot);
+    launch_timed(k_jacobi_cheb, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, omega, gamma, has_contact, dx_slot);
     return hipGetLastError();
 }
 

@@ -30,11 +30,12 @@ def test_warm_start_hanging_cloth(precision):
 
 
 def test_residual_forwarding_after_a_filtered_step():
-    """A cloth 1.5 mm above a sphere falling at 0.6 m/s: the exiting filter cuts
-    the step (t_TOI < rf_toi), the forwarded dx and the next step agree."""
+    """A cloth 1.5 mm above a sphere falling at 2 m/s: the exiting filter cuts
+    the step (t_TOI about 0.49 < rf_toi), the forwarded dx and the next step
+    agree."""
     sc = scenegen.drop_cloth(20, seed=9, obstacle="sphere", r=8, steps=2, drop=0.0015, d_hat=1e-3,
                              iters_outer=2, iters_inner=5)
-    sc.v0[:] = np.array([0.0, -0.6, 0.0], np.float32)
+    sc.v0[:] = np.array([0.0, -2.0, 0.0], np.float32)
     o, U, rho = oracle_side(sc, "fp32", gamma=0.6)
     o.p.rf_iters, o.p.rf_toi = 4, 1.5
     g = gpu_side(sc, U, "fp32", rho, gamma=0.6)
