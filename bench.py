@@ -53,22 +53,28 @@ def make_gpu_scene(sc, precision, P, basis_mod):
 
 def kernel_bytes(name, sc, nnz, ubytes, contact):
     """Algorithmic bytes one launch moves: every array the kernel reads or
-    writes counted once (neighbour gathers count as cache hits)."""
+    writes counted once (neighbour gathers count as cache hits).  The sweeps
+    read the off-diagonal part of H in SELL-64 (8 bytes per entry; these
+    grids have no padding) plus 4 bytes per 64-row slice pointer."""
     N, T, r = sc.nv, sc.nt, sc.r
     nblk = (N + 255) // 256
-    csr = 4 * (N + 1) + 8 * nnz
+    sell = 8 * (nnz - N) + 4 * ((N + 63) // 64 + 1)
     if name == "local_residual":
-        b = 12 * N + 4 * N + 4 * (N + 1) + 12 * T + 32 * T + 12 * N + csr + N + N * r * ubytes
-        b += 12 * N + nblk * r * 3 * 4
+        b = 12 * N + 4 * N                      # z, m/h^2
+        b += 4 * (N + 1) + 12 * T + 32 * T      # incidence, triangle records
+        b += 12 * N + sell + N                  # x (gathers as hits), H off-diagonal, pin flags
+        b += N * r * ubytes                     # U rows for U^T r0
+        b += 12 * N + nblk * r * 3 * 4          # r0 out, block partials out
         if contact:
-            b += 4 * (N + 1) + 4 * N * len(sc.obstacles) + 4 * N
+            b += 4 * (N + 1) + 4 * N * len(sc.obstacles) + 4 * N   # slot lists, obstacle spans, W out
         return b
     if name == "expand":
-        return N * r * ubytes + 12 * N + 12 * N
+        return N * r * ubytes + 12 * N          # U rows, delta out
     if name == "jacobi_cheb":
-        b = 12 * N * 3 + N + csr + 4 * N + 12 * N + 12 * N
+        b = 12 * N + 12 * N + 12 * N + N        # delta (gathers as hits), x^k, x^{k-1}, pin flags
+        b += sell + 4 * N + 12 * N + 12 * N     # H off-diagonal, diag(H), r0, x^{k+1} out
         if contact:
-            b += 4 * N
+            b += 4 * N                          # W
         return b
     return None
 
@@ -133,7 +139,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
     ap.add_argument("--precision", default=None, choices=["mixed", "fp32"])
-    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing-pass", action="store_true")
     ap.add_argument("--eager", action="store_true",

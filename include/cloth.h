@@ -92,7 +92,9 @@ typedef struct {
  *   cheb_delay          iterations before the Chebyshev weights start
  *   precision           CLOTH_PLAIN_FP32 or CLOTH_MIXED
  *   self_contact        1: vertex-triangle and edge-edge contact on
- *   pair_capacity       candidate pairs the arena holds (0: 48 per vertex) */
+ *   pair_capacity       candidate pairs per list (VT, EE) the arena holds
+ *                       (0: 128 per vertex); a stage that finds more makes
+ *                       the next stats read return CLOTH_E_CAPACITY */
 typedef struct {
     int32_t r, iters_inner, iters_outer;
     double cheb_rho, cheb_gamma;
@@ -112,6 +114,9 @@ typedef struct {
     double dx_norm;      /* max per-vertex change of the last inner iteration */
     double min_toi;      /* smallest time of impact seen (2 = none) */
     double cheb_rho, cheb_gamma;
+    int64_t peak_candidates;  /* largest VT or EE candidate list of any outer
+                                 stage since the previous stats read (for
+                                 sizing pair_capacity) */
 } cloth_step_stats;
 
 const char* cloth_status_string(cloth_status s);
@@ -257,7 +262,9 @@ cloth_status cloth_stage_broad_phase(cloth_scene s, const float* xm, const float
                                      int64_t cap, int32_t* vt, int64_t* n_vt, int32_t* ee,
                                      int64_t* n_ee);
 
-/* FP64 time of impact over (xm, xp) for given VT and EE pairs (2.0 = no hit). */
+/* FP64 time of impact over (xm, xp) for given VT and EE pairs (2.0 = no hit).
+ * Sections 4.1 and 7.  CLOTH_E_INVALID on a scene without self contact,
+ * CLOTH_E_CAPACITY if a list exceeds the scene's pair capacity. */
 cloth_status cloth_stage_toi(cloth_scene s, const float* xm, const float* xp, int64_t n_vt,
                              const int32_t* vt, int64_t n_ee, const int32_t* ee,
                              double* toi_vt, double* toi_ee);

@@ -65,7 +65,7 @@ class StepStats(C.Structure):
     _fields_ = [("inner_iters", C.c_int32), ("outer_iters", C.c_int32),
                 ("n_candidates", C.c_int64), ("n_constraints", C.c_int64),
                 ("dx_norm", C.c_double), ("min_toi", C.c_double), ("cheb_rho", C.c_double),
-                ("cheb_gamma", C.c_double)]
+                ("cheb_gamma", C.c_double), ("peak_candidates", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -167,8 +167,8 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     d.Qd = cv<double>(carve_fn, (size_t)s.r * 3);
     d.Ainv = cv<double>(carve_fn, (size_t)s.r * s.r);
     d.Lam = cv<double>(carve_fn, (size_t)s.r * s.r);
-    d.Amat = cv<double>(carve_fn, (size_t)s.r * s.r);
-    d.gram_part = cv<float>(carve_fn, (size_t)GRAM_CHUNKS * s.r * s.r);
+    d.Amat = cv<double>(carve_fn, (size_t)(GRAM_GROUPS_MAX + 2) * s.r * (s.r + 1) / 2 + s.r);
+    d.gram_part = cv<double>(carve_fn, (size_t)GRAM_CHUNKS * s.r * s.r);
     d.dxbits = cv<unsigned long long>(carve_fn, 4096);
     s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);
     if (!d.W || !d.mh2 || !d.diag || !s.d_pinned || !s.d_rowptr || !s.d_col || !s.d_val || !s.d_tri ||
@@ -382,7 +382,7 @@ cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_pa
     ds.r = params->r;
     ds.prec = params->precision;
     ds.self_contact = params->self_contact;
-    ds.pair_cap = params->pair_capacity > 0 ? params->pair_capacity : (int64_t)48 * mesh->nv;
+    ds.pair_cap = params->pair_capacity > 0 ? params->pair_capacity : (int64_t)128 * mesh->nv;
     ds.nblk = (ds.nv + TPB - 1) / TPB;
     *bytes = dry_footprint(ds);
     return CLOTH_OK;
@@ -646,6 +646,11 @@ cloth_status cloth_set_state(cloth_scene sc, const float* x, const float* v, voi
     } else {
         HIPCHECK(hipMemsetAsync(s.d.v, 0, sizeof(float) * 3 * s.nv, st));
     }
+    // a new state starts without a forwarded residual and with a clear
+    // overflow record
+    HIPCHECK(hipMemsetAsync(s.d_rfdx, 0, sizeof(float) * 3 * s.nv, st));
+    cloth_status rc = contact_reset(s, sc->c, st);
+    if (rc != CLOTH_OK) return rc;
     HIPCHECK(hipStreamSynchronize(st));
     return CLOTH_OK;
 }

@@ -9,17 +9,17 @@
 
 namespace cloth {
 
-// Broad-phase grid of one target family (cell widths, column axes) and the
-// inline record of a target in its column bucket.
+// Broad-phase grids of one target family (cell widths of the fine grid 1
+// and the coarse grid 2) and the inline record of a target in its bucket.
 struct BpGrid {
-    double cs[3];   // cell width per axis
-    int au, av;     // column axes (the third axis runs inside a column)
-    int ok;         // all extents finite
-    int pad;
+    double cs1[3], cs2[3];   // cell width per axis
+    int ok;                  // all extents finite
+    int use2;                // some target is wider than a grid-1 cell
 };
 
 struct BpRec {
-    int cu, cv, id, a, b, c;   // column, target id, its vertices (c = -1 for edges)
+    long long key;             // grid (bit 63) and packed low-corner cell (21 bits per axis)
+    int id, a, b, c;           // target id, its vertices (c = -1 for edges)
     float lo[3], hi[3];
 };
 static_assert(sizeof(BpRec) == 48, "BpRec layout");
@@ -29,19 +29,20 @@ struct ContactState {
     bool active = false;    // the current block has constraints (or may have)
     int nob = 0;
     ObstD ob[MAX_OBST];
-    int64_t cap = 0;        // pair capacity (candidates and constraints per type)
+    int64_t cap = 0;        // candidate capacity per list (VT, EE)
+    int64_t ccap = 0;       // constraint capacity (VT + EE together)
     int hash_p = 0;         // hash buckets (power of two)
     int max_out = 1024;     // candidate pairs one query may produce
     int ntiles_cap = 0;     // scan tiles for the largest scan
 
     // boxes (lo xyz, hi xyz as 6 floats)
     float *vbox = nullptr, *tbox = nullptr, *ebox = nullptr;
-    int2* tcol = nullptr;   // column of each target's low corner
     int *bucket_cnt = nullptr, *bucket_ptr = nullptr;
-    BpRec* rec = nullptr;   // targets in column-bucket order
+    BpRec* rec = nullptr;   // targets in cell-bucket order
     int* qscratch = nullptr;  // per query: up to QK target ids from the counting pass
     float* bpart = nullptr;   // per-block box extents
     BpGrid* grid = nullptr;   // [0] triangles, [1] edges
+    float4 *xm4 = nullptr, *xp4 = nullptr;   // AoS copies of the stage's two positions (TOI gathers)
 
     // candidates
     int* vcount = nullptr;  // per vertex VT counts, then offsets (nv+1)
@@ -63,7 +64,9 @@ struct ContactState {
     ObstD* ob_dev = nullptr;     // device copy of ob[]
 
     // device scalars: [0] n_vt cand, [1] n_ee cand, [2] n_cvt, [3] n_cee,
-    // [4] n_prev_vt, [5] n_prev_ee, [6] n_cv, [7] overflow flag,
+    // [4] n_prev_vt, [5] n_prev_ee, [6] n_cv, [7] overflow bits (sticky until
+    // read by contact_stats or cleared with a new state), [12] largest
+    // candidate list since the last stats read,
     // [9] n_vt + n_ee, [10] obstacle constraints
     int* cnt = nullptr;
     unsigned long long* tmin_bits = nullptr;  // [0] stage min, [1] step min, [2] last stage's t_TOI
@@ -92,6 +95,8 @@ cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, hipStream_t st);
 cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step_stats* out);
+// clears the sticky overflow record (with a new state)
+cloth_status contact_reset(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_load_constraints(Scene& s, ContactState& c, int64_t n_vt, const int32_t* vt,
                                       const int32_t* a_vt, int64_t n_ee, const int32_t* ee,
                                       const int32_t* a_ee, const int32_t* ob_a);

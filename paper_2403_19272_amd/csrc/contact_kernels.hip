@@ -346,6 +346,29 @@ __device__ __forceinline__ void pair_points(const Dev& d, bool vt, int i, int j,
     }
 }
 
+__device__ __forceinline__ d3 ld4(const float4* X4, int v) {
+    float4 p = X4[v];
+    return {(double)p.x, (double)p.y, (double)p.z};
+}
+
+// the pair's four points at both ends of the interval, from AoS copies
+__device__ __forceinline__ void pair_points2(const Dev& d, bool vt, int i, int j, const float4* X0, const float4* X1,
+                                             d3* q0, d3* q1) {
+    int id[4];
+    if (vt) {
+        TriRec tr = d.tri[j];
+        id[0] = i; id[1] = tr.v0; id[2] = tr.v1; id[3] = tr.v2;
+    } else {
+        int2 e = reinterpret_cast<const int2*>(d.edges)[i], f = reinterpret_cast<const int2*>(d.edges)[j];
+        id[0] = e.x; id[1] = e.y; id[2] = f.x; id[3] = f.y;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        q0[k] = ld4(X0, id[k]);
+        q1[k] = ld4(X1, id[k]);
+    }
+}
+
 __device__ __forceinline__ void pair_ids(const Dev& d, bool vt, int i, int j, int* id) {
     if (vt) {
         TriRec tr = d.tri[j];
@@ -474,46 +497,90 @@ static hipError_t scan_exclusive(const int* in, int* out, int n_cap, const int* 
 //
 // Candidate pairs are the pairs whose FP32 swept boxes (grown by d^) overlap;
 // the structure below only has to find each of them once.  Targets
-// (triangles for VT, edges for EE) are filed by the grid column of their low
-// corner on the two axes with the most cells (cell width = widest target box
-// on that axis, plus a margin); a query box looks at the columns from one
-// below its low corner to its high corner on those axes, so every
-// overlapping target is seen exactly once.  Each target is stored inline in
-// its column bucket (column, ids, box), so a query reads contiguous records.
+// (triangles for VT, edges for EE) are filed in the grid cell of their low
+// corner, and a query box looks at the cells from one below its low corner
+// to its high corner on every axis: every overlapping target is seen exactly
+// once provided each target is narrower than a cell.  Two grids keep the
+// cells small when a few boxes are much wider than the rest (fast-moving
+// parts): grid 1 has cells of 1.5 x the mean target width per axis and holds
+// the targets narrower than that; grid 2 has cells as wide as the widest
+// target and holds the others (it is used only when such targets exist).
+// Cells are hashed into one bucket table; each bucket holds inline records
+// (packed grid + cell key, ids, box), so a query reads contiguous records
+// and skips the ones of other cells that share its bucket.
 
 __global__ void k_fill_i32(int* p, int v, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
-constexpr int BP_PART = 18;   // per block: tri (maxw, lo, hi) x 3 axes, edge (maxw, lo, hi) x 3 axes
-constexpr int QK = 32;        // candidates per query kept from the counting pass
+// per block and family (triangles, edges): widest box, lowest and highest
+// corner, sum of widths, per axis
+constexpr int BP_FAM = 12;
+constexpr int BP_PART = 2 * BP_FAM;
+constexpr int QK = 48;        // candidates per query kept from the counting pass
+constexpr int CELL_LIM = 1 << 20;   // |cell index| bound of the packed keys
+constexpr double CELL_MARGIN = 1.0 + 1.0 / 1024.0;
+// overflow flag bits (sticky until the host reads them)
+constexpr int OVF_QUERY = 1, OVF_CELL = 2, OVF_LIST = 4, OVF_CONS = 8;
+constexpr int PEAK_SLOT = 12;   // cnt[12]: largest candidate list since the last stats read
 
-__device__ __forceinline__ unsigned hash2(int u, int v) { return ((unsigned)u * 73856093u) ^ ((unsigned)v * 19349663u); }
+__device__ __forceinline__ int bp_op(int k) { return (k % BP_FAM) / 3; }   // 0 max, 1 min, 2 max, 3 sum
+__device__ __forceinline__ float bp_combine(int op, float a, float b) {
+    return op == 1 ? fminf(a, b) : (op == 3 ? a + b : fmaxf(a, b));
+}
+__device__ __forceinline__ float bp_identity(int op) {
+    return op == 1 ? INFINITY : (op == 2 ? -INFINITY : 0.f);
+}
+
+__device__ __forceinline__ unsigned hash3(int grid, int x, int y, int z) {
+    return ((unsigned)x * 73856093u) ^ ((unsigned)y * 19349663u) ^ ((unsigned)z * 83492791u) ^
+           (grid ? 0x9E3779B9u : 0u);
+}
+__device__ __forceinline__ long long cell_key(int grid, int x, int y, int z) {
+    return ((long long)grid << 63) | ((long long)(x & 0x1FFFFF) << 42) | ((long long)(y & 0x1FFFFF) << 21) |
+           (long long)(z & 0x1FFFFF);
+}
 
 // cell index along one axis, in FP64 so that the one-cell margin of the
 // query range cannot be eaten by rounding; false for non-finite or far-away
 // coordinates
 __device__ __forceinline__ bool cell_d(float x, double cs, int& c) {
     double q = (double)x / cs;
-    if (!(fabs(q) < 1e9)) return false;
+    if (!(fabs(q) < (double)(CELL_LIM - 64))) return false;
     c = (int)floor(q);
     return true;
 }
 
-// Swept boxes over (xm, xp) grown by dhat (FP32); per block the widest box
-// and the extent per axis of the triangle and edge boxes (reduced by k_grid).
+__device__ __forceinline__ bool cell3(const float* lo, const double* cs, int* c) {
+    return cell_d(lo[0], cs[0], c[0]) && cell_d(lo[1], cs[1], c[1]) && cell_d(lo[2], cs[2], c[2]);
+}
+
+// grid of a target box: 0 if narrower than a grid-1 cell on every axis
+__device__ __forceinline__ int target_grid(const float* box, const BpGrid& g) {
+    for (int a = 0; a < 3; ++a)
+        if ((double)(box[3 + a] - box[a]) * CELL_MARGIN > g.cs1[a]) return 1;
+    return 0;
+}
+
+// cell of a target: false (and cell 0 of grid 0) if it cannot be filed
+__device__ __forceinline__ bool target_cell(const float* box, const BpGrid& g, int& grid, int* c) {
+    grid = target_grid(box, g);
+    if (g.ok && cell3(box, grid ? g.cs2 : g.cs1, c)) return true;
+    grid = 0;
+    c[0] = c[1] = c[2] = 0;
+    return false;
+}
+
+// Swept boxes over (xm, xp) grown by dhat (FP32); per block the box
+// statistics of the triangle and edge boxes (reduced by k_grid).
 __global__ void __launch_bounds__(256) k_boxes(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
-                                               float dhat, float* vbox, float* tbox, float* ebox, float* bpart) {
+                                               float dhat, float* vbox, float* tbox, float* ebox, float* bpart,
+                                               float4* xm4, float4* xp4) {
     __shared__ float red[4][BP_PART];
     const int n = d.nv;
     const int total = d.nv + d.nt + d.ne;
     float acc[BP_PART];
-    for (int f = 0; f < 2; ++f)
-        for (int c = 0; c < 3; ++c) {
-            acc[f * 9 + c] = 0.f;                 // widest box
-            acc[f * 9 + 3 + c] = INFINITY;        // lowest corner
-            acc[f * 9 + 6 + c] = -INFINITY;       // highest corner
-        }
+    for (int k = 0; k < BP_PART; ++k) acc[k] = bp_identity(bp_op(k));
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         int ids[3];
         int nvert;
@@ -524,6 +591,9 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float* __restrict__ 
             nvert = 1;
             out = vbox + 6 * (size_t)i;
             kind = 0;
+            // AoS copies of the two positions for the gathers of the TOI
+            xm4[i] = make_float4(xm[i], xm[n + i], xm[2 * n + i], 0.f);
+            xp4[i] = make_float4(xp[i], xp[n + i], xp[2 * n + i], 0.f);
         } else if (i < d.nv + d.nt) {
             int t = i - d.nv;
             TriRec tr = d.tri[t];
@@ -550,104 +620,87 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float* __restrict__ 
             out[c] = l;
             out[3 + c] = h;
             if (kind) {
-                const int f = (kind - 1) * 9;
+                const int f = (kind - 1) * BP_FAM;
                 acc[f + c] = fmaxf(acc[f + c], h - l);
                 acc[f + 3 + c] = fminf(acc[f + 3 + c], l);
                 acc[f + 6 + c] = fmaxf(acc[f + 6 + c], h);
+                acc[f + 9 + c] += h - l;
             }
         }
     }
     for (int k = 0; k < BP_PART; ++k) {
-        const bool is_min = (k % 9) >= 3 && (k % 9) < 6;
+        const int op = bp_op(k);
         float w = acc[k];
-        for (int o = 32; o > 0; o >>= 1) {
-            float u = __shfl_xor(w, o);
-            w = is_min ? fminf(w, u) : fmaxf(w, u);
-        }
+        for (int o = 32; o > 0; o >>= 1) w = bp_combine(op, w, __shfl_xor(w, o));
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = w;
     }
     __syncthreads();
     if (threadIdx.x < BP_PART) {
-        const int k = threadIdx.x;
-        const bool is_min = (k % 9) >= 3 && (k % 9) < 6;
+        const int k = threadIdx.x, op = bp_op(k);
         float w = red[0][k];
-        for (int q = 1; q < 4; ++q) w = is_min ? fminf(w, red[q][k]) : fmaxf(w, red[q][k]);
+        for (int q = 1; q < 4; ++q) w = bp_combine(op, w, red[q][k]);
         bpart[(size_t)blockIdx.x * BP_PART + k] = w;
     }
 }
 
 // One block: reduce the box partials; per family (0 = triangles, 1 = edges)
-// the cell widths and the column axes (the two with the most cells).
-__global__ void k_grid(const float* __restrict__ bpart, int nblk, BpGrid* grid) {
+// the cell widths of the two grids.
+__global__ void k_grid(const float* __restrict__ bpart, int nblk, int nt, int ne, BpGrid* grid) {
     __shared__ float red[256][BP_PART];
     for (int q = 0; q < BP_PART; ++q) {
-        const bool is_min = (q % 9) >= 3 && (q % 9) < 6;
-        float w = is_min ? INFINITY : (q % 9 < 3 ? 0.f : -INFINITY);
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-            float u = bpart[(size_t)b * BP_PART + q];
-            w = is_min ? fminf(w, u) : fmaxf(w, u);
-        }
+        const int op = bp_op(q);
+        float w = bp_identity(op);
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) w = bp_combine(op, w, bpart[(size_t)b * BP_PART + q]);
         red[threadIdx.x][q] = w;
     }
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o)
-            for (int q = 0; q < BP_PART; ++q) {
-                const bool is_min = (q % 9) >= 3 && (q % 9) < 6;
-                float a = red[threadIdx.x][q], b = red[threadIdx.x + o][q];
-                red[threadIdx.x][q] = is_min ? fminf(a, b) : fmaxf(a, b);
-            }
+            for (int q = 0; q < BP_PART; ++q)
+                red[threadIdx.x][q] = bp_combine(bp_op(q), red[threadIdx.x][q], red[threadIdx.x + o][q]);
         __syncthreads();
     }
     if (threadIdx.x < 2) {
         const int f = threadIdx.x;
-        const float* r = red[0] + f * 9;
+        const float* r = red[0] + f * BP_FAM;
+        const double count = (double)max(1, f == 0 ? nt : ne);
         BpGrid g;
         g.ok = 1;
-        double cells[3];
+        g.use2 = 0;
         for (int c = 0; c < 3; ++c) {
-            g.cs[c] = (double)r[c] * (1.0 + 1.0 / 1024.0) + 1e-30;
+            g.cs2[c] = (double)r[c] * CELL_MARGIN + 1e-30;
+            g.cs1[c] = fmin(g.cs2[c], 1.5 * ((double)r[9 + c] / count) * CELL_MARGIN + 1e-30);
             double ext = (double)r[6 + c] - (double)r[3 + c];
-            if (!isfinite(g.cs[c]) || !isfinite(ext)) g.ok = 0;
-            cells[c] = ext > 0 ? ext / g.cs[c] : 0.0;
+            if (!isfinite(g.cs2[c]) || !isfinite(g.cs1[c]) || !isfinite(ext)) g.ok = 0;
+            // targets wider than a grid-1 cell exist
+            if ((double)r[c] * CELL_MARGIN > g.cs1[c]) g.use2 = 1;
         }
-        int run = 0;
-        for (int c = 1; c < 3; ++c)
-            if (cells[c] < cells[run]) run = c;
-        g.au = run == 0 ? 1 : 0;
-        g.av = run == 2 ? 1 : 2;
-        g.pad = 0;
         grid[f] = g;
     }
 }
 
-// column of each target's low corner and bucket counts
-__global__ void __launch_bounds__(256) k_cols(int m, const float* __restrict__ box, const BpGrid* __restrict__ gp, int2* col,
-                       int* bucket_cnt, int P, int* overflow) {
+// bucket counts of the targets' low-corner cells
+__global__ void __launch_bounds__(256) k_cells(int m, const float* __restrict__ box, const BpGrid* __restrict__ gp,
+                                               int* bucket_cnt, int P, int* overflow) {
     const BpGrid g = *gp;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        int cu = 0, cv = 0;
-        bool ok = g.ok && cell_d(box[6 * (size_t)i + g.au], g.cs[g.au], cu) &&
-                  cell_d(box[6 * (size_t)i + g.av], g.cs[g.av], cv);
-        if (!ok) {   // counted and filed in column (0, 0); the step reports the overflow
-            atomicExch(overflow, 1);
-            cu = cv = 0;
-        }
-        col[i] = make_int2(cu, cv);
-        atomicAdd(&bucket_cnt[hash2(cu, cv) & (P - 1)], 1);
+        int c[3], grid;
+        if (!target_cell(box + 6 * (size_t)i, g, grid, c)) atomicOr(overflow, OVF_CELL);   // filed in cell 0
+        atomicAdd(&bucket_cnt[hash3(grid, c[0], c[1], c[2]) & (P - 1)], 1);
     }
 }
 
-// targets into their column buckets as inline records (order inside a
-// bucket is arbitrary: query outputs are sorted by target id)
-__global__ void __launch_bounds__(256) k_bucket_fill(Dev d, int vt, int m, const float* __restrict__ box, const int2* __restrict__ col,
-                              int P, int* cursor, BpRec* rec) {
+// targets into their cell buckets as inline records (order inside a bucket
+// is arbitrary: query outputs are sorted by target id)
+__global__ void __launch_bounds__(256) k_bucket_fill(Dev d, int vt, int m, const float* __restrict__ box,
+                                                     const BpGrid* __restrict__ gp, int P, int* cursor, BpRec* rec) {
+    const BpGrid g = *gp;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        int2 cc = col[i];
-        int pos = atomicAdd(&cursor[hash2(cc.x, cc.y) & (P - 1)], 1);
+        int c[3], grid;
+        target_cell(box + 6 * (size_t)i, g, grid, c);
+        int pos = atomicAdd(&cursor[hash3(grid, c[0], c[1], c[2]) & (P - 1)], 1);
         BpRec r;
-        r.cu = cc.x;
-        r.cv = cc.y;
+        r.key = cell_key(grid, c[0], c[1], c[2]);
         r.id = i;
         if (vt) {
             TriRec tr = d.tri[i];
@@ -659,15 +712,15 @@ __global__ void __launch_bounds__(256) k_bucket_fill(Dev d, int vt, int m, const
             r.b = d.edges[2 * i + 1];
             r.c = -1;
         }
-        for (int c = 0; c < 3; ++c) {
-            r.lo[c] = box[6 * (size_t)i + c];
-            r.hi[c] = box[6 * (size_t)i + 3 + c];
+        for (int k = 0; k < 3; ++k) {
+            r.lo[k] = box[6 * (size_t)i + k];
+            r.hi[k] = box[6 * (size_t)i + 3 + k];
         }
         rec[pos] = r;
     }
 }
 
-// Query of one box against the column buckets.  VT: query = vertex v,
+// Query of one box against the cell buckets.  VT: query = vertex v,
 // targets = triangles not incident to v; EE: query = edge e, targets = edges
 // f > e sharing no vertex.
 //   PASS 0: count, keep up to QK target ids per query in `scratch`, sorted.
@@ -675,10 +728,13 @@ __global__ void __launch_bounds__(256) k_bucket_fill(Dev d, int vt, int m, const
 //           scratch when they fit there, else found again and sorted in
 //           place).
 // Work and output per query are bounded (MAX_VISIT records, max_out pairs,
-// at most 8 columns per axis, finite boxes only); hitting a bound sets the
+// at most 32 grid-1 and 8 grid-2 cells per axis and MAX_CELLS per grid,
+// finite boxes only); hitting
+// a bound sets the
 // overflow flag and the step reports a capacity error instead of running
 // away on a diverged state.
 constexpr int MAX_VISIT = 1 << 16;
+constexpr int MAX_CELLS = 4096;   // cells one query may visit in one grid
 template <bool VT, int PASS>
 __global__ void __launch_bounds__(256) k_query(Dev d, const float* __restrict__ qbox, const BpGrid* __restrict__ gp,
                         const int* __restrict__ bptr, const BpRec* __restrict__ rec, int P, int* count,
@@ -708,45 +764,52 @@ __global__ void __launch_bounds__(256) k_query(Dev d, const float* __restrict__ 
             qb2 = d.edges[2 * q + 1];
         }
         float ql[3] = {qb[0], qb[1], qb[2]}, qh[3] = {qb[3], qb[4], qb[5]};
-        int lu = 0, hu = 0, lv = 0, hv = 0;
-        bool ok = g.ok && cell_d(ql[g.au], g.cs[g.au], lu) && cell_d(qh[g.au], g.cs[g.au], hu) &&
-                  cell_d(ql[g.av], g.cs[g.av], lv) && cell_d(qh[g.av], g.cs[g.av], hv) &&
-                  isfinite(ql[0] + ql[1] + ql[2] + qh[0] + qh[1] + qh[2]);
-        lu -= 1;
-        lv -= 1;
-        if (ok && (hu - lu > 8 || hv - lv > 8)) ok = false;
         int cnt = 0, visits = 0;
-        bool full = !ok;
-        if (ok) {
-            for (int cu = lu; cu <= hu && !full; ++cu)
-                for (int cv = lv; cv <= hv && !full; ++cv) {
-                    const unsigned b = hash2(cu, cv) & (P - 1);
-                    for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
-                        if (++visits > MAX_VISIT || cnt >= max_out) {
-                            full = true;
-                            break;
+        bool full = !(g.ok && isfinite(ql[0] + ql[1] + ql[2] + qh[0] + qh[1] + qh[2]));
+        for (int grid = 0; grid < 1 + g.use2 && !full; ++grid) {
+            const double* cs = grid ? g.cs2 : g.cs1;
+            const int span = grid ? 8 : 32;   // cells per axis a query may cover
+            int lo[3], hi[3];
+            if (!cell3(ql, cs, lo) || !cell3(qh, cs, hi)) {
+                full = true;
+                break;
+            }
+            for (int c = 0; c < 3; ++c) {
+                lo[c] -= 1;
+                if (hi[c] - lo[c] > span) full = true;
+            }
+            if (!full && (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1) > MAX_CELLS) full = true;
+            for (int cx = lo[0]; cx <= hi[0] && !full; ++cx)
+                for (int cy = lo[1]; cy <= hi[1] && !full; ++cy)
+                    for (int cz = lo[2]; cz <= hi[2] && !full; ++cz) {
+                        const long long key = cell_key(grid, cx, cy, cz);
+                        const unsigned b = hash3(grid, cx, cy, cz) & (P - 1);
+                        for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
+                            if (++visits > MAX_VISIT || cnt >= max_out) {
+                                full = true;
+                                break;
+                            }
+                            const BpRec r = rec[k];
+                            if (r.key != key) continue;
+                            if (VT) {
+                                if (r.a == q || r.b == q || r.c == q) continue;
+                            } else {
+                                if (r.id <= q || r.a == qa || r.a == qb2 || r.b == qa || r.b == qb2) continue;
+                            }
+                            if (ql[0] > r.hi[0] || r.lo[0] > qh[0] || ql[1] > r.hi[1] || r.lo[1] > qh[1] ||
+                                ql[2] > r.hi[2] || r.lo[2] > qh[2])
+                                continue;
+                            if (PASS == 0) {
+                                if (cnt < QK) sq[cnt] = r.id;
+                            } else {
+                                int64_t pos = (int64_t)base + cnt;
+                                if (pos < cap) out[pos] = make_int2(q, r.id);
+                            }
+                            ++cnt;
                         }
-                        const BpRec r = rec[k];
-                        if (r.cu != cu || r.cv != cv) continue;
-                        if (VT) {
-                            if (r.a == q || r.b == q || r.c == q) continue;
-                        } else {
-                            if (r.id <= q || r.a == qa || r.a == qb2 || r.b == qa || r.b == qb2) continue;
-                        }
-                        if (ql[0] > r.hi[0] || r.lo[0] > qh[0] || ql[1] > r.hi[1] || r.lo[1] > qh[1] ||
-                            ql[2] > r.hi[2] || r.lo[2] > qh[2])
-                            continue;
-                        if (PASS == 0) {
-                            if (cnt < QK) sq[cnt] = r.id;
-                        } else {
-                            int64_t pos = (int64_t)base + cnt;
-                            if (pos < cap) out[pos] = make_int2(q, r.id);
-                        }
-                        ++cnt;
                     }
-                }
         }
-        if (full) atomicExch(overflow, 1);
+        if (full) atomicOr(overflow, OVF_QUERY);
         if (PASS == 0) {
             for (int i = 1; i < min(cnt, QK); ++i) {  // insertion sort by target id
                 int key = sq[i];
@@ -761,7 +824,7 @@ __global__ void __launch_bounds__(256) k_query(Dev d, const float* __restrict__ 
         } else {
             int64_t b0 = base, b1 = (int64_t)base + cnt;
             if (b1 > cap) {
-                atomicExch(overflow, 1);
+                atomicOr(overflow, OVF_LIST);
                 b1 = cap;
             }
             for (int64_t i = b0 + 1; i < b1; ++i) {
@@ -782,8 +845,9 @@ __global__ void k_count_total(const int* counts_scanned, const int* counts_raw, 
                               int* overflow) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         long long tot = m > 0 ? (long long)counts_scanned[m - 1] + counts_raw[m - 1] : 0;
+        overflow[PEAK_SLOT - 7] = max(overflow[PEAK_SLOT - 7], (int)min(tot, (long long)INT_MAX));
         if (tot > cap) {
-            *overflow = 1;
+            *overflow |= OVF_LIST;
             tot = cap;
         }
         *n_out = (int)tot;
@@ -826,7 +890,7 @@ __device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, int2 pr, dou
     cand_a[i] = found >= 0 ? prev_a[found] : 0;
 }
 
-__global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
+__global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restrict__ xm, const float4* __restrict__ xp,
                                                    const int2* __restrict__ cvt, const int2* __restrict__ cee,
                                                    const int* cnt, double* toi_vt, double* toi_ee,
                                                    const int2* __restrict__ prev, const int* __restrict__ prev_a,
@@ -847,8 +911,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float* __restric
             const bool vt = i < nvt;
             const int2 pr = vt ? cvt[i] : cee[i - nvt];
             d3 q0[4], q1[4];
-            pair_points(d, vt, pr.x, pr.y, xm, q0);
-            pair_points(d, vt, pr.x, pr.y, xp, q1);
+            pair_points2(d, vt, pr.x, pr.y, xm, xp, q0, q1);
             if (pair_no_hit(vt, q0, q1))
                 toi_finish(i, vt, nvt, pr, NOHIT, toi_vt, toi_ee, prev, prev_a, pvt, pee, keep, cand_a, do_merge);
             else
@@ -861,8 +924,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float* __restric
             const bool vt = i < nvt;
             const int2 pr = vt ? cvt[i] : cee[i - nvt];
             d3 q0[4], q1[4];
-            pair_points(d, vt, pr.x, pr.y, xm, q0);
-            pair_points(d, vt, pr.x, pr.y, xp, q1);
+            pair_points2(d, vt, pr.x, pr.y, xm, xp, q0, q1);
             const double t = vt ? pair_toi_vt(q0, q1) : pair_toi_ee(q0, q1);
             tmin = fmin(tmin, t);
             toi_finish(i, vt, nvt, pr, t, toi_vt, toi_ee, prev, prev_a, pvt, pee, keep, cand_a, do_merge);
@@ -935,19 +997,26 @@ __global__ void k_step_length(const double* __restrict__ tpart, int npart, unsig
 // compaction of kept candidates into the new constraint list (order kept)
 __global__ void k_compact(const int2* __restrict__ cvt, const int2* __restrict__ cee, int* cnt,
                           const int* __restrict__ keep, const int* __restrict__ ofs, const int* __restrict__ cand_a,
-                          int2* cpair, int* ca) {
+                          int2* cpair, int* ca, int64_t ccap) {
     const int nvt = cnt[0], nee = cnt[1];
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nvt + nee; i += gridDim.x * blockDim.x) {
         if (keep[i]) {
             int o = ofs[i];
-            cpair[o] = i < nvt ? cvt[i] : cee[i - nvt];
-            ca[o] = cand_a[i];
+            if (o < ccap) {
+                cpair[o] = i < nvt ? cvt[i] : cee[i - nvt];
+                ca[o] = cand_a[i];
+            }
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         int tot = nvt + nee;
         int nk = tot > 0 ? ofs[tot - 1] + keep[tot - 1] : 0;
         int nk_vt = nvt > 0 ? (nvt < tot ? ofs[nvt] : nk) : 0;
+        if (nk > ccap) {   // the set is cut to the capacity and the step reports it
+            cnt[7] |= OVF_CONS;
+            nk = (int)ccap;
+            nk_vt = min(nk_vt, nk);
+        }
         cnt[2] = nk_vt;
         cnt[3] = nk - nk_vt;
     }
@@ -1149,10 +1218,10 @@ __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, cons
 // U^T diag(W) U over the contact vertices: chunk c of the vertex list,
 // upper triangle (i <= j) of the r x r partial, FP32 accumulation.
 // Gram of the contact rows, Eq. (uu): sum over contact vertices j of
-// W_j U_j U_j^T (r x r, FP32 partial per chunk of vertices).  Thread = one
+// W_j U_j U_j^T (r x r, FP64 partial per chunk of vertices).  Thread = one
 // 8 x 8 tile of the upper block triangle; blockIdx.y picks a group of 256
 // tiles, blockIdx.x a chunk of the contact-vertex list.  Vertices are staged
-// 32 at a time in LDS as W-scaled and plain FP32 rows.
+// 16 at a time in LDS as W-scaled (FP64) and plain (FP32) rows.
 constexpr int GRAM_MIN_PER_CHUNK = 32;
 __device__ __forceinline__ int gram_per_chunk(int ncv, int nchunk) {
     return max(GRAM_MIN_PER_CHUNK, (ncv + nchunk - 1) / nchunk);
@@ -1160,9 +1229,10 @@ __device__ __forceinline__ int gram_per_chunk(int ncv, int nchunk) {
 
 template <typename UT>
 __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
-                                            int nchunk, float* part) {
-    __shared__ float us[32][MAX_R];
-    __shared__ float ws[32][MAX_R];
+                                            int nchunk, double* part) {
+    constexpr int VB = 16;   // contact vertices staged per round
+    __shared__ float us[VB][MAX_R];
+    __shared__ double ws[VB][MAX_R];
     const int r = d.r, T = r >> 3;
     const int ncv = *n_cv;
     const int per = gram_per_chunk(ncv, nchunk);
@@ -1180,14 +1250,17 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
         }
         tj = ti + rem;
     }
-    float acc[8][8];
+    // FP64 products and sums: the weights span many orders of magnitude
+    // (k 2^a), and an FP32 Gram's rounding reaches the scale of Lambda~'s
+    // smallest eigenvalues, which can cost A its definiteness
+    double acc[8][8];
     for (int a = 0; a < 8; ++a)
-        for (int b = 0; b < 8; ++b) acc[a][b] = 0.f;
+        for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
     const UT* U = static_cast<const UT*>(d.U);
-    for (int base = c0; base < c1; base += 32) {
-        const int m = min(32, c1 - base);
+    for (int base = c0; base < c1; base += VB) {
+        const int m = min(VB, c1 - base);
         __syncthreads();
-        for (int q = threadIdx.x; q < 32 * r; q += 256) {
+        for (int q = threadIdx.x; q < VB * r; q += 256) {
             int vv = q / r, cc = q % r;
             float u = 0.f, w = 0.f;
             if (vv < m) {
@@ -1198,12 +1271,12 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
                 w = d.W[v];
             }
             us[vv][cc] = u;
-            ws[vv][cc] = w * u;
+            ws[vv][cc] = (double)w * (double)u;   // exact
         }
         __syncthreads();
         if (active) {
             for (int vv = 0; vv < m; ++vv) {
-                float wa[8], ub[8];
+                double wa[8], ub[8];
                 for (int a = 0; a < 8; ++a) wa[a] = ws[vv][ti * 8 + a];
                 for (int b = 0; b < 8; ++b) ub[b] = us[vv][tj * 8 + b];
                 for (int a = 0; a < 8; ++a)
@@ -1217,142 +1290,250 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
             part[((size_t)blockIdx.x * r + ti * 8 + a) * r + tj * 8 + b] = acc[a][b];
 }
 
-// A = Lambda~ + sum of the Gram chunks, in FP64, packed lower triangle
-// (A(i, j), j <= i, at i (i + 1) / 2 + j).  The chunk sums read the upper
-// triangle of the partials: A(i, j) = part(j, i).
-__global__ void k_gram_reduce(Dev d, const float* __restrict__ part, int nchunk, const int* __restrict__ n_cv,
-                              double* __restrict__ Apk) {
+// Packed lower triangle, column-major: column k holds rows k..r-1 at
+// pk_off(k) = k r - k (k - 1) / 2, so that every column is contiguous.
+__device__ __forceinline__ int pk_off(int k, int r) { return k * r - (k * (k - 1)) / 2; }
+__device__ __forceinline__ void pk_entry(int e, int r, int& i, int& k) {
+    // largest k with pk_off(k) <= e (pk_off is increasing in k)
+    double b = 2.0 * r + 1.0;
+    int kk = (int)((b - sqrt(b * b - 8.0 * e)) * 0.5);
+    kk = max(0, min(r - 1, kk));
+    while (kk > 0 && pk_off(kk, r) > e) --kk;
+    while (kk + 1 < r && pk_off(kk + 1, r) <= e) ++kk;
+    k = kk;
+    i = k + (e - pk_off(k, r));
+}
+
+// First level of A = Lambda~ + sum of the Gram chunks: block (entry tile,
+// group g) sums the chunks of group g for its entries in FP64.  The chunk
+// partials hold the upper block triangle: A(i, k) = part(k, i) for k <= i.
+constexpr int GRAM_GROUPS = GRAM_GROUPS_MAX;
+__global__ void __launch_bounds__(256) k_gram_reduce(Dev d, const double* __restrict__ part, int nchunk,
+                                                     const int* __restrict__ n_cv, double* __restrict__ gred) {
     const int r = d.r;
     const int ncv = *n_cv;
     if (ncv == 0) return;
     const int per = gram_per_chunk(ncv, nchunk);
     const int used = min(nchunk, (ncv + per - 1) / per);
     const int tot = r * (r + 1) / 2;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
-        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while ((i + 1) * (i + 2) / 2 <= e) ++i;
-        while (i * (i + 1) / 2 > e) --i;
-        int j = e - i * (i + 1) / 2;
-        double acc = d.Lam[(size_t)i * r + j];
-        for (int c = 0; c < used; ++c) acc += (double)part[((size_t)c * r + j) * r + i];
-        Apk[e] = acc;
-    }
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    const int g = blockIdx.y;
+    const int per_g = (used + GRAM_GROUPS - 1) / GRAM_GROUPS;
+    const int c0 = g * per_g, c1 = min(used, c0 + per_g);
+    int i, k;
+    pk_entry(e, r, i, k);
+    double acc = 0.0;
+#pragma unroll 4
+    for (int c = c0; c < c1; ++c) acc += part[((size_t)c * r + k) * r + i];
+    gred[(size_t)g * tot + e] = acc;
 }
 
-// One workgroup: Cholesky of the packed A (FP64, in LDS) and q = A^{-1} g by
-// two triangular solves.  Right-looking elimination without square roots
-// (A(i, j) -= A(i, k) A(j, k) / A(k, k) for k < j <= i, one barrier per
-// column; each thread owns fixed entries), then L(i, k) = A(i, k) / s_k with
-// s_k = sqrt(A(k, k)).  The solves run in wavefront 0 with the right-hand
-// sides in registers (lane l holds rows l, l + 64, l + 128).
-constexpr int CHOL_OWN = (MAX_R * (MAX_R + 1) / 2 + 1023) / 1024;
-__global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __restrict__ Apk,
-                                                   const double* __restrict__ g, const int* __restrict__ n_cv) {
+// packed lower triangle, row-major: A(i, j), j <= i, at i (i + 1) / 2 + j
+__device__ __forceinline__ int rm(int i, int j) { return i * (i + 1) / 2 + j; }
+__device__ __forceinline__ void tri_rc(int e, int& i, int& j) {
+    i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    while (i * (i + 1) / 2 > e) --i;
+    j = e - i * (i + 1) / 2;
+}
+
+// A = Lambda~ + the group sums, packed row-major (second reduction level).
+__global__ void __launch_bounds__(256) k_gram_final(Dev d, const double* __restrict__ gred,
+                                                    const int* __restrict__ n_cv, double* __restrict__ Arm) {
+    if (*n_cv == 0) return;
+    const int r = d.r;
+    const int tot = r * (r + 1) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    int i, k;
+    tri_rc(e, i, k);
+    const int ec = pk_off(k, r) + (i - k);   // the same entry in the column-major group sums
+    double s = d.Lam[(size_t)i * r + k];
+    for (int g = 0; g < GRAM_GROUPS; ++g) s += gred[(size_t)g * tot + ec];
+    Arm[e] = s;
+}
+
+// One workgroup: Cholesky of A (FP64, packed row-major in LDS); writes the
+// factor L (strictly lower part) and 1 / s_k (s_k = L(k, k)) for the
+// triangular solves.  Right-looking elimination without square roots: at
+// step k, A(i, j) -= A(i, k) A(j, k) / A(k, k) for k < j <= i.  The entries
+// of the trailing triangle (size m = r - k - 1) are dealt densely over the
+// threads: thread t takes the entries t + 1024 q of the row-major
+// enumeration of a triangle, whose (row, column) offsets it keeps in
+// registers (the first m (m + 1) / 2 of them form the triangle of size m).
+// One barrier per step.  Then L(i, k) = A(i, k) / s_k.
+constexpr int CHOL_T = (MAX_R * (MAX_R - 1) / 2 + 1023) / 1024;
+__global__ void __launch_bounds__(1024) k_chol_factor(Dev d, const double* __restrict__ Arm,
+                                                      const int* __restrict__ n_cv, double* __restrict__ Lout) {
+    if (*n_cv == 0) return;
     extern __shared__ double A[];
     const int r = d.r;
     const int tot = r * (r + 1) / 2;
-    double* sq = A + tot;   // r
-    const int tid = threadIdx.x, nt = 1024;
-    if (*n_cv == 0) {  // no contact vertex: A = Lambda~, use its inverse
-        for (int o = tid; o < r * 3; o += nt) {
-            int c = o / 3, k = o % 3;
-            double acc = 0.0;
-            for (int j = 0; j < r; ++j) acc += d.Ainv[(size_t)c * r + j] * g[j * 3 + k];
-            d.Qd[o] = acc;
-            d.Qf[o] = (float)acc;
-        }
-        return;
-    }
-    // entries owned by this thread: e = tid + 1024 q, as (row i, column j)
-    int own[CHOL_OWN];
+    double* rinv = A + tot;   // r
+    const int tid = threadIdx.x;
+    for (int e = tid; e < tot; e += 1024) A[e] = Arm[e];
+    int tdi[CHOL_T], tdj[CHOL_T];
 #pragma unroll
-    for (int q = 0; q < CHOL_OWN; ++q) {
-        const int e = tid + q * 1024;
-        own[q] = -1;
-        if (e < tot) {
-            A[e] = Apk[e];
-            int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-            while ((i + 1) * (i + 2) / 2 <= e) ++i;
-            while (i * (i + 1) / 2 > e) --i;
-            own[q] = (i << 16) | (e - i * (i + 1) / 2);
-        }
-    }
+    for (int t = 0; t < CHOL_T; ++t) tri_rc(tid + 1024 * t, tdi[t], tdj[t]);
     __syncthreads();
-    for (int k = 0; k < r; ++k) {
-        const double inv = 1.0 / A[k * (k + 1) / 2 + k];
+    for (int k = 0; k < r - 1; ++k) {
+        const int m = r - k - 1;
+        const int mt = m * (m + 1) / 2;
+        const double inv = 1.0 / A[rm(k, k)];
 #pragma unroll
-        for (int q = 0; q < CHOL_OWN; ++q) {
-            const int i = own[q] >> 16, j = own[q] & 0xffff;
-            if (own[q] >= 0 && j > k)
-                A[i * (i + 1) / 2 + j] -= A[i * (i + 1) / 2 + k] * A[j * (j + 1) / 2 + k] * inv;
+        for (int t = 0; t < CHOL_T; ++t) {
+            if (tid + 1024 * t >= mt) break;
+            const int i = k + 1 + tdi[t], j = k + 1 + tdj[t];
+            A[rm(i, j)] -= A[rm(i, k)] * A[rm(j, k)] * inv;
         }
         __syncthreads();
     }
-    for (int k = tid; k < r; k += nt) sq[k] = sqrt(A[k * (k + 1) / 2 + k]);
+    for (int k = tid; k < r; k += 1024) rinv[k] = 1.0 / sqrt(A[rm(k, k)]);
     __syncthreads();
-    if (tid >= 64) return;
-    constexpr int RPL = (MAX_R + 63) / 64;   // rows per lane
-    double y[RPL][3];
-    for (int q = 0; q < RPL; ++q) {
-        int i = tid + 64 * q;
-        for (int c = 0; c < 3; ++c) y[q][c] = i < r ? g[i * 3 + c] : 0.0;
+    for (int e = tid; e < tot; e += 1024) {
+        int i, k;
+        tri_rc(e, i, k);
+        Lout[e] = (i > k) ? A[e] * rinv[k] : 0.0;
     }
-    auto bcast = [](double v, int lane) {
+    for (int k = tid; k < r; k += 1024) Lout[tot + k] = rinv[k];
+}
+
+// q = A^{-1} g from the factor (three wavefronts, one per coordinate; lane
+// l holds rows l + 64 j).  Forward and backward substitution by 64-row
+// blocks: inside a block the lane's factor entries are held in registers
+// and row k's value is broadcast from its lane; the other blocks are
+// updated by a block product.  Without contact vertices A = Lambda~ and its
+// precomputed inverse is applied instead.
+__global__ void __launch_bounds__(192) k_chol_tri(Dev d, const double* __restrict__ Lg, const double* __restrict__ g,
+                                                  const int* __restrict__ n_cv) {
+    extern __shared__ double sl[];
+    const int r = d.r;
+    const int tot = r * (r + 1) / 2;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int c = wave;   // right-hand side of this wavefront
+    if (*n_cv == 0) {   // a wavefront per row of A^{-1}, lanes over its columns
+        for (int row = wave; row < r; row += 3) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int j = lane; j < r; j += 64) {
+                const double a = d.Ainv[(size_t)row * r + j];
+                a0 += a * g[j * 3];
+                a1 += a * g[j * 3 + 1];
+                a2 += a * g[j * 3 + 2];
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                a0 += __shfl_xor(a0, o);
+                a1 += __shfl_xor(a1, o);
+                a2 += __shfl_xor(a2, o);
+            }
+            if (lane == 0) {
+                d.Qd[row * 3] = a0;
+                d.Qd[row * 3 + 1] = a1;
+                d.Qd[row * 3 + 2] = a2;
+                d.Qf[row * 3] = (float)a0;
+                d.Qf[row * 3 + 1] = (float)a1;
+                d.Qf[row * 3 + 2] = (float)a2;
+            }
+        }
+        return;
+    }
+    for (int e = tid; e < tot + r; e += blockDim.x) sl[e] = Lg[e];
+    __syncthreads();
+    const double* L = sl;
+    const double* rinv = sl + tot;
+    constexpr int RPL = (MAX_R + 63) / 64;
+    const int nb = (r + 63) / 64;
+    double y[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int i = lane + 64 * q;
+        y[q] = i < r ? g[i * 3 + c] : 0.0;
+    }
+    auto bcast = [](double v, int src) {
         long long b = __double_as_longlong(v);
-        int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
-        int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+        int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
         return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
     };
-    // forward: L y' = g, L(i, k) = A(i, k) / s_k
-    for (int k = 0; k < r; ++k) {
-        const int ql = k >> 6, lk = k & 63;
-        double yk[3];
-        for (int c = 0; c < 3; ++c) {
-            double mine = 0.0;
-            for (int q = 0; q < RPL; ++q)
-                if (q == ql) mine = y[q][c];
-            yk[c] = bcast(mine, lk) / sq[k];
+    // forward: L y' = g
+#pragma unroll
+    for (int qb = 0; qb < RPL; ++qb) {
+        if (qb >= nb) break;
+        const int i = lane + 64 * qb;
+        double lr[64], rv[64];
+#pragma unroll
+        for (int kk = 0; kk < 64; ++kk) {
+            const int k = 64 * qb + kk;
+            lr[kk] = (k < i && i < r) ? L[rm(i, k)] : 0.0;
+            rv[kk] = k < r ? rinv[k] : 0.0;
         }
-        for (int q = 0; q < RPL; ++q) {
-            int i = tid + 64 * q;
-            if (i == k)
-                for (int c = 0; c < 3; ++c) y[q][c] = yk[c];
-            else if (i > k && i < r) {
-                double l = A[i * (i + 1) / 2 + k] / sq[k];
-                for (int c = 0; c < 3; ++c) y[q][c] -= l * yk[c];
+        double yb = y[qb];
+#pragma unroll
+        for (int kk = 0; kk < 64; ++kk) {
+            const double yk = bcast(yb, kk) * rv[kk];
+            yb = (lane == kk) ? yk : yb - lr[kk] * yk;
+        }
+        y[qb] = yb;
+#pragma unroll
+        for (int q = qb + 1; q < RPL; ++q) {
+            if (q >= nb) break;
+            const int i2 = lane + 64 * q;
+            double acc = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < 64; ++kk) {
+                const double yk = bcast(yb, kk);
+                if (i2 < r) acc += L[rm(i2, 64 * qb + kk)] * yk;
             }
+            y[q] -= acc;
         }
     }
-    // backward: L^T q = y', L^T(i, k) = L(k, i) = A(k, i) / s_i
-    for (int k = r - 1; k >= 0; --k) {
-        const int ql = k >> 6, lk = k & 63;
-        double qk[3];
-        for (int c = 0; c < 3; ++c) {
-            double mine = 0.0;
-            for (int q = 0; q < RPL; ++q)
-                if (q == ql) mine = y[q][c];
-            qk[c] = bcast(mine, lk) / sq[k];
-        }
-        for (int q = 0; q < RPL; ++q) {
-            int i = tid + 64 * q;
-            if (i == k)
-                for (int c = 0; c < 3; ++c) y[q][c] = qk[c];
-            else if (i < k) {
-                double l = A[k * (k + 1) / 2 + i] / sq[i];
-                for (int c = 0; c < 3; ++c) y[q][c] -= l * qk[c];
+    // backward: L^T q = y'
+#pragma unroll
+    for (int qb = RPL - 1; qb >= 0; --qb) {
+        if (qb >= nb) continue;
+        const int i = lane + 64 * qb;
+#pragma unroll
+        for (int q = qb + 1; q < RPL; ++q) {
+            if (q >= nb) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < 64; ++kk) {
+                const int k = 64 * q + kk;
+                const double xk = bcast(y[q], kk);
+                if (k < r && i < r) acc += L[rm(k, i)] * xk;
             }
+            y[qb] -= acc;
         }
+        double lr[64], rv[64];
+#pragma unroll
+        for (int kk = 0; kk < 64; ++kk) {
+            const int k = 64 * qb + kk;
+            lr[kk] = (i < k && k < r) ? L[rm(k, i)] : 0.0;
+            rv[kk] = k < r ? rinv[k] : 0.0;
+        }
+        double yb = y[qb];
+#pragma unroll
+        for (int kk = 63; kk >= 0; --kk) {
+            const double xk = bcast(yb, kk) * rv[kk];
+            yb = (lane == kk) ? xk : yb - lr[kk] * xk;
+        }
+        y[qb] = yb;
     }
+#pragma unroll
     for (int q = 0; q < RPL; ++q) {
-        int i = tid + 64 * q;
-        if (i < r)
-            for (int c = 0; c < 3; ++c) {
-                d.Qd[i * 3 + c] = y[q][c];
-                d.Qf[i * 3 + c] = (float)y[q][c];
-            }
+        const int i = lane + 64 * q;
+        if (i < r) {
+            d.Qd[i * 3 + c] = y[q];
+            d.Qf[i * 3 + c] = (float)y[q];
+        }
     }
 }
 
+
+__global__ void k_aos4(int n, const float* __restrict__ X, float4* X4) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        X4[v] = make_float4(X[v], X[n + v], X[2 * n + v], 0.f);
+}
 
 __global__ void k_copy_i32(int* __restrict__ dst, const int* __restrict__ src, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
@@ -1376,10 +1557,7 @@ __global__ void k_stage_counters(int* cnt, int first, unsigned long long* tmin_b
         cnt[0] = 0;
         cnt[1] = 0;
         cnt[10] = 0;
-        if (first) {
-            cnt[7] = 0;
-            tmin_bits[1] = (unsigned long long)__double_as_longlong(NOHIT);
-        }
+        if (first) tmin_bits[1] = (unsigned long long)__double_as_longlong(NOHIT);
         tmin_bits[0] = (unsigned long long)__double_as_longlong(NOHIT);
     }
 }
@@ -1438,16 +1616,21 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     // pair buffers only when self contact is on; obstacles need only per-vertex data
     int64_t pc = s.self_contact ? c.cap : 1;
     c.cap = pc;
+    // constraints (kept candidates, VT + EE) are a small fraction of the
+    // candidates: their lists get a sixth of the candidate capacity
+    const int64_t cc = s.self_contact ? std::max<int64_t>(4096, 2 * pc / 6) : 1;
+    c.ccap = cc;
     c.vbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? n : 1)));
     c.tbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? s.nt : 1)));
     c.ebox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? s.ne : 1)));
     const size_t mt = s.self_contact ? (size_t)std::max(s.nt, s.ne) : 1;
-    c.tcol = static_cast<int2*>(carve(sizeof(int2) * mt));
     c.bucket_cnt = I((size_t)P + 1);
     c.bucket_ptr = I((size_t)P + 1);
     c.rec = static_cast<BpRec*>(carve(sizeof(BpRec) * mt));
     c.qscratch = I((size_t)QK * (s.self_contact ? (size_t)std::max(n, s.ne) : 1));
     c.bpart = static_cast<float*>(carve(sizeof(float) * BP_PART * GRID_LOOP));
+    c.xm4 = static_cast<float4*>(carve(sizeof(float4) * (s.self_contact ? (size_t)n : 1)));
+    c.xp4 = static_cast<float4*>(carve(sizeof(float4) * (s.self_contact ? (size_t)n : 1)));
     c.grid = static_cast<BpGrid*>(carve(sizeof(BpGrid) * 2));
     c.vcount = I((size_t)n + 1);
     c.ecount = I((size_t)s.ne + 1);
@@ -1458,21 +1641,21 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.keep = I(std::max<int64_t>(2 * pc, (int64_t)std::max(n, s.ne) + 1));
     c.keep_ofs = I(2 * pc);
     c.cand_a = I(2 * pc);
-    c.cpair = static_cast<int2*>(carve(sizeof(int2) * 2 * pc));
-    c.cpair_prev = static_cast<int2*>(carve(sizeof(int2) * 2 * pc));
-    c.ca = I(2 * pc);
-    c.ca_prev = I(2 * pc);
-    c.clam = static_cast<double2*>(carve(sizeof(double2) * 2 * pc));
-    c.cnrm = static_cast<float4*>(carve(sizeof(float4) * 2 * pc));
-    c.slot = static_cast<float4*>(carve(sizeof(float4) * 8 * pc));
+    c.cpair = static_cast<int2*>(carve(sizeof(int2) * cc));
+    c.cpair_prev = static_cast<int2*>(carve(sizeof(int2) * cc));
+    c.ca = I(cc);
+    c.ca_prev = I(cc);
+    c.clam = static_cast<double2*>(carve(sizeof(double2) * cc));
+    c.cnrm = static_cast<float4*>(carve(sizeof(float4) * cc));
+    c.slot = static_cast<float4*>(carve(sizeof(float4) * 4 * cc));
     c.vslot_ptr = I((size_t)n + 1);
     c.vslot_fill = I((size_t)n + 1);
-    c.vslot = I(8 * pc);
+    c.vslot = I(4 * cc);
     c.cvlist = I((size_t)n + 1);
     c.cvflag = I((size_t)n + 1);
     c.cvofs = I((size_t)n + 1);
-    if (!c.vbox || !c.tbox || !c.ebox || !c.tcol || !c.bucket_cnt || !c.bucket_ptr || !c.rec || !c.qscratch ||
-        !c.bpart || !c.grid || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
+    if (!c.vbox || !c.tbox || !c.ebox || !c.bucket_cnt || !c.bucket_ptr || !c.rec || !c.qscratch ||
+        !c.bpart || !c.grid || !c.xm4 || !c.xp4 || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
         !c.toi_ee || !c.keep || !c.keep_ofs || !c.cand_a || !c.cpair || !c.cpair_prev || !c.ca ||
         !c.ca_prev || !c.clam || !c.cnrm || !c.slot || !c.vslot_ptr || !c.vslot_fill || !c.vslot || !c.cvlist ||
         !c.cvflag || !c.cvofs)
@@ -1493,7 +1676,9 @@ cloth_status contact_upload(Scene& s, ContactState& c) {
     double one = 1.0;
     HC(hipMemcpy(c.s_dev, &one, 8, hipMemcpyHostToDevice));
     HC(hipMemset(c.vslot_ptr, 0, sizeof(int) * (n + 1)));
-    HC(hipFuncSetAttribute((const void*)k_chol_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HC(hipFuncSetAttribute((const void*)k_chol_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)chol_lds_bytes(s.r)));
+    HC(hipFuncSetAttribute((const void*)k_chol_tri, hipFuncAttributeMaxDynamicSharedMemorySize,
                            (int)chol_lds_bytes(s.r)));
     return CLOTH_OK;
 }
@@ -1515,19 +1700,19 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
     const int P = c.hash_p;
     const int nbb = gblocks((int64_t)n + s.nt + s.ne);
     hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, xm, xp, (float)s.dhat, c.vbox, c.tbox, c.ebox,
-                       c.bpart);
-    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, (const float*)c.bpart, nbb, c.grid);
+                       c.bpart, c.xm4, c.xp4);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, (const float*)c.bpart, nbb, s.nt, s.ne, c.grid);
     for (int pass = 0; pass < 2; ++pass) {
         const bool vt = pass == 0;
         const int m = vt ? s.nt : s.ne;
         const float* tb = vt ? c.tbox : c.ebox;
         const BpGrid* g = c.grid + (vt ? 0 : 1);
         hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, c.bucket_cnt, 0, P + 1);
-        hipLaunchKernelGGL(k_cols, dim3(gblocks(m)), dim3(TPB), 0, st, m, tb, g, c.tcol, c.bucket_cnt, P, c.cnt + 7);
+        hipLaunchKernelGGL(k_cells, dim3(gblocks(m)), dim3(TPB), 0, st, m, tb, g, c.bucket_cnt, P, c.cnt + 7);
         HC(scan_exclusive(c.bucket_cnt, c.bucket_ptr, P + 1, nullptr, c.scan_tiles, nullptr, st));
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, c.bucket_cnt, c.bucket_ptr, P + 1);
-        hipLaunchKernelGGL(k_bucket_fill, dim3(gblocks(m)), dim3(TPB), 0, st, d, vt ? 1 : 0, m, tb,
-                           (const int2*)c.tcol, P, c.bucket_cnt, c.rec);
+        hipLaunchKernelGGL(k_bucket_fill, dim3(gblocks(m)), dim3(TPB), 0, st, d, vt ? 1 : 0, m, tb, g, P,
+                           c.bucket_cnt, c.rec);
         const int nq = vt ? n : s.ne;
         int* cnts = vt ? c.vcount : c.ecount;
         int2* outp = vt ? c.cand_vt : c.cand_ee;
@@ -1561,7 +1746,8 @@ static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm,
     int npart = 0;
     if (s.self_contact) {
         const int nb = gblocks(2 * c.cap);
-        hipLaunchKernelGGL(k_toi_merge, dim3(nb), dim3(TPB), 0, st, d, xm, xp, c.cand_vt, c.cand_ee, c.cnt, c.toi_vt,
+        hipLaunchKernelGGL(k_toi_merge, dim3(nb), dim3(TPB), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
+                           c.cand_vt, c.cand_ee, c.cnt, c.toi_vt,
                            c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tpart, 1);
         npart = nb;
     }
@@ -1576,7 +1762,7 @@ static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm,
         hipLaunchKernelGGL(k_sum2, dim3(1), dim3(64), 0, st, c.cnt);
         HC(scan_exclusive(c.keep, c.keep_ofs, (int)(2 * c.cap), c.cnt + 9, c.scan_tiles, nullptr, st));
         hipLaunchKernelGGL(k_compact, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, c.cand_vt, c.cand_ee, c.cnt, c.keep,
-                           c.keep_ofs, c.cand_a, c.cpair, c.ca);
+                           c.keep_ofs, c.cand_a, c.cpair, c.ca, c.ccap);
     }
     HC(launch_filter(d, xm, xp, c.s_dev, d.x, d.xm, st));
     HC(hipGetLastError());
@@ -1660,9 +1846,17 @@ cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st) {
         hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
                            d.gram_part);
     const int tot = s.r * (s.r + 1) / 2;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((tot + 255) / 256), dim3(256), 0, st, d, d.gram_part, c.gram_chunks,
-                       c.cnt + 6, d.Amat);
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, d.Amat, c.gvec, c.cnt + 6);
+    double* gred = d.Amat;
+    double* Arm = d.Amat + (size_t)GRAM_GROUPS * tot;
+    double* Lfac = Arm + tot;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((tot + 255) / 256, GRAM_GROUPS), dim3(256), 0, st, d, d.gram_part,
+                       c.gram_chunks, c.cnt + 6, gred);
+    hipLaunchKernelGGL(k_gram_final, dim3((tot + 255) / 256), dim3(256), 0, st, d, (const double*)gred, c.cnt + 6,
+                       Arm);
+    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm,
+                       c.cnt + 6, Lfac);
+    hipLaunchKernelGGL(k_chol_tri, dim3(1), dim3(192), chol_lds_bytes(s.r), st, d, (const double*)Lfac, c.gvec,
+                       c.cnt + 6);
     HC(hipGetLastError());
     return CLOTH_OK;
 }
@@ -1672,6 +1866,15 @@ cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st) {
     hipLaunchKernelGGL(k_partial_ccd, dim3(gblocks(2 * c.cap + s.nv)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca,
                        c.clam, s.amax, d.xk);
     HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
+cloth_status contact_reset(Scene& s, ContactState& c, hipStream_t st) {
+    (void)s;
+    if (c.cnt) {
+        HC(hipMemsetAsync(c.cnt + 7, 0, sizeof(int), st));
+        HC(hipMemsetAsync(c.cnt + 12, 0, sizeof(int), st));
+    }
     return CLOTH_OK;
 }
 
@@ -1687,7 +1890,20 @@ cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step
     out->min_toi = t;
     out->n_candidates = (int64_t)h[0] + h[1];
     out->n_constraints = (int64_t)h[2] + h[3] + h[10];
-    if (h[7]) return set_error(CLOTH_E_CAPACITY, "pair capacity exceeded");
+    out->peak_candidates = h[12];
+    HC(hipMemsetAsync(c.cnt + 12, 0, sizeof(int), st));
+    if (h[7]) {
+        // sticky since the last read: clear it, then report what overflowed
+        HC(hipMemsetAsync(c.cnt + 7, 0, sizeof(int), st));
+        HC(hipStreamSynchronize(st));
+        std::string why;
+        if (h[7] & 1) why += " a query exceeded its work bound (cells, records or pairs);";
+        if (h[7] & 2) why += " a box could not be placed on the grid;";
+        if (h[7] & 4) why += " a candidate list exceeded the pair capacity (" + std::to_string(c.cap) + ");";
+        if (h[7] & 8) why += " the constraint set exceeded its capacity (" + std::to_string(c.ccap) + ");";
+        return set_error(CLOTH_E_CAPACITY, "broad phase overflow since the last check:" + why +
+                                               " last lists VT " + std::to_string(h[0]) + ", EE " + std::to_string(h[1]));
+    }
     (void)s;
     return CLOTH_OK;
 }
@@ -1712,12 +1928,14 @@ cloth_status contact_stage_broad_phase(Scene& s, ContactState& c, const float* x
     to_soa(xp, t, s.nv);
     HC(hipMemcpy(s.d.xt, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
     hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, nullptr, c.cnt, 1, c.tmin_bits);
+    HC(hipMemset(c.cnt + 7, 0, sizeof(int)));
     cloth_status rc = broad_phase(s, c, s.d.xm, s.d.xt, nullptr);
     if (rc != CLOTH_OK) return rc;
     int h[16];
     HC(hipMemcpy(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost));
     *n_vt = h[0];
     *n_ee = h[1];
+    if (h[7]) HC(hipMemset(c.cnt + 7, 0, sizeof(int)));
     if (h[7] || h[0] > cap || h[1] > cap) return set_error(CLOTH_E_CAPACITY, "pair list does not fit");
     if (vt && h[0]) HC(hipMemcpy(vt, c.cand_vt, sizeof(int2) * h[0], hipMemcpyDeviceToHost));
     if (ee && h[1]) HC(hipMemcpy(ee, c.cand_ee, sizeof(int2) * h[1], hipMemcpyDeviceToHost));
@@ -1726,6 +1944,7 @@ cloth_status contact_stage_broad_phase(Scene& s, ContactState& c, const float* x
 
 cloth_status contact_stage_toi(Scene& s, ContactState& c, const float* xm, const float* xp, int64_t n_vt,
                                const int32_t* vt, int64_t n_ee, const int32_t* ee, double* toi_vt, double* toi_ee) {
+    if (!s.self_contact) return set_error(CLOTH_E_INVALID, "pair TOI needs a scene with self contact");
     if (n_vt > c.cap || n_ee > c.cap) return set_error(CLOTH_E_CAPACITY, "pair list exceeds capacity");
     std::vector<float> t;
     to_soa(xm, t, s.nv);
@@ -1736,8 +1955,11 @@ cloth_status contact_stage_toi(Scene& s, ContactState& c, const float* xm, const
     if (n_ee) HC(hipMemcpy(c.cand_ee, ee, sizeof(int2) * n_ee, hipMemcpyHostToDevice));
     int h[2] = {(int)n_vt, (int)n_ee};
     HC(hipMemcpy(c.cnt, h, sizeof(h), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_toi_merge, dim3(gblocks(n_vt + n_ee)), dim3(TPB), 0, nullptr, s.d, s.d.xm, s.d.xt, c.cand_vt,
-                       c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tpart, 0);
+    hipLaunchKernelGGL(k_aos4, dim3(gblocks(s.nv)), dim3(TPB), 0, nullptr, s.nv, (const float*)s.d.xm, c.xm4);
+    hipLaunchKernelGGL(k_aos4, dim3(gblocks(s.nv)), dim3(TPB), 0, nullptr, s.nv, (const float*)s.d.xt, c.xp4);
+    hipLaunchKernelGGL(k_toi_merge, dim3(gblocks(n_vt + n_ee)), dim3(TPB), 0, nullptr, s.d, (const float4*)c.xm4,
+                       (const float4*)c.xp4, c.cand_vt, c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.cpair_prev, c.ca_prev,
+                       c.keep, c.cand_a, c.tpart, 0);
     HC(hipGetLastError());
     HC(hipDeviceSynchronize());
     if (n_vt) HC(hipMemcpy(toi_vt, c.toi_vt, sizeof(double) * n_vt, hipMemcpyDeviceToHost));
@@ -1752,7 +1974,7 @@ cloth_status contact_load_constraints(Scene& s, ContactState& c, int64_t n_vt, c
         c.active = false;
         return CLOTH_OK;
     }
-    if (n_vt + n_ee > 2 * c.cap) return set_error(CLOTH_E_CAPACITY, "constraint list exceeds capacity");
+    if (n_vt + n_ee > c.ccap) return set_error(CLOTH_E_CAPACITY, "constraint list exceeds capacity");
     if ((n_vt || n_ee) && !s.self_contact) return set_error(CLOTH_E_INVALID, "pair constraints without self contact");
     std::vector<int2> pr(n_vt + n_ee);
     std::vector<int> a(n_vt + n_ee);
@@ -1800,12 +2022,16 @@ cloth_status contact_stage_outer(Scene& s, ContactState& c, const float* xm, con
     HC(hipMemcpy(s.d.xm, t.data(), 12 * (size_t)n, hipMemcpyHostToDevice));
     to_soa(xp, t, n);
     HC(hipMemcpy(s.d.xt, t.data(), 12 * (size_t)n, hipMemcpyHostToDevice));
+    HC(hipMemset(c.cnt + 7, 0, sizeof(int)));
     cloth_status rc = outer_stage(s, c, s.d.xm, s.d.xt, first != 0, true, nullptr);
     if (rc != CLOTH_OK) return rc;
     HC(hipDeviceSynchronize());
     int h[16];
     HC(hipMemcpy(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost));
-    if (h[7]) return set_error(CLOTH_E_CAPACITY, "pair capacity exceeded");
+    if (h[7]) {
+        HC(hipMemset(c.cnt + 7, 0, sizeof(int)));
+        return set_error(CLOTH_E_CAPACITY, "pair capacity exceeded");
+    }
     if (s_out) HC(hipMemcpy(s_out, c.s_dev, 8, hipMemcpyDeviceToHost));
     if (x_out) {
         HC(hipMemcpy(t.data(), s.d.x, 12 * (size_t)n, hipMemcpyDeviceToHost));

@@ -240,7 +240,7 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     s.delay = prm->cheb_delay;
     s.prec = prm->precision;
     s.self_contact = prm->self_contact;
-    s.pair_cap = prm->pair_capacity > 0 ? prm->pair_capacity : (int64_t)48 * nv;
+    s.pair_cap = prm->pair_capacity > 0 ? prm->pair_capacity : (int64_t)128 * nv;
     return "";
 }
 

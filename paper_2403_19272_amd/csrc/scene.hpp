@@ -15,9 +15,11 @@ constexpr int TPB = 256;          // threads per block of the vertex/pair kernel
 constexpr int MAX_OBST = 4;
 constexpr double NO_HIT = 2.0;
 constexpr int MAX_R = 192;        // widest basis: the packed FP64 Cholesky factor lives in LDS
-constexpr int GRAM_CHUNKS = 128;  // contact-vertex chunks of the Gram partials
+constexpr int GRAM_CHUNKS = 512;  // contact-vertex chunks of the Gram partials
+constexpr int GRAM_GROUPS_MAX = 16;  // chunk groups of the first FP64 reduction level
 
-// LDS of the contact-solve Cholesky: packed lower triangle + r pivots roots
+// LDS of the contact-solve Cholesky and triangular solves: packed lower
+// triangle + r inverse pivot roots
 inline size_t chol_lds_bytes(int r) { return sizeof(double) * ((size_t)r * (r + 1) / 2 + r); }
 
 // Triangle record for the local step: corner ids, PD weight w = k_s * area,
@@ -61,8 +63,9 @@ struct Dev {
     double* Qd;               // r * 3
     double* Ainv;             // r * r (no-contact inverse of Lambda~)
     double* Lam;              // r * r
-    double* Amat;             // r (r + 1) / 2: packed Lambda~ + U^T W U (contact)
-    float* gram_part;         // GRAM_CHUNKS * r * r Gram partials
+    double* Amat;             // contact reduced matrix work: FP64 group sums of U^T W U
+                              // (GRAM_GROUPS_MAX packed triangles), A (one), factor + 1/s_k
+    double* gram_part;        // GRAM_CHUNKS * r * r Gram partials (FP64)
     unsigned long long* dxbits;  // per-iteration max |dx| as double bits
     double* gvec;             // r * 3: g = U^T r0 (FP64)
     // contact (read when the contact flag is set)
