@@ -62,17 +62,18 @@ def kernel_bytes(name, sc, nnz, ubytes, contact):
     if name == "local_residual":
         b = 12 * N + 4 * N                      # z, m/h^2
         b += 4 * (N + 1) + 12 * T + 32 * T      # incidence, triangle records
-        b += 12 * N + sell + N                  # x (gathers as hits), H off-diagonal, pin flags
+        b += 12 * N + 16 * N + sell + N         # x (SoA) and its AoS gather copy, H off-diagonal, pin flags
         b += N * r * ubytes                     # U rows for U^T r0
         b += 12 * N + nblk * r * 3 * 4          # r0 out, block partials out
         if contact:
             b += 4 * (N + 1) + 4 * N * len(sc.obstacles) + 4 * N   # slot lists, obstacle spans, W out
         return b
     if name == "expand":
-        return N * r * ubytes + 12 * N          # U rows, delta out
+        return N * r * ubytes + 16 * N          # U rows, delta out (AoS)
     if name == "jacobi_cheb":
-        b = 12 * N + 12 * N + 12 * N + N        # delta (gathers as hits), x^k, x^{k-1}, pin flags
+        b = 16 * N + 12 * N + 12 * N + N        # delta (AoS, gathers as hits), x^k, x^{k-1}, pin flags
         b += sell + 4 * N + 12 * N + 12 * N     # H off-diagonal, diag(H), r0, x^{k+1} out
+        b += 16 * N                             # x^{k+1} AoS gather copy out
         if contact:
             b += 4 * N                          # W
         return b

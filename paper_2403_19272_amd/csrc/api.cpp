@@ -144,6 +144,8 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
         *pv = cv<float>(carve_fn, 3 * (size_t)n);
         if (!*pv) return fail(CLOTH_E_OOM, "arena exhausted (state)");
     }
+    d.x4 = cv<float4>(carve_fn, n);
+    d.d4 = cv<float4>(carve_fn, n);
     d.W = cv<float>(carve_fn, n);
     d.mh2 = cv<float>(carve_fn, n);
     d.diag = cv<float>(carve_fn, n);
@@ -171,7 +173,7 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     d.gram_part = cv<double>(carve_fn, (size_t)GRAM_CHUNKS * s.r * s.r);
     d.dxbits = cv<unsigned long long>(carve_fn, 4096);
     s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);
-    if (!d.W || !d.mh2 || !d.diag || !s.d_pinned || !s.d_rowptr || !s.d_col || !s.d_val || !s.d_tri ||
+    if (!d.x4 || !d.d4 || !d.W || !d.mh2 || !d.diag || !s.d_pinned || !s.d_rowptr || !s.d_col || !s.d_val || !s.d_tri ||
         !s.d_sell_ptr || !s.d_sell_col || !s.d_sell_val ||
         !s.d_inc_ptr || !s.d_inc || !s.d_edges || !s.d_U || !d.gpart || !d.Qf || !d.Qd || !d.Ainv ||
         !d.Lam || !d.Amat || !d.gram_part || !d.dxbits || !s.d_rfdx)
@@ -274,6 +276,7 @@ static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStrea
     ContactState& c = sc->c;
     Dev& d = s.d;
     int has_contact = (c.active && !linear) ? 1 : 0;
+    if (k == 0 || !s.x4_valid) TIMED(K_MISC, launch_aos4(d.xk, d.x4, s.nv, st));
     if (has_contact) TIMED(K_TARGETS, contact_prepare_iteration(s, c, force_k, st));
     TIMED(K_LOCAL, launch_local_residual(d, s.prec, has_contact | (linear ? 2 : 0) | (force_k ? 4 : 0), st));
     TIMED(K_REDUCE, launch_reduce_solve(d, s.nblk, has_contact, c.gpart2, st));
@@ -285,6 +288,7 @@ static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStrea
     d.xkm1 = d.xk;
     d.xk = d.xk1;
     d.xk1 = t;
+    s.x4_valid = true;   // the sweep wrote x^{k+1} to d.x4 as well
     return CLOTH_OK;
 }
 
@@ -295,12 +299,14 @@ static cloth_status modal_iteration(cloth_scene_s* sc, hipStream_t st) {
     Scene& s = sc->s;
     ContactState& c = sc->c;
     Dev& d = s.d;
+    TIMED(K_MISC, launch_aos4(d.xk, d.x4, s.nv, st));
     TIMED(K_LOCAL, launch_local_residual(d, s.prec, 0, st));
     TIMED(K_REDUCE, launch_reduce_solve(d, s.nblk, 0, c.gpart2, st));
     TIMED(K_EXPAND, launch_expand(d, s.prec, 1, st));
     float* t = d.xk;
     d.xk = d.xt;
     d.xt = t;
+    s.x4_valid = false;
     return CLOTH_OK;
 }
 
@@ -985,6 +991,7 @@ cloth_status cloth_stage_load_block(cloth_scene sc, const float* xm, const float
     HIPCHECK(hipMemcpy(d.x, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
     aos_to_soa(xk, t, s.nv);
     HIPCHECK(hipMemcpy(d.xk, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
+    s.x4_valid = false;
     aos_to_soa(xkm1, t, s.nv);
     HIPCHECK(hipMemcpy(d.xkm1, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
     aos_to_soa(z, t, s.nv);

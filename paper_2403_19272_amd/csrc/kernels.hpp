@@ -16,6 +16,8 @@ void clear_kernel_events();
 // ---- PD iteration (pd_kernels.hip)
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);
 hipError_t launch_copy3(float* dst, const float* src, int nv, hipStream_t st);
+// AoS float4 copy of an SoA position vector (gather copy of x^k)
+hipError_t launch_aos4(const float* src, float4* dst, int nv, hipStream_t st);
 hipError_t launch_predict(const Dev& d, float h, float gx, float gy, float gz, const float* rfdx, hipStream_t st);
 hipError_t launch_rf_finish(const Dev& d, const float* xrf, const float* x, float* rfdx,
                             const unsigned long long* t_last_bits, double rf_toi, hipStream_t st);
@@ -28,7 +30,7 @@ hipError_t launch_local_residual(const Dev& d, int prec, int flags, hipStream_t 
 // sum of U^T r0 partials -> d.gvec; without contact also Q = A^{-1} g
 hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpart2,
                                hipStream_t st);
-// delta = U q into d.xt (add: d.xt = x^k + U q)
+// delta = U q into d.d4 (AoS); add: d.xt = x^k + U q (SoA)
 hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st);
 hipError_t launch_jacobi_cheb(const Dev& d, float omega, float gamma, int has_contact,
                               unsigned long long* dx_slot, hipStream_t st);

@@ -47,6 +47,45 @@ __device__ __forceinline__ void load8<uint16_t>(const uint16_t* __restrict__ U, 
     u[6] = __uint_as_float(a.w << 16); u[7] = __uint_as_float(a.w & 0xffff0000u);
 }
 
+// Eight consecutive basis entries kept in their stored form (16 bytes of
+// BF16 or 32 bytes of FP32), so that many rows can be in flight at once.
+template <typename UT>
+struct RowChunk;
+
+template <>
+struct RowChunk<uint16_t> {
+    uint4 a;
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ U, size_t off) {
+        a = *reinterpret_cast<const uint4*>(U + off);
+    }
+    __device__ __forceinline__ void zero() { a = make_uint4(0u, 0u, 0u, 0u); }
+    __device__ __forceinline__ void unpack(float u[8]) const {
+        u[0] = __uint_as_float(a.x << 16); u[1] = __uint_as_float(a.x & 0xffff0000u);
+        u[2] = __uint_as_float(a.y << 16); u[3] = __uint_as_float(a.y & 0xffff0000u);
+        u[4] = __uint_as_float(a.z << 16); u[5] = __uint_as_float(a.z & 0xffff0000u);
+        u[6] = __uint_as_float(a.w << 16); u[7] = __uint_as_float(a.w & 0xffff0000u);
+    }
+};
+
+template <>
+struct RowChunk<float> {
+    float4 a, b;
+    __device__ __forceinline__ void load(const float* __restrict__ U, size_t off) {
+        const float4* p = reinterpret_cast<const float4*>(U + off);
+        a = p[0];
+        b = p[1];
+    }
+    __device__ __forceinline__ void zero() { a = b = make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ __forceinline__ void unpack(float u[8]) const {
+        u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
+        u[4] = b.x; u[5] = b.y; u[6] = b.z; u[7] = b.w;
+    }
+};
+
+// rows of U a lane keeps in flight (64 VGPRs of stored data)
+template <typename UT>
+constexpr int kRowsInFlight = sizeof(UT) == 2 ? 16 : 8;
+
 // Closest 3x2 matrix with orthonormal columns: T = F (F^T F)^{-1/2}, with
 // the 2x2 square root sqrt(S) = (S + sqrt(det S) I) / sqrt(tr S + 2 sqrt(det S)).
 // F and T are row-major 3x2 (F[2*d + i]).
@@ -97,6 +136,11 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
 __global__ void k_copy3(float* __restrict__ dst, const float* __restrict__ src, int n3) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n3) dst[i] = src[i];
+}
+
+__global__ void k_aos4(const float* __restrict__ src, float4* __restrict__ dst, int n) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) dst[v] = make_float4(src[v], src[n + v], src[2 * n + v], 0.f);
 }
 
 // z = x* + h v* + h^2 g + 2 dx_rf (free rows), z = x* at pinned rows; x*
@@ -164,9 +208,27 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int v = tile * TPB + tid;
     const bool contact = flags & 1, linear = flags & 2, force_k = flags & 4;
+    // this thread's share of the block's U rows for U^T r0 (column group cg
+    // of 8, vertices vg, vg + nvg, ...): the first PF rows are requested
+    // now, so that they stream in while the local step runs
+    const int r = d.r;
+    const int ncg = r >> 3;
+    const int nvg = TPB / ncg;
+    const int cg = tid % ncg, vg = tid / ncg;
+    const UT* U = static_cast<const UT*>(d.U);
+    constexpr int PF = kRowsInFlight<UT>;
+    RowChunk<UT> pre[PF];
+#pragma unroll
+    for (int b = 0; b < PF; ++b) {
+        const int vv = vg + b * nvg;
+        const int vtx = tile * TPB + vv;
+        if (vg < nvg && vv < TPB && vtx < n) pre[b].load(U, (size_t)vtx * r + cg * 8);
+        else pre[b].zero();
+    }
     float r0[3] = {0.f, 0.f, 0.f};
     if (v < n) {
         const float* X = d.xk;
+        const float4* X4 = d.x4;   // the same positions, AoS, for the gathers
         const float x0 = X[v], x1 = X[n + v], x2 = X[2 * n + v];
         // right-hand side minus the diagonal terms, accumulated as differences
         // (b - (M/h^2 + W) x) so that no large, nearly cancelling products
@@ -182,9 +244,9 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
                 int code = d.inc[i];
                 int t = code >> 2, c = code & 3;
                 TriRec tr = d.tri[t];
-                float p0[3] = {X[tr.v0], X[n + tr.v0], X[2 * n + tr.v0]};
-                float e1[3] = {X[tr.v1] - p0[0], X[n + tr.v1] - p0[1], X[2 * n + tr.v1] - p0[2]};
-                float e2[3] = {X[tr.v2] - p0[0], X[n + tr.v2] - p0[1], X[2 * n + tr.v2] - p0[2]};
+                const float4 q0 = X4[tr.v0], q1 = X4[tr.v1], q2 = X4[tr.v2];
+                float e1[3] = {q1.x - q0.x, q1.y - q0.y, q1.z - q0.z};
+                float e2[3] = {q2.x - q0.x, q2.y - q0.y, q2.z - q0.z};
                 float F[6], T[6];
                 for (int q = 0; q < 3; ++q) {
                     F[2 * q] = e1[q] * tr.gj0 + e2[q] * tr.gk0;
@@ -253,22 +315,22 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
             float ax = 0.f, ay = 0.f, az = 0.f;
             if (!linear) {
                 for (int j = p0 + lane; j < p1; j += 64) {
-                    int c = d.sell_col[j];
-                    float a = d.sell_val[j];
-                    ax += a * (X[c] - x0);
-                    ay += a * (X[n + c] - x1);
-                    az += a * (X[2 * n + c] - x2);
+                    const float a = d.sell_val[j];
+                    const float4 xc = X4[d.sell_col[j]];
+                    ax += a * (xc.x - x0);
+                    ay += a * (xc.y - x1);
+                    az += a * (xc.z - x2);
                 }
                 r0[0] = bx - ax;
                 r0[1] = by - ay;
                 r0[2] = bz - az;
             } else {
                 for (int j = p0 + lane; j < p1; j += 64) {
-                    int c = d.sell_col[j];
-                    float a = d.sell_val[j];
-                    ax += a * X[c];
-                    ay += a * X[n + c];
-                    az += a * X[2 * n + c];
+                    const float a = d.sell_val[j];
+                    const float4 xc = X4[d.sell_col[j]];
+                    ax += a * xc.x;
+                    ay += a * xc.y;
+                    az += a * xc.z;
                 }
                 const float dv = d.diag[v] + Wv;
                 r0[0] = -ax - dv * x0;
@@ -286,16 +348,24 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     sr[2][tid] = r0[2];
     __syncthreads();
     // partial U^T r0 over this block's vertices: thread = (column group of 8, vertex group)
-    const int r = d.r;
-    const int ncg = r >> 3;
-    const int nvg = TPB / ncg;
-    const int cg = tid % ncg, vg = tid / ncg;
     float acc[8][3];
     for (int i = 0; i < 8; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.f;
-    const UT* U = static_cast<const UT*>(d.U);
     if (vg < nvg) {
-        // vertices in batches of 4: the batch's loads are issued together
-        for (int vv0 = vg; vv0 < TPB; vv0 += 4 * nvg) {
+#pragma unroll
+        for (int b = 0; b < PF; ++b) {
+            const int vv = vg + b * nvg;
+            if (vv >= TPB) break;
+            float u[8];
+            pre[b].unpack(u);
+            float a0 = sr[0][vv], a1 = sr[1][vv], a2 = sr[2][vv];
+            for (int i = 0; i < 8; ++i) {
+                acc[i][0] += u[i] * a0;
+                acc[i][1] += u[i] * a1;
+                acc[i][2] += u[i] * a2;
+            }
+        }
+        // the remaining rows (r > 128 BF16 / 64 FP32) in batches of 4
+        for (int vv0 = vg + PF * nvg; vv0 < TPB; vv0 += 4 * nvg) {
             float u[4][8];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
@@ -384,7 +454,8 @@ __global__ void __launch_bounds__(1024) k_solve_reduced(Dev d, const double* __r
     }
 }
 
-// delta = U q into d.xt (add = 1: d.xt = x^k + U q).
+// delta = U q into d.d4 (AoS, gathered by the Jacobi sweep); add = 1:
+// d.xt = x^k + U q (SoA).
 // G lanes share one row of U (G = r/8 rounded up to a power of two), each
 // lane holding the q entries of its 8 columns in registers, so that a
 // wavefront reads 64/G whole rows per load: contiguous runs of U instead of
@@ -406,29 +477,29 @@ __global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
     const int n = d.nv;
     const int base = xcd_tile(blockIdx.x, gridDim.x) * TPB + wave * 64;
     const UT* U = static_cast<const UT*>(d.U);
-    // rounds in batches of EXP_BATCH: all loads of a batch are issued before
-    // their products, so that each lane keeps several rows in flight
-    constexpr int EXP_BATCH = 4;
-    for (int rnd0 = 0; rnd0 < G; rnd0 += EXP_BATCH) {
-        float u[EXP_BATCH][8];
+    // rounds in batches of PF: all loads of a batch (one row per round, PF
+    // rounds: 16 rows of BF16 or 8 of FP32 per lane) are issued before their
+    // products, so that each lane keeps that many rows in flight
+    constexpr int PF = kRowsInFlight<UT>;
+    for (int rnd0 = 0; rnd0 < G; rnd0 += PF) {
+        RowChunk<UT> raw[PF];
 #pragma unroll
-        for (int b = 0; b < EXP_BATCH; ++b) {
+        for (int b = 0; b < PF; ++b) {
             const int v = base + (rnd0 + b) * per + vs;
-            if (rnd0 + b < G && active && v < n) {
-                load8<UT>(U, (size_t)v * r + cg * 8, u[b]);
-            } else {
-                for (int i = 0; i < 8; ++i) u[b][i] = 0.f;
-            }
+            if (rnd0 + b < G && active && v < n) raw[b].load(U, (size_t)v * r + cg * 8);
+            else raw[b].zero();
         }
 #pragma unroll
-        for (int b = 0; b < EXP_BATCH; ++b) {
+        for (int b = 0; b < PF; ++b) {
             if (rnd0 + b >= G) break;
             const int lv = (rnd0 + b) * per + vs;
+            float u[8];
+            raw[b].unpack(u);
             float a0 = 0.f, a1 = 0.f, a2 = 0.f;
             for (int i = 0; i < 8; ++i) {
-                a0 += u[b][i] * q[i][0];
-                a1 += u[b][i] * q[i][1];
-                a2 += u[b][i] * q[i][2];
+                a0 += u[i] * q[i][0];
+                a1 += u[i] * q[i][1];
+                a2 += u[i] * q[i][2];
             }
             for (int o = 1; o < G; o <<= 1) {
                 a0 += __shfl_xor(a0, o);
@@ -450,9 +521,7 @@ __global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
         d.xt[n + v] = d.xk[n + v] + res[1][tid];
         d.xt[2 * n + v] = d.xk[2 * n + v] + res[2][tid];
     } else {
-        d.xt[v] = res[0][tid];
-        d.xt[n + v] = res[1][tid];
-        d.xt[2 * n + v] = res[2][tid];
+        d.d4[v] = make_float4(res[0][tid], res[1][tid], res[2][tid], 0.f);
     }
 }
 
@@ -460,7 +529,8 @@ __global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
 //   r1 = r0 - (H + diag W) delta   (= b - (H + diag W) x~, by linearity),
 //   x^ - x^k = delta + r1 / (diag H + W) = (r0 - offdiag(H) delta) / (diag H + W),
 //   x^{k+1} = x^{k-1} + omega (gamma (x^ - x^k) + x^k - x^{k-1}).
-// d.b holds r0 and d.xt holds delta = U q.
+// d.b holds r0 and d.d4 holds delta = U q; x^{k+1} is written SoA to d.xk1
+// and AoS to d.x4 (the next local step's gathers).
 __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float gamma, int has_contact,
                                                     unsigned long long* dx_slot) {
     __shared__ double wmax[TPB / 64];
@@ -468,7 +538,7 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
     const int v = xcd_tile(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     double dxm = 0.0;
     if (v < n) {
-        const float* DL = d.xt;
+        const float4* DL = d.d4;
         float xk[3] = {d.xk[v], d.xk[n + v], d.xk[2 * n + v]};
         float xkm1[3] = {d.xkm1[v], d.xkm1[n + v], d.xkm1[2 * n + v]};
         float dh[3] = {0.f, 0.f, 0.f};
@@ -477,11 +547,11 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
             const int lane = v & 63;
             const int p1 = d.sell_ptr[(v >> 6) + 1];
             for (int j = d.sell_ptr[v >> 6] + lane; j < p1; j += 64) {
-                int c = d.sell_col[j];
-                float a = d.sell_val[j];
-                ax += a * DL[c];
-                ay += a * DL[n + c];
-                az += a * DL[2 * n + c];
+                const float a = d.sell_val[j];
+                const float4 dc = DL[d.sell_col[j]];
+                ax += a * dc.x;
+                ay += a * dc.y;
+                az += a * dc.z;
             }
             float Wv = has_contact ? d.W[v] : 0.f;
             float inv = 1.0f / (d.diag[v] + Wv);
@@ -492,12 +562,14 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
             dh[2] = (d.b[2 * n + v] - az) * inv;
         }
         double s2 = 0.0;
+        float nx[3];
         for (int c = 0; c < 3; ++c) {
-            float nx = xkm1[c] + omega * (gamma * dh[c] + (xk[c] - xkm1[c]));
-            d.xk1[c * n + v] = nx;
-            double dd = (double)nx - (double)xk[c];
+            nx[c] = xkm1[c] + omega * (gamma * dh[c] + (xk[c] - xkm1[c]));
+            d.xk1[c * n + v] = nx[c];
+            double dd = (double)nx[c] - (double)xk[c];
             s2 += dd * dd;
         }
+        d.x4[v] = make_float4(nx[0], nx[1], nx[2], 0.f);   // gather copy for the next local step
         dxm = sqrt(s2);
     }
     dxm = warp_max(dxm);
@@ -543,6 +615,11 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, h
 
 hipError_t launch_copy3(float* dst, const float* src, int nv, hipStream_t st) {
     hipLaunchKernelGGL(k_copy3, dim3(blocks_for(3 * nv)), dim3(TPB), 0, st, dst, src, 3 * nv);
+    return hipGetLastError();
+}
+
+hipError_t launch_aos4(const float* src, float4* dst, int nv, hipStream_t st) {
+    hipLaunchKernelGGL(k_aos4, dim3(blocks_for(nv)), dim3(TPB), 0, st, src, dst, nv);
     return hipGetLastError();
 }
 

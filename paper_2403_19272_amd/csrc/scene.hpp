@@ -43,6 +43,8 @@ struct Dev {
     int nv, nt, ne, r;
     // SoA 3*nv arrays: [0,nv) x, [nv,2nv) y, [2nv,3nv) z
     float *x, *v, *xstar, *z, *xm, *xk, *xkm1, *xk1, *xt, *b, *WY;
+    float4* x4;               // nv: AoS copy of x^k for the neighbour gathers
+    float4* d4;               // nv: AoS delta = U q (gathered by the Jacobi sweep)
     float* W;                 // nv: diagonal collision weights
     float* mh2;               // nv: m / h^2
     float* diag;              // nv: diag(H)
@@ -89,6 +91,7 @@ struct Scene {
     double rho = 0, gamma = 0;
     int64_t pair_cap = 0;
     bool basis_set = false;
+    bool x4_valid = false;        // d.x4 holds x^k (written by the Jacobi sweep)
     int warm_iters = 0, rf_iters = 0;   // modal warm start / residual forwarding iterations
     double rf_toi = 0.5;                // forward when the exiting t_TOI is below this
 
