@@ -101,9 +101,12 @@ def pmc_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(sc, iters):
+def cpu_baseline(sc, iters, rho, gamma):
     """The FP64 oracle as it stands, on one step of the same workload cut to
-    one outer block of `iters` inner iterations (with its two CCD stages)."""
+    one outer block of `iters` inner iterations (with its two CCD stages),
+    with the Chebyshev rho and damping gamma the device estimated for this
+    workload (other values can make the damped sweep diverge, and the
+    blown-up positions then swamp the CCD stage with candidate pairs)."""
     from threadpoolctl import threadpool_info
 
     from oracle import model as M
@@ -115,7 +118,7 @@ def cpu_baseline(sc, iters):
     # basis of the workload's width stands in for the eigenvectors here
     U, _ = np.linalg.qr(rng.standard_normal((sc.nv, sc.r)))
     Us = M.stored_basis(U, sc.precision)
-    p = S.Params(iters_outer=1, iters_inner=iters, cheb_rho=0.95, cheb_gamma=0.9, cheb_delay=3,
+    p = S.Params(iters_outer=1, iters_inner=iters, cheb_rho=rho, cheb_gamma=gamma, cheb_delay=3,
                  d_hat=sc.d_hat, self_contact=sc.self_contact)
     obs = [S.Obst(o.kind, np.array(o.center, float), o.radius, np.array(o.axis, float))
            for o in sc.obstacles]
@@ -253,7 +256,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(sc, args.cpu_iters)
+            cpu = cpu_baseline(sc, args.cpu_iters, st["cheb_rho"], st["cheb_gamma"])
         except Exception as e:  # reported, never fatal for the GPU figure
             log(f"cpu baseline failed: {e!r}")
     out = {

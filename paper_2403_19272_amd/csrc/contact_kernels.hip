@@ -536,6 +536,14 @@ __device__ __forceinline__ unsigned hash3(int grid, int x, int y, int z) {
     return ((unsigned)x * 73856093u) ^ ((unsigned)y * 19349663u) ^ ((unsigned)z * 83492791u) ^
            (grid ? 0x9E3779B9u : 0u);
 }
+// Bucket of a cell: the 4 x 4 x 4 block of cells around it is hashed and the
+// cell's place in its block picks one of 64 consecutive buckets, so that the
+// cells a query scans (a 2..3-cell cube) lie in a few contiguous runs of the
+// record array and neighbouring queries share cache lines.
+__device__ __forceinline__ unsigned cell_bucket(int grid, int x, int y, int z, int P) {
+    const unsigned in_block = (unsigned)(x & 3) | ((unsigned)(y & 3) << 2) | ((unsigned)(z & 3) << 4);
+    return ((hash3(grid, x >> 2, y >> 2, z >> 2) << 6) | in_block) & (unsigned)(P - 1);
+}
 __device__ __forceinline__ long long cell_key(int grid, int x, int y, int z) {
     return ((long long)grid << 63) | ((long long)(x & 0x1FFFFF) << 42) | ((long long)(y & 0x1FFFFF) << 21) |
            (long long)(z & 0x1FFFFF);
@@ -686,7 +694,7 @@ __global__ void __launch_bounds__(256) k_cells(int m, const float* __restrict__ 
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         int c[3], grid;
         if (!target_cell(box + 6 * (size_t)i, g, grid, c)) atomicOr(overflow, OVF_CELL);   // filed in cell 0
-        atomicAdd(&bucket_cnt[hash3(grid, c[0], c[1], c[2]) & (P - 1)], 1);
+        atomicAdd(&bucket_cnt[cell_bucket(grid, c[0], c[1], c[2], P)], 1);
     }
 }
 
@@ -698,7 +706,7 @@ __global__ void __launch_bounds__(256) k_bucket_fill(Dev d, int vt, int m, const
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         int c[3], grid;
         target_cell(box + 6 * (size_t)i, g, grid, c);
-        int pos = atomicAdd(&cursor[hash3(grid, c[0], c[1], c[2]) & (P - 1)], 1);
+        int pos = atomicAdd(&cursor[cell_bucket(grid, c[0], c[1], c[2], P)], 1);
         BpRec r;
         r.key = cell_key(grid, c[0], c[1], c[2]);
         r.id = i;
@@ -783,7 +791,7 @@ __global__ void __launch_bounds__(256) k_query(Dev d, const float* __restrict__ 
                 for (int cy = lo[1]; cy <= hi[1] && !full; ++cy)
                     for (int cz = lo[2]; cz <= hi[2] && !full; ++cz) {
                         const long long key = cell_key(grid, cx, cy, cz);
-                        const unsigned b = hash3(grid, cx, cy, cz) & (P - 1);
+                        const unsigned b = cell_bucket(grid, cx, cy, cz, P);
                         for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
                             if (++visits > MAX_VISIT || cnt >= max_out) {
                                 full = true;

@@ -121,6 +121,33 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
     return x * q + min(x, rem) + i;
 }
 
+// Off-diagonal row v of H in SELL-64: calls fn(H_vj, x4[j]) for its entries
+// in storage order.  The column and value loads of C entries are issued
+// together, then their C gathers, so that a row costs two dependent memory
+// round trips per C entries instead of two per entry.  The slice width is
+// common to the 64 rows of a wavefront, so the chunk bounds are uniform.
+template <int C, typename Fn>
+__device__ __forceinline__ void sell_row(const Dev& d, const float4* __restrict__ x4, int v, Fn&& fn) {
+    const int lane = v & 63;
+    const int p0 = d.sell_ptr[v >> 6], p1 = d.sell_ptr[(v >> 6) + 1];
+    for (int j0 = p0 + lane; j0 < p1; j0 += 64 * C) {
+        int col[C];
+        float val[C];
+#pragma unroll
+        for (int b = 0; b < C; ++b) {
+            const int j = j0 + 64 * b;
+            col[b] = j < p1 ? d.sell_col[j] : v;
+            val[b] = j < p1 ? d.sell_val[j] : 0.f;
+        }
+        float4 xc[C];
+#pragma unroll
+        for (int b = 0; b < C; ++b) xc[b] = x4[col[b]];
+#pragma unroll
+        for (int b = 0; b < C; ++b)
+            if (j0 + 64 * b < p1) fn(val[b], xc[b]);
+    }
+}
+
 __device__ __forceinline__ double warp_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
@@ -240,33 +267,55 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
             bx = m * (d.z[v] - x0);
             by = m * (d.z[n + v] - x1);
             bz = m * (d.z[2 * n + v] - x2);
-            for (int i = d.inc_ptr[v], e = d.inc_ptr[v + 1]; i < e; ++i) {
-                int code = d.inc[i];
-                int t = code >> 2, c = code & 3;
-                TriRec tr = d.tri[t];
-                const float4 q0 = X4[tr.v0], q1 = X4[tr.v1], q2 = X4[tr.v2];
-                float e1[3] = {q1.x - q0.x, q1.y - q0.y, q1.z - q0.z};
-                float e2[3] = {q2.x - q0.x, q2.y - q0.y, q2.z - q0.z};
-                float F[6], T[6];
-                for (int q = 0; q < 3; ++q) {
-                    F[2 * q] = e1[q] * tr.gj0 + e2[q] * tr.gk0;
-                    F[2 * q + 1] = e1[q] * tr.gj1 + e2[q] * tr.gk1;
+            // incident triangles, CT at a time: their incidence codes, then
+            // their records, then the corner positions are requested
+            // together; the projections are summed in incidence order
+            constexpr int CT = 2;
+            for (int i = d.inc_ptr[v], e = d.inc_ptr[v + 1]; i < e; i += CT) {
+                int code[CT];
+#pragma unroll
+                for (int b = 0; b < CT; ++b) code[b] = i + b < e ? d.inc[i + b] : 0;
+                TriRec trs[CT];
+#pragma unroll
+                for (int b = 0; b < CT; ++b)
+                    if (i + b < e) trs[b] = d.tri[code[b] >> 2];
+                float4 qs[CT][3];
+#pragma unroll
+                for (int b = 0; b < CT; ++b)
+                    if (i + b < e) {
+                        qs[b][0] = X4[trs[b].v0];
+                        qs[b][1] = X4[trs[b].v1];
+                        qs[b][2] = X4[trs[b].v2];
+                    }
+#pragma unroll
+                for (int b = 0; b < CT; ++b) {
+                    if (i + b >= e) break;
+                    const TriRec& tr = trs[b];
+                    const int c = code[b] & 3;
+                    const float4 q0 = qs[b][0], q1 = qs[b][1], q2 = qs[b][2];
+                    float e1[3] = {q1.x - q0.x, q1.y - q0.y, q1.z - q0.z};
+                    float e2[3] = {q2.x - q0.x, q2.y - q0.y, q2.z - q0.z};
+                    float F[6], T[6];
+                    for (int q = 0; q < 3; ++q) {
+                        F[2 * q] = e1[q] * tr.gj0 + e2[q] * tr.gk0;
+                        F[2 * q + 1] = e1[q] * tr.gj1 + e2[q] * tr.gk1;
+                    }
+                    polar32(F, T);
+                    float g0, g1;
+                    if (c == 0) {
+                        g0 = -tr.gj0 - tr.gk0;
+                        g1 = -tr.gj1 - tr.gk1;
+                    } else if (c == 1) {
+                        g0 = tr.gj0;
+                        g1 = tr.gj1;
+                    } else {
+                        g0 = tr.gk0;
+                        g1 = tr.gk1;
+                    }
+                    bx += tr.w * (T[0] * g0 + T[1] * g1);
+                    by += tr.w * (T[2] * g0 + T[3] * g1);
+                    bz += tr.w * (T[4] * g0 + T[5] * g1);
                 }
-                polar32(F, T);
-                float g0, g1;
-                if (c == 0) {
-                    g0 = -tr.gj0 - tr.gk0;
-                    g1 = -tr.gj1 - tr.gk1;
-                } else if (c == 1) {
-                    g0 = tr.gj0;
-                    g1 = tr.gj1;
-                } else {
-                    g0 = tr.gk0;
-                    g1 = tr.gk1;
-                }
-                bx += tr.w * (T[0] * g0 + T[1] * g1);
-                by += tr.w * (T[2] * g0 + T[3] * g1);
-                bz += tr.w * (T[4] * g0 + T[5] * g1);
             }
         }
         float Wv = 0.f;
@@ -310,28 +359,22 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
         if (!d.pinned[v]) {
             // off-diagonal part of H from the SELL-64 slices; elastic rows
             // sum to zero, so H x = (m/h^2) x + sum_{j != v} H_vj (x_j - x_v)
-            const int lane = v & 63;
-            const int p0 = d.sell_ptr[v >> 6], p1 = d.sell_ptr[(v >> 6) + 1];
             float ax = 0.f, ay = 0.f, az = 0.f;
             if (!linear) {
-                for (int j = p0 + lane; j < p1; j += 64) {
-                    const float a = d.sell_val[j];
-                    const float4 xc = X4[d.sell_col[j]];
+                sell_row<5>(d, X4, v, [&](float a, float4 xc) {
                     ax += a * (xc.x - x0);
                     ay += a * (xc.y - x1);
                     az += a * (xc.z - x2);
-                }
+                });
                 r0[0] = bx - ax;
                 r0[1] = by - ay;
                 r0[2] = bz - az;
             } else {
-                for (int j = p0 + lane; j < p1; j += 64) {
-                    const float a = d.sell_val[j];
-                    const float4 xc = X4[d.sell_col[j]];
+                sell_row<5>(d, X4, v, [&](float a, float4 xc) {
                     ax += a * xc.x;
                     ay += a * xc.y;
                     az += a * xc.z;
-                }
+                });
                 const float dv = d.diag[v] + Wv;
                 r0[0] = -ax - dv * x0;
                 r0[1] = -ay - dv * x1;
@@ -543,23 +586,21 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
         float xkm1[3] = {d.xkm1[v], d.xkm1[n + v], d.xkm1[2 * n + v]};
         float dh[3] = {0.f, 0.f, 0.f};
         if (!d.pinned[v]) {
+            // the row's own data is requested before the gathers
+            const float r00 = d.b[v], r01 = d.b[n + v], r02 = d.b[2 * n + v];
+            const float dg = d.diag[v] + (has_contact ? d.W[v] : 0.f);
             float ax = 0.f, ay = 0.f, az = 0.f;
-            const int lane = v & 63;
-            const int p1 = d.sell_ptr[(v >> 6) + 1];
-            for (int j = d.sell_ptr[v >> 6] + lane; j < p1; j += 64) {
-                const float a = d.sell_val[j];
-                const float4 dc = DL[d.sell_col[j]];
+            sell_row<5>(d, DL, v, [&](float a, float4 dc) {
                 ax += a * dc.x;
                 ay += a * dc.y;
                 az += a * dc.z;
-            }
-            float Wv = has_contact ? d.W[v] : 0.f;
-            float inv = 1.0f / (d.diag[v] + Wv);
+            });
+            float inv = 1.0f / dg;
             // x^ - x^k = delta + (r0 - (H + diag W) delta) / (diag H + W)
             //          = (r0 - offdiag(H) delta) / (diag H + W)
-            dh[0] = (d.b[v] - ax) * inv;
-            dh[1] = (d.b[n + v] - ay) * inv;
-            dh[2] = (d.b[2 * n + v] - az) * inv;
+            dh[0] = (r00 - ax) * inv;
+            dh[1] = (r01 - ay) * inv;
+            dh[2] = (r02 - az) * inv;
         }
         double s2 = 0.0;
         float nx[3];
