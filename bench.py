@@ -275,7 +275,8 @@ def main():
         "steps_per_s": round(K / wall, 2),
         "last_step": {"n_candidates": stats["n_candidates"], "n_constraints": stats["n_constraints"],
                       "min_toi": stats["min_toi"], "dx_norm": stats["dx_norm"],
-                      "cheb_rho": stats["cheb_rho"], "cheb_gamma": stats["cheb_gamma"], "finite": finite},
+                      "cheb_rho": stats["cheb_rho"], "cheb_gamma": stats["cheb_gamma"],
+                      "n_contact_vertices": stats["n_contact_vertices"], "finite": finite},
         "launch": "eager" if args.eager else "graph replay",
         "roofline": roof,
         "cpu_baseline": cpu,

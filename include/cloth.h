@@ -117,6 +117,9 @@ typedef struct {
     int64_t peak_candidates;  /* largest VT or EE candidate list of any outer
                                  stage since the previous stats read (for
                                  sizing pair_capacity) */
+    int64_t n_contact_vertices;  /* vertices with a collision weight in the
+                                    last block: the rows of the contact Gram
+                                    U_C^T diag(W) U_C (Eq. (uu)) */
 } cloth_step_stats;
 
 const char* cloth_status_string(cloth_status s);

@@ -65,7 +65,8 @@ class StepStats(C.Structure):
     _fields_ = [("inner_iters", C.c_int32), ("outer_iters", C.c_int32),
                 ("n_candidates", C.c_int64), ("n_constraints", C.c_int64),
                 ("dx_norm", C.c_double), ("min_toi", C.c_double), ("cheb_rho", C.c_double),
-                ("cheb_gamma", C.c_double), ("peak_candidates", C.c_int64)]
+                ("cheb_gamma", C.c_double), ("peak_candidates", C.c_int64),
+                ("n_contact_vertices", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,7 +74,7 @@ class StepStats(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libcloth.so not built at {LIB_PATH}; run python -m paper_2403_19272_amd.build")
+        raise ImportError(f"libcloth.so not built at {LIB_PATH}; run python paper_2403_19272_amd/build.py")
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     i32, i64, f64 = C.c_int32, C.c_int64, C.c_double

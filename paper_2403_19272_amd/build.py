@@ -1,6 +1,7 @@
 """Builds libcloth.so (the HIP library behind include/cloth.h) for gfx950.
 
-Usage: python -m paper_2403_19272_amd.build   (or build() from Python).
+Usage: python paper_2403_19272_amd/build.py   (or build() from this module; importing
+the package itself needs the built library).
 """
 from __future__ import annotations
 

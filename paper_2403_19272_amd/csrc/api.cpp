@@ -169,7 +169,7 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     d.Qd = cv<double>(carve_fn, (size_t)s.r * 3);
     d.Ainv = cv<double>(carve_fn, (size_t)s.r * s.r);
     d.Lam = cv<double>(carve_fn, (size_t)s.r * s.r);
-    d.Amat = cv<double>(carve_fn, (size_t)(GRAM_GROUPS_MAX + 2) * s.r * (s.r + 1) / 2 + s.r);
+    d.Amat = cv<double>(carve_fn, (size_t)(GRAM_GROUPS_MAX + 1) * s.r * (s.r + 1) / 2);
     d.gram_part = cv<double>(carve_fn, (size_t)GRAM_CHUNKS * s.r * s.r);
     d.dxbits = cv<unsigned long long>(carve_fn, 4096);
     s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);

@@ -409,87 +409,112 @@ __device__ double obst_toi(const ObstD& o, d3 xm, d3 xp) {
 
 // ================================================================ scans
 // Exclusive prefix sums over n = min(n_dev ? *n_dev : n_host, cap) ints.
-__global__ void k_scan_tiles(const int* __restrict__ in, int n_host, const int* __restrict__ n_dev, int* tiles) {
-    __shared__ int red[256];
-    int n = n_dev ? *n_dev : n_host;
-    int base = blockIdx.x * SCAN_TILE;
-    int s = 0;
-    if (base < n)
-        for (int i = threadIdx.x; i < SCAN_TILE; i += 256) {
-            int g = base + i;
-            if (g < n) s += in[g];
-        }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
+// Within a wavefront the sums are formed with lane shuffles; one barrier
+// per block combines the wavefront totals.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
     }
-    if (threadIdx.x == 0) tiles[blockIdx.x] = red[0];
+    return v;
 }
 
-// single block: exclusive scan of the tile sums in place; total -> *total
-__global__ void k_scan_top(int* tiles, int ntiles, int* total) {
-    __shared__ int part[1024];
-    int per = (ntiles + 1023) / 1024;
-    int b0 = threadIdx.x * per, b1 = min(ntiles, b0 + per);
+// tiles holding the first n items
+__device__ __forceinline__ int scan_used_tiles(int n_host, const int* n_dev, int ntiles) {
+    const int n = n_dev ? min(*n_dev, n_host) : n_host;
+    return min(ntiles, (max(n, 0) + SCAN_TILE - 1) / SCAN_TILE);
+}
+
+// per-tile sums, tiles taken grid-stride
+__global__ void __launch_bounds__(256) k_scan_tiles(const int* __restrict__ in, int n_host,
+                                                    const int* __restrict__ n_dev, int ntiles, int* tiles) {
+    __shared__ int red[4];
+    const int n = n_dev ? min(*n_dev, n_host) : n_host;
+    const int used = scan_used_tiles(n_host, n_dev, ntiles);
+    for (int tile = blockIdx.x; tile < used; tile += gridDim.x) {
+        const int base = tile * SCAN_TILE;
+        int s = 0;
+        for (int i = threadIdx.x; i < SCAN_TILE; i += 256) {
+            const int g = base + i;
+            if (g < n) s += in[g];
+        }
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) tiles[tile] = red[0] + red[1] + red[2] + red[3];
+        __syncthreads();   // red is reused by the next tile
+    }
+}
+
+// single block: exclusive scan of the used tile sums in place; total -> *total
+__global__ void __launch_bounds__(1024) k_scan_top(int* tiles, int n_host, const int* __restrict__ n_dev, int ntiles,
+                                                   int* total) {
+    __shared__ int wsum[16];
+    const int used = scan_used_tiles(n_host, n_dev, ntiles);
+    const int per = (used + 1023) / 1024;
+    const int b0 = threadIdx.x * per, b1 = min(used, b0 + per);
     int s = 0;
     for (int i = b0; i < b1; ++i) s += tiles[i];
-    part[threadIdx.x] = s;
+    const int incl = wave_incl_scan(s);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) wsum[w] = incl;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    int woff = 0;
+    for (int k = 0; k < w; ++k) woff += wsum[k];
+    int run = woff + incl - s;
     for (int i = b0; i < b1; ++i) {
-        int t = tiles[i];
+        const int t = tiles[i];
         tiles[i] = run;
         run += t;
     }
-    if (threadIdx.x == 1023 && total) *total = part[1023];
+    if (threadIdx.x == 1023 && total) *total = woff + incl;
 }
 
-__global__ void k_scan_apply(const int* __restrict__ in, int n_host, const int* __restrict__ n_dev,
-                             const int* __restrict__ tiles, int* __restrict__ out) {
-    __shared__ int ts[256];
-    int n = n_dev ? *n_dev : n_host;
-    int base = blockIdx.x * SCAN_TILE;
-    if (base >= n) return;
-    // each thread owns 8 consecutive items
-    int v[8];
-    int s = 0;
-    for (int k = 0; k < 8; ++k) {
-        int g = base + threadIdx.x * 8 + k;
-        v[k] = g < n ? in[g] : 0;
-        s += v[k];
-    }
-    ts[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        int t = threadIdx.x >= o ? ts[threadIdx.x - o] : 0;
+// items of each used tile, tiles taken grid-stride
+__global__ void __launch_bounds__(256) k_scan_apply(const int* __restrict__ in, int n_host,
+                                                    const int* __restrict__ n_dev, int ntiles,
+                                                    const int* __restrict__ tiles, int* __restrict__ out) {
+    __shared__ int wsum[4];
+    const int n = n_dev ? min(*n_dev, n_host) : n_host;
+    const int used = scan_used_tiles(n_host, n_dev, ntiles);
+    for (int tile = blockIdx.x; tile < used; tile += gridDim.x) {
+        const int base = tile * SCAN_TILE;
+        // each thread owns 8 consecutive items
+        int v[8];
+        int s = 0;
+        for (int k = 0; k < 8; ++k) {
+            const int g = base + threadIdx.x * 8 + k;
+            v[k] = g < n ? in[g] : 0;
+            s += v[k];
+        }
+        const int incl = wave_incl_scan(s);
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 63) wsum[w] = incl;
         __syncthreads();
-        ts[threadIdx.x] += t;
-        __syncthreads();
-    }
-    int run = tiles[blockIdx.x] + (threadIdx.x ? ts[threadIdx.x - 1] : 0);
-    for (int k = 0; k < 8; ++k) {
-        int g = base + threadIdx.x * 8 + k;
-        if (g < n) out[g] = run;
-        run += v[k];
+        int run = tiles[tile] + incl - s;
+        for (int k = 0; k < w; ++k) run += wsum[k];
+        for (int k = 0; k < 8; ++k) {
+            const int g = base + threadIdx.x * 8 + k;
+            if (g < n) out[g] = run;
+            run += v[k];
+        }
+        __syncthreads();   // wsum is reused by the next tile
     }
 }
 
-// out[i] = exclusive prefix of in[0..i); out may alias in only through `tmp`.
+// out[i] = exclusive prefix of in[0..i) for i < n = min(n_dev ? *n_dev : n_cap,
+// n_cap) (out may not alias in); the grids are sized for n_cap and the
+// kernels skip the tiles past n.
+constexpr int SCAN_GRID = 1024;
 static hipError_t scan_exclusive(const int* in, int* out, int n_cap, const int* n_dev, int* tiles, int* total,
                                  hipStream_t st) {
     int nt = (n_cap + SCAN_TILE - 1) / SCAN_TILE;
     if (nt == 0) nt = 1;
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st, in, n_cap, n_dev, tiles);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tiles, nt, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(256), 0, st, in, n_cap, n_dev, tiles, out);
+    const int grid = std::min(nt, SCAN_GRID);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(grid), dim3(256), 0, st, in, n_cap, n_dev, nt, tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tiles, n_cap, n_dev, nt, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(256), 0, st, in, n_cap, n_dev, nt, (const int*)tiles, out);
     return hipGetLastError();
 }
 
@@ -559,8 +584,11 @@ __device__ __forceinline__ bool cell_d(float x, double cs, int& c) {
     return true;
 }
 
-__device__ __forceinline__ bool cell3(const float* lo, const double* cs, int* c) {
-    return cell_d(lo[0], cs[0], c[0]) && cell_d(lo[1], cs[1], c[1]) && cell_d(lo[2], cs[2], c[2]);
+// cell of a point on grid `grid` of g (the cell sizes are selected per
+// component: a pointer into a local grid struct would put it in scratch)
+__device__ __forceinline__ bool cell3g(const float* lo, const BpGrid& g, int grid, int* c) {
+    return cell_d(lo[0], grid ? g.cs2[0] : g.cs1[0], c[0]) && cell_d(lo[1], grid ? g.cs2[1] : g.cs1[1], c[1]) &&
+           cell_d(lo[2], grid ? g.cs2[2] : g.cs1[2], c[2]);
 }
 
 // grid of a target box: 0 if narrower than a grid-1 cell on every axis
@@ -573,7 +601,7 @@ __device__ __forceinline__ int target_grid(const float* box, const BpGrid& g) {
 // cell of a target: false (and cell 0 of grid 0) if it cannot be filed
 __device__ __forceinline__ bool target_cell(const float* box, const BpGrid& g, int& grid, int* c) {
     grid = target_grid(box, g);
-    if (g.ok && cell3(box, grid ? g.cs2 : g.cs1, c)) return true;
+    if (g.ok && cell3g(box, g, grid, c)) return true;
     grid = 0;
     c[0] = c[1] = c[2] = 0;
     return false;
@@ -653,21 +681,31 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float* __restrict__ 
 
 // One block: reduce the box partials; per family (0 = triangles, 1 = edges)
 // the cell widths of the two grids.
-__global__ void k_grid(const float* __restrict__ bpart, int nblk, int nt, int ne, BpGrid* grid) {
-    __shared__ float red[256][BP_PART];
-    for (int q = 0; q < BP_PART; ++q) {
-        const int op = bp_op(q);
-        float w = bp_identity(op);
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) w = bp_combine(op, w, bpart[(size_t)b * BP_PART + q]);
-        red[threadIdx.x][q] = w;
+__global__ void __launch_bounds__(256) k_grid(const float* __restrict__ bpart, int nblk, int nt, int ne,
+                                              BpGrid* grid) {
+    __shared__ float red[4][BP_PART];
+    // each thread folds whole partial records (BP_PART contiguous values),
+    // then the wavefronts fold theirs with shuffles
+    float w[BP_PART];
+#pragma unroll
+    for (int q = 0; q < BP_PART; ++q) w[q] = bp_identity(bp_op(q));
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < BP_PART; ++q) w[q] = bp_combine(bp_op(q), w[q], bpart[(size_t)b * BP_PART + q]);
+    }
+#pragma unroll
+    for (int q = 0; q < BP_PART; ++q)
+        for (int o = 32; o > 0; o >>= 1) w[q] = bp_combine(bp_op(q), w[q], __shfl_xor(w[q], o, 64));
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < BP_PART; ++q) red[threadIdx.x >> 6][q] = w[q];
     }
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
-            for (int q = 0; q < BP_PART; ++q)
-                red[threadIdx.x][q] = bp_combine(bp_op(q), red[threadIdx.x][q], red[threadIdx.x + o][q]);
-        __syncthreads();
+    if (threadIdx.x < BP_PART) {
+        const int q = threadIdx.x, op = bp_op(q);
+        red[0][q] = bp_combine(op, bp_combine(op, red[0][q], red[1][q]), bp_combine(op, red[2][q], red[3][q]));
     }
+    __syncthreads();
     if (threadIdx.x < 2) {
         const int f = threadIdx.x;
         const float* r = red[0] + f * BP_FAM;
@@ -730,123 +768,21 @@ __global__ void __launch_bounds__(256) k_bucket_fill(Dev d, int vt, int m, const
 
 // Query of one box against the cell buckets.  VT: query = vertex v,
 // targets = triangles not incident to v; EE: query = edge e, targets = edges
-// f > e sharing no vertex.
-//   PASS 0: count, keep up to QK target ids per query in `scratch`, sorted.
-//   PASS 1: write the query's sorted pairs at ofs[q] (copied from the
-//           scratch when they fit there, else found again and sorted in
-//           place).
+// f > e sharing no vertex.  Three kernels, all built on group_query (G lanes
+// per query):
+//   k_query_count  counts each query's hits and keeps up to QK of them in
+//                  `scratch`, sorted by target id;
+//   k_query_copy   writes the queries whose hits fit the scratch to the
+//                  candidate list at their offsets;
+//   k_query_rescan finds the hits of the other (rare) queries again, one
+//                  wavefront per query, and writes them sorted.
 // Work and output per query are bounded (MAX_VISIT records, max_out pairs,
 // at most 32 grid-1 and 8 grid-2 cells per axis and MAX_CELLS per grid,
-// finite boxes only); hitting
-// a bound sets the
-// overflow flag and the step reports a capacity error instead of running
-// away on a diverged state.
+// finite boxes only); hitting a bound sets the overflow flag and the step
+// reports a capacity error instead of running away on a diverged state.
 constexpr int MAX_VISIT = 1 << 16;
 constexpr int MAX_CELLS = 4096;   // cells one query may visit in one grid
-template <bool VT, int PASS>
-__global__ void __launch_bounds__(256) k_query(Dev d, const float* __restrict__ qbox, const BpGrid* __restrict__ gp,
-                        const int* __restrict__ bptr, const BpRec* __restrict__ rec, int P, int* count,
-                        const int* __restrict__ raw, int* scratch, int2* out, int64_t cap, int max_out,
-                        int* overflow) {
-    const int nq = VT ? d.nv : d.ne;
-    const BpGrid g = *gp;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
-        int* sq = scratch + (size_t)q * QK;
-        int base = 0;
-        if (PASS == 1) {
-            base = count[q];
-            const int k = raw[q];
-            if (base < 0) continue;
-            if (k <= QK) {
-                for (int i = 0; i < k; ++i) {
-                    int64_t pos = (int64_t)base + i;
-                    if (pos < cap) out[pos] = make_int2(q, sq[i]);
-                }
-                continue;
-            }
-        }
-        const float* qb = qbox + 6 * (size_t)q;
-        int qa = -1, qb2 = -1;
-        if (!VT) {
-            qa = d.edges[2 * q];
-            qb2 = d.edges[2 * q + 1];
-        }
-        float ql[3] = {qb[0], qb[1], qb[2]}, qh[3] = {qb[3], qb[4], qb[5]};
-        int cnt = 0, visits = 0;
-        bool full = !(g.ok && isfinite(ql[0] + ql[1] + ql[2] + qh[0] + qh[1] + qh[2]));
-        for (int grid = 0; grid < 1 + g.use2 && !full; ++grid) {
-            const double* cs = grid ? g.cs2 : g.cs1;
-            const int span = grid ? 8 : 32;   // cells per axis a query may cover
-            int lo[3], hi[3];
-            if (!cell3(ql, cs, lo) || !cell3(qh, cs, hi)) {
-                full = true;
-                break;
-            }
-            for (int c = 0; c < 3; ++c) {
-                lo[c] -= 1;
-                if (hi[c] - lo[c] > span) full = true;
-            }
-            if (!full && (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1) > MAX_CELLS) full = true;
-            for (int cx = lo[0]; cx <= hi[0] && !full; ++cx)
-                for (int cy = lo[1]; cy <= hi[1] && !full; ++cy)
-                    for (int cz = lo[2]; cz <= hi[2] && !full; ++cz) {
-                        const long long key = cell_key(grid, cx, cy, cz);
-                        const unsigned b = cell_bucket(grid, cx, cy, cz, P);
-                        for (int k = bptr[b], e = bptr[b + 1]; k < e; ++k) {
-                            if (++visits > MAX_VISIT || cnt >= max_out) {
-                                full = true;
-                                break;
-                            }
-                            const BpRec r = rec[k];
-                            if (r.key != key) continue;
-                            if (VT) {
-                                if (r.a == q || r.b == q || r.c == q) continue;
-                            } else {
-                                if (r.id <= q || r.a == qa || r.a == qb2 || r.b == qa || r.b == qb2) continue;
-                            }
-                            if (ql[0] > r.hi[0] || r.lo[0] > qh[0] || ql[1] > r.hi[1] || r.lo[1] > qh[1] ||
-                                ql[2] > r.hi[2] || r.lo[2] > qh[2])
-                                continue;
-                            if (PASS == 0) {
-                                if (cnt < QK) sq[cnt] = r.id;
-                            } else {
-                                int64_t pos = (int64_t)base + cnt;
-                                if (pos < cap) out[pos] = make_int2(q, r.id);
-                            }
-                            ++cnt;
-                        }
-                    }
-        }
-        if (full) atomicOr(overflow, OVF_QUERY);
-        if (PASS == 0) {
-            for (int i = 1; i < min(cnt, QK); ++i) {  // insertion sort by target id
-                int key = sq[i];
-                int j = i - 1;
-                while (j >= 0 && sq[j] > key) {
-                    sq[j + 1] = sq[j];
-                    --j;
-                }
-                sq[j + 1] = key;
-            }
-            count[q] = cnt;
-        } else {
-            int64_t b0 = base, b1 = (int64_t)base + cnt;
-            if (b1 > cap) {
-                atomicOr(overflow, OVF_LIST);
-                b1 = cap;
-            }
-            for (int64_t i = b0 + 1; i < b1; ++i) {
-                int2 key = out[i];
-                int64_t j = i - 1;
-                while (j >= b0 && out[j].y > key.y) {
-                    out[j + 1] = out[j];
-                    --j;
-                }
-                out[j + 1] = key;
-            }
-        }
-    }
-}
+constexpr int MAX_HITS = 1024;    // largest per-query output bound (max_out)
 
 // total of the last count + last offset -> n (clamped to cap), overflow flag
 __global__ void k_count_total(const int* counts_scanned, const int* counts_raw, int m, int* n_out, int64_t cap,
@@ -862,55 +798,257 @@ __global__ void k_count_total(const int* counts_scanned, const int* counts_raw, 
     }
 }
 
+// Workgroups are dealt round-robin over the 8 XCDs; block b of a grid of
+// nblk is given tile xcd_block(b, nblk), so that each XCD works through one
+// contiguous range of tiles (a bijection of [0, nblk)).
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+    constexpr int X = 8;
+    const int x = b % X, i = b / X;
+    const int q = nblk / X, rem = nblk % X;
+    return x * q + min(x, rem) + i;
+}
+
+// The hits of query q, found by the G lanes of a group (lane = this thread's
+// place in it; the group is a G-aligned segment of a wavefront, `sub` its
+// index there).  The lanes split the query's cells, lay the records of those
+// cells' buckets end to end (prefix sum of the bucket lengths) and read them
+// together, consecutive lanes on consecutive records; hits are compacted
+// with a ballot and handed to hit(index, target id) in a fixed order (cells,
+// then records).  Returns the hit count (capped at max_out + G); `full` is
+// set when a bound is hit.
+template <bool VT, int G, typename Hit>
+__device__ __forceinline__ int group_query(const Dev& d, int q, int lane, int sub, const float* __restrict__ qbox,
+                                           const BpGrid& g, const int* __restrict__ bptr,
+                                           const BpRec* __restrict__ rec, int P, int max_out, bool& full,
+                                           Hit&& hit) {
+    static_assert(G >= 2 && G <= 64 && (G & (G - 1)) == 0, "lanes per query");
+    const unsigned long long seg = G == 64 ? ~0ull : ((1ull << G) - 1);
+    const float* qb = qbox + 6 * (size_t)q;
+    const float ql[3] = {qb[0], qb[1], qb[2]}, qh[3] = {qb[3], qb[4], qb[5]};
+    int qa = -1, qb2 = -1;
+    if (!VT) {
+        qa = d.edges[2 * q];
+        qb2 = d.edges[2 * q + 1];
+    }
+    int cnt = 0, visits = 0;
+    full = !(g.ok && isfinite(ql[0] + ql[1] + ql[2] + qh[0] + qh[1] + qh[2]));
+    for (int grid = 0; grid < 1 + g.use2 && !full; ++grid) {
+        const int span = grid ? 8 : 32;   // cells per axis a query may cover
+        int lo[3], hi[3];
+        if (!cell3g(ql, g, grid, lo) || !cell3g(qh, g, grid, hi)) {
+            full = true;
+            break;
+        }
+        for (int c = 0; c < 3; ++c) {
+            lo[c] -= 1;
+            if (hi[c] - lo[c] > span) full = true;
+        }
+        const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+        if (!full && nx * ny * nz > MAX_CELLS) full = true;
+        if (full) break;
+        const int ncell = nx * ny * nz;
+        for (int c0 = 0; c0 < ncell && !full; c0 += G) {
+            // this lane's cell and its bucket's record range
+            const int c = c0 + lane;
+            int s0 = 0, len = 0;
+            long long key = 0;
+            if (c < ncell) {
+                const int cz = lo[2] + c % nz, cy = lo[1] + (c / nz) % ny, cx = lo[0] + c / (nz * ny);
+                const unsigned b = cell_bucket(grid, cx, cy, cz, P);
+                s0 = bptr[b];
+                len = bptr[b + 1] - s0;
+                key = cell_key(grid, cx, cy, cz);
+            }
+            int incl = len;
+            for (int o = 1; o < G; o <<= 1) {
+                const int t = __shfl_up(incl, o, G);
+                if (lane >= o) incl += t;
+            }
+            const int V = __shfl(incl, G - 1, G);   // records of this chunk of cells
+            const int excl = incl - len;
+            visits += V;
+            if (visits > MAX_VISIT) {
+                full = true;
+                break;
+            }
+            for (int t0 = 0; t0 < V; t0 += G) {
+                // record t of the chunk: the cell j with excl_j <= t < excl_j + len_j
+                // (the last lane whose exclusive prefix is <= t)
+                const int t = min(t0 + lane, V - 1);
+                int j = 0;
+                for (int step = G / 2; step > 0; step >>= 1)
+                    if (__shfl(excl, j + step, G) <= t) j += step;
+                const int k = __shfl(s0, j, G) + (t - __shfl(excl, j, G));
+                const long long kj = __shfl(key, j, G);
+                bool pass = false;
+                int id = 0;
+                if (t0 + lane < V) {
+                    const BpRec r = rec[k];
+                    id = r.id;
+                    pass = r.key == kj;
+                    if (VT)
+                        pass = pass && r.a != q && r.b != q && r.c != q;
+                    else
+                        pass = pass && r.id > q && r.a != qa && r.a != qb2 && r.b != qa && r.b != qb2;
+                    pass = pass && !(ql[0] > r.hi[0] || r.lo[0] > qh[0] || ql[1] > r.hi[1] || r.lo[1] > qh[1] ||
+                                     ql[2] > r.hi[2] || r.lo[2] > qh[2]);
+                }
+                const unsigned long long gm = (__ballot(pass) >> (sub * G)) & seg;
+                if (pass) hit(cnt + __popcll(gm & ((1ull << lane) - 1)), id);
+                cnt += __popcll(gm);
+            }
+            if (cnt > max_out) full = true;
+        }
+    }
+    return cnt;
+}
+
+// Counting pass: one group of G lanes per query.  The kept hits (at most
+// QK) are ranked in LDS and written to the scratch sorted by target id.
+// Blocks take consecutive queries and each XCD a contiguous range of blocks,
+// so few queries are in flight per XCD and the records of their cells stay
+// in its L2.
+template <bool VT, int G>
+__global__ void __launch_bounds__(256) k_query_count(Dev d, const float* __restrict__ qbox,
+                                                     const BpGrid* __restrict__ gp, const int* __restrict__ bptr,
+                                                     const BpRec* __restrict__ rec, int P, int* count, int* scratch,
+                                                     int max_out, int* overflow) {
+    constexpr int GPB = 256 / G;
+    __shared__ int res[GPB][QK];
+    const int nq = VT ? d.nv : d.ne;
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int sub = (threadIdx.x & 63) / G;
+    const int q = xcd_block(blockIdx.x, gridDim.x) * GPB + grp;
+    const BpGrid g = *gp;
+    int cnt = 0;
+    bool full = false;
+    if (q < nq) {
+        cnt = group_query<VT, G>(d, q, lane, sub, qbox, g, bptr, rec, P, max_out, full, [&](int idx, int id) {
+            if (idx < QK) res[grp][idx] = id;
+        });
+        if (lane == 0) {
+            count[q] = min(cnt, max_out);
+            if (full) atomicOr(overflow, OVF_QUERY);
+        }
+    }
+    __syncthreads();
+    // the kept hits in target-id order (ids are distinct within a query)
+    if (q < nq && cnt <= QK) {
+        int* sq = scratch + (size_t)q * QK;
+        for (int i = lane; i < cnt; i += G) {
+            const int v = res[grp][i];
+            int rank = 0;
+            for (int k2 = 0; k2 < cnt; ++k2) rank += res[grp][k2] < v;
+            sq[rank] = v;
+        }
+    }
+}
+
+// Writing pass for the queries whose hits fit the scratch (at most QK): the
+// G lanes of a query copy its sorted hits to the candidate list at its
+// offset, consecutive lanes to consecutive entries.
+template <int G>
+__global__ void __launch_bounds__(256) k_query_copy(int nq, const int* __restrict__ ofs, const int* __restrict__ raw,
+                                                    const int* __restrict__ scratch, int2* out, int64_t cap) {
+    constexpr int GPB = 256 / G;
+    const int lane = threadIdx.x % G;
+    const int q = xcd_block(blockIdx.x, gridDim.x) * GPB + threadIdx.x / G;
+    if (q >= nq) return;
+    const int k = raw[q], base = ofs[q];
+    if (base < 0 || k > QK) return;
+    const int* sq = scratch + (size_t)q * QK;
+    for (int i = lane; i < k; i += G) {
+        const int64_t pos = (int64_t)base + i;
+        if (pos < cap) out[pos] = make_int2(q, sq[i]);
+    }
+}
+
+// Writing pass for the queries with more than QK hits.  Each block looks
+// through its range of queries 256 at a time for such queries; each
+// wavefront then takes one of them, finds its hits again with group_query
+// (G = 64) into LDS, ranks them and writes them sorted at the query's offset.
+template <bool VT>
+__global__ void __launch_bounds__(256) k_query_rescan(Dev d, const float* __restrict__ qbox,
+                                                      const BpGrid* __restrict__ gp, const int* __restrict__ bptr,
+                                                      const BpRec* __restrict__ rec, int P,
+                                                      const int* __restrict__ ofs, const int* __restrict__ raw,
+                                                      int2* out, int64_t cap, int max_out, int* overflow) {
+    __shared__ int heavy[256];
+    __shared__ int nheavy;
+    __shared__ int hits[4][MAX_HITS];
+    const int nq = VT ? d.nv : d.ne;
+    const int chunk = (nq + gridDim.x - 1) / gridDim.x;
+    const int q0 = blockIdx.x * chunk, q1 = min(nq, q0 + chunk);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const BpGrid g = *gp;
+    for (int b = q0; b < q1; b += 256) {
+        if (threadIdx.x == 0) nheavy = 0;
+        __syncthreads();
+        const int q = b + threadIdx.x;
+        if (q < q1 && ofs[q] >= 0 && raw[q] > QK) heavy[atomicAdd(&nheavy, 1)] = q;
+        __syncthreads();
+        const int nh = nheavy;
+        for (int h = w; h < nh; h += 4) {
+            const int qq = heavy[h];
+            bool full = false;
+            const int cnt = group_query<VT, 64>(d, qq, lane, 0, qbox, g, bptr, rec, P, max_out, full,
+                                                [&](int idx, int id) {
+                                                    if (idx < MAX_HITS) hits[w][idx] = id;
+                                                });
+            if (full && lane == 0) atomicOr(overflow, OVF_QUERY);
+            const int m = min(cnt, min(max_out, MAX_HITS));
+            const int64_t base = ofs[qq];
+            if (lane == 0 && base + m > cap) atomicOr(overflow, OVF_LIST);
+            __builtin_amdgcn_wave_barrier();
+            for (int i = lane; i < m; i += 64) {
+                const int v = hits[w][i];
+                int rank = 0;
+                for (int k2 = 0; k2 < m; ++k2) rank += hits[w][k2] < v;
+                if (base + rank < cap) out[base + rank] = make_int2(qq, v);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();   // heavy[] and nheavy are reused
+    }
+}
+
 // ================================================================ TOI + merge
-// For candidate i (VT in [0, n_vt), EE after): TOI, whether it was in the
-// previous constraint set (binary search on the sorted previous list), the
-// keep flag (TOI <= 1 or present before) and the carried life span.
-// Work is taken in chunks of TOI_CHUNK candidates per block: every lane first
+// For candidate i (VT in [0, n_vt), EE after): TOI and the keep flag
+// TOI <= 1 (k_prev_match then adds the pairs of the previous constraint set
+// and their life spans).  Work is taken in chunks of TOI_CHUNK candidates per block: every lane first
 // settles the pairs that cannot hit (no root of the coplanarity cubic in
 // [0, 1]); the rest go to an LDS queue that all lanes then drain, so the
 // root refinement and the inside tests run on full wavefronts.
 constexpr int TOI_CHUNK = 1024;
 
-__device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, int2 pr, double t, double* toi_vt,
-                                           double* toi_ee, const int2* __restrict__ prev,
-                                           const int* __restrict__ prev_a, int pvt, int pee, int* keep,
-                                           int* cand_a, int do_merge) {
+__device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, double t, double* toi_vt, double* toi_ee,
+                                           int* keep, int* cand_a, int do_merge) {
     if (vt) toi_vt[i] = t; else toi_ee[i - nvt] = t;
     if (!do_merge) return;
-    // binary search in the previous list of the same type
-    int lo = vt ? 0 : pvt, hi = vt ? pvt : pvt + pee;
-    long long key = ((long long)pr.x << 32) | (unsigned)pr.y;
-    int found = -1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        int2 p = prev[mid];
-        long long k2 = ((long long)p.x << 32) | (unsigned)p.y;
-        if (k2 < key) lo = mid + 1;
-        else hi = mid;
-    }
-    int end = vt ? pvt : pvt + pee;
-    if (lo < end) {
-        int2 p = prev[lo];
-        if (p.x == pr.x && p.y == pr.y) found = lo;
-    }
-    keep[i] = (t <= 1.0 || found >= 0) ? 1 : 0;
-    cand_a[i] = found >= 0 ? prev_a[found] : 0;
+    // the pairs of the previous set that are still candidates are added,
+    // with their life spans, by k_prev_match
+    keep[i] = t <= 1.0 ? 1 : 0;
+    cand_a[i] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restrict__ xm, const float4* __restrict__ xp,
                                                    const int2* __restrict__ cvt, const int2* __restrict__ cee,
-                                                   const int* cnt, double* toi_vt, double* toi_ee,
-                                                   const int2* __restrict__ prev, const int* __restrict__ prev_a,
-                                                   int* keep, int* cand_a, double* tpart, int do_merge) {
+                                                   const int* cnt, double* toi_vt, double* toi_ee, int* keep,
+                                                   int* cand_a, double* tpart, int do_merge) {
     __shared__ double wmin[4];
     __shared__ int queue[TOI_CHUNK];
     __shared__ int qn;
     const int nvt = cnt[0], nee = cnt[1];
-    const int pvt = cnt[4], pee = cnt[5];
     const int total = nvt + nee;
     double tmin = NOHIT;
-    for (int base = blockIdx.x * TOI_CHUNK; base < total; base += gridDim.x * TOI_CHUNK) {
+    // chunks are split into 8 contiguous ranges, one per XCD (workgroups
+    // are dealt round-robin over the XCDs), so that an XCD gathers the
+    // positions of one region of the cloth, which then stay in its L2
+    const int nchunk = (total + TOI_CHUNK - 1) / TOI_CHUNK;
+    const int xcd = blockIdx.x % 8, nb_x = (gridDim.x - xcd + 7) / 8;
+    const int per_x = (nchunk + 7) / 8, c_end = min(nchunk, (xcd + 1) * per_x);
+    for (int ch = xcd * per_x + blockIdx.x / 8; ch < c_end; ch += nb_x) {
+        const int base = ch * TOI_CHUNK;
         if (threadIdx.x == 0) qn = 0;
         __syncthreads();
         for (int k = threadIdx.x; k < TOI_CHUNK; k += blockDim.x) {
@@ -921,7 +1059,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
             d3 q0[4], q1[4];
             pair_points2(d, vt, pr.x, pr.y, xm, xp, q0, q1);
             if (pair_no_hit(vt, q0, q1))
-                toi_finish(i, vt, nvt, pr, NOHIT, toi_vt, toi_ee, prev, prev_a, pvt, pee, keep, cand_a, do_merge);
+                toi_finish(i, vt, nvt, NOHIT, toi_vt, toi_ee, keep, cand_a, do_merge);
             else
                 queue[atomicAdd(&qn, 1)] = i;
         }
@@ -935,7 +1073,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
             pair_points2(d, vt, pr.x, pr.y, xm, xp, q0, q1);
             const double t = vt ? pair_toi_vt(q0, q1) : pair_toi_ee(q0, q1);
             tmin = fmin(tmin, t);
-            toi_finish(i, vt, nvt, pr, t, toi_vt, toi_ee, prev, prev_a, pvt, pee, keep, cand_a, do_merge);
+            toi_finish(i, vt, nvt, t, toi_vt, toi_ee, keep, cand_a, do_merge);
         }
         __syncthreads();   // the queue is reused by the next chunk
     }
@@ -943,6 +1081,41 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
     __syncthreads();
     if (threadIdx.x == 0) tpart[blockIdx.x] = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+}
+
+// Second half of the constraint-set update, C_o = {TOI <= 1} U (C_{o-1}
+// intersected with the candidates): each pair of the previous set looks
+// itself up among the candidates of its query (the candidate list is grouped
+// by query at the offsets ofs and sorted by target inside a group) and, when
+// found, keeps that candidate and hands it its life span.  Runs after
+// k_toi_merge, which set keep = (TOI <= 1) and a = 0 for every candidate.
+__global__ void __launch_bounds__(256) k_prev_match(const int* __restrict__ cnt, const int2* __restrict__ prev,
+                                                    const int* __restrict__ prev_a, const int2* __restrict__ cvt,
+                                                    const int2* __restrict__ cee, const int* __restrict__ vofs,
+                                                    const int* __restrict__ eofs, int nv, int ne, int* keep,
+                                                    int* cand_a) {
+    const int nvt = cnt[0], nee = cnt[1], pvt = cnt[4], pee = cnt[5];
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < pvt + pee; p += gridDim.x * blockDim.x) {
+        const bool vt = p < pvt;
+        const int2 pr = prev[p];
+        const int nq = vt ? nv : ne, nl = vt ? nvt : nee;
+        if (pr.x < 0 || pr.x >= nq) continue;
+        const int* ofs = vt ? vofs : eofs;
+        const int2* list = vt ? cvt : cee;
+        int lo = min(ofs[pr.x], nl);
+        const int end = pr.x + 1 < nq ? min(ofs[pr.x + 1], nl) : nl;
+        int hi = end;
+        while (lo < hi) {   // first candidate of the query with target >= pr.y
+            const int mid = (lo + hi) >> 1;
+            if (list[mid].y < pr.y) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < end && list[lo].x == pr.x && list[lo].y == pr.y) {
+            const int i = (vt ? 0 : nvt) + lo;
+            keep[i] = 1;
+            cand_a[i] = prev_a[p];
+        }
+    }
 }
 
 // obstacles: TOI on (xm, xp) and membership with carried life spans
@@ -1288,7 +1461,7 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
                 for (int a = 0; a < 8; ++a) wa[a] = ws[vv][ti * 8 + a];
                 for (int b = 0; b < 8; ++b) ub[b] = us[vv][tj * 8 + b];
                 for (int a = 0; a < 8; ++a)
-                    for (int b = 0; b < 8; ++b) acc[a][b] += wa[a] * ub[b];
+                    for (int b = 0; b < 8; ++b) acc[a][b] = fma(wa[a], ub[b], acc[a][b]);
             }
         }
     }
@@ -1362,66 +1535,28 @@ __global__ void __launch_bounds__(256) k_gram_final(Dev d, const double* __restr
     Arm[e] = s;
 }
 
-// One workgroup: Cholesky of A (FP64, packed row-major in LDS); writes the
-// factor L (strictly lower part) and 1 / s_k (s_k = L(k, k)) for the
-// triangular solves.  Right-looking elimination without square roots: at
-// step k, A(i, j) -= A(i, k) A(j, k) / A(k, k) for k < j <= i.  The entries
-// of the trailing triangle (size m = r - k - 1) are dealt densely over the
-// threads: thread t takes the entries t + 1024 q of the row-major
-// enumeration of a triangle, whose (row, column) offsets it keeps in
-// registers (the first m (m + 1) / 2 of them form the triangle of size m).
-// One barrier per step.  Then L(i, k) = A(i, k) / s_k.
-constexpr int CHOL_T = (MAX_R * (MAX_R - 1) / 2 + 1023) / 1024;
-__global__ void __launch_bounds__(1024) k_chol_factor(Dev d, const double* __restrict__ Arm,
-                                                      const int* __restrict__ n_cv, double* __restrict__ Lout) {
-    if (*n_cv == 0) return;
+// q = A^{-1} g for the three coordinates (Eq. (subspace_collision)), in one
+// workgroup.  A = Lambda~ + U_C^T diag(W) U_C (packed row-major, from
+// k_gram_final) is factored in LDS as A = L D L^T without square roots: at
+// elimination step k, A(i, j) -= A(i, k) A(j, k) / A(k, k) for k < j <= i,
+// so that afterwards L(i, k) = A(i, k) / A(k, k) and D = diag(A).  The
+// elimination goes by panels of 16 columns with three barriers each: one
+// wavefront eliminates the panel's diagonal block column by column, a thread
+// per row below applies those columns to its row of the panel, and the
+// trailing triangle receives the panel's rank-16 update in 4 x 4 register
+// tiles.  The triangular solves are done by one wavefront on the factor in
+// LDS (lane l holds rows l, l + 64, l + 128 of the three right-hand sides;
+// the LDS entries of the next four columns are requested before the current
+// four are applied).  Without contact vertices A = Lambda~, whose
+// precomputed inverse is applied instead.
+constexpr int CHOL_PANEL = 16;
+__global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __restrict__ Arm,
+                                                     const double* __restrict__ g, const int* __restrict__ n_cv) {
     extern __shared__ double A[];
     const int r = d.r;
-    const int tot = r * (r + 1) / 2;
-    double* rinv = A + tot;   // r
-    const int tid = threadIdx.x;
-    for (int e = tid; e < tot; e += 1024) A[e] = Arm[e];
-    int tdi[CHOL_T], tdj[CHOL_T];
-#pragma unroll
-    for (int t = 0; t < CHOL_T; ++t) tri_rc(tid + 1024 * t, tdi[t], tdj[t]);
-    __syncthreads();
-    for (int k = 0; k < r - 1; ++k) {
-        const int m = r - k - 1;
-        const int mt = m * (m + 1) / 2;
-        const double inv = 1.0 / A[rm(k, k)];
-#pragma unroll
-        for (int t = 0; t < CHOL_T; ++t) {
-            if (tid + 1024 * t >= mt) break;
-            const int i = k + 1 + tdi[t], j = k + 1 + tdj[t];
-            A[rm(i, j)] -= A[rm(i, k)] * A[rm(j, k)] * inv;
-        }
-        __syncthreads();
-    }
-    for (int k = tid; k < r; k += 1024) rinv[k] = 1.0 / sqrt(A[rm(k, k)]);
-    __syncthreads();
-    for (int e = tid; e < tot; e += 1024) {
-        int i, k;
-        tri_rc(e, i, k);
-        Lout[e] = (i > k) ? A[e] * rinv[k] : 0.0;
-    }
-    for (int k = tid; k < r; k += 1024) Lout[tot + k] = rinv[k];
-}
-
-// q = A^{-1} g from the factor (three wavefronts, one per coordinate; lane
-// l holds rows l + 64 j).  Forward and backward substitution by 64-row
-// blocks: inside a block the lane's factor entries are held in registers
-// and row k's value is broadcast from its lane; the other blocks are
-// updated by a block product.  Without contact vertices A = Lambda~ and its
-// precomputed inverse is applied instead.
-__global__ void __launch_bounds__(192) k_chol_tri(Dev d, const double* __restrict__ Lg, const double* __restrict__ g,
-                                                  const int* __restrict__ n_cv) {
-    extern __shared__ double sl[];
-    const int r = d.r;
-    const int tot = r * (r + 1) / 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int c = wave;   // right-hand side of this wavefront
     if (*n_cv == 0) {   // a wavefront per row of A^{-1}, lanes over its columns
-        for (int row = wave; row < r; row += 3) {
+        for (int row = wave; row < r; row += 16) {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
             for (int j = lane; j < r; j += 64) {
                 const double a = d.Ainv[(size_t)row * r + j];
@@ -1445,94 +1580,211 @@ __global__ void __launch_bounds__(192) k_chol_tri(Dev d, const double* __restric
         }
         return;
     }
-    for (int e = tid; e < tot + r; e += blockDim.x) sl[e] = Lg[e];
+    const int tot = r * (r + 1) / 2;
+    double* dinv = A + tot;   // 1 / A(k, k) once column k is final
+    for (int e = tid; e < tot; e += 1024) A[e] = Arm[e];
     __syncthreads();
-    const double* L = sl;
-    const double* rinv = sl + tot;
+    for (int p0 = 0; p0 < r; p0 += CHOL_PANEL) {
+        const int pe = min(r, p0 + CHOL_PANEL), w = pe - p0;   // w = 16, or 8 for the last panel
+        // 1. the panel's diagonal block, one wavefront: each lane owns up to
+        // three (row, column) entries of the block's lower triangle
+        if (wave == 0) {
+            int ei[3], ej[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int e = lane + 64 * t;
+                ei[t] = -1;
+                ej[t] = 0;
+                if (e < w * (w + 1) / 2) {
+                    int a, b;
+                    tri_rc(e, a, b);
+                    ei[t] = p0 + a;
+                    ej[t] = p0 + b;
+                }
+            }
+            for (int k = p0; k < pe - 1; ++k) {
+                const double inv = 1.0 / A[rm(k, k)];
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+                    if (ei[t] >= 0 && ej[t] > k)
+                        A[rm(ei[t], ej[t])] = fma(-A[rm(ei[t], k)] * inv, A[rm(ej[t], k)], A[rm(ei[t], ej[t])]);
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (lane < w) dinv[p0 + lane] = 1.0 / A[rm(p0 + lane, p0 + lane)];
+        }
+        __syncthreads();
+        // 2. the panel's part of every row below the block, a thread per row
+        for (int i = pe + tid; i < r; i += 1024) {
+            double a[CHOL_PANEL];
+#pragma unroll
+            for (int t = 0; t < CHOL_PANEL; ++t) a[t] = t < w ? A[rm(i, p0 + t)] : 0.0;
+#pragma unroll
+            for (int k = 0; k < CHOL_PANEL - 1; ++k) {
+                const double f = k < w - 1 ? a[k] * dinv[p0 + k] : 0.0;
+#pragma unroll
+                for (int j = k + 1; j < CHOL_PANEL; ++j)
+                    if (j < w) a[j] = fma(-f, A[rm(p0 + j, p0 + k)], a[j]);
+            }
+#pragma unroll
+            for (int t = 0; t < CHOL_PANEL; ++t)
+                if (t < w) A[rm(i, p0 + t)] = a[t];
+        }
+        __syncthreads();
+        // 3. trailing triangle: A(i, j) -= sum over the panel's k of
+        // A(i, k) A(j, k) / A(k, k), 4 x 4 tiles (r - pe is a multiple of 8)
+        const int nt4 = (r - pe) / 4;
+        for (int t = tid; t < nt4 * (nt4 + 1) / 2; t += 1024) {
+            int I, J;
+            tri_rc(t, I, J);
+            const int i0 = pe + 4 * I, j0 = pe + 4 * J;
+            double acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+            for (int k0 = 0; k0 < w; k0 += 2) {
+                double ai[4][2], aj[4][2];
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    const double dk = dinv[p0 + k0 + kk];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        ai[a][kk] = A[rm(i0 + a, p0 + k0 + kk)] * dk;
+                        aj[a][kk] = A[rm(j0 + a, p0 + k0 + kk)];
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+#pragma unroll
+                        for (int kk = 0; kk < 2; ++kk) acc[a][b] = fma(ai[a][kk], aj[b][kk], acc[a][b]);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (I != J || b <= a) A[rm(i0 + a, j0 + b)] -= acc[a][b];
+        }
+        __syncthreads();
+    }
+    if (wave != 0) return;
+    // L y = g (L unit lower), then q = L^{-T} D^{-1} y.  Row slot q of a
+    // lane holds row lane + 64 q; slots past r are skipped, and the slot
+    // being worked on is a compile-time index (the outer loops over it are
+    // unrolled), so no per-step selects are needed.
     constexpr int RPL = (MAX_R + 63) / 64;
-    const int nb = (r + 63) / 64;
-    double y[RPL];
+    const int nslot = (r + 63) / 64;
+    auto bcast = [](double v, int src) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    };
+    double y[RPL][3], di[RPL];
+    int ic[RPL];   // the slot's row, clamped into the matrix for addressing
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
         const int i = lane + 64 * q;
-        y[q] = i < r ? g[i * 3 + c] : 0.0;
+        ic[q] = min(i, r - 1);
+        di[q] = i < r ? dinv[i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) y[q][c] = i < r ? g[i * 3 + c] : 0.0;
     }
-    auto bcast = [](double v, int src) {
-        long long b = __double_as_longlong(v);
-        int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
-        int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    // forward: step k applies column k (y(k) final) to the rows below it;
+    // the entries of the next four columns are loaded while the current four
+    // are applied (clamped addresses, zeroed where the row is not below k)
+    double cur[4][RPL], nxt[4][RPL];
+    auto load_fwd = [&](int k0, int qk, double (&buf)[4][RPL]) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int i = lane + 64 * q, k = min(k0 + kk, r - 1);
+                const double v = (q >= qk && q < nslot) ? A[rm(ic[q], k)] : 0.0;
+                buf[kk][q] = (i > k0 + kk && i < r) ? v : 0.0;
+            }
     };
-    // forward: L y' = g
 #pragma unroll
-    for (int qb = 0; qb < RPL; ++qb) {
-        if (qb >= nb) break;
-        const int i = lane + 64 * qb;
-        double lr[64], rv[64];
+    for (int qk = 0; qk < RPL; ++qk) {
+        if (qk >= nslot) break;
+        const int kend = min(r, 64 * qk + 64);
+        load_fwd(64 * qk, qk, cur);
+        for (int k0 = 64 * qk; k0 < kend; k0 += 4) {
+            load_fwd(k0 + 4, qk, nxt);
 #pragma unroll
-        for (int kk = 0; kk < 64; ++kk) {
-            const int k = 64 * qb + kk;
-            lr[kk] = (k < i && i < r) ? L[rm(i, k)] : 0.0;
-            rv[kk] = k < r ? rinv[k] : 0.0;
-        }
-        double yb = y[qb];
+            for (int kk = 0; kk < 4; ++kk) {
+                const int src = (k0 + kk) & 63;
+                const double s = bcast(di[qk], src);
+                double yk[3];
 #pragma unroll
-        for (int kk = 0; kk < 64; ++kk) {
-            const double yk = bcast(yb, kk) * rv[kk];
-            yb = (lane == kk) ? yk : yb - lr[kk] * yk;
-        }
-        y[qb] = yb;
+                for (int c = 0; c < 3; ++c) yk[c] = bcast(y[qk][c], src) * s;
 #pragma unroll
-        for (int q = qb + 1; q < RPL; ++q) {
-            if (q >= nb) break;
-            const int i2 = lane + 64 * q;
-            double acc = 0.0;
+                for (int q = qk; q < RPL; ++q)
+                    if (q < nslot)
 #pragma unroll
-            for (int kk = 0; kk < 64; ++kk) {
-                const double yk = bcast(yb, kk);
-                if (i2 < r) acc += L[rm(i2, 64 * qb + kk)] * yk;
+                        for (int c = 0; c < 3; ++c) y[q][c] = fma(-cur[kk][q], yk[c], y[q][c]);
             }
-            y[q] -= acc;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) cur[kk][q] = nxt[kk][q];
         }
     }
-    // backward: L^T q = y'
+    // backward: with z = D^{-1} y, q(i) = z(i) - (1 / A(i, i)) sum_{k > i} A(k, i) q(k);
+    // acc holds the sums, and row k's value is final when step k broadcasts it
+    double acc[RPL][3];
 #pragma unroll
-    for (int qb = RPL - 1; qb >= 0; --qb) {
-        if (qb >= nb) continue;
-        const int i = lane + 64 * qb;
+    for (int q = 0; q < RPL; ++q)
 #pragma unroll
-        for (int q = qb + 1; q < RPL; ++q) {
-            if (q >= nb) break;
-            double acc = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            y[q][c] *= di[q];
+            acc[q][c] = 0.0;
+        }
+    auto load_bwd = [&](int k0, int qk, double (&buf)[4][RPL]) {   // columns k0, k0 - 1, k0 - 2, k0 - 3
 #pragma unroll
-            for (int kk = 0; kk < 64; ++kk) {
-                const int k = 64 * q + kk;
-                const double xk = bcast(y[q], kk);
-                if (k < r && i < r) acc += L[rm(k, i)] * xk;
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int i = lane + 64 * q, k = max(k0 - kk, 0);
+                const double v = q <= qk ? A[rm(k, min(ic[q], k))] : 0.0;
+                buf[kk][q] = (i < k0 - kk) ? v : 0.0;
             }
-            y[qb] -= acc;
-        }
-        double lr[64], rv[64];
+    };
 #pragma unroll
-        for (int kk = 0; kk < 64; ++kk) {
-            const int k = 64 * qb + kk;
-            lr[kk] = (i < k && k < r) ? L[rm(k, i)] : 0.0;
-            rv[kk] = k < r ? rinv[k] : 0.0;
-        }
-        double yb = y[qb];
+    for (int qk = RPL - 1; qk >= 0; --qk) {
+        if (qk >= nslot) continue;
+        const int ktop = min(r, 64 * qk + 64) - 1;   // r is a multiple of 8
+        load_bwd(ktop, qk, cur);
+        for (int k0 = ktop; k0 >= 64 * qk; k0 -= 4) {
+            load_bwd(k0 - 4, qk, nxt);
 #pragma unroll
-        for (int kk = 63; kk >= 0; --kk) {
-            const double xk = bcast(yb, kk) * rv[kk];
-            yb = (lane == kk) ? xk : yb - lr[kk] * xk;
+            for (int kk = 0; kk < 4; ++kk) {
+                const int src = (k0 - kk) & 63;
+                double qv[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) qv[c] = bcast(fma(-di[qk], acc[qk][c], y[qk][c]), src);
+#pragma unroll
+                for (int q = 0; q <= qk; ++q)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[q][c] = fma(cur[kk][q], qv[c], acc[q][c]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) cur[kk][q] = nxt[kk][q];
         }
-        y[qb] = yb;
     }
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
         const int i = lane + 64 * q;
         if (i < r) {
-            d.Qd[i * 3 + c] = y[q];
-            d.Qf[i * 3 + c] = (float)y[q];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double v = fma(-di[q], acc[q][c], y[q][c]);
+                d.Qd[i * 3 + c] = v;
+                d.Qf[i * 3 + c] = (float)v;
+            }
         }
     }
 }
@@ -1575,6 +1827,10 @@ __global__ void k_sum2(int* cnt) {
 }
 
 // ================================================================ host side
+
+// lanes per query of the counting pass, and its grid (one group per query)
+constexpr int QUERY_LANES = 16;
+static inline int qblocks(int64_t nq) { return (int)std::max<int64_t>(1, (nq + 256 / QUERY_LANES - 1) / (256 / QUERY_LANES)); }
 
 static inline int gblocks(int64_t n) {
     int64_t b = (n + TPB - 1) / TPB;
@@ -1684,9 +1940,7 @@ cloth_status contact_upload(Scene& s, ContactState& c) {
     double one = 1.0;
     HC(hipMemcpy(c.s_dev, &one, 8, hipMemcpyHostToDevice));
     HC(hipMemset(c.vslot_ptr, 0, sizeof(int) * (n + 1)));
-    HC(hipFuncSetAttribute((const void*)k_chol_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
-                           (int)chol_lds_bytes(s.r)));
-    HC(hipFuncSetAttribute((const void*)k_chol_tri, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HC(hipFuncSetAttribute((const void*)k_chol_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
                            (int)chol_lds_bytes(s.r)));
     return CLOTH_OK;
 }
@@ -1726,21 +1980,23 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
         int2* outp = vt ? c.cand_vt : c.cand_ee;
         const float* qb = vt ? c.vbox : c.ebox;
         if (vt)
-            hipLaunchKernelGGL((k_query<true, 0>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr, c.rec,
-                               P, cnts, (const int*)nullptr, c.qscratch, outp, c.cap, c.max_out, c.cnt + 7);
+            hipLaunchKernelGGL((k_query_count<true, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
+                               c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7);
         else
-            hipLaunchKernelGGL((k_query<false, 0>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
-                               c.rec, P, cnts, (const int*)nullptr, c.qscratch, outp, c.cap, c.max_out, c.cnt + 7);
+            hipLaunchKernelGGL((k_query_count<false, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
+                               c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7);
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, c.keep, cnts, nq);
         HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, st));
         hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
                            c.cnt + 7);
+        hipLaunchKernelGGL(k_query_copy<QUERY_LANES>, dim3(qblocks(nq)), dim3(256), 0, st, nq, (const int*)cnts,
+                           (const int*)c.keep, (const int*)c.qscratch, outp, c.cap);
         if (vt)
-            hipLaunchKernelGGL((k_query<true, 1>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr, c.rec,
-                               P, cnts, (const int*)c.keep, c.qscratch, outp, c.cap, c.max_out, c.cnt + 7);
+            hipLaunchKernelGGL(k_query_rescan<true>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
+                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, c.cap, c.max_out, c.cnt + 7);
         else
-            hipLaunchKernelGGL((k_query<false, 1>), dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
-                               c.rec, P, cnts, (const int*)c.keep, c.qscratch, outp, c.cap, c.max_out, c.cnt + 7);
+            hipLaunchKernelGGL(k_query_rescan<false>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
+                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, c.cap, c.max_out, c.cnt + 7);
     }
     HC(hipGetLastError());
     return CLOTH_OK;
@@ -1755,8 +2011,11 @@ static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm,
     if (s.self_contact) {
         const int nb = gblocks(2 * c.cap);
         hipLaunchKernelGGL(k_toi_merge, dim3(nb), dim3(TPB), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
-                           c.cand_vt, c.cand_ee, c.cnt, c.toi_vt,
-                           c.toi_ee, c.cpair_prev, c.ca_prev, c.keep, c.cand_a, c.tpart, 1);
+                           c.cand_vt, c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.keep, c.cand_a, c.tpart, 1);
+        hipLaunchKernelGGL(k_prev_match, dim3(gblocks(c.ccap)), dim3(TPB), 0, st, (const int*)c.cnt,
+                           (const int2*)c.cpair_prev, (const int*)c.ca_prev, (const int2*)c.cand_vt,
+                           (const int2*)c.cand_ee, (const int*)c.vcount, (const int*)c.ecount, n, s.ne, c.keep,
+                           c.cand_a);
         npart = nb;
     }
     if (c.nob > 0) {
@@ -1806,11 +2065,6 @@ static cloth_status outer_stage(Scene& s, ContactState& c, const float* xm, cons
     hipLaunchKernelGGL(k_save_prev, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, c.cnt, c.cpair, c.ca, c.cpair_prev,
                        c.ca_prev, first ? 1 : 0);
     hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, st, c.cnt, first ? 1 : 0, c.tmin_bits);
-    if (first) {
-        // the previous set of the first stage is empty; the current one too
-        int z[2] = {0, 0};
-        (void)z;
-    }
     cloth_status rc = broad_phase(s, c, xm, xp, st);
     if (rc != CLOTH_OK) return rc;
     rc = toi_merge_filter(s, c, xm, xp, st);
@@ -1856,14 +2110,11 @@ cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st) {
     const int tot = s.r * (s.r + 1) / 2;
     double* gred = d.Amat;
     double* Arm = d.Amat + (size_t)GRAM_GROUPS * tot;
-    double* Lfac = Arm + tot;
     hipLaunchKernelGGL(k_gram_reduce, dim3((tot + 255) / 256, GRAM_GROUPS), dim3(256), 0, st, d, d.gram_part,
                        c.gram_chunks, c.cnt + 6, gred);
     hipLaunchKernelGGL(k_gram_final, dim3((tot + 255) / 256), dim3(256), 0, st, d, (const double*)gred, c.cnt + 6,
                        Arm);
-    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm,
-                       c.cnt + 6, Lfac);
-    hipLaunchKernelGGL(k_chol_tri, dim3(1), dim3(192), chol_lds_bytes(s.r), st, d, (const double*)Lfac, c.gvec,
+    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm, c.gvec,
                        c.cnt + 6);
     HC(hipGetLastError());
     return CLOTH_OK;
@@ -1899,6 +2150,7 @@ cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step
     out->n_candidates = (int64_t)h[0] + h[1];
     out->n_constraints = (int64_t)h[2] + h[3] + h[10];
     out->peak_candidates = h[12];
+    out->n_contact_vertices = h[6];
     HC(hipMemsetAsync(c.cnt + 12, 0, sizeof(int), st));
     if (h[7]) {
         // sticky since the last read: clear it, then report what overflowed
@@ -1966,8 +2218,8 @@ cloth_status contact_stage_toi(Scene& s, ContactState& c, const float* xm, const
     hipLaunchKernelGGL(k_aos4, dim3(gblocks(s.nv)), dim3(TPB), 0, nullptr, s.nv, (const float*)s.d.xm, c.xm4);
     hipLaunchKernelGGL(k_aos4, dim3(gblocks(s.nv)), dim3(TPB), 0, nullptr, s.nv, (const float*)s.d.xt, c.xp4);
     hipLaunchKernelGGL(k_toi_merge, dim3(gblocks(n_vt + n_ee)), dim3(TPB), 0, nullptr, s.d, (const float4*)c.xm4,
-                       (const float4*)c.xp4, c.cand_vt, c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.cpair_prev, c.ca_prev,
-                       c.keep, c.cand_a, c.tpart, 0);
+                       (const float4*)c.xp4, c.cand_vt, c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.keep, c.cand_a,
+                       c.tpart, 0);
     HC(hipGetLastError());
     HC(hipDeviceSynchronize());
     if (n_vt) HC(hipMemcpy(toi_vt, c.toi_vt, sizeof(double) * n_vt, hipMemcpyDeviceToHost));

@@ -18,8 +18,8 @@ constexpr int MAX_R = 192;        // widest basis: the packed FP64 Cholesky fact
 constexpr int GRAM_CHUNKS = 512;  // contact-vertex chunks of the Gram partials
 constexpr int GRAM_GROUPS_MAX = 16;  // chunk groups of the first FP64 reduction level
 
-// LDS of the contact-solve Cholesky and triangular solves: packed lower
-// triangle + r inverse pivot roots
+// LDS of the contact solve (factor and triangular solves in one workgroup):
+// packed lower triangle + r inverse pivots
 inline size_t chol_lds_bytes(int r) { return sizeof(double) * ((size_t)r * (r + 1) / 2 + r); }
 
 // Triangle record for the local step: corner ids, PD weight w = k_s * area,
@@ -66,7 +66,7 @@ struct Dev {
     double* Ainv;             // r * r (no-contact inverse of Lambda~)
     double* Lam;              // r * r
     double* Amat;             // contact reduced matrix work: FP64 group sums of U^T W U
-                              // (GRAM_GROUPS_MAX packed triangles), A (one), factor + 1/s_k
+                              // (GRAM_GROUPS_MAX packed triangles), then A (one)
     double* gram_part;        // GRAM_CHUNKS * r * r Gram partials (FP64)
     unsigned long long* dxbits;  // per-iteration max |dx| as double bits
     double* gvec;             // r * 3: g = U^T r0 (FP64)

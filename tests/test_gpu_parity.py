@@ -69,6 +69,29 @@ def test_broad_phase_and_toi_bit_exact(n, seed):
     assert np.abs(te[hit] - ote[hit]).max(initial=0) <= 1e-6
 
 
+def test_broad_phase_heavy_queries_bit_exact():
+    """A cloth scrambled in its plane (vertices moved by ~3 edge lengths)
+    stacks many layers, so that hundreds of queries have more than the 48
+    hits the counting pass keeps: those lists are found a second time by the
+    writing pass.  Both lists bit-exact with the oracle's."""
+    n = 20
+    sc = scenegen.drop_cloth(n, seed=7, obstacle="sphere", r=8, steps=1, d_hat=1e-3)
+    h = 1.0 / (n - 1)
+    rng = np.random.default_rng(7)
+    xm = (sc.x0 + rng.normal(0, 1, sc.x0.shape) * np.array([3 * h, 0.3 * h, 3 * h])).astype(np.float32)
+    xp = (xm + rng.normal(0, 0.1 * h, xm.shape)).astype(np.float32)
+    o, U, rho = oracle_side(sc, "fp32", rho=0.9)
+    g = gpu_side(sc, U, "fp32", 0.9, pair_capacity=512 * sc.nv)
+    vt, ee = g.stage_broad_phase(xm, xp, cap=512 * sc.nv)
+    ovt, oee = native.broad_phase(xm, xp, o.m.edges, o.m.tris, sc.d_hat)
+    hv, he = np.bincount(ovt[:, 0]), np.bincount(oee[:, 0])
+    print(f"[bp heavy] vt={len(vt)} ee={len(ee)} queries over 48 hits: vt {(hv > 48).sum()} ee {(he > 48).sum()} "
+          f"max {hv.max()}/{he.max()}", flush=True)
+    assert (hv > 48).sum() > 0 and (he > 48).sum() > 0
+    assert np.array_equal(vt, ovt)
+    assert np.array_equal(ee, oee)
+
+
 def contact_block(n=20, seed=3, precision="fp32", step=0.1):
     """A block state with pair and obstacle constraints on identical FP32 inputs."""
     sc = scenegen.drop_cloth(n, seed=seed, obstacle="sphere", r=8, steps=1, d_hat=2e-3, drop=0.002)
