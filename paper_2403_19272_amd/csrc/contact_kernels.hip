@@ -1535,21 +1535,212 @@ __global__ void __launch_bounds__(256) k_gram_final(Dev d, const double* __restr
     Arm[e] = s;
 }
 
+constexpr int CHOL_PANEL = 16;
+
+// One panel of W columns [p0, p0 + W) of the L D L^T elimination (W is a
+// compile-time width, so every loop below unrolls without bound checks and
+// the LDS loads of a step are issued together).
+template <int W>
+__device__ __forceinline__ void chol_panel(double* A, double* dinv, int r, int p0, int tid) {
+    const int wave = tid >> 6, lane = tid & 63;
+    // 1. the diagonal block, one wavefront; lane owns up to three entries
+    // (row, column) of the block's lower triangle
+    if (wave == 0) {
+        constexpr int NE = W * (W + 1) / 2;
+        int ei[3], ej[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int e = min(lane + 64 * t, NE - 1);
+            int a, b;
+            tri_rc(e, a, b);
+            ei[t] = a;
+            ej[t] = (lane + 64 * t < NE) ? b : W;   // W: owns nothing
+        }
+#pragma unroll
+        for (int k = 0; k < W - 1; ++k) {
+            const double inv = 1.0 / A[rm(p0 + k, p0 + k)];
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+                if (ej[t] > k && ej[t] < W) {
+                    const int i = p0 + ei[t], j = p0 + ej[t];
+                    A[rm(i, j)] = fma(-A[rm(i, p0 + k)] * inv, A[rm(j, p0 + k)], A[rm(i, j)]);
+                }
+        }
+        if (lane < W) dinv[p0 + lane] = 1.0 / A[rm(p0 + lane, p0 + lane)];
+    }
+    __syncthreads();
+    // 2. the panel's part of every row below the block, a thread per row
+    const int pe = p0 + W;
+    for (int i = pe + tid; i < r; i += 1024) {
+        double a[W];
+#pragma unroll
+        for (int t = 0; t < W; ++t) a[t] = A[rm(i, p0 + t)];
+#pragma unroll
+        for (int k = 0; k < W - 1; ++k) {
+            const double f = a[k] * dinv[p0 + k];
+#pragma unroll
+            for (int jj = k + 1; jj < W; ++jj) a[jj] = fma(-f, A[rm(p0 + jj, p0 + k)], a[jj]);
+        }
+#pragma unroll
+        for (int t = 0; t < W; ++t) A[rm(i, p0 + t)] = a[t];
+    }
+    __syncthreads();
+    // 3. trailing triangle: A(i, j) -= sum over the panel's k of
+    // A(i, k) A(j, k) / A(k, k), 4 x 4 tiles (r - pe is a multiple of 8)
+    const int nt4 = (r - pe) / 4;
+    for (int t = tid; t < nt4 * (nt4 + 1) / 2; t += 1024) {
+        int I, J;
+        tri_rc(t, I, J);
+        const int i0 = pe + 4 * I, j0 = pe + 4 * J;
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 2
+        for (int k0 = 0; k0 < W; k0 += 2) {
+            double ai[4][2], aj[4][2];
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const double dk = dinv[p0 + k0 + kk];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    ai[a][kk] = A[rm(i0 + a, p0 + k0 + kk)] * dk;
+                    aj[a][kk] = A[rm(j0 + a, p0 + k0 + kk)];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int kk = 0; kk < 2; ++kk) acc[a][b] = fma(ai[a][kk], aj[b][kk], acc[a][b]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (I != J || b <= a) A[rm(i0 + a, j0 + b)] -= acc[a][b];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double bcast_f64(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// L y = g (L unit lower), then q = L^{-T} D^{-1} y for right-hand side c,
+// by one wavefront on the factor in LDS (three wavefronts take the three
+// coordinates side by side).  NS = row slots in use (64 NS >= r): slot q of a
+// lane holds row lane + 64 q; the slot being worked on is a compile-time
+// index (the outer loops over it unroll), and the LDS entries of the next
+// four columns are loaded while the current four are applied.
+template <int NS>
+__device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* dinv, const double* __restrict__ g,
+                                         int r, int lane, int c) {
+    double y[NS], di[NS];
+    int ic[NS];   // the slot's row, clamped into the matrix for addressing
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int i = lane + 64 * q;
+        ic[q] = min(i, r - 1);
+        di[q] = i < r ? dinv[i] : 0.0;
+        y[q] = i < r ? g[i * 3 + c] : 0.0;
+    }
+    // forward: step k applies column k (y(k) final) to the rows below it
+    double cur[4][NS], nxt[4][NS];
+    auto load_fwd = [&](int k0, double (&buf)[4][NS]) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int i = lane + 64 * q, k = min(k0 + kk, r - 1);
+                const double v = A[rm(ic[q], min(k, ic[q]))];
+                buf[kk][q] = (i > k0 + kk && i < r) ? v : 0.0;
+            }
+    };
+#pragma unroll
+    for (int qk = 0; qk < NS; ++qk) {
+        const int kend = min(r, 64 * qk + 64);
+        load_fwd(64 * qk, cur);
+        for (int k0 = 64 * qk; k0 < kend; k0 += 4) {
+            load_fwd(k0 + 4, nxt);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int src = (k0 + kk) & 63;
+                const double yk = bcast_f64(y[qk] * di[qk], src);
+#pragma unroll
+                for (int q = qk; q < NS; ++q) y[q] = fma(-cur[kk][q], yk, y[q]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int q = 0; q < NS; ++q) cur[kk][q] = nxt[kk][q];
+        }
+    }
+    // backward: with z = D^{-1} y, q(i) = z(i) - (1 / A(i, i)) sum_{k > i} A(k, i) q(k);
+    // acc holds the sums, and row k's value is final when step k broadcasts it
+    double acc[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        y[q] *= di[q];
+        acc[q] = 0.0;
+    }
+    auto load_bwd = [&](int k0, double (&buf)[4][NS]) {   // columns k0, k0 - 1, k0 - 2, k0 - 3
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int i = lane + 64 * q, k = max(k0 - kk, 0);
+                const double v = A[rm(k, min(ic[q], k))];
+                buf[kk][q] = (i < k0 - kk) ? v : 0.0;
+            }
+    };
+#pragma unroll
+    for (int qk = NS - 1; qk >= 0; --qk) {
+        const int ktop = min(r, 64 * qk + 64) - 1;   // r is a multiple of 8
+        load_bwd(ktop, cur);
+        for (int k0 = ktop; k0 >= 64 * qk; k0 -= 4) {
+            load_bwd(k0 - 4, nxt);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int src = (k0 - kk) & 63;
+                const double qv = bcast_f64(fma(-di[qk], acc[qk], y[qk]), src);
+#pragma unroll
+                for (int q = 0; q <= qk; ++q) acc[q] = fma(cur[kk][q], qv, acc[q]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int q = 0; q < NS; ++q) cur[kk][q] = nxt[kk][q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int i = lane + 64 * q;
+        if (i < r) {
+            const double v = fma(-di[q], acc[q], y[q]);
+            d.Qd[i * 3 + c] = v;
+            d.Qf[i * 3 + c] = (float)v;
+        }
+    }
+}
+
 // q = A^{-1} g for the three coordinates (Eq. (subspace_collision)), in one
 // workgroup.  A = Lambda~ + U_C^T diag(W) U_C (packed row-major, from
 // k_gram_final) is factored in LDS as A = L D L^T without square roots: at
 // elimination step k, A(i, j) -= A(i, k) A(j, k) / A(k, k) for k < j <= i,
 // so that afterwards L(i, k) = A(i, k) / A(k, k) and D = diag(A).  The
-// elimination goes by panels of 16 columns with three barriers each: one
-// wavefront eliminates the panel's diagonal block column by column, a thread
-// per row below applies those columns to its row of the panel, and the
-// trailing triangle receives the panel's rank-16 update in 4 x 4 register
-// tiles.  The triangular solves are done by one wavefront on the factor in
-// LDS (lane l holds rows l, l + 64, l + 128 of the three right-hand sides;
-// the LDS entries of the next four columns are requested before the current
-// four are applied).  Without contact vertices A = Lambda~, whose
-// precomputed inverse is applied instead.
-constexpr int CHOL_PANEL = 16;
+// elimination goes by panels of 16 columns with three barriers each
+// (chol_panel), then three wavefronts solve on the factor in LDS (chol_tri).
+// Without contact vertices A = Lambda~, whose precomputed inverse is
+// applied instead.
+// NS: row slots of the solve, 2 for r <= 128 and 3 up to MAX_R (chosen on
+// the host; one instantiation per kernel keeps it within 128 VGPRs).
+template <int NS>
 __global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __restrict__ Arm,
                                                      const double* __restrict__ g, const int* __restrict__ n_cv) {
     extern __shared__ double A[];
@@ -1560,9 +1751,9 @@ __global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __rest
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
             for (int j = lane; j < r; j += 64) {
                 const double a = d.Ainv[(size_t)row * r + j];
-                a0 += a * g[j * 3];
-                a1 += a * g[j * 3 + 1];
-                a2 += a * g[j * 3 + 2];
+                a0 = fma(a, g[j * 3], a0);
+                a1 = fma(a, g[j * 3 + 1], a1);
+                a2 = fma(a, g[j * 3 + 2], a2);
             }
             for (int o = 32; o > 0; o >>= 1) {
                 a0 += __shfl_xor(a0, o);
@@ -1584,209 +1775,11 @@ __global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __rest
     double* dinv = A + tot;   // 1 / A(k, k) once column k is final
     for (int e = tid; e < tot; e += 1024) A[e] = Arm[e];
     __syncthreads();
-    for (int p0 = 0; p0 < r; p0 += CHOL_PANEL) {
-        const int pe = min(r, p0 + CHOL_PANEL), w = pe - p0;   // w = 16, or 8 for the last panel
-        // 1. the panel's diagonal block, one wavefront: each lane owns up to
-        // three (row, column) entries of the block's lower triangle
-        if (wave == 0) {
-            int ei[3], ej[3];
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const int e = lane + 64 * t;
-                ei[t] = -1;
-                ej[t] = 0;
-                if (e < w * (w + 1) / 2) {
-                    int a, b;
-                    tri_rc(e, a, b);
-                    ei[t] = p0 + a;
-                    ej[t] = p0 + b;
-                }
-            }
-            for (int k = p0; k < pe - 1; ++k) {
-                const double inv = 1.0 / A[rm(k, k)];
-#pragma unroll
-                for (int t = 0; t < 3; ++t)
-                    if (ei[t] >= 0 && ej[t] > k)
-                        A[rm(ei[t], ej[t])] = fma(-A[rm(ei[t], k)] * inv, A[rm(ej[t], k)], A[rm(ei[t], ej[t])]);
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (lane < w) dinv[p0 + lane] = 1.0 / A[rm(p0 + lane, p0 + lane)];
-        }
-        __syncthreads();
-        // 2. the panel's part of every row below the block, a thread per row
-        for (int i = pe + tid; i < r; i += 1024) {
-            double a[CHOL_PANEL];
-#pragma unroll
-            for (int t = 0; t < CHOL_PANEL; ++t) a[t] = t < w ? A[rm(i, p0 + t)] : 0.0;
-#pragma unroll
-            for (int k = 0; k < CHOL_PANEL - 1; ++k) {
-                const double f = k < w - 1 ? a[k] * dinv[p0 + k] : 0.0;
-#pragma unroll
-                for (int j = k + 1; j < CHOL_PANEL; ++j)
-                    if (j < w) a[j] = fma(-f, A[rm(p0 + j, p0 + k)], a[j]);
-            }
-#pragma unroll
-            for (int t = 0; t < CHOL_PANEL; ++t)
-                if (t < w) A[rm(i, p0 + t)] = a[t];
-        }
-        __syncthreads();
-        // 3. trailing triangle: A(i, j) -= sum over the panel's k of
-        // A(i, k) A(j, k) / A(k, k), 4 x 4 tiles (r - pe is a multiple of 8)
-        const int nt4 = (r - pe) / 4;
-        for (int t = tid; t < nt4 * (nt4 + 1) / 2; t += 1024) {
-            int I, J;
-            tri_rc(t, I, J);
-            const int i0 = pe + 4 * I, j0 = pe + 4 * J;
-            double acc[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-            for (int k0 = 0; k0 < w; k0 += 2) {
-                double ai[4][2], aj[4][2];
-#pragma unroll
-                for (int kk = 0; kk < 2; ++kk) {
-                    const double dk = dinv[p0 + k0 + kk];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        ai[a][kk] = A[rm(i0 + a, p0 + k0 + kk)] * dk;
-                        aj[a][kk] = A[rm(j0 + a, p0 + k0 + kk)];
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-#pragma unroll
-                        for (int kk = 0; kk < 2; ++kk) acc[a][b] = fma(ai[a][kk], aj[b][kk], acc[a][b]);
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (I != J || b <= a) A[rm(i0 + a, j0 + b)] -= acc[a][b];
-        }
-        __syncthreads();
-    }
-    if (wave != 0) return;
-    // L y = g (L unit lower), then q = L^{-T} D^{-1} y.  Row slot q of a
-    // lane holds row lane + 64 q; slots past r are skipped, and the slot
-    // being worked on is a compile-time index (the outer loops over it are
-    // unrolled), so no per-step selects are needed.
-    constexpr int RPL = (MAX_R + 63) / 64;
-    const int nslot = (r + 63) / 64;
-    auto bcast = [](double v, int src) {
-        const long long b = __double_as_longlong(v);
-        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
-        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-    };
-    double y[RPL][3], di[RPL];
-    int ic[RPL];   // the slot's row, clamped into the matrix for addressing
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-        const int i = lane + 64 * q;
-        ic[q] = min(i, r - 1);
-        di[q] = i < r ? dinv[i] : 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) y[q][c] = i < r ? g[i * 3 + c] : 0.0;
-    }
-    // forward: step k applies column k (y(k) final) to the rows below it;
-    // the entries of the next four columns are loaded while the current four
-    // are applied (clamped addresses, zeroed where the row is not below k)
-    double cur[4][RPL], nxt[4][RPL];
-    auto load_fwd = [&](int k0, int qk, double (&buf)[4][RPL]) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const int i = lane + 64 * q, k = min(k0 + kk, r - 1);
-                const double v = (q >= qk && q < nslot) ? A[rm(ic[q], k)] : 0.0;
-                buf[kk][q] = (i > k0 + kk && i < r) ? v : 0.0;
-            }
-    };
-#pragma unroll
-    for (int qk = 0; qk < RPL; ++qk) {
-        if (qk >= nslot) break;
-        const int kend = min(r, 64 * qk + 64);
-        load_fwd(64 * qk, qk, cur);
-        for (int k0 = 64 * qk; k0 < kend; k0 += 4) {
-            load_fwd(k0 + 4, qk, nxt);
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int src = (k0 + kk) & 63;
-                const double s = bcast(di[qk], src);
-                double yk[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) yk[c] = bcast(y[qk][c], src) * s;
-#pragma unroll
-                for (int q = qk; q < RPL; ++q)
-                    if (q < nslot)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) y[q][c] = fma(-cur[kk][q], yk[c], y[q][c]);
-            }
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                for (int q = 0; q < RPL; ++q) cur[kk][q] = nxt[kk][q];
-        }
-    }
-    // backward: with z = D^{-1} y, q(i) = z(i) - (1 / A(i, i)) sum_{k > i} A(k, i) q(k);
-    // acc holds the sums, and row k's value is final when step k broadcasts it
-    double acc[RPL][3];
-#pragma unroll
-    for (int q = 0; q < RPL; ++q)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            y[q][c] *= di[q];
-            acc[q][c] = 0.0;
-        }
-    auto load_bwd = [&](int k0, int qk, double (&buf)[4][RPL]) {   // columns k0, k0 - 1, k0 - 2, k0 - 3
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const int i = lane + 64 * q, k = max(k0 - kk, 0);
-                const double v = q <= qk ? A[rm(k, min(ic[q], k))] : 0.0;
-                buf[kk][q] = (i < k0 - kk) ? v : 0.0;
-            }
-    };
-#pragma unroll
-    for (int qk = RPL - 1; qk >= 0; --qk) {
-        if (qk >= nslot) continue;
-        const int ktop = min(r, 64 * qk + 64) - 1;   // r is a multiple of 8
-        load_bwd(ktop, qk, cur);
-        for (int k0 = ktop; k0 >= 64 * qk; k0 -= 4) {
-            load_bwd(k0 - 4, qk, nxt);
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int src = (k0 - kk) & 63;
-                double qv[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) qv[c] = bcast(fma(-di[qk], acc[qk][c], y[qk][c]), src);
-#pragma unroll
-                for (int q = 0; q <= qk; ++q)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[q][c] = fma(cur[kk][q], qv[c], acc[q][c]);
-            }
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                for (int q = 0; q < RPL; ++q) cur[kk][q] = nxt[kk][q];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-        const int i = lane + 64 * q;
-        if (i < r) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double v = fma(-di[q], acc[q][c], y[q][c]);
-                d.Qd[i * 3 + c] = v;
-                d.Qf[i * 3 + c] = (float)v;
-            }
-        }
-    }
+    int p0 = 0;
+    for (; p0 + CHOL_PANEL <= r; p0 += CHOL_PANEL) chol_panel<CHOL_PANEL>(A, dinv, r, p0, tid);
+    if (p0 < r) chol_panel<CHOL_PANEL / 2>(A, dinv, r, p0, tid);   // r is a multiple of 8
+    if (wave >= 3) return;   // wavefront c solves for coordinate c
+    chol_tri<NS>(d, A, dinv, g, r, lane, wave);
 }
 
 
@@ -1940,7 +1933,9 @@ cloth_status contact_upload(Scene& s, ContactState& c) {
     double one = 1.0;
     HC(hipMemcpy(c.s_dev, &one, 8, hipMemcpyHostToDevice));
     HC(hipMemset(c.vslot_ptr, 0, sizeof(int) * (n + 1)));
-    HC(hipFuncSetAttribute((const void*)k_chol_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HC(hipFuncSetAttribute((const void*)k_chol_solve<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)chol_lds_bytes(s.r)));
+    HC(hipFuncSetAttribute((const void*)k_chol_solve<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
                            (int)chol_lds_bytes(s.r)));
     return CLOTH_OK;
 }
@@ -2114,8 +2109,12 @@ cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st) {
                        c.gram_chunks, c.cnt + 6, gred);
     hipLaunchKernelGGL(k_gram_final, dim3((tot + 255) / 256), dim3(256), 0, st, d, (const double*)gred, c.cnt + 6,
                        Arm);
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm, c.gvec,
-                       c.cnt + 6);
+    if (s.r <= 128)
+        hipLaunchKernelGGL(k_chol_solve<2>, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm,
+                           c.gvec, c.cnt + 6);
+    else
+        hipLaunchKernelGGL(k_chol_solve<3>, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm,
+                           c.gvec, c.cnt + 6);
     HC(hipGetLastError());
     return CLOTH_OK;
 }
