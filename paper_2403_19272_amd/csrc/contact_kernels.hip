@@ -1403,6 +1403,36 @@ __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, cons
 // 8 x 8 tile of the upper block triangle; blockIdx.y picks a group of 256
 // tiles, blockIdx.x a chunk of the contact-vertex list.  Vertices are staged
 // 16 at a time in LDS as W-scaled (FP64) and plain (FP32) rows.
+// Eight consecutive basis entries of a row (16 bytes of BF16 or 32 of FP32)
+template <typename UT>
+struct RowChunkG;
+template <>
+struct RowChunkG<uint16_t> {
+    uint4 a;
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ U, size_t off) {
+        a = *reinterpret_cast<const uint4*>(U + off);
+    }
+    __device__ __forceinline__ void unpack(float u[8]) const {
+        u[0] = __uint_as_float(a.x << 16); u[1] = __uint_as_float(a.x & 0xffff0000u);
+        u[2] = __uint_as_float(a.y << 16); u[3] = __uint_as_float(a.y & 0xffff0000u);
+        u[4] = __uint_as_float(a.z << 16); u[5] = __uint_as_float(a.z & 0xffff0000u);
+        u[6] = __uint_as_float(a.w << 16); u[7] = __uint_as_float(a.w & 0xffff0000u);
+    }
+};
+template <>
+struct RowChunkG<float> {
+    float4 a, b;
+    __device__ __forceinline__ void load(const float* __restrict__ U, size_t off) {
+        const float4* p = reinterpret_cast<const float4*>(U + off);
+        a = p[0];
+        b = p[1];
+    }
+    __device__ __forceinline__ void unpack(float u[8]) const {
+        u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
+        u[4] = b.x; u[5] = b.y; u[6] = b.z; u[7] = b.w;
+    }
+};
+
 constexpr int GRAM_MIN_PER_CHUNK = 32;
 __device__ __forceinline__ int gram_per_chunk(int ncv, int nchunk) {
     return max(GRAM_MIN_PER_CHUNK, (ncv + nchunk - 1) / nchunk);
@@ -1414,6 +1444,8 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
     constexpr int VB = 16;   // contact vertices staged per round
     __shared__ float us[VB][MAX_R];
     __shared__ double ws[VB][MAX_R];
+    __shared__ int vidx[VB];
+    __shared__ float wv[VB];
     const int r = d.r, T = r >> 3;
     const int ncv = *n_cv;
     const int per = gram_per_chunk(ncv, nchunk);
@@ -1438,21 +1470,34 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
     for (int a = 0; a < 8; ++a)
         for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
     const UT* U = static_cast<const UT*>(d.U);
+    const int ncg = r >> 3;   // groups of 8 basis columns per row
     for (int base = c0; base < c1; base += VB) {
         const int m = min(VB, c1 - base);
         __syncthreads();
-        for (int q = threadIdx.x; q < VB * r; q += 256) {
-            int vv = q / r, cc = q % r;
-            float u = 0.f, w = 0.f;
-            if (vv < m) {
-                int v = cvlist[base + vv];
-                UT raw = U[(size_t)v * r + cc];
-                if constexpr (sizeof(UT) == 2) u = __uint_as_float((uint32_t)raw << 16);
-                else u = (float)raw;
-                w = d.W[v];
+        // the round's vertices and weights first, then every row's 8-column
+        // groups with one wide load each, all independent of each other
+        if (threadIdx.x < VB) {
+            const int v = threadIdx.x < m ? cvlist[base + threadIdx.x] : -1;
+            vidx[threadIdx.x] = v;
+            wv[threadIdx.x] = v >= 0 ? d.W[v] : 0.f;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < VB * ncg; q += 256) {
+            const int vv = q / ncg, cg = q % ncg;
+            const int v = vidx[vv];
+            float u[8];
+            if (v >= 0) {
+                RowChunkG<UT> rc;
+                rc.load(U, (size_t)v * r + cg * 8);
+                rc.unpack(u);
+            } else {
+                for (int k = 0; k < 8; ++k) u[k] = 0.f;
             }
-            us[vv][cc] = u;
-            ws[vv][cc] = (double)w * (double)u;   // exact
+            const double w = (double)wv[vv];
+            for (int k = 0; k < 8; ++k) {
+                us[vv][cg * 8 + k] = u[k];
+                ws[vv][cg * 8 + k] = w * (double)u[k];   // exact
+            }
         }
         __syncthreads();
         if (active) {
