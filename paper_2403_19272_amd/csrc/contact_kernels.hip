@@ -1582,36 +1582,43 @@ __global__ void __launch_bounds__(256) k_gram_final(Dev d, const double* __restr
 
 constexpr int CHOL_PANEL = 16;
 
+__device__ __forceinline__ double bcast_f64(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // One panel of W columns [p0, p0 + W) of the L D L^T elimination (W is a
 // compile-time width, so every loop below unrolls without bound checks and
 // the LDS loads of a step are issued together).
 template <int W>
 __device__ __forceinline__ void chol_panel(double* A, double* dinv, int r, int p0, int tid) {
     const int wave = tid >> 6, lane = tid & 63;
-    // 1. the diagonal block, one wavefront; lane owns up to three entries
-    // (row, column) of the block's lower triangle
+    // 1. the diagonal block, one wavefront in registers: lane i < W holds row
+    // i of the block (entries j > i are placeholders that are updated but
+    // never stored); step k broadcasts the pivot and column k from the lanes
+    // that hold them
     if (wave == 0) {
-        constexpr int NE = W * (W + 1) / 2;
-        int ei[3], ej[3];
+        const int i = min(lane, W - 1);
+        double row[W];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int e = min(lane + 64 * t, NE - 1);
-            int a, b;
-            tri_rc(e, a, b);
-            ei[t] = a;
-            ej[t] = (lane + 64 * t < NE) ? b : W;   // W: owns nothing
-        }
+        for (int j = 0; j < W; ++j) row[j] = A[rm(p0 + i, p0 + min(j, i))];
 #pragma unroll
         for (int k = 0; k < W - 1; ++k) {
-            const double inv = 1.0 / A[rm(p0 + k, p0 + k)];
+            const double inv = 1.0 / bcast_f64(row[k], k);
+            if (lane == 0) dinv[p0 + k] = inv;
+            const double f = row[k] * inv;
 #pragma unroll
-            for (int t = 0; t < 3; ++t)
-                if (ej[t] > k && ej[t] < W) {
-                    const int i = p0 + ei[t], j = p0 + ej[t];
-                    A[rm(i, j)] = fma(-A[rm(i, p0 + k)] * inv, A[rm(j, p0 + k)], A[rm(i, j)]);
-                }
+            for (int j = k + 1; j < W; ++j) row[j] = fma(-f, bcast_f64(row[k], j), row[j]);
         }
-        if (lane < W) dinv[p0 + lane] = 1.0 / A[rm(p0 + lane, p0 + lane)];
+        const double last = 1.0 / bcast_f64(row[W - 1], W - 1);
+        if (lane == 0) dinv[p0 + W - 1] = last;
+        if (lane < W) {
+#pragma unroll
+            for (int j = 1; j < W; ++j)
+                if (j <= lane) A[rm(p0 + lane, p0 + j)] = row[j];
+        }
     }
     __syncthreads();
     // 2. the panel's part of every row below the block, a thread per row
@@ -1670,13 +1677,6 @@ __device__ __forceinline__ void chol_panel(double* A, double* dinv, int r, int p
     __syncthreads();
 }
 
-__device__ __forceinline__ double bcast_f64(double v, int src) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 // L y = g (L unit lower), then q = L^{-T} D^{-1} y for right-hand side c,
 // by one wavefront on the factor in LDS (three wavefronts take the three
 // coordinates side by side).  NS = row slots in use (64 NS >= r): slot q of a
@@ -1685,13 +1685,11 @@ __device__ __forceinline__ double bcast_f64(double v, int src) {
 // four columns are loaded while the current four are applied.
 template <int NS>
 __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* dinv, const double* __restrict__ g,
-                                         int r, int lane, int c) {
+                                         int r, int lane, int c, int zs) {
     double y[NS], di[NS];
-    int ic[NS];   // the slot's row, clamped into the matrix for addressing
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         const int i = lane + 64 * q;
-        ic[q] = min(i, r - 1);
         di[q] = i < r ? dinv[i] : 0.0;
         y[q] = i < r ? g[i * 3 + c] : 0.0;
     }
@@ -1702,9 +1700,11 @@ __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* 
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
-                const int i = lane + 64 * q, k = min(k0 + kk, r - 1);
-                const double v = A[rm(ic[q], min(k, ic[q]))];
-                buf[kk][q] = (i > k0 + kk && i < r) ? v : 0.0;
+                // entries outside the strict lower part read the zero at zs:
+                // the address is chosen, not the value, so that the loads
+                // are unconditional and their waits come only at the use
+                const int i = lane + 64 * q, k = k0 + kk;
+                buf[kk][q] = A[(i > k && i < r) ? rm(i, k) : zs];
             }
     };
 #pragma unroll
@@ -1739,9 +1739,8 @@ __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* 
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
-                const int i = lane + 64 * q, k = max(k0 - kk, 0);
-                const double v = A[rm(k, min(ic[q], k))];
-                buf[kk][q] = (i < k0 - kk) ? v : 0.0;
+                const int i = lane + 64 * q, k = k0 - kk;
+                buf[kk][q] = A[i < k ? rm(k, i) : zs];
             }
     };
 #pragma unroll
@@ -1819,12 +1818,14 @@ __global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __rest
     const int tot = r * (r + 1) / 2;
     double* dinv = A + tot;   // 1 / A(k, k) once column k is final
     for (int e = tid; e < tot; e += 1024) A[e] = Arm[e];
+    const int zs = tot + r;   // a zero entry for the solves
+    if (tid == 0) A[zs] = 0.0;
     __syncthreads();
     int p0 = 0;
     for (; p0 + CHOL_PANEL <= r; p0 += CHOL_PANEL) chol_panel<CHOL_PANEL>(A, dinv, r, p0, tid);
     if (p0 < r) chol_panel<CHOL_PANEL / 2>(A, dinv, r, p0, tid);   // r is a multiple of 8
     if (wave >= 3) return;   // wavefront c solves for coordinate c
-    chol_tri<NS>(d, A, dinv, g, r, lane, wave);
+    chol_tri<NS>(d, A, dinv, g, r, lane, wave, zs);
 }
 
 

@@ -19,8 +19,8 @@ constexpr int GRAM_CHUNKS = 512;  // contact-vertex chunks of the Gram partials
 constexpr int GRAM_GROUPS_MAX = 16;  // chunk groups of the first FP64 reduction level
 
 // LDS of the contact solve (factor and triangular solves in one workgroup):
-// packed lower triangle + r inverse pivots
-inline size_t chol_lds_bytes(int r) { return sizeof(double) * ((size_t)r * (r + 1) / 2 + r); }
+// packed lower triangle, r inverse pivots and one zero entry
+inline size_t chol_lds_bytes(int r) { return sizeof(double) * ((size_t)r * (r + 1) / 2 + r + 1); }
 
 // Triangle record for the local step: corner ids, PD weight w = k_s * area,
 // and the gradient rows g_j, g_k (g_i = -g_j - g_k) with F = sum_c x_c g_c^T.
