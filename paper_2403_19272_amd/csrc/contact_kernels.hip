@@ -1020,6 +1020,7 @@ __global__ void __launch_bounds__(256) k_query_rescan(Dev d, const float* __rest
 // [0, 1]); the rest go to an LDS queue that all lanes then drain, so the
 // root refinement and the inside tests run on full wavefronts.
 constexpr int TOI_CHUNK = 1024;
+constexpr int TOI_SCHED = 16;   // cnt[16..23]: next chunk of each XCD's range, cnt[24]: workgroups done
 
 __device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, double t, double* toi_vt, double* toi_ee,
                                            int* keep, int* cand_a, int do_merge) {
@@ -1033,24 +1034,44 @@ __device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, double t, do
 
 __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restrict__ xm, const float4* __restrict__ xp,
                                                    const int2* __restrict__ cvt, const int2* __restrict__ cee,
-                                                   const int* cnt, double* toi_vt, double* toi_ee, int* keep,
+                                                   int* cnt, double* toi_vt, double* toi_ee, int* keep,
                                                    int* cand_a, double* tpart, int do_merge) {
     __shared__ double wmin[4];
     __shared__ int queue[TOI_CHUNK];
-    __shared__ int qn;
+    __shared__ int qn, s_ch;
     const int nvt = cnt[0], nee = cnt[1];
     const int total = nvt + nee;
+    int* next = cnt + TOI_SCHED;   // next chunk of each XCD's range
     double tmin = NOHIT;
-    // chunks are split into 8 contiguous ranges, one per XCD (workgroups
+    // the chunks are split into 8 contiguous ranges, one per XCD (workgroups
     // are dealt round-robin over the XCDs), so that an XCD gathers the
-    // positions of one region of the cloth, which then stay in its L2
+    // positions of one region of the cloth, which then stay in its L2.
+    // Workgroups claim chunks of their XCD's range one at a time and, once
+    // it is used up, of the other ranges: the cost of a chunk varies (the
+    // share of pairs that need root refinement, the rare sampled fallback),
+    // and claiming keeps every CU busy until the last chunk is taken.
     const int nchunk = (total + TOI_CHUNK - 1) / TOI_CHUNK;
-    const int xcd = blockIdx.x % 8, nb_x = (gridDim.x - xcd + 7) / 8;
-    const int per_x = (nchunk + 7) / 8, c_end = min(nchunk, (xcd + 1) * per_x);
-    for (int ch = xcd * per_x + blockIdx.x / 8; ch < c_end; ch += nb_x) {
-        const int base = ch * TOI_CHUNK;
-        if (threadIdx.x == 0) qn = 0;
+    const int per_x = (nchunk + 7) / 8;
+    const int xcd = blockIdx.x % 8;
+    int range = 0;   // thread 0 only: ranges already used up
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int ch = -1;
+            for (; range < 8; ++range) {
+                const int x = (xcd + range) & 7;
+                const int c = x * per_x + atomicAdd(&next[x], 1);
+                if (c < min(nchunk, (x + 1) * per_x)) {
+                    ch = c;
+                    break;
+                }
+            }
+            s_ch = ch;
+            qn = 0;
+        }
         __syncthreads();
+        const int ch = s_ch;
+        if (ch < 0) break;
+        const int base = ch * TOI_CHUNK;
         for (int k = threadIdx.x; k < TOI_CHUNK; k += blockDim.x) {
             const int i = base + k;
             if (i >= total) break;
@@ -1075,12 +1096,20 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
             tmin = fmin(tmin, t);
             toi_finish(i, vt, nvt, t, toi_vt, toi_ee, keep, cand_a, do_merge);
         }
-        __syncthreads();   // the queue is reused by the next chunk
+        __syncthreads();   // the queue, qn and s_ch are reused by the next chunk
     }
     tmin = warp_min(tmin);
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
     __syncthreads();
-    if (threadIdx.x == 0) tpart[blockIdx.x] = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+    if (threadIdx.x == 0) {
+        tpart[blockIdx.x] = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+        // the last workgroup out clears the claim counters for the next launch
+        // (every other workgroup has made its last claim before counting itself)
+        __threadfence();
+        if (atomicAdd(&next[8], 1) == (int)gridDim.x - 1) {
+            for (int x = 0; x < 9; ++x) atomicExch(&next[x], 0);
+        }
+    }
 }
 
 // Second half of the constraint-set update, C_o = {TOI <= 1} U (C_{o-1}
@@ -1396,13 +1425,6 @@ __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, cons
     }
 }
 
-// U^T diag(W) U over the contact vertices: chunk c of the vertex list,
-// upper triangle (i <= j) of the r x r partial, FP32 accumulation.
-// Gram of the contact rows, Eq. (uu): sum over contact vertices j of
-// W_j U_j U_j^T (r x r, FP64 partial per chunk of vertices).  Thread = one
-// 8 x 8 tile of the upper block triangle; blockIdx.y picks a group of 256
-// tiles, blockIdx.x a chunk of the contact-vertex list.  Vertices are staged
-// 16 at a time in LDS as W-scaled (FP64) and plain (FP32) rows.
 // Eight consecutive basis entries of a row (16 bytes of BF16 or 32 of FP32)
 template <typename UT>
 struct RowChunkG;
@@ -1438,10 +1460,15 @@ __device__ __forceinline__ int gram_per_chunk(int ncv, int nchunk) {
     return max(GRAM_MIN_PER_CHUNK, (ncv + nchunk - 1) / nchunk);
 }
 
+// Gram of the contact rows, Eq. (uu): sum over contact vertices j of
+// W_j U_j U_j^T (r x r, FP64 partial per chunk of vertices).  Thread = one
+// 8 x 8 tile of the upper block triangle; blockIdx.y picks a group of 256
+// tiles, blockIdx.x a chunk of the contact-vertex list.  Vertices are staged
+// 32 at a time in LDS as W-scaled (FP64) and plain (FP32) rows.
 template <typename UT>
 __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
                                             int nchunk, double* part) {
-    constexpr int VB = 16;   // contact vertices staged per round
+    constexpr int VB = 32;   // contact vertices staged per round
     __shared__ float us[VB][MAX_R];
     __shared__ double ws[VB][MAX_R];
     __shared__ int vidx[VB];
@@ -1790,27 +1817,51 @@ __global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __rest
     extern __shared__ double A[];
     const int r = d.r;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (*n_cv == 0) {   // a wavefront per row of A^{-1}, lanes over its columns
-        for (int row = wave; row < r; row += 16) {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            for (int j = lane; j < r; j += 64) {
-                const double a = d.Ainv[(size_t)row * r + j];
-                a0 = fma(a, g[j * 3], a0);
-                a1 = fma(a, g[j * 3 + 1], a1);
-                a2 = fma(a, g[j * 3 + 2], a2);
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                a0 += __shfl_xor(a0, o);
-                a1 += __shfl_xor(a1, o);
-                a2 += __shfl_xor(a2, o);
-            }
-            if (lane == 0) {
-                d.Qd[row * 3] = a0;
-                d.Qd[row * 3 + 1] = a1;
-                d.Qd[row * 3 + 2] = a2;
-                d.Qf[row * 3] = (float)a0;
-                d.Qf[row * 3 + 1] = (float)a1;
-                d.Qf[row * 3 + 2] = (float)a2;
+    if (*n_cv == 0) {
+        // q = A^{-1} g: wavefront w takes rows w, w + 16, ..., lanes the
+        // columns lane + 64 s; g is loaded once and the rows four at a time
+        // (addresses clamped into the matrix, the extra entries multiplied
+        // by 0), each row then reduced across the wavefront
+        constexpr int RW = 4 * NS;   // rows per wavefront: 16 RW >= 64 NS >= r
+        double gj[NS][3];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int j = lane + 64 * q, jc = min(j, r - 1);
+            const double m = j < r ? 1.0 : 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gj[q][c] = g[jc * 3 + c] * m;
+        }
+#pragma unroll
+        for (int t0 = 0; t0 < RW; t0 += 4) {
+            double a[4][NS];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int q = 0; q < NS; ++q)
+                    a[t][q] = d.Ainv[(size_t)min(wave + 16 * (t0 + t), r - 1) * r + min(lane + 64 * q, r - 1)];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = wave + 16 * (t0 + t);
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    s0 = fma(a[t][q], gj[q][0], s0);
+                    s1 = fma(a[t][q], gj[q][1], s1);
+                    s2 = fma(a[t][q], gj[q][2], s2);
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    s0 += __shfl_xor(s0, o);
+                    s1 += __shfl_xor(s1, o);
+                    s2 += __shfl_xor(s2, o);
+                }
+                if (lane == 0 && row < r) {
+                    d.Qd[row * 3] = s0;
+                    d.Qd[row * 3 + 1] = s1;
+                    d.Qd[row * 3 + 2] = s2;
+                    d.Qf[row * 3] = (float)s0;
+                    d.Qf[row * 3 + 1] = (float)s1;
+                    d.Qf[row * 3 + 2] = (float)s2;
+                }
             }
         }
         return;
@@ -1898,7 +1949,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     auto I = [&](size_t k) { return static_cast<int*>(carve(sizeof(int) * k)); };
     c.gpart2 = static_cast<double*>(carve(sizeof(double) * ((size_t)(s.nblk + 31) / 32 + 1) * s.r * 3));
     c.gvec = static_cast<double*>(carve(sizeof(double) * s.r * 3));
-    c.cnt = I(16);
+    c.cnt = I(32);
     c.tmin_bits = static_cast<unsigned long long*>(carve(32));
     c.tpart = static_cast<double*>(carve(sizeof(double) * 2 * GRID_LOOP));
     c.s_dev = static_cast<double*>(carve(8));
@@ -1972,7 +2023,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
 
 cloth_status contact_upload(Scene& s, ContactState& c) {
     const int n = s.nv;
-    HC(hipMemset(c.cnt, 0, sizeof(int) * 16));
+    HC(hipMemset(c.cnt, 0, sizeof(int) * 32));
     HC(hipMemset(c.ob_a, 0xff, sizeof(int) * (size_t)MAX_OBST * n));
     std::vector<unsigned long long> tb(4, 0x4000000000000000ull);  // 2.0
     HC(hipMemcpy(c.tmin_bits, tb.data(), 32, hipMemcpyHostToDevice));
