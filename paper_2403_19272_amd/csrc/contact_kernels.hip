@@ -255,6 +255,36 @@ __device__ double sampled_toi(const d3* q0, const d3* q1, double eta) {
     return NOHIT;
 }
 
+// The same fallback for one pair, taken by a whole wavefront: the samples
+// are evaluated 64 at a time (lane l takes sample i0 + l) and the first one
+// within eta is found with a ballot; the bisection that follows is the
+// sequential one.  The result is bitwise that of sampled_toi: the same
+// distances at the same parameters decide the same first sample.
+template <bool VT>
+__device__ double sampled_toi_wave(const d3* q0, const d3* q1, double eta, int lane) {
+    int first = -1;
+    for (int i0 = 0; i0 <= FALLBACK_SAMPLES && first < 0; i0 += 64) {
+        const int i = i0 + lane;
+        bool within = false;
+        if (i <= FALLBACK_SAMPLES) {
+            const double t = (double)i / FALLBACK_SAMPLES;
+            within = (VT ? dist_vt(q0, q1, t) : dist_ee(q0, q1, t)) <= eta;
+        }
+        const unsigned long long m = __ballot(within);
+        if (m) first = i0 + __ffsll((long long)m) - 1;
+    }
+    if (first < 0) return NOHIT;
+    if (first == 0) return 0.0;
+    double lo = (double)(first - 1) / FALLBACK_SAMPLES, hi = (double)first / FALLBACK_SAMPLES;
+    for (int it = 0; it < 64; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double dm = VT ? dist_vt(q0, q1, mid) : dist_ee(q0, q1, mid);
+        if (dm <= eta) hi = mid; else lo = mid;
+    }
+    return lo;
+}
+
 // coplanarity cubic of the points (p, a, b, c): ((b-a) x (c-a)) . (p-a)
 __device__ void cubic_of(const d3* q0, const d3* q1, double c[4], double& L) {
     d3 E1 = q0[2] - q0[1], E2 = q0[3] - q0[1], W = q0[0] - q0[1];
@@ -273,12 +303,17 @@ __device__ bool degenerate(const double c[4], double L) {
     return s <= DEGEN_REL * L * L * L;
 }
 
-// q: (vertex, a, b, c) at t=0 and t=1
-__device__ double pair_toi_vt(const d3* q0, const d3* q1) {
+// q: (vertex, a, b, c) at t=0 and t=1.  When the sampled fallback is
+// needed, eta is set to its distance bound (> 0) and the return value is
+// meaningless; otherwise eta is left at 0.
+__device__ double pair_toi_vt(const d3* q0, const d3* q1, double& eta) {
     double c[4], L;
     cubic_of(q0, q1, c, L);
     if (L == 0.0) return NOHIT;
-    if (degenerate(c, L)) return sampled_toi<true>(q0, q1, 1e-12 * L);
+    if (degenerate(c, L)) {
+        eta = 1e-12 * L;
+        return NOHIT;
+    }
     return first_root01(c, [&](double t) {
         return in_tri(lerp(q0[0], q1[0], t), lerp(q0[1], q1[1], t), lerp(q0[2], q1[2], t), lerp(q0[3], q1[3], t))
                    ? 1
@@ -293,20 +328,23 @@ __device__ __forceinline__ void ee_as_vt(const d3* e, d3* q) {
     q[3] = e[0] + (e[3] - e[2]);
 }
 
-// e: (p1, p2, p3, p4) at t=0 and t=1
-__device__ double pair_toi_ee(const d3* e0, const d3* e1) {
+// e: (p1, p2, p3, p4) at t=0 and t=1; eta as for pair_toi_vt
+__device__ double pair_toi_ee(const d3* e0, const d3* e1, double& eta) {
     d3 q0[4], q1[4];
     ee_as_vt(e0, q0);
     ee_as_vt(e1, q1);
     double c[4], L;
     cubic_of(q0, q1, c, L);
     if (L == 0.0) return NOHIT;
-    if (degenerate(c, L)) return sampled_toi<false>(e0, e1, 1e-12 * L);
+    if (degenerate(c, L)) {
+        eta = 1e-12 * L;
+        return NOHIT;
+    }
     double t = first_root01(c, [&](double t) {
         int r = seg_cross(lerp(e0[0], e1[0], t), lerp(e0[1], e1[1], t), lerp(e0[2], e1[2], t), lerp(e0[3], e1[3], t));
         return r < 0 ? -1 : (r ? 1 : 0);
     });
-    if (t < 0.0) return sampled_toi<false>(e0, e1, 1e-12 * L);
+    if (t < 0.0) eta = 1e-12 * L;
     return t;
 }
 
@@ -1020,6 +1058,7 @@ __global__ void __launch_bounds__(256) k_query_rescan(Dev d, const float* __rest
 // [0, 1]); the rest go to an LDS queue that all lanes then drain, so the
 // root refinement and the inside tests run on full wavefronts.
 constexpr int TOI_CHUNK = 1024;
+constexpr int TOI_FB = 32;        // fallback pairs per chunk taken by whole wavefronts
 constexpr int TOI_SCHED = 16;   // cnt[16..23]: next chunk of each XCD's range, cnt[24]: workgroups done
 
 __device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, double t, double* toi_vt, double* toi_ee,
@@ -1038,7 +1077,9 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
                                                    int* cand_a, double* tpart, int do_merge) {
     __shared__ double wmin[4];
     __shared__ int queue[TOI_CHUNK];
-    __shared__ int qn, s_ch;
+    __shared__ int fbq[TOI_FB];   // pairs that need the sampled fallback
+    __shared__ double fbe[TOI_FB];
+    __shared__ int qn, fbn, s_ch;
     const int nvt = cnt[0], nee = cnt[1];
     const int total = nvt + nee;
     int* next = cnt + TOI_SCHED;   // next chunk of each XCD's range
@@ -1067,6 +1108,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
             }
             s_ch = ch;
             qn = 0;
+            fbn = 0;
         }
         __syncthreads();
         const int ch = s_ch;
@@ -1092,11 +1134,37 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
             const int2 pr = vt ? cvt[i] : cee[i - nvt];
             d3 q0[4], q1[4];
             pair_points2(d, vt, pr.x, pr.y, xm, xp, q0, q1);
-            const double t = vt ? pair_toi_vt(q0, q1) : pair_toi_ee(q0, q1);
+            double eta = 0.0;
+            double t = vt ? pair_toi_vt(q0, q1, eta) : pair_toi_ee(q0, q1, eta);
+            if (eta > 0.0) {
+                const int f = atomicAdd(&fbn, 1);
+                if (f < TOI_FB) {
+                    fbq[f] = i;
+                    fbe[f] = eta;
+                    continue;
+                }
+                t = vt ? sampled_toi<true>(q0, q1, eta) : sampled_toi<false>(q0, q1, eta);
+            }
             tmin = fmin(tmin, t);
             toi_finish(i, vt, nvt, t, toi_vt, toi_ee, keep, cand_a, do_merge);
         }
-        __syncthreads();   // the queue, qn and s_ch are reused by the next chunk
+        __syncthreads();
+        // the sampled fallbacks (rare; a thousand distance evaluations each),
+        // one pair per wavefront with the samples spread over its lanes
+        const int nf = min(fbn, TOI_FB);
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int f = wave; f < nf; f += blockDim.x >> 6) {
+            const int i = fbq[f];
+            const bool vt = i < nvt;
+            const int2 pr = vt ? cvt[i] : cee[i - nvt];
+            d3 q0[4], q1[4];
+            pair_points2(d, vt, pr.x, pr.y, xm, xp, q0, q1);
+            const double t = vt ? sampled_toi_wave<true>(q0, q1, fbe[f], lane)
+                                : sampled_toi_wave<false>(q0, q1, fbe[f], lane);
+            tmin = fmin(tmin, t);
+            if (lane == 0) toi_finish(i, vt, nvt, t, toi_vt, toi_ee, keep, cand_a, do_merge);
+        }
+        __syncthreads();   // the queues, their counts and s_ch are reused by the next chunk
     }
     tmin = warp_min(tmin);
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
