@@ -1529,43 +1529,58 @@ __device__ __forceinline__ int gram_per_chunk(int ncv, int nchunk) {
 }
 
 // Gram of the contact rows, Eq. (uu): sum over contact vertices j of
-// W_j U_j U_j^T (r x r, FP64 partial per chunk of vertices).  Thread = one
-// 8 x 8 tile of the upper block triangle; blockIdx.y picks a group of 256
-// tiles, blockIdx.x a chunk of the contact-vertex list.  Vertices are staged
-// 32 at a time in LDS as W-scaled (FP64) and plain (FP32) rows.
+// W_j U_j U_j^T (r x r, FP64 partial per chunk of vertices), on the matrix
+// cores: the upper block triangle of 16 x 16 tiles (r padded to a multiple
+// of 16 with zero columns) is dealt to the four wavefronts of a block,
+// GRAM_TW tiles each (blockIdx.y picks a group of 4 GRAM_TW tiles,
+// blockIdx.x a chunk of the contact-vertex list), and each
+// v_mfma_f64_16x16x4f64 adds four vertices to one tile: lane l supplies
+// W u(row l % 16) and u(column l % 16) of vertex l / 16 and holds rows
+// l / 16 + 4 e (e = 0..3) of column l % 16 of the tile.  Vertices are staged 32
+// at a time in LDS as W-scaled (FP64) and plain (FP32) rows.
+constexpr int GRAM_TW = 10;   // 16 x 16 FP64 tiles per wavefront
+typedef double gram_d4 __attribute__((ext_vector_type(4)));
 template <typename UT>
 __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
                                             int nchunk, double* part) {
-    constexpr int VB = 32;   // contact vertices staged per round
+    constexpr int VB = 32;   // contact vertices staged per round (a multiple of 4)
     __shared__ float us[VB][MAX_R];
     __shared__ double ws[VB][MAX_R];
     __shared__ int vidx[VB];
     __shared__ float wv[VB];
-    const int r = d.r, T = r >> 3;
+    const int r = d.r;
+    const int R16 = (r + 15) >> 4;   // tile rows
     const int ncv = *n_cv;
     const int per = gram_per_chunk(ncv, nchunk);
     const int c0 = blockIdx.x * per, c1 = min(ncv, c0 + per);
     if (c0 >= c1) return;
-    // tile -> (ti, tj), ti <= tj, row-major over the upper block triangle
-    int tile = blockIdx.y * 256 + threadIdx.x;
-    const bool active = tile < T * (T + 1) / 2;
-    int ti = 0, tj = 0;
-    if (active) {
-        int rem = tile;
-        while (rem >= T - ti) {
-            rem -= T - ti;
-            ++ti;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = lane & 15, kv = lane >> 4;   // operand row / column, vertex of the four
+    // this wavefront's tiles t = (blockIdx.y GRAM_TW + s) 4 + wave -> (ti, tj),
+    // ti <= tj, row-major over the upper block triangle (wave-uniform)
+    int ti[GRAM_TW], tj[GRAM_TW];
+    bool on[GRAM_TW];
+#pragma unroll
+    for (int s = 0; s < GRAM_TW; ++s) {
+        const int t = (blockIdx.y * GRAM_TW + s) * 4 + wave;
+        on[s] = t < R16 * (R16 + 1) / 2;
+        int a = 0, rem = on[s] ? t : 0;
+        while (rem >= R16 - a) {
+            rem -= R16 - a;
+            ++a;
         }
-        tj = ti + rem;
+        ti[s] = a;
+        tj[s] = a + rem;
     }
     // FP64 products and sums: the weights span many orders of magnitude
     // (k 2^a), and an FP32 Gram's rounding reaches the scale of Lambda~'s
     // smallest eigenvalues, which can cost A its definiteness
-    double acc[8][8];
-    for (int a = 0; a < 8; ++a)
-        for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    gram_d4 acc[GRAM_TW];
+#pragma unroll
+    for (int s = 0; s < GRAM_TW; ++s) acc[s] = gram_d4{0.0, 0.0, 0.0, 0.0};
     const UT* U = static_cast<const UT*>(d.U);
-    const int ncg = r >> 3;   // groups of 8 basis columns per row
+    const int ncg = r >> 3;            // groups of 8 basis columns per row
+    const int ncg16 = R16 * 2;         // the same, up to the padded width
     for (int base = c0; base < c1; base += VB) {
         const int m = min(VB, c1 - base);
         __syncthreads();
@@ -1577,11 +1592,11 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
             wv[threadIdx.x] = v >= 0 ? d.W[v] : 0.f;
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < VB * ncg; q += 256) {
-            const int vv = q / ncg, cg = q % ncg;
+        for (int q = threadIdx.x; q < VB * ncg16; q += 256) {
+            const int vv = q / ncg16, cg = q % ncg16;
             const int v = vidx[vv];
             float u[8];
-            if (v >= 0) {
+            if (v >= 0 && cg < ncg) {
                 RowChunkG<UT> rc;
                 rc.load(U, (size_t)v * r + cg * 8);
                 rc.unpack(u);
@@ -1595,20 +1610,26 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
             }
         }
         __syncthreads();
-        if (active) {
-            for (int vv = 0; vv < m; ++vv) {
-                double wa[8], ub[8];
-                for (int a = 0; a < 8; ++a) wa[a] = ws[vv][ti * 8 + a];
-                for (int b = 0; b < 8; ++b) ub[b] = us[vv][tj * 8 + b];
-                for (int a = 0; a < 8; ++a)
-                    for (int b = 0; b < 8; ++b) acc[a][b] = fma(wa[a], ub[b], acc[a][b]);
-            }
+        for (int v0 = 0; v0 < m; v0 += 4) {
+#pragma unroll
+            for (int s = 0; s < GRAM_TW; ++s)
+                if (on[s]) {
+                    const double a = ws[v0 + kv][ti[s] * 16 + row];
+                    const double b = (double)us[v0 + kv][tj[s] * 16 + row];
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+                }
         }
     }
-    if (!active) return;
-    for (int a = 0; a < 8; ++a)
-        for (int b = 0; b < 8; ++b)
-            part[((size_t)blockIdx.x * r + ti * 8 + a) * r + tj * 8 + b] = acc[a][b];
+#pragma unroll
+    for (int s = 0; s < GRAM_TW; ++s) {
+        if (!on[s]) continue;
+        const int col = tj[s] * 16 + row;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int rw = ti[s] * 16 + kv + 4 * e;
+            if (rw < r && col < r) part[((size_t)blockIdx.x * r + rw) * r + col] = acc[s][e];
+        }
+    }
 }
 
 // Packed lower triangle, column-major: column k holds rows k..r-1 at
@@ -2259,8 +2280,8 @@ cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, 
 
 cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st) {
     Dev& d = s.d;
-    const int T = s.r / 8;
-    dim3 grid(c.gram_chunks, (T * (T + 1) / 2 + 255) / 256);
+    const int T = (s.r + 15) / 16;   // 16 x 16 tiles per side of the Gram
+    dim3 grid(c.gram_chunks, (T * (T + 1) / 2 + 4 * GRAM_TW - 1) / (4 * GRAM_TW));
     if (s.prec == CLOTH_MIXED)
         hipLaunchKernelGGL(k_gram<uint16_t>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
                            d.gram_part);
