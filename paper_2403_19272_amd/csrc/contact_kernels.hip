@@ -1753,42 +1753,30 @@ __device__ __forceinline__ void chol_panel(double* A, double* dinv, int r, int p
         for (int t = 0; t < W; ++t) A[rm(i, p0 + t)] = a[t];
     }
     __syncthreads();
-    // 3. trailing triangle: A(i, j) -= sum over the panel's k of
-    // A(i, k) A(j, k) / A(k, k), 4 x 4 tiles (r - pe is a multiple of 8)
-    const int nt4 = (r - pe) / 4;
-    for (int t = tid; t < nt4 * (nt4 + 1) / 2; t += 1024) {
+    // 3. trailing triangle on the matrix cores: A(i, j) -= sum over the
+    // panel's k of (A(i, k) / A(k, k)) A(j, k) for pe <= j <= i, in 16 x 16
+    // tiles of the lower part, one wavefront per tile, four k per
+    // v_mfma_f64_16x16x4f64 (lane l: row / column l % 16 and k = l / 16 of
+    // the operands; rows l / 16 + 4 e of column l % 16 of the result)
+    const int nT = (r - pe + 15) >> 4;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int t = wave; t < nT * (nT + 1) / 2; t += 16) {
         int I, J;
         tri_rc(t, I, J);
-        const int i0 = pe + 4 * I, j0 = pe + 4 * J;
-        double acc[4][4];
+        const int i = pe + 16 * I + lr, j = pe + 16 * J + lr;
+        gram_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-#pragma unroll 2
-        for (int k0 = 0; k0 < W; k0 += 2) {
-            double ai[4][2], aj[4][2];
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                const double dk = dinv[p0 + k0 + kk];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    ai[a][kk] = A[rm(i0 + a, p0 + k0 + kk)] * dk;
-                    aj[a][kk] = A[rm(j0 + a, p0 + k0 + kk)];
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-#pragma unroll
-                    for (int kk = 0; kk < 2; ++kk) acc[a][b] = fma(ai[a][kk], aj[b][kk], acc[a][b]);
+        for (int k0 = 0; k0 < W; k0 += 4) {
+            const int k = p0 + k0 + lk;
+            const double a = i < r ? A[rm(i, k)] * dinv[k] : 0.0;
+            const double b = j < r ? A[rm(j, k)] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (I != J || b <= a) A[rm(i0 + a, j0 + b)] -= acc[a][b];
+        for (int e = 0; e < 4; ++e) {
+            const int ii = pe + 16 * I + lk + 4 * e;
+            if (ii < r && j <= ii) A[rm(ii, j)] -= acc[e];
+        }
     }
     __syncthreads();
 }
