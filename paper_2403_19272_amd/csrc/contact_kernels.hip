@@ -1076,7 +1076,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
                                                    int* cnt, double* toi_vt, double* toi_ee, int* keep,
                                                    int* cand_a, double* tpart, int do_merge) {
     __shared__ double wmin[4];
-    __shared__ int queue[TOI_CHUNK];
+    __shared__ int queue[TOI_CHUNK + 256];   // pairs waiting for root refinement
     __shared__ int fbq[TOI_FB];   // pairs that need the sampled fallback
     __shared__ double fbe[TOI_FB];
     __shared__ int qn, fbn, s_ch;
@@ -1095,6 +1095,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
     const int per_x = (nchunk + 7) / 8;
     const int xcd = blockIdx.x % 8;
     int range = 0;   // thread 0 only: ranges already used up
+    int q_left = 0;  // pairs still waiting in the queue
     for (;;) {
         if (threadIdx.x == 0) {
             int ch = -1;
@@ -1107,14 +1108,13 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
                 }
             }
             s_ch = ch;
-            qn = 0;
+            qn = q_left;
             fbn = 0;
         }
         __syncthreads();
         const int ch = s_ch;
-        if (ch < 0) break;
         const int base = ch * TOI_CHUNK;
-        for (int k = threadIdx.x; k < TOI_CHUNK; k += blockDim.x) {
+        for (int k = threadIdx.x; ch >= 0 && k < TOI_CHUNK; k += blockDim.x) {
             const int i = base + k;
             if (i >= total) break;
             const bool vt = i < nvt;
@@ -1127,9 +1127,14 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
                 queue[atomicAdd(&qn, 1)] = i;
         }
         __syncthreads();
+        // root refinement in whole passes of the block: the queue is drained
+        // down to fewer than 256 pairs, which wait for the next chunk's (all
+        // of it after the last chunk), so that the lanes of a pass are busy
         const int nq = qn;
-        for (int k = threadIdx.x; k < nq; k += blockDim.x) {
-            const int i = queue[k];
+        const int take = ch < 0 ? nq : nq - nq % (int)blockDim.x;
+        q_left = nq - take;
+        for (int k = threadIdx.x; k < take; k += blockDim.x) {
+            const int i = queue[q_left + k];
             const bool vt = i < nvt;
             const int2 pr = vt ? cvt[i] : cee[i - nvt];
             d3 q0[4], q1[4];
@@ -1165,6 +1170,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
             if (lane == 0) toi_finish(i, vt, nvt, t, toi_vt, toi_ee, keep, cand_a, do_merge);
         }
         __syncthreads();   // the queues, their counts and s_ch are reused by the next chunk
+        if (ch < 0) break;
     }
     tmin = warp_min(tmin);
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
