@@ -645,13 +645,21 @@ __device__ __forceinline__ bool target_cell(const float* box, const BpGrid& g, i
     return false;
 }
 
+// AoS float4 copies of the two SoA position arrays (one 16-byte gather per
+// corner in the boxes and the TOI)
+__global__ void k_aos_pair(int n, const float* __restrict__ xm, const float* __restrict__ xp, float4* xm4,
+                           float4* xp4) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        xm4[v] = make_float4(xm[v], xm[n + v], xm[2 * n + v], 0.f);
+        xp4[v] = make_float4(xp[v], xp[n + v], xp[2 * n + v], 0.f);
+    }
+}
+
 // Swept boxes over (xm, xp) grown by dhat (FP32); per block the box
 // statistics of the triangle and edge boxes (reduced by k_grid).
-__global__ void __launch_bounds__(256) k_boxes(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
-                                               float dhat, float* vbox, float* tbox, float* ebox, float* bpart,
-                                               float4* xm4, float4* xp4) {
+__global__ void __launch_bounds__(256) k_boxes(Dev d, const float4* __restrict__ xm4, const float4* __restrict__ xp4,
+                                               float dhat, float* vbox, float* tbox, float* ebox, float* bpart) {
     __shared__ float red[4][BP_PART];
-    const int n = d.nv;
     const int total = d.nv + d.nt + d.ne;
     float acc[BP_PART];
     for (int k = 0; k < BP_PART; ++k) acc[k] = bp_identity(bp_op(k));
@@ -665,9 +673,6 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float* __restrict__ 
             nvert = 1;
             out = vbox + 6 * (size_t)i;
             kind = 0;
-            // AoS copies of the two positions for the gathers of the TOI
-            xm4[i] = make_float4(xm[i], xm[n + i], xm[2 * n + i], 0.f);
-            xp4[i] = make_float4(xp[i], xp[n + i], xp[2 * n + i], 0.f);
         } else if (i < d.nv + d.nt) {
             int t = i - d.nv;
             TriRec tr = d.tri[t];
@@ -683,10 +688,17 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float* __restrict__ 
             out = ebox + 6 * (size_t)e;
             kind = 2;
         }
+        // the corners' two positions, one 16-byte load each
+        float pa[3][3], pb[3][3];
+        for (int k = 0; k < nvert; ++k) {
+            const float4 a = xm4[ids[k]], b = xp4[ids[k]];
+            pa[k][0] = a.x; pa[k][1] = a.y; pa[k][2] = a.z;
+            pb[k][0] = b.x; pb[k][1] = b.y; pb[k][2] = b.z;
+        }
         for (int c = 0; c < 3; ++c) {
-            float lo = xm[c * n + ids[0]], hi = lo;
+            float lo = pa[0][c], hi = lo;
             for (int k = 0; k < nvert; ++k) {
-                float a = xm[c * n + ids[k]], b = xp[c * n + ids[k]];
+                float a = pa[k][c], b = pb[k][c];
                 lo = fminf(lo, fminf(a, b));
                 hi = fmaxf(hi, fmaxf(a, b));
             }
@@ -2136,8 +2148,10 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
     const int n = s.nv;
     const int P = c.hash_p;
     const int nbb = gblocks((int64_t)n + s.nt + s.ne);
-    hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, xm, xp, (float)s.dhat, c.vbox, c.tbox, c.ebox,
-                       c.bpart, c.xm4, c.xp4);
+    // AoS copies of the two positions, for the corner gathers of the boxes and the TOI
+    hipLaunchKernelGGL(k_aos_pair, dim3(gblocks(n)), dim3(TPB), 0, st, n, xm, xp, c.xm4, c.xp4);
+    hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
+                       (float)s.dhat, c.vbox, c.tbox, c.ebox, c.bpart);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, (const float*)c.bpart, nbb, s.nt, s.ne, c.grid);
     for (int pass = 0; pass < 2; ++pass) {
         const bool vt = pass == 0;
