@@ -40,6 +40,7 @@ struct ContactState {
     int *bucket_cnt = nullptr, *bucket_ptr = nullptr;
     BpRec* rec = nullptr;   // targets in cell-bucket order
     int* qscratch = nullptr;  // per query: up to QK target ids from the counting pass
+    int* heavy_q = nullptr;   // the queries with more than QK hits (counting pass -> rescan)
     float* bpart = nullptr;   // per-block box extents
     BpGrid* grid = nullptr;   // [0] triangles, [1] edges
     float4 *xm4 = nullptr, *xp4 = nullptr;   // AoS copies of the stage's two positions (TOI gathers)

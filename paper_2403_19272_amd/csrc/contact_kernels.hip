@@ -586,6 +586,7 @@ constexpr double CELL_MARGIN = 1.0 + 1.0 / 1024.0;
 // overflow flag bits (sticky until the host reads them)
 constexpr int OVF_QUERY = 1, OVF_CELL = 2, OVF_LIST = 4, OVF_CONS = 8;
 constexpr int PEAK_SLOT = 12;   // cnt[12]: largest candidate list since the last stats read
+constexpr int HEAVY_SLOT = 25;  // cnt[25]: queries listed for k_query_rescan, cnt[26]: its workgroups done
 
 __device__ __forceinline__ int bp_op(int k) { return (k % BP_FAM) / 3; }   // 0 max, 1 min, 2 max, 3 sum
 __device__ __forceinline__ float bp_combine(int op, float a, float b) {
@@ -962,7 +963,7 @@ template <bool VT, int G>
 __global__ void __launch_bounds__(256) k_query_count(Dev d, const float* __restrict__ qbox,
                                                      const BpGrid* __restrict__ gp, const int* __restrict__ bptr,
                                                      const BpRec* __restrict__ rec, int P, int* count, int* scratch,
-                                                     int max_out, int* overflow) {
+                                                     int max_out, int* overflow, int* heavy_list, int* heavy_n) {
     constexpr int GPB = 256 / G;
     __shared__ int res[GPB][QK];
     const int nq = VT ? d.nv : d.ne;
@@ -979,6 +980,11 @@ __global__ void __launch_bounds__(256) k_query_count(Dev d, const float* __restr
         if (lane == 0) {
             count[q] = min(cnt, max_out);
             if (full) atomicOr(overflow, OVF_QUERY);
+            // the queries whose hits do not fit the scratch, for k_query_rescan
+            if (min(cnt, max_out) > QK) {
+                const int h = atomicAdd(heavy_n, 1);
+                if (h < nq) heavy_list[h] = q;
+            }
         }
     }
     __syncthreads();
@@ -1013,52 +1019,52 @@ __global__ void __launch_bounds__(256) k_query_copy(int nq, const int* __restric
     }
 }
 
-// Writing pass for the queries with more than QK hits.  Each block looks
-// through its range of queries 256 at a time for such queries; each
-// wavefront then takes one of them, finds its hits again with group_query
+// Writing pass for the queries with more than QK hits, listed by
+// k_query_count (in no particular order: each one's output place is fixed by
+// its offset).  The wavefronts of the whole grid take them one at a time, so
+// that the heavy queries, which cluster where the cloth folds, are spread
+// over every CU; a wavefront finds the query's hits again with group_query
 // (G = 64) into LDS, ranks them and writes them sorted at the query's offset.
+// The last workgroup out clears the list's count for the next pass.
 template <bool VT>
 __global__ void __launch_bounds__(256) k_query_rescan(Dev d, const float* __restrict__ qbox,
                                                       const BpGrid* __restrict__ gp, const int* __restrict__ bptr,
                                                       const BpRec* __restrict__ rec, int P,
                                                       const int* __restrict__ ofs, const int* __restrict__ raw,
-                                                      int2* out, int64_t cap, int max_out, int* overflow) {
-    __shared__ int heavy[256];
-    __shared__ int nheavy;
+                                                      int2* out, int64_t cap, int max_out, int* overflow,
+                                                      const int* __restrict__ heavy_list, int* heavy_n) {
     __shared__ int hits[4][MAX_HITS];
-    const int nq = VT ? d.nv : d.ne;
-    const int chunk = (nq + gridDim.x - 1) / gridDim.x;
-    const int q0 = blockIdx.x * chunk, q1 = min(nq, q0 + chunk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const BpGrid g = *gp;
-    for (int b = q0; b < q1; b += 256) {
-        if (threadIdx.x == 0) nheavy = 0;
-        __syncthreads();
-        const int q = b + threadIdx.x;
-        if (q < q1 && ofs[q] >= 0 && raw[q] > QK) heavy[atomicAdd(&nheavy, 1)] = q;
-        __syncthreads();
-        const int nh = nheavy;
-        for (int h = w; h < nh; h += 4) {
-            const int qq = heavy[h];
-            bool full = false;
-            const int cnt = group_query<VT, 64>(d, qq, lane, 0, qbox, g, bptr, rec, P, max_out, full,
-                                                [&](int idx, int id) {
-                                                    if (idx < MAX_HITS) hits[w][idx] = id;
-                                                });
-            if (full && lane == 0) atomicOr(overflow, OVF_QUERY);
-            const int m = min(cnt, min(max_out, MAX_HITS));
-            const int64_t base = ofs[qq];
-            if (lane == 0 && base + m > cap) atomicOr(overflow, OVF_LIST);
-            __builtin_amdgcn_wave_barrier();
-            for (int i = lane; i < m; i += 64) {
-                const int v = hits[w][i];
-                int rank = 0;
-                for (int k2 = 0; k2 < m; ++k2) rank += hits[w][k2] < v;
-                if (base + rank < cap) out[base + rank] = make_int2(qq, v);
-            }
-            __builtin_amdgcn_wave_barrier();
+    const int nh = min(heavy_n[0], VT ? d.nv : d.ne);
+    for (int h = blockIdx.x * 4 + w; h < nh; h += gridDim.x * 4) {
+        const int qq = heavy_list[h];
+        if (ofs[qq] < 0 || raw[qq] <= QK) continue;   // wavefront-uniform
+        bool full = false;
+        const int cnt = group_query<VT, 64>(d, qq, lane, 0, qbox, g, bptr, rec, P, max_out, full,
+                                            [&](int idx, int id) {
+                                                if (idx < MAX_HITS) hits[w][idx] = id;
+                                            });
+        if (full && lane == 0) atomicOr(overflow, OVF_QUERY);
+        const int m = min(cnt, min(max_out, MAX_HITS));
+        const int64_t base = ofs[qq];
+        if (lane == 0 && base + m > cap) atomicOr(overflow, OVF_LIST);
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < m; i += 64) {
+            const int v = hits[w][i];
+            int rank = 0;
+            for (int k2 = 0; k2 < m; ++k2) rank += hits[w][k2] < v;
+            if (base + rank < cap) out[base + rank] = make_int2(qq, v);
         }
-        __syncthreads();   // heavy[] and nheavy are reused
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&heavy_n[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&heavy_n[0], 0);
+            atomicExch(&heavy_n[1], 0);
+        }
     }
 }
 
@@ -2077,6 +2083,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.bucket_ptr = I((size_t)P + 1);
     c.rec = static_cast<BpRec*>(carve(sizeof(BpRec) * mt));
     c.qscratch = I((size_t)QK * (s.self_contact ? (size_t)std::max(n, s.ne) : 1));
+    c.heavy_q = I(s.self_contact ? (size_t)std::max(n, s.ne) : 1);
     c.bpart = static_cast<float*>(carve(sizeof(float) * BP_PART * GRID_LOOP));
     c.xm4 = static_cast<float4*>(carve(sizeof(float4) * (s.self_contact ? (size_t)n : 1)));
     c.xp4 = static_cast<float4*>(carve(sizeof(float4) * (s.self_contact ? (size_t)n : 1)));
@@ -2103,7 +2110,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.cvlist = I((size_t)n + 1);
     c.cvflag = I((size_t)n + 1);
     c.cvofs = I((size_t)n + 1);
-    if (!c.vbox || !c.tbox || !c.ebox || !c.bucket_cnt || !c.bucket_ptr || !c.rec || !c.qscratch ||
+    if (!c.vbox || !c.tbox || !c.ebox || !c.bucket_cnt || !c.bucket_ptr || !c.rec || !c.qscratch || !c.heavy_q ||
         !c.bpart || !c.grid || !c.xm4 || !c.xp4 || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
         !c.toi_ee || !c.keep || !c.keep_ofs || !c.cand_a || !c.cpair || !c.cpair_prev || !c.ca ||
         !c.ca_prev || !c.clam || !c.cnrm || !c.slot || !c.vslot_ptr || !c.vslot_fill || !c.vslot || !c.cvlist ||
@@ -2170,10 +2177,12 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
         const float* qb = vt ? c.vbox : c.ebox;
         if (vt)
             hipLaunchKernelGGL((k_query_count<true, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
-                               c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7);
+                               c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7, c.heavy_q,
+                               c.cnt + HEAVY_SLOT);
         else
             hipLaunchKernelGGL((k_query_count<false, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
-                               c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7);
+                               c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7, c.heavy_q,
+                               c.cnt + HEAVY_SLOT);
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, c.keep, cnts, nq);
         HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, st));
         hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
@@ -2182,10 +2191,12 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
                            (const int*)c.keep, (const int*)c.qscratch, outp, c.cap);
         if (vt)
             hipLaunchKernelGGL(k_query_rescan<true>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
-                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, c.cap, c.max_out, c.cnt + 7);
+                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, c.cap, c.max_out, c.cnt + 7,
+                               (const int*)c.heavy_q, c.cnt + HEAVY_SLOT);
         else
             hipLaunchKernelGGL(k_query_rescan<false>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
-                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, c.cap, c.max_out, c.cnt + 7);
+                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, c.cap, c.max_out, c.cnt + 7,
+                               (const int*)c.heavy_q, c.cnt + HEAVY_SLOT);
     }
     HC(hipGetLastError());
     return CLOTH_OK;
