@@ -2020,7 +2020,7 @@ __global__ void k_sum2(int* cnt) {
 // ================================================================ host side
 
 // lanes per query of the counting pass, and its grid (one group per query)
-constexpr int QUERY_LANES = 16;
+constexpr int QUERY_LANES = 8;
 static inline int qblocks(int64_t nq) { return (int)std::max<int64_t>(1, (nq + 256 / QUERY_LANES - 1) / (256 / QUERY_LANES)); }
 
 static inline int gblocks(int64_t n) {
