@@ -501,8 +501,9 @@ void og_toi_pairs(const double* xm, const double* xp, const int* tris, const int
 /* ------------------------------------------------------- closest points */
 
 /* Closest point of triangle abc to p, as (l1, l2) with q = a + l1 (b-a) + l2 (c-a).
- * Region test: the seven Voronoi regions of the triangle (three vertices,
- * three edges, the face). */
+ * Region test over the seven Voronoi regions of the triangle (three vertices,
+ * three edges, the face), the published method of C. Ericson, Real-Time
+ * Collision Detection (2005), sec. 5.1.5. */
 static void closest_on_tri(v3 p, v3 a, v3 b, v3 c, double* l1, double* l2) {
     v3 ab = sub(b, a), ac = sub(c, a), ap = sub(p, a);
     double d1 = dot(ab, ap), d2 = dot(ac, ap);
@@ -533,7 +534,9 @@ static void closest_on_tri(v3 p, v3 a, v3 b, v3 c, double* l1, double* l2) {
 static double clamp01(double v) { return v < 0 ? 0 : (v > 1 ? 1 : v); }
 
 /* Closest points of segments p1p2 (parameter s) and p3p4 (parameter t):
- * minimise |p1 + s d1 - p3 - t d2|^2 over the unit square. */
+ * minimise |p1 + s d1 - p3 - t d2|^2 over the unit square by the clamped
+ * line-line solution of C. Ericson, Real-Time Collision Detection (2005),
+ * sec. 5.1.9. */
 static void closest_seg_seg(v3 p1, v3 p2, v3 p3, v3 p4, double* s_out, double* t_out) {
     v3 d1 = sub(p2, p1), d2 = sub(p4, p3), r = sub(p1, p3);
     double a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);

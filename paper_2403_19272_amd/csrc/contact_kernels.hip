@@ -178,7 +178,10 @@ __device__ int seg_cross(d3 p1, d3 p2, d3 p3, d3 p4) {
 
 __device__ double clamp01(double v) { return v < 0 ? 0 : (v > 1 ? 1 : v); }
 
-// closest point of triangle abc to p as (l1, l2): q = a + l1 (b-a) + l2 (c-a)
+// closest point of triangle abc to p as (l1, l2): q = a + l1 (b-a) + l2 (c-a),
+// by the Voronoi-region test of C. Ericson, Real-Time Collision Detection
+// (2005), sec. 5.1.5 (the same operation order as the FP64 reference, so the
+// frozen parameters agree bit for bit)
 __device__ void tri_closest(d3 p, d3 a, d3 b, d3 c, double& l1, double& l2) {
     d3 ab = b - a, ac = c - a, ap = p - a;
     double d1 = dot(ab, ap), d2 = dot(ac, ap);
@@ -203,7 +206,8 @@ __device__ void tri_closest(d3 p, d3 a, d3 b, d3 c, double& l1, double& l2) {
     l1 = vb / den; l2 = vc / den;
 }
 
-// closest parameters (s on p1p2, t on p3p4)
+// closest parameters (s on p1p2, t on p3p4): clamped line-line solution of
+// C. Ericson, Real-Time Collision Detection (2005), sec. 5.1.9
 __device__ void seg_closest(d3 p1, d3 p2, d3 p3, d3 p4, double& s, double& t) {
     d3 d1 = p2 - p1, d2 = p4 - p3, r = p1 - p3;
     double a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
