@@ -46,8 +46,9 @@ typedef int32_t cloth_status;
 #define CLOTH_E_INVALID -1   /* bad argument or call order */
 #define CLOTH_E_MESH -2      /* non-manifold or degenerate mesh */
 #define CLOTH_E_OOM -3       /* arena too small / allocation failed */
-#define CLOTH_E_CAPACITY -4  /* pair or constraint buffer overflow after regrow */
-#define CLOTH_E_DIVERGED -5  /* NaN or Inf in the state */
+#define CLOTH_E_CAPACITY -4  /* a candidate or constraint list outgrew the arena's capacity */
+#define CLOTH_E_DIVERGED -5  /* NaN or Inf in an iterate */
+#define CLOTH_E_TANGLED -6   /* the debug tangle check found intersecting triangles */
 #define CLOTH_E_DEVICE -7    /* a HIP runtime error */
 
 #define CLOTH_PLAIN_FP32 0   /* basis U stored in FP32 */
@@ -70,6 +71,11 @@ typedef struct {
  *   density    mass per area, kg/m^2 (lumped: one third of each incident area)
  *   k_stretch  strain weight per rest area (PD weight w_t = k_stretch * area)
  *   k_bend     bending weight (hinge weight k_bend * 3 / (A1 + A2))
+ *   sigma_min, sigma_max
+ *              strain limits of the triangle projection (Eq. (local)): the
+ *              target is F with its singular values clamped to this range,
+ *              0 < sigma_min <= 1 <= sigma_max; 1, 1 projects onto
+ *              rotations (0, 0 is read as 1, 1)
  *   k_contact  initial barrier weight k of Eq. (exp); <= 0 selects the mean
  *              elastic diagonal of H over free vertices
  *   K_base     growth base K of Eq. (exp) (the paper uses 2)
@@ -77,7 +83,7 @@ typedef struct {
  *   d_hat      contact target distance (m)
  *   alpha      filter back-off, s = alpha * t_TOI (the paper uses 0.8) */
 typedef struct {
-    double density, k_stretch, k_bend, k_contact, K_base;
+    double density, k_stretch, k_bend, sigma_min, sigma_max, k_contact, K_base;
     int32_t a_max;
     double d_hat, alpha;
 } cloth_material;
@@ -85,7 +91,17 @@ typedef struct {
 /* Solver settings.
  *   r                   basis width (scalar modes; each acts on x, y and z), a
  *                       multiple of 8 in [8, 192]
- *   iters_inner/outer   fixed iteration budget per step (inner per block)
+ *   iters_inner/outer   iteration budget per step (inner per block); the
+ *                       product is at most 65536
+ *   tol_inner/outer     loop conditions of Algorithm 1 (section 7): an inner
+ *                       block stops once the previous iteration moved no
+ *                       vertex by tol_inner or more (max over vertices of
+ *                       |x^{k+1} - x^k|), the outer loop once an outer block
+ *                       moved no vertex by tol_outer or more (the filtered
+ *                       x against the previous block's); both within the
+ *                       budgets above, decided on the device (the remaining
+ *                       launches of the step run as no-ops).  <= 0: the
+ *                       budget alone
  *   cheb_rho            spectral radius estimate for the Chebyshev weights;
  *                       <= 0: estimated by power iteration when the basis is set
  *   cheb_gamma          damping of the Jacobi step; <= 0: chosen with rho
@@ -93,13 +109,19 @@ typedef struct {
  *   precision           CLOTH_PLAIN_FP32 or CLOTH_MIXED
  *   self_contact        1: vertex-triangle and edge-edge contact on
  *   pair_capacity       candidate pairs per list (VT, EE) the arena holds
- *                       (0: 128 per vertex); a stage that finds more makes
- *                       the next stats read return CLOTH_E_CAPACITY */
+ *                       (0: 128 per vertex); a step whose stage finds more
+ *                       fails (see cloth_step)
+ *   debug_tangles       1: after every step, test the end state for pairs of
+ *                       vertex-disjoint triangles that intersect (FP64
+ *                       orientation tests); a step that has any fails with
+ *                       CLOTH_E_TANGLED */
 typedef struct {
     int32_t r, iters_inner, iters_outer;
+    double tol_inner, tol_outer;
     double cheb_rho, cheb_gamma;
     int32_t cheb_delay, precision, self_contact;
     int64_t pair_capacity;
+    int32_t debug_tangles;
 } cloth_solver_params;
 
 typedef struct {
@@ -109,9 +131,10 @@ typedef struct {
 
 /* Filled after the step's stream has been synchronised. */
 typedef struct {
-    int32_t inner_iters, outer_iters;
+    int32_t inner_iters, outer_iters;   /* executed by the last step */
     int64_t n_candidates, n_constraints;
-    double dx_norm;      /* max per-vertex change of the last inner iteration */
+    double dx_norm;      /* max per-vertex change of the last inner iteration run */
+    double outer_dx;     /* max per-vertex change of x over the last outer block run */
     double min_toi;      /* smallest time of impact seen (2 = none) */
     double cheb_rho, cheb_gamma;
     int64_t peak_candidates;  /* largest VT or EE candidate list of any outer
@@ -168,7 +191,8 @@ cloth_status cloth_compute_basis(cloth_scene s, int32_t r, int32_t degree, int32
                                  double tol, double* U, double* ritz, int32_t* passes,
                                  double* residual);
 
-/* Adds an analytic obstacle (at most 4 per scene). */
+/* Adds an analytic obstacle (at most 4 per scene); the next step records
+ * its graph again. */
 cloth_status cloth_add_obstacle(cloth_scene s, const cloth_obstacle* ob);
 
 /* State upload / download (host arrays of nv*3 floats; v may be NULL).
@@ -176,12 +200,22 @@ cloth_status cloth_add_obstacle(cloth_scene s, const cloth_obstacle* ob);
 cloth_status cloth_set_state(cloth_scene s, const float* x, const float* v, void* stream);
 cloth_status cloth_get_state(cloth_scene s, float* x, float* v, void* stream);
 
-/* One implicit time step with gravity g (m/s^2); stats may be NULL. */
+/* One implicit time step with gravity g (m/s^2); stats may be NULL.
+ * Failure: a step in which a candidate or constraint list outgrows its
+ * capacity, an iterate becomes non-finite, or (debug_tangles) the end state
+ * has intersecting triangles is rolled back on the device: x and v keep the
+ * values the step started from (so do the forwarded residual and the
+ * scene's other state), and its blocks after the failing stage do not move
+ * (step length 0).  The failure is reported by the next call that reads
+ * stats (this one, when stats is given): CLOTH_E_CAPACITY, CLOTH_E_DIVERGED
+ * or CLOTH_E_TANGLED, with the reasons in cloth_last_error(); the record is
+ * cleared by that read and by cloth_set_state. */
 cloth_status cloth_step(cloth_scene s, const float gravity[3], void* stream,
                         cloth_step_stats* stats);
 
 /* n steps in a row on the same stream without host synchronisation in
- * between; stats (may be NULL) describe the last step. */
+ * between; stats (may be NULL) describe the last step; a failure of any of
+ * the n steps is reported. */
 cloth_status cloth_step_n(cloth_scene s, const float gravity[3], int32_t n, void* stream,
                           cloth_step_stats* stats);
 
@@ -204,7 +238,9 @@ cloth_status cloth_step_batch(cloth_scene* scenes, int32_t n, const float gravit
  *   release: waits for the scene's queued steps, then frees its budget
  *   submit:  queues one step of the scene; returns a ticket
  *   poll / wait: completion of a ticket, with latency (submission to
- *            completion, host clock) and service time (device, ms)
+ *            completion, host clock) and service time (device, ms); the
+ *            ticket's status is the step's own (CLOTH_E_CAPACITY,
+ *            CLOTH_E_DIVERGED or CLOTH_E_TANGLED for a rolled-back step)
  *   destroy: finishes queued work and stops the thread */
 typedef struct cloth_server_s* cloth_server;
 cloth_status cloth_server_create(int32_t slots, size_t hbm_budget, cloth_server* out);

@@ -115,9 +115,12 @@ class Model:
     H: sp.csr_matrix          # scalar N x N
     diagH: np.ndarray
     k_contact: float
+    sigma_min: float = 1.0    # strain limits of the triangle projection
+    sigma_max: float = 1.0
 
 
-def build_model(tris, rest, pinned, dt, density, k_stretch, k_bend, k_contact=0.0) -> Model:
+def build_model(tris, rest, pinned, dt, density, k_stretch, k_bend, k_contact=0.0, sigma_min=1.0,
+                sigma_max=1.0) -> Model:
     tris = np.asarray(tris, np.int64)
     X = np.asarray(rest, np.float64)
     nv = X.shape[0]
@@ -156,7 +159,8 @@ def build_model(tris, rest, pinned, dt, density, k_stretch, k_bend, k_contact=0.
         k_contact = float((diagH - mass * h2)[free].mean())
     return Model(nv=nv, tris=tris.astype(np.int32), edges=unique_edges(tris), hinges=hg,
                  rest=X, pinned=pinned, h=dt, mass=mass, area=area, g=g, w_tri=w_tri, K=K,
-                 w_hinge=w_h, rest_bend=rb, H=H, diagH=diagH, k_contact=float(k_contact))
+                 w_hinge=w_h, rest_bend=rb, H=H, diagH=diagH, k_contact=float(k_contact),
+                 sigma_min=float(sigma_min), sigma_max=float(sigma_max))
 
 
 def eigenbasis(model: Model, r: int, dense_limit: int = 4096):

@@ -49,6 +49,8 @@ class Params:
     K_base: float = 2.0
     a_max: int = 20
     self_contact: bool = True
+    tol_inner: float = 0.0     # Algorithm 1 inner loop condition (<= 0: the budget alone)
+    tol_outer: float = 0.0     # Algorithm 1 outer loop condition (<= 0: the budget alone)
     warm_iters: int = 0        # modal warm-start iterations (0 = start from z)
     rf_iters: int = 0          # residual-forwarding iterations (0 = off)
     rf_toi: float = 0.5        # forward the residual when the exiting t_TOI is below this
@@ -86,6 +88,10 @@ class StepStats:
     n_constraints: int = 0
     fallbacks: int = 0
     t_exit: float = NO_HIT     # t_TOI of the step's last (exiting) filter
+    outer_dx: List[float] = field(default_factory=list)   # change of x over each outer block run
+    inner_iters: int = 0       # inner iterations run
+    outer_iters: int = 0       # outer blocks run
+    block_iters: List[int] = field(default_factory=list)   # inner iterations of each block run
 
 
 def chebyshev_weights(n: int, rho: float, delay: int) -> np.ndarray:
@@ -124,12 +130,26 @@ def polar_3x2(F: np.ndarray) -> np.ndarray:
     return T
 
 
+def strain_limited_3x2(F: np.ndarray, smin: float, smax: float) -> np.ndarray:
+    """Closest 3x2 matrix to each F whose singular values lie in
+    [smin, smax]: T = U clamp(Sigma) V^T from the thin SVD F = U Sigma V^T
+    (the strain-limiting projection of a triangle's deformation gradient;
+    smin = smax = 1 is the rotation of polar_3x2)."""
+    Uf, sv, Vt = np.linalg.svd(F, full_matrices=False)
+    return np.einsum("tdi,ti,tij->tdj", Uf, np.clip(sv, smin, smax), Vt)
+
+
 def elastic_rhs(model: Model, x: np.ndarray) -> np.ndarray:
     """sum_t w_t G_t^T T_t^T + sum_e w_e K_e y_e (local step, Eq. (local)) as
-    a per-vertex 3-vector."""
+    a per-vertex 3-vector; T is the projection of the deformation gradient
+    onto rotations, or onto the strain-limited set when the model's limits
+    are not (1, 1)."""
     xs = x[model.tris]                                      # (T,3,3) corners x xyz
     F = np.einsum("tcd,tci->tdi", xs, model.g)              # (T,3,2)
-    T = polar_3x2(F)
+    if model.sigma_min == 1.0 and model.sigma_max == 1.0:
+        T = polar_3x2(F)
+    else:
+        T = strain_limited_3x2(F, model.sigma_min, model.sigma_max)
     contrib = np.einsum("tdi,tci->tcd", T, model.g) * model.w_tri[:, None, None]
     rhs = np.zeros_like(x)
     np.add.at(rhs, model.tris.ravel(), contrib.reshape(-1, 3))
@@ -357,12 +377,23 @@ class Oracle:
         self._freeze(C, xm)
         t_exit = NO_HIT
         for o in range(p.iters_outer):
+            # outer loop condition (Algorithm 1, section 7): stop once the
+            # previous block moved no vertex by tol_outer or more
+            if o > 0 and p.tol_outer > 0 and st.outer_dx[-1] < p.tol_outer:
+                break
+            st.outer_iters += 1
+            st.block_iters.append(0)
             xk = x.copy()
             xkm1 = x.copy()
             for k in range(p.iters_inner):
+                # inner loop condition: the previous iteration's max change
+                if k > 0 and p.tol_inner > 0 and st.dx[-1] < p.tol_inner:
+                    break
                 xk1 = self.iterate(xk, xkm1, k, C, inertia, xm)
                 self._partial_ccd(C, xm, xk1)
                 st.dx.append(float(np.linalg.norm(xk1 - xk, axis=1).max()))
+                st.inner_iters += 1
+                st.block_iters[-1] += 1
                 xkm1, xk = xk, xk1
             xp = xk
             st_o = StepStats()
@@ -372,6 +403,7 @@ class Oracle:
             st.fallbacks += st_o.fallbacks
             t_exit = st_o.min_toi
             x = xm + s * (xp - xm)
+            st.outer_dx.append(float(np.linalg.norm(x - xm, axis=1).max()))
             xm = x.copy()
             self._freeze(C, xm)
         st.n_constraints = len(C.vt) + len(C.ee) + len(C.ob)
@@ -408,8 +440,13 @@ class Oracle:
                           a_ob=np.zeros_like(C.a_ob), lam_vt=C.lam_vt, n_vt=C.n_vt, lam_ee=C.lam_ee, n_ee=C.n_ee)
         xk = x.copy()
         xkm1 = x.copy()
+        dx_prev = np.inf
         for k in range(self.p.rf_iters):
+            # the inner loop condition applies here too (Algorithm 1, end)
+            if k > 0 and self.p.tol_inner > 0 and dx_prev < self.p.tol_inner:
+                break
             xk1 = self.iterate(xk, xkm1, k, Crf, inertia, x)
+            dx_prev = float(np.linalg.norm(xk1 - xk, axis=1).max())
             xkm1, xk = xk, xk1
         dx = xk - x
         dx[~self.free] = 0

@@ -21,6 +21,7 @@ CLOTH_E_MESH = -2
 CLOTH_E_OOM = -3
 CLOTH_E_CAPACITY = -4
 CLOTH_E_DIVERGED = -5
+CLOTH_E_TANGLED = -6
 CLOTH_E_DEVICE = -7
 CLOTH_PLAIN_FP32 = 0
 CLOTH_MIXED = 1
@@ -46,14 +47,17 @@ class Mesh(C.Structure):
 
 class Material(C.Structure):
     _fields_ = [("density", C.c_double), ("k_stretch", C.c_double), ("k_bend", C.c_double),
+                ("sigma_min", C.c_double), ("sigma_max", C.c_double),
                 ("k_contact", C.c_double), ("K_base", C.c_double), ("a_max", C.c_int32),
                 ("d_hat", C.c_double), ("alpha", C.c_double)]
 
 
 class SolverParams(C.Structure):
     _fields_ = [("r", C.c_int32), ("iters_inner", C.c_int32), ("iters_outer", C.c_int32),
+                ("tol_inner", C.c_double), ("tol_outer", C.c_double),
                 ("cheb_rho", C.c_double), ("cheb_gamma", C.c_double), ("cheb_delay", C.c_int32),
-                ("precision", C.c_int32), ("self_contact", C.c_int32), ("pair_capacity", C.c_int64)]
+                ("precision", C.c_int32), ("self_contact", C.c_int32), ("pair_capacity", C.c_int64),
+                ("debug_tangles", C.c_int32)]
 
 
 class Obstacle(C.Structure):
@@ -64,7 +68,8 @@ class Obstacle(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("inner_iters", C.c_int32), ("outer_iters", C.c_int32),
                 ("n_candidates", C.c_int64), ("n_constraints", C.c_int64),
-                ("dx_norm", C.c_double), ("min_toi", C.c_double), ("cheb_rho", C.c_double),
+                ("dx_norm", C.c_double), ("outer_dx", C.c_double), ("min_toi", C.c_double),
+                ("cheb_rho", C.c_double),
                 ("cheb_gamma", C.c_double), ("peak_candidates", C.c_int64),
                 ("n_contact_vertices", C.c_int64)]
 
@@ -157,9 +162,11 @@ class ClothScene:
     """One cloth scene resident on the device."""
 
     def __init__(self, tris, rest, *, dt, density=0.3, k_stretch=160.0, k_bend=3e-4,
-                 k_contact=0.0, K_base=2.0, a_max=20, d_hat=1e-3, alpha=0.8, pinned=None, r=16,
-                 iters_inner=10, iters_outer=1, cheb_rho=0.0, cheb_gamma=0.0, cheb_delay=3,
-                 precision=CLOTH_PLAIN_FP32, self_contact=False, pair_capacity=0, arena=None):
+                 sigma_min=1.0, sigma_max=1.0, k_contact=0.0, K_base=2.0, a_max=20, d_hat=1e-3,
+                 alpha=0.8, pinned=None, r=16, iters_inner=10, iters_outer=1, tol_inner=0.0,
+                 tol_outer=0.0, cheb_rho=0.0, cheb_gamma=0.0, cheb_delay=3,
+                 precision=CLOTH_PLAIN_FP32, self_contact=False, pair_capacity=0,
+                 debug_tangles=False, arena=None):
         self._tris = np.ascontiguousarray(tris, np.int32)
         rest = _f32(rest)
         nv = rest.shape[0]
@@ -167,9 +174,11 @@ class ClothScene:
         self._pinned = None if pinned is None else np.ascontiguousarray(pinned, np.uint8)
         self.mesh = Mesh(nv, self._tris.shape[0], self._tris.ctypes.data, None if self._pinned is None
                          else self._pinned.ctypes.data)
-        self.mat = Material(density, k_stretch, k_bend, k_contact, K_base, a_max, d_hat, alpha)
-        self.params = SolverParams(r, iters_inner, iters_outer, cheb_rho, cheb_gamma, cheb_delay,
-                                   precision, int(bool(self_contact)), pair_capacity)
+        self.mat = Material(density, k_stretch, k_bend, sigma_min, sigma_max, k_contact, K_base, a_max,
+                            d_hat, alpha)
+        self.params = SolverParams(r, iters_inner, iters_outer, tol_inner, tol_outer, cheb_rho,
+                                   cheb_gamma, cheb_delay, precision, int(bool(self_contact)),
+                                   pair_capacity, int(bool(debug_tangles)))
         self.r = r
         nbytes = C.c_size_t(0)
         _check(lib.cloth_query_footprint(C.byref(self.mesh), C.byref(self.params), C.byref(nbytes)),

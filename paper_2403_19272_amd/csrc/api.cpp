@@ -127,6 +127,14 @@ T* cv(const Carver& f, size_t count) {
     return static_cast<T*>(f(sizeof(T) * count));
 }
 
+// Norm slots of d.dxbits: one per inner iteration of the step (block-major),
+// then the residual-forwarding iterations, then one per outer block (the
+// change of x over the block); at least the Chebyshev estimate's.
+int slot_inner(const Scene& s, int o, int k) { return o * s.iters_in + k; }
+int slot_rf(const Scene& s, int k) { return s.iters_out * s.iters_in + k; }
+int slot_outer(const Scene& s, int o) { return s.iters_out * s.iters_in + RF_MAX + o; }
+int slots_needed(const Scene& s) { return std::max(slot_outer(s, s.iters_out), CHEB_EST_SLOTS); }
+
 }  // namespace
 
 // Carves every device buffer of a scene from `carve` (the arena, or a
@@ -171,12 +179,14 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     d.Lam = cv<double>(carve_fn, (size_t)s.r * s.r);
     d.Amat = cv<double>(carve_fn, (size_t)(GRAM_GROUPS_MAX + 1) * s.r * (s.r + 1) / 2);
     d.gram_part = cv<double>(carve_fn, (size_t)GRAM_CHUNKS * s.r * s.r);
-    d.dxbits = cv<unsigned long long>(carve_fn, 4096);
+    s.nslots_cap = slots_needed(s);
+    d.dxbits = cv<unsigned long long>(carve_fn, (size_t)s.nslots_cap);
     s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);
+    s.d_gate = cv<int>(carve_fn, 4);
     if (!d.x4 || !d.d4 || !d.W || !d.mh2 || !d.diag || !s.d_pinned || !s.d_rowptr || !s.d_col || !s.d_val || !s.d_tri ||
         !s.d_sell_ptr || !s.d_sell_col || !s.d_sell_val ||
         !s.d_inc_ptr || !s.d_inc || !s.d_edges || !s.d_U || !d.gpart || !d.Qf || !d.Qd || !d.Ainv ||
-        !d.Lam || !d.Amat || !d.gram_part || !d.dxbits || !s.d_rfdx)
+        !d.Lam || !d.Amat || !d.gram_part || !d.dxbits || !s.d_rfdx || !s.d_gate)
         return fail(CLOTH_E_OOM, "arena exhausted");
     return contact_layout(s, c, carve_fn);
 }
@@ -189,6 +199,8 @@ static size_t dry_footprint(const Scene& src) {
     s.nnz = src.nnz;
     s.nsell = src.nsell;
     s.r = src.r;
+    s.iters_in = src.iters_in;
+    s.iters_out = src.iters_out;
     s.prec = src.prec;
     s.self_contact = src.self_contact;
     s.pair_cap = src.pair_cap;
@@ -271,7 +283,7 @@ static cloth_status fail_any(cloth_status c, const char*) { return c; }
 // One inner iteration on the device state: x^k = d.xk, x^{k-1} = d.xkm1 ->
 // d.xk1; then buffers rotate so that d.xk holds x^{k+1}.
 static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStream_t st, bool linear,
-                                    float omega_override, bool force_k = false) {
+                                    float omega_override, bool force_k = false, int prev_slot = -1) {
     Scene& s = sc->s;
     ContactState& c = sc->c;
     Dev& d = s.d;
@@ -283,7 +295,8 @@ static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStrea
     if (has_contact) TIMED(K_GRAM_CHOL, contact_dynamic_solve(s, c, st));
     TIMED(K_EXPAND, launch_expand(d, s.prec, 0, st));
     float om = omega_override > 0 ? omega_override : s.omega[std::min(k, (int)s.omega.size() - 1)];
-    TIMED(K_JACOBI, launch_jacobi_cheb(d, om, (float)s.gamma, has_contact, s.d.dxbits + slot, st));
+    TIMED(K_JACOBI, launch_jacobi_cheb(d, om, (float)s.gamma, has_contact, s.d.dxbits + slot,
+                                       prev_slot >= 0 ? s.d.dxbits + prev_slot : nullptr, st));
     float* t = d.xkm1;
     d.xkm1 = d.xk;
     d.xk = d.xk1;
@@ -324,6 +337,7 @@ const char* cloth_status_string(cloth_status s) {
         case CLOTH_E_OOM: return "out of device memory";
         case CLOTH_E_CAPACITY: return "buffer capacity exceeded";
         case CLOTH_E_DIVERGED: return "diverged";
+        case CLOTH_E_TANGLED: return "tangled";
         case CLOTH_E_DEVICE: return "device error";
         default: return "unknown status";
     }
@@ -386,6 +400,8 @@ cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_pa
     ds.nnz = nnz;
     ds.nsell = nsell;
     ds.r = params->r;
+    ds.iters_in = std::max(1, params->iters_inner);
+    ds.iters_out = std::max(1, params->iters_outer);
     ds.prec = params->precision;
     ds.self_contact = params->self_contact;
     ds.pair_cap = params->pair_capacity > 0 ? params->pair_capacity : (int64_t)128 * mesh->nv;
@@ -402,6 +418,18 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
         return fail(CLOTH_E_INVALID, "r must be a multiple of 8 in [8, " + std::to_string(MAX_R) + "]");
     if (params->iters_inner <= 0 || params->iters_outer <= 0)
         return fail(CLOTH_E_INVALID, "iteration budgets must be positive");
+    if (params->debug_tangles && !params->self_contact)
+        return fail(CLOTH_E_INVALID, "the tangle check needs self contact on");
+    if ((int64_t)params->iters_inner * params->iters_outer > 65536)
+        return fail(CLOTH_E_INVALID, "iters_inner * iters_outer must be at most 65536");
+    if (!std::isfinite(params->tol_inner) || !std::isfinite(params->tol_outer))
+        return fail(CLOTH_E_INVALID, "tolerances must be finite");
+    {
+        const bool unset = mat->sigma_min == 0 && mat->sigma_max == 0;
+        if (!unset && !(mat->sigma_min > 0 && mat->sigma_min <= 1.0 && mat->sigma_max >= 1.0 &&
+                        std::isfinite(mat->sigma_max)))
+            return fail(CLOTH_E_INVALID, "strain limits must satisfy 0 < sigma_min <= 1 <= sigma_max");
+    }
     if (params->precision != CLOTH_PLAIN_FP32 && params->precision != CLOTH_MIXED)
         return fail(CLOTH_E_INVALID, "unknown precision");
     std::unique_ptr<cloth_scene_s> sc(new (std::nothrow) cloth_scene_s());
@@ -440,6 +468,8 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     d.inc = s.d_inc;
     d.edges = s.d_edges;
     d.U = s.d_U;
+    d.smin = (float)s.smin;
+    d.smax = (float)s.smax;
 
     // static uploads
     std::vector<float> tmp(3 * (size_t)n);
@@ -507,9 +537,21 @@ cloth_status cloth_system_matrix(cloth_scene sc, int64_t* nnz, int32_t* row_ptr,
 
 cloth_status cloth_estimate_chebyshev(cloth_scene sc, void* stream);
 
+// The recorded step graph holds the scene's settings as kernel arguments
+// (Chebyshev weights, obstacle count, step options); a setter that changes
+// them drops it so that the next step records it again.
+static cloth_status drop_graph(Scene& s) {
+    if (s.graph_exec) {
+        HIPCHECK(hipGraphExecDestroy(s.graph_exec));
+        s.graph_exec = nullptr;
+    }
+    return CLOTH_OK;
+}
+
 cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
     if (!sc || !U) return fail(CLOTH_E_INVALID, "null argument");
     Scene& s = sc->s;
+    if (drop_graph(s) != CLOTH_OK) return CLOTH_E_DEVICE;
     if (r != s.r) return fail(CLOTH_E_INVALID, "basis width differs from params.r");
     const int n = s.nv;
     s.Ustored.assign((size_t)n * r, 0.0);
@@ -578,16 +620,14 @@ cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
 
 cloth_status cloth_set_step_options(cloth_scene sc, int32_t warm_iters, int32_t rf_iters, double rf_toi) {
     if (!sc || warm_iters < 0 || rf_iters < 0) return fail(CLOTH_E_INVALID, "bad step options");
+    if (rf_iters > RF_MAX)
+        return fail(CLOTH_E_INVALID, "rf_iters must be at most " + std::to_string(RF_MAX));
     Scene& s = sc->s;
     s.warm_iters = warm_iters;
     s.rf_iters = rf_iters;
     s.rf_toi = rf_toi;
     if (s.basis_set) s.omega = cheb_weights(std::max(s.iters_in, s.rf_iters), s.rho, s.delay);
-    if (s.graph_exec) {
-        HIPCHECK(hipGraphExecDestroy(s.graph_exec));
-        s.graph_exec = nullptr;
-    }
-    return CLOTH_OK;
+    return drop_graph(s);
 }
 
 cloth_status cloth_get_forwarded(cloth_scene sc, float* dx) {
@@ -634,6 +674,8 @@ cloth_status cloth_add_obstacle(cloth_scene sc, const cloth_obstacle* ob) {
         o.a[i] = an > 0 ? ob->axis[i] / an : (i == 0 ? 1.0 : 0.0);
     }
     o.R = ob->radius;
+    cloth_status rc = drop_graph(s);
+    if (rc != CLOTH_OK) return rc;
     s.obst.push_back(o);
     return contact_set_obstacles(s, sc->c);
 }
@@ -684,8 +726,18 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
     ContactState& c = sc->c;
     Dev& d = s.d;
     const int n = s.nv;
-    const int nslots = s.iters_out * s.iters_in;
-    TIMED(K_MISC, launch_fill_u64(d.dxbits, 0ull, nslots + 1, st));
+    // tolerance mode: the loop conditions of Algorithm 1 are decided on the
+    // device before each inner iteration (k_gate); the launches of a skipped
+    // iteration or block see a set gate and do nothing
+    const bool tol = s.tol_in > 0 || s.tol_out > 0;
+    // the gate is set only around the launches of one iteration or block end;
+    // an early return must not leave it set for later launches
+    struct GateReset {
+        Dev& d;
+        ~GateReset() { d.gate = nullptr; }
+    } gate_reset{d};
+    d.gate = nullptr;
+    TIMED(K_MISC, launch_step_open(d.dxbits, s.nslots_cap, c.cnt, s.d_gate, st));
     const bool contact = contact_enabled(s, c);
     const bool rf = s.rf_iters > 0 && contact;
     TIMED(K_PREDICT, launch_predict(d, (float)s.h, g[0], g[1], g[2], rf ? s.d_rfdx : nullptr, st));
@@ -707,16 +759,27 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
         TIMED(K_MISC, launch_copy3(d.xk, d.x, n, st));
         TIMED(K_MISC, launch_copy3(d.xkm1, d.x, n, st));
         for (int k = 0; k < s.iters_in; ++k) {
-            cloth_status rc = inner_iteration(sc, k, o * s.iters_in + k, st, false, 0.f);
+            const int slot = slot_inner(s, o, k);
+            if (tol) {
+                TIMED(K_MISC, launch_gate(s.d_gate, d.dxbits, k > 0 ? slot - 1 : -1, s.tol_in,
+                                          o > 0 ? slot_outer(s, o - 1) : -1, s.tol_out, 1, c.cnt, st));
+                d.gate = s.d_gate;
+            }
+            cloth_status rc = inner_iteration(sc, k, slot, st, false, 0.f, false, slot > 0 ? slot - 1 : -1);
+            if (rc == CLOTH_OK && contact) TIMED(K_PCCD, contact_partial_ccd(s, c, st));
+            d.gate = nullptr;
             if (rc != CLOTH_OK) return rc;
-            if (contact) TIMED(K_PCCD, contact_partial_ccd(s, c, st));
         }
+        // the block's end (its gate: the outer condition of its first iteration)
+        if (tol) d.gate = s.d_gate + 1;
+        unsigned long long* dxo = d.dxbits + slot_outer(s, o);
         if (contact) {
             bool last = o == s.iters_out - 1;
-            TIMED(K_OUTER, contact_block_end(s, c, !last || rf, st));  // x+ = x^k -> x, x-
+            TIMED(K_OUTER, contact_block_end(s, c, !last || rf, dxo, st));  // x+ = x^k -> x, x-
         } else {
-            TIMED(K_MISC, launch_copy3(d.x, d.xk, n, st));
+            TIMED(K_MISC, launch_block_end(d, dxo, st));
         }
+        d.gate = nullptr;
     }
     if (rf) {
         // residual forwarding (section 6): collision weights at k, no filter;
@@ -724,12 +787,19 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
         TIMED(K_MISC, launch_copy3(d.xk, d.x, n, st));
         TIMED(K_MISC, launch_copy3(d.xkm1, d.x, n, st));
         for (int k = 0; k < s.rf_iters; ++k) {
-            cloth_status rc = inner_iteration(sc, k, nslots, st, false, 0.f, true);
+            const int slot = slot_rf(s, k);
+            if (s.tol_in > 0) {
+                TIMED(K_MISC, launch_gate(s.d_gate, d.dxbits, k > 0 ? slot - 1 : -1, s.tol_in, -1, 0.0, 0, c.cnt, st));
+                d.gate = s.d_gate;
+            }
+            cloth_status rc = inner_iteration(sc, k, slot, st, false, 0.f, true, k > 0 ? slot - 1 : -1);
+            d.gate = nullptr;
             if (rc != CLOTH_OK) return rc;
         }
         TIMED(K_MISC, launch_rf_finish(d, d.xk, d.x, s.d_rfdx, c.tmin_bits + 2, s.rf_toi, st));
     }
-    TIMED(K_MISC, launch_epilogue(d, (float)(1.0 / s.h), st));
+    if (s.debug_tangles) TIMED(K_MISC, contact_tangle_check(s, c, d.x, st));
+    TIMED(K_MISC, launch_epilogue(d, (float)(1.0 / s.h), c.cnt, st));
     return CLOTH_OK;
 }
 
@@ -775,24 +845,45 @@ extern "C" {
 
 static cloth_status collect_stats(cloth_scene sc, hipStream_t st, cloth_step_stats* stats) {
     Scene& s = sc->s;
-    int last = s.iters_out * s.iters_in - 1;
-    unsigned long long bits = 0;
-    HIPCHECK(hipMemcpyAsync(&bits, s.d.dxbits + last, 8, hipMemcpyDeviceToHost, st));
+    ContactState& c = sc->c;
+    const bool tol = s.tol_in > 0 || s.tol_out > 0;
+    int h[CNT_TANGLES + 2];
+    HIPCHECK(hipMemcpyAsync(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+    std::vector<unsigned long long> bits((size_t)s.nslots_cap);
+    HIPCHECK(hipMemcpyAsync(bits.data(), s.d.dxbits, 8 * bits.size(), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
-    double dx;
-    std::memcpy(&dx, &bits, 8);
+    auto as_d = [](unsigned long long b) {
+        double v;
+        std::memcpy(&v, &b, 8);
+        return v;
+    };
     cloth_step_stats out{};
-    out.inner_iters = s.iters_in * s.iters_out;
-    out.outer_iters = s.iters_out;
-    out.dx_norm = dx;
+    out.inner_iters = tol ? h[CNT_INNER_DONE] : s.iters_in * s.iters_out;
+    out.outer_iters = tol ? h[CNT_OUTER_DONE] : s.iters_out;
+    // a skipped iteration repeats the norm of the last one that ran
+    out.dx_norm = as_d(bits[slot_inner(s, s.iters_out - 1, s.iters_in - 1)]);
+    out.outer_dx = as_d(bits[slot_outer(s, std::max(out.outer_iters, 1) - 1)]);
     out.cheb_rho = s.rho;
     out.cheb_gamma = s.gamma;
     out.min_toi = NO_HIT;
-    cloth_status rc = contact_stats(s, sc->c, st, &out);
+    cloth_status rc = contact_stats(s, c, st, &out);
     if (rc != CLOTH_OK) return rc;
-    if (!std::isfinite(dx)) return fail(CLOTH_E_DIVERGED, "non-finite iterate");
     s.last = out;
     if (stats) *stats = out;
+    const int fail_bits = h[CNT_STICKY];
+    if (fail_bits) {
+        // reported once: the record restarts empty
+        HIPCHECK(hipMemsetAsync(c.cnt + CNT_STICKY, 0, sizeof(int), st));
+        HIPCHECK(hipStreamSynchronize(st));
+        std::string why = step_failure_text(s, c, fail_bits);
+        if (fail_bits & STEP_TANGLED)
+            why += " last check: " + std::to_string(h[CNT_TANGLES]) + " crossing edge-triangle pairs, " +
+                   std::to_string(h[CNT_TANGLES + 1]) + " undecided;";
+        const cloth_status code = (fail_bits & STEP_DIVERGED)  ? CLOTH_E_DIVERGED
+                                  : (fail_bits & STEP_TANGLED) ? CLOTH_E_TANGLED
+                                                               : CLOTH_E_CAPACITY;
+        return fail(code, "a step since the last check failed and was rolled back:" + why);
+    }
     return CLOTH_OK;
 }
 

@@ -65,10 +65,11 @@ struct ContactState {
     ObstD* ob_dev = nullptr;     // device copy of ob[]
 
     // device scalars: [0] n_vt cand, [1] n_ee cand, [2] n_cvt, [3] n_cee,
-    // [4] n_prev_vt, [5] n_prev_ee, [6] n_cv, [7] overflow bits (sticky until
-    // read by contact_stats or cleared with a new state), [12] largest
-    // candidate list since the last stats read,
-    // [9] n_vt + n_ee, [10] obstacle constraints
+    // [4] n_prev_vt, [5] n_prev_ee, [6] n_cv, [7] status bits of the running
+    // step (capacity overflows, divergence), [12] largest candidate list
+    // since the last stats read, [9] n_vt + n_ee, [10] obstacle constraints,
+    // [13] status bits since the last stats read, [14] the last step's
+    // status, [15] / [16] inner iterations / outer blocks the step ran
     int* cnt = nullptr;
     unsigned long long* tmin_bits = nullptr;  // [0] stage min, [1] step min, [2] last stage's t_TOI
     double* tpart = nullptr;                  // per-block TOI minima of a stage (TOI, then obstacle blocks)
@@ -94,8 +95,14 @@ cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, hipStream_t st);
 cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st);
-cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, hipStream_t st);
+// dxo: slot of the change of x over the block (the outer loop condition)
+cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, unsigned long long* dxo, hipStream_t st);
 cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step_stats* out);
+// debug tangle check of the positions x (sets STEP_TANGLED in the running
+// step's status when an edge crosses a triangle sharing none of its vertices)
+cloth_status contact_tangle_check(Scene& s, ContactState& c, const float* x, hipStream_t st);
+// the reasons behind a failed step's status bits
+std::string step_failure_text(const Scene& s, const ContactState& c, int bits);
 // clears the sticky overflow record (with a new state)
 cloth_status contact_reset(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_load_constraints(Scene& s, ContactState& c, int64_t n_vt, const int32_t* vt,

@@ -20,6 +20,9 @@
 
 namespace cloth {
 
+// tolerance mode: a set gate turns the launch into a no-op (see Dev::gate)
+__device__ __forceinline__ bool gated(const int* g) { return g && *g; }
+
 namespace {
 
 constexpr int SCAN_TILE = 2048;   // items per scan block (256 threads x 8)
@@ -469,8 +472,9 @@ __device__ __forceinline__ int scan_used_tiles(int n_host, const int* n_dev, int
 }
 
 // per-tile sums, tiles taken grid-stride
-__global__ void __launch_bounds__(256) k_scan_tiles(const int* __restrict__ in, int n_host,
+__global__ void __launch_bounds__(256) k_scan_tiles(const int* __restrict__ gate, const int* __restrict__ in, int n_host,
                                                     const int* __restrict__ n_dev, int ntiles, int* tiles) {
+    if (gated(gate)) return;
     __shared__ int red[4];
     const int n = n_dev ? min(*n_dev, n_host) : n_host;
     const int used = scan_used_tiles(n_host, n_dev, ntiles);
@@ -490,8 +494,9 @@ __global__ void __launch_bounds__(256) k_scan_tiles(const int* __restrict__ in, 
 }
 
 // single block: exclusive scan of the used tile sums in place; total -> *total
-__global__ void __launch_bounds__(1024) k_scan_top(int* tiles, int n_host, const int* __restrict__ n_dev, int ntiles,
+__global__ void __launch_bounds__(1024) k_scan_top(const int* __restrict__ gate, int* tiles, int n_host, const int* __restrict__ n_dev, int ntiles,
                                                    int* total) {
+    if (gated(gate)) return;
     __shared__ int wsum[16];
     const int used = scan_used_tiles(n_host, n_dev, ntiles);
     const int per = (used + 1023) / 1024;
@@ -514,9 +519,10 @@ __global__ void __launch_bounds__(1024) k_scan_top(int* tiles, int n_host, const
 }
 
 // items of each used tile, tiles taken grid-stride
-__global__ void __launch_bounds__(256) k_scan_apply(const int* __restrict__ in, int n_host,
+__global__ void __launch_bounds__(256) k_scan_apply(const int* __restrict__ gate, const int* __restrict__ in, int n_host,
                                                     const int* __restrict__ n_dev, int ntiles,
                                                     const int* __restrict__ tiles, int* __restrict__ out) {
+    if (gated(gate)) return;
     __shared__ int wsum[4];
     const int n = n_dev ? min(*n_dev, n_host) : n_host;
     const int used = scan_used_tiles(n_host, n_dev, ntiles);
@@ -550,13 +556,13 @@ __global__ void __launch_bounds__(256) k_scan_apply(const int* __restrict__ in, 
 // kernels skip the tiles past n.
 constexpr int SCAN_GRID = 1024;
 static hipError_t scan_exclusive(const int* in, int* out, int n_cap, const int* n_dev, int* tiles, int* total,
-                                 hipStream_t st) {
+                                 const int* gate, hipStream_t st) {
     int nt = (n_cap + SCAN_TILE - 1) / SCAN_TILE;
     if (nt == 0) nt = 1;
     const int grid = std::min(nt, SCAN_GRID);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(grid), dim3(256), 0, st, in, n_cap, n_dev, nt, tiles);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tiles, n_cap, n_dev, nt, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(256), 0, st, in, n_cap, n_dev, nt, (const int*)tiles, out);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(grid), dim3(256), 0, st, gate, in, n_cap, n_dev, nt, tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, gate, tiles, n_cap, n_dev, nt, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(256), 0, st, gate, in, n_cap, n_dev, nt, (const int*)tiles, out);
     return hipGetLastError();
 }
 
@@ -576,7 +582,8 @@ static hipError_t scan_exclusive(const int* in, int* out, int n_cap, const int* 
 // (packed grid + cell key, ids, box), so a query reads contiguous records
 // and skips the ones of other cells that share its bucket.
 
-__global__ void k_fill_i32(int* p, int v, int n) {
+__global__ void k_fill_i32(const int* __restrict__ gate, int* p, int v, int n) {
+    if (gated(gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
@@ -652,8 +659,9 @@ __device__ __forceinline__ bool target_cell(const float* box, const BpGrid& g, i
 
 // AoS float4 copies of the two SoA position arrays (one 16-byte gather per
 // corner in the boxes and the TOI)
-__global__ void k_aos_pair(int n, const float* __restrict__ xm, const float* __restrict__ xp, float4* xm4,
+__global__ void k_aos_pair(const int* __restrict__ gate, int n, const float* __restrict__ xm, const float* __restrict__ xp, float4* xm4,
                            float4* xp4) {
+    if (gated(gate)) return;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         xm4[v] = make_float4(xm[v], xm[n + v], xm[2 * n + v], 0.f);
         xp4[v] = make_float4(xp[v], xp[n + v], xp[2 * n + v], 0.f);
@@ -664,6 +672,7 @@ __global__ void k_aos_pair(int n, const float* __restrict__ xm, const float* __r
 // statistics of the triangle and edge boxes (reduced by k_grid).
 __global__ void __launch_bounds__(256) k_boxes(Dev d, const float4* __restrict__ xm4, const float4* __restrict__ xp4,
                                                float dhat, float* vbox, float* tbox, float* ebox, float* bpart) {
+    if (gated(d.gate)) return;
     __shared__ float red[4][BP_PART];
     const int total = d.nv + d.nt + d.ne;
     float acc[BP_PART];
@@ -736,8 +745,9 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float4* __restrict__
 
 // One block: reduce the box partials; per family (0 = triangles, 1 = edges)
 // the cell widths of the two grids.
-__global__ void __launch_bounds__(256) k_grid(const float* __restrict__ bpart, int nblk, int nt, int ne,
+__global__ void __launch_bounds__(256) k_grid(const int* __restrict__ gate, const float* __restrict__ bpart, int nblk, int nt, int ne,
                                               BpGrid* grid) {
+    if (gated(gate)) return;
     __shared__ float red[4][BP_PART];
     // each thread folds whole partial records (BP_PART contiguous values),
     // then the wavefronts fold theirs with shuffles
@@ -781,8 +791,9 @@ __global__ void __launch_bounds__(256) k_grid(const float* __restrict__ bpart, i
 }
 
 // bucket counts of the targets' low-corner cells
-__global__ void __launch_bounds__(256) k_cells(int m, const float* __restrict__ box, const BpGrid* __restrict__ gp,
+__global__ void __launch_bounds__(256) k_cells(const int* __restrict__ gate, int m, const float* __restrict__ box, const BpGrid* __restrict__ gp,
                                                int* bucket_cnt, int P, int* overflow) {
+    if (gated(gate)) return;
     const BpGrid g = *gp;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         int c[3], grid;
@@ -795,6 +806,7 @@ __global__ void __launch_bounds__(256) k_cells(int m, const float* __restrict__ 
 // is arbitrary: query outputs are sorted by target id)
 __global__ void __launch_bounds__(256) k_bucket_fill(Dev d, int vt, int m, const float* __restrict__ box,
                                                      const BpGrid* __restrict__ gp, int P, int* cursor, BpRec* rec) {
+    if (gated(d.gate)) return;
     const BpGrid g = *gp;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         int c[3], grid;
@@ -840,8 +852,9 @@ constexpr int MAX_CELLS = 4096;   // cells one query may visit in one grid
 constexpr int MAX_HITS = 1024;    // largest per-query output bound (max_out)
 
 // total of the last count + last offset -> n (clamped to cap), overflow flag
-__global__ void k_count_total(const int* counts_scanned, const int* counts_raw, int m, int* n_out, int64_t cap,
+__global__ void k_count_total(const int* __restrict__ gate, const int* counts_scanned, const int* counts_raw, int m, int* n_out, int64_t cap,
                               int* overflow) {
+    if (gated(gate)) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         long long tot = m > 0 ? (long long)counts_scanned[m - 1] + counts_raw[m - 1] : 0;
         overflow[PEAK_SLOT - 7] = max(overflow[PEAK_SLOT - 7], (int)min(tot, (long long)INT_MAX));
@@ -871,7 +884,7 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
 // with a ballot and handed to hit(index, target id) in a fixed order (cells,
 // then records).  Returns the hit count (capped at max_out + G); `full` is
 // set when a bound is hit.
-template <bool VT, int G, typename Hit>
+template <bool VT, int G, bool ET = false, typename Hit>
 __device__ __forceinline__ int group_query(const Dev& d, int q, int lane, int sub, const float* __restrict__ qbox,
                                            const BpGrid& g, const int* __restrict__ bptr,
                                            const BpRec* __restrict__ rec, int P, int max_out, bool& full,
@@ -943,6 +956,9 @@ __device__ __forceinline__ int group_query(const Dev& d, int q, int lane, int su
                     pass = r.key == kj;
                     if (VT)
                         pass = pass && r.a != q && r.b != q && r.c != q;
+                    else if (ET)   // edge query, triangle targets sharing no vertex with it
+                        pass = pass && r.a != qa && r.a != qb2 && r.b != qa && r.b != qb2 && r.c != qa &&
+                               r.c != qb2;
                     else
                         pass = pass && r.id > q && r.a != qa && r.a != qb2 && r.b != qa && r.b != qb2;
                     pass = pass && !(ql[0] > r.hi[0] || r.lo[0] > qh[0] || ql[1] > r.hi[1] || r.lo[1] > qh[1] ||
@@ -968,6 +984,7 @@ __global__ void __launch_bounds__(256) k_query_count(Dev d, const float* __restr
                                                      const BpGrid* __restrict__ gp, const int* __restrict__ bptr,
                                                      const BpRec* __restrict__ rec, int P, int* count, int* scratch,
                                                      int max_out, int* overflow, int* heavy_list, int* heavy_n) {
+    if (gated(d.gate)) return;
     constexpr int GPB = 256 / G;
     __shared__ int res[GPB][QK];
     const int nq = VT ? d.nv : d.ne;
@@ -1008,8 +1025,9 @@ __global__ void __launch_bounds__(256) k_query_count(Dev d, const float* __restr
 // G lanes of a query copy its sorted hits to the candidate list at its
 // offset, consecutive lanes to consecutive entries.
 template <int G>
-__global__ void __launch_bounds__(256) k_query_copy(int nq, const int* __restrict__ ofs, const int* __restrict__ raw,
+__global__ void __launch_bounds__(256) k_query_copy(const int* __restrict__ gate, int nq, const int* __restrict__ ofs, const int* __restrict__ raw,
                                                     const int* __restrict__ scratch, int2* out, int64_t cap) {
+    if (gated(gate)) return;
     constexpr int GPB = 256 / G;
     const int lane = threadIdx.x % G;
     const int q = xcd_block(blockIdx.x, gridDim.x) * GPB + threadIdx.x / G;
@@ -1037,6 +1055,7 @@ __global__ void __launch_bounds__(256) k_query_rescan(Dev d, const float* __rest
                                                       const int* __restrict__ ofs, const int* __restrict__ raw,
                                                       int2* out, int64_t cap, int max_out, int* overflow,
                                                       const int* __restrict__ heavy_list, int* heavy_n) {
+    if (gated(d.gate)) return;
     __shared__ int hits[4][MAX_HITS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const BpGrid g = *gp;
@@ -1097,6 +1116,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
                                                    const int2* __restrict__ cvt, const int2* __restrict__ cee,
                                                    int* cnt, double* toi_vt, double* toi_ee, int* keep,
                                                    int* cand_a, double* tpart, int do_merge) {
+    if (gated(d.gate)) return;
     __shared__ double wmin[4];
     __shared__ int queue[TOI_CHUNK + 256];   // pairs waiting for root refinement
     __shared__ int fbq[TOI_FB];   // pairs that need the sampled fallback
@@ -1214,11 +1234,12 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
 // by query at the offsets ofs and sorted by target inside a group) and, when
 // found, keeps that candidate and hands it its life span.  Runs after
 // k_toi_merge, which set keep = (TOI <= 1) and a = 0 for every candidate.
-__global__ void __launch_bounds__(256) k_prev_match(const int* __restrict__ cnt, const int2* __restrict__ prev,
+__global__ void __launch_bounds__(256) k_prev_match(const int* __restrict__ gate, const int* __restrict__ cnt, const int2* __restrict__ prev,
                                                     const int* __restrict__ prev_a, const int2* __restrict__ cvt,
                                                     const int2* __restrict__ cee, const int* __restrict__ vofs,
                                                     const int* __restrict__ eofs, int nv, int ne, int* keep,
                                                     int* cand_a) {
+    if (gated(gate)) return;
     const int nvt = cnt[0], nee = cnt[1], pvt = cnt[4], pee = cnt[5];
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < pvt + pee; p += gridDim.x * blockDim.x) {
         const bool vt = p < pvt;
@@ -1246,6 +1267,7 @@ __global__ void __launch_bounds__(256) k_prev_match(const int* __restrict__ cnt,
 // obstacles: TOI on (xm, xp) and membership with carried life spans
 __global__ void __launch_bounds__(256) k_obstacles_outer(Dev d, const float* __restrict__ xm, const float* __restrict__ xp,
                                   double* tpart, int* n_ob) {
+    if (gated(d.gate)) return;
     __shared__ double wmin[4];
     const int nob = d.nob;
     const ObstD* ob = d.ob;
@@ -1279,8 +1301,9 @@ __global__ void __launch_bounds__(256) k_obstacles_outer(Dev d, const float* __r
 // kernels (npart of them) and tmin_bits[0]; s = 1 (no hit) or alpha t_TOI;
 // running minimum for the statistics and the stage's own t_TOI (the exiting
 // one after the last stage).  One block of 256 threads.
-__global__ void k_step_length(const double* __restrict__ tpart, int npart, unsigned long long* tmin_bits,
-                              double alpha, double* s_dev) {
+__global__ void k_step_length(const int* __restrict__ gate, const double* __restrict__ tpart, int npart, unsigned long long* tmin_bits,
+                              double alpha, double* s_dev, const int* __restrict__ fail) {
+    if (gated(gate)) return;
     __shared__ double red[256];
     double m = NOHIT;
     for (int i = threadIdx.x; i < npart; i += blockDim.x) m = fmin(m, tpart[i]);
@@ -1293,7 +1316,10 @@ __global__ void k_step_length(const double* __restrict__ tpart, int npart, unsig
     if (threadIdx.x == 0) {
         double t = fmin(red[0], __longlong_as_double((long long)tmin_bits[0]));
         tmin_bits[0] = (unsigned long long)__double_as_longlong(t);
-        s_dev[0] = t > 1.0 ? 1.0 : alpha * t;
+        // a stage whose candidate or constraint lists overflowed has pairs
+        // without a time of impact: the block does not move (the step is
+        // rolled back at its end and reports the overflow)
+        s_dev[0] = (fail && (*fail & (OVF_QUERY | OVF_CELL | OVF_LIST | OVF_CONS))) ? 0.0 : (t > 1.0 ? 1.0 : alpha * t);
         tmin_bits[2] = tmin_bits[0];
         if (tmin_bits[0] < tmin_bits[1]) tmin_bits[1] = tmin_bits[0];
         tmin_bits[0] = (unsigned long long)__double_as_longlong(NOHIT);
@@ -1301,9 +1327,10 @@ __global__ void k_step_length(const double* __restrict__ tpart, int npart, unsig
 }
 
 // compaction of kept candidates into the new constraint list (order kept)
-__global__ void k_compact(const int2* __restrict__ cvt, const int2* __restrict__ cee, int* cnt,
+__global__ void k_compact(const int* __restrict__ gate, const int2* __restrict__ cvt, const int2* __restrict__ cee, int* cnt,
                           const int* __restrict__ keep, const int* __restrict__ ofs, const int* __restrict__ cand_a,
                           int2* cpair, int* ca, int64_t ccap) {
+    if (gated(gate)) return;
     const int nvt = cnt[0], nee = cnt[1];
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nvt + nee; i += gridDim.x * blockDim.x) {
         if (keep[i]) {
@@ -1331,6 +1358,7 @@ __global__ void k_compact(const int2* __restrict__ cvt, const int2* __restrict__
 // ================================================================ frozen data
 // Closest-point parameters and normals at x- (start of the block).
 __global__ void __launch_bounds__(256) k_freeze(Dev d, const int* cnt, const int2* __restrict__ cpair, double2* clam, float4* cnrm) {
+    if (gated(d.gate)) return;
     const int nvt = cnt[2], nc = cnt[2] + cnt[3];
     const int n = d.nv;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
@@ -1365,6 +1393,7 @@ __global__ void __launch_bounds__(256) k_freeze(Dev d, const int* cnt, const int
 
 // vertex -> slot incidence (slot = 4 * constraint + corner)
 __global__ void k_slot_count(Dev d, const int* cnt, const int2* __restrict__ cpair, int* vcnt) {
+    if (gated(d.gate)) return;
     const int nvt = cnt[2], nc = cnt[2] + cnt[3];
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
         int2 pr = cpair[p];
@@ -1375,6 +1404,7 @@ __global__ void k_slot_count(Dev d, const int* cnt, const int2* __restrict__ cpa
 }
 
 __global__ void k_slot_fill(Dev d, const int* cnt, const int2* __restrict__ cpair, int* cursor, int* vslot) {
+    if (gated(d.gate)) return;
     const int nvt = cnt[2], nc = cnt[2] + cnt[3];
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
         int2 pr = cpair[p];
@@ -1388,6 +1418,7 @@ __global__ void k_slot_fill(Dev d, const int* cnt, const int2* __restrict__ cpai
 // contact vertices (in a pair constraint or an obstacle constraint)
 __global__ void __launch_bounds__(256) k_slot_sort(Dev d, const int* __restrict__ ptr, int* vslot, const int* __restrict__ ob_a, int nob,
                             int* flag) {
+    if (gated(d.gate)) return;
     const int n = d.nv;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         int b0 = ptr[v], b1 = ptr[v + 1];
@@ -1405,7 +1436,8 @@ __global__ void __launch_bounds__(256) k_slot_sort(Dev d, const int* __restrict_
     }
 }
 
-__global__ void k_cv_compact(int n, const int* __restrict__ flag, const int* __restrict__ ofs, int* list, int* n_out) {
+__global__ void k_cv_compact(const int* __restrict__ gate, int n, const int* __restrict__ flag, const int* __restrict__ ofs, int* list, int* n_out) {
+    if (gated(gate)) return;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
         if (flag[v]) list[ofs[v]] = v;
     if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = n > 0 ? ofs[n - 1] + flag[n - 1] : 0;
@@ -1419,6 +1451,7 @@ __global__ void k_cv_compact(int n, const int* __restrict__ flag, const int* __r
 __global__ void __launch_bounds__(256) k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ cpair, const int* __restrict__ ca,
                                const double2* __restrict__ clam, const float4* __restrict__ cnrm, float kc, float Kb,
                                float dhat, float4* slot, int force_k) {
+    if (gated(d.gate)) return;
     const int nvt = cnt[2], nc = cnt[2] + cnt[3];
     const int n = d.nv;
     const float* X = d.xk;
@@ -1458,6 +1491,7 @@ __global__ void __launch_bounds__(256) k_pair_targets(Dev d, const int* cnt, con
 // min(a+1, a_max) : 0.  Obstacles: active when phi(x^{k+1}) < d_hat.
 __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cpair, int* ca,
                               const double2* __restrict__ clam, int amax, const float* __restrict__ xnew) {
+    if (gated(d.gate)) return;
     const int nob = d.nob;
     const ObstD* ob = d.ob;
     int* ob_a = d.ob_a;
@@ -1571,6 +1605,7 @@ typedef double gram_d4 __attribute__((ext_vector_type(4)));
 template <typename UT>
 __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
                                             int nchunk, double* part) {
+    if (gated(d.gate)) return;
     constexpr int VB = 32;   // contact vertices staged per round (a multiple of 4)
     __shared__ float us[VB][MAX_R];
     __shared__ double ws[VB][MAX_R];
@@ -1680,6 +1715,7 @@ __device__ __forceinline__ void pk_entry(int e, int r, int& i, int& k) {
 constexpr int GRAM_GROUPS = GRAM_GROUPS_MAX;
 __global__ void __launch_bounds__(256) k_gram_reduce(Dev d, const double* __restrict__ part, int nchunk,
                                                      const int* __restrict__ n_cv, double* __restrict__ gred) {
+    if (gated(d.gate)) return;
     const int r = d.r;
     const int ncv = *n_cv;
     if (ncv == 0) return;
@@ -1711,6 +1747,7 @@ __device__ __forceinline__ void tri_rc(int e, int& i, int& j) {
 // A = Lambda~ + the group sums, packed row-major (second reduction level).
 __global__ void __launch_bounds__(256) k_gram_final(Dev d, const double* __restrict__ gred,
                                                     const int* __restrict__ n_cv, double* __restrict__ Arm) {
+    if (gated(d.gate)) return;
     if (*n_cv == 0) return;
     const int r = d.r;
     const int tot = r * (r + 1) / 2;
@@ -1919,6 +1956,7 @@ __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* 
 template <int NS>
 __global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __restrict__ Arm,
                                                      const double* __restrict__ g, const int* __restrict__ n_cv) {
+    if (gated(d.gate)) return;
     extern __shared__ double A[];
     const int r = d.r;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1990,13 +2028,15 @@ __global__ void k_aos4(int n, const float* __restrict__ X, float4* X4) {
         X4[v] = make_float4(X[v], X[n + v], X[2 * n + v], 0.f);
 }
 
-__global__ void k_copy_i32(int* __restrict__ dst, const int* __restrict__ src, int n) {
+__global__ void k_copy_i32(const int* __restrict__ gate, int* __restrict__ dst, const int* __restrict__ src, int n) {
+    if (gated(gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
 // previous constraint set <- current (count from device)
-__global__ void k_save_prev(int* cnt, const int2* __restrict__ cp, const int* __restrict__ a, int2* pp, int* pa,
+__global__ void k_save_prev(const int* __restrict__ gate, int* cnt, const int2* __restrict__ cp, const int* __restrict__ a, int2* pp, int* pa,
                             int first) {
+    if (gated(gate)) return;
     const int nc = first ? 0 : cnt[2] + cnt[3];
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
         pp[i] = cp[i];
@@ -2005,7 +2045,8 @@ __global__ void k_save_prev(int* cnt, const int2* __restrict__ cp, const int* __
 }
 
 // bookkeeping of the device counters at the start of an outer stage
-__global__ void k_stage_counters(int* cnt, int first, unsigned long long* tmin_bits) {
+__global__ void k_stage_counters(const int* __restrict__ gate, int* cnt, int first, unsigned long long* tmin_bits) {
+    if (gated(gate)) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         cnt[4] = first ? 0 : cnt[2];
         cnt[5] = first ? 0 : cnt[3];
@@ -2017,8 +2058,72 @@ __global__ void k_stage_counters(int* cnt, int first, unsigned long long* tmin_b
     }
 }
 
-__global__ void k_sum2(int* cnt) {
+__global__ void k_sum2(const int* __restrict__ gate, int* cnt) {
+    if (gated(gate)) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) cnt[9] = cnt[0] + cnt[1];
+}
+
+// ================================================================ tangle check
+// Debug check of an end state: an edge that crosses a triangle sharing none
+// of its vertices means two triangles intersect.  Orientation signs in FP64
+// (the FP32 coordinates and their differences are exact there) with a
+// static error bound; a sign the bound cannot certify makes the pair
+// "undecided", which is counted apart and never reported as a tangle.
+__device__ __forceinline__ int orient_sign(double4 a, double4 b, double4 c, double4 p) {
+    const double bx = b.x - a.x, by = b.y - a.y, bz = b.z - a.z;
+    const double cx = c.x - a.x, cy = c.y - a.y, cz = c.z - a.z;
+    const double px = p.x - a.x, py = p.y - a.y, pz = p.z - a.z;
+    const double m0 = cy * pz - cz * py, m1 = cx * pz - cz * px, m2 = cx * py - cy * px;
+    const double det = bx * m0 - by * m1 + bz * m2;
+    const double perm = fabs(bx) * (fabs(cy * pz) + fabs(cz * py)) + fabs(by) * (fabs(cx * pz) + fabs(cz * px)) +
+                        fabs(bz) * (fabs(cx * py) + fabs(cy * px));
+    const double bound = 1e-14 * perm;
+    return det > bound ? 1 : (det < -bound ? -1 : 0);
+}
+
+__device__ __forceinline__ double4 to_d4(float4 v) { return make_double4(v.x, v.y, v.z, 0.0); }
+
+// closed segment pq against closed triangle abc: 1 crossing, 0 apart, -1 undecided
+__device__ __forceinline__ int segment_crosses_triangle(double4 p, double4 q, double4 a, double4 b, double4 c) {
+    const int sp = orient_sign(a, b, c, p), sq = orient_sign(a, b, c, q);
+    if (sp == 0 || sq == 0) return -1;
+    if (sp == sq) return 0;
+    const int o1 = orient_sign(p, q, a, b), o2 = orient_sign(p, q, b, c), o3 = orient_sign(p, q, c, a);
+    if (o1 == 0 || o2 == 0 || o3 == 0) return -1;
+    return (o1 == o2 && o2 == o3) ? 1 : 0;
+}
+
+// One group of G lanes per edge, triangles from the cell buckets (static
+// boxes of the state, the triangle grid).  cnt[CNT_TANGLES]: crossings,
+// cnt[CNT_TANGLES + 1]: undecided pairs and queries beyond their work bound;
+// a crossing flags the running step.
+template <int G>
+__global__ void __launch_bounds__(256) k_tangle_query(Dev d, const float* __restrict__ ebox,
+                                                      const BpGrid* __restrict__ gp, const int* __restrict__ bptr,
+                                                      const BpRec* __restrict__ rec, int P,
+                                                      const float4* __restrict__ x4, int* cnt) {
+    constexpr int GPB = 256 / G;
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int sub = (threadIdx.x & 63) / G;
+    const int q = xcd_block(blockIdx.x, gridDim.x) * GPB + grp;
+    const BpGrid g = *gp;
+    int crossings = 0, undecided = 0;
+    if (q < d.ne) {
+        const double4 p0 = to_d4(x4[d.edges[2 * q]]), p1 = to_d4(x4[d.edges[2 * q + 1]]);
+        bool full = false;
+        group_query<false, G, true>(d, q, lane, sub, ebox, g, bptr, rec, P, MAX_VISIT, full, [&](int, int id) {
+            const TriRec tr = d.tri[id];
+            const int r = segment_crosses_triangle(p0, p1, to_d4(x4[tr.v0]), to_d4(x4[tr.v1]), to_d4(x4[tr.v2]));
+            crossings += r > 0;
+            undecided += r < 0;
+        });
+        if (full && lane == 0) undecided += 1;
+    }
+    if (crossings) {
+        atomicAdd(&cnt[CNT_TANGLES], crossings);
+        atomicOr(&cnt[CNT_STEP_FAIL], STEP_TANGLED);
+    }
+    if (undecided) atomicAdd(&cnt[CNT_TANGLES + 1], undecided);
 }
 
 // ================================================================ host side
@@ -2065,6 +2170,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
         return set_error(CLOTH_E_OOM, "arena exhausted (contact scalars)");
     Dev& d = s.d;
     d.gvec = c.gvec;
+    d.fail = c.cnt + CNT_STEP_FAIL;
     d.ob_a = c.ob_a;
     d.ob = c.ob_dev;
     d.nob = 0;
@@ -2152,29 +2258,48 @@ cloth_status contact_set_obstacles(Scene& s, ContactState& c) {
     return CLOTH_OK;
 }
 
+// Boxes of the vertices, triangles and edges over (xm, xp) grown by dhat,
+// and the cell sizes of the two target families.
+static void bp_boxes(Scene& s, ContactState& c, const float* xm, const float* xp, float dhat, hipStream_t st) {
+    Dev& d = s.d;
+    const int n = s.nv;
+    const int nbb = gblocks((int64_t)n + s.nt + s.ne);
+    // AoS copies of the two positions, for the corner gathers of the boxes and the TOI
+    hipLaunchKernelGGL(k_aos_pair, dim3(gblocks(n)), dim3(TPB), 0, st, s.d.gate, n, xm, xp, c.xm4, c.xp4);
+    hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
+                       dhat, c.vbox, c.tbox, c.ebox, c.bpart);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, s.d.gate, (const float*)c.bpart, nbb, s.nt, s.ne, c.grid);
+}
+
+// Files the targets of one family (vt: triangles, else edges) in the cell
+// buckets: counts, bucket offsets, inline records.
+static cloth_status bp_file_targets(Scene& s, ContactState& c, bool vt, hipStream_t st) {
+    Dev& d = s.d;
+    const int P = c.hash_p;
+    const int m = vt ? s.nt : s.ne;
+    const float* tb = vt ? c.tbox : c.ebox;
+    const BpGrid* g = c.grid + (vt ? 0 : 1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, s.d.gate, c.bucket_cnt, 0, P + 1);
+    hipLaunchKernelGGL(k_cells, dim3(gblocks(m)), dim3(TPB), 0, st, s.d.gate, m, tb, g, c.bucket_cnt, P, c.cnt + 7);
+    HC(scan_exclusive(c.bucket_cnt, c.bucket_ptr, P + 1, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
+    hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, s.d.gate, c.bucket_cnt, c.bucket_ptr, P + 1);
+    hipLaunchKernelGGL(k_bucket_fill, dim3(gblocks(m)), dim3(TPB), 0, st, d, vt ? 1 : 0, m, tb, g, P,
+                       c.bucket_cnt, c.rec);
+    return CLOTH_OK;
+}
+
 // Broad phase on (xm, xp) -> sorted candidates, counts in cnt[0], cnt[1].
 static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, const float* xp, hipStream_t st) {
     if (!s.self_contact) return CLOTH_OK;
     Dev& d = s.d;
     const int n = s.nv;
     const int P = c.hash_p;
-    const int nbb = gblocks((int64_t)n + s.nt + s.ne);
-    // AoS copies of the two positions, for the corner gathers of the boxes and the TOI
-    hipLaunchKernelGGL(k_aos_pair, dim3(gblocks(n)), dim3(TPB), 0, st, n, xm, xp, c.xm4, c.xp4);
-    hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
-                       (float)s.dhat, c.vbox, c.tbox, c.ebox, c.bpart);
-    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, (const float*)c.bpart, nbb, s.nt, s.ne, c.grid);
+    bp_boxes(s, c, xm, xp, (float)s.dhat, st);
     for (int pass = 0; pass < 2; ++pass) {
         const bool vt = pass == 0;
-        const int m = vt ? s.nt : s.ne;
-        const float* tb = vt ? c.tbox : c.ebox;
         const BpGrid* g = c.grid + (vt ? 0 : 1);
-        hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, c.bucket_cnt, 0, P + 1);
-        hipLaunchKernelGGL(k_cells, dim3(gblocks(m)), dim3(TPB), 0, st, m, tb, g, c.bucket_cnt, P, c.cnt + 7);
-        HC(scan_exclusive(c.bucket_cnt, c.bucket_ptr, P + 1, nullptr, c.scan_tiles, nullptr, st));
-        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, c.bucket_cnt, c.bucket_ptr, P + 1);
-        hipLaunchKernelGGL(k_bucket_fill, dim3(gblocks(m)), dim3(TPB), 0, st, d, vt ? 1 : 0, m, tb, g, P,
-                           c.bucket_cnt, c.rec);
+        cloth_status rc = bp_file_targets(s, c, vt, st);
+        if (rc != CLOTH_OK) return rc;
         const int nq = vt ? n : s.ne;
         int* cnts = vt ? c.vcount : c.ecount;
         int2* outp = vt ? c.cand_vt : c.cand_ee;
@@ -2187,11 +2312,11 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
             hipLaunchKernelGGL((k_query_count<false, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
                                c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7, c.heavy_q,
                                c.cnt + HEAVY_SLOT);
-        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, c.keep, cnts, nq);
-        HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, st));
-        hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
+        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, s.d.gate, c.keep, cnts, nq);
+        HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
+        hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, s.d.gate, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
                            c.cnt + 7);
-        hipLaunchKernelGGL(k_query_copy<QUERY_LANES>, dim3(qblocks(nq)), dim3(256), 0, st, nq, (const int*)cnts,
+        hipLaunchKernelGGL(k_query_copy<QUERY_LANES>, dim3(qblocks(nq)), dim3(256), 0, st, s.d.gate, nq, (const int*)cnts,
                            (const int*)c.keep, (const int*)c.qscratch, outp, c.cap);
         if (vt)
             hipLaunchKernelGGL(k_query_rescan<true>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
@@ -2206,9 +2331,26 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
     return CLOTH_OK;
 }
 
+// Debug tangle check of the positions x (end of a step): static boxes,
+// triangles filed in their grid, one query per edge (k_tangle_query).
+// The broad-phase buffers are free at this point of the step.
+cloth_status contact_tangle_check(Scene& s, ContactState& c, const float* x, hipStream_t st) {
+    if (!s.self_contact) return CLOTH_OK;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (const int*)nullptr, c.cnt + CNT_TANGLES, 0, 2);
+    bp_boxes(s, c, x, x, 0.0f, st);
+    cloth_status rc = bp_file_targets(s, c, true, st);
+    if (rc != CLOTH_OK) return rc;
+    hipLaunchKernelGGL(k_tangle_query<QUERY_LANES>, dim3(qblocks(s.ne)), dim3(256), 0, st, s.d,
+                       (const float*)c.ebox, (const BpGrid*)c.grid, (const int*)c.bucket_ptr, (const BpRec*)c.rec,
+                       c.hash_p, (const float4*)c.xm4, c.cnt);
+    HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
 // TOI + merge with the previous set + obstacles + step length + compaction +
 // filter x = xm + s (xp - xm) written to d.x and d.xm.
-static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm, const float* xp, hipStream_t st) {
+static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm, const float* xp,
+                                    unsigned long long* dxo, hipStream_t st) {
     Dev& d = s.d;
     const int n = s.nv;
     int npart = 0;
@@ -2216,7 +2358,7 @@ static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm,
         const int nb = gblocks(2 * c.cap);
         hipLaunchKernelGGL(k_toi_merge, dim3(nb), dim3(TPB), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
                            c.cand_vt, c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.keep, c.cand_a, c.tpart, 1);
-        hipLaunchKernelGGL(k_prev_match, dim3(gblocks(c.ccap)), dim3(TPB), 0, st, (const int*)c.cnt,
+        hipLaunchKernelGGL(k_prev_match, dim3(gblocks(c.ccap)), dim3(TPB), 0, st, s.d.gate, (const int*)c.cnt,
                            (const int2*)c.cpair_prev, (const int*)c.ca_prev, (const int2*)c.cand_vt,
                            (const int2*)c.cand_ee, (const int*)c.vcount, (const int*)c.ecount, n, s.ne, c.keep,
                            c.cand_a);
@@ -2227,15 +2369,15 @@ static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm,
         hipLaunchKernelGGL(k_obstacles_outer, dim3(nb), dim3(TPB), 0, st, d, xm, xp, c.tpart + npart, c.cnt + 10);
         npart += nb;
     }
-    hipLaunchKernelGGL(k_step_length, dim3(1), dim3(256), 0, st, (const double*)c.tpart, npart, c.tmin_bits, s.alpha,
-                       c.s_dev);
+    hipLaunchKernelGGL(k_step_length, dim3(1), dim3(256), 0, st, s.d.gate, (const double*)c.tpart, npart, c.tmin_bits, s.alpha,
+                       c.s_dev, (const int*)(c.cnt + CNT_STEP_FAIL));
     if (s.self_contact) {
-        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(64), 0, st, c.cnt);
-        HC(scan_exclusive(c.keep, c.keep_ofs, (int)(2 * c.cap), c.cnt + 9, c.scan_tiles, nullptr, st));
-        hipLaunchKernelGGL(k_compact, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, c.cand_vt, c.cand_ee, c.cnt, c.keep,
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(64), 0, st, s.d.gate, c.cnt);
+        HC(scan_exclusive(c.keep, c.keep_ofs, (int)(2 * c.cap), c.cnt + 9, c.scan_tiles, nullptr, s.d.gate, st));
+        hipLaunchKernelGGL(k_compact, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, s.d.gate, c.cand_vt, c.cand_ee, c.cnt, c.keep,
                            c.keep_ofs, c.cand_a, c.cpair, c.ca, c.ccap);
     }
-    HC(launch_filter(d, xm, xp, c.s_dev, d.x, d.xm, st));
+    HC(launch_filter(d, xm, xp, c.s_dev, d.x, d.xm, dxo, st));
     HC(hipGetLastError());
     return CLOTH_OK;
 }
@@ -2246,39 +2388,39 @@ static cloth_status block_setup(Scene& s, ContactState& c, hipStream_t st) {
     const int n = s.nv;
     if (s.self_contact) {
         hipLaunchKernelGGL(k_freeze, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.clam, c.cnrm);
-        hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(n + 1)), dim3(TPB), 0, st, c.vslot_fill, 0, n + 1);
+        hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(n + 1)), dim3(TPB), 0, st, s.d.gate, c.vslot_fill, 0, n + 1);
         hipLaunchKernelGGL(k_slot_count, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.vslot_fill);
-        HC(scan_exclusive(c.vslot_fill, c.vslot_ptr, n + 1, nullptr, c.scan_tiles, nullptr, st));
-        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(n + 1)), dim3(TPB), 0, st, c.vslot_fill, c.vslot_ptr, n + 1);
+        HC(scan_exclusive(c.vslot_fill, c.vslot_ptr, n + 1, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
+        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(n + 1)), dim3(TPB), 0, st, s.d.gate, c.vslot_fill, c.vslot_ptr, n + 1);
         hipLaunchKernelGGL(k_slot_fill, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.vslot_fill,
                            c.vslot);
     }
     hipLaunchKernelGGL(k_slot_sort, dim3(gblocks(n)), dim3(TPB), 0, st, d, c.vslot_ptr, c.vslot, c.ob_a, c.nob,
                        c.cvflag);
-    HC(scan_exclusive(c.cvflag, c.cvofs, n, nullptr, c.scan_tiles, nullptr, st));
-    hipLaunchKernelGGL(k_cv_compact, dim3(gblocks(n)), dim3(TPB), 0, st, n, c.cvflag, c.cvofs, c.cvlist, c.cnt + 6);
+    HC(scan_exclusive(c.cvflag, c.cvofs, n, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
+    hipLaunchKernelGGL(k_cv_compact, dim3(gblocks(n)), dim3(TPB), 0, st, s.d.gate, n, c.cvflag, c.cvofs, c.cvlist, c.cnt + 6);
     HC(hipGetLastError());
     c.active = true;
     return CLOTH_OK;
 }
 
 static cloth_status outer_stage(Scene& s, ContactState& c, const float* xm, const float* xp, bool first,
-                                bool setup, hipStream_t st) {
-    if (first) hipLaunchKernelGGL(k_fill_i32, dim3(gblocks((int64_t)MAX_OBST * s.nv)), dim3(TPB), 0, st, c.ob_a, -1,
+                                bool setup, unsigned long long* dxo, hipStream_t st) {
+    if (first) hipLaunchKernelGGL(k_fill_i32, dim3(gblocks((int64_t)MAX_OBST * s.nv)), dim3(TPB), 0, st, s.d.gate, c.ob_a, -1,
                                   MAX_OBST * s.nv);
-    hipLaunchKernelGGL(k_save_prev, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, c.cnt, c.cpair, c.ca, c.cpair_prev,
+    hipLaunchKernelGGL(k_save_prev, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, s.d.gate, c.cnt, c.cpair, c.ca, c.cpair_prev,
                        c.ca_prev, first ? 1 : 0);
-    hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, st, c.cnt, first ? 1 : 0, c.tmin_bits);
+    hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, st, s.d.gate, c.cnt, first ? 1 : 0, c.tmin_bits);
     cloth_status rc = broad_phase(s, c, xm, xp, st);
     if (rc != CLOTH_OK) return rc;
-    rc = toi_merge_filter(s, c, xm, xp, st);
+    rc = toi_merge_filter(s, c, xm, xp, dxo, st);
     if (rc != CLOTH_OK) return rc;
     if (setup) return block_setup(s, c, st);
     return CLOTH_OK;
 }
 
 cloth_status contact_step_begin(Scene& s, ContactState& c, const float* xp, hipStream_t st) {
-    return outer_stage(s, c, s.d.xstar, xp, true, true, st);
+    return outer_stage(s, c, s.d.xstar, xp, true, true, nullptr, st);
 }
 
 cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st) {
@@ -2288,8 +2430,8 @@ cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st) {
     return CLOTH_OK;
 }
 
-cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, hipStream_t st) {
-    return outer_stage(s, c, s.d.xm, s.d.xk, false, setup, st);
+cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, unsigned long long* dxo, hipStream_t st) {
+    return outer_stage(s, c, s.d.xm, s.d.xk, false, setup, dxo, st);
 }
 
 cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, hipStream_t st) {
@@ -2339,8 +2481,9 @@ cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st) {
 cloth_status contact_reset(Scene& s, ContactState& c, hipStream_t st) {
     (void)s;
     if (c.cnt) {
-        HC(hipMemsetAsync(c.cnt + 7, 0, sizeof(int), st));
-        HC(hipMemsetAsync(c.cnt + 12, 0, sizeof(int), st));
+        HC(hipMemsetAsync(c.cnt + CNT_STEP_FAIL, 0, sizeof(int), st));
+        HC(hipMemsetAsync(c.cnt + PEAK_SLOT, 0, sizeof(int), st));
+        HC(hipMemsetAsync(c.cnt + CNT_STICKY, 0, 2 * sizeof(int), st));
     }
     return CLOTH_OK;
 }
@@ -2360,20 +2503,21 @@ cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step
     out->peak_candidates = h[12];
     out->n_contact_vertices = h[6];
     HC(hipMemsetAsync(c.cnt + 12, 0, sizeof(int), st));
-    if (h[7]) {
-        // sticky since the last read: clear it, then report what overflowed
-        HC(hipMemsetAsync(c.cnt + 7, 0, sizeof(int), st));
-        HC(hipStreamSynchronize(st));
-        std::string why;
-        if (h[7] & 1) why += " a query exceeded its work bound (cells, records or pairs);";
-        if (h[7] & 2) why += " a box could not be placed on the grid;";
-        if (h[7] & 4) why += " a candidate list exceeded the pair capacity (" + std::to_string(c.cap) + ");";
-        if (h[7] & 8) why += " the constraint set exceeded its capacity (" + std::to_string(c.ccap) + ");";
-        return set_error(CLOTH_E_CAPACITY, "broad phase overflow since the last check:" + why +
-                                               " last lists VT " + std::to_string(h[0]) + ", EE " + std::to_string(h[1]));
-    }
     (void)s;
     return CLOTH_OK;
+}
+
+// text for the status bits of a failed step
+std::string step_failure_text(const Scene& s, const ContactState& c, int bits) {
+    std::string why;
+    if (bits & OVF_QUERY) why += " a broad-phase query exceeded its work bound (cells, records or pairs);";
+    if (bits & OVF_CELL) why += " a box could not be placed on the broad-phase grid;";
+    if (bits & OVF_LIST) why += " a candidate list exceeded the pair capacity (" + std::to_string(c.cap) + ");";
+    if (bits & OVF_CONS) why += " the constraint set exceeded its capacity (" + std::to_string(c.ccap) + ");";
+    if (bits & STEP_DIVERGED) why += " an iterate became non-finite;";
+    if (bits & STEP_TANGLED) why += " the tangle check found edges crossing triangles;";
+    (void)s;
+    return why;
 }
 
 // ---- stage entry points (host arrays, caller order; SoA conversion here)
@@ -2395,7 +2539,7 @@ cloth_status contact_stage_broad_phase(Scene& s, ContactState& c, const float* x
     HC(hipMemcpy(s.d.xm, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
     to_soa(xp, t, s.nv);
     HC(hipMemcpy(s.d.xt, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, nullptr, c.cnt, 1, c.tmin_bits);
+    hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, nullptr, s.d.gate, c.cnt, 1, c.tmin_bits);
     HC(hipMemset(c.cnt + 7, 0, sizeof(int)));
     cloth_status rc = broad_phase(s, c, s.d.xm, s.d.xt, nullptr);
     if (rc != CLOTH_OK) return rc;
@@ -2491,7 +2635,7 @@ cloth_status contact_stage_outer(Scene& s, ContactState& c, const float* xm, con
     to_soa(xp, t, n);
     HC(hipMemcpy(s.d.xt, t.data(), 12 * (size_t)n, hipMemcpyHostToDevice));
     HC(hipMemset(c.cnt + 7, 0, sizeof(int)));
-    cloth_status rc = outer_stage(s, c, s.d.xm, s.d.xt, first != 0, true, nullptr);
+    cloth_status rc = outer_stage(s, c, s.d.xm, s.d.xt, first != 0, true, nullptr, nullptr);
     if (rc != CLOTH_OK) return rc;
     HC(hipDeviceSynchronize());
     int h[16];

@@ -46,6 +46,10 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     s.amax = mat->a_max > 0 ? mat->a_max : 20;
     s.dhat = mat->d_hat;
     s.alpha = mat->alpha > 0 ? mat->alpha : 0.8;
+    // strain limits: 0, 0 reads as the rotation projection (1, 1)
+    s.smin = (mat->sigma_min == 0 && mat->sigma_max == 0) ? 1.0 : mat->sigma_min;
+    s.smax = (mat->sigma_min == 0 && mat->sigma_max == 0) ? 1.0 : mat->sigma_max;
+
     s.tris.assign(mesh->tris, mesh->tris + 3 * (size_t)nt);
     s.pinned.assign(nv, 0);
     if (mesh->pinned)
@@ -241,6 +245,9 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     s.prec = prm->precision;
     s.self_contact = prm->self_contact;
     s.pair_cap = prm->pair_capacity > 0 ? prm->pair_capacity : (int64_t)128 * nv;
+    s.tol_in = prm->tol_inner > 0 ? prm->tol_inner : 0.0;
+    s.tol_out = prm->tol_outer > 0 ? prm->tol_outer : 0.0;
+    s.debug_tangles = prm->debug_tangles ? 1 : 0;
     return "";
 }
 

@@ -110,6 +110,38 @@ __device__ __forceinline__ void polar32(const float F[6], float T[6]) {
     }
 }
 
+// Strain-limited projection of a 3x2 deformation gradient: the nearest
+// matrix whose singular values lie in [smin, smax], T = F M with
+// M = V diag(c_i / sigma_i) V^T (F = U Sigma V^T, c_i = sigma_i clamped).
+// M is the matrix function f(S) = clamp(sqrt(S)) / sqrt(S) of S = F^T F,
+// formed from the two eigenvalues of S by spectral projectors:
+// f(S) = f2 I + (f1 - f2) (S - l2 I) / (l1 - l2), which stays accurate when
+// l1 - l2 is small (f1 - f2 is then small with it).
+__device__ __forceinline__ void strain_limit32(const float F[6], float smin, float smax, float T[6]) {
+    float s00 = F[0] * F[0] + F[2] * F[2] + F[4] * F[4];
+    float s01 = F[0] * F[1] + F[2] * F[3] + F[4] * F[5];
+    float s11 = F[1] * F[1] + F[3] * F[3] + F[5] * F[5];
+    float det = s00 * s11 - s01 * s01;
+    if (!(det > 1e-20f)) {
+        for (int i = 0; i < 6; ++i) T[i] = F[i];
+        return;
+    }
+    const float half_diff = 0.5f * (s00 - s11);
+    const float disc = sqrtf(half_diff * half_diff + s01 * s01);   // (l1 - l2) / 2
+    const float l1 = 0.5f * (s00 + s11) + disc;
+    const float l2 = det / l1;
+    const float g1 = sqrtf(l1), g2 = sqrtf(l2);
+    const float f1 = fminf(fmaxf(g1, smin), smax) / g1;
+    const float f2 = fminf(fmaxf(g2, smin), smax) / g2;
+    const float b = disc > 0.f ? (f1 - f2) / (2.0f * disc) : 0.f;
+    const float m00 = f2 + b * (s00 - l2), m11 = f2 + b * (s11 - l2), m01 = b * s01;
+    for (int d = 0; d < 3; ++d) {
+        float a0 = F[2 * d], a1 = F[2 * d + 1];
+        T[2 * d] = a0 * m00 + a1 * m01;
+        T[2 * d + 1] = a0 * m01 + a1 * m11;
+    }
+}
+
 // Workgroups are dealt round-robin over the 8 XCDs; this maps workgroup b to
 // a vertex tile so that each XCD (and its L2) works on one contiguous range,
 // where the neighbour gathers of the SpMV and of the triangle stencils hit.
@@ -153,11 +185,64 @@ __device__ __forceinline__ double warp_max(double v) {
     return v;
 }
 
+__device__ __forceinline__ bool gated(const int* g) { return g && *g; }
+
+__device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// block maximum of a per-thread value folded into *slot (FP64 bits; the
+// values are non-negative, so their bit patterns order like the values)
+__device__ __forceinline__ void block_max_to(double v, unsigned long long* slot) {
+    __shared__ double wmax[TPB / 64];
+    v = warp_max(v);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, wmax[i]);
+        atomicMax(slot, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
 }  // namespace
 
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Start of a step: the norm slots are cleared, the running step's status
+// and iteration counters reset, the gates opened.
+__global__ void k_step_open(unsigned long long* dxbits, int nslots, int* cnt, int* gate) {
+    for (int i = threadIdx.x; i < nslots; i += blockDim.x) dxbits[i] = 0ull;
+    if (threadIdx.x == 0) {
+        cnt[CNT_STEP_FAIL] = 0;
+        cnt[CNT_INNER_DONE] = 0;
+        cnt[CNT_OUTER_DONE] = 0;
+        gate[0] = 0;
+        gate[1] = 0;
+    }
+}
+
+// Loop conditions of Algorithm 1 (tolerance mode), evaluated on the device
+// before an inner iteration: the outer loop stops once the change of x over
+// the previous outer block is below tol_out (prev_outer: that block's norm
+// slot, -1 for the first block); the inner loop stops once the previous
+// iteration's max |x^{k+1} - x^k| is below tol_in (prev_inner: its slot, -1
+// for the first iteration of a block).  gate[1] = skip the block (set at its
+// first iteration), gate[0] = skip this iteration.  block = 0 (residual
+// forwarding): only the inner condition applies and nothing is counted.
+__global__ void k_gate(int* gate, const unsigned long long* __restrict__ dxbits, int prev_inner, double tol_in,
+                       int prev_outer, double tol_out, int block, int* cnt) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (block && prev_inner < 0) {
+        const int stop = prev_outer >= 0 && tol_out > 0 && bits_to_double(dxbits[prev_outer]) < tol_out;
+        gate[1] = stop;
+        if (!stop) cnt[CNT_OUTER_DONE] += 1;
+    }
+    const int skip = (block && gate[1]) ||
+                     (prev_inner >= 0 && tol_in > 0 && bits_to_double(dxbits[prev_inner]) < tol_in);
+    gate[0] = skip;
+    if (block && !skip) cnt[CNT_INNER_DONE] += 1;
 }
 
 __global__ void k_copy3(float* __restrict__ dst, const float* __restrict__ src, int n3) {
@@ -194,29 +279,72 @@ __global__ void k_rf_finish(Dev d, const float* __restrict__ xrf, const float* _
                             const unsigned long long* __restrict__ t_last_bits, double rf_toi) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 3 * d.nv) return;
+    if (*d.fail) return;   // a failed step keeps the residual it started from
     double t = __longlong_as_double((long long)t_last_bits[0]);
     int v = i % d.nv;
     rfdx[i] = (t < rf_toi && !d.pinned[v]) ? xrf[i] - x[i] : 0.0f;
 }
 
 // x = x- + s (x+ - x-), x- <- x (the step-length filter, section 7).
-__global__ void k_filter(int nv, const float* __restrict__ xm, const float* __restrict__ xp,
-                         const double* __restrict__ s_dev, float* __restrict__ x,
-                         float* __restrict__ xm_out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 3 * nv) return;
-    float s = (float)s_dev[0];
-    float a = xm[i];
-    float r = (s == 1.0f) ? xp[i] : a + s * (xp[i] - a);
-    x[i] = r;
-    xm_out[i] = r;
+// dxo (if set): max over vertices of |x - x-|, the change of x over the
+// outer block (the outer loop condition of Algorithm 1), FP64.
+__global__ void __launch_bounds__(TPB) k_filter(const int* __restrict__ gate, int nv, const float* __restrict__ xm,
+                                                const float* __restrict__ xp, const double* __restrict__ s_dev,
+                                                float* __restrict__ x, float* __restrict__ xm_out,
+                                                unsigned long long* dxo) {
+    if (gated(gate)) return;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    double s2 = 0.0;
+    if (v < nv) {
+        const float s = (float)s_dev[0];
+        for (int c = 0; c < 3; ++c) {
+            const int i = c * nv + v;
+            const float a = xm[i];
+            const float r = (s == 1.0f) ? xp[i] : a + s * (xp[i] - a);
+            x[i] = r;
+            xm_out[i] = r;
+            const double dd = (double)r - (double)a;
+            s2 += dd * dd;
+        }
+    }
+    if (dxo) block_max_to(sqrt(s2), dxo);
 }
 
-// v = (x - x*) / h
-__global__ void k_epilogue(Dev d, float inv_h) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// End of an outer block without contact: x = x^k, and the change of x over
+// the block (max over vertices, FP64) into dxo.
+__global__ void __launch_bounds__(TPB) k_block_end(const int* __restrict__ gate, int nv, const float* __restrict__ xk,
+                                                   float* __restrict__ x, unsigned long long* dxo) {
+    if (gated(gate)) return;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    double s2 = 0.0;
+    if (v < nv) {
+        for (int c = 0; c < 3; ++c) {
+            const int i = c * nv + v;
+            const float r = xk[i];
+            const double dd = (double)r - (double)x[i];
+            x[i] = r;
+            s2 += dd * dd;
+        }
+    }
+    block_max_to(sqrt(s2), dxo);
+}
+
+// v = (x - x*) / h.  A step whose status bits are set (a capacity overflow
+// in a contact stage, a non-finite iterate, a tangle) is rolled back: x
+// returns to x*, v keeps its value.  The step's status is published for the
+// host (last step, and OR-ed into the record kept until the next stats read).
+__global__ void k_epilogue(Dev d, float inv_h, int* cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = cnt[CNT_STEP_FAIL];
+    if (i == 0) {
+        cnt[CNT_LAST_STATUS] = f;
+        atomicOr(&cnt[CNT_STICKY], f);
+    }
     if (i >= 3 * d.nv) return;
-    d.v[i] = (d.x[i] - d.xstar[i]) * inv_h;
+    if (f)
+        d.x[i] = d.xstar[i];
+    else
+        d.v[i] = (d.x[i] - d.xstar[i]) * inv_h;
 }
 
 // Local step, right-hand side b, residual r0 and the block's partial U^T r0.
@@ -230,11 +358,13 @@ template <typename UT>
 __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
     __shared__ float sr[3][TPB];
     __shared__ float red[TPB * 24];
+    if (gated(d.gate)) return;
     const int tid = threadIdx.x;
     const int n = d.nv;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int v = tile * TPB + tid;
     const bool contact = flags & 1, linear = flags & 2, force_k = flags & 4;
+    const bool limited = !(d.smin == 1.0f && d.smax == 1.0f);
     // this thread's share of the block's U rows for U^T r0 (column group cg
     // of 8, vertices vg, vg + nvg, ...): the first PF rows are requested
     // now, so that they stream in while the local step runs
@@ -300,7 +430,10 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
                         F[2 * q] = e1[q] * tr.gj0 + e2[q] * tr.gk0;
                         F[2 * q + 1] = e1[q] * tr.gj1 + e2[q] * tr.gk1;
                     }
-                    polar32(F, T);
+                    if (limited)
+                        strain_limit32(F, d.smin, d.smax, T);
+                    else
+                        polar32(F, T);
                     float g0, g1;
                     if (c == 0) {
                         g0 = -tr.gj0 - tr.gk0;
@@ -445,7 +578,9 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
 
 // First reduction level: block s sums partial rows [s*SEG, (s+1)*SEG) in FP64.
 constexpr int SEG = 32;
-__global__ void k_reduce_g1(const float* __restrict__ gpart, int nblk, int m, double* __restrict__ out) {
+__global__ void k_reduce_g1(const int* __restrict__ gate, const float* __restrict__ gpart, int nblk, int m,
+                            double* __restrict__ out) {
+    if (gated(gate)) return;
     int s = blockIdx.x;
     int b0 = s * SEG, b1 = min(nblk, b0 + SEG);
     for (int o = threadIdx.x; o < m; o += blockDim.x) {
@@ -462,6 +597,7 @@ __global__ void k_reduce_g1(const float* __restrict__ gpart, int nblk, int m, do
 // right-hand sides reduced across the wavefront.
 __global__ void __launch_bounds__(1024) k_solve_reduced(Dev d, const double* __restrict__ g1, int nseg, int solve) {
     extern __shared__ double gs[];
+    if (gated(d.gate)) return;
     const int r = d.r, m = r * 3;
     for (int o = threadIdx.x; o < m; o += blockDim.x) {
         double acc = 0.0;
@@ -507,6 +643,7 @@ __global__ void __launch_bounds__(1024) k_solve_reduced(Dev d, const double* __r
 template <typename UT>
 __global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
     __shared__ float res[3][TPB];
+    if (gated(d.gate)) return;
     const int r = d.r, ncg = r >> 3;
     int G = 1;
     while (G < ncg) G <<= 1;               // r <= 256: G <= 32
@@ -573,12 +710,20 @@ __global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
 //   x^ - x^k = delta + r1 / (diag H + W) = (r0 - offdiag(H) delta) / (diag H + W),
 //   x^{k+1} = x^{k-1} + omega (gamma (x^ - x^k) + x^k - x^{k-1}).
 // d.b holds r0 and d.d4 holds delta = U q; x^{k+1} is written SoA to d.xk1
-// and AoS to d.x4 (the next local step's gathers).
+// and AoS to d.x4 (the next local step's gathers).  A non-finite change
+// flags the step as diverged.  Gated (a converged loop): x^{k+1} = x^k and
+// the slot repeats the previous iteration's norm (dx_prev).
 __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float gamma, int has_contact,
-                                                    unsigned long long* dx_slot) {
-    __shared__ double wmax[TPB / 64];
+                                                    unsigned long long* dx_slot,
+                                                    const unsigned long long* __restrict__ dx_prev) {
     const int n = d.nv;
     const int v = xcd_tile(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    if (gated(d.gate)) {
+        if (v < n)
+            for (int c = 0; c < 3; ++c) d.xk1[c * n + v] = d.xk[c * n + v];
+        if (blockIdx.x == 0 && threadIdx.x == 0 && dx_prev) *dx_slot = *dx_prev;
+        return;
+    }
     double dxm = 0.0;
     if (v < n) {
         const float4* DL = d.d4;
@@ -612,15 +757,9 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
         }
         d.x4[v] = make_float4(nx[0], nx[1], nx[2], 0.f);   // gather copy for the next local step
         dxm = sqrt(s2);
+        if (!(dxm <= 1.0e300) && d.fail) atomicOr(d.fail, STEP_DIVERGED);
     }
-    dxm = warp_max(dxm);
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = dxm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = wmax[0];
-        for (int i = 1; i < TPB / 64; ++i) m = fmax(m, wmax[i]);
-        atomicMax(dx_slot, (unsigned long long)__double_as_longlong(m));
-    }
+    block_max_to(dxm, dx_slot);
 }
 
 // ------------------------------------------------------------ launchers
@@ -677,14 +816,32 @@ hipError_t launch_rf_finish(const Dev& d, const float* xrf, const float* x, floa
 }
 
 hipError_t launch_filter(const Dev& d, const float* xm, const float* xp, const double* s_dev, float* x,
-                         float* xm_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_filter, dim3(blocks_for(3 * d.nv)), dim3(TPB), 0, st, d.nv, xm, xp, s_dev, x,
-                       xm_out);
+                         float* xm_out, unsigned long long* dxo, hipStream_t st) {
+    hipLaunchKernelGGL(k_filter, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d.gate, d.nv, xm, xp, s_dev, x,
+                       xm_out, dxo);
     return hipGetLastError();
 }
 
-hipError_t launch_epilogue(const Dev& d, float inv_h, hipStream_t st) {
-    hipLaunchKernelGGL(k_epilogue, dim3(blocks_for(3 * d.nv)), dim3(TPB), 0, st, d, inv_h);
+hipError_t launch_block_end(const Dev& d, unsigned long long* dxo, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_end, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d.gate, d.nv, (const float*)d.xk, d.x,
+                       dxo);
+    return hipGetLastError();
+}
+
+hipError_t launch_epilogue(const Dev& d, float inv_h, int* cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_epilogue, dim3(blocks_for(3 * d.nv)), dim3(TPB), 0, st, d, inv_h, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_open(unsigned long long* dxbits, int nslots, int* cnt, int* gate, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_open, dim3(1), dim3(256), 0, st, dxbits, nslots, cnt, gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate(int* gate, const unsigned long long* dxbits, int prev_inner, double tol_in, int prev_outer,
+                       double tol_out, int block, int* cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, st, gate, dxbits, prev_inner, tol_in, prev_outer, tol_out, block,
+                       cnt);
     return hipGetLastError();
 }
 
@@ -699,7 +856,7 @@ hipError_t launch_local_residual(const Dev& d, int prec, int flags, hipStream_t 
 hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpart2, hipStream_t st) {
     const int m = d.r * 3;
     int nseg = (nblk + SEG - 1) / SEG;
-    hipLaunchKernelGGL(k_reduce_g1, dim3(nseg), dim3(256), 0, st, d.gpart, nblk, m, gpart2);
+    hipLaunchKernelGGL(k_reduce_g1, dim3(nseg), dim3(256), 0, st, d.gate, (const float*)d.gpart, nblk, m, gpart2);
     hipLaunchKernelGGL(k_solve_reduced, dim3(1), dim3(1024), sizeof(double) * m, st, d,
                        (const double*)gpart2, nseg, contact ? 0 : 1);
     return hipGetLastError();
@@ -714,8 +871,9 @@ hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st) {
 }
 
 hipError_t launch_jacobi_cheb(const Dev& d, float omega, float gamma, int has_contact,
-                              unsigned long long* dx_slot, hipStream_t st) {
-    launch_timed(k_jacobi_cheb, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, omega, gamma, has_contact, dx_slot);
+                              unsigned long long* dx_slot, const unsigned long long* dx_prev, hipStream_t st) {
+    launch_timed(k_jacobi_cheb, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, omega, gamma, has_contact, dx_slot,
+                 dx_prev);
     return hipGetLastError();
 }
 

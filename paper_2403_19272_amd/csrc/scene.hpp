@@ -17,6 +17,20 @@ constexpr double NO_HIT = 2.0;
 constexpr int MAX_R = 192;        // widest basis: the packed FP64 Cholesky factor lives in LDS
 constexpr int GRAM_CHUNKS = 512;  // contact-vertex chunks of the Gram partials
 constexpr int GRAM_GROUPS_MAX = 16;  // chunk groups of the first FP64 reduction level
+constexpr int RF_MAX = 64;        // residual-forwarding iterations per step at most
+constexpr int CHEB_EST_SLOTS = 201;  // per-iteration norms of the Chebyshev estimate
+
+// Step status bits (device word, 0 = the step succeeded).  The first four
+// are the capacity overflows of the contact stages; a step that sets any of
+// them, or a non-finite iterate, is rolled back to its starting state.
+constexpr int STEP_OVF_QUERY = 1, STEP_OVF_CELL = 2, STEP_OVF_LIST = 4, STEP_OVF_CONS = 8;
+constexpr int STEP_DIVERGED = 16;
+constexpr int STEP_TANGLED = 32;
+// device counter words (ContactState::cnt): overflow bits of the running
+// step, failure bits since the last stats read, the last step's status, and
+// the inner iterations and outer blocks the last step executed
+constexpr int CNT_STEP_FAIL = 7, CNT_STICKY = 13, CNT_LAST_STATUS = 14, CNT_INNER_DONE = 15,
+              CNT_OUTER_DONE = 16, CNT_TANGLES = 17;
 
 // LDS of the contact solve (factor and triangular solves in one workgroup):
 // packed lower triangle, r inverse pivots and one zero entry
@@ -79,6 +93,12 @@ struct Dev {
     int nob;
     float kc, Kb;             // initial weight k and growth base K of Eq. (exp)
     double dhat;
+    float smin, smax;         // strain limits of the projection (1, 1: rotation)
+    // Tolerance mode: while `gate` is set and *gate != 0 the kernel returns
+    // at once (the Jacobi sweep copies x^k forward instead), so a converged
+    // loop runs its remaining launches of the fixed step graph as no-ops.
+    const int* gate;
+    int* fail;                // step status bits (non-finite iterates are flagged here)
 };
 
 struct Scene {
@@ -89,6 +109,9 @@ struct Scene {
     int amax = 20;
     int iters_in = 10, iters_out = 1, delay = 3, prec = CLOTH_PLAIN_FP32, self_contact = 0;
     double rho = 0, gamma = 0;
+    double tol_in = 0, tol_out = 0;   // Algorithm 1 loop tolerances (<= 0: fixed budgets)
+    double smin = 1, smax = 1;        // strain limits
+    int debug_tangles = 0;            // check the end state of every step for intersecting triangles
     int64_t pair_cap = 0;
     bool basis_set = false;
     bool x4_valid = false;        // d.x4 holds x^k (written by the Jacobi sweep)
@@ -116,6 +139,8 @@ struct Scene {
     int nblk = 0;                 // vertex blocks
     uint8_t* d_pinned = nullptr;
     float* d_rfdx = nullptr;      // forwarded residual dx (3*nv)
+    int* d_gate = nullptr;        // [0] skip this inner iteration, [1] skip this outer block
+    int nslots_cap = 0;           // entries of d.dxbits (norm slots)
     int *d_rowptr = nullptr, *d_col = nullptr, *d_inc_ptr = nullptr, *d_inc = nullptr,
         *d_edges = nullptr;
     float* d_val = nullptr;

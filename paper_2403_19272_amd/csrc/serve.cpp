@@ -129,6 +129,7 @@ struct cloth_server_s {
     struct Slot {
         hipStream_t stream = nullptr;
         hipEvent_t start = nullptr, end = nullptr;
+        int* status = nullptr;   // pinned host word: the step's status bits, copied after its graph
         bool busy = false;
         Req req{};
     };
@@ -171,6 +172,11 @@ void cloth_server_s::run() {
             float ms = 0.f;
             if (q != hipSuccess || hipEventElapsedTime(&ms, sl.start, sl.end) != hipSuccess) {
                 d.status = CLOTH_E_DEVICE;
+            } else if (const int bits = *sl.status) {
+                // the step was rolled back on the device (see cloth_step)
+                d.status = (bits & STEP_DIVERGED) ? CLOTH_E_DIVERGED
+                           : (bits & STEP_TANGLED) ? CLOTH_E_TANGLED
+                                                   : CLOTH_E_CAPACITY;
             }
             d.service_ms = ms;
             busy[sl.req.scene] = false;
@@ -191,6 +197,9 @@ void cloth_server_s::run() {
             if (rc == CLOTH_OK) {
                 e = hipEventRecord(sl.start, sl.stream);
                 if (e == hipSuccess) e = hipGraphLaunch(r.scene->s.graph_exec, sl.stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(sl.status, r.scene->c.cnt + CNT_LAST_STATUS, sizeof(int),
+                                       hipMemcpyDeviceToHost, sl.stream);
                 if (e == hipSuccess) e = hipEventRecord(sl.end, sl.stream);
             }
             if (rc != CLOTH_OK || e != hipSuccess) {
@@ -227,7 +236,8 @@ cloth_status cloth_server_create(int32_t n_slots, size_t hbm_budget, cloth_serve
     sv->slots.resize(n_slots);
     for (auto& sl : sv->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreate(&sl.start) != hipSuccess || hipEventCreate(&sl.end) != hipSuccess) {
+            hipEventCreate(&sl.start) != hipSuccess || hipEventCreate(&sl.end) != hipSuccess ||
+            hipHostMalloc((void**)&sl.status, sizeof(int), hipHostMallocDefault) != hipSuccess) {
             delete sv;
             return set_error(CLOTH_E_DEVICE, "stream/event creation");
         }
@@ -327,6 +337,7 @@ cloth_status cloth_server_destroy(cloth_server sv) {
         if (sl.start) (void)hipEventDestroy(sl.start);
         if (sl.end) (void)hipEventDestroy(sl.end);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.status) (void)hipHostFree(sl.status);
     }
     delete sv;
     return CLOTH_OK;

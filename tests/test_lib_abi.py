@@ -32,10 +32,41 @@ def test_status_strings_and_footprint_on_host():
     sc = scenegen.config(0)
     tris = np.ascontiguousarray(sc.tris, np.int32)
     mesh = P.Mesh(sc.nv, sc.nt, tris.ctypes.data, None)
-    prm = P.SolverParams(16, 20, 1, 0.9, 0.9, 3, 0, 0, 0)
+    prm = P.SolverParams(r=16, iters_inner=20, iters_outer=1, cheb_rho=0.9, cheb_gamma=0.9, cheb_delay=3)
     n = ctypes.c_size_t(0)
     assert P.lib.cloth_query_footprint(ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(n)) == 0
     assert n.value > sc.nv * 100
     bad = np.array([[0, 1, 99999]], np.int32)
     mesh2 = P.Mesh(3, 1, bad.ctypes.data, None)
     assert P.lib.cloth_query_footprint(ctypes.byref(mesh2), ctypes.byref(prm), ctypes.byref(n)) == P.CLOTH_E_MESH
+
+
+def test_init_rejects_bad_budgets_tolerances_and_strain_limits_on_host():
+    """Argument checks that run before any device call: a per-step budget
+    beyond the norm slots, non-finite tolerances, strain limits outside
+    0 < sigma_min <= 1 <= sigma_max, and too many forwarding iterations."""
+    import paper_2403_19272_amd as P
+    import scenegen
+    sc = scenegen.config(0)
+    tris = np.ascontiguousarray(sc.tris, np.int32)
+    rest = np.ascontiguousarray(sc.rest, np.float32)
+    mesh = P.Mesh(sc.nv, sc.nt, tris.ctypes.data, None)
+    out = ctypes.c_void_p()
+
+    def init(mat, prm):
+        return P.lib.cloth_init(ctypes.byref(mesh), rest.ctypes.data, ctypes.byref(mat), sc.dt, ctypes.byref(prm),
+                                None, 0, ctypes.byref(out))
+
+    good = P.Material(density=0.3, k_stretch=160.0, k_bend=3e-4, sigma_min=1.0, sigma_max=1.0, a_max=20,
+                      d_hat=1e-3, alpha=0.8)
+    big = P.SolverParams(r=16, iters_inner=4096, iters_outer=17, cheb_delay=3)
+    assert init(good, big) == P.CLOTH_E_INVALID
+    assert "65536" in P.lib.cloth_last_error().decode()
+    nan_tol = P.SolverParams(r=16, iters_inner=20, iters_outer=1, tol_inner=float("nan"), cheb_delay=3)
+    assert init(good, nan_tol) == P.CLOTH_E_INVALID
+    ok = P.SolverParams(r=16, iters_inner=20, iters_outer=1, cheb_delay=3)
+    for smin, smax in ((1.2, 1.5), (0.9, 0.95), (-0.1, 1.1), (0.9, float("inf"))):
+        bad = P.Material(density=0.3, k_stretch=160.0, k_bend=3e-4, sigma_min=smin, sigma_max=smax, a_max=20,
+                         d_hat=1e-3, alpha=0.8)
+        assert init(bad, ok) == P.CLOTH_E_INVALID, (smin, smax)
+        assert "strain limits" in P.lib.cloth_last_error().decode()
