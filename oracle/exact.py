@@ -1,13 +1,25 @@
-"""Exact triangle-triangle intersection decisions with rational arithmetic,
+"""Exact triangle-triangle intersection decisions with integer arithmetic,
 for the pairs whose FP64 orientation signs the C filter could not certify
-(TEST INFRASTRUCTURE ONLY)."""
-from __future__ import annotations
+(TEST INFRASTRUCTURE ONLY).
 
-from fractions import Fraction
+Every FP32 value is an integer multiple of 2^-149, so scaling all
+coordinates by 2^149 turns them into Python integers exactly; the predicates
+below only add, subtract, multiply and compare, and a common positive scale
+leaves every sign they test unchanged."""
+from __future__ import annotations
 
 import numpy as np
 
 from . import native
+
+_FP32_SCALE_EXP = 149
+
+
+def _exact_int(v) -> int:
+    """The FP32 value v times 2^149, exactly."""
+    num, den = float(np.float32(v)).as_integer_ratio()
+    shift = _FP32_SCALE_EXP - (den.bit_length() - 1)
+    return num << shift
 
 
 def _orient(a, b, c, d) -> int:
@@ -125,8 +137,8 @@ def _degenerate(T) -> bool:
 
 
 def tri_tri_exact(A, B) -> bool:
-    A = [[Fraction(float(v)) for v in row] for row in A]
-    B = [[Fraction(float(v)) for v in row] for row in B]
+    A = [[_exact_int(v) for v in row] for row in A]
+    B = [[_exact_int(v) for v in row] for row in B]
     for k in range(3):
         if max(r[k] for r in A) < min(r[k] for r in B) or max(r[k] for r in B) < min(r[k] for r in A):
             return False

@@ -621,8 +621,12 @@ void og_frozen_ee(const double* xm, const int* edges, long n, const int* ee, dou
 /* ------------------------------------------------------------ tangles */
 
 /* Sign of orient3d(a,b,c,d) = (b-a) x (c-a) . (d-a) with a static error
- * filter; returns +1/-1, or 0 when the FP64 value cannot be trusted (the
- * caller then decides exactly). */
+ * filter (the bound is a multiple of the evaluation's rounding-error bound);
+ * returns +1/-1, 0 when every product of the expansion is exactly zero (the
+ * FP32 inputs make their differences and a zero product exact, so the
+ * determinant is exactly zero), or ORIENT_UNSURE when the FP64 value cannot
+ * be trusted (the caller then decides exactly). */
+#define ORIENT_UNSURE 2
 static int orient_f(v3 a, v3 b, v3 c, v3 d) {
     v3 ab = sub(b, a), ac = sub(c, a), ad = sub(d, a);
     double det = ab.x * (ac.y * ad.z - ac.z * ad.y) - ab.y * (ac.x * ad.z - ac.z * ad.x) +
@@ -630,21 +634,32 @@ static int orient_f(v3 a, v3 b, v3 c, v3 d) {
     double perm = fabs(ab.x) * (fabs(ac.y * ad.z) + fabs(ac.z * ad.y)) +
                   fabs(ab.y) * (fabs(ac.x * ad.z) + fabs(ac.z * ad.x)) +
                   fabs(ab.z) * (fabs(ac.x * ad.y) + fabs(ac.y * ad.x));
+    if (perm == 0.0) return 0;
     double eb = 1e-12 * perm;
     if (det > eb) return 1;
     if (det < -eb) return -1;
-    return 0;
+    return ORIENT_UNSURE;
 }
 
 /* Segment pq against triangle abc (closed), using filtered orientations.
- * Returns 1 = intersect, 0 = disjoint, -1 = undecided in FP64. */
+ * Returns 1 = intersect, 0 = disjoint, -1 = undecided in FP64.  With the
+ * endpoints strictly on both sides of the triangle's plane, the segment
+ * meets the closed triangle iff the three edge orientations seen from pq
+ * agree where they are not zero (a zero puts the crossing on that edge's
+ * line). */
 static int seg_tri(v3 p, v3 q, v3 a, v3 b, v3 c) {
     int s1 = orient_f(a, b, c, p), s2 = orient_f(a, b, c, q);
-    if (s1 == 0 || s2 == 0) return -1;
+    if (s1 == ORIENT_UNSURE || s2 == ORIENT_UNSURE || s1 == 0 || s2 == 0) return -1;
     if (s1 == s2) return 0;
-    int o1 = orient_f(p, q, a, b), o2 = orient_f(p, q, b, c), o3 = orient_f(p, q, c, a);
-    if (o1 == 0 || o2 == 0 || o3 == 0) return -1;
-    return (o1 == o2 && o2 == o3) ? 1 : 0;
+    int o[3] = {orient_f(p, q, a, b), orient_f(p, q, b, c), orient_f(p, q, c, a)};
+    int sign = 0;
+    for (int i = 0; i < 3; ++i) {
+        if (o[i] == ORIENT_UNSURE) return -1;
+        if (o[i] == 0) continue;
+        if (sign != 0 && o[i] != sign) return 0;
+        sign = o[i];
+    }
+    return 1;
 }
 
 /* Count intersecting pairs of vertex-disjoint triangles at positions x

@@ -2159,7 +2159,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     auto I = [&](size_t k) { return static_cast<int*>(carve(sizeof(int) * k)); };
     c.gpart2 = static_cast<double*>(carve(sizeof(double) * ((size_t)(s.nblk + 31) / 32 + 1) * s.r * 3));
     c.gvec = static_cast<double*>(carve(sizeof(double) * s.r * 3));
-    c.cnt = I(32);
+    c.cnt = I(CNT_WORDS);
     c.tmin_bits = static_cast<unsigned long long*>(carve(32));
     c.tpart = static_cast<double*>(carve(sizeof(double) * 2 * GRID_LOOP));
     c.s_dev = static_cast<double*>(carve(8));
@@ -2235,7 +2235,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
 
 cloth_status contact_upload(Scene& s, ContactState& c) {
     const int n = s.nv;
-    HC(hipMemset(c.cnt, 0, sizeof(int) * 32));
+    HC(hipMemset(c.cnt, 0, sizeof(int) * CNT_WORDS));
     HC(hipMemset(c.ob_a, 0xff, sizeof(int) * (size_t)MAX_OBST * n));
     std::vector<unsigned long long> tb(4, 0x4000000000000000ull);  // 2.0
     HC(hipMemcpy(c.tmin_bits, tb.data(), 32, hipMemcpyHostToDevice));

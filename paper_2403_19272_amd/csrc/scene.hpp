@@ -26,11 +26,17 @@ constexpr int CHEB_EST_SLOTS = 201;  // per-iteration norms of the Chebyshev est
 constexpr int STEP_OVF_QUERY = 1, STEP_OVF_CELL = 2, STEP_OVF_LIST = 4, STEP_OVF_CONS = 8;
 constexpr int STEP_DIVERGED = 16;
 constexpr int STEP_TANGLED = 32;
-// device counter words (ContactState::cnt): overflow bits of the running
-// step, failure bits since the last stats read, the last step's status, and
-// the inner iterations and outer blocks the last step executed
+// Device counter words (ContactState::cnt, 32 ints).  The contact stages
+// use [0..6], [9], [10], [12] (list counts), [16..24] (the time-of-impact
+// chunk scheduler) and [25..26] (the heavy-query rescan); these are the
+// step's: overflow bits of the running step, failure bits since the last
+// stats read, the last step's status, the inner iterations and outer blocks
+// the last step executed, and the tangle check's crossing and undecided
+// counts ([28], [29]).
 constexpr int CNT_STEP_FAIL = 7, CNT_STICKY = 13, CNT_LAST_STATUS = 14, CNT_INNER_DONE = 15,
-              CNT_OUTER_DONE = 16, CNT_TANGLES = 17;
+              CNT_OUTER_DONE = 27, CNT_TANGLES = 28;
+constexpr int CNT_WORDS = 32;
+static_assert(CNT_TANGLES + 1 < CNT_WORDS, "counter words");
 
 // LDS of the contact solve (factor and triangular solves in one workgroup):
 // packed lower triangle, r inverse pivots and one zero entry

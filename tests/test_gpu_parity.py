@@ -101,9 +101,10 @@ def contact_block(n=20, seed=3, precision="fp32", step=0.1):
     vt, ee = native.broad_phase(xm, xp, o.m.edges, o.m.tris, sc.d_hat)
     vt = vt[rng.random(len(vt)) < 0.3]
     ee = ee[rng.random(len(ee)) < 0.3]
-    a_vt = rng.integers(0, 6, len(vt)).astype(np.int32)
-    a_ee = rng.integers(0, 6, len(ee)).astype(np.int32)
-    ob_a = np.where(rng.random(sc.nv) < 0.3, rng.integers(0, 6, sc.nv), -1).astype(np.int32)[None]
+    # life spans over the whole range 0..a_max (weights up to k 2^20)
+    a_vt = rng.integers(0, 21, len(vt)).astype(np.int32)
+    a_ee = rng.integers(0, 21, len(ee)).astype(np.int32)
+    ob_a = np.where(rng.random(sc.nv) < 0.3, rng.integers(0, 21, sc.nv), -1).astype(np.int32)[None]
     ob_a[0, sc.pinned.astype(bool)] = -1
     xk = (xm + rng.normal(0, 0.05 / n, xm.shape)).astype(np.float32)
     xkm1 = (xk + rng.normal(0, 0.02 / n, xm.shape)).astype(np.float32)
@@ -283,8 +284,8 @@ def test_full_size_inner_iteration():
     vt = vt[rng.random(len(vt)) < 0.05]
     ee = ee[rng.random(len(ee)) < 0.05]
     blk = dict(xm=xm, xk=(xm + rng.normal(0, 1e-4, xm.shape)).astype(np.float32), vt=vt, ee=ee,
-               a_vt=rng.integers(0, 6, len(vt)).astype(np.int32), a_ee=rng.integers(0, 6, len(ee)).astype(np.int32),
-               ob_a=np.where(rng.random(sc.nv) < 0.1, rng.integers(0, 6, sc.nv), -1).astype(np.int32)[None])
+               a_vt=rng.integers(0, 21, len(vt)).astype(np.int32), a_ee=rng.integers(0, 21, len(ee)).astype(np.int32),
+               ob_a=np.where(rng.random(sc.nv) < 0.1, rng.integers(0, 21, sc.nv), -1).astype(np.int32)[None])
     blk["xkm1"] = (blk["xk"] + rng.normal(0, 5e-5, xm.shape)).astype(np.float32)
     blk["z"] = (blk["xk"] + rng.normal(0, 2e-4, xm.shape)).astype(np.float32)
     g = gpu_side(sc, U, "mixed", rho, gamma=0.5)

@@ -641,3 +641,43 @@ def test_spectral_radius_against_dense_spectrum(gamma):
     # radius is the one of the low modes, much closer to 1
     ev0 = np.abs(np.linalg.eigvals(J[np.ix_(f, f)])).max()
     assert ev0 > want + 1e-3
+
+
+# ------------------------------------------------- exact tangle arithmetic
+
+def test_exact_integer_scaling_preserves_orientation_signs():
+    """The exact tangle check scales FP32 coordinates to integers by 2^149:
+    every orientation sign equals the one of the rational determinant, also
+    for tiny, subnormal and exactly coplanar inputs."""
+    from fractions import Fraction
+
+    from oracle import exact
+    rng = np.random.default_rng(41)
+
+    def frac_orient(a, b, c, d):
+        ab = [b[i] - a[i] for i in range(3)]
+        ac = [c[i] - a[i] for i in range(3)]
+        ad = [d[i] - a[i] for i in range(3)]
+        det = (ab[0] * (ac[1] * ad[2] - ac[2] * ad[1]) - ab[1] * (ac[0] * ad[2] - ac[2] * ad[0])
+               + ab[2] * (ac[0] * ad[1] - ac[1] * ad[0]))
+        return (det > 0) - (det < 0)
+
+    cases = []
+    for _ in range(300):
+        P = rng.standard_normal((4, 3)).astype(np.float32)
+        cases.append(P)
+        Q = P.copy()
+        Q[3] = (Q[0] + np.float32(0.5) * (Q[1] - Q[0])).astype(np.float32)   # near the line / plane
+        cases.append(Q)
+        cases.append((P * np.float32(1e-38)).astype(np.float32))            # subnormal range
+        R = P.copy()
+        R[:, 2] = np.float32(0.25)                                           # exactly coplanar
+        cases.append(R)
+    zeros = 0
+    for P in cases:
+        F = [[Fraction(float(v)) for v in row] for row in P]
+        I = [[exact._exact_int(v) for v in row] for row in P]
+        want = frac_orient(*F)
+        assert exact._orient(*I) == want
+        zeros += want == 0
+    assert zeros >= 300
