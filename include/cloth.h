@@ -191,6 +191,23 @@ cloth_status cloth_compute_basis(cloth_scene s, int32_t r, int32_t degree, int32
                                  double tol, double* U, double* ritz, int32_t* passes,
                                  double* residual);
 
+/* As cloth_compute_basis, but allocating no device memory, for callers that
+ * cannot allocate (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc).  The iteration's workspace is a fixed array of
+ * 64 MiB that the library holds on each GPU it runs on until the process
+ * ends; a call needs 4 * nv * m * 4 + m * m * 4 + c * m * m * 8 bytes of it
+ * (m = r + max(8, r/4) rounded up to a multiple of 4, c = min(64,
+ * max(1, nv / 4096)); nv = 16,384 at r = 32 takes 10.5 MB), and a scene that
+ * needs more is refused with CLOTH_E_INVALID before any work.  Call it with
+ * the scene's device current.  Every call on one GPU uses that GPU's one
+ * array: calls that overlap on one GPU (from several host threads) race, and
+ * the caller must serialise them.  Nothing in the array needs to start
+ * cleared; it keeps the last call's contents.  Results are those of
+ * cloth_compute_basis on the same scene. */
+cloth_status cloth_compute_basis_static(cloth_scene s, int32_t r, int32_t degree, int32_t max_passes,
+                                        double tol, double* U, double* ritz, int32_t* passes,
+                                        double* residual);
+
 /* Adds an analytic obstacle (at most 4 per scene); the next step records
  * its graph again. */
 cloth_status cloth_add_obstacle(cloth_scene s, const cloth_obstacle* ob);

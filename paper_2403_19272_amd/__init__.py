@@ -37,7 +37,7 @@ EXPORTS = [
     "cloth_stage_outer", "cloth_stage_read_set", "cloth_step_batch", "cloth_server_create",
     "cloth_server_admit", "cloth_server_release", "cloth_server_submit", "cloth_server_poll",
     "cloth_server_wait", "cloth_server_destroy", "cloth_compute_basis", "cloth_set_step_options",
-    "cloth_get_forwarded",
+    "cloth_get_forwarded", "cloth_compute_basis_static",
 ]
 
 
@@ -115,6 +115,7 @@ def _load():
         "cloth_server_wait": (i32, [P, i64, C.POINTER(f64), C.POINTER(f64)]),
         "cloth_server_destroy": (i32, [P]),
         "cloth_compute_basis": (i32, [P, i32, i32, i32, f64, P, P, C.POINTER(i32), C.POINTER(f64)]),
+        "cloth_compute_basis_static": (i32, [P, i32, i32, i32, f64, P, P, C.POINTER(i32), C.POINTER(f64)]),
         "cloth_set_step_options": (i32, [P, i32, i32, f64]),
         "cloth_get_forwarded": (i32, [P, P]),
         "cloth_kernel_times": (i32, [P, i32, P, P, P, C.POINTER(i32)]),
@@ -210,14 +211,16 @@ class ClothScene:
         U = np.ascontiguousarray(U, np.float64)
         _check(lib.cloth_set_basis(self._h, _ptr(U), U.shape[1]), "cloth_set_basis")
 
-    def compute_basis(self, degree=300, max_passes=12, tol=2e-2, return_basis=False):
-        """Device eigenbasis (Chebyshev-filtered subspace iteration), then set."""
+    def compute_basis(self, degree=300, max_passes=12, tol=2e-2, return_basis=False, static=False):
+        """Device eigenbasis (Chebyshev-filtered subspace iteration), then set.
+        static: use the entry point that allocates no device memory."""
         U = np.empty((self.nv, self.r)) if return_basis else None
         w = np.empty(self.r)
         npass = C.c_int32(0)
         res = C.c_double(0)
-        _check(lib.cloth_compute_basis(self._h, self.r, degree, max_passes, tol, _ptr(U), _ptr(w),
-                                       C.byref(npass), C.byref(res)), "cloth_compute_basis")
+        name = "cloth_compute_basis_static" if static else "cloth_compute_basis"
+        _check(getattr(lib, name)(self._h, self.r, degree, max_passes, tol, _ptr(U), _ptr(w),
+                                  C.byref(npass), C.byref(res)), name)
         return dict(U=U, ritz=w, passes=npass.value, residual=res.value)
 
     def add_obstacle(self, kind, center, radius, axis=(1.0, 0.0, 0.0), half_length=0.0, omega=0.0):

@@ -650,7 +650,34 @@ cloth_status cloth_compute_basis(cloth_scene sc, int32_t r, int32_t degree, int3
     std::string err;
     int p = 0;
     double res = 0;
-    cloth_status rc = device_eigenbasis(s, r, degree, max_passes, tol, Uh, w, &p, &res, err);
+    cloth_status rc = device_eigenbasis(s, r, degree, max_passes, tol, Uh, w, &p, &res, err, nullptr);
+    if (rc != CLOTH_OK) return fail(rc, err);
+    if (U) std::copy(Uh.begin(), Uh.end(), U);
+    if (ritz) std::copy(w.begin(), w.end(), ritz);
+    if (passes) *passes = p;
+    if (residual) *residual = res;
+    return cloth_set_basis(sc, Uh.data(), r);
+}
+
+cloth_status cloth_compute_basis_static(cloth_scene sc, int32_t r, int32_t degree, int32_t max_passes, double tol,
+                                        double* U, double* ritz, int32_t* passes, double* residual) {
+    if (!sc) return fail(CLOTH_E_INVALID, "null argument");
+    Scene& s = sc->s;
+    if (r != s.r) return fail(CLOTH_E_INVALID, "basis width differs from params.r");
+    if (degree < 1 || max_passes < 1) return fail(CLOTH_E_INVALID, "degree and passes must be positive");
+    const size_t need = eig_workspace_bytes(s.nv, r);
+    if (need > EIG_SCRATCH_BYTES)
+        return fail(CLOTH_E_INVALID, "the basis iteration needs " + std::to_string(need) +
+                                         " bytes of workspace; the fixed workspace holds " +
+                                         std::to_string(EIG_SCRATCH_BYTES) + " (use cloth_compute_basis)");
+    std::string err;
+    void* ws = nullptr;
+    cloth_status rc = eig_static_workspace(&ws, err);
+    if (rc != CLOTH_OK) return fail(rc, err);
+    std::vector<double> Uh, w;
+    int p = 0;
+    double res = 0;
+    rc = device_eigenbasis(s, r, degree, max_passes, tol, Uh, w, &p, &res, err, ws);
     if (rc != CLOTH_OK) return fail(rc, err);
     if (U) std::copy(Uh.begin(), Uh.end(), U);
     if (ritz) std::copy(w.begin(), w.end(), ritz);

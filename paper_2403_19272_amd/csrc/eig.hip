@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -216,12 +217,29 @@ void jacobi_eig(std::vector<double> A, int m, std::vector<double>& V, std::vecto
 struct Work {
     float *Y = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z = nullptr, *M = nullptr;
     double* part = nullptr;
+    bool owned = false;  // allocated here (freed on exit) or carved from a workspace
     ~Work() {
+        if (!owned) return;
         for (float* p : {Y, Y0, Y1, Z, M})
             if (p) (void)hipFree(p);
         if (part) (void)hipFree(part);
     }
 };
+
+// Block width and Gram chunk count of the iteration for n rows and r wanted
+// vectors.
+int block_width(int r) { return ((r + std::max(8, r / 4)) + 3) / 4 * 4; }
+int gram_chunks(int n) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 4096)); }
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Workspace of the no-allocation entry point: a fixed array in device
+// memory, one copy per GPU, held until the process ends.  In host code its
+// name is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, taken once per device and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[EIG_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
 
 // Largest filter degree for which the scaled Chebyshev polynomial on [a, b]
 // amplifies the lowest Ritz value theta_0 at most `growth` times more than
@@ -241,19 +259,61 @@ int filter_degree(double theta0, double thetar, double a, double b, int dmax, do
 
 // Computes the basis into U (nv x r FP64, row-major, pinned rows zero) and
 // the Ritz values into w.  Returns CLOTH_OK or an error with text in err.
+size_t eig_workspace_bytes(int n, int r) {
+    const int m = block_width(r), nchunk = gram_chunks(n);
+    return 4 * align256(sizeof(float) * (size_t)n * m) + align256(sizeof(float) * (size_t)m * m) +
+           align256(sizeof(double) * (size_t)nchunk * m * m);
+}
+
+cloth_status eig_static_workspace(void** out, std::string& err) {
+    int dev = -1;
+    HC(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = "device ordinal out of range";
+        return CLOTH_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        HC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            err = "hipGetSymbolAddress returned a null address for the basis workspace";
+            return CLOTH_E_DEVICE;
+        }
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return CLOTH_OK;
+}
+
 cloth_status device_eigenbasis(Scene& s, int r, int degree, int max_passes, double tol, std::vector<double>& U,
-                               std::vector<double>& wout, int* passes_done, double* max_res, std::string& err) {
+                               std::vector<double>& wout, int* passes_done, double* max_res, std::string& err,
+                               void* workspace) {
     const int n = s.nv;
-    const int m = ((r + std::max(8, r / 4)) + 3) / 4 * 4;
-    const int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 4096));
+    const int m = block_width(r);
+    const int nchunk = gram_chunks(n);
     Work w;
     size_t blk = sizeof(float) * (size_t)n * m;
-    HC(hipMalloc(&w.Y, blk));
-    HC(hipMalloc(&w.Y0, blk));
-    HC(hipMalloc(&w.Y1, blk));
-    HC(hipMalloc(&w.Z, blk));
-    HC(hipMalloc(&w.M, sizeof(float) * (size_t)m * m));
-    HC(hipMalloc(&w.part, sizeof(double) * (size_t)nchunk * m * m));
+    if (workspace) {
+        // carve the buffers in eig_workspace_bytes' order; every one is
+        // written before it is read, so nothing needs clearing
+        unsigned char* p = static_cast<unsigned char*>(workspace);
+        for (float** b : {&w.Y, &w.Y0, &w.Y1, &w.Z}) {
+            *b = reinterpret_cast<float*>(p);
+            p += align256(blk);
+        }
+        w.M = reinterpret_cast<float*>(p);
+        p += align256(sizeof(float) * (size_t)m * m);
+        w.part = reinterpret_cast<double*>(p);
+    } else {
+        w.owned = true;
+        HC(hipMalloc(&w.Y, blk));
+        HC(hipMalloc(&w.Y0, blk));
+        HC(hipMalloc(&w.Y1, blk));
+        HC(hipMalloc(&w.Z, blk));
+        HC(hipMalloc(&w.M, sizeof(float) * (size_t)m * m));
+        HC(hipMalloc(&w.part, sizeof(double) * (size_t)nchunk * m * m));
+    }
     const int* rp = s.d.rowptr;
     const int* col = s.d.col;
     const float* val = s.d.val;

@@ -186,8 +186,16 @@ static const char* const kKernelNames[K_COUNT] = {
 // host precompute (host_build.cpp)
 std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, double dt,
                         const cloth_material* mat, const cloth_solver_params* prm);
-// device eigenbasis (eig.hip)
+// device eigenbasis (eig.hip).  workspace: device memory of at least
+// eig_workspace_bytes(nv, r) bytes, or null to allocate (and free) it here.
 cloth_status device_eigenbasis(Scene& s, int r, int degree, int max_passes, double tol, std::vector<double>& U,
-                               std::vector<double>& w, int* passes, double* max_res, std::string& err);
+                               std::vector<double>& w, int* passes, double* max_res, std::string& err,
+                               void* workspace);
+// Bytes of workspace the device eigenbasis needs, and the size of the
+// library's fixed per-GPU workspace array (eig_static_workspace).
+constexpr size_t EIG_SCRATCH_BYTES = size_t(64) << 20;
+size_t eig_workspace_bytes(int nv, int r);
+// Device address of the current GPU's fixed workspace (EIG_SCRATCH_BYTES).
+cloth_status eig_static_workspace(void** out, std::string& err);
 
 }  // namespace cloth
