@@ -78,8 +78,11 @@ def tolerance_run(sc, precision, steps, budget_in, budget_out, cand_in, cand_out
               flush=True)
         assert sg["inner_iters"] == so.inner_iters and sg["outer_iters"] == so.outer_iters
         assert err <= 1e-5
-        assert abs(sg["dx_norm"] - so.dx[-1]) <= 0.02 * so.dx[-1]
-        assert abs(sg["outer_dx"] - so.outer_dx[-1]) <= 0.02 * so.outer_dx[-1]
+        # the device norms are differences of FP32 positions: beside the 2 %
+        # relative bound, each may be off by a few roundings of a coordinate
+        ulp = 4 * float(np.spacing(np.float32(np.abs(o.x).max())))
+        assert abs(sg["dx_norm"] - so.dx[-1]) <= 0.02 * so.dx[-1] + ulp
+        assert abs(sg["outer_dx"] - so.outer_dx[-1]) <= 0.02 * so.outer_dx[-1] + ulp
     return g
 
 

@@ -4,14 +4,15 @@ leave out (MI355X only):
   * the sampled TOI fallback: a cloth moving in its own plane makes every
     coplanarity cubic vanish identically, so every pair takes the sampled
     fallback, more per chunk than the wavefront queue holds;
-  * the outer stage at full size (600 x 600) from a state past first
-    contact, with a carried constraint set: sets and spans bit-exact, step
-    length within 1e-6;
+  * the outer stage at full size (600 x 600) from a state lying on the
+    cylinder, with jittered end positions so that self-contact pairs arise,
+    and a carried constraint set: sets and spans bit-exact, step length
+    within 1e-6;
   * the sphere drape (256 x 256): per-stage parity at a shared mid-run state
     and no intersecting triangles after any step;
   * the cylinder drape (600 x 600) from the 0.3 m drop through its
-    heavy-contact steps: no intersecting triangles (exact check every 10th
-    step and the last, the device check after every step).
+    contact steps: no intersecting triangles (exact check every 10th step
+    and the last, the device check after every step).
 """
 import numpy as np
 import pytest
@@ -103,11 +104,14 @@ def test_full_size_outer_stage_past_first_contact():
     g.step(sc.gravity, n=70, stats=False)
     st = g.step(sc.gravity, n=0)
     x, v = g.get_state()
-    assert st["n_constraints"] > 1000
+    assert st["n_constraints"] > 1000    # lying on the cylinder
+    # the drape itself makes no self contact within its 200 steps (the
+    # flaps hang apart), so the end positions get an in-plane jitter of
+    # about half an edge: neighbouring triangles and edges then cross
     rng = np.random.default_rng(14)
     xm = x
     xp = (x + sc.dt * v + sc.dt ** 2 * np.array(sc.gravity, np.float32)
-          + rng.normal(0, 2e-4, x.shape)).astype(np.float32)
+          + rng.normal(0, 8e-4, x.shape)).astype(np.float32)
     o, _, _ = oracle_side(sc, "mixed", rho=0.95, U=U)
     # first stage of a step, then a second stage carrying the first one's
     # set with drawn life spans
@@ -200,9 +204,10 @@ def test_sphere_drape_stages_and_no_tangles():
 
 
 def test_cylinder_drape_heavy_contact_stays_tangle_free():
-    """The bench workload from the 0.3 m drop through 200 steps (folding on
-    the cylinder): the device check after every step and the exact check
-    every 10th step and at the end find no intersecting triangles."""
+    """The bench workload from the 0.3 m drop through 200 steps (contact
+    from step 48 on, up to about 200,000 vertex-cylinder constraints): the
+    device check after every step and the exact check every 10th step and at
+    the end find no intersecting triangles."""
     import paper_2403_19272_amd as P
     from paper_2403_19272_amd import basis as B
     sc = scenegen.config(2)
