@@ -5,16 +5,25 @@ Workload (default): the 600 x 600-vertex cloth (360,000 vertices, 717,602
 triangles) dropped 0.3 m onto a horizontal cylinder spinning at 2 rad/s,
 self contact on, dt = 1/200 s, 3 outer blocks x 10 inner PD iterations per
 step, BF16 basis (r = 128) with FP32 local step / SpMV and FP64 reduced
-solve, 200 steps.  Synthetic, seeded input (scenegen.config(2)).
+solve.  Synthetic, seeded input (scenegen.config(2)).
 
-Metric: vertex-iterations per second = vertices x inner iterations x steps /
-wall time of the timed steps (inputs resident in HBM).  Also reported:
-p50/p99 per-step GPU time, the dominant kernel's achieved bandwidth against
-the HBM roofline (HIP events around its launches in a second, instrumented
-pass over the same steps), and the FP64 CPU oracle timed on a bounded sample
-of the same workload.
+The timed window is in the contact regime: an untimed pre-roll steps the
+seeded drop from rest past first contact (default 100 steps; the cloth meets
+the cylinder at step 48), the state there is kept, and every pass below
+starts from it:
+  * the timed pass: --steps steps replayed from the step graph, bracketed by
+    HIP events (vertex-iterations/s, p50/p99 step time);
+  * a statistics pass: the same steps with per-step statistics (constraint
+    and candidate counts over the window);
+  * an instrumented pass: the same steps with per-kernel HIP events (the
+    dominant kernel's achieved bandwidth against the HBM roofline);
+  * the same window in plain FP32 (FP32 basis), at the same iteration budget.
+Then the FP64 CPU oracle runs one step of the same workload from the same
+state (cut to 1 outer block x --cpu-iters inner iterations), on one thread
+and on the default thread pool, and the GPU's result of that same step (both
+precisions) is compared with it.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--preroll P]
 """
 from __future__ import annotations
 
@@ -22,6 +31,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -32,31 +42,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "vertex-iters/s on 360K-vert cloth (plain FP32 vs mixed/batched); p50/p99 step ms"
 HBM_PEAK_GBS = 8000.0
+SINGLE_KERNELS = ("local_residual", "expand", "jacobi_cheb", "query_count_ee", "toi_merge")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def make_gpu_scene(sc, precision, P, basis_mod):
+def make_gpu_scene(sc, precision, P, k_contact=0.0, iters_inner=None, iters_outer=None, rho=0.0, gamma=0.0):
     prec = P.CLOTH_MIXED if precision == "mixed" else P.CLOTH_PLAIN_FP32
     g = P.ClothScene(sc.tris, sc.rest, dt=sc.dt, density=sc.density, k_stretch=sc.k_stretch,
-                     k_bend=sc.k_bend, k_contact=0.0, d_hat=sc.d_hat, pinned=sc.pinned, r=sc.r,
-                     iters_inner=sc.iters_inner, iters_outer=sc.iters_outer, cheb_rho=0.0,
-                     cheb_gamma=0.0, cheb_delay=3, precision=prec, self_contact=sc.self_contact,
-                     arena="torch")
+                     k_bend=sc.k_bend, k_contact=k_contact, d_hat=sc.d_hat, pinned=sc.pinned, r=sc.r,
+                     iters_inner=iters_inner or sc.iters_inner, iters_outer=iters_outer or sc.iters_outer,
+                     cheb_rho=rho, cheb_gamma=gamma, cheb_delay=3, precision=prec,
+                     self_contact=sc.self_contact, arena="torch")
     for ob in sc.obstacles:
         g.add_obstacle(ob.kind, ob.center, ob.radius, axis=ob.axis, half_length=ob.half_length,
                        omega=ob.omega)
     return g
 
 
-def kernel_bytes(name, sc, nnz, ubytes, contact):
+def kernel_bytes(name, sc, nnz, ubytes, contact, window):
     """Algorithmic bytes one launch moves: every array the kernel reads or
     writes counted once (neighbour gathers count as cache hits).  The sweeps
     read the off-diagonal part of H in SELL-64 (8 bytes per entry; these
-    grids have no padding) plus 4 bytes per 64-row slice pointer."""
+    grids have no padding) plus 4 bytes per 64-row slice pointer.  For the
+    contact kernels the pair counts are the window's means."""
     N, T, r = sc.nv, sc.nt, sc.r
+    E = int(window.get("edges", 0))
     nblk = (N + 255) // 256
     sell = 8 * (nnz - N) + 4 * ((N + 63) // 64 + 1)
     if name == "local_residual":
@@ -77,7 +90,25 @@ def kernel_bytes(name, sc, nnz, ubytes, contact):
         if contact:
             b += 4 * N                          # W
         return b
+    if name == "query_count_ee":
+        # edge boxes and endpoint ids in, the edge records filed in the cell
+        # buckets (48 B each) and bucket offsets read once, per-edge counts
+        # and the kept hits (4 B each) out
+        hits = window.get("mean_ee_candidates_per_stage", 0.0)
+        return 24 * E + 8 * E + 48 * E + 4 * (window.get("hash_buckets", 0) + 1) + 4 * E + 4 * hits
+    if name == "toi_merge":
+        # per candidate: the pair (8 B) in, its TOI (8 B), keep flag and
+        # life span (4 + 4 B) out; positions x-, x+ (AoS, 16 B each) once
+        pairs = window.get("mean_candidates_per_stage", 0.0)
+        return 24 * pairs + 32 * N
     return None
+
+
+def edge_count(tris, nv):
+    """Number of distinct mesh edges."""
+    t = np.asarray(tris, np.int64)
+    e = np.sort(np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]]), axis=1)
+    return int(np.unique(e[:, 0] * nv + e[:, 1]).size)
 
 
 def source_hash(paths):
@@ -101,39 +132,82 @@ def pmc_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(sc, iters, rho, gamma):
-    """The FP64 oracle as it stands, on one step of the same workload cut to
-    one outer block of `iters` inner iterations (with its two CCD stages),
-    with the Chebyshev rho and damping gamma the device estimated for this
-    workload (other values can make the damped sweep diverge, and the
-    blown-up positions then swamp the CCD stage with candidate pairs)."""
-    from threadpoolctl import threadpool_info
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        out = subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip()
+        info["nproc"] = int(out)
+    except Exception:
+        pass
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return info
+
+
+def cpu_leg(sc, U, xs, vs, iters, rho, gamma, P):
+    """The FP64 oracle as it stands, one step of the workload from the
+    window's start state cut to 1 outer block x `iters` inner iterations
+    (its initial and final CCD stages included), with the Chebyshev rho and
+    damping gamma the device estimated for the workload.  It runs twice: fed
+    the BF16-stored basis on one thread (the timed baseline), and fed the
+    FP32-stored basis on the default thread pool.  The GPU steps the same
+    step in both precisions with the same settings, and its positions are
+    compared with the oracle's."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import model as M
     from oracle import step as S
     t0 = time.time()
     m = M.build_model(sc.tris, sc.rest, sc.pinned, sc.dt, sc.density, sc.k_stretch, sc.k_bend)
-    rng = np.random.default_rng(0)
-    # the timed work does not depend on the basis values: a seeded orthonormal
-    # basis of the workload's width stands in for the eigenvectors here
-    U, _ = np.linalg.qr(rng.standard_normal((sc.nv, sc.r)))
-    Us = M.stored_basis(U, sc.precision)
     p = S.Params(iters_outer=1, iters_inner=iters, cheb_rho=rho, cheb_gamma=gamma, cheb_delay=3,
                  d_hat=sc.d_hat, self_contact=sc.self_contact)
     obs = [S.Obst(o.kind, np.array(o.center, float), o.radius, np.array(o.axis, float))
            for o in sc.obstacles]
-    o = S.Oracle(m, Us, p, sc.gravity, obs)
-    o.set_state(sc.x0, sc.v0)
     log(f"cpu oracle set-up {time.time() - t0:.1f}s")
-    t0 = time.perf_counter()
-    o.step()
-    dt = time.perf_counter() - t0
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": sc.nv * iters / dt, "unit": "vertex-iters/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"one step of the same workload cut to 1 outer block x {iters} inner "
-                      f"iterations (initial and final CCD stages included), FP64 numpy/scipy + C "
-                      f"geometry; {dt:.1f} s"}
+    runs = {}
+    for prec, threads in (("mixed", 1), ("fp32", None)):
+        o = S.Oracle(m, M.stored_basis(U, prec), p, sc.gravity, obs)
+        o.set_state(xs, vs)
+        with threadpool_limits(threads):
+            used = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+            t0 = time.perf_counter()
+            st = o.step()
+            dt = time.perf_counter() - t0
+        runs[prec] = (dt, used, o.x.copy(), st)
+        log(f"cpu oracle ({prec} basis, {used} BLAS threads): {dt:.1f}s")
+    acc = {}
+    for prec in ("mixed", "fp32"):
+        g = make_gpu_scene(sc, prec, P, k_contact=m.k_contact, iters_inner=iters, iters_outer=1,
+                           rho=rho, gamma=gamma)
+        g.set_basis(U)
+        g.set_state(xs, vs)
+        g.step(sc.gravity, n=1, stats=False)
+        x, _ = g.get_state()
+        g.close()
+        xo = runs[prec][2]
+        diag = float(np.linalg.norm(xo.max(0) - xo.min(0)))
+        acc[prec] = float(np.linalg.norm(x.astype(np.float64) - xo, axis=1).max()) / diag
+    dt1, _, _, _ = runs["mixed"]
+    dtn, nth, _, _ = runs["fp32"]
+    base = {"value": sc.nv * iters / dt1, "unit": "vertex-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"one step of the same workload from the timed window's start state, cut to 1 outer "
+                      f"block x {iters} inner iterations (its initial and final CCD stages included), FP64 "
+                      f"numpy/scipy + C geometry on one thread; {dt1:.1f} s",
+            "all_threads": {"value": sc.nv * iters / dtn, "threads": int(nth),
+                            "note": "default thread pool: only the BLAS calls use it; the element-wise, "
+                                    "sparse and C-geometry parts run on one thread",
+                            "seconds": round(dtn, 2)},
+            "host": host_info()}
+    accuracy = {"max_vertex_err_over_bbox_diag": acc,
+                "reference": f"the FP64 oracle fed the same stored basis (BF16 for mixed, FP32 for plain), "
+                             f"one step (1 block x {iters} iterations, same Chebyshev parameters and contact "
+                             f"weight) from the timed window's start state"}
+    return base, accuracy
 
 
 def main():
@@ -141,11 +215,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--preroll", type=int, default=100,
+                    help="untimed steps from the seeded rest state before the timed window")
     ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
     ap.add_argument("--precision", default=None, choices=["mixed", "fp32"])
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing-pass", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 window")
     ap.add_argument("--eager", action="store_true",
                     help="launch each kernel from the host instead of replaying the step graph "
                          "(for counter collection)")
@@ -182,7 +259,7 @@ def main():
     if args.precision:
         sc.precision = args.precision
     log(f"workload {sc.name}: nv={sc.nv} nt={sc.nt} r={sc.r} {sc.precision}")
-    g = make_gpu_scene(sc, sc.precision, P, B)
+    g = make_gpu_scene(sc, sc.precision, P)
     if args.eager:
         g.set_graph(False)
     t0 = time.time()
@@ -198,65 +275,125 @@ def main():
             np.save(args.basis_cache, U)
     log(f"basis {time.time() - t0:.1f}s")
     g.set_basis(U)
-    log("basis set (Chebyshev parameters estimated on the device)")
     stream = torch.cuda.current_stream()
-    g.set_state(sc.x0, sc.v0, stream=stream)
-    for i in range(max(args.warmup, 1)):
-        st = g.step(sc.gravity, n=1, stream=stream)
-        log(f"warmup step {i}: dx={st['dx_norm']:.3e} candidates={st['n_candidates']} "
-            f"constraints={st['n_constraints']} min_toi={st['min_toi']:.4f} "
-            f"rho={st['cheb_rho']:.4f} gamma={st['cheb_gamma']:.4f}")
+    K = args.steps
+    iters = sc.iters_inner * sc.iters_outer
 
-    def timed_pass(K, timing):
-        g.set_state(sc.x0, sc.v0, stream=stream)
-        g.set_timing(timing)
+    # ---- pre-roll from the seeded rest state into the contact regime
+    g.set_state(sc.x0, sc.v0, stream=stream)
+    t0 = time.time()
+    if args.preroll > 0:
+        g.step(sc.gravity, n=args.preroll, stream=stream, stats=False)
+    st0 = g.step(sc.gravity, n=0, stream=stream)
+    xs, vs = g.get_state(stream=stream)
+    log(f"pre-roll {args.preroll} steps {time.time() - t0:.1f}s: constraints={st0['n_constraints']} "
+        f"candidates={st0['n_candidates']} min_toi={st0['min_toi']:.3f} rho={st0['cheb_rho']:.4f} "
+        f"gamma={st0['cheb_gamma']:.4f}")
+
+    def timed_pass(scene, K, timing):
+        scene.set_state(xs, vs, stream=stream)
+        scene.set_timing(timing)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev[0].record(stream)
         for i in range(K):
-            g.step(sc.gravity, n=1, stream=stream, stats=False)
+            scene.step(sc.gravity, n=1, stream=stream, stats=False)
             ev[i + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(K)])
-        kt = g.kernel_times() if timing else None
-        g.set_timing(False)
+        kt = scene.kernel_times() if timing else None
+        scene.set_timing(False)
         return wall, per, kt
 
-    K = args.steps
-    wall, per, _ = timed_pass(K, False)
-    stats = g.step(sc.gravity, n=0, stream=stream)  # stats of the last step
-    iters = sc.iters_inner * sc.iters_outer
+    def warm(scene):
+        scene.set_state(xs, vs, stream=stream)
+        for _ in range(max(args.warmup, 1)):
+            scene.step(sc.gravity, n=1, stream=stream, stats=False)
+        torch.cuda.synchronize()
+
+    warm(g)
+    wall, per, _ = timed_pass(g, K, False)
     value = sc.nv * iters * K / wall
-    log(f"timed {K} steps: {wall:.3f}s  {value:.3e} vertex-iters/s  p50 {np.percentile(per, 50):.3f} ms")
+    log(f"timed {K} steps from step {args.preroll}: {wall:.3f}s  {value:.3e} vertex-iters/s  "
+        f"p50 {np.percentile(per, 50):.3f} ms")
+
+    # ---- statistics of the same window
+    g.set_state(xs, vs, stream=stream)
+    wst = []
+    for i in range(K):
+        wst.append(g.step(sc.gravity, n=1, stream=stream))
     x, v = g.get_state(stream=stream)
     finite = bool(np.isfinite(x).all() and np.isfinite(v).all())
+    ncon = np.array([s["n_constraints"] for s in wst], float)
+    ncand = np.array([s["n_candidates"] for s in wst], float)
+    cur = g.stage_read_set(nob=len(sc.obstacles), cap=1)
+    window = {"start_step": args.preroll, "steps": K,
+              "mean_constraints": float(ncon.mean()), "min_constraints": int(ncon.min()),
+              "max_constraints": int(ncon.max()),
+              "mean_candidates_per_step": float(ncand.mean()),
+              "mean_contact_vertices": float(np.mean([s["n_contact_vertices"] for s in wst])),
+              "last_self_contact_constraints": int(g._nvt + g._nee),
+              "min_toi": float(min(s["min_toi"] for s in wst)),
+              "contact": bool(ncon.min() > 0)}
+    log("window:", json.dumps(window))
 
-    roof = None
-    kt = None
+    roof, rooflines, kt, step_roof = None, {}, None, None
     if not args.no_timing_pass:
-        wall2, per2, kt = timed_pass(K, True)
+        wall2, per2, kt = timed_pass(g, K, True)
         nnz = H.nnz
         ub = 2 if sc.precision == "mixed" else 4
         contact = sc.self_contact or bool(sc.obstacles)
-        cands = {k: v for k, v in kt.items() if k in ("local_residual", "expand", "jacobi_cheb") and v[1]}
-        dom = max(cands, key=lambda k: cands[k][0])
-        tot_ms, n_launch = cands[dom]
-        avg_s = tot_ms / n_launch / 1e3
-        nbytes = kernel_bytes(dom, sc, nnz, ub, contact)
-        ach = nbytes / avg_s / 1e9
-        traffic = pmc_traffic(dom, args.workload)
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(nbytes),
+        # pair counts per stage for the contact kernels' byte counts: the
+        # candidate total of a step is summed over its (iters_outer + 1)
+        # stages (VT + EE); the EE share is taken from the edge/vertex ratio
+        stages = sc.iters_outer + 1
+        E = edge_count(sc.tris, sc.nv)
+        win = {"edges": E, "mean_candidates_per_stage": window["mean_candidates_per_step"] / stages,
+               "mean_ee_candidates_per_stage": window["mean_candidates_per_step"] / stages * E / (E + sc.nv),
+               "hash_buckets": 0}
+        for k in SINGLE_KERNELS:
+            if k not in kt or not kt[k][1]:
+                continue
+            tot_ms, n_launch = kt[k]
+            avg_s = tot_ms / n_launch / 1e3
+            nbytes = kernel_bytes(k, sc, nnz, ub, contact, win)
+            ach = nbytes / avg_s / 1e9
+            rooflines[k] = {"avg_launch_us": round(avg_s * 1e6, 2), "launches_per_step": n_launch / K,
+                            "ms_per_step": round(tot_ms / K, 4), "bytes_per_launch": int(nbytes),
+                            "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)}
+        dom = max(rooflines, key=lambda k: rooflines[k]["ms_per_step"])
+        rd = rooflines[dom]
+        roof = {"bound": "hbm", "achieved": rd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": rd["frac"], "traffic": pmc_traffic(dom, args.workload), "kernel": dom,
+                "avg_launch_us": rd["avg_launch_us"], "bytes_per_launch": rd["bytes_per_launch"],
                 "instrumented_wall_s": round(wall2, 3)}
+        pd_bytes = sum(kernel_bytes(k, sc, nnz, ub, contact, win) for k in ("local_residual", "expand",
+                                                                          "jacobi_cheb"))
+        ceil_ms = pd_bytes * iters / (HBM_PEAK_GBS * 1e9) * 1e3
+        step_roof = {"pd_bytes_per_iteration": int(pd_bytes), "pd_ceiling_ms_per_step": round(ceil_ms, 4),
+                     "measured_ms_per_step": round(wall / K * 1e3, 4),
+                     "frac": round(ceil_ms / (wall / K * 1e3), 4)}
         log("kernel times (ms, launches):", json.dumps({k: [round(a, 3), b] for k, (a, b) in kt.items()}))
 
-    cpu = None
+    fp32 = None
+    if not args.no_fp32 and sc.precision == "mixed":
+        g32 = make_gpu_scene(sc, "fp32", P)
+        g32.set_basis(U)
+        warm(g32)
+        wall3, per3, _ = timed_pass(g32, K, False)
+        fp32 = {"value": round(sc.nv * iters * K / wall3, 1), "ms_per_step": round(wall3 / K * 1e3, 4),
+                "p50_step_ms": round(float(np.percentile(per3, 50)), 4),
+                "p99_step_ms": round(float(np.percentile(per3, 99)), 4),
+                "dtype": "f32", "note": "plain FP32 (FP32 basis), same window and iteration budget"}
+        log(f"plain fp32: {fp32['value']:.3e} vertex-iters/s, {fp32['ms_per_step']:.3f} ms/step")
+        g32.close()
+
+    cpu, accuracy = None, None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(sc, args.cpu_iters, st["cheb_rho"], st["cheb_gamma"])
+            cpu, accuracy = cpu_leg(sc, U, xs, vs, args.cpu_iters, st0["cheb_rho"], st0["cheb_gamma"], P)
         except Exception as e:  # reported, never fatal for the GPU figure
             log(f"cpu baseline failed: {e!r}")
     out = {
@@ -265,24 +402,32 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+bf16" if sc.precision == "mixed" else "f32", "data": "synthetic",
         "config": {"workload": f"{sc.name}: {sc.n_side}x{sc.n_side} cloth ({sc.nv} verts, {sc.nt} tris) "
-                               f"dropped {0.3} m onto a {'cylinder spinning at 2 rad/s' if args.workload == 'c2' else 'sphere'}, "
-                               f"self contact, dt=1/200 s, {sc.iters_outer}x{sc.iters_inner} PD iterations/step, "
-                               f"r={sc.r} {'BF16' if sc.precision == 'mixed' else 'FP32'} basis, FP64 reduced solve",
+                               f"dropped 0.3 m onto a "
+                               f"{'cylinder spinning at 2 rad/s' if args.workload == 'c2' else 'sphere'}, "
+                               f"self contact, dt=1/200 s, {sc.iters_outer}x{sc.iters_inner} PD "
+                               f"iterations/step, r={sc.r} {'BF16' if sc.precision == 'mixed' else 'FP32'} "
+                               f"basis, FP64 reduced solve; timed window of {K} steps from step "
+                               f"{args.preroll} (in contact)",
                    "vertices": sc.nv, "triangles": sc.nt, "iters_per_step": iters, "r": sc.r,
-                   "precision": sc.precision, "steps_from_rest_state": K},
+                   "precision": sc.precision, "window_start_step": args.preroll},
         "p50_step_ms": round(float(np.percentile(per, 50)), 4),
         "p99_step_ms": round(float(np.percentile(per, 99)), 4),
         "steps_per_s": round(K / wall, 2),
-        "last_step": {"n_candidates": stats["n_candidates"], "n_constraints": stats["n_constraints"],
-                      "min_toi": stats["min_toi"], "dx_norm": stats["dx_norm"],
-                      "cheb_rho": stats["cheb_rho"], "cheb_gamma": stats["cheb_gamma"],
-                      "n_contact_vertices": stats["n_contact_vertices"], "finite": finite},
+        "window": window,
+        "last_step": {"n_candidates": wst[-1]["n_candidates"], "n_constraints": wst[-1]["n_constraints"],
+                      "min_toi": wst[-1]["min_toi"], "dx_norm": wst[-1]["dx_norm"],
+                      "cheb_rho": wst[-1]["cheb_rho"], "cheb_gamma": wst[-1]["cheb_gamma"],
+                      "n_contact_vertices": wst[-1]["n_contact_vertices"], "finite": finite},
+        "plain_fp32": fp32,
+        "accuracy": accuracy,
         "launch": "eager" if args.eager else "graph replay",
         "roofline": roof,
+        "kernel_rooflines": rooflines or None,
+        "step_roofline": step_roof,
         "cpu_baseline": cpu,
     }
     if kt:
-        out["kernel_ms"] = {k: round(a, 3) for k, (a, b) in kt.items() if b}
+        out["kernel_ms_per_step"] = {k: round(a / K, 4) for k, (a, b) in kt.items() if b}
     print(json.dumps(out), flush=True)
 
 

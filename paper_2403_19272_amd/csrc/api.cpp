@@ -223,7 +223,9 @@ namespace cloth {
 // Jacobi sweep) get the kernel's own start/end time (the launcher passes the
 // events to hipExtLaunchKernelGGL); the other operations, which may launch
 // several kernels, are bracketed by two recorded events.
-static bool single_kernel_op(int id) { return id == K_LOCAL || id == K_EXPAND || id == K_JACOBI; }
+static bool single_kernel_op(int id) {
+    return id == K_LOCAL || id == K_EXPAND || id == K_JACOBI || id == K_QUERY_EE || id == K_TOI;
+}
 
 static void t_begin(Scene& s, int id, hipStream_t st) {
     if (!s.timing) return;
@@ -266,6 +268,9 @@ static void t_collect(Scene& s) {
     }
     s.ev_used.clear();
 }
+
+void timing_begin(Scene& s, int id, hipStream_t st) { t_begin(s, id, st); }
+void timing_end(Scene& s, hipStream_t st) { t_end(s, st); }
 
 #define TIMED(id, expr)            \
     do {                           \
@@ -778,7 +783,9 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
         xplus = d.xk;
     }
     if (contact) {
-        TIMED(K_OUTER, contact_step_begin(s, c, xplus, st));   // x- = x*, x+: CCD, filter -> x, x-
+        // x- = x*, x+: CCD, filter -> x, x- (timed by phase inside)
+        cloth_status rc = contact_step_begin(s, c, xplus, st);
+        if (rc != CLOTH_OK) return rc;
     } else {
         TIMED(K_MISC, launch_copy3(d.x, xplus, n, st));
     }
@@ -802,7 +809,8 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
         unsigned long long* dxo = d.dxbits + slot_outer(s, o);
         if (contact) {
             bool last = o == s.iters_out - 1;
-            TIMED(K_OUTER, contact_block_end(s, c, !last || rf, dxo, st));  // x+ = x^k -> x, x-
+            cloth_status rc = contact_block_end(s, c, !last || rf, dxo, st);  // x+ = x^k -> x, x-
+            if (rc != CLOTH_OK) return rc;
         } else {
             TIMED(K_MISC, launch_block_end(d, dxo, st));
         }

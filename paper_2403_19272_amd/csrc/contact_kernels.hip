@@ -7,6 +7,7 @@
 // Every kernel takes its item counts from device memory and loops over them
 // with a fixed grid, so the whole step can be enqueued without reading
 // anything back on the host.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +20,20 @@
 #include "kernels.hpp"
 
 namespace cloth {
+
+namespace {
+// Launch carrying the timing events of a single-kernel timing bracket, if
+// one is open on this thread (see timing_begin).
+template <typename... KArgs, typename... Args>
+void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shm, hipStream_t st, Args... args) {
+    hipEvent_t a, b;
+    if (kernel_events(&a, &b))
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, st, a, b, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+}
+}  // namespace
+
 
 // tolerance mode: a set gate turns the launch into a no-op (see Dev::gate)
 __device__ __forceinline__ bool gated(const int* g) { return g && *g; }
@@ -2308,10 +2323,15 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
             hipLaunchKernelGGL((k_query_count<true, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
                                c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7, c.heavy_q,
                                c.cnt + HEAVY_SLOT);
-        else
-            hipLaunchKernelGGL((k_query_count<false, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
-                               c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7, c.heavy_q,
-                               c.cnt + HEAVY_SLOT);
+        else {
+            timing_end(s, st);
+            timing_begin(s, K_QUERY_EE, st);
+            launch_timed(k_query_count<false, QUERY_LANES>, dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
+                         (const int*)c.bucket_ptr, (const BpRec*)c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7,
+                         c.heavy_q, c.cnt + HEAVY_SLOT);
+            timing_end(s, st);
+            timing_begin(s, K_BROAD, st);
+        }
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, s.d.gate, c.keep, cnts, nq);
         HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
         hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, s.d.gate, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
@@ -2356,14 +2376,20 @@ static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm,
     int npart = 0;
     if (s.self_contact) {
         const int nb = gblocks(2 * c.cap);
-        hipLaunchKernelGGL(k_toi_merge, dim3(nb), dim3(TPB), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
-                           c.cand_vt, c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.keep, c.cand_a, c.tpart, 1);
+        timing_begin(s, K_TOI, st);
+        launch_timed(k_toi_merge, dim3(nb), dim3(TPB), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
+                     (const int2*)c.cand_vt, (const int2*)c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.keep,
+                     c.cand_a, c.tpart, 1);
+        timing_end(s, st);
+        timing_begin(s, K_OUTER, st);
         hipLaunchKernelGGL(k_prev_match, dim3(gblocks(c.ccap)), dim3(TPB), 0, st, s.d.gate, (const int*)c.cnt,
                            (const int2*)c.cpair_prev, (const int*)c.ca_prev, (const int2*)c.cand_vt,
                            (const int2*)c.cand_ee, (const int*)c.vcount, (const int*)c.ecount, n, s.ne, c.keep,
                            c.cand_a);
         npart = nb;
     }
+    else
+        timing_begin(s, K_OUTER, st);
     if (c.nob > 0) {
         const int nb = gblocks(n);
         hipLaunchKernelGGL(k_obstacles_outer, dim3(nb), dim3(TPB), 0, st, d, xm, xp, c.tpart + npart, c.cnt + 10);
@@ -2404,19 +2430,24 @@ static cloth_status block_setup(Scene& s, ContactState& c, hipStream_t st) {
     return CLOTH_OK;
 }
 
+// Timing brackets of a stage: K_BROAD from the start to the end of the
+// broad phase (closed and reopened around the edge-edge counting pass,
+// K_QUERY_EE), K_TOI around the TOI kernel, K_OUTER from there to the end.
 static cloth_status outer_stage(Scene& s, ContactState& c, const float* xm, const float* xp, bool first,
                                 bool setup, unsigned long long* dxo, hipStream_t st) {
+    timing_begin(s, K_BROAD, st);
     if (first) hipLaunchKernelGGL(k_fill_i32, dim3(gblocks((int64_t)MAX_OBST * s.nv)), dim3(TPB), 0, st, s.d.gate, c.ob_a, -1,
                                   MAX_OBST * s.nv);
     hipLaunchKernelGGL(k_save_prev, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, s.d.gate, c.cnt, c.cpair, c.ca, c.cpair_prev,
                        c.ca_prev, first ? 1 : 0);
     hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, st, s.d.gate, c.cnt, first ? 1 : 0, c.tmin_bits);
     cloth_status rc = broad_phase(s, c, xm, xp, st);
+    timing_end(s, st);
     if (rc != CLOTH_OK) return rc;
     rc = toi_merge_filter(s, c, xm, xp, dxo, st);
-    if (rc != CLOTH_OK) return rc;
-    if (setup) return block_setup(s, c, st);
-    return CLOTH_OK;
+    if (rc == CLOTH_OK && setup) rc = block_setup(s, c, st);
+    timing_end(s, st);
+    return rc;
 }
 
 cloth_status contact_step_begin(Scene& s, ContactState& c, const float* xp, hipStream_t st) {

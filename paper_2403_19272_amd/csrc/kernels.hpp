@@ -12,6 +12,8 @@ namespace cloth {
 // the kernel's own start and end time instead of a marker around it.
 void set_kernel_events(hipEvent_t start, hipEvent_t stop);
 void clear_kernel_events();
+// the pair set on this thread, if any (for launchers in other files)
+bool kernel_events(hipEvent_t* start, hipEvent_t* stop);
 
 // ---- PD iteration (pd_kernels.hip)
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);

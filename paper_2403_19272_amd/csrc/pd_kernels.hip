@@ -788,6 +788,12 @@ void clear_kernel_events() {
     t_ev_stop = nullptr;
 }
 
+bool kernel_events(hipEvent_t* start, hipEvent_t* stop) {
+    *start = t_ev_start;
+    *stop = t_ev_stop;
+    return t_ev_start && t_ev_stop;
+}
+
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
     return hipGetLastError();

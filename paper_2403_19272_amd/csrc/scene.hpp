@@ -175,13 +175,23 @@ struct Scene {
 };
 
 // kernel ids of the timing table
+// (the outer CCD stage: K_BROAD broad phase other than the edge-edge
+// counting pass K_QUERY_EE, K_TOI the time-of-impact kernel, K_OUTER the
+// rest: set merge, obstacles, step length, compaction, filter, block set-up)
 enum KernelId {
     K_PREDICT = 0, K_LOCAL, K_REDUCE, K_EXPAND, K_JACOBI, K_TARGETS, K_GRAM_CHOL, K_PCCD, K_OUTER,
-    K_MISC, K_COUNT
+    K_BROAD, K_QUERY_EE, K_TOI, K_MISC, K_COUNT
 };
 static const char* const kKernelNames[K_COUNT] = {
     "predict", "local_residual", "reduce_solve", "expand", "jacobi_cheb", "pair_targets",
-    "gram_cholesky", "partial_ccd", "outer_ccd_stage", "misc"};
+    "gram_cholesky", "partial_ccd", "outer_set_filter", "broad_phase", "query_count_ee", "toi_merge",
+    "misc"};
+
+// Timing brackets (api.cpp): no-ops unless the scene's timing is on.  For a
+// single-kernel id (local residual, expand, Jacobi sweep, edge-edge query
+// count, TOI) the next launch through launch_timed carries the events.
+void timing_begin(Scene& s, int id, hipStream_t st);
+void timing_end(Scene& s, hipStream_t st);
 
 // host precompute (host_build.cpp)
 std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, double dt,
