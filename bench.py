@@ -49,13 +49,14 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def make_gpu_scene(sc, precision, P, k_contact=0.0, iters_inner=None, iters_outer=None, rho=0.0, gamma=0.0):
+def make_gpu_scene(sc, precision, P, k_contact=0.0, iters_inner=None, iters_outer=None, rho=0.0, gamma=0.0,
+                   broad_reuse=False):
     prec = P.CLOTH_MIXED if precision == "mixed" else P.CLOTH_PLAIN_FP32
     g = P.ClothScene(sc.tris, sc.rest, dt=sc.dt, density=sc.density, k_stretch=sc.k_stretch,
                      k_bend=sc.k_bend, k_contact=k_contact, d_hat=sc.d_hat, pinned=sc.pinned, r=sc.r,
                      iters_inner=iters_inner or sc.iters_inner, iters_outer=iters_outer or sc.iters_outer,
                      cheb_rho=rho, cheb_gamma=gamma, cheb_delay=3, precision=prec,
-                     self_contact=sc.self_contact, arena="torch")
+                     self_contact=sc.self_contact, broad_reuse=broad_reuse, arena="torch")
     for ob in sc.obstacles:
         g.add_obstacle(ob.kind, ob.center, ob.radius, axis=ob.axis, half_length=ob.half_length,
                        omega=ob.omega)
@@ -223,6 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing-pass", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 window")
+    ap.add_argument("--broad-reuse", action="store_true",
+                    help="filter the candidate lists from the reusable superset (broad_reuse)")
     ap.add_argument("--eager", action="store_true",
                     help="launch each kernel from the host instead of replaying the step graph "
                          "(for counter collection)")
@@ -259,7 +262,7 @@ def main():
     if args.precision:
         sc.precision = args.precision
     log(f"workload {sc.name}: nv={sc.nv} nt={sc.nt} r={sc.r} {sc.precision}")
-    g = make_gpu_scene(sc, sc.precision, P)
+    g = make_gpu_scene(sc, sc.precision, P, broad_reuse=args.broad_reuse)
     if args.eager:
         g.set_graph(False)
     t0 = time.time()
@@ -334,6 +337,11 @@ def main():
               "max_constraints": int(ncon.max()),
               "mean_candidates_per_step": float(ncand.mean()),
               "mean_contact_vertices": float(np.mean([s["n_contact_vertices"] for s in wst])),
+              # (the first read also counts the warm-up and timed passes)
+              "mean_factorizations_per_step": float(np.mean([s["n_factorizations"] for s in wst[1:]]))
+              if K > 1 else None,
+              "mean_broad_rebuilds_per_step": float(np.mean([s["n_broad_rebuilds"] for s in wst[1:]]))
+              if K > 1 else None,
               "last_self_contact_constraints": int(g._nvt + g._nee),
               "min_toi": float(min(s["min_toi"] for s in wst)),
               "contact": bool(ncon.min() > 0)}
@@ -379,7 +387,7 @@ def main():
 
     fp32 = None
     if not args.no_fp32 and sc.precision == "mixed":
-        g32 = make_gpu_scene(sc, "fp32", P)
+        g32 = make_gpu_scene(sc, "fp32", P, broad_reuse=args.broad_reuse)
         g32.set_basis(U)
         warm(g32)
         wall3, per3, _ = timed_pass(g32, K, False)

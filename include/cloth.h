@@ -114,7 +114,29 @@ typedef struct {
  *   debug_tangles       1: after every step, test the end state for pairs of
  *                       vertex-disjoint triangles that intersect (FP64
  *                       orientation tests); a step that has any fails with
- *                       CLOTH_E_TANGLED */
+ *                       CLOTH_E_TANGLED
+ *   broad_reuse         1: the broad phase filters a superset of the candidate
+ *                       pairs (below) instead of querying the grid at every
+ *                       stage; it pays where boxes move less than their
+ *                       margins between stages (slow scenes), and costs a
+ *                       rebuild with grown boxes where some primitive always
+ *                       escapes.  0 (default): query per stage
+ *   broad_margin, broad_margin_motion
+ *                       with broad_reuse, the broad phase filters a superset of the candidate
+ *                       pairs built on boxes grown along each axis c by
+ *                       min(broad_margin + broad_margin_motion * m_c,
+ *                       16 broad_margin), m_c the largest change of
+ *                       coordinate c of the primitive in the stage that
+ *                       built it, and builds it again when a stage box
+ *                       leaves its grown box; the candidate lists are the
+ *                       same either way.  The superset lists hold twice
+ *                       pair_capacity (peak_candidates reports the largest
+ *                       list, superset included).  <= 0: d_hat / 4 and 1
+ *   r_warm              width of the modal warm start's own basis (set with
+ *                       cloth_set_warm_basis; the paper uses a wider one
+ *                       there, 120 modes against 30, section 8.1), a
+ *                       multiple of 8 in [8, 192]; 0: the warm start uses
+ *                       the reuse basis */
 typedef struct {
     int32_t r, iters_inner, iters_outer;
     double tol_inner, tol_outer;
@@ -122,6 +144,8 @@ typedef struct {
     int32_t cheb_delay, precision, self_contact;
     int64_t pair_capacity;
     int32_t debug_tangles;
+    double broad_margin, broad_margin_motion;
+    int32_t r_warm, broad_reuse;
 } cloth_solver_params;
 
 typedef struct {
@@ -143,6 +167,13 @@ typedef struct {
     int64_t n_contact_vertices;  /* vertices with a collision weight in the
                                     last block: the rows of the contact Gram
                                     U_C^T diag(W) U_C (Eq. (uu)) */
+    int64_t n_factorizations;    /* factorizations of the contact reduced
+                                    matrix since the previous stats read: an
+                                    inner iteration whose collision weights
+                                    equal those of the last factorization
+                                    reuses it */
+    int64_t n_broad_rebuilds;    /* rebuilds of the reusable candidate
+                                    superset since the previous stats read */
 } cloth_step_stats;
 
 const char* cloth_status_string(cloth_status s);
@@ -176,6 +207,14 @@ cloth_status cloth_system_matrix(cloth_scene s, int64_t* nnz, int32_t* row_ptr, 
  * Section 5: U holds the eigenvectors of H for the r smallest eigenvalues;
  * any basis is accepted (the correction is a Galerkin projection). */
 cloth_status cloth_set_basis(cloth_scene s, const double* U, int32_t r);
+
+/* Sets the modal warm start's own basis Uw (nv*r_warm FP64, row-major,
+ * caller's vertex order; pinned rows stored as zero): Algorithm 1's warm
+ * start then runs its local/global iterations in span(Uw) with the Galerkin
+ * matrix Uw~^T H Uw~ (the diagonal of eigenvalues for an exact eigenbasis)
+ * formed and inverted in FP64.  CLOTH_E_INVALID if the scene was created
+ * with r_warm = 0 or r_warm differs. */
+cloth_status cloth_set_warm_basis(cloth_scene s, const double* U, int32_t r_warm);
 
 /* Computes the basis on the device and sets it (as cloth_set_basis): the r
  * lowest eigenvectors of H on the free vertices by Chebyshev-filtered
@@ -244,6 +283,19 @@ cloth_status cloth_destroy(cloth_scene s);
  * joins them.  stats: n entries or NULL (then no synchronisation). */
 cloth_status cloth_step_batch(cloth_scene* scenes, int32_t n, const float gravity[3], void* stream,
                               cloth_step_stats* stats);
+
+/* One launch for many scenes (same device): cloth_batch_create records each
+ * scene's step with gravity g as a child graph of one parent graph (no
+ * edges between scenes) and instantiates it; cloth_batch_step replays it
+ * `steps` times on the stream, one hipGraphLaunch per step for all scenes.
+ * Results equal those of stepping each scene alone.  The scenes must
+ * outlive the batch and must not be stepped, modified or given another
+ * basis or obstacle while it is used (its recorded launches would then be
+ * stale: create the batch again). */
+typedef struct cloth_batch_s* cloth_batch;
+cloth_status cloth_batch_create(cloth_scene* scenes, int32_t n, const float gravity[3], cloth_batch* out);
+cloth_status cloth_batch_step(cloth_batch b, int32_t steps, void* stream);
+cloth_status cloth_batch_destroy(cloth_batch b);
 
 /* Continuous-batching step server.  A host thread keeps up to `slots` steps
  * in flight (one stream each), starts queued requests as slots and their

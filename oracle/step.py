@@ -219,9 +219,15 @@ class Oracle:
     """FP64 reference solver for one scene; state is (x, v)."""
 
     def __init__(self, model: Model, Us: np.ndarray, params: Params, gravity,
-                 obstacles: Optional[List[Obst]] = None):
+                 obstacles: Optional[List[Obst]] = None, Uw: Optional[np.ndarray] = None):
+        """Us: the stored basis of the subspace reuse (section 5); Uw: the
+        stored basis of the modal warm start (Algorithm 1 before the first
+        full CCD), by default Us (the paper uses a wider one there, 120
+        modes against 30, section 8.1)."""
         self.m = model
         self.U = np.asarray(Us, np.float64)
+        self.Uw = self.U if Uw is None else np.asarray(Uw, np.float64)
+        self.Lw = self.Uw.T @ (model.H @ self.Uw)
         self.p = params
         self.g = np.asarray(gravity, np.float64)
         self.obs = obstacles or []
@@ -418,16 +424,17 @@ class Oracle:
     def warm_start(self, z, inertia):
         """Modal warm start (Algorithm 1 before the first full CCD): local
         projections of the elastic terms and the global solve restricted to
-        span(U), collisions ignored: q = Lambda~^{-1} U^T (b - H x), x += U q,
-        warm_iters times from x = z."""
+        span(Uw), collisions ignored: q = Lw^{-1} Uw^T (b - H x), x += Uw q
+        with Lw = Uw^T H Uw (the diagonal of eigenvalues for an exact
+        eigenbasis), warm_iters times from x = z."""
         m = self.m
-        cf = sla.cho_factor(self.Lam)
+        cf = sla.cho_factor(self.Lw)
         x = z.copy()
         for _ in range(self.p.warm_iters):
             b = inertia + elastic_rhs(m, x)
             r = b - m.H @ x
             r[~self.free] = 0
-            x = x + self.U @ sla.cho_solve(cf, self.U.T @ r)
+            x = x + self.Uw @ sla.cho_solve(cf, self.Uw.T @ r)
         return x
 
     def residual_forward(self, x, C, inertia):

@@ -37,7 +37,8 @@ EXPORTS = [
     "cloth_stage_outer", "cloth_stage_read_set", "cloth_step_batch", "cloth_server_create",
     "cloth_server_admit", "cloth_server_release", "cloth_server_submit", "cloth_server_poll",
     "cloth_server_wait", "cloth_server_destroy", "cloth_compute_basis", "cloth_set_step_options",
-    "cloth_get_forwarded", "cloth_compute_basis_static",
+    "cloth_get_forwarded", "cloth_compute_basis_static", "cloth_set_warm_basis", "cloth_batch_create",
+    "cloth_batch_step", "cloth_batch_destroy",
 ]
 
 
@@ -57,7 +58,8 @@ class SolverParams(C.Structure):
                 ("tol_inner", C.c_double), ("tol_outer", C.c_double),
                 ("cheb_rho", C.c_double), ("cheb_gamma", C.c_double), ("cheb_delay", C.c_int32),
                 ("precision", C.c_int32), ("self_contact", C.c_int32), ("pair_capacity", C.c_int64),
-                ("debug_tangles", C.c_int32)]
+                ("debug_tangles", C.c_int32), ("broad_margin", C.c_double),
+                ("broad_margin_motion", C.c_double), ("r_warm", C.c_int32), ("broad_reuse", C.c_int32)]
 
 
 class Obstacle(C.Structure):
@@ -71,7 +73,8 @@ class StepStats(C.Structure):
                 ("dx_norm", C.c_double), ("outer_dx", C.c_double), ("min_toi", C.c_double),
                 ("cheb_rho", C.c_double),
                 ("cheb_gamma", C.c_double), ("peak_candidates", C.c_int64),
-                ("n_contact_vertices", C.c_int64)]
+                ("n_contact_vertices", C.c_int64), ("n_factorizations", C.c_int64),
+                ("n_broad_rebuilds", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +94,10 @@ def _load():
                              C.c_size_t, C.POINTER(P)]),
         "cloth_system_matrix": (i32, [P, C.POINTER(i64), P, P, P]),
         "cloth_set_basis": (i32, [P, P, i32]),
+        "cloth_set_warm_basis": (i32, [P, P, i32]),
+        "cloth_batch_create": (i32, [P, i32, P, C.POINTER(P)]),
+        "cloth_batch_step": (i32, [P, i32, P]),
+        "cloth_batch_destroy": (i32, [P]),
         "cloth_add_obstacle": (i32, [P, C.POINTER(Obstacle)]),
         "cloth_set_state": (i32, [P, P, P, P]),
         "cloth_get_state": (i32, [P, P, P, P]),
@@ -167,7 +174,8 @@ class ClothScene:
                  alpha=0.8, pinned=None, r=16, iters_inner=10, iters_outer=1, tol_inner=0.0,
                  tol_outer=0.0, cheb_rho=0.0, cheb_gamma=0.0, cheb_delay=3,
                  precision=CLOTH_PLAIN_FP32, self_contact=False, pair_capacity=0,
-                 debug_tangles=False, arena=None):
+                 debug_tangles=False, broad_margin=0.0, broad_margin_motion=0.0, r_warm=0,
+                 broad_reuse=False, arena=None):
         self._tris = np.ascontiguousarray(tris, np.int32)
         rest = _f32(rest)
         nv = rest.shape[0]
@@ -179,8 +187,10 @@ class ClothScene:
                             d_hat, alpha)
         self.params = SolverParams(r, iters_inner, iters_outer, tol_inner, tol_outer, cheb_rho,
                                    cheb_gamma, cheb_delay, precision, int(bool(self_contact)),
-                                   pair_capacity, int(bool(debug_tangles)))
+                                   pair_capacity, int(bool(debug_tangles)), broad_margin,
+                                   broad_margin_motion, r_warm, int(bool(broad_reuse)))
         self.r = r
+        self.r_warm = r_warm
         nbytes = C.c_size_t(0)
         _check(lib.cloth_query_footprint(C.byref(self.mesh), C.byref(self.params), C.byref(nbytes)),
                "cloth_query_footprint")
@@ -210,6 +220,11 @@ class ClothScene:
     def set_basis(self, U: np.ndarray):
         U = np.ascontiguousarray(U, np.float64)
         _check(lib.cloth_set_basis(self._h, _ptr(U), U.shape[1]), "cloth_set_basis")
+
+    def set_warm_basis(self, U):
+        """The modal warm start's own basis (nv x r_warm)."""
+        U = np.ascontiguousarray(U, np.float64)
+        _check(lib.cloth_set_warm_basis(self._h, _ptr(U), U.shape[1]), "cloth_set_warm_basis")
 
     def compute_basis(self, degree=300, max_passes=12, tol=2e-2, return_basis=False, static=False):
         """Device eigenbasis (Chebyshev-filtered subspace iteration), then set.
@@ -371,6 +386,32 @@ def step_batch(scenes, gravity=(0.0, -9.8, 0.0), stream=None, stats=True):
     _check(lib.cloth_step_batch(hs, n, _ptr(g), _stream(stream), st if stats else None),
            "cloth_step_batch")
     return [s.as_dict() for s in st] if stats else None
+
+
+class BatchGraph:
+    """Every scene's step as one graph launch (see cloth_batch_* in cloth.h)."""
+
+    def __init__(self, scenes, gravity=(0.0, -9.8, 0.0)):
+        self.scenes = list(scenes)
+        n = len(self.scenes)
+        hs = (C.c_void_p * n)(*[sc._h.value for sc in self.scenes])
+        g = np.asarray(gravity, np.float32)
+        self._h = C.c_void_p()
+        _check(lib.cloth_batch_create(hs, n, _ptr(g), C.byref(self._h)), "cloth_batch_create")
+
+    def step(self, steps=1, stream=None):
+        _check(lib.cloth_batch_step(self._h, steps, _stream(stream)), "cloth_batch_step")
+
+    def close(self):
+        if self._h:
+            lib.cloth_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class StepServer:

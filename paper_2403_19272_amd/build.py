@@ -42,7 +42,8 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(out)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fopenmp", "-pthread", "-o", tmp, *objs]
+    # -z defs: an unresolved symbol fails the link instead of the first load
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fopenmp", "-pthread", "-Wl,-z,defs", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

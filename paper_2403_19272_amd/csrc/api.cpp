@@ -172,13 +172,21 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     s.d_edges = cv<int>(carve_fn, 2 * (size_t)s.ne);
     size_t ubytes = (s.prec == CLOTH_MIXED ? 2 : 4) * (size_t)n * s.r;
     s.d_U = cv<char>(carve_fn, ubytes);
-    d.gpart = cv<float>(carve_fn, (size_t)s.nblk * s.r * 3);
-    d.Qf = cv<float>(carve_fn, (size_t)s.r * 3);
-    d.Qd = cv<double>(carve_fn, (size_t)s.r * 3);
+    // the warm-start basis (optional) and the work buffers of the wider basis
+    const int rw = std::max(s.r, s.r_warm);
+    if (s.r_warm > 0) {
+        s.d_Uw = cv<char>(carve_fn, (s.prec == CLOTH_MIXED ? 2 : 4) * (size_t)n * s.r_warm);
+        s.d_Ainvw = cv<double>(carve_fn, (size_t)s.r_warm * s.r_warm);
+        if (!s.d_Uw || !s.d_Ainvw) return fail(CLOTH_E_OOM, "arena exhausted (warm basis)");
+    }
+    d.gpart = cv<float>(carve_fn, (size_t)s.nblk * rw * 3);
+    d.Qf = cv<float>(carve_fn, (size_t)rw * 3);
+    d.Qd = cv<double>(carve_fn, (size_t)rw * 3);
     d.Ainv = cv<double>(carve_fn, (size_t)s.r * s.r);
     d.Lam = cv<double>(carve_fn, (size_t)s.r * s.r);
     d.Amat = cv<double>(carve_fn, (size_t)(GRAM_GROUPS_MAX + 1) * s.r * (s.r + 1) / 2);
     d.gram_part = cv<double>(carve_fn, (size_t)GRAM_CHUNKS * s.r * s.r);
+    d.cholf = cv<double>(carve_fn, (size_t)s.r * (s.r + 1) / 2 + s.r);
     s.nslots_cap = slots_needed(s);
     d.dxbits = cv<unsigned long long>(carve_fn, (size_t)s.nslots_cap);
     s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);
@@ -186,7 +194,7 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     if (!d.x4 || !d.d4 || !d.W || !d.mh2 || !d.diag || !s.d_pinned || !s.d_rowptr || !s.d_col || !s.d_val || !s.d_tri ||
         !s.d_sell_ptr || !s.d_sell_col || !s.d_sell_val ||
         !s.d_inc_ptr || !s.d_inc || !s.d_edges || !s.d_U || !d.gpart || !d.Qf || !d.Qd || !d.Ainv ||
-        !d.Lam || !d.Amat || !d.gram_part || !d.dxbits || !s.d_rfdx || !s.d_gate)
+        !d.Lam || !d.Amat || !d.gram_part || !d.cholf || !d.dxbits || !s.d_rfdx || !s.d_gate)
         return fail(CLOTH_E_OOM, "arena exhausted");
     return contact_layout(s, c, carve_fn);
 }
@@ -199,6 +207,8 @@ static size_t dry_footprint(const Scene& src) {
     s.nnz = src.nnz;
     s.nsell = src.nsell;
     s.r = src.r;
+    s.r_warm = src.r_warm;
+    s.bp_reuse = src.bp_reuse;
     s.iters_in = src.iters_in;
     s.iters_out = src.iters_out;
     s.prec = src.prec;
@@ -294,10 +304,27 @@ static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStrea
     Dev& d = s.d;
     int has_contact = (c.active && !linear) ? 1 : 0;
     if (k == 0 || !s.x4_valid) TIMED(K_MISC, launch_aos4(d.xk, d.x4, s.nv, st));
-    if (has_contact) TIMED(K_TARGETS, contact_prepare_iteration(s, c, force_k, st));
+    if (has_contact) {
+        TIMED(K_TARGETS, contact_prepare_iteration(s, c, force_k, st));
+        // fork: the contact matrix needs only the collision weights, fixed
+        // once the targets are; it is formed and factored on the side stream
+        // while the local step and U^T r0 run
+        HIPCHECK(hipEventRecord(s.ev_fork, st));
+        HIPCHECK(hipStreamWaitEvent(s.side, s.ev_fork, 0));
+        {
+            hipStream_t st_main = st;
+            st = s.side;
+            TIMED(K_GRAM_CHOL, contact_factor(s, c, force_k, st));
+            st = st_main;
+        }
+        HIPCHECK(hipEventRecord(s.ev_join, s.side));
+    }
     TIMED(K_LOCAL, launch_local_residual(d, s.prec, has_contact | (linear ? 2 : 0) | (force_k ? 4 : 0), st));
     TIMED(K_REDUCE, launch_reduce_solve(d, s.nblk, has_contact, c.gpart2, st));
-    if (has_contact) TIMED(K_GRAM_CHOL, contact_dynamic_solve(s, c, st));
+    if (has_contact) {
+        HIPCHECK(hipStreamWaitEvent(st, s.ev_join, 0));   // join
+        TIMED(K_CHOL_TRI, contact_solve(s, c, st));
+    }
     TIMED(K_EXPAND, launch_expand(d, s.prec, 0, st));
     float om = omega_override > 0 ? omega_override : s.omega[std::min(k, (int)s.omega.size() - 1)];
     TIMED(K_JACOBI, launch_jacobi_cheb(d, om, (float)s.gamma, has_contact, s.d.dxbits + slot,
@@ -316,14 +343,21 @@ static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStrea
 static cloth_status modal_iteration(cloth_scene_s* sc, hipStream_t st) {
     Scene& s = sc->s;
     ContactState& c = sc->c;
-    Dev& d = s.d;
+    // the warm-start basis when one is set (its own width and inverse
+    // Galerkin matrix; the work buffers are sized for the wider basis)
+    Dev d = s.d;
+    if (s.warm_set) {
+        d.U = s.d_Uw;
+        d.r = s.r_warm;
+        d.Ainv = s.d_Ainvw;
+    }
     TIMED(K_MISC, launch_aos4(d.xk, d.x4, s.nv, st));
     TIMED(K_LOCAL, launch_local_residual(d, s.prec, 0, st));
     TIMED(K_REDUCE, launch_reduce_solve(d, s.nblk, 0, c.gpart2, st));
     TIMED(K_EXPAND, launch_expand(d, s.prec, 1, st));
-    float* t = d.xk;
-    d.xk = d.xt;
-    d.xt = t;
+    float* t = s.d.xk;
+    s.d.xk = s.d.xt;
+    s.d.xt = t;
     s.x4_valid = false;
     return CLOTH_OK;
 }
@@ -405,6 +439,8 @@ cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_pa
     ds.nnz = nnz;
     ds.nsell = nsell;
     ds.r = params->r;
+    ds.r_warm = params->r_warm;
+    ds.bp_reuse = params->broad_reuse ? 1 : 0;
     ds.iters_in = std::max(1, params->iters_inner);
     ds.iters_out = std::max(1, params->iters_outer);
     ds.prec = params->precision;
@@ -423,6 +459,8 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
         return fail(CLOTH_E_INVALID, "r must be a multiple of 8 in [8, " + std::to_string(MAX_R) + "]");
     if (params->iters_inner <= 0 || params->iters_outer <= 0)
         return fail(CLOTH_E_INVALID, "iteration budgets must be positive");
+    if (params->r_warm != 0 && (params->r_warm < 8 || params->r_warm > MAX_R || params->r_warm % 8 != 0))
+        return fail(CLOTH_E_INVALID, "r_warm must be 0 or a multiple of 8 in [8, " + std::to_string(MAX_R) + "]");
     if (params->debug_tangles && !params->self_contact)
         return fail(CLOTH_E_INVALID, "the tangle check needs self contact on");
     if ((int64_t)params->iters_inner * params->iters_outer > 65536)
@@ -525,6 +563,10 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     HIPCHECK(hipMemset(s.d_rfdx, 0, sizeof(float) * 3 * n));
     cloth_status rc = contact_upload(s, sc->c);
     if (rc != CLOTH_OK) return rc;
+    // the step's second stream (default priority) and its fork / join events
+    HIPCHECK(hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
     HIPCHECK(hipDeviceSynchronize());
     *out = sc.release();
     return CLOTH_OK;
@@ -553,13 +595,13 @@ static cloth_status drop_graph(Scene& s) {
     return CLOTH_OK;
 }
 
-cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
-    if (!sc || !U) return fail(CLOTH_E_INVALID, "null argument");
-    Scene& s = sc->s;
-    if (drop_graph(s) != CLOTH_OK) return CLOTH_E_DEVICE;
-    if (r != s.r) return fail(CLOTH_E_INVALID, "basis width differs from params.r");
+// Rounds a basis U (nv x r FP64, row-major; pinned rows stored as zero) to
+// the storage precision into dst, keeps the stored values, and forms
+// L = U~^T H U~ in FP64 (symmetrised) and its inverse.
+static cloth_status store_basis(Scene& s, const double* U, int r, void* dst, std::vector<double>& Ustored,
+                                std::vector<double>& Lam, std::vector<double>& inv) {
     const int n = s.nv;
-    s.Ustored.assign((size_t)n * r, 0.0);
+    Ustored.assign((size_t)n * r, 0.0);
     std::vector<float> uf;
     std::vector<uint16_t> ub;
     if (s.prec == CLOTH_MIXED)
@@ -573,45 +615,54 @@ cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
             float f = (float)U[i];
             if (s.prec == CLOTH_MIXED) {
                 ub[i] = to_bf16(f);
-                s.Ustored[i] = bf16_to_f(ub[i]);
+                Ustored[i] = bf16_to_f(ub[i]);
             } else {
                 uf[i] = f;
-                s.Ustored[i] = f;
+                Ustored[i] = f;
             }
         }
     }
-    // Lambda~ = U~^T H U~ (FP64)
     std::vector<double> HU((size_t)n * r, 0.0);
 #pragma omp parallel for schedule(static)
     for (int v = 0; v < n; ++v) {
         double* out = &HU[(size_t)v * r];
         for (int j = s.rowptr[v]; j < s.rowptr[v + 1]; ++j) {
             double a = s.val[j];
-            const double* u = &s.Ustored[(size_t)s.col[j] * r];
+            const double* u = &Ustored[(size_t)s.col[j] * r];
             for (int c = 0; c < r; ++c) out[c] += a * u[c];
         }
     }
-    s.Lam.assign((size_t)r * r, 0.0);
+    Lam.assign((size_t)r * r, 0.0);
 #pragma omp parallel for schedule(static)
     for (int a = 0; a < r; ++a)
         for (int v = 0; v < n; ++v) {
-            double ua = s.Ustored[(size_t)v * r + a];
+            double ua = Ustored[(size_t)v * r + a];
             if (ua == 0.0) continue;
             const double* h = &HU[(size_t)v * r];
-            double* row = &s.Lam[(size_t)a * r];
+            double* row = &Lam[(size_t)a * r];
             for (int b = 0; b < r; ++b) row[b] += ua * h[b];
         }
     for (int a = 0; a < r; ++a)
         for (int b = a + 1; b < r; ++b) {
-            double m = 0.5 * (s.Lam[(size_t)a * r + b] + s.Lam[(size_t)b * r + a]);
-            s.Lam[(size_t)a * r + b] = s.Lam[(size_t)b * r + a] = m;
+            double m = 0.5 * (Lam[(size_t)a * r + b] + Lam[(size_t)b * r + a]);
+            Lam[(size_t)a * r + b] = Lam[(size_t)b * r + a] = m;
         }
-    std::vector<double> inv;
-    if (!spd_inverse(s.Lam, r, inv)) return fail(CLOTH_E_INVALID, "U~^T H U~ is not positive definite");
+    if (!spd_inverse(Lam, r, inv)) return fail(CLOTH_E_INVALID, "U~^T H U~ is not positive definite");
     if (s.prec == CLOTH_MIXED)
-        HIPCHECK(hipMemcpy(s.d_U, ub.data(), ub.size() * 2, hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(dst, ub.data(), ub.size() * 2, hipMemcpyHostToDevice));
     else
-        HIPCHECK(hipMemcpy(s.d_U, uf.data(), uf.size() * 4, hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(dst, uf.data(), uf.size() * 4, hipMemcpyHostToDevice));
+    return CLOTH_OK;
+}
+
+cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
+    if (!sc || !U) return fail(CLOTH_E_INVALID, "null argument");
+    Scene& s = sc->s;
+    if (drop_graph(s) != CLOTH_OK) return CLOTH_E_DEVICE;
+    if (r != s.r) return fail(CLOTH_E_INVALID, "basis width differs from params.r");
+    std::vector<double> inv;
+    cloth_status rc0 = store_basis(s, U, r, s.d_U, s.Ustored, s.Lam, inv);
+    if (rc0 != CLOTH_OK) return rc0;
     HIPCHECK(hipMemcpy(s.d.Ainv, inv.data(), sizeof(double) * r * r, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(s.d.Lam, s.Lam.data(), sizeof(double) * r * r, hipMemcpyHostToDevice));
     s.basis_set = true;
@@ -620,6 +671,20 @@ cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
         if (rc != CLOTH_OK) return rc;
     }
     s.omega = cheb_weights(std::max(s.iters_in, s.rf_iters), s.rho, s.delay);
+    return CLOTH_OK;
+}
+
+cloth_status cloth_set_warm_basis(cloth_scene sc, const double* U, int32_t r_warm) {
+    if (!sc || !U) return fail(CLOTH_E_INVALID, "null argument");
+    Scene& s = sc->s;
+    if (s.r_warm <= 0) return fail(CLOTH_E_INVALID, "the scene was created without a warm-start basis (r_warm)");
+    if (r_warm != s.r_warm) return fail(CLOTH_E_INVALID, "basis width differs from params.r_warm");
+    if (drop_graph(s) != CLOTH_OK) return CLOTH_E_DEVICE;
+    std::vector<double> stored, lam, inv;
+    cloth_status rc = store_basis(s, U, r_warm, s.d_Uw, stored, lam, inv);
+    if (rc != CLOTH_OK) return rc;
+    HIPCHECK(hipMemcpy(s.d_Ainvw, inv.data(), sizeof(double) * r_warm * r_warm, hipMemcpyHostToDevice));
+    s.warm_set = true;
     return CLOTH_OK;
 }
 
@@ -840,15 +905,19 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
 
 // Records one step's launches into a graph (every count the kernels need is
 // read from device memory, so the launch sequence of a step never changes).
-static cloth_status capture_step(cloth_scene sc, const float g[3]) {
+}  // extern "C"
+
+namespace cloth {
+// Records one step's launches (with gravity g) into a new graph.
+cloth_status record_step_graph(cloth_scene_s* sc, const float g[3], hipGraph_t* out) {
     Scene& s = sc->s;
+    *out = nullptr;
     if (!s.cap_stream) HIPCHECK(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
-    if (s.graph_exec) {
-        HIPCHECK(hipGraphExecDestroy(s.graph_exec));
-        s.graph_exec = nullptr;
-    }
     HIPCHECK(hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal));
+    const bool timing = s.timing;
+    s.timing = false;   // no timing events inside a graph
     cloth_status rc = step_enqueue(sc, g, s.cap_stream);
+    s.timing = timing;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s.cap_stream, &graph);
     if (rc != CLOTH_OK) {
@@ -856,7 +925,23 @@ static cloth_status capture_step(cloth_scene sc, const float g[3]) {
         return rc;
     }
     if (e != hipSuccess) return fail(CLOTH_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&s.graph_exec, graph, nullptr, nullptr, 0);
+    *out = graph;
+    return CLOTH_OK;
+}
+}  // namespace cloth
+
+extern "C" {
+
+static cloth_status capture_step(cloth_scene sc, const float g[3]) {
+    Scene& s = sc->s;
+    if (s.graph_exec) {
+        HIPCHECK(hipGraphExecDestroy(s.graph_exec));
+        s.graph_exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    cloth_status rc = record_step_graph(sc, g, &graph);
+    if (rc != CLOTH_OK) return rc;
+    hipError_t e = hipGraphInstantiate(&s.graph_exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(CLOTH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     for (int i = 0; i < 3; ++i) s.graph_g[i] = g[i];
@@ -1001,6 +1086,9 @@ cloth_status cloth_destroy(cloth_scene sc) {
     if (sc->s.graph_exec) (void)hipGraphExecDestroy(sc->s.graph_exec);
     if (sc->s.cap_stream) (void)hipStreamDestroy(sc->s.cap_stream);
     for (hipEvent_t e : sc->s.ev_pool) (void)hipEventDestroy(e);
+    if (sc->s.ev_fork) (void)hipEventDestroy(sc->s.ev_fork);
+    if (sc->s.ev_join) (void)hipEventDestroy(sc->s.ev_join);
+    if (sc->s.side) (void)hipStreamDestroy(sc->s.side);
     contact_destroy(sc->s, sc->c);
     if (sc->s.arena_owned) (void)hipFree(sc->s.arena);
     delete sc;

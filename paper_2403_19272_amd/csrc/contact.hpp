@@ -44,6 +44,13 @@ struct ContactState {
     float* bpart = nullptr;   // per-block box extents
     BpGrid* grid = nullptr;   // [0] triangles, [1] edges
     float4 *xm4 = nullptr, *xp4 = nullptr;   // AoS copies of the stage's two positions (TOI gathers)
+    // reusable candidate superset: grown boxes, its sorted pairs, its words
+    // (see k_sup_gate) and the growth margins
+    float *svbox = nullptr, *stbox = nullptr, *sebox = nullptr;
+    int2 *sup_vt = nullptr, *sup_ee = nullptr;
+    int* supw = nullptr;
+    double sup_mu0 = 0.0, sup_kappa = 1.0;
+    bool sup_on = false;   // candidate lists filtered from the superset (else queried per stage)
 
     // candidates
     int* vcount = nullptr;  // per vertex VT counts, then offsets (nv+1)
@@ -62,6 +69,7 @@ struct ContactState {
     int* ob_a = nullptr;         // MAX_OBST * nv, -1 = not a member
     int* cvlist = nullptr;       // contact vertices (for the Gram)
     int *cvflag = nullptr, *cvofs = nullptr;
+    float* Wc = nullptr;         // collision weight of each contact vertex (cvlist order)
     ObstD* ob_dev = nullptr;     // device copy of ob[]
 
     // device scalars: [0] n_vt cand, [1] n_ee cand, [2] n_cvt, [3] n_cee,
@@ -93,7 +101,10 @@ bool contact_enabled(const Scene& s, const ContactState& c);
 cloth_status contact_step_begin(Scene& s, ContactState& c, const float* xp, hipStream_t st);
 cloth_status contact_block_begin(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, hipStream_t st);
-cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st);
+// the contact matrix and its factorization (needs only the weights: may
+// run beside the local step), then q = A^{-1} g on it
+cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t st);
+cloth_status contact_solve(Scene& s, ContactState& c, hipStream_t st);
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st);
 // dxo: slot of the change of x over the block (the outer loop condition)
 cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, unsigned long long* dxo, hipStream_t st);

@@ -686,12 +686,15 @@ __global__ void k_aos_pair(const int* __restrict__ gate, int n, const float* __r
 // Swept boxes over (xm, xp) grown by dhat (FP32); per block the box
 // statistics of the triangle and edge boxes (reduced by k_grid).
 __global__ void __launch_bounds__(256) k_boxes(Dev d, const float4* __restrict__ xm4, const float4* __restrict__ xp4,
-                                               float dhat, float* vbox, float* tbox, float* ebox, float* bpart) {
+                                               float dhat, float* vbox, float* tbox, float* ebox, float* bpart,
+                                               const float* __restrict__ svbox, const float* __restrict__ stbox,
+                                               const float* __restrict__ sebox, int* escaped) {
     if (gated(d.gate)) return;
     __shared__ float red[4][BP_PART];
     const int total = d.nv + d.nt + d.ne;
     float acc[BP_PART];
     for (int k = 0; k < BP_PART; ++k) acc[k] = bp_identity(bp_op(k));
+    bool esc = false;   // a box not inside its reusable-list box (escaped != null)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         int ids[3];
         int nvert;
@@ -717,6 +720,10 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float4* __restrict__
             out = ebox + 6 * (size_t)e;
             kind = 2;
         }
+        const float* sb = !escaped ? nullptr
+                          : kind == 0 ? svbox + 6 * (size_t)i
+                          : kind == 1 ? stbox + 6 * (size_t)(i - d.nv)
+                                      : sebox + 6 * (size_t)(i - d.nv - d.nt);
         // the corners' two positions, one 16-byte load each
         float pa[3][3], pb[3][3];
         for (int k = 0; k < nvert; ++k) {
@@ -732,6 +739,130 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float4* __restrict__
                 hi = fmaxf(hi, fmaxf(a, b));
             }
             float l = lo - dhat, h = hi + dhat;
+            out[c] = l;
+            out[3 + c] = h;
+            if (sb) esc |= !(l >= sb[c] && h <= sb[3 + c]);
+            if (kind) {
+                const int f = (kind - 1) * BP_FAM;
+                acc[f + c] = fmaxf(acc[f + c], h - l);
+                acc[f + 3 + c] = fminf(acc[f + 3 + c], l);
+                acc[f + 6 + c] = fmaxf(acc[f + 6 + c], h);
+                acc[f + 9 + c] += h - l;
+            }
+        }
+    }
+    if (escaped && __ballot(esc) && (threadIdx.x & 63) == 0) *escaped = 1;
+    for (int k = 0; k < BP_PART; ++k) {
+        const int op = bp_op(k);
+        float w = acc[k];
+        for (int o = 32; o > 0; o >>= 1) w = bp_combine(op, w, __shfl_xor(w, o));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < BP_PART) {
+        const int k = threadIdx.x, op = bp_op(k);
+        float w = red[0][k];
+        for (int q = 1; q < 4; ++q) w = bp_combine(op, w, red[q][k]);
+        bpart[(size_t)blockIdx.x * BP_PART + k] = w;
+    }
+}
+
+// ---------------------------------------------------------- reusable lists
+// The candidate lists of a stage are taken from a superset built on boxes
+// grown by a margin, kept for as long as every stage box stays inside its
+// grown box: then every pair whose stage boxes overlap has overlapping grown
+// boxes and is in the superset, and filtering the (sorted) superset by the
+// stage boxes gives exactly the sorted candidate lists.  The superset is
+// rebuilt when a box leaves its grown box (checked in k_boxes).
+// A superset on grown boxes can outgrow a capacity (a violent stage) where
+// the candidate lists themselves fit: the rebuild is then done again at
+// once on the stage boxes themselves (no margin).
+// Words of ContactState::supw: [0] / [1] VT / EE superset sizes, [2] rebuild
+// needed, [3] rebuilds since the last stats read, [4] superset size (VT +
+// EE), [5] gate of the rebuild launches (1 = skip), [6] the gate of the
+// stage (1 = skip) for the filter, [7] 1 = build without margins, [8] the
+// step's overflow bits before the rebuild, [9] gate of the retry.
+
+// gate of the rebuild: skipped when the stage is or the superset stands
+__global__ void k_sup_gate(const int* __restrict__ stage_gate, int* supw, const int* __restrict__ cnt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int skip_stage = gated(stage_gate) ? 1 : 0;
+        supw[5] = (skip_stage || !supw[2]) ? 1 : 0;
+        supw[6] = skip_stage;
+        supw[7] = 0;
+        supw[8] = cnt[7];
+        supw[9] = 1;
+    }
+}
+
+// after the first rebuild: if it overflowed, forget those overflow bits and
+// open the retry without margins
+__global__ void k_sup_retry(int* supw, int* cnt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int mask = OVF_QUERY | OVF_CELL | OVF_LIST;
+        if (!supw[5] && (cnt[7] & mask & ~supw[8])) {
+            cnt[7] = supw[8];
+            supw[7] = 1;
+            supw[9] = 0;
+        }
+    }
+}
+
+// grown boxes: the stage box widened along axis c by min(mu0 + kappa m_c,
+// 16 mu0), m_c the largest change of coordinate c of the primitive's corners
+// over the stage, so that a box grows along its motion (a falling sheet
+// keeps its neighbours in the plane) and the cap bounds the superset of a
+// violent stage; per block the statistics of the grown triangle and edge
+// boxes (for k_grid)
+__global__ void __launch_bounds__(256) k_sup_grow(Dev d, const float4* __restrict__ xm4, const float4* __restrict__ xp4,
+                                                  const float* __restrict__ vbox, const float* __restrict__ tbox,
+                                                  const float* __restrict__ ebox, float* svbox, float* stbox,
+                                                  float* sebox, float* bpart, float mu0, float kappa,
+                                                  const int* __restrict__ exact) {
+    if (gated(d.gate)) return;
+    if (*exact) mu0 = kappa = 0.f;
+    __shared__ float red[4][BP_PART];
+    const int total = d.nv + d.nt + d.ne;
+    float acc[BP_PART];
+    for (int k = 0; k < BP_PART; ++k) acc[k] = bp_identity(bp_op(k));
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        int ids[3];
+        int nvert, kind;
+        const float* in;
+        float* out;
+        if (i < d.nv) {
+            ids[0] = i;
+            nvert = 1;
+            kind = 0;
+            in = vbox + 6 * (size_t)i;
+            out = svbox + 6 * (size_t)i;
+        } else if (i < d.nv + d.nt) {
+            const int t = i - d.nv;
+            const TriRec tr = d.tri[t];
+            ids[0] = tr.v0; ids[1] = tr.v1; ids[2] = tr.v2;
+            nvert = 3;
+            kind = 1;
+            in = tbox + 6 * (size_t)t;
+            out = stbox + 6 * (size_t)t;
+        } else {
+            const int e = i - d.nv - d.nt;
+            ids[0] = d.edges[2 * e];
+            ids[1] = d.edges[2 * e + 1];
+            nvert = 2;
+            kind = 2;
+            in = ebox + 6 * (size_t)e;
+            out = sebox + 6 * (size_t)e;
+        }
+        float m[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < nvert; ++k) {
+            const float4 a = xm4[ids[k]], b = xp4[ids[k]];
+            m[0] = fmaxf(m[0], fabsf(b.x - a.x));
+            m[1] = fmaxf(m[1], fabsf(b.y - a.y));
+            m[2] = fmaxf(m[2], fabsf(b.z - a.z));
+        }
+        for (int c = 0; c < 3; ++c) {
+            const float mu = fminf(mu0 + kappa * m[c], 16.f * mu0);
+            const float l = in[c] - mu, h = in[3 + c] + mu;
             out[c] = l;
             out[3 + c] = h;
             if (kind) {
@@ -755,6 +886,93 @@ __global__ void __launch_bounds__(256) k_boxes(Dev d, const float4* __restrict__
         float w = red[0][k];
         for (int q = 1; q < 4; ++q) w = bp_combine(op, w, red[q][k]);
         bpart[(size_t)blockIdx.x * BP_PART + k] = w;
+    }
+}
+
+// after a rebuild: the superset stands unless a list overflowed (then the
+// next stage rebuilds again)
+__global__ void k_sup_done(const int* __restrict__ gate, int* supw, const int* __restrict__ cnt) {
+    if (gated(gate)) return;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        supw[2] = (cnt[7] & (OVF_QUERY | OVF_CELL | OVF_LIST)) ? 1 : 0;
+        supw[3] += 1;
+    }
+}
+
+__device__ __forceinline__ bool boxes_overlap(const float* a, const float* b) {
+    return !(a[0] > b[3] || b[0] > a[3] || a[1] > b[4] || b[1] > a[4] || a[2] > b[5] || b[2] > a[5]);
+}
+
+// keep[i] = 1 for the superset pairs (VT, then EE) whose stage boxes overlap
+// (ids outside the mesh, possible only in a list cut short by an overflow,
+// are dropped)
+__global__ void __launch_bounds__(256) k_sup_filter(int* supw, const int2* __restrict__ svt,
+                                                    const int2* __restrict__ see, const float* __restrict__ vbox,
+                                                    const float* __restrict__ tbox, const float* __restrict__ ebox,
+                                                    int nv, int nt, int ne, int* keep) {
+    if (supw[6]) return;
+    const int nvt = supw[0], tot = supw[0] + supw[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) supw[4] = tot;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x) {
+        bool k;
+        if (i < nvt) {
+            const int2 p = svt[i];
+            k = (unsigned)p.x < (unsigned)nv && (unsigned)p.y < (unsigned)nt &&
+                boxes_overlap(vbox + 6 * (size_t)p.x, tbox + 6 * (size_t)p.y);
+        } else {
+            const int2 p = see[i - nvt];
+            k = (unsigned)p.x < (unsigned)ne && (unsigned)p.y < (unsigned)ne &&
+                boxes_overlap(ebox + 6 * (size_t)p.x, ebox + 6 * (size_t)p.y);
+        }
+        keep[i] = k ? 1 : 0;
+    }
+}
+
+// the kept pairs to the candidate lists (order kept), their counts in
+// cnt[0], cnt[1] and the largest list in the peak slot; a list longer than
+// the candidate capacity is cut there and flagged (the step then fails)
+__global__ void __launch_bounds__(256) k_sup_compact(const int* __restrict__ supw, const int2* __restrict__ svt,
+                                                     const int2* __restrict__ see, const int* __restrict__ keep,
+                                                     const int* __restrict__ ofs, int2* cvt, int2* cee, int* cnt,
+                                                     int64_t cap) {
+    if (supw[6]) return;
+    const int nvt = supw[0], tot = supw[0] + supw[1];
+    const int kvt = nvt > 0 ? ofs[nvt - 1] + keep[nvt - 1] : 0;
+    const int kall = tot > 0 ? ofs[tot - 1] + keep[tot - 1] : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int kee = kall - kvt;
+        cnt[PEAK_SLOT] = max(cnt[PEAK_SLOT], max(kvt, kee));
+        if (kvt > cap || kee > cap) atomicOr(&cnt[7], OVF_LIST);
+        cnt[0] = (int)min((int64_t)kvt, cap);
+        cnt[1] = (int)min((int64_t)kee, cap);
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x) {
+        if (!keep[i]) continue;
+        if (i < nvt) {
+            if (ofs[i] < cap) cvt[ofs[i]] = svt[i];
+        } else if (ofs[i] - kvt < cap) {
+            cee[ofs[i] - kvt] = see[i - nvt];
+        }
+    }
+}
+
+// per-query offsets of the candidate lists: the first entry of query q
+// (lists sorted by query), for the vertices and then the edges
+__global__ void __launch_bounds__(256) k_query_ofs(const int* __restrict__ supw, const int* __restrict__ cnt,
+                                                   const int2* __restrict__ cvt, const int2* __restrict__ cee, int nv,
+                                                   int ne, int* vofs, int* eofs) {
+    if (supw[6]) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv + ne; i += gridDim.x * blockDim.x) {
+        const bool vt = i < nv;
+        const int q = vt ? i : i - nv;
+        const int2* list = vt ? cvt : cee;
+        int lo = 0, hi = vt ? cnt[0] : cnt[1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (list[mid].x < q) lo = mid + 1;
+            else hi = mid;
+        }
+        (vt ? vofs : eofs)[q] = lo;
     }
 }
 
@@ -1451,11 +1669,15 @@ __global__ void __launch_bounds__(256) k_slot_sort(Dev d, const int* __restrict_
     }
 }
 
-__global__ void k_cv_compact(const int* __restrict__ gate, int n, const int* __restrict__ flag, const int* __restrict__ ofs, int* list, int* n_out) {
+__global__ void k_cv_compact(const int* __restrict__ gate, int n, const int* __restrict__ flag, const int* __restrict__ ofs, int* list, int* n_out,
+                             int* wchg) {
     if (gated(gate)) return;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
         if (flag[v]) list[ofs[v]] = v;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = n > 0 ? ofs[n - 1] + flag[n - 1] : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *n_out = n > 0 ? ofs[n - 1] + flag[n - 1] : 0;
+        *wchg = 1;   // a new constraint set: refactor
+    }
 }
 
 // ================================================================ per iteration
@@ -1505,8 +1727,10 @@ __global__ void __launch_bounds__(256) k_pair_targets(Dev d, const int* cnt, con
 // (three fixed samples plus the frozen closest point); a <- active ?
 // min(a+1, a_max) : 0.  Obstacles: active when phi(x^{k+1}) < d_hat.
 __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cpair, int* ca,
-                              const double2* __restrict__ clam, int amax, const float* __restrict__ xnew) {
+                              const double2* __restrict__ clam, int amax, const float* __restrict__ xnew,
+                              int* wchg) {
     if (gated(d.gate)) return;
+    bool changed = false;
     const int nob = d.nob;
     const ObstD* ob = d.ob;
     int* ob_a = d.ob_a;
@@ -1553,8 +1777,9 @@ __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, cons
                 }
                 act |= dot(a1, a0) <= 0.0;
             }
-            int a = ca[p];
-            ca[p] = act ? min(a + 1, amax) : 0;
+            const int a = ca[p], na = act ? min(a + 1, amax) : 0;
+            ca[p] = na;
+            changed |= na != a;
         } else {
             int v = p - nc;
             d3 x = ld3(xnew, n, v);
@@ -1564,10 +1789,13 @@ __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, cons
                 d3 rv;
                 double rad;
                 bool act = obst_phi(ob[j], x, rv, rad) < dhat;
-                ob_a[(size_t)j * n + v] = act ? min(a + 1, amax) : 0;
+                const int na = act ? min(a + 1, amax) : 0;
+                ob_a[(size_t)j * n + v] = na;
+                changed |= na != a;
             }
         }
     }
+    if (__ballot(changed) && (threadIdx.x & 63) == 0) *wchg = 1;
 }
 
 // Eight consecutive basis entries of a row (16 bytes of BF16 or 32 of FP32)
@@ -1616,11 +1844,33 @@ __device__ __forceinline__ int gram_per_chunk(int ncv, int nchunk) {
 // l / 16 + 4 e (e = 0..3) of column l % 16 of the tile.  Vertices are staged 32
 // at a time in LDS as W-scaled (FP64) and plain (FP32) rows.
 constexpr int GRAM_TW = 10;   // 16 x 16 FP64 tiles per wavefront
+// Collision weight W_v of each contact vertex (the Gram's rows), summed as
+// the local step sums it (pair slots in slot order, then obstacles), so that
+// the contact matrix can be formed while the local step runs.
+__global__ void __launch_bounds__(256) k_contact_w(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
+                                                   float* Wc, int force_k) {
+    if (gated(d.gate)) return;
+    const int ncv = *n_cv, n = d.nv;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncv; i += gridDim.x * blockDim.x) {
+        const int v = cvlist[i];
+        float Wv = 0.f;
+        for (int j = d.vslot_ptr[v], e = d.vslot_ptr[v + 1]; j < e; ++j) Wv += d.slot[d.vslot[j]].x;
+        for (int j = 0; j < d.nob; ++j) {
+            int a = d.ob_a[j * n + v];
+            if (a < 0) continue;
+            if (force_k) a = 0;
+            Wv += (d.Kb == 2.0f) ? ldexpf(d.kc, a) : d.kc * powf(d.Kb, (float)a);
+        }
+        Wc[i] = Wv;
+    }
+}
+
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
 template <typename UT>
 __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
-                                            int nchunk, double* part) {
-    if (gated(d.gate)) return;
+                                            int nchunk, double* part, const int* __restrict__ wchg,
+                                            const float* __restrict__ Wc) {
+    if (gated(d.gate) || !*wchg) return;   // no weight changed: the last factorization stands
     constexpr int VB = 32;   // contact vertices staged per round (a multiple of 4)
     __shared__ float us[VB][MAX_R];
     __shared__ double ws[VB][MAX_R];
@@ -1667,7 +1917,7 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
         if (threadIdx.x < VB) {
             const int v = threadIdx.x < m ? cvlist[base + threadIdx.x] : -1;
             vidx[threadIdx.x] = v;
-            wv[threadIdx.x] = v >= 0 ? d.W[v] : 0.f;
+            wv[threadIdx.x] = v >= 0 ? Wc[base + threadIdx.x] : 0.f;
         }
         __syncthreads();
         for (int q = threadIdx.x; q < VB * ncg16; q += 256) {
@@ -1729,8 +1979,9 @@ __device__ __forceinline__ void pk_entry(int e, int r, int& i, int& k) {
 // partials hold the upper block triangle: A(i, k) = part(k, i) for k <= i.
 constexpr int GRAM_GROUPS = GRAM_GROUPS_MAX;
 __global__ void __launch_bounds__(256) k_gram_reduce(Dev d, const double* __restrict__ part, int nchunk,
-                                                     const int* __restrict__ n_cv, double* __restrict__ gred) {
-    if (gated(d.gate)) return;
+                                                     const int* __restrict__ n_cv, double* __restrict__ gred,
+                                                     const int* __restrict__ wchg) {
+    if (gated(d.gate) || !*wchg) return;
     const int r = d.r;
     const int ncv = *n_cv;
     if (ncv == 0) return;
@@ -1761,8 +2012,9 @@ __device__ __forceinline__ void tri_rc(int e, int& i, int& j) {
 
 // A = Lambda~ + the group sums, packed row-major (second reduction level).
 __global__ void __launch_bounds__(256) k_gram_final(Dev d, const double* __restrict__ gred,
-                                                    const int* __restrict__ n_cv, double* __restrict__ Arm) {
-    if (gated(d.gate)) return;
+                                                    const int* __restrict__ n_cv, double* __restrict__ Arm,
+                                                    const int* __restrict__ wchg) {
+    if (gated(d.gate) || !*wchg) return;
     if (*n_cv == 0) return;
     const int r = d.r;
     const int tot = r * (r + 1) / 2;
@@ -1957,20 +2209,43 @@ __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* 
     }
 }
 
-// q = A^{-1} g for the three coordinates (Eq. (subspace_collision)), in one
-// workgroup.  A = Lambda~ + U_C^T diag(W) U_C (packed row-major, from
-// k_gram_final) is factored in LDS as A = L D L^T without square roots: at
+// The contact matrix A = Lambda~ + U_C^T diag(W) U_C (packed row-major, from
+// k_gram_final) factored in LDS as A = L D L^T without square roots: at
 // elimination step k, A(i, j) -= A(i, k) A(j, k) / A(k, k) for k < j <= i,
 // so that afterwards L(i, k) = A(i, k) / A(k, k) and D = diag(A).  The
 // elimination goes by panels of 16 columns with three barriers each
-// (chol_panel), then three wavefronts solve on the factor in LDS (chol_tri).
-// Without contact vertices A = Lambda~, whose precomputed inverse is
-// applied instead.
+// (chol_panel); the factor and 1 / D are kept in d.cholf for k_chol_tri.
+// Skipped when no collision weight changed since the last factorization
+// (wchg clear): the kept factor is still that of A.
+__global__ void __launch_bounds__(1024) k_chol_factor(Dev d, const double* __restrict__ Arm,
+                                                      const int* __restrict__ n_cv, int* wchg, int* nfact) {
+    if (gated(d.gate)) return;
+    if (*n_cv == 0 || *wchg == 0) return;
+    extern __shared__ double A[];
+    const int r = d.r;
+    const int tid = threadIdx.x;
+    const int tot = r * (r + 1) / 2;
+    double* dinv = A + tot;   // 1 / A(k, k) once column k is final
+    for (int e = tid; e < tot; e += 1024) A[e] = Arm[e];
+    __syncthreads();
+    int p0 = 0;
+    for (; p0 + CHOL_PANEL <= r; p0 += CHOL_PANEL) chol_panel<CHOL_PANEL>(A, dinv, r, p0, tid);
+    if (p0 < r) chol_panel<CHOL_PANEL / 2>(A, dinv, r, p0, tid);   // r is a multiple of 8
+    for (int e = tid; e < tot + r; e += 1024) d.cholf[e] = A[e];
+    if (tid == 0) {
+        *wchg = 0;   // every thread read the flag before the first barrier above
+        atomicAdd(nfact, 1);
+    }
+}
+
+// q = A^{-1} g for the three coordinates (Eq. (subspace_collision)), in one
+// workgroup: three wavefronts solve on the kept factor (chol_tri), loaded
+// into LDS.  Without contact vertices A = Lambda~, whose precomputed inverse
+// is applied instead.
 // NS: row slots of the solve, 2 for r <= 128 and 3 up to MAX_R (chosen on
 // the host; one instantiation per kernel keeps it within 128 VGPRs).
 template <int NS>
-__global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __restrict__ Arm,
-                                                     const double* __restrict__ g, const int* __restrict__ n_cv) {
+__global__ void __launch_bounds__(1024) k_chol_tri(Dev d, const double* __restrict__ g, const int* __restrict__ n_cv) {
     if (gated(d.gate)) return;
     extern __shared__ double A[];
     const int r = d.r;
@@ -2025,14 +2300,11 @@ __global__ void __launch_bounds__(1024) k_chol_solve(Dev d, const double* __rest
         return;
     }
     const int tot = r * (r + 1) / 2;
-    double* dinv = A + tot;   // 1 / A(k, k) once column k is final
-    for (int e = tid; e < tot; e += 1024) A[e] = Arm[e];
+    double* dinv = A + tot;
     const int zs = tot + r;   // a zero entry for the solves
+    for (int e = tid; e < tot + r; e += 1024) A[e] = d.cholf[e];
     if (tid == 0) A[zs] = 0.0;
     __syncthreads();
-    int p0 = 0;
-    for (; p0 + CHOL_PANEL <= r; p0 += CHOL_PANEL) chol_panel<CHOL_PANEL>(A, dinv, r, p0, tid);
-    if (p0 < r) chol_panel<CHOL_PANEL / 2>(A, dinv, r, p0, tid);   // r is a multiple of 8
     if (wave >= 3) return;   // wavefront c solves for coordinate c
     chol_tri<NS>(d, A, dinv, g, r, lane, wave, zs);
 }
@@ -2169,11 +2441,15 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.hash_p = P;
     // per-query output bound: the int prefix sums over queries cannot overflow
     c.max_out = (int)std::min<int64_t>(1024, (int64_t)0x7fffffff / std::max<int64_t>(1, std::max(n, s.ne)) - 1);
-    int64_t maxscan = std::max<int64_t>({2 * c.cap, (int64_t)n + 1, (int64_t)s.ne + 1, (int64_t)P + 1});
+    // (the largest scan: the keep flags over both candidate lists, or with
+    // the reusable superset over both superset lists)
+    const int64_t kmul = s.bp_reuse ? 4 : 2;
+    int64_t maxscan = std::max<int64_t>({kmul * c.cap, (int64_t)n + 1, (int64_t)s.ne + 1, (int64_t)P + 1});
     c.ntiles_cap = (int)((maxscan + SCAN_TILE - 1) / SCAN_TILE) + 1;
     auto I = [&](size_t k) { return static_cast<int*>(carve(sizeof(int) * k)); };
-    c.gpart2 = static_cast<double*>(carve(sizeof(double) * ((size_t)(s.nblk + 31) / 32 + 1) * s.r * 3));
-    c.gvec = static_cast<double*>(carve(sizeof(double) * s.r * 3));
+    const int rw = std::max(s.r, s.r_warm);   // the warm-start basis may be wider
+    c.gpart2 = static_cast<double*>(carve(sizeof(double) * ((size_t)(s.nblk + 31) / 32 + 1) * rw * 3));
+    c.gvec = static_cast<double*>(carve(sizeof(double) * rw * 3));
     c.cnt = I(CNT_WORDS);
     c.tmin_bits = static_cast<unsigned long long*>(carve(32));
     c.tpart = static_cast<double*>(carve(sizeof(double) * 2 * GRID_LOOP));
@@ -2217,10 +2493,22 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.ecount = I((size_t)s.ne + 1);
     c.cand_vt = static_cast<int2*>(carve(sizeof(int2) * pc));
     c.cand_ee = static_cast<int2*>(carve(sizeof(int2) * pc));
+    // the reusable superset (only when used): grown boxes and lists of twice
+    // the candidate capacity
+    const bool sup = s.self_contact && s.bp_reuse;
+    c.svbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(sup ? n : 1)));
+    c.stbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(sup ? s.nt : 1)));
+    c.sebox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(sup ? s.ne : 1)));
+    c.sup_vt = static_cast<int2*>(carve(sizeof(int2) * (sup ? 2 * pc : 1)));
+    c.sup_ee = static_cast<int2*>(carve(sizeof(int2) * (sup ? 2 * pc : 1)));
+    c.supw = I(16);
+    c.sup_mu0 = s.bp_mu0;
+    c.sup_kappa = s.bp_kappa;
+    c.sup_on = s.bp_reuse != 0;
     c.toi_vt = static_cast<double*>(carve(sizeof(double) * pc));
     c.toi_ee = static_cast<double*>(carve(sizeof(double) * pc));
-    c.keep = I(std::max<int64_t>(2 * pc, (int64_t)std::max(n, s.ne) + 1));
-    c.keep_ofs = I(2 * pc);
+    c.keep = I(std::max<int64_t>((sup ? 4 : 2) * pc, (int64_t)std::max(n, s.ne) + 1));
+    c.keep_ofs = I((sup ? 4 : 2) * pc);
     c.cand_a = I(2 * pc);
     c.cpair = static_cast<int2*>(carve(sizeof(int2) * cc));
     c.cpair_prev = static_cast<int2*>(carve(sizeof(int2) * cc));
@@ -2235,11 +2523,12 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.cvlist = I((size_t)n + 1);
     c.cvflag = I((size_t)n + 1);
     c.cvofs = I((size_t)n + 1);
+    c.Wc = static_cast<float*>(carve(sizeof(float) * ((size_t)n + 1)));
     if (!c.vbox || !c.tbox || !c.ebox || !c.bucket_cnt || !c.bucket_ptr || !c.rec || !c.qscratch || !c.heavy_q ||
         !c.bpart || !c.grid || !c.xm4 || !c.xp4 || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
         !c.toi_ee || !c.keep || !c.keep_ofs || !c.cand_a || !c.cpair || !c.cpair_prev || !c.ca ||
         !c.ca_prev || !c.clam || !c.cnrm || !c.slot || !c.vslot_ptr || !c.vslot_fill || !c.vslot || !c.cvlist ||
-        !c.cvflag || !c.cvofs)
+        !c.cvflag || !c.cvofs || !c.Wc || !c.svbox || !c.stbox || !c.sebox || !c.sup_vt || !c.sup_ee || !c.supw)
         return set_error(CLOTH_E_OOM, "arena exhausted (contact buffers)");
     d.vslot_ptr = c.vslot_ptr;
     d.vslot = c.vslot;
@@ -2251,15 +2540,20 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
 cloth_status contact_upload(Scene& s, ContactState& c) {
     const int n = s.nv;
     HC(hipMemset(c.cnt, 0, sizeof(int) * CNT_WORDS));
+    // no superset yet: the first stage builds it
+    const int supw0[16] = {0, 0, 1};
+    HC(hipMemcpy(c.supw, supw0, sizeof(supw0), hipMemcpyHostToDevice));
     HC(hipMemset(c.ob_a, 0xff, sizeof(int) * (size_t)MAX_OBST * n));
     std::vector<unsigned long long> tb(4, 0x4000000000000000ull);  // 2.0
     HC(hipMemcpy(c.tmin_bits, tb.data(), 32, hipMemcpyHostToDevice));
     double one = 1.0;
     HC(hipMemcpy(c.s_dev, &one, 8, hipMemcpyHostToDevice));
     HC(hipMemset(c.vslot_ptr, 0, sizeof(int) * (n + 1)));
-    HC(hipFuncSetAttribute((const void*)k_chol_solve<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HC(hipFuncSetAttribute((const void*)k_chol_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
                            (int)chol_lds_bytes(s.r)));
-    HC(hipFuncSetAttribute((const void*)k_chol_solve<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HC(hipFuncSetAttribute((const void*)k_chol_tri<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)chol_lds_bytes(s.r)));
+    HC(hipFuncSetAttribute((const void*)k_chol_tri<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
                            (int)chol_lds_bytes(s.r)));
     return CLOTH_OK;
 }
@@ -2274,7 +2568,8 @@ cloth_status contact_set_obstacles(Scene& s, ContactState& c) {
 }
 
 // Boxes of the vertices, triangles and edges over (xm, xp) grown by dhat,
-// and the cell sizes of the two target families.
+// and the cell sizes of the two target families (the tangle check's boxes:
+// no reusable-list check).
 static void bp_boxes(Scene& s, ContactState& c, const float* xm, const float* xp, float dhat, hipStream_t st) {
     Dev& d = s.d;
     const int n = s.nv;
@@ -2282,17 +2577,17 @@ static void bp_boxes(Scene& s, ContactState& c, const float* xm, const float* xp
     // AoS copies of the two positions, for the corner gathers of the boxes and the TOI
     hipLaunchKernelGGL(k_aos_pair, dim3(gblocks(n)), dim3(TPB), 0, st, s.d.gate, n, xm, xp, c.xm4, c.xp4);
     hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
-                       dhat, c.vbox, c.tbox, c.ebox, c.bpart);
+                       dhat, c.vbox, c.tbox, c.ebox, c.bpart, (const float*)nullptr, (const float*)nullptr,
+                       (const float*)nullptr, (int*)nullptr);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, s.d.gate, (const float*)c.bpart, nbb, s.nt, s.ne, c.grid);
 }
 
-// Files the targets of one family (vt: triangles, else edges) in the cell
-// buckets: counts, bucket offsets, inline records.
-static cloth_status bp_file_targets(Scene& s, ContactState& c, bool vt, hipStream_t st) {
+// Files the targets of one family (vt: triangles, else edges; boxes tb) in
+// the cell buckets: counts, bucket offsets, inline records.
+static cloth_status bp_file_targets(Scene& s, ContactState& c, bool vt, const float* tb, hipStream_t st) {
     Dev& d = s.d;
     const int P = c.hash_p;
     const int m = vt ? s.nt : s.ne;
-    const float* tb = vt ? c.tbox : c.ebox;
     const BpGrid* g = c.grid + (vt ? 0 : 1);
     hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(P + 1)), dim3(TPB), 0, st, s.d.gate, c.bucket_cnt, 0, P + 1);
     hipLaunchKernelGGL(k_cells, dim3(gblocks(m)), dim3(TPB), 0, st, s.d.gate, m, tb, g, c.bucket_cnt, P, c.cnt + 7);
@@ -2303,22 +2598,26 @@ static cloth_status bp_file_targets(Scene& s, ContactState& c, bool vt, hipStrea
     return CLOTH_OK;
 }
 
-// Broad phase on (xm, xp) -> sorted candidates, counts in cnt[0], cnt[1].
-static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, const float* xp, hipStream_t st) {
-    if (!s.self_contact) return CLOTH_OK;
+// Sorted VT and EE pairs of the boxes (vb: vertices, tb: triangles, eb:
+// edges) that overlap, into out_vt / out_ee with their counts in n_out[0],
+// n_out[1]; per-query offsets in c.vcount / c.ecount.  The grid comes from
+// the box statistics in c.bpart.  Gated by s.d.gate.
+static cloth_status bp_pairs(Scene& s, ContactState& c, const float* vb, const float* tb, const float* eb,
+                             int2* out_vt, int2* out_ee, int* n_out, int64_t cap, hipStream_t st) {
     Dev& d = s.d;
     const int n = s.nv;
     const int P = c.hash_p;
-    bp_boxes(s, c, xm, xp, (float)s.dhat, st);
+    const int nbb = gblocks((int64_t)n + s.nt + s.ne);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, s.d.gate, (const float*)c.bpart, nbb, s.nt, s.ne, c.grid);
     for (int pass = 0; pass < 2; ++pass) {
         const bool vt = pass == 0;
         const BpGrid* g = c.grid + (vt ? 0 : 1);
-        cloth_status rc = bp_file_targets(s, c, vt, st);
+        cloth_status rc = bp_file_targets(s, c, vt, vt ? tb : eb, st);
         if (rc != CLOTH_OK) return rc;
         const int nq = vt ? n : s.ne;
         int* cnts = vt ? c.vcount : c.ecount;
-        int2* outp = vt ? c.cand_vt : c.cand_ee;
-        const float* qb = vt ? c.vbox : c.ebox;
+        int2* outp = vt ? out_vt : out_ee;
+        const float* qb = vt ? vb : eb;
         if (vt)
             hipLaunchKernelGGL((k_query_count<true, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
                                c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7, c.heavy_q,
@@ -2334,19 +2633,70 @@ static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, cons
         }
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, s.d.gate, c.keep, cnts, nq);
         HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
-        hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, s.d.gate, cnts, c.keep, nq, c.cnt + (vt ? 0 : 1), c.cap,
+        hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, s.d.gate, cnts, c.keep, nq, n_out + (vt ? 0 : 1), cap,
                            c.cnt + 7);
         hipLaunchKernelGGL(k_query_copy<QUERY_LANES>, dim3(qblocks(nq)), dim3(256), 0, st, s.d.gate, nq, (const int*)cnts,
-                           (const int*)c.keep, (const int*)c.qscratch, outp, c.cap);
+                           (const int*)c.keep, (const int*)c.qscratch, outp, cap);
         if (vt)
             hipLaunchKernelGGL(k_query_rescan<true>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
-                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, c.cap, c.max_out, c.cnt + 7,
+                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, cap, c.max_out, c.cnt + 7,
                                (const int*)c.heavy_q, c.cnt + HEAVY_SLOT);
         else
             hipLaunchKernelGGL(k_query_rescan<false>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
-                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, c.cap, c.max_out, c.cnt + 7,
+                               c.rec, P, (const int*)cnts, (const int*)c.keep, outp, cap, c.max_out, c.cnt + 7,
                                (const int*)c.heavy_q, c.cnt + HEAVY_SLOT);
     }
+    HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
+// Broad phase on (xm, xp) -> sorted candidates, counts in cnt[0], cnt[1],
+// per-query offsets in c.vcount / c.ecount: stage boxes (checked against the
+// reusable superset's boxes), a rebuild of the superset on grown boxes when
+// a box escaped (launched always, gated on the device), then the superset
+// filtered by the stage boxes.
+static cloth_status broad_phase(Scene& s, ContactState& c, const float* xm, const float* xp, hipStream_t st) {
+    if (!s.self_contact) return CLOTH_OK;
+    Dev& d = s.d;
+    const int n = s.nv;
+    const int nbb = gblocks((int64_t)n + s.nt + s.ne);
+    if (!c.sup_on) {
+        // pairs of the stage boxes themselves
+        hipLaunchKernelGGL(k_aos_pair, dim3(gblocks(n)), dim3(TPB), 0, st, s.d.gate, n, xm, xp, c.xm4, c.xp4);
+        hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
+                           (float)s.dhat, c.vbox, c.tbox, c.ebox, c.bpart, (const float*)nullptr,
+                           (const float*)nullptr, (const float*)nullptr, (int*)nullptr);
+        return bp_pairs(s, c, c.vbox, c.tbox, c.ebox, c.cand_vt, c.cand_ee, c.cnt, c.cap, st);
+    }
+    hipLaunchKernelGGL(k_aos_pair, dim3(gblocks(n)), dim3(TPB), 0, st, s.d.gate, n, xm, xp, c.xm4, c.xp4);
+    hipLaunchKernelGGL(k_boxes, dim3(nbb), dim3(256), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
+                       (float)s.dhat, c.vbox, c.tbox, c.ebox, c.bpart, (const float*)c.svbox, (const float*)c.stbox,
+                       (const float*)c.sebox, c.supw + 2);
+    hipLaunchKernelGGL(k_sup_gate, dim3(1), dim3(64), 0, st, (const int*)s.d.gate, c.supw, (const int*)c.cnt);
+    const int* const stage_gate = s.d.gate;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        // the rebuild (gated by supw[5]), then its retry without margins
+        // (gated by supw[9])
+        if (attempt == 1) hipLaunchKernelGGL(k_sup_retry, dim3(1), dim3(64), 0, st, c.supw, c.cnt);
+        s.d.gate = c.supw + (attempt == 0 ? 5 : 9);
+        hipLaunchKernelGGL(k_sup_grow, dim3(nbb), dim3(256), 0, st, s.d, (const float4*)c.xm4, (const float4*)c.xp4,
+                           (const float*)c.vbox, (const float*)c.tbox, (const float*)c.ebox, c.svbox, c.stbox,
+                           c.sebox, c.bpart, (float)c.sup_mu0, (float)c.sup_kappa, (const int*)(c.supw + 7));
+        cloth_status rc = bp_pairs(s, c, c.svbox, c.stbox, c.sebox, c.sup_vt, c.sup_ee, c.supw, 2 * c.cap, st);
+        hipLaunchKernelGGL(k_sup_done, dim3(1), dim3(64), 0, st, (const int*)s.d.gate, c.supw, (const int*)c.cnt);
+        s.d.gate = stage_gate;
+        if (rc != CLOTH_OK) return rc;
+    }
+    const int64_t scap = 4 * c.cap;   // both superset lists
+    const int fb = gblocks(scap);
+    hipLaunchKernelGGL(k_sup_filter, dim3(fb), dim3(256), 0, st, c.supw, (const int2*)c.sup_vt, (const int2*)c.sup_ee,
+                       (const float*)c.vbox, (const float*)c.tbox, (const float*)c.ebox, n, s.nt, s.ne, c.keep);
+    HC(scan_exclusive(c.keep, c.keep_ofs, (int)scap, c.supw + 4, c.scan_tiles, nullptr, c.supw + 6, st));
+    hipLaunchKernelGGL(k_sup_compact, dim3(fb), dim3(256), 0, st, (const int*)c.supw, (const int2*)c.sup_vt,
+                       (const int2*)c.sup_ee, (const int*)c.keep, (const int*)c.keep_ofs, c.cand_vt, c.cand_ee, c.cnt,
+                       c.cap);
+    hipLaunchKernelGGL(k_query_ofs, dim3(gblocks((int64_t)n + s.ne)), dim3(256), 0, st, (const int*)c.supw,
+                       (const int*)c.cnt, (const int2*)c.cand_vt, (const int2*)c.cand_ee, n, s.ne, c.vcount, c.ecount);
     HC(hipGetLastError());
     return CLOTH_OK;
 }
@@ -2358,7 +2708,7 @@ cloth_status contact_tangle_check(Scene& s, ContactState& c, const float* x, hip
     if (!s.self_contact) return CLOTH_OK;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (const int*)nullptr, c.cnt + CNT_TANGLES, 0, 2);
     bp_boxes(s, c, x, x, 0.0f, st);
-    cloth_status rc = bp_file_targets(s, c, true, st);
+    cloth_status rc = bp_file_targets(s, c, true, c.tbox, st);
     if (rc != CLOTH_OK) return rc;
     hipLaunchKernelGGL(k_tangle_query<QUERY_LANES>, dim3(qblocks(s.ne)), dim3(256), 0, st, s.d,
                        (const float*)c.ebox, (const BpGrid*)c.grid, (const int*)c.bucket_ptr, (const BpRec*)c.rec,
@@ -2424,7 +2774,8 @@ static cloth_status block_setup(Scene& s, ContactState& c, hipStream_t st) {
     hipLaunchKernelGGL(k_slot_sort, dim3(gblocks(n)), dim3(TPB), 0, st, d, c.vslot_ptr, c.vslot, c.ob_a, c.nob,
                        c.cvflag);
     HC(scan_exclusive(c.cvflag, c.cvofs, n, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
-    hipLaunchKernelGGL(k_cv_compact, dim3(gblocks(n)), dim3(TPB), 0, st, s.d.gate, n, c.cvflag, c.cvofs, c.cvlist, c.cnt + 6);
+    hipLaunchKernelGGL(k_cv_compact, dim3(gblocks(n)), dim3(TPB), 0, st, s.d.gate, n, c.cvflag, c.cvofs, c.cvlist, c.cnt + 6,
+                       c.cnt + CNT_WCHG);
     HC(hipGetLastError());
     c.active = true;
     return CLOTH_OK;
@@ -2474,29 +2825,46 @@ cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, 
     return CLOTH_OK;
 }
 
-cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st) {
+// The contact matrix of the iteration (Eq. (subspace_collision) with the
+// Gram of Eq. (uu)) and its factorization; it depends on the collision
+// weights only, so it may run beside the local step (on a second stream).
+cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t st) {
     Dev& d = s.d;
+    int* wchg = c.cnt + CNT_WCHG;
+    // weights forced to k (residual forwarding) differ from the spans' ones
+    if (force_k) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, s.d.gate, wchg, 1, 1);
+    hipLaunchKernelGGL(k_contact_w, dim3(gblocks(s.nv)), dim3(256), 0, st, d, (const int*)c.cvlist,
+                       (const int*)(c.cnt + 6), c.Wc, force_k ? 1 : 0);
     const int T = (s.r + 15) / 16;   // 16 x 16 tiles per side of the Gram
     dim3 grid(c.gram_chunks, (T * (T + 1) / 2 + 4 * GRAM_TW - 1) / (4 * GRAM_TW));
     if (s.prec == CLOTH_MIXED)
         hipLaunchKernelGGL(k_gram<uint16_t>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
-                           d.gram_part);
+                           d.gram_part, (const int*)wchg, (const float*)c.Wc);
     else
         hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
-                           d.gram_part);
+                           d.gram_part, (const int*)wchg, (const float*)c.Wc);
     const int tot = s.r * (s.r + 1) / 2;
     double* gred = d.Amat;
     double* Arm = d.Amat + (size_t)GRAM_GROUPS * tot;
     hipLaunchKernelGGL(k_gram_reduce, dim3((tot + 255) / 256, GRAM_GROUPS), dim3(256), 0, st, d, d.gram_part,
-                       c.gram_chunks, c.cnt + 6, gred);
+                       c.gram_chunks, c.cnt + 6, gred, (const int*)wchg);
     hipLaunchKernelGGL(k_gram_final, dim3((tot + 255) / 256), dim3(256), 0, st, d, (const double*)gred, c.cnt + 6,
-                       Arm);
+                       Arm, (const int*)wchg);
+    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm,
+                       (const int*)(c.cnt + 6), wchg, c.cnt + CNT_NFACT);
+    HC(hipGetLastError());
+    return CLOTH_OK;
+}
+
+// q = A^{-1} g on the factor of contact_factor (g = U^T r0 from the local step)
+cloth_status contact_solve(Scene& s, ContactState& c, hipStream_t st) {
+    Dev& d = s.d;
     if (s.r <= 128)
-        hipLaunchKernelGGL(k_chol_solve<2>, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm,
-                           c.gvec, c.cnt + 6);
+        hipLaunchKernelGGL(k_chol_tri<2>, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)c.gvec,
+                           (const int*)(c.cnt + 6));
     else
-        hipLaunchKernelGGL(k_chol_solve<3>, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm,
-                           c.gvec, c.cnt + 6);
+        hipLaunchKernelGGL(k_chol_tri<3>, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)c.gvec,
+                           (const int*)(c.cnt + 6));
     HC(hipGetLastError());
     return CLOTH_OK;
 }
@@ -2504,7 +2872,7 @@ cloth_status contact_dynamic_solve(Scene& s, ContactState& c, hipStream_t st) {
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st) {
     Dev& d = s.d;
     hipLaunchKernelGGL(k_partial_ccd, dim3(gblocks(2 * c.cap + s.nv)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca,
-                       c.clam, s.amax, d.xk);
+                       c.clam, s.amax, d.xk, c.cnt + CNT_WCHG);
     HC(hipGetLastError());
     return CLOTH_OK;
 }
@@ -2521,7 +2889,7 @@ cloth_status contact_reset(Scene& s, ContactState& c, hipStream_t st) {
 
 cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step_stats* out) {
     if (!c.enabled) return CLOTH_OK;
-    int h[16];
+    int h[CNT_WORDS];
     unsigned long long tb[2];
     HC(hipMemcpyAsync(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
     HC(hipMemcpyAsync(tb, c.tmin_bits, sizeof(tb), hipMemcpyDeviceToHost, st));
@@ -2533,7 +2901,14 @@ cloth_status contact_stats(Scene& s, ContactState& c, hipStream_t st, cloth_step
     out->n_constraints = (int64_t)h[2] + h[3] + h[10];
     out->peak_candidates = h[12];
     out->n_contact_vertices = h[6];
+    out->n_factorizations = h[CNT_NFACT];
+    int sw[8];
+    HC(hipMemcpyAsync(sw, c.supw, sizeof(sw), hipMemcpyDeviceToHost, st));
+    HC(hipStreamSynchronize(st));
+    out->n_broad_rebuilds = sw[3];
+    HC(hipMemsetAsync(c.supw + 3, 0, sizeof(int), st));
     HC(hipMemsetAsync(c.cnt + 12, 0, sizeof(int), st));
+    HC(hipMemsetAsync(c.cnt + CNT_NFACT, 0, sizeof(int), st));
     (void)s;
     return CLOTH_OK;
 }

@@ -237,6 +237,7 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     }
 
     s.r = prm->r;
+    s.r_warm = prm->r_warm;
     s.iters_in = prm->iters_inner;
     s.iters_out = prm->iters_outer;
     s.rho = prm->cheb_rho;
@@ -248,6 +249,9 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     s.tol_in = prm->tol_inner > 0 ? prm->tol_inner : 0.0;
     s.tol_out = prm->tol_outer > 0 ? prm->tol_outer : 0.0;
     s.debug_tangles = prm->debug_tangles ? 1 : 0;
+    s.bp_mu0 = prm->broad_margin > 0 ? prm->broad_margin : 0.25 * s.dhat;
+    s.bp_kappa = prm->broad_margin_motion > 0 ? prm->broad_margin_motion : 1.0;
+    s.bp_reuse = prm->broad_reuse ? 1 : 0;
     return "";
 }
 

@@ -180,6 +180,43 @@ __device__ __forceinline__ void sell_row(const Dev& d, const float4* __restrict_
     }
 }
 
+// The same, for the short rows of cloth meshes (slices at most CA wide, the
+// rest by sell_row): the wavefront's slice bounds come from scalar loads,
+// the column and value loads of all CA entries are issued together, then
+// their gathers in two batches (CB, then CA - CB), so that a row costs three
+// dependent memory round trips.
+template <int CA, int CB, typename Fn>
+__device__ __forceinline__ void sell_row_short(const Dev& d, const float4* __restrict__ x4, int v, Fn&& fn) {
+    const int lane = v & 63;
+    const int slice = __builtin_amdgcn_readfirstlane(v >> 6);
+    const int p0 = d.sell_ptr[slice], p1 = d.sell_ptr[slice + 1];
+    int col[CA];
+    float val[CA];
+#pragma unroll
+    for (int b = 0; b < CA; ++b) {
+        const int jj = p0 + lane + 64 * b;
+        col[b] = jj < p1 ? d.sell_col[jj] : v;
+        val[b] = jj < p1 ? d.sell_val[jj] : 0.f;
+    }
+    {
+        float4 xc[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) xc[b] = x4[col[b]];
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+            if (p0 + lane + 64 * b < p1) fn(val[b], xc[b]);
+    }
+    {
+        float4 xc[CA - CB];
+#pragma unroll
+        for (int b = CB; b < CA; ++b) xc[b - CB] = x4[col[b]];
+#pragma unroll
+        for (int b = CB; b < CA; ++b)
+            if (p0 + lane + 64 * b < p1) fn(val[b], xc[b - CB]);
+    }
+    for (int j0 = p0 + lane + 64 * CA; j0 < p1; j0 += 64) fn(d.sell_val[j0], x4[d.sell_col[j0]]);
+}
+
 __device__ __forceinline__ double warp_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
@@ -705,6 +742,107 @@ __global__ void __launch_bounds__(TPB) k_expand(Dev d, int add) {
     }
 }
 
+// delta = U q on the matrix cores for a BF16 basis (v_mfma_f32_16x16x32_bf16:
+// 16 vertices x 32 basis columns of U against 32 x 16 of q, whose columns
+// 0..2 are the coordinates and the rest zero).  q (FP32) is split into three
+// BF16 parts hi + mid + lo that sum to it exactly, so the three products add
+// up to U~ q with FP32 accumulation.  The contraction order over the basis
+// columns is free, so lane group g = l / 16 (of the A operand) takes the NC
+// chunks of 8 columns [8 NC g, 8 NC (g + 1)) of its row: a lane reads 16 NC
+// contiguous bytes of one row, four lanes cover the row (r <= 32 NC).
+// A wavefront takes 16-vertex tiles of its workgroup's 256 vertices.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int NC>
+__global__ void __launch_bounds__(TPB) k_expand_mfma(Dev d, int add) {
+    __shared__ uint4 frag[3][NC][64];   // B operands, in lane order
+    __shared__ float res[TPB / 64][3][64];
+    if (gated(d.gate)) return;
+    const int r = d.r;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int n = d.nv;
+    // B operands: q's three BF16 parts for lane l's column l % 16 and rows
+    // k = 8 NC (l / 16) + 8 c + i, staged once per workgroup
+    for (int e = tid; e < NC * 64; e += TPB) {
+        const int c = e / 64, l = e % 64, gl = l >> 4, jl = l & 15;
+        uint32_t w[3][4];
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) {
+            uint32_t h2[3] = {0u, 0u, 0u};
+#pragma unroll
+            for (int i2 = 0; i2 < 2; ++i2) {
+                const int k = 8 * NC * gl + 8 * c + i + i2;
+                const float q = (jl < 3 && k < r) ? d.Qf[k * 3 + jl] : 0.f;
+                const uint32_t h = f32_to_bf16_rne(q);
+                const float qh = __uint_as_float(h << 16);
+                const uint32_t m = f32_to_bf16_rne(q - qh);
+                const float qm = __uint_as_float(m << 16);
+                const uint32_t lo = f32_to_bf16_rne(q - qh - qm);
+                h2[0] |= h << (16 * i2);
+                h2[1] |= m << (16 * i2);
+                h2[2] |= lo << (16 * i2);
+            }
+#pragma unroll
+            for (int p = 0; p < 3; ++p) w[p][i / 2] = h2[p];
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) frag[p][c][l] = make_uint4(w[p][0], w[p][1], w[p][2], w[p][3]);
+    }
+    const int base = xcd_tile(blockIdx.x, gridDim.x) * TPB + wave * 64;
+    const uint16_t* U = static_cast<const uint16_t*>(d.U);
+    const int col0 = 8 * NC * g;
+    // the A operands of the wavefront's four tiles, two tiles in flight:
+    // tile t + 2 is requested before tile t is multiplied
+    uint4 a[2][NC];
+    auto load_tile = [&](int t, uint4 (&buf)[NC]) {
+        const int v = base + 16 * t + j;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int k = col0 + 8 * c;
+            if (v < n && k < r) buf[c] = *reinterpret_cast<const uint4*>(U + (size_t)v * r + k);
+            else buf[c] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    load_tile(0, a[0]);
+    load_tile(1, a[1]);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, a[t & 1][c]);
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8_t, frag[p][c][lane]),
+                                                              acc, 0, 0, 0);
+        }
+        if (t + 2 < 4) load_tile(t + 2, a[t & 1]);
+        // lane (g, j < 3) holds coordinate j of the tile's vertices 4 g + e
+        if (j < 3)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) res[wave][j][16 * t + 4 * g + e] = acc[e];
+    }
+    __syncthreads();
+    const int v = base + lane;
+    if (v >= n) return;
+    if (add) {
+        d.xt[v] = d.xk[v] + res[wave][0][lane];
+        d.xt[n + v] = d.xk[n + v] + res[wave][1][lane];
+        d.xt[2 * n + v] = d.xk[2 * n + v] + res[wave][2][lane];
+    } else {
+        d.d4[v] = make_float4(res[wave][0][lane], res[wave][1][lane], res[wave][2][lane], 0.f);
+    }
+}
+
 // Jacobi sweep on the residual of x~ = x^k + delta with the Chebyshev blend:
 //   r1 = r0 - (H + diag W) delta   (= b - (H + diag W) x~, by linearity),
 //   x^ - x^k = delta + r1 / (diag H + W) = (r0 - offdiag(H) delta) / (diag H + W),
@@ -735,7 +873,7 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
             const float r00 = d.b[v], r01 = d.b[n + v], r02 = d.b[2 * n + v];
             const float dg = d.diag[v] + (has_contact ? d.W[v] : 0.f);
             float ax = 0.f, ay = 0.f, az = 0.f;
-            sell_row<5>(d, DL, v, [&](float a, float4 dc) {
+            sell_row_short<12, 8>(d, DL, v, [&](float a, float4 dc) {
                 ax += a * dc.x;
                 ay += a * dc.y;
                 az += a * dc.z;
@@ -869,8 +1007,15 @@ hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpar
 }
 
 hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st) {
-    if (prec == CLOTH_MIXED)
-        launch_timed(k_expand<uint16_t>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
+    const int nc = (d.r + 31) / 32;   // 8-column chunks per lane (r <= 32 nc)
+    if (prec == CLOTH_MIXED && nc <= 1)
+        launch_timed(k_expand_mfma<1>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
+    else if (prec == CLOTH_MIXED && nc <= 2)
+        launch_timed(k_expand_mfma<2>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
+    else if (prec == CLOTH_MIXED && nc <= 4)
+        launch_timed(k_expand_mfma<4>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
+    else if (prec == CLOTH_MIXED)
+        launch_timed(k_expand_mfma<6>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
     else
         launch_timed(k_expand<float>, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, add);
     return hipGetLastError();

@@ -33,10 +33,14 @@ constexpr int STEP_TANGLED = 32;
 // stats read, the last step's status, the inner iterations and outer blocks
 // the last step executed, and the tangle check's crossing and undecided
 // counts ([28], [29]).
+// [30] is set whenever a collision weight may have changed since the last
+// factorization of the reduced matrix (a life span changed, a new
+// constraint set, weights forced to k) and cleared by the factorization;
+// [31] counts the factorizations since the last stats read.
 constexpr int CNT_STEP_FAIL = 7, CNT_STICKY = 13, CNT_LAST_STATUS = 14, CNT_INNER_DONE = 15,
-              CNT_OUTER_DONE = 27, CNT_TANGLES = 28;
+              CNT_OUTER_DONE = 27, CNT_TANGLES = 28, CNT_WCHG = 30, CNT_NFACT = 31;
 constexpr int CNT_WORDS = 32;
-static_assert(CNT_TANGLES + 1 < CNT_WORDS, "counter words");
+static_assert(CNT_NFACT < CNT_WORDS, "counter words");
 
 // LDS of the contact solve (factor and triangular solves in one workgroup):
 // packed lower triangle, r inverse pivots and one zero entry
@@ -86,6 +90,7 @@ struct Dev {
     double* Ainv;             // r * r (no-contact inverse of Lambda~)
     double* Lam;              // r * r
     double* Amat;             // contact reduced matrix work: FP64 group sums of U^T W U
+    double* cholf;            // the last factorization: packed L D L^T (r (r + 1) / 2) and 1 / D (r)
                               // (GRAM_GROUPS_MAX packed triangles), then A (one)
     double* gram_part;        // GRAM_CHUNKS * r * r Gram partials (FP64)
     unsigned long long* dxbits;  // per-iteration max |dx| as double bits
@@ -118,6 +123,12 @@ struct Scene {
     double tol_in = 0, tol_out = 0;   // Algorithm 1 loop tolerances (<= 0: fixed budgets)
     double smin = 1, smax = 1;        // strain limits
     int debug_tangles = 0;            // check the end state of every step for intersecting triangles
+    double bp_mu0 = 0.0, bp_kappa = 1.0;   // reusable candidate superset: box growth margins
+    int bp_reuse = 0;                      // ... and whether it is used
+    int r_warm = 0;                   // width of the modal warm-start basis (0: the reuse basis)
+    void* d_Uw = nullptr;             // its stored values (nv * r_warm)
+    double* d_Ainvw = nullptr;        // inverse of its Galerkin matrix (r_warm * r_warm)
+    bool warm_set = false;
     int64_t pair_cap = 0;
     bool basis_set = false;
     bool x4_valid = false;        // d.x4 holds x^k (written by the Jacobi sweep)
@@ -167,6 +178,10 @@ struct Scene {
     float graph_g[3] = {0, 0, 0};
 
     // optional per-kernel timing: event pairs recorded around launches
+    // second stream of the step (the contact matrix beside the local step),
+    // joined by events; both are recorded into the step graph
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> ev_used;   // (kernel id, pool index of the start event)
@@ -178,14 +193,16 @@ struct Scene {
 // (the outer CCD stage: K_BROAD broad phase other than the edge-edge
 // counting pass K_QUERY_EE, K_TOI the time-of-impact kernel, K_OUTER the
 // rest: set merge, obstacles, step length, compaction, filter, block set-up)
+// (K_GRAM_CHOL: the contact matrix and its factorization, on the side
+// stream beside the local step; K_CHOL_TRI: the solve on the factor)
 enum KernelId {
     K_PREDICT = 0, K_LOCAL, K_REDUCE, K_EXPAND, K_JACOBI, K_TARGETS, K_GRAM_CHOL, K_PCCD, K_OUTER,
-    K_BROAD, K_QUERY_EE, K_TOI, K_MISC, K_COUNT
+    K_BROAD, K_QUERY_EE, K_TOI, K_CHOL_TRI, K_MISC, K_COUNT
 };
 static const char* const kKernelNames[K_COUNT] = {
     "predict", "local_residual", "reduce_solve", "expand", "jacobi_cheb", "pair_targets",
     "gram_cholesky", "partial_ccd", "outer_set_filter", "broad_phase", "query_count_ee", "toi_merge",
-    "misc"};
+    "contact_solve", "misc"};
 
 // Timing brackets (api.cpp): no-ops unless the scene's timing is on.  For a
 // single-kernel id (local residual, expand, Jacobi sweep, edge-edge query

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -33,6 +34,7 @@
 
 namespace cloth {
 cloth_status prepare_step_graph(cloth_scene_s* sc, const float g[3]);   // api.cpp
+cloth_status record_step_graph(cloth_scene_s* sc, const float g[3], hipGraph_t* out);   // api.cpp
 cloth_status scene_stats(cloth_scene_s* sc, hipStream_t st, cloth_step_stats* out);  // api.cpp
 }  // namespace cloth
 
@@ -112,6 +114,71 @@ cloth_status cloth_step_batch(cloth_scene* scenes, int32_t n, const float gravit
             rc = scene_stats(scenes[i], st, &stats[i]);
             if (rc != CLOTH_OK) return rc;
         }
+    return CLOTH_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch graph
+//
+// One graph for many scenes: each scene's recorded step is a child graph of
+// one parent graph, with no edges between them, so one hipGraphLaunch steps
+// every scene and the device runs their kernels side by side.
+
+struct cloth_batch_s {
+    std::vector<cloth_scene> scenes;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+cloth_status cloth_batch_create(cloth_scene* scenes, int32_t n, const float gravity[3], cloth_batch* out) {
+    if (!scenes || n <= 0 || !gravity || !out) return set_error(CLOTH_E_INVALID, "null argument");
+    for (int i = 0; i < n; ++i) {
+        if (!scenes[i] || !scenes[i]->s.basis_set) return set_error(CLOTH_E_INVALID, "scene without basis");
+        for (int j = 0; j < i; ++j)
+            if (scenes[j] == scenes[i]) return set_error(CLOTH_E_INVALID, "scene listed twice");
+    }
+    auto b = std::make_unique<cloth_batch_s>();
+    b->scenes.assign(scenes, scenes + n);
+    HC(hipGraphCreate(&b->graph, 0));
+    for (int i = 0; i < n; ++i) {
+        hipGraph_t child = nullptr;
+        cloth_status rc = record_step_graph(scenes[i], gravity, &child);
+        if (rc != CLOTH_OK) {
+            (void)hipGraphDestroy(b->graph);
+            return rc;
+        }
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddChildGraphNode(&node, b->graph, nullptr, 0, child);
+        (void)hipGraphDestroy(child);   // the node holds its own copy
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(b->graph);
+            return set_error(CLOTH_E_DEVICE, std::string("hipGraphAddChildGraphNode: ") + hipGetErrorString(e));
+        }
+    }
+    hipError_t e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(b->graph);
+        return set_error(CLOTH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    *out = b.release();
+    return CLOTH_OK;
+}
+
+cloth_status cloth_batch_step(cloth_batch b, int32_t steps, void* stream) {
+    if (!b || steps < 0) return set_error(CLOTH_E_INVALID, "invalid argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < steps; ++i) HC(hipGraphLaunch(b->exec, st));
+    return CLOTH_OK;
+}
+
+cloth_status cloth_batch_destroy(cloth_batch b) {
+    if (!b) return CLOTH_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
     return CLOTH_OK;
 }
 

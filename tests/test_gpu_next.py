@@ -53,3 +53,54 @@ def test_residual_forwarding_after_a_filtered_step():
     g.step(sc.gravity)
     x, _ = g.get_state()
     assert vertex_err(x, o.x) / diag <= 1e-5
+
+
+def warm_pair(sc, precision, r_warm, warm_iters, rho=None, gamma=0.9):
+    """Oracle and library scenes whose warm start has its own r_warm-mode
+    basis (the oracle's eigenvectors, the same FP64 values on both sides)."""
+    from oracle import model as M
+    from oracle import step as S
+    o, U, rho = oracle_side(sc, precision, rho=rho, gamma=gamma)
+    _, Uw = M.eigenbasis(o.m, r_warm)
+    o2 = S.Oracle(o.m, M.stored_basis(U, precision), o.p, sc.gravity, o.obs, Uw=M.stored_basis(Uw, precision))
+    o2.set_state(sc.x0, sc.v0)
+    o2.p.warm_iters = warm_iters
+    g = gpu_side(sc, U, precision, rho, gamma=gamma, r_warm=r_warm)
+    g.set_warm_basis(Uw)
+    g.set_step_options(warm_iters=warm_iters)
+    return o2, g
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_warm_start_with_a_wider_basis_hanging_cloth(precision):
+    """Hanging cloth, warm start in 32 modes against 16 for the reuse (the
+    paper's 120 | 30 split of section 8.1, scaled)."""
+    sc = scenegen.config(0)
+    o, g = warm_pair(sc, precision, r_warm=32, warm_iters=3)
+    for _ in range(sc.steps):
+        o.step()
+        g.step(sc.gravity)
+    x, _ = g.get_state()
+    err = vertex_err(x, o.x) / bbox_diag(o.x)
+    print(f"[warm r_warm=32 {precision}] err/diag={err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_warm_start_with_a_wider_basis_on_contact():
+    """A cloth falling onto a sphere with self contact, warm start in 24
+    modes against 8: the warm-started predictor feeds the first full CCD."""
+    sc = scenegen.drop_cloth(20, seed=9, obstacle="sphere", r=8, steps=3, drop=0.0015, d_hat=1e-3,
+                             iters_outer=2, iters_inner=5)
+    sc.v0[:] = np.array([0.0, -2.0, 0.0], np.float32)
+    o, g = warm_pair(sc, "fp32", r_warm=24, warm_iters=3, gamma=0.6)
+    diag = None
+    for s in range(sc.steps):
+        so = o.step()
+        sg = g.step(sc.gravity)
+        x, _ = g.get_state()
+        diag = diag or bbox_diag(o.x)
+        err = vertex_err(x, o.x) / diag
+        print(f"[warm contact] step {s} constraints {so.n_constraints}/{sg['n_constraints']} err/diag={err:.2e}",
+              flush=True)
+        assert err <= 1e-5
+    assert sg["n_constraints"] > 0

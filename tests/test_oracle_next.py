@@ -95,3 +95,30 @@ def test_residual_forwarding_uses_weight_k_and_no_filter():
     assert np.all(C.a_ob == 7)                       # the block's spans are untouched
     assert np.allclose(W[verts], m.k_contact)        # every collision weight is k
     assert np.all(dx[m.pinned] == 0) and np.abs(dx).max() > 0
+
+
+def test_warm_start_uses_its_own_wider_basis():
+    """The warm start takes its own basis (r_warm = 2 r modes): with the
+    exact eigenvectors its Galerkin matrix is the diagonal of eigenvalues
+    (library special case), one warm iteration is the closed-form modal
+    solve in the wide span, and the correction leaves span(U) of the reuse
+    basis."""
+    sc, m, lam, U = linear_setup(r=8)
+    lam_w, Uw = M.eigenbasis(m, 16)
+    p = S.Params(1, 5, 0.9, 0.8, warm_iters=1, self_contact=False)
+    o = S.Oracle(m, U, p, sc.gravity, Uw=Uw)
+    assert np.allclose(o.Lw, np.diag(lam_w), atol=1e-9 * lam_w.max())
+    rng = np.random.default_rng(4)
+    z = m.rest + 0.01 * rng.standard_normal(m.rest.shape)
+    z[m.pinned] = m.rest[m.pinned]
+    inertia = (m.mass / m.h ** 2)[:, None] * z
+    x1 = o.warm_start(z, inertia)
+    ref = z + Uw @ ((Uw.T @ (inertia - m.H @ z)) / lam_w[:, None])
+    assert np.allclose(x1, ref, atol=1e-12)
+    d = x1 - z
+    outside = d - U @ (U.T @ d)
+    assert np.abs(outside).max() > 1e-3 * np.abs(d).max()
+    # the default warm basis is the reuse basis
+    o2 = S.Oracle(m, U, p, sc.gravity)
+    x2 = o2.warm_start(z, inertia)
+    assert np.allclose(x2 - z, U @ (U.T @ (x2 - z)), atol=1e-12)
