@@ -69,7 +69,6 @@ struct ContactState {
     int* ob_a = nullptr;         // MAX_OBST * nv, -1 = not a member
     int* cvlist = nullptr;       // contact vertices (for the Gram)
     int *cvflag = nullptr, *cvofs = nullptr;
-    float* Wc = nullptr;         // collision weight of each contact vertex (cvlist order)
     ObstD* ob_dev = nullptr;     // device copy of ob[]
 
     // device scalars: [0] n_vt cand, [1] n_ee cand, [2] n_cvt, [3] n_cee,
@@ -104,7 +103,7 @@ cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, 
 // the contact matrix and its factorization (needs only the weights: may
 // run beside the local step), then q = A^{-1} g on it
 cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t st);
-cloth_status contact_solve(Scene& s, ContactState& c, hipStream_t st);
+cloth_status contact_solve(Scene& s, ContactState& c, int nseg, hipStream_t st);
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st);
 // dxo: slot of the change of x over the block (the outer loop condition)
 cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, unsigned long long* dxo, hipStream_t st);

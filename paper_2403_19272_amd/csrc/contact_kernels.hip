@@ -1844,32 +1844,25 @@ __device__ __forceinline__ int gram_per_chunk(int ncv, int nchunk) {
 // l / 16 + 4 e (e = 0..3) of column l % 16 of the tile.  Vertices are staged 32
 // at a time in LDS as W-scaled (FP64) and plain (FP32) rows.
 constexpr int GRAM_TW = 10;   // 16 x 16 FP64 tiles per wavefront
-// Collision weight W_v of each contact vertex (the Gram's rows), summed as
-// the local step sums it (pair slots in slot order, then obstacles), so that
-// the contact matrix can be formed while the local step runs.
-__global__ void __launch_bounds__(256) k_contact_w(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
-                                                   float* Wc, int force_k) {
-    if (gated(d.gate)) return;
-    const int ncv = *n_cv, n = d.nv;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncv; i += gridDim.x * blockDim.x) {
-        const int v = cvlist[i];
-        float Wv = 0.f;
-        for (int j = d.vslot_ptr[v], e = d.vslot_ptr[v + 1]; j < e; ++j) Wv += d.slot[d.vslot[j]].x;
-        for (int j = 0; j < d.nob; ++j) {
-            int a = d.ob_a[j * n + v];
-            if (a < 0) continue;
-            if (force_k) a = 0;
-            Wv += (d.Kb == 2.0f) ? ldexpf(d.kc, a) : d.kc * powf(d.Kb, (float)a);
-        }
-        Wc[i] = Wv;
+// Collision weight W_v of a contact vertex (a row of the Gram), summed as the
+// local step sums it (pair slots in slot order, then obstacles), so that the
+// contact matrix can be formed while the local step runs.
+__device__ __forceinline__ float contact_weight(const Dev& d, int v, int force_k) {
+    float Wv = 0.f;
+    for (int j = d.vslot_ptr[v], e = d.vslot_ptr[v + 1]; j < e; ++j) Wv += d.slot[d.vslot[j]].x;
+    for (int j = 0; j < d.nob; ++j) {
+        int a = d.ob_a[j * d.nv + v];
+        if (a < 0) continue;
+        if (force_k) a = 0;
+        Wv += (d.Kb == 2.0f) ? ldexpf(d.kc, a) : d.kc * powf(d.Kb, (float)a);
     }
+    return Wv;
 }
 
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
 template <typename UT>
 __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvlist, const int* __restrict__ n_cv,
-                                            int nchunk, double* part, const int* __restrict__ wchg,
-                                            const float* __restrict__ Wc) {
+                                            int nchunk, double* part, const int* __restrict__ wchg, int force_k) {
     if (gated(d.gate) || !*wchg) return;   // no weight changed: the last factorization stands
     constexpr int VB = 32;   // contact vertices staged per round (a multiple of 4)
     __shared__ float us[VB][MAX_R];
@@ -1917,7 +1910,7 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, const int* __restrict__ cvl
         if (threadIdx.x < VB) {
             const int v = threadIdx.x < m ? cvlist[base + threadIdx.x] : -1;
             vidx[threadIdx.x] = v;
-            wv[threadIdx.x] = v >= 0 ? Wc[base + threadIdx.x] : 0.f;
+            wv[threadIdx.x] = v >= 0 ? contact_weight(d, v, force_k) : 0.f;
         }
         __syncthreads();
         for (int q = threadIdx.x; q < VB * ncg16; q += 256) {
@@ -2040,6 +2033,29 @@ __device__ __forceinline__ double bcast_f64(double v, int src) {
 // One panel of W columns [p0, p0 + W) of the L D L^T elimination (W is a
 // compile-time width, so every loop below unrolls without bound checks and
 // the LDS loads of a step are issued together).
+// (FT threads: the factor kernel's workgroup size)
+constexpr int FT = 512;
+
+// n doubles from global memory into LDS, each thread issuing K loads before
+// its stores (one memory round trip per K NT entries, not one per NT: these
+// one-workgroup kernels run beside bandwidth-heavy ones, where a round trip
+// is long)
+template <int NT, int K>
+__device__ __forceinline__ void copy_to_lds(double* dst, const double* __restrict__ src, int n, int tid) {
+    for (int base = 0; base < n; base += NT * K) {
+        double v[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int e = base + q * NT + tid;
+            v[q] = e < n ? src[e] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int e = base + q * NT + tid;
+            if (e < n) dst[e] = v[q];
+        }
+    }
+}
 template <int W>
 __device__ __forceinline__ void chol_panel(double* A, double* dinv, int r, int p0, int tid) {
     const int wave = tid >> 6, lane = tid & 63;
@@ -2071,7 +2087,7 @@ __device__ __forceinline__ void chol_panel(double* A, double* dinv, int r, int p
     __syncthreads();
     // 2. the panel's part of every row below the block, a thread per row
     const int pe = p0 + W;
-    for (int i = pe + tid; i < r; i += 1024) {
+    for (int i = pe + tid; i < r; i += FT) {
         double a[W];
 #pragma unroll
         for (int t = 0; t < W; ++t) a[t] = A[rm(i, p0 + t)];
@@ -2092,7 +2108,7 @@ __device__ __forceinline__ void chol_panel(double* A, double* dinv, int r, int p
     // the operands; rows l / 16 + 4 e of column l % 16 of the result)
     const int nT = (r - pe + 15) >> 4;
     const int lr = lane & 15, lk = lane >> 4;
-    for (int t = wave; t < nT * (nT + 1) / 2; t += 16) {
+    for (int t = wave; t < nT * (nT + 1) / 2; t += FT / 64) {
         int I, J;
         tri_rc(t, I, J);
         const int i = pe + 16 * I + lr, j = pe + 16 * J + lr;
@@ -2217,7 +2233,7 @@ __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* 
 // (chol_panel); the factor and 1 / D are kept in d.cholf for k_chol_tri.
 // Skipped when no collision weight changed since the last factorization
 // (wchg clear): the kept factor is still that of A.
-__global__ void __launch_bounds__(1024) k_chol_factor(Dev d, const double* __restrict__ Arm,
+__global__ void __launch_bounds__(FT) k_chol_factor(Dev d, const double* __restrict__ Arm,
                                                       const int* __restrict__ n_cv, int* wchg, int* nfact) {
     if (gated(d.gate)) return;
     if (*n_cv == 0 || *wchg == 0) return;
@@ -2226,12 +2242,12 @@ __global__ void __launch_bounds__(1024) k_chol_factor(Dev d, const double* __res
     const int tid = threadIdx.x;
     const int tot = r * (r + 1) / 2;
     double* dinv = A + tot;   // 1 / A(k, k) once column k is final
-    for (int e = tid; e < tot; e += 1024) A[e] = Arm[e];
+    copy_to_lds<FT, 17>(A, Arm, tot, tid);
     __syncthreads();
     int p0 = 0;
     for (; p0 + CHOL_PANEL <= r; p0 += CHOL_PANEL) chol_panel<CHOL_PANEL>(A, dinv, r, p0, tid);
     if (p0 < r) chol_panel<CHOL_PANEL / 2>(A, dinv, r, p0, tid);   // r is a multiple of 8
-    for (int e = tid; e < tot + r; e += 1024) d.cholf[e] = A[e];
+    for (int e = tid; e < tot + r; e += FT) d.cholf[e] = A[e];
     if (tid == 0) {
         *wchg = 0;   // every thread read the flag before the first barrier above
         atomicAdd(nfact, 1);
@@ -2245,12 +2261,25 @@ __global__ void __launch_bounds__(1024) k_chol_factor(Dev d, const double* __res
 // NS: row slots of the solve, 2 for r <= 128 and 3 up to MAX_R (chosen on
 // the host; one instantiation per kernel keeps it within 128 VGPRs).
 template <int NS>
-__global__ void __launch_bounds__(1024) k_chol_tri(Dev d, const double* __restrict__ g, const int* __restrict__ n_cv) {
+__global__ void __launch_bounds__(1024) k_chol_tri(Dev d, const double* __restrict__ g1, int nseg,
+                                                   const int* __restrict__ n_cv) {
     if (gated(d.gate)) return;
     extern __shared__ double A[];
     const int r = d.r;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tot = r * (r + 1) / 2;
+    // g = U^T r0: the sum of the level-1 partials (FP64), kept in LDS after
+    // the factor (and in d.gvec)
+    double* g = A + tot + r + 1;
+    for (int o = tid; o < 3 * r; o += 1024) {
+        double acc = 0.0;
+#pragma unroll 16
+        for (int sg = 0; sg < nseg; ++sg) acc += g1[(size_t)sg * 3 * r + o];
+        g[o] = acc;
+        d.gvec[o] = acc;
+    }
     if (*n_cv == 0) {
+        __syncthreads();   // g complete
         // q = A^{-1} g: wavefront w takes rows w, w + 16, ..., lanes the
         // columns lane + 64 s; g is loaded once and the rows four at a time
         // (addresses clamped into the matrix, the extra entries multiplied
@@ -2299,10 +2328,9 @@ __global__ void __launch_bounds__(1024) k_chol_tri(Dev d, const double* __restri
         }
         return;
     }
-    const int tot = r * (r + 1) / 2;
     double* dinv = A + tot;
     const int zs = tot + r;   // a zero entry for the solves
-    for (int e = tid; e < tot + r; e += 1024) A[e] = d.cholf[e];
+    copy_to_lds<1024, 9>(A, d.cholf, tot + r, tid);
     if (tid == 0) A[zs] = 0.0;
     __syncthreads();
     if (wave >= 3) return;   // wavefront c solves for coordinate c
@@ -2523,12 +2551,11 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.cvlist = I((size_t)n + 1);
     c.cvflag = I((size_t)n + 1);
     c.cvofs = I((size_t)n + 1);
-    c.Wc = static_cast<float*>(carve(sizeof(float) * ((size_t)n + 1)));
     if (!c.vbox || !c.tbox || !c.ebox || !c.bucket_cnt || !c.bucket_ptr || !c.rec || !c.qscratch || !c.heavy_q ||
         !c.bpart || !c.grid || !c.xm4 || !c.xp4 || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
         !c.toi_ee || !c.keep || !c.keep_ofs || !c.cand_a || !c.cpair || !c.cpair_prev || !c.ca ||
         !c.ca_prev || !c.clam || !c.cnrm || !c.slot || !c.vslot_ptr || !c.vslot_fill || !c.vslot || !c.cvlist ||
-        !c.cvflag || !c.cvofs || !c.Wc || !c.svbox || !c.stbox || !c.sebox || !c.sup_vt || !c.sup_ee || !c.supw)
+        !c.cvflag || !c.cvofs || !c.svbox || !c.stbox || !c.sebox || !c.sup_vt || !c.sup_ee || !c.supw)
         return set_error(CLOTH_E_OOM, "arena exhausted (contact buffers)");
     d.vslot_ptr = c.vslot_ptr;
     d.vslot = c.vslot;
@@ -2552,9 +2579,9 @@ cloth_status contact_upload(Scene& s, ContactState& c) {
     HC(hipFuncSetAttribute((const void*)k_chol_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
                            (int)chol_lds_bytes(s.r)));
     HC(hipFuncSetAttribute((const void*)k_chol_tri<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                           (int)chol_lds_bytes(s.r)));
+                           (int)(chol_lds_bytes(s.r) + sizeof(double) * 3 * s.r)));
     HC(hipFuncSetAttribute((const void*)k_chol_tri<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                           (int)chol_lds_bytes(s.r)));
+                           (int)(chol_lds_bytes(s.r) + sizeof(double) * 3 * s.r)));
     return CLOTH_OK;
 }
 
@@ -2833,16 +2860,14 @@ cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t
     int* wchg = c.cnt + CNT_WCHG;
     // weights forced to k (residual forwarding) differ from the spans' ones
     if (force_k) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, s.d.gate, wchg, 1, 1);
-    hipLaunchKernelGGL(k_contact_w, dim3(gblocks(s.nv)), dim3(256), 0, st, d, (const int*)c.cvlist,
-                       (const int*)(c.cnt + 6), c.Wc, force_k ? 1 : 0);
     const int T = (s.r + 15) / 16;   // 16 x 16 tiles per side of the Gram
     dim3 grid(c.gram_chunks, (T * (T + 1) / 2 + 4 * GRAM_TW - 1) / (4 * GRAM_TW));
     if (s.prec == CLOTH_MIXED)
         hipLaunchKernelGGL(k_gram<uint16_t>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
-                           d.gram_part, (const int*)wchg, (const float*)c.Wc);
+                           d.gram_part, (const int*)wchg, force_k ? 1 : 0);
     else
         hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
-                           d.gram_part, (const int*)wchg, (const float*)c.Wc);
+                           d.gram_part, (const int*)wchg, force_k ? 1 : 0);
     const int tot = s.r * (s.r + 1) / 2;
     double* gred = d.Amat;
     double* Arm = d.Amat + (size_t)GRAM_GROUPS * tot;
@@ -2850,20 +2875,22 @@ cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t
                        c.gram_chunks, c.cnt + 6, gred, (const int*)wchg);
     hipLaunchKernelGGL(k_gram_final, dim3((tot + 255) / 256), dim3(256), 0, st, d, (const double*)gred, c.cnt + 6,
                        Arm, (const int*)wchg);
-    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)Arm,
+    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(FT), chol_lds_bytes(s.r), st, d, (const double*)Arm,
                        (const int*)(c.cnt + 6), wchg, c.cnt + CNT_NFACT);
     HC(hipGetLastError());
     return CLOTH_OK;
 }
 
-// q = A^{-1} g on the factor of contact_factor (g = U^T r0 from the local step)
-cloth_status contact_solve(Scene& s, ContactState& c, hipStream_t st) {
+// q = A^{-1} g on the factor of contact_factor; g = U^T r0 is the sum of the
+// nseg level-1 partials of the local step's product
+cloth_status contact_solve(Scene& s, ContactState& c, int nseg, hipStream_t st) {
     Dev& d = s.d;
+    const size_t lds = chol_lds_bytes(s.r) + sizeof(double) * 3 * s.r;
     if (s.r <= 128)
-        hipLaunchKernelGGL(k_chol_tri<2>, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)c.gvec,
+        hipLaunchKernelGGL(k_chol_tri<2>, dim3(1), dim3(1024), lds, st, d, (const double*)c.gpart2, nseg,
                            (const int*)(c.cnt + 6));
     else
-        hipLaunchKernelGGL(k_chol_tri<3>, dim3(1), dim3(1024), chol_lds_bytes(s.r), st, d, (const double*)c.gvec,
+        hipLaunchKernelGGL(k_chol_tri<3>, dim3(1), dim3(1024), lds, st, d, (const double*)c.gpart2, nseg,
                            (const int*)(c.cnt + 6));
     HC(hipGetLastError());
     return CLOTH_OK;

@@ -614,7 +614,7 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
 }
 
 // First reduction level: block s sums partial rows [s*SEG, (s+1)*SEG) in FP64.
-constexpr int SEG = 32;
+constexpr int SEG = U_SEG;
 __global__ void k_reduce_g1(const int* __restrict__ gate, const float* __restrict__ gpart, int nblk, int m,
                             double* __restrict__ out) {
     if (gated(gate)) return;
@@ -1001,8 +1001,10 @@ hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpar
     const int m = d.r * 3;
     int nseg = (nblk + SEG - 1) / SEG;
     hipLaunchKernelGGL(k_reduce_g1, dim3(nseg), dim3(256), 0, st, d.gate, (const float*)d.gpart, nblk, m, gpart2);
-    hipLaunchKernelGGL(k_solve_reduced, dim3(1), dim3(1024), sizeof(double) * m, st, d,
-                       (const double*)gpart2, nseg, contact ? 0 : 1);
+    // with contact the second level is summed by the solve on the contact factor
+    if (!contact)
+        hipLaunchKernelGGL(k_solve_reduced, dim3(1), dim3(1024), sizeof(double) * m, st, d,
+                           (const double*)gpart2, nseg, 1);
     return hipGetLastError();
 }
 

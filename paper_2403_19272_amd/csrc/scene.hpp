@@ -16,9 +16,10 @@ constexpr int MAX_OBST = 4;
 constexpr double NO_HIT = 2.0;
 constexpr int MAX_R = 192;        // widest basis: the packed FP64 Cholesky factor lives in LDS
 constexpr int GRAM_CHUNKS = 512;  // contact-vertex chunks of the Gram partials
-constexpr int GRAM_GROUPS_MAX = 16;  // chunk groups of the first FP64 reduction level
 constexpr int RF_MAX = 64;        // residual-forwarding iterations per step at most
 constexpr int CHEB_EST_SLOTS = 201;  // per-iteration norms of the Chebyshev estimate
+constexpr int GRAM_GROUPS_MAX = 16;  // chunk groups of the first FP64 reduction level
+constexpr int U_SEG = 32;         // local-step blocks summed per level-1 partial of U^T r0
 
 // Step status bits (device word, 0 = the step succeeded).  The first four
 // are the capacity overflows of the contact stages; a step that sets any of
@@ -90,8 +91,8 @@ struct Dev {
     double* Ainv;             // r * r (no-contact inverse of Lambda~)
     double* Lam;              // r * r
     double* Amat;             // contact reduced matrix work: FP64 group sums of U^T W U
-    double* cholf;            // the last factorization: packed L D L^T (r (r + 1) / 2) and 1 / D (r)
                               // (GRAM_GROUPS_MAX packed triangles), then A (one)
+    double* cholf;            // the last factorization: packed L D L^T (r (r + 1) / 2) and 1 / D (r)
     double* gram_part;        // GRAM_CHUNKS * r * r Gram partials (FP64)
     unsigned long long* dxbits;  // per-iteration max |dx| as double bits
     double* gvec;             // r * 3: g = U^T r0 (FP64)

@@ -174,6 +174,41 @@ def drop_cloth(n: int, seed: int, obstacle: str, r: int, steps: int,
                  precision=precision)
 
 
+def draped_state(sc: Scene, gap_scale: float = 0.5, seed: int = 0) -> np.ndarray:
+    """A seeded draped configuration of a cylinder-drop scene: the rest grid
+    laid over the cylinder's top along arc length (the z coordinate measured
+    from the axis becomes the angle over a circle of radius R + gap_scale
+    d_hat) and hanging straight down beyond the two tangent lines, lifted
+    radially by the absolute value of a seeded sum of eight sinusoids
+    (|h| <= 1 cm x side).  Arc length is kept along z, so the sheet starts
+    nearly unstretched and touching the obstacle's contact band over the arc.
+    Input data only: it holds no solver arithmetic."""
+    ob = sc.obstacles[0]
+    if ob.kind != CYLINDER:
+        raise ValueError("draped_state needs a cylinder scene")
+    rng = np.random.default_rng(seed)
+    cy, cz = ob.center[1], ob.center[2]
+    Ro = ob.radius + gap_scale * sc.d_hat
+    rest = sc.rest.astype(np.float64)
+    side = float(rest[:, 2].max() - rest[:, 2].min())
+    h = np.abs(sinusoid_heights(rest[:, [0, 2]], rng, amp=1.25e-3 * side))
+    s = rest[:, 2] - cz                      # arc length from the top line
+    half = 0.5 * math.pi * Ro
+    th = np.clip(s / Ro, -0.5 * math.pi, 0.5 * math.pi)
+    x = np.empty_like(rest)
+    x[:, 0] = rest[:, 0]
+    on = np.abs(s) <= half
+    # over the arc: radius Ro + h at angle th from the top
+    x[on, 1] = cy + (Ro + h[on]) * np.cos(th[on])
+    x[on, 2] = cz + (Ro + h[on]) * np.sin(th[on])
+    # hanging: straight down from the tangent lines, pushed out by h
+    off = ~on
+    sg = np.sign(s[off])
+    x[off, 1] = cy - (np.abs(s[off]) - half)
+    x[off, 2] = cz + sg * (Ro + h[off])
+    return x.astype(np.float32)
+
+
 def config(idx: int, **over) -> Scene:
     """The five workloads: 0 small hanging cloth, 1 sphere drape 256^2,
     2 cylinder drape 600^2 (mixed precision), 3/4 are multi-scene sets built by
