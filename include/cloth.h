@@ -297,19 +297,53 @@ cloth_status cloth_batch_create(cloth_scene* scenes, int32_t n, const float grav
 cloth_status cloth_batch_step(cloth_batch b, int32_t steps, void* stream);
 cloth_status cloth_batch_destroy(cloth_batch b);
 
+/* Autotuner of the launch settings that leave results bitwise unchanged,
+ * chosen on time at equal accuracy: lanes per broad-phase query (4, 8, 16)
+ * and, for scenes created with broad_reuse, the reusable superset and its
+ * margin.  Trials step the scene from its current state (one untimed step,
+ * then `steps` steps timed with HIP events on the stream) and restore the
+ * state after; the fastest setting is applied and cached per size class
+ * (vertex count to a quarter octave, r, precision, self contact); later
+ * calls for the class apply the cached one without trials unless force.
+ * The Chebyshev schedule (rho, damping) is chosen on the device when the
+ * basis is set (by measured error growth) and is reported here.  The scene
+ * must not be in a server or batch while tuned. */
+typedef struct {
+    int32_t query_lanes, broad_reuse;
+    double broad_margin, broad_margin_motion;
+    double ms_per_step;   /* the chosen setting's time per step (trials) */
+    double ms_default;    /* the default setting's (8 lanes, no superset) */
+    double cheb_rho, cheb_gamma;
+    int32_t trials, from_cache;
+} cloth_tuning;
+cloth_status cloth_autotune(cloth_scene s, const float gravity[3], int32_t steps, int32_t force, void* stream,
+                            cloth_tuning* out);
+cloth_status cloth_set_tuning(cloth_scene s, const cloth_tuning* t);
+
 /* Continuous-batching step server.  A host thread keeps up to `slots` steps
  * in flight (one stream each), starts queued requests as slots and their
  * scenes free up (two steps of one scene never overlap; requests of a scene
  * run in submission order), and admits scenes while the sum of their device
- * footprints stays within hbm_budget bytes (0 = no limit).  A scene in a
- * server must not be stepped or modified by the caller until it is released.
- *   admit:   *admitted = 1 if the scene fits (or is already in), else 0
+ * footprints stays within hbm_budget bytes (0 = no limit): the scenes it
+ * steps at any time are an admitted working set of at most that footprint.
+ * The budget is accounting only: a scene keeps its device memory (allocated
+ * by cloth_init) whether admitted or not.
+ * A scene in a server must not be stepped or modified by the caller until it
+ * is released.
+ *   admit:   *admitted = 1 if the scene fits now (or is already in), else 0
  *   release: waits for the scene's queued steps, then frees its budget
- *   submit:  queues one step of the scene; returns a ticket
+ *   submit:  queues one step of the scene and returns a ticket; a scene not
+ *            admitted waits (its requests queued) until its footprint fits:
+ *            the worker admits waiting scenes in arrival order, releasing
+ *            admitted scenes that have no queued or running step, least
+ *            recently used first.  CLOTH_E_OOM if the footprint alone
+ *            exceeds the budget
  *   poll / wait: completion of a ticket, with latency (submission to
  *            completion, host clock) and service time (device, ms); the
  *            ticket's status is the step's own (CLOTH_E_CAPACITY,
  *            CLOTH_E_DIVERGED or CLOTH_E_TANGLED for a rolled-back step)
+ *   info:    admitted and waiting scene counts, admitted footprint, and the
+ *            releases made to admit waiting scenes
  *   destroy: finishes queued work and stops the thread */
 typedef struct cloth_server_s* cloth_server;
 cloth_status cloth_server_create(int32_t slots, size_t hbm_budget, cloth_server* out);
@@ -321,6 +355,8 @@ cloth_status cloth_server_poll(cloth_server sv, int64_t ticket, int32_t* done, d
                                double* service_ms);
 cloth_status cloth_server_wait(cloth_server sv, int64_t ticket, double* latency_ms,
                                double* service_ms);
+cloth_status cloth_server_info(cloth_server sv, int32_t* n_admitted, int32_t* n_waiting, size_t* used_bytes,
+                               int64_t* evictions);
 cloth_status cloth_server_destroy(cloth_server sv);
 
 /* Optional parts of Algorithm 1 around the inner loop:

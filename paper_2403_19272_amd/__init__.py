@@ -38,7 +38,7 @@ EXPORTS = [
     "cloth_server_admit", "cloth_server_release", "cloth_server_submit", "cloth_server_poll",
     "cloth_server_wait", "cloth_server_destroy", "cloth_compute_basis", "cloth_set_step_options",
     "cloth_get_forwarded", "cloth_compute_basis_static", "cloth_set_warm_basis", "cloth_batch_create",
-    "cloth_batch_step", "cloth_batch_destroy",
+    "cloth_batch_step", "cloth_batch_destroy", "cloth_autotune", "cloth_set_tuning", "cloth_server_info",
 ]
 
 
@@ -65,6 +65,16 @@ class SolverParams(C.Structure):
 class Obstacle(C.Structure):
     _fields_ = [("kind", C.c_int32), ("center", C.c_double * 3), ("axis", C.c_double * 3),
                 ("radius", C.c_double), ("half_length", C.c_double), ("omega", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("query_lanes", C.c_int32), ("broad_reuse", C.c_int32), ("broad_margin", C.c_double),
+                ("broad_margin_motion", C.c_double), ("ms_per_step", C.c_double), ("ms_default", C.c_double),
+                ("cheb_rho", C.c_double), ("cheb_gamma", C.c_double), ("trials", C.c_int32),
+                ("from_cache", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class StepStats(C.Structure):
@@ -98,6 +108,8 @@ def _load():
         "cloth_batch_create": (i32, [P, i32, P, C.POINTER(P)]),
         "cloth_batch_step": (i32, [P, i32, P]),
         "cloth_batch_destroy": (i32, [P]),
+        "cloth_autotune": (i32, [P, P, i32, i32, P, C.POINTER(Tuning)]),
+        "cloth_set_tuning": (i32, [P, C.POINTER(Tuning)]),
         "cloth_add_obstacle": (i32, [P, C.POINTER(Obstacle)]),
         "cloth_set_state": (i32, [P, P, P, P]),
         "cloth_get_state": (i32, [P, P, P, P]),
@@ -121,6 +133,7 @@ def _load():
         "cloth_server_poll": (i32, [P, i64, C.POINTER(i32), C.POINTER(f64), C.POINTER(f64)]),
         "cloth_server_wait": (i32, [P, i64, C.POINTER(f64), C.POINTER(f64)]),
         "cloth_server_destroy": (i32, [P]),
+        "cloth_server_info": (i32, [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_size_t), C.POINTER(i64)]),
         "cloth_compute_basis": (i32, [P, i32, i32, i32, f64, P, P, C.POINTER(i32), C.POINTER(f64)]),
         "cloth_compute_basis_static": (i32, [P, i32, i32, i32, f64, P, P, C.POINTER(i32), C.POINTER(f64)]),
         "cloth_set_step_options": (i32, [P, i32, i32, f64]),
@@ -225,6 +238,19 @@ class ClothScene:
         """The modal warm start's own basis (nv x r_warm)."""
         U = np.ascontiguousarray(U, np.float64)
         _check(lib.cloth_set_warm_basis(self._h, _ptr(U), U.shape[1]), "cloth_set_warm_basis")
+
+    def autotune(self, gravity=(0.0, -9.8, 0.0), steps=5, force=False, stream=None):
+        """Picks the launch settings that leave results unchanged by timing
+        trials from the current state (see cloth_autotune)."""
+        g = np.asarray(gravity, np.float32)
+        t = Tuning()
+        _check(lib.cloth_autotune(self._h, _ptr(g), steps, int(bool(force)), _stream(stream), C.byref(t)),
+               "cloth_autotune")
+        return t.as_dict()
+
+    def set_tuning(self, query_lanes=8, broad_reuse=False, broad_margin=0.0, broad_margin_motion=0.0):
+        t = Tuning(query_lanes, int(bool(broad_reuse)), broad_margin, broad_margin_motion, 0.0, 0.0, 0.0, 0.0, 0, 0)
+        _check(lib.cloth_set_tuning(self._h, C.byref(t)), "cloth_set_tuning")
 
     def compute_basis(self, degree=300, max_passes=12, tol=2e-2, return_basis=False, static=False):
         """Device eigenbasis (Chebyshev-filtered subspace iteration), then set.
@@ -446,6 +472,15 @@ class StepServer:
         lat, svc = C.c_double(0), C.c_double(0)
         _check(lib.cloth_server_wait(self._h, ticket, C.byref(lat), C.byref(svc)), "cloth_server_wait")
         return lat.value, svc.value
+
+    def info(self):
+        """(admitted scenes, waiting scenes, admitted footprint bytes, releases
+        made to admit waiting scenes)."""
+        na, nw = C.c_int32(0), C.c_int32(0)
+        used, ev = C.c_size_t(0), C.c_int64(0)
+        _check(lib.cloth_server_info(self._h, C.byref(na), C.byref(nw), C.byref(used), C.byref(ev)),
+               "cloth_server_info")
+        return na.value, nw.value, used.value, ev.value
 
     def close(self):
         if self._h:

@@ -23,6 +23,7 @@ SOURCES = [
     ("host_build.cpp", []),
     ("api.cpp", ["-fopenmp"]),
     ("serve.cpp", []),
+    ("tune.cpp", []),
     ("pd_kernels.hip", []),
     ("eig.hip", []),
     # FP64 geometric predicates: keep the written operation order

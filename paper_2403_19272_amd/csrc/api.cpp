@@ -595,6 +595,12 @@ static cloth_status drop_graph(Scene& s) {
     return CLOTH_OK;
 }
 
+}  // extern "C"
+namespace cloth {
+cloth_status scene_drop_graph(cloth_scene_s* sc) { return drop_graph(sc->s); }
+}  // namespace cloth
+extern "C" {
+
 // Rounds a basis U (nv x r FP64, row-major; pinned rows stored as zero) to
 // the storage precision into dst, keeps the stored values, and forms
 // L = U~^T H U~ in FP64 (symmetrised) and its inverse.

@@ -51,6 +51,7 @@ struct ContactState {
     int* supw = nullptr;
     double sup_mu0 = 0.0, sup_kappa = 1.0;
     bool sup_on = false;   // candidate lists filtered from the superset (else queried per stage)
+    int qlanes = 8;        // lanes per broad-phase query (4, 8 or 16; the autotuner's choice)
 
     // candidates
     int* vcount = nullptr;  // per vertex VT counts, then offsets (nv+1)

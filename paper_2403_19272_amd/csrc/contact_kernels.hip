@@ -2444,8 +2444,12 @@ __global__ void __launch_bounds__(256) k_tangle_query(Dev d, const float* __rest
 // ================================================================ host side
 
 // lanes per query of the counting pass, and its grid (one group per query)
-constexpr int QUERY_LANES = 8;
-static inline int qblocks(int64_t nq) { return (int)std::max<int64_t>(1, (nq + 256 / QUERY_LANES - 1) / (256 / QUERY_LANES)); }
+constexpr int QUERY_LANES = 8;   // lanes per query of the tangle check (the broad phase's are c.qlanes)
+static inline int qblocks(int64_t nq, int G = QUERY_LANES) {
+    return (int)std::max<int64_t>(1, (nq + 256 / G - 1) / (256 / G));
+}
+
+
 
 static inline int gblocks(int64_t n) {
     int64_t b = (n + TPB - 1) / TPB;
@@ -2625,6 +2629,38 @@ static cloth_status bp_file_targets(Scene& s, ContactState& c, bool vt, const fl
     return CLOTH_OK;
 }
 
+// the counting and writing passes with G lanes per query (4, 8 or 16, a
+// scene setting the autotuner picks; the candidate lists do not depend on it)
+template <int G>
+static void query_passes(Scene& s, ContactState& c, bool vt, const float* qb, const BpGrid* g, int* cnts, int2* outp,
+                         int* n_out, int64_t cap, bool timed_ee, hipStream_t st) {
+    Dev& d = s.d;
+    const int nq = vt ? s.nv : s.ne;
+    const int P = c.hash_p;
+    if (vt)
+        hipLaunchKernelGGL((k_query_count<true, G>), dim3(qblocks(nq, G)), dim3(256), 0, st, d, qb, g, c.bucket_ptr,
+                           c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7, c.heavy_q, c.cnt + HEAVY_SLOT);
+    else {
+        if (timed_ee) {
+            timing_end(s, st);
+            timing_begin(s, K_QUERY_EE, st);
+        }
+        launch_timed(k_query_count<false, G>, dim3(qblocks(nq, G)), dim3(256), 0, st, d, qb, g,
+                     (const int*)c.bucket_ptr, (const BpRec*)c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7,
+                     c.heavy_q, c.cnt + HEAVY_SLOT);
+        if (timed_ee) {
+            timing_end(s, st);
+            timing_begin(s, K_BROAD, st);
+        }
+    }
+    hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, s.d.gate, c.keep, cnts, nq);
+    (void)scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, s.d.gate, st);
+    hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, s.d.gate, cnts, c.keep, nq, n_out + (vt ? 0 : 1), cap,
+                       c.cnt + 7);
+    hipLaunchKernelGGL(k_query_copy<G>, dim3(qblocks(nq, G)), dim3(256), 0, st, s.d.gate, nq, (const int*)cnts,
+                       (const int*)c.keep, (const int*)c.qscratch, outp, cap);
+}
+
 // Sorted VT and EE pairs of the boxes (vb: vertices, tb: triangles, eb:
 // edges) that overlap, into out_vt / out_ee with their counts in n_out[0],
 // n_out[1]; per-query offsets in c.vcount / c.ecount.  The grid comes from
@@ -2645,25 +2681,12 @@ static cloth_status bp_pairs(Scene& s, ContactState& c, const float* vb, const f
         int* cnts = vt ? c.vcount : c.ecount;
         int2* outp = vt ? out_vt : out_ee;
         const float* qb = vt ? vb : eb;
-        if (vt)
-            hipLaunchKernelGGL((k_query_count<true, QUERY_LANES>), dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
-                               c.bucket_ptr, c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7, c.heavy_q,
-                               c.cnt + HEAVY_SLOT);
-        else {
-            timing_end(s, st);
-            timing_begin(s, K_QUERY_EE, st);
-            launch_timed(k_query_count<false, QUERY_LANES>, dim3(qblocks(nq)), dim3(256), 0, st, d, qb, g,
-                         (const int*)c.bucket_ptr, (const BpRec*)c.rec, P, cnts, c.qscratch, c.max_out, c.cnt + 7,
-                         c.heavy_q, c.cnt + HEAVY_SLOT);
-            timing_end(s, st);
-            timing_begin(s, K_BROAD, st);
-        }
-        hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(nq)), dim3(TPB), 0, st, s.d.gate, c.keep, cnts, nq);
-        HC(scan_exclusive(c.keep, cnts, nq, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
-        hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, s.d.gate, cnts, c.keep, nq, n_out + (vt ? 0 : 1), cap,
-                           c.cnt + 7);
-        hipLaunchKernelGGL(k_query_copy<QUERY_LANES>, dim3(qblocks(nq)), dim3(256), 0, st, s.d.gate, nq, (const int*)cnts,
-                           (const int*)c.keep, (const int*)c.qscratch, outp, cap);
+        if (c.qlanes == 4)
+            query_passes<4>(s, c, vt, qb, g, cnts, outp, n_out, cap, true, st);
+        else if (c.qlanes == 16)
+            query_passes<16>(s, c, vt, qb, g, cnts, outp, n_out, cap, true, st);
+        else
+            query_passes<8>(s, c, vt, qb, g, cnts, outp, n_out, cap, true, st);
         if (vt)
             hipLaunchKernelGGL(k_query_rescan<true>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
                                c.rec, P, (const int*)cnts, (const int*)c.keep, outp, cap, c.max_out, c.cnt + 7,

@@ -213,16 +213,69 @@ struct cloth_server_s {
     std::unordered_map<int64_t, Done> results;
     std::map<cloth_scene, size_t> admitted;   // scene -> footprint
     std::map<cloth_scene, bool> busy;
+    std::map<cloth_scene, double> last_used;  // admitted scenes: when their last step started
+    std::deque<cloth_scene> waiting;          // scenes with requests, waiting for admission
     size_t budget = 0, used = 0;
     int64_t next_ticket = 1;
     int64_t in_flight = 0;
+    int64_t evictions = 0;
     bool stop = false;
     cloth_status error = CLOTH_OK;
     std::string error_msg;
     std::thread worker;
 
     void run();
+    bool admit_locked(cloth_scene sc);
+    void admit_waiting();
 };
+
+// admits sc if its footprint fits the budget (caller holds mu)
+bool cloth_server_s::admit_locked(cloth_scene sc) {
+    if (admitted.count(sc)) return true;
+    const size_t fp = sc->s.arena_bytes;
+    if (budget && used + fp > budget) return false;
+    admitted[sc] = fp;
+    used += fp;
+    busy[sc] = false;
+    last_used[sc] = now_ms();
+    return true;
+}
+
+// Admits waiting scenes in arrival order; when the next one does not fit,
+// admitted scenes with no queued or running step are released, least
+// recently used first, until it does (caller holds mu).
+void cloth_server_s::admit_waiting() {
+    while (!waiting.empty()) {
+        cloth_scene sc = waiting.front();
+        if (admit_locked(sc)) {
+            waiting.pop_front();
+            continue;
+        }
+        std::vector<std::pair<double, cloth_scene>> idle;
+        for (auto& kv : admitted) {
+            cloth_scene a = kv.first;
+            if (busy[a]) continue;
+            if (std::any_of(queue.begin(), queue.end(), [&](const Req& r) { return r.scene == a; })) continue;
+            idle.push_back({last_used[a], a});
+        }
+        std::sort(idle.begin(), idle.end());
+        const size_t need = sc->s.arena_bytes;
+        size_t freed = 0;
+        size_t k = 0;
+        while (k < idle.size() && used - freed + need > budget) freed += admitted[idle[k++].second];
+        if (used - freed + need > budget) return;   // wait for running steps to finish
+        for (size_t i = 0; i < k; ++i) {
+            cloth_scene a = idle[i].second;
+            used -= admitted[a];
+            admitted.erase(a);
+            busy.erase(a);
+            last_used.erase(a);
+            ++evictions;
+        }
+        admit_locked(sc);
+        waiting.pop_front();
+    }
+}
 
 void cloth_server_s::run() {
     std::unique_lock<std::mutex> lk(mu);
@@ -252,10 +305,12 @@ void cloth_server_s::run() {
             progressed = true;
         }
         if (progressed) cv_done.notify_all();
-        // start queued requests whose scene is idle, oldest first
+        admit_waiting();
+        // start queued requests whose scene is admitted and idle, oldest first
         for (auto& sl : slots) {
             if (sl.busy) continue;
-            auto it = std::find_if(queue.begin(), queue.end(), [&](const Req& r) { return !busy[r.scene]; });
+            auto it = std::find_if(queue.begin(), queue.end(),
+                                   [&](const Req& r) { return admitted.count(r.scene) && !busy[r.scene]; });
             if (it == queue.end()) break;
             Req r = *it;
             queue.erase(it);
@@ -279,6 +334,7 @@ void cloth_server_s::run() {
             sl.busy = true;
             sl.req = r;
             busy[r.scene] = true;
+            last_used[r.scene] = now_ms();
             ++in_flight;
         }
         if (stop && queue.empty() && in_flight == 0) break;
@@ -317,19 +373,7 @@ cloth_status cloth_server_create(int32_t n_slots, size_t hbm_budget, cloth_serve
 cloth_status cloth_server_admit(cloth_server sv, cloth_scene sc, int32_t* admitted) {
     if (!sv || !sc || !admitted) return set_error(CLOTH_E_INVALID, "null argument");
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->admitted.count(sc)) {
-        *admitted = 1;
-        return CLOTH_OK;
-    }
-    size_t fp = sc->s.arena_bytes;
-    if (sv->budget && sv->used + fp > sv->budget) {
-        *admitted = 0;
-        return CLOTH_OK;
-    }
-    sv->admitted[sc] = fp;
-    sv->used += fp;
-    sv->busy[sc] = false;
-    *admitted = 1;
+    *admitted = sv->admit_locked(sc) ? 1 : 0;
     return CLOTH_OK;
 }
 
@@ -345,13 +389,18 @@ cloth_status cloth_server_release(cloth_server sv, cloth_scene sc) {
     sv->used -= it->second;
     sv->admitted.erase(it);
     sv->busy.erase(sc);
+    sv->last_used.erase(sc);
     return CLOTH_OK;
 }
 
 cloth_status cloth_server_submit(cloth_server sv, cloth_scene sc, const float gravity[3], int64_t* ticket) {
     if (!sv || !sc || !gravity || !ticket) return set_error(CLOTH_E_INVALID, "null argument");
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (!sv->admitted.count(sc)) return set_error(CLOTH_E_INVALID, "scene not admitted");
+    if (sv->budget && sc->s.arena_bytes > sv->budget)
+        return set_error(CLOTH_E_OOM, "the scene's footprint exceeds the server's budget");
+    if (!sv->admitted.count(sc) &&
+        std::find(sv->waiting.begin(), sv->waiting.end(), sc) == sv->waiting.end())
+        sv->waiting.push_back(sc);   // admitted by the worker when its footprint fits
     cloth_server_s::Req r;
     r.ticket = sv->next_ticket++;
     r.scene = sc;
@@ -389,6 +438,17 @@ cloth_status cloth_server_wait(cloth_server sv, int64_t ticket, double* latency_
     if (latency_ms) *latency_ms = d.latency_ms;
     if (service_ms) *service_ms = d.service_ms;
     return d.status;
+}
+
+cloth_status cloth_server_info(cloth_server sv, int32_t* n_admitted, int32_t* n_waiting, size_t* used_bytes,
+                               int64_t* evictions) {
+    if (!sv) return set_error(CLOTH_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (n_admitted) *n_admitted = (int32_t)sv->admitted.size();
+    if (n_waiting) *n_waiting = (int32_t)sv->waiting.size();
+    if (used_bytes) *used_bytes = sv->used;
+    if (evictions) *evictions = sv->evictions;
+    return CLOTH_OK;
 }
 
 cloth_status cloth_server_destroy(cloth_server sv) {

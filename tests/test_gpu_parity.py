@@ -396,6 +396,38 @@ def test_server_results_equal_alone_runs():
     small.close()
 
 
+def test_server_admits_waiting_scenes_as_budget_frees():
+    """With a budget of two footprints, requests of five scenes submitted
+    without admission all complete, each scene bitwise equal to its alone
+    run; idle scenes were released to admit the waiting ones."""
+    import paper_2403_19272_amd as P
+    specs = uneven_scenes(5, seed=23)
+    alone = [gpu_side(sc, U, "mixed", 0.95, gamma=0.6) for sc, U in specs]
+    served = [gpu_side(sc, U, "mixed", 0.95, gamma=0.6) for sc, U in specs]
+    g = specs[0][0].gravity
+    steps = [2, 3, 1, 2, 2]
+    for a, k in zip(alone, steps):
+        for _ in range(k):
+            a.step(g)
+    fps = sorted(s.footprint for s in served)
+    srv = P.StepServer(slots=2, hbm_budget=fps[-1] + fps[-2])
+    order = [i for i, k in enumerate(steps) for _ in range(k)]
+    tickets = [srv.submit(served[i], g) for i in order]
+    for t in tickets:
+        srv.wait(t)
+    na, nw, used, ev = srv.info()
+    print(f"[server] admitted {na} waiting {nw} used {used} releases {ev}", flush=True)
+    srv.close()
+    assert nw == 0 and used <= fps[-1] + fps[-2] and ev >= 1
+    for a, b in zip(alone, served):
+        xa, va = a.get_state()
+        xb, vb = b.get_state()
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    with pytest.raises(P.ClothError) as e:
+        P.StepServer(slots=1, hbm_budget=fps[0] - 1).submit(served[0], g)
+    assert e.value.code == P.CLOTH_E_OOM
+
+
 def test_one_graph_launch_for_64_uneven_cloths():
     """The 64 uneven cloths of the batched workload (16..128 vertices a side,
     each over its own sphere, self contact, BF16 basis r = 32): one graph
