@@ -24,6 +24,13 @@ and on the default thread pool, and the GPU's result of that same step (both
 precisions) is compared with it.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--preroll P]
+
+Two multi-scene workloads print a line of the same form:
+  --workload batch   64 uneven cloths; plain FP32 scene by scene against
+                     mixed precision as one graph launch per step
+  --workload serve   200 live scenes under Poisson step requests through the
+                     step server (p50/p99 from arrival), against the same
+                     requests stepped scene by scene
 """
 from __future__ import annotations
 
@@ -50,13 +57,14 @@ def log(*a):
 
 
 def make_gpu_scene(sc, precision, P, k_contact=0.0, iters_inner=None, iters_outer=None, rho=0.0, gamma=0.0,
-                   broad_reuse=False):
+                   broad_reuse=False, pair_capacity=0):
     prec = P.CLOTH_MIXED if precision == "mixed" else P.CLOTH_PLAIN_FP32
     g = P.ClothScene(sc.tris, sc.rest, dt=sc.dt, density=sc.density, k_stretch=sc.k_stretch,
                      k_bend=sc.k_bend, k_contact=k_contact, d_hat=sc.d_hat, pinned=sc.pinned, r=sc.r,
                      iters_inner=iters_inner or sc.iters_inner, iters_outer=iters_outer or sc.iters_outer,
                      cheb_rho=rho, cheb_gamma=gamma, cheb_delay=3, precision=prec,
-                     self_contact=sc.self_contact, broad_reuse=broad_reuse, arena="torch")
+                     self_contact=sc.self_contact, broad_reuse=broad_reuse, pair_capacity=pair_capacity,
+                     arena="torch")
     for ob in sc.obstacles:
         g.add_obstacle(ob.kind, ob.center, ob.radius, axis=ob.axis, half_length=ob.half_length,
                        omega=ob.omega)
@@ -211,18 +219,340 @@ def cpu_leg(sc, U, xs, vs, iters, rho, gamma, P):
     return base, accuracy
 
 
+def oracle_error(sc, U, xs, vs, iters, rho, gamma, P):
+    """Max vertex error over the bounding-box diagonal of one GPU step (1
+    outer block x `iters` inner iterations, same Chebyshev parameters and
+    contact weight) against the FP64 oracle fed the same stored basis, for
+    the mixed and the plain FP32 forms."""
+    from oracle import model as M
+    from oracle import step as S
+    m = M.build_model(sc.tris, sc.rest, sc.pinned, sc.dt, sc.density, sc.k_stretch, sc.k_bend)
+    p = S.Params(iters_outer=1, iters_inner=iters, cheb_rho=rho, cheb_gamma=gamma, cheb_delay=3,
+                 d_hat=sc.d_hat, self_contact=sc.self_contact)
+    obs = [S.Obst(o.kind, np.array(o.center, float), o.radius, np.array(o.axis, float))
+           for o in sc.obstacles]
+    err = {}
+    for prec in ("mixed", "fp32"):
+        o = S.Oracle(m, M.stored_basis(U, prec), p, sc.gravity, obs)
+        o.set_state(xs, vs)
+        o.step()
+        g = make_gpu_scene(sc, prec, P, k_contact=m.k_contact, iters_inner=iters, iters_outer=1,
+                           rho=rho, gamma=gamma)
+        g.set_basis(U)
+        g.set_state(xs, vs)
+        g.step(sc.gravity, n=1, stats=False)
+        x, _ = g.get_state()
+        g.close()
+        diag = float(np.linalg.norm(o.x.max(0) - o.x.min(0)))
+        err[prec] = float(np.linalg.norm(x.astype(np.float64) - o.x, axis=1).max()) / diag
+    return err
+
+
+def scene_set(scs, P, log_every=20, twins=True, keep=(), caps=None):
+    """Mixed scenes (and plain FP32 twins), the basis computed on the device
+    (Chebyshev-filtered subspace iteration) on the mixed scene and stored in
+    both.  Returns the scenes and the bases of the scenes listed in `keep`
+    (all of them, as FP32, when `keep` is "all")."""
+    mixed, plain, bases = [], [], {}
+    t0 = time.time()
+    for i, sc in enumerate(scs):
+        a = make_gpu_scene(sc, "mixed", P, pair_capacity=caps[i] if caps else 0)
+        U = a.compute_basis(degree=200, max_passes=8, tol=5e-2, return_basis=True)["U"]
+        a.set_state(sc.x0, sc.v0)
+        mixed.append(a)
+        if twins:
+            b = make_gpu_scene(sc, "fp32", P, pair_capacity=caps[i] if caps else 0)
+            b.set_basis(U)
+            b.set_state(sc.x0, sc.v0)
+            plain.append(b)
+        if keep == "all":
+            bases[i] = U.astype(np.float32)   # the FP32 twin stores exactly these values
+        elif i in keep:
+            bases[i] = U
+        if (i + 1) % log_every == 0:
+            log(f"scenes built {i + 1}/{len(scs)} ({time.time() - t0:.1f}s)")
+    return mixed, plain, bases
+
+
+def windows(stream, torch, runs, states, K, warmup):
+    """Times each run over the same K-step window from `states`: a run is
+    (name, scenes it steps, step function); returns name -> (wall s, per-step
+    ms array)."""
+    out = {}
+    for name, ss, fn in runs:
+        for s, (x, v) in zip(ss, states):
+            s.set_state(x, v, stream=stream)
+        for _ in range(warmup):
+            fn()
+        for s, (x, v) in zip(ss, states):
+            s.set_state(x, v, stream=stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(K):
+            fn()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = (wall, np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(K)]))
+        log(f"{name}: {wall:.3f}s for {K} steps")
+    return out
+
+
+def batch_main(args, P, torch):
+    """64 uneven cloths (16..128 vertices a side, edge 1/127 m), each dropped
+    onto its own sphere, self contact, 3 x 10 iterations, r = 32.  After a
+    pre-roll into contact (one graph launch per step for all 64), the same
+    window is timed as: plain FP32 stepped scene by scene, mixed stepped
+    scene by scene, mixed overlapped on streams (cloth_step_batch), and mixed
+    as one graph launch per step (cloth_batch_step) with autotuned query
+    lanes."""
+    import scenegen
+    scs = scenegen.batch_scenes(64, seed=3, r=32)
+    stream = torch.cuda.current_stream()
+    nvs = [sc.nv for sc in scs]
+    keep = sorted(set([0, int(np.argmin(nvs)), int(np.argmax(nvs))]))
+    mixed, plain, bases = scene_set(scs, P, keep=keep)
+    g = scs[0].gravity
+    preroll = 60 if args.preroll is None else args.preroll
+    t0 = time.time()
+    pre = P.BatchGraph(mixed, g)
+    pre.step(preroll, stream=stream)
+    pre.close()
+    torch.cuda.synchronize()
+    states = [s.get_state(stream=stream) for s in mixed]
+    st0 = [s.step(g, n=0, stream=stream) for s in mixed]
+    log(f"pre-roll {preroll} steps {time.time() - t0:.1f}s; constraints "
+        f"{sum(s['n_constraints'] for s in st0)}")
+    t0 = time.time()
+    tunes = [s.autotune(g, steps=3, stream=stream) for s in mixed]
+    log(f"autotune {time.time() - t0:.1f}s: {sum(t['from_cache'] for t in tunes)} of {len(tunes)} cached")
+    bg = P.BatchGraph(mixed, g)
+    K = args.steps
+    runs = [("plain_fp32_per_scene", plain, lambda: [s.step(g, n=1, stream=stream, stats=False) for s in plain]),
+            ("mixed_per_scene", mixed, lambda: [s.step(g, n=1, stream=stream, stats=False) for s in mixed]),
+            ("mixed_streams", mixed, lambda: P.step_batch(mixed, g, stream=stream, stats=False)),
+            ("mixed_one_graph", mixed, lambda: bg.step(1, stream=stream))]
+    res = windows(stream, torch, runs, states, K, max(args.warmup, 1))
+    iters = scs[0].iters_inner * scs[0].iters_outer
+    vi = sum(sc.nv for sc in scs) * iters * K
+    forms = {k: {"value": round(vi / w, 1), "ms_per_step": round(w / K * 1e3, 4),
+                 "p50_step_ms": round(float(np.percentile(per, 50)), 4),
+                 "p99_step_ms": round(float(np.percentile(per, 99)), 4)} for k, (w, per) in res.items()}
+    for s, (x, v) in zip(mixed, states):
+        s.set_state(x, v, stream=stream)
+    wst = [s.step(g, n=1, stream=stream) for s in mixed]
+    acc = {}
+    if not args.no_cpu_baseline:
+        for i in sorted(bases)[:3]:
+            acc[f"scene{i}_nv{scs[i].nv}"] = oracle_error(scs[i], bases[i], *states[i], iters,
+                                                          st0[i]["cheb_rho"], st0[i]["cheb_gamma"], P)
+    bg.close()
+    best = forms["mixed_one_graph"]
+    out = {
+        "metric": METRIC, "value": best["value"], "unit": "vertex-iters/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": f"64 uneven cloths, {min(s.nv for s in scs)}..{max(s.nv for s in scs)} "
+                               f"vertices ({sum(s.nv for s in scs)} in all), each dropped onto its own "
+                               f"sphere, self contact, dt=1/200 s, {iters} PD iterations/step, r=32 BF16 "
+                               f"basis; one graph launch per step for all; timed window of {K} steps "
+                               f"from step {preroll} (in contact)",
+                   "scenes": len(scs), "vertices": sum(s.nv for s in scs), "iters_per_step": iters},
+        "p50_step_ms": best["p50_step_ms"], "p99_step_ms": best["p99_step_ms"],
+        "forms": forms,
+        "speedup_vs_plain_fp32_per_scene": round(best["value"] / forms["plain_fp32_per_scene"]["value"], 3),
+        "window": {"mean_constraints_per_scene": float(np.mean([s["n_constraints"] for s in wst])),
+                   "scenes_in_contact": int(sum(s["n_constraints"] > 0 for s in wst))},
+        "tuning": {"query_lanes": {str(q): sum(t["query_lanes"] == q for t in tunes) for q in (4, 8, 16)}},
+        "accuracy": {"max_vertex_err_over_bbox_diag": acc,
+                     "reference": f"the FP64 oracle fed the same stored basis, one step (1 block x {iters} "
+                                  f"iterations) from the window's start state"} if acc else None,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_main(args, P, torch):
+    """200 live scenes, vertex counts log-uniform in [4K, 360K], alternating
+    sphere and cylinder drops, mixed precision, r = 64.  After a pre-roll into
+    contact, step requests arrive as a Poisson process (mean --rate req/s, a
+    uniformly chosen scene each) for --serve-seconds and go through the step
+    server; latency is taken from each request's scheduled arrival to its
+    completion.  The same request sequence is then stepped back to back scene
+    by scene in plain FP32 and in mixed precision, for the per-scene
+    throughput at the same iteration budget."""
+    import scenegen
+    scs = scenegen.serving_scenes(200, seed=4, r=64)
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    # the plain FP32 twins are built after the mixed scenes are freed (both
+    # sets at the default candidate capacity would not fit in HBM together)
+    # The sphere drops of more than 200K vertices slide off the sphere at up
+    # to 5 m/s (12 edge lengths per step) about 20 steps after first contact,
+    # and their swept boxes then give up to ~130 candidates per vertex: they
+    # get twice the default capacity of 128 per vertex.
+    caps = [256 * sc.nv if (i % 2 == 0 and sc.nv > 200000) else 0 for i, sc in enumerate(scs)]
+    mixed, _, bases = scene_set(scs, P, twins=False, keep="all", caps=caps)
+    log(f"scene set {time.time() - t0:.1f}s: {sum(s.nv for s in scs)} vertices, "
+        f"{sum(s.footprint for s in mixed) / 2**30:.2f} GiB mixed")
+    g = scs[0].gravity
+    preroll = 55 if args.preroll is None else args.preroll
+    t0 = time.time()
+    pre = P.BatchGraph(mixed, g)
+    pre.step(preroll, stream=stream)
+    pre.close()
+    torch.cuda.synchronize()
+    states = [s.get_state(stream=stream) for s in mixed]
+    st0 = [s.step(g, n=0, stream=stream) for s in mixed]
+    log(f"pre-roll {preroll} steps {time.time() - t0:.1f}s; scenes in contact "
+        f"{sum(s['n_constraints'] > 0 for s in st0)}; largest candidate list per vertex "
+        f"{max(s['peak_candidates'] / sc.nv for s, sc in zip(st0, scs)):.1f}; most constraints per vertex "
+        f"{max(s['n_constraints'] / sc.nv for s, sc in zip(st0, scs)):.2f}")
+    tunes = [s.autotune(g, steps=3, stream=stream) for s in mixed]
+    torch.cuda.synchronize()
+    iters = scs[0].iters_inner * scs[0].iters_outer
+    rng = np.random.default_rng(4)
+    n_req = int(args.rate * args.serve_seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, n_req))
+    which = rng.integers(0, len(scs), n_req)
+
+    def serve(rate_scale, budget, slots):
+        for s, (x, v) in zip(mixed, states):
+            s.set_state(x, v, stream=stream)
+        torch.cuda.synchronize()
+        arr = arrivals / rate_scale
+        srv = P.StepServer(slots=slots, hbm_budget=budget)
+        tickets, t_sub = [], np.empty(n_req)
+        t0 = time.perf_counter()
+        for i in range(n_req):
+            while time.perf_counter() - t0 < arr[i]:
+                pass
+            t_sub[i] = time.perf_counter() - t0
+            tickets.append(srv.submit(mixed[which[i]], g))
+        res, failed = [], []
+        for i, t in enumerate(tickets):
+            try:
+                res.append(srv.wait(t))
+            except P.ClothError as e:   # a rolled-back step: its latency is not counted
+                failed.append((i, e.code))
+        info = srv.info()
+        srv.close()
+        if failed:
+            bad = sorted(set(int(which[i]) for i, _ in failed))
+            log(f"{len(failed)} requests failed, scenes {bad[:10]}")
+            for w in bad[:2]:
+                try:
+                    mixed[w].step(g, n=1, stream=stream)
+                except P.ClothError as e:
+                    log(f"scene {w} (nv {scs[w].nv}) stepped alone: {e}")
+        ok = np.ones(n_req, bool)
+        ok[[i for i, _ in failed]] = False
+        res = np.array(res)
+        done = t_sub[ok] + res[:, 0] / 1e3
+        e2e = (done - arr[ok]) * 1e3
+        span = done.max() - arr[0]
+        vi = float(sum(scs[w].nv for w in which[ok])) * iters
+        return {"offered_req_per_s": round(args.rate * rate_scale, 1), "requests": n_req,
+                "failed_requests": len(failed),
+                "served_req_per_s": round(int(ok.sum()) / span, 1), "value": round(vi / span, 1),
+                "p50_ms": round(float(np.percentile(e2e, 50)), 3),
+                "p99_ms": round(float(np.percentile(e2e, 99)), 3),
+                "p50_service_ms": round(float(np.percentile(res[:, 1], 50)), 3),
+                "p99_service_ms": round(float(np.percentile(res[:, 1], 99)), 3),
+                "max_submit_lag_ms": round(float((t_sub - arr).max() * 1e3), 3),
+                "slots": slots, "hbm_budget": budget, "releases_for_admission": int(info[3])}
+
+    full = serve(1.0, 0, args.slots)
+    log("serving at the offered rate:", json.dumps(full))
+    # below saturation, and under an artificial HBM budget
+    cap = full["served_req_per_s"]
+    scale = 0.7 * cap / args.rate
+    light = serve(scale, 0, args.slots)
+    log("serving at 70% of the served rate:", json.dumps(light))
+    # (at least twice the largest scene's footprint)
+    budget = max(int(args.serve_budget_gib * 2**30), 2 * max(s.footprint for s in mixed))
+    tight = serve(scale, budget, args.slots)
+    log(f"serving under a {budget / 2**30:.1f} GiB budget:", json.dumps(tight))
+
+    def back_to_back(ss):
+        """The same request sequence stepped scene by scene on one stream."""
+        for s, (x, v) in zip(ss, states):
+            s.set_state(x, v, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for w in which:
+            ss[w].step(g, n=1, stream=stream, stats=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return {"value": round(float(sum(scs[w].nv for w in which)) * iters / wall, 1),
+                "req_per_s": round(n_req / wall, 1), "wall_s": round(wall, 3)}
+
+    seq = {"mixed_per_scene": back_to_back(mixed)}
+    log(f"mixed per scene: {json.dumps(seq['mixed_per_scene'])}")
+    acc = {}
+    if not args.no_cpu_baseline:
+        small = sorted(range(len(scs)), key=lambda i: scs[i].nv)[:2]
+        for i in small:
+            acc[f"scene{i}_nv{scs[i].nv}"] = oracle_error(scs[i], bases[i].astype(np.float64), *states[i],
+                                                          iters, st0[i]["cheb_rho"], st0[i]["cheb_gamma"], P)
+    for s in mixed:
+        s.close()
+    mixed = None
+    torch.cuda.synchronize()
+    t0 = time.time()
+    plain = []
+    for i, sc in enumerate(scs):
+        b = make_gpu_scene(sc, "fp32", P, pair_capacity=caps[i])
+        b.set_basis(bases[i].astype(np.float64))
+        plain.append(b)
+    log(f"plain FP32 set {time.time() - t0:.1f}s")
+    seq["plain_fp32_per_scene"] = back_to_back(plain)
+    log(f"plain FP32 per scene: {json.dumps(seq['plain_fp32_per_scene'])}")
+    for s in plain:
+        s.close()
+    out = {
+        "metric": METRIC, "value": full["value"], "unit": "vertex-iters/s", "n_gpus": 1,
+        "steps": n_req, "warmup": 0, "ms_per_step": round(1e3 / full["served_req_per_s"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"200 live scenes, {min(s.nv for s in scs)}..{max(s.nv for s in scs)} "
+                               f"vertices (log-uniform), sphere and cylinder drops, self contact, "
+                               f"{iters} PD iterations/step, r=64 BF16 basis; Poisson step requests at "
+                               f"{args.rate:g} req/s for {args.serve_seconds:g} s from step {preroll}",
+                   "scenes": len(scs), "vertices": sum(s.nv for s in scs), "iters_per_step": iters},
+        "p50_step_ms": full["p50_ms"], "p99_step_ms": full["p99_ms"],
+        "serving": full, "serving_70pct": light, "serving_budget": tight, "per_scene": seq,
+        "speedup_vs_plain_fp32_per_scene": round(full["value"] / seq["plain_fp32_per_scene"]["value"], 3),
+        "tuning": {"query_lanes": {str(q): sum(t["query_lanes"] == q for t in tunes) for q in (4, 8, 16)}},
+        "accuracy": {"max_vertex_err_over_bbox_diag": acc,
+                     "reference": f"the FP64 oracle fed the same stored basis, one step (1 block x {iters} "
+                                  f"iterations) from the window's start state"} if acc else None,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--preroll", type=int, default=100,
+    ap.add_argument("--preroll", type=int, default=None,
                     help="untimed steps from the seeded start state before the timed window")
     ap.add_argument("--start", default="drop", choices=["drop", "draped"],
                     help="drop: the seeded 0.3 m drop from rest (default); draped: the seeded draped "
                          "configuration over the cylinder (scenegen.draped_state, at rest), which does "
                          "not depend on the solver's rounding")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "batch", "serve"],
+                    help="c2: the 360K-vertex cylinder drape (default); c1: the 65K-vertex sphere drape; "
+                         "batch: 64 uneven cloths; serve: 200 live scenes under Poisson requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean request rate, req/s")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="serve: arrival window, s")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0,
+                    help="serve: artificial HBM budget (raised to twice the largest footprint)")
+    ap.add_argument("--slots", type=int, default=8, help="serve: steps in flight")
     ap.add_argument("--precision", default=None, choices=["mixed", "fp32"])
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -253,6 +583,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return batch_main(args, P, torch)
+    if args.workload == "serve":
+        return serve_main(args, P, torch)
+    if args.preroll is None:
+        args.preroll = 100
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         src = torch.rand(n, device="cuda")

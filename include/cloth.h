@@ -110,7 +110,8 @@ typedef struct {
  *   self_contact        1: vertex-triangle and edge-edge contact on
  *   pair_capacity       candidate pairs per list (VT, EE) the arena holds
  *                       (0: 128 per vertex); a step whose stage finds more
- *                       fails (see cloth_step)
+ *                       fails (see cloth_step).  The constraint lists hold
+ *                       an eighth of it (at least 4096)
  *   debug_tangles       1: after every step, test the end state for pairs of
  *                       vertex-disjoint triangles that intersect (FP64
  *                       orientation tests); a step that has any fails with

@@ -395,6 +395,7 @@ class ClothScene:
         if self._h:
             lib.cloth_destroy(self._h)
             self._h = C.c_void_p()
+        self._arena = None   # a torch-owned arena goes back to the caching allocator
 
     def __del__(self):
         try:

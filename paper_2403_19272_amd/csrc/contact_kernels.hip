@@ -2505,8 +2505,9 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     int64_t pc = s.self_contact ? c.cap : 1;
     c.cap = pc;
     // constraints (kept candidates, VT + EE) are a small fraction of the
-    // candidates: their lists get a sixth of the candidate capacity
-    const int64_t cc = s.self_contact ? std::max<int64_t>(4096, 2 * pc / 6) : 1;
+    // candidates (under one per vertex in the drapes, against ten or more
+    // candidates): their lists get an eighth of the candidate capacity
+    const int64_t cc = s.self_contact ? std::max<int64_t>(4096, pc / 8) : 1;
     c.ccap = cc;
     c.vbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? n : 1)));
     c.tbox = static_cast<float*>(carve(sizeof(float) * 6 * (size_t)(s.self_contact ? s.nt : 1)));

@@ -209,6 +209,7 @@ struct cloth_server_s {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Req> queue;
+    std::map<cloth_scene, int> queued;        // requests in `queue` per scene
     std::vector<Slot> slots;
     std::unordered_map<int64_t, Done> results;
     std::map<cloth_scene, size_t> admitted;   // scene -> footprint
@@ -255,7 +256,7 @@ void cloth_server_s::admit_waiting() {
         for (auto& kv : admitted) {
             cloth_scene a = kv.first;
             if (busy[a]) continue;
-            if (std::any_of(queue.begin(), queue.end(), [&](const Req& r) { return r.scene == a; })) continue;
+            if (queued[a] > 0) continue;
             idle.push_back({last_used[a], a});
         }
         std::sort(idle.begin(), idle.end());
@@ -314,6 +315,7 @@ void cloth_server_s::run() {
             if (it == queue.end()) break;
             Req r = *it;
             queue.erase(it);
+            --queued[r.scene];
             cloth_status rc = prepare_step_graph(r.scene, r.g);
             hipError_t e = hipSuccess;
             if (rc == CLOTH_OK) {
@@ -383,9 +385,10 @@ cloth_status cloth_server_release(cloth_server sv, cloth_scene sc) {
     auto it = sv->admitted.find(sc);
     if (it == sv->admitted.end()) return set_error(CLOTH_E_INVALID, "scene not admitted");
     sv->cv_done.wait(lk, [&] {
-        return !sv->busy[sc] && std::none_of(sv->queue.begin(), sv->queue.end(),
-                                             [&](const cloth_server_s::Req& r) { return r.scene == sc; });
+        return !sv->busy[sc] && sv->queued[sc] == 0;
     });
+    it = sv->admitted.find(sc);   // the worker may have released it meanwhile
+    if (it == sv->admitted.end()) return CLOTH_OK;
     sv->used -= it->second;
     sv->admitted.erase(it);
     sv->busy.erase(sc);
@@ -408,6 +411,7 @@ cloth_status cloth_server_submit(cloth_server sv, cloth_scene sc, const float gr
     r.t_submit = now_ms();
     sv->results[r.ticket] = cloth_server_s::Done{};
     sv->queue.push_back(r);
+    ++sv->queued[sc];
     *ticket = r.ticket;
     sv->cv_work.notify_one();
     return CLOTH_OK;
