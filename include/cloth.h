@@ -137,7 +137,23 @@ typedef struct {
  *                       cloth_set_warm_basis; the paper uses a wider one
  *                       there, 120 modes against 30, section 8.1), a
  *                       multiple of 8 in [8, 192]; 0: the warm start uses
- *                       the reuse basis */
+ *                       the reuse basis
+ *   uu_store            1: the contact part of the reduced matrix,
+ *                       U~^T diag(W) U~, is summed from per-vertex
+ *                       precomputed upper triangles of U_j U_j^T (Eq. (uu),
+ *                       section 5.1; FP32, r (r + 1) / 2 per vertex, built by
+ *                       cloth_set_basis; products of BF16 values are exact in
+ *                       FP32) with FP64 sums, instead of the Gram of the
+ *                       contact rows on the matrix cores (0).  The store adds
+ *                       2 r (r + 1) bytes per vertex to the footprint
+ *   reorder             1: the scene numbers its vertices in the order of
+ *                       cloth_vertex_order (triangles sorted by their lowest
+ *                       new vertex), so that the sweeps' neighbour gathers
+ *                       stay within a narrow band of the state vectors.  The
+ *                       boundary keeps the caller's order: positions,
+ *                       velocities, bases and the system matrix cross it in
+ *                       the caller's numbering.  The stage-level calls need
+ *                       the caller's order (CLOTH_E_INVALID when set) */
 typedef struct {
     int32_t r, iters_inner, iters_outer;
     double tol_inner, tol_outer;
@@ -147,6 +163,7 @@ typedef struct {
     int32_t debug_tangles;
     double broad_margin, broad_margin_motion;
     int32_t r_warm, broad_reuse;
+    int32_t uu_store, reorder;
 } cloth_solver_params;
 
 typedef struct {
@@ -182,6 +199,12 @@ const char* cloth_last_error(void);
 
 /* Device bytes a scene needs for this mesh and these settings.  Builds the
  * mesh's system-matrix pattern on the host to count its nonzeros. */
+/* Reverse Cuthill-McKee order of the mesh's vertex graph (host only, no
+ * device call): order[i] (nv entries, caller-allocated) is the vertex placed
+ * at position i.  Each connected component starts from a pseudo-peripheral
+ * vertex; neighbours are taken in increasing degree, ties by index; the order
+ * is reversed at the end.  CLOTH_E_MESH for an index out of range. */
+cloth_status cloth_vertex_order(const cloth_mesh* mesh, int32_t* order);
 cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_params* params,
                                    size_t* bytes);
 

@@ -39,6 +39,7 @@ EXPORTS = [
     "cloth_server_wait", "cloth_server_destroy", "cloth_compute_basis", "cloth_set_step_options",
     "cloth_get_forwarded", "cloth_compute_basis_static", "cloth_set_warm_basis", "cloth_batch_create",
     "cloth_batch_step", "cloth_batch_destroy", "cloth_autotune", "cloth_set_tuning", "cloth_server_info",
+    "cloth_vertex_order",
 ]
 
 
@@ -59,7 +60,8 @@ class SolverParams(C.Structure):
                 ("cheb_rho", C.c_double), ("cheb_gamma", C.c_double), ("cheb_delay", C.c_int32),
                 ("precision", C.c_int32), ("self_contact", C.c_int32), ("pair_capacity", C.c_int64),
                 ("debug_tangles", C.c_int32), ("broad_margin", C.c_double),
-                ("broad_margin_motion", C.c_double), ("r_warm", C.c_int32), ("broad_reuse", C.c_int32)]
+                ("broad_margin_motion", C.c_double), ("r_warm", C.c_int32), ("broad_reuse", C.c_int32),
+                ("uu_store", C.c_int32), ("reorder", C.c_int32)]
 
 
 class Obstacle(C.Structure):
@@ -100,6 +102,7 @@ def _load():
         "cloth_status_string": (C.c_char_p, [i32]),
         "cloth_last_error": (C.c_char_p, []),
         "cloth_query_footprint": (i32, [C.POINTER(Mesh), C.POINTER(SolverParams), C.POINTER(C.c_size_t)]),
+        "cloth_vertex_order": (i32, [C.POINTER(Mesh), C.POINTER(i32)]),
         "cloth_init": (i32, [C.POINTER(Mesh), P, C.POINTER(Material), f64, C.POINTER(SolverParams), P,
                              C.c_size_t, C.POINTER(P)]),
         "cloth_system_matrix": (i32, [P, C.POINTER(i64), P, P, P]),
@@ -179,6 +182,16 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+def vertex_order(tris, nv):
+    """Reverse Cuthill-McKee order of a mesh's vertices (cloth_vertex_order):
+    entry i is the vertex placed at position i."""
+    t = np.ascontiguousarray(tris, np.int32)
+    mesh = Mesh(nv, t.shape[0], t.ctypes.data, None)
+    out = np.empty(nv, np.int32)
+    _check(lib.cloth_vertex_order(C.byref(mesh), out.ctypes.data_as(C.POINTER(C.c_int32))), "cloth_vertex_order")
+    return out
+
+
 class ClothScene:
     """One cloth scene resident on the device."""
 
@@ -188,7 +201,7 @@ class ClothScene:
                  tol_outer=0.0, cheb_rho=0.0, cheb_gamma=0.0, cheb_delay=3,
                  precision=CLOTH_PLAIN_FP32, self_contact=False, pair_capacity=0,
                  debug_tangles=False, broad_margin=0.0, broad_margin_motion=0.0, r_warm=0,
-                 broad_reuse=False, arena=None):
+                 broad_reuse=False, uu_store=False, reorder=False, arena=None):
         self._tris = np.ascontiguousarray(tris, np.int32)
         rest = _f32(rest)
         nv = rest.shape[0]
@@ -201,7 +214,8 @@ class ClothScene:
         self.params = SolverParams(r, iters_inner, iters_outer, tol_inner, tol_outer, cheb_rho,
                                    cheb_gamma, cheb_delay, precision, int(bool(self_contact)),
                                    pair_capacity, int(bool(debug_tangles)), broad_margin,
-                                   broad_margin_motion, r_warm, int(bool(broad_reuse)))
+                                   broad_margin_motion, r_warm, int(bool(broad_reuse)),
+                                   int(bool(uu_store)), int(bool(reorder)))
         self.r = r
         self.r_warm = r_warm
         nbytes = C.c_size_t(0)

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <numeric>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,16 +59,32 @@ float bf16_to_f(uint16_t b) {
     return f;
 }
 
-// AoS (x0,y0,z0,...) host <-> SoA device planes
-void aos_to_soa(const float* a, std::vector<float>& s, int n) {
+// AoS (x0,y0,z0,...) host <-> SoA device planes; with a vertex order, row
+// perm[i] of the caller's array is internal vertex i
+void aos_to_soa(const float* a, std::vector<float>& s, int n, const std::vector<int>& perm = {}) {
     s.resize(3 * (size_t)n);
-    for (int i = 0; i < n; ++i)
-        for (int c = 0; c < 3; ++c) s[(size_t)c * n + i] = a[3 * (size_t)i + c];
+    for (int i = 0; i < n; ++i) {
+        const size_t src = perm.empty() ? i : perm[i];
+        for (int c = 0; c < 3; ++c) s[(size_t)c * n + i] = a[3 * src + c];
+    }
 }
-void soa_to_aos(const std::vector<float>& s, float* a, int n) {
-    for (int i = 0; i < n; ++i)
-        for (int c = 0; c < 3; ++c) a[3 * (size_t)i + c] = s[(size_t)c * n + i];
+void soa_to_aos(const std::vector<float>& s, float* a, int n, const std::vector<int>& perm = {}) {
+    for (int i = 0; i < n; ++i) {
+        const size_t dst = perm.empty() ? i : perm[i];
+        for (int c = 0; c < 3; ++c) a[3 * dst + c] = s[(size_t)c * n + i];
+    }
 }
+// rows of an n x r basis between the caller's order and the internal one
+static std::vector<double> rows_to_internal(const double* U, int n, int r, const std::vector<int>& perm) {
+    std::vector<double> out((size_t)n * r);
+    for (int i = 0; i < n; ++i) std::copy(U + (size_t)perm[i] * r, U + (size_t)(perm[i] + 1) * r, &out[(size_t)i * r]);
+    return out;
+}
+static void rows_to_caller(const std::vector<double>& Ui, double* U, int n, int r, const std::vector<int>& perm) {
+    for (int i = 0; i < n; ++i)
+        std::copy(&Ui[(size_t)i * r], &Ui[(size_t)(i + 1) * r], U + (size_t)(perm.empty() ? i : perm[i]) * r);
+}
+static bool reordered(const Scene& s) { return !s.perm.empty(); }
 
 // Symmetric positive definite inverse by Cholesky (FP64, host).
 bool spd_inverse(const std::vector<double>& A, int r, std::vector<double>& inv) {
@@ -187,6 +204,11 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     d.Amat = cv<double>(carve_fn, (size_t)(GRAM_GROUPS_MAX + 1) * s.r * (s.r + 1) / 2);
     d.gram_part = cv<double>(carve_fn, (size_t)GRAM_CHUNKS * s.r * s.r);
     d.cholf = cv<double>(carve_fn, (size_t)s.r * (s.r + 1) / 2 + s.r);
+    d.UU = nullptr;
+    if (s.uu_store) {
+        d.UU = cv<float>(carve_fn, (size_t)n * s.r * (s.r + 1) / 2);
+        if (!d.UU) return fail(CLOTH_E_OOM, "arena exhausted (U_j U_j^T store)");
+    }
     s.nslots_cap = slots_needed(s);
     d.dxbits = cv<unsigned long long>(carve_fn, (size_t)s.nslots_cap);
     s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);
@@ -209,6 +231,7 @@ static size_t dry_footprint(const Scene& src) {
     s.r = src.r;
     s.r_warm = src.r_warm;
     s.bp_reuse = src.bp_reuse;
+    s.uu_store = src.uu_store;
     s.iters_in = src.iters_in;
     s.iters_out = src.iters_out;
     s.prec = src.prec;
@@ -384,6 +407,15 @@ const char* cloth_status_string(cloth_status s) {
 
 const char* cloth_last_error(void) { return g_err.c_str(); }
 
+cloth_status cloth_vertex_order(const cloth_mesh* mesh, int32_t* order) {
+    if (!mesh || !mesh->tris || !order || mesh->nv <= 0 || mesh->nt <= 0) return fail(CLOTH_E_INVALID, "null argument");
+    for (size_t i = 0; i < 3 * (size_t)mesh->nt; ++i)
+        if (mesh->tris[i] < 0 || mesh->tris[i] >= mesh->nv) return fail(CLOTH_E_MESH, "triangle index out of range");
+    std::vector<int> o = rcm_order(mesh->nv, mesh->nt, mesh->tris);
+    std::copy(o.begin(), o.end(), order);
+    return CLOTH_OK;
+}
+
 cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_params* params, size_t* bytes) {
     if (!mesh || !params || !bytes) return fail(CLOTH_E_INVALID, "null argument");
     if (!mesh->tris || mesh->nv <= 0 || mesh->nt <= 0) return fail(CLOTH_E_INVALID, "empty mesh");
@@ -440,6 +472,7 @@ cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_pa
     ds.nsell = nsell;
     ds.r = params->r;
     ds.r_warm = params->r_warm;
+    ds.uu_store = params->uu_store ? 1 : 0;
     ds.bp_reuse = params->broad_reuse ? 1 : 0;
     ds.iters_in = std::max(1, params->iters_inner);
     ds.iters_out = std::max(1, params->iters_outer);
@@ -478,7 +511,40 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     std::unique_ptr<cloth_scene_s> sc(new (std::nothrow) cloth_scene_s());
     if (!sc) return fail(CLOTH_E_OOM, "host allocation");
     Scene& s = sc->s;
-    std::string err = build_scene(s, mesh, rest_xyz, dt, mat, params);
+    // optional vertex reorder: the scene is built on the renumbered mesh
+    // (triangles sorted by their lowest new vertex), and every host array
+    // that crosses the boundary is mapped between the two orders
+    cloth_mesh pm = *mesh;
+    std::vector<int32_t> ptris;
+    std::vector<uint8_t> ppin;
+    std::vector<float> prest;
+    if (params->reorder) {
+        for (size_t i = 0; i < 3 * (size_t)mesh->nt; ++i)
+            if (mesh->tris[i] < 0 || mesh->tris[i] >= mesh->nv) return fail(CLOTH_E_MESH, "triangle index out of range");
+        s.perm = rcm_order(mesh->nv, mesh->nt, mesh->tris);
+        std::vector<int> inv(mesh->nv);
+        for (int i = 0; i < mesh->nv; ++i) inv[s.perm[i]] = i;
+        std::vector<int> tord(mesh->nt);
+        std::iota(tord.begin(), tord.end(), 0);
+        auto lo = [&](int t) {
+            return std::min({inv[mesh->tris[3 * t]], inv[mesh->tris[3 * t + 1]], inv[mesh->tris[3 * t + 2]]});
+        };
+        std::stable_sort(tord.begin(), tord.end(), [&](int a, int b) { return lo(a) < lo(b); });
+        ptris.resize(3 * (size_t)mesh->nt);
+        for (int t = 0; t < mesh->nt; ++t)
+            for (int c = 0; c < 3; ++c) ptris[3 * (size_t)t + c] = inv[mesh->tris[3 * (size_t)tord[t] + c]];
+        prest.resize(3 * (size_t)mesh->nv);
+        for (int i = 0; i < mesh->nv; ++i)
+            for (int c = 0; c < 3; ++c) prest[3 * (size_t)i + c] = rest_xyz[3 * (size_t)s.perm[i] + c];
+        if (mesh->pinned) {
+            ppin.resize(mesh->nv);
+            for (int i = 0; i < mesh->nv; ++i) ppin[i] = mesh->pinned[s.perm[i]];
+            pm.pinned = ppin.data();
+        }
+        pm.tris = ptris.data();
+        rest_xyz = prest.data();
+    }
+    std::string err = build_scene(s, &pm, rest_xyz, dt, mat, params);
     if (!err.empty()) return fail(CLOTH_E_MESH, err);
     s.nblk = (s.nv + TPB - 1) / TPB;
     size_t need = dry_footprint(s);
@@ -576,9 +642,32 @@ cloth_status cloth_system_matrix(cloth_scene sc, int64_t* nnz, int32_t* row_ptr,
     if (!sc || !nnz) return fail(CLOTH_E_INVALID, "null argument");
     Scene& s = sc->s;
     *nnz = s.nnz;
-    if (row_ptr) std::copy(s.rowptr.begin(), s.rowptr.end(), row_ptr);
-    if (col) std::copy(s.col.begin(), s.col.end(), col);
-    if (val) std::copy(s.val.begin(), s.val.end(), val);
+    if (!reordered(s)) {
+        if (row_ptr) std::copy(s.rowptr.begin(), s.rowptr.end(), row_ptr);
+        if (col) std::copy(s.col.begin(), s.col.end(), col);
+        if (val) std::copy(s.val.begin(), s.val.end(), val);
+        return CLOTH_OK;
+    }
+    // rows and columns back in the caller's order, columns sorted per row
+    const int n = s.nv;
+    std::vector<int32_t> rp(n + 1, 0);
+    for (int i = 0; i < n; ++i) rp[s.perm[i] + 1] = s.rowptr[i + 1] - s.rowptr[i];
+    for (int i = 0; i < n; ++i) rp[i + 1] += rp[i];
+    if (row_ptr) std::copy(rp.begin(), rp.end(), row_ptr);
+    if (col || val) {
+        std::vector<std::pair<int, double>> row;
+        for (int i = 0; i < n; ++i) {
+            row.clear();
+            for (int k = s.rowptr[i]; k < s.rowptr[i + 1]; ++k) row.push_back({s.perm[s.col[k]], s.val[k]});
+            std::sort(row.begin(), row.end());
+            int32_t o = rp[s.perm[i]];
+            for (auto& e : row) {
+                if (col) col[o] = e.first;
+                if (val) val[o] = e.second;
+                ++o;
+            }
+        }
+    }
     return CLOTH_OK;
 }
 
@@ -661,8 +750,19 @@ static cloth_status store_basis(Scene& s, const double* U, int r, void* dst, std
     return CLOTH_OK;
 }
 
+static cloth_status set_basis_internal(cloth_scene sc, const double* U, int32_t r);
+
 cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
     if (!sc || !U) return fail(CLOTH_E_INVALID, "null argument");
+    Scene& s = sc->s;
+    if (r != s.r) return fail(CLOTH_E_INVALID, "basis width differs from params.r");
+    if (!reordered(s)) return set_basis_internal(sc, U, r);
+    std::vector<double> Ui = rows_to_internal(U, s.nv, r, s.perm);
+    return set_basis_internal(sc, Ui.data(), r);
+}
+
+// U in the internal vertex order
+static cloth_status set_basis_internal(cloth_scene sc, const double* U, int32_t r) {
     Scene& s = sc->s;
     if (drop_graph(s) != CLOTH_OK) return CLOTH_E_DEVICE;
     if (r != s.r) return fail(CLOTH_E_INVALID, "basis width differs from params.r");
@@ -671,6 +771,10 @@ cloth_status cloth_set_basis(cloth_scene sc, const double* U, int32_t r) {
     if (rc0 != CLOTH_OK) return rc0;
     HIPCHECK(hipMemcpy(s.d.Ainv, inv.data(), sizeof(double) * r * r, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(s.d.Lam, s.Lam.data(), sizeof(double) * r * r, hipMemcpyHostToDevice));
+    if (s.uu_store) {
+        cloth_status rc = contact_build_uu(s);
+        if (rc != CLOTH_OK) return rc;
+    }
     s.basis_set = true;
     if (s.rho <= 0 || s.gamma <= 0) {
         cloth_status rc = cloth_estimate_chebyshev(sc, nullptr);
@@ -687,6 +791,11 @@ cloth_status cloth_set_warm_basis(cloth_scene sc, const double* U, int32_t r_war
     if (r_warm != s.r_warm) return fail(CLOTH_E_INVALID, "basis width differs from params.r_warm");
     if (drop_graph(s) != CLOTH_OK) return CLOTH_E_DEVICE;
     std::vector<double> stored, lam, inv;
+    std::vector<double> Ui;
+    if (reordered(s)) {
+        Ui = rows_to_internal(U, s.nv, r_warm, s.perm);
+        U = Ui.data();
+    }
     cloth_status rc = store_basis(s, U, r_warm, s.d_Uw, stored, lam, inv);
     if (rc != CLOTH_OK) return rc;
     HIPCHECK(hipMemcpy(s.d_Ainvw, inv.data(), sizeof(double) * r_warm * r_warm, hipMemcpyHostToDevice));
@@ -712,7 +821,7 @@ cloth_status cloth_get_forwarded(cloth_scene sc, float* dx) {
     std::vector<float> t(3 * (size_t)s.nv);
     HIPCHECK(hipDeviceSynchronize());
     HIPCHECK(hipMemcpy(t.data(), s.d_rfdx, 12 * (size_t)s.nv, hipMemcpyDeviceToHost));
-    soa_to_aos(t, dx, s.nv);
+    soa_to_aos(t, dx, s.nv, s.perm);
     return CLOTH_OK;
 }
 
@@ -728,11 +837,11 @@ cloth_status cloth_compute_basis(cloth_scene sc, int32_t r, int32_t degree, int3
     double res = 0;
     cloth_status rc = device_eigenbasis(s, r, degree, max_passes, tol, Uh, w, &p, &res, err, nullptr);
     if (rc != CLOTH_OK) return fail(rc, err);
-    if (U) std::copy(Uh.begin(), Uh.end(), U);
+    if (U) rows_to_caller(Uh, U, s.nv, r, s.perm);
     if (ritz) std::copy(w.begin(), w.end(), ritz);
     if (passes) *passes = p;
     if (residual) *residual = res;
-    return cloth_set_basis(sc, Uh.data(), r);
+    return set_basis_internal(sc, Uh.data(), r);
 }
 
 cloth_status cloth_compute_basis_static(cloth_scene sc, int32_t r, int32_t degree, int32_t max_passes, double tol,
@@ -755,11 +864,11 @@ cloth_status cloth_compute_basis_static(cloth_scene sc, int32_t r, int32_t degre
     double res = 0;
     rc = device_eigenbasis(s, r, degree, max_passes, tol, Uh, w, &p, &res, err, ws);
     if (rc != CLOTH_OK) return fail(rc, err);
-    if (U) std::copy(Uh.begin(), Uh.end(), U);
+    if (U) rows_to_caller(Uh, U, s.nv, r, s.perm);
     if (ritz) std::copy(w.begin(), w.end(), ritz);
     if (passes) *passes = p;
     if (residual) *residual = res;
-    return cloth_set_basis(sc, Uh.data(), r);
+    return set_basis_internal(sc, Uh.data(), r);
 }
 
 cloth_status cloth_add_obstacle(cloth_scene sc, const cloth_obstacle* ob) {
@@ -788,11 +897,11 @@ cloth_status cloth_set_state(cloth_scene sc, const float* x, const float* v, voi
     Scene& s = sc->s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     std::vector<float> t;
-    aos_to_soa(x, t, s.nv);
+    aos_to_soa(x, t, s.nv, s.perm);
     HIPCHECK(hipMemcpyAsync(s.d.x, t.data(), sizeof(float) * 3 * s.nv, hipMemcpyHostToDevice, st));
     HIPCHECK(hipStreamSynchronize(st));
     if (v) {
-        aos_to_soa(v, t, s.nv);
+        aos_to_soa(v, t, s.nv, s.perm);
         HIPCHECK(hipMemcpyAsync(s.d.v, t.data(), sizeof(float) * 3 * s.nv, hipMemcpyHostToDevice, st));
     } else {
         HIPCHECK(hipMemsetAsync(s.d.v, 0, sizeof(float) * 3 * s.nv, st));
@@ -814,12 +923,12 @@ cloth_status cloth_get_state(cloth_scene sc, float* x, float* v, void* stream) {
     if (x) {
         HIPCHECK(hipMemcpyAsync(t.data(), s.d.x, sizeof(float) * 3 * s.nv, hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
-        soa_to_aos(t, x, s.nv);
+        soa_to_aos(t, x, s.nv, s.perm);
     }
     if (v) {
         HIPCHECK(hipMemcpyAsync(t.data(), s.d.v, sizeof(float) * 3 * s.nv, hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
-        soa_to_aos(t, v, s.nv);
+        soa_to_aos(t, v, s.nv, s.perm);
     }
     return CLOTH_OK;
 }
@@ -1203,6 +1312,7 @@ cloth_status cloth_stage_load_block(cloth_scene sc, const float* xm, const float
                                     int64_t n_ee, const int32_t* ee, const int32_t* a_ee,
                                     const int32_t* ob_a) {
     if (!sc || !xm || !xk || !xkm1 || !z) return fail(CLOTH_E_INVALID, "null argument");
+    if (reordered(sc->s)) return fail(CLOTH_E_INVALID, "stage calls need a scene in the caller's vertex order");
     Scene& s = sc->s;
     Dev& d = s.d;
     std::vector<float> t;
@@ -1238,6 +1348,7 @@ cloth_status cloth_stage_inner(cloth_scene sc, int32_t k) {
 
 cloth_status cloth_stage_partial_ccd(cloth_scene sc, const float* xnew) {
     if (!sc || !xnew) return fail(CLOTH_E_INVALID, "null argument");
+    if (reordered(sc->s)) return fail(CLOTH_E_INVALID, "stage calls need a scene in the caller's vertex order");
     Scene& s = sc->s;
     if (!sc->c.active) return CLOTH_OK;
     std::vector<float> t;
@@ -1252,6 +1363,7 @@ cloth_status cloth_stage_partial_ccd(cloth_scene sc, const float* xnew) {
 cloth_status cloth_stage_read_block(cloth_scene sc, float* xk, int32_t* a_vt, int32_t* a_ee, int32_t* ob_a,
                                     double* dx, float* b, double* Q) {
     if (!sc) return fail(CLOTH_E_INVALID, "null argument");
+    if (reordered(sc->s)) return fail(CLOTH_E_INVALID, "stage calls need a scene in the caller's vertex order");
     Scene& s = sc->s;
     Dev& d = s.d;
     std::vector<float> t(3 * (size_t)s.nv);
@@ -1275,24 +1387,28 @@ cloth_status cloth_stage_read_block(cloth_scene sc, float* xk, int32_t* a_vt, in
 cloth_status cloth_stage_outer(cloth_scene sc, const float* xm, const float* xp, int32_t first, float* x_out,
                                double* s_out) {
     if (!sc || !xm || !xp) return fail(CLOTH_E_INVALID, "null argument");
+    if (reordered(sc->s)) return fail(CLOTH_E_INVALID, "stage calls need a scene in the caller's vertex order");
     return contact_stage_outer(sc->s, sc->c, xm, xp, first, x_out, s_out);
 }
 
 cloth_status cloth_stage_read_set(cloth_scene sc, int64_t cap, int32_t* vt, int32_t* a_vt, int64_t* n_vt,
                                   int32_t* ee, int32_t* a_ee, int64_t* n_ee, int32_t* ob_a) {
     if (!sc) return fail(CLOTH_E_INVALID, "null argument");
+    if (reordered(sc->s)) return fail(CLOTH_E_INVALID, "stage calls need a scene in the caller's vertex order");
     return contact_stage_read_set(sc->s, sc->c, cap, vt, a_vt, n_vt, ee, a_ee, n_ee, ob_a);
 }
 
 cloth_status cloth_stage_broad_phase(cloth_scene sc, const float* xm, const float* xp, int64_t cap, int32_t* vt,
                                      int64_t* n_vt, int32_t* ee, int64_t* n_ee) {
     if (!sc || !xm || !xp || !n_vt || !n_ee) return fail(CLOTH_E_INVALID, "null argument");
+    if (reordered(sc->s)) return fail(CLOTH_E_INVALID, "stage calls need a scene in the caller's vertex order");
     return contact_stage_broad_phase(sc->s, sc->c, xm, xp, cap, vt, n_vt, ee, n_ee);
 }
 
 cloth_status cloth_stage_toi(cloth_scene sc, const float* xm, const float* xp, int64_t n_vt, const int32_t* vt,
                              int64_t n_ee, const int32_t* ee, double* toi_vt, double* toi_ee) {
     if (!sc || !xm || !xp) return fail(CLOTH_E_INVALID, "null argument");
+    if (reordered(sc->s)) return fail(CLOTH_E_INVALID, "stage calls need a scene in the caller's vertex order");
     return contact_stage_toi(sc->s, sc->c, xm, xp, n_vt, vt, n_ee, ee, toi_vt, toi_ee);
 }
 

@@ -93,6 +93,9 @@ struct ContactState {
 
 using Carver = std::function<void*(size_t)>;
 
+// fills the per-vertex store of upper triangles of U_j U_j^T (Eq. (uu)) from
+// the stored basis (synchronous)
+cloth_status contact_build_uu(Scene& s);
 // carves the contact buffers (a counting carver gives the footprint)
 cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve);
 cloth_status contact_upload(Scene& s, ContactState& c);

@@ -2021,6 +2021,67 @@ __global__ void __launch_bounds__(256) k_gram_final(Dev d, const double* __restr
     Arm[e] = s;
 }
 
+// Eq. (uu), precomputed form: the upper triangle of U_j U_j^T of every
+// vertex, entry e of vertex v at UU[v tot + e] in the packed column-major
+// order of the group sums (pk_off), from the stored basis values (exact in
+// FP32 for a BF16 basis).  Block = vertex, threads over the entries.
+__device__ __forceinline__ float uu_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float uu_val(float f) { return f; }
+
+template <typename UT>
+__global__ void __launch_bounds__(256) k_uu_build(Dev d, float* __restrict__ UU) {
+    __shared__ float u[MAX_R];
+    const int r = d.r;
+    const int tot = r * (r + 1) / 2;
+    const UT* __restrict__ U = static_cast<const UT*>(d.U);
+    for (int v = blockIdx.x; v < d.nv; v += gridDim.x) {
+        for (int a = threadIdx.x; a < r; a += blockDim.x) u[a] = uu_val(U[(size_t)v * r + a]);
+        __syncthreads();
+        float* out = UU + (size_t)v * tot;
+        for (int k = 0; k < r; ++k) {
+            const float uk = u[k];
+            const int o = pk_off(k, r) - k;
+            for (int i = k + threadIdx.x; i < r; i += blockDim.x) out[o + i] = u[i] * uk;
+        }
+        __syncthreads();
+    }
+}
+
+// Group sums of the contact part of A from the store: block (entry tile,
+// group g) sums W_j UU_j over group g's share of the contact-vertex list in
+// FP64, the weights of a round of 64 vertices staged in LDS (summed as the
+// local step sums them), and writes the layout k_gram_reduce writes.
+__global__ void __launch_bounds__(256) k_uu_sum(Dev d, const int* __restrict__ cvlist,
+                                                const int* __restrict__ n_cv, double* __restrict__ gred,
+                                                const int* __restrict__ wchg, int force_k) {
+    if (gated(d.gate) || !*wchg) return;
+    const int ncv = *n_cv;
+    if (ncv == 0) return;
+    const int r = d.r;
+    const int tot = r * (r + 1) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    const int per_g = (ncv + gridDim.y - 1) / gridDim.y;
+    const int j0 = g * per_g, j1 = min(ncv, j0 + per_g);
+    __shared__ float ws[64];
+    __shared__ int vs[64];
+    double acc = 0.0;
+    for (int jb = j0; jb < j1; jb += 64) {
+        const int m = min(64, j1 - jb);
+        if (threadIdx.x < m) {
+            const int v = cvlist[jb + threadIdx.x];
+            vs[threadIdx.x] = v;
+            ws[threadIdx.x] = contact_weight(d, v, force_k);
+        }
+        __syncthreads();
+        if (e < tot)
+            for (int t = 0; t < m; ++t) acc += (double)ws[t] * (double)d.UU[(size_t)vs[t] * tot + e];
+        __syncthreads();
+    }
+    if (e < tot) gred[(size_t)g * tot + e] = acc;
+}
+
+
 constexpr int CHOL_PANEL = 16;
 
 __device__ __forceinline__ double bcast_f64(double v, int src) {
@@ -2876,6 +2937,18 @@ cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, 
     return CLOTH_OK;
 }
 
+cloth_status contact_build_uu(Scene& s) {
+    if (!s.d.UU) return CLOTH_OK;
+    const int grid = std::min(s.nv, 4096);
+    if (s.prec == CLOTH_MIXED)
+        hipLaunchKernelGGL(k_uu_build<uint16_t>, dim3(grid), dim3(256), 0, 0, s.d, s.d.UU);
+    else
+        hipLaunchKernelGGL(k_uu_build<float>, dim3(grid), dim3(256), 0, 0, s.d, s.d.UU);
+    HC(hipGetLastError());
+    HC(hipDeviceSynchronize());
+    return CLOTH_OK;
+}
+
 // The contact matrix of the iteration (Eq. (subspace_collision) with the
 // Gram of Eq. (uu)) and its factorization; it depends on the collision
 // weights only, so it may run beside the local step (on a second stream).
@@ -2884,19 +2957,25 @@ cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t
     int* wchg = c.cnt + CNT_WCHG;
     // weights forced to k (residual forwarding) differ from the spans' ones
     if (force_k) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, s.d.gate, wchg, 1, 1);
-    const int T = (s.r + 15) / 16;   // 16 x 16 tiles per side of the Gram
-    dim3 grid(c.gram_chunks, (T * (T + 1) / 2 + 4 * GRAM_TW - 1) / (4 * GRAM_TW));
-    if (s.prec == CLOTH_MIXED)
-        hipLaunchKernelGGL(k_gram<uint16_t>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
-                           d.gram_part, (const int*)wchg, force_k ? 1 : 0);
-    else
-        hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
-                           d.gram_part, (const int*)wchg, force_k ? 1 : 0);
     const int tot = s.r * (s.r + 1) / 2;
     double* gred = d.Amat;
     double* Arm = d.Amat + (size_t)GRAM_GROUPS * tot;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((tot + 255) / 256, GRAM_GROUPS), dim3(256), 0, st, d, d.gram_part,
-                       c.gram_chunks, c.cnt + 6, gred, (const int*)wchg);
+    if (d.UU) {
+        // Eq. (uu) from the precomputed store, straight into the group sums
+        hipLaunchKernelGGL(k_uu_sum, dim3((tot + 255) / 256, GRAM_GROUPS), dim3(256), 0, st, d, c.cvlist,
+                           c.cnt + 6, gred, (const int*)wchg, force_k ? 1 : 0);
+    } else {
+        const int T = (s.r + 15) / 16;   // 16 x 16 tiles per side of the Gram
+        dim3 grid(c.gram_chunks, (T * (T + 1) / 2 + 4 * GRAM_TW - 1) / (4 * GRAM_TW));
+        if (s.prec == CLOTH_MIXED)
+            hipLaunchKernelGGL(k_gram<uint16_t>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
+                               d.gram_part, (const int*)wchg, force_k ? 1 : 0);
+        else
+            hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, st, d, c.cvlist, c.cnt + 6, c.gram_chunks,
+                               d.gram_part, (const int*)wchg, force_k ? 1 : 0);
+        hipLaunchKernelGGL(k_gram_reduce, dim3((tot + 255) / 256, GRAM_GROUPS), dim3(256), 0, st, d, d.gram_part,
+                           c.gram_chunks, c.cnt + 6, gred, (const int*)wchg);
+    }
     hipLaunchKernelGGL(k_gram_final, dim3((tot + 255) / 256), dim3(256), 0, st, d, (const double*)gred, c.cnt + 6,
                        Arm, (const int*)wchg);
     hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(FT), chol_lds_bytes(s.r), st, d, (const double*)Arm,

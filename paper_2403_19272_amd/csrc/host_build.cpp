@@ -7,7 +7,9 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <numeric>
 #include <utility>
+#include <vector>
 
 #include "scene.hpp"
 
@@ -30,6 +32,79 @@ V3 vtx(const std::vector<double>& X, int i) { return {X[3 * i], X[3 * i + 1], X[
 double cotan(V3 a, V3 b) { return dot(a, b) / norm(cross(a, b)); }
 
 }  // namespace
+
+// Reverse Cuthill-McKee order of the mesh's vertex graph (edges of the
+// triangles): order[i] is the input vertex placed at position i.  Each
+// connected component starts from a pseudo-peripheral vertex (the last vertex
+// reached by a breadth-first search from its lowest-degree vertex, repeated
+// while the search depth grows); a search visits the unvisited neighbours of
+// each vertex in increasing degree (ties by index), and the whole order is
+// reversed at the end.  Neighbouring vertices get nearby positions, so the
+// sweeps' gathers stay within a narrow band of the state vectors.
+std::vector<int> rcm_order(int nv, int nt, const int32_t* tris) {
+    std::vector<std::vector<int>> adj(nv);
+    for (int t = 0; t < nt; ++t)
+        for (int c = 0; c < 3; ++c) {
+            const int a = tris[3 * t + c], b = tris[3 * t + (c + 1) % 3];
+            adj[a].push_back(b);
+            adj[b].push_back(a);
+        }
+    for (auto& l : adj) {
+        std::sort(l.begin(), l.end());
+        l.erase(std::unique(l.begin(), l.end()), l.end());
+    }
+    std::vector<int> deg(nv);
+    for (int v = 0; v < nv; ++v) deg[v] = (int)adj[v].size();
+    for (auto& l : adj)
+        std::stable_sort(l.begin(), l.end(), [&](int a, int b) { return deg[a] < deg[b]; });
+    std::vector<int> level(nv, -1), order, comp;
+    order.reserve(nv);
+    std::vector<char> done(nv, 0);
+    // breadth-first levels from `root` over the unplaced vertices; returns the
+    // depth and leaves the vertices in visiting order in `out`
+    auto bfs = [&](int root, std::vector<int>& out) {
+        out.clear();
+        out.push_back(root);
+        level[root] = 0;
+        int depth = 0;
+        for (size_t h = 0; h < out.size(); ++h) {
+            const int v = out[h];
+            for (int w : adj[v])
+                if (!done[w] && level[w] < 0) {
+                    level[w] = level[v] + 1;
+                    depth = std::max(depth, level[w]);
+                    out.push_back(w);
+                }
+        }
+        for (int v : out) level[v] = -1;
+        return depth;
+    };
+    std::vector<int> by_deg(nv);
+    std::iota(by_deg.begin(), by_deg.end(), 0);
+    std::stable_sort(by_deg.begin(), by_deg.end(), [&](int a, int b) { return deg[a] < deg[b]; });
+    for (int start : by_deg) {
+        if (done[start]) continue;
+        int root = start;
+        int depth = bfs(root, comp);
+        for (int it = 0; it < 8; ++it) {
+            // restart from the last vertex reached
+            int far = comp.back();
+            const int d2 = bfs(far, comp);
+            if (d2 <= depth) {
+                bfs(root, comp);
+                break;
+            }
+            root = far;
+            depth = d2;
+        }
+        for (int v : comp) {
+            done[v] = 1;
+            order.push_back(v);
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
 
 std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, double dt,
                         const cloth_material* mat, const cloth_solver_params* prm) {
@@ -238,6 +313,7 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
 
     s.r = prm->r;
     s.r_warm = prm->r_warm;
+    s.uu_store = prm->uu_store ? 1 : 0;
     s.iters_in = prm->iters_inner;
     s.iters_out = prm->iters_outer;
     s.rho = prm->cheb_rho;

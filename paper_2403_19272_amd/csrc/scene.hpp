@@ -96,6 +96,7 @@ struct Dev {
     double* gram_part;        // GRAM_CHUNKS * r * r Gram partials (FP64)
     unsigned long long* dxbits;  // per-iteration max |dx| as double bits
     double* gvec;             // r * 3: g = U^T r0 (FP64)
+    float* UU;                // nv * r (r + 1) / 2: upper triangles of U_j U_j^T (Eq. (uu)), or null
     // contact (read when the contact flag is set)
     const int* vslot_ptr;     // nv+1: vertex -> slots of pair constraints
     const int* vslot;         // slot ids (4 * constraint + corner), sorted per vertex
@@ -127,6 +128,8 @@ struct Scene {
     double bp_mu0 = 0.0, bp_kappa = 1.0;   // reusable candidate superset: box growth margins
     int bp_reuse = 0;                      // ... and whether it is used
     int r_warm = 0;                   // width of the modal warm-start basis (0: the reuse basis)
+    int uu_store = 0;                 // contact matrix from the precomputed U_j U_j^T store
+    std::vector<int> perm;            // internal vertex i is the caller's perm[i] (empty: the caller's order)
     void* d_Uw = nullptr;             // its stored values (nv * r_warm)
     double* d_Ainvw = nullptr;        // inverse of its Galerkin matrix (r_warm * r_warm)
     bool warm_set = false;
@@ -212,6 +215,7 @@ void timing_begin(Scene& s, int id, hipStream_t st);
 void timing_end(Scene& s, hipStream_t st);
 
 // host precompute (host_build.cpp)
+std::vector<int> rcm_order(int nv, int nt, const int32_t* tris);
 std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, double dt,
                         const cloth_material* mat, const cloth_solver_params* prm);
 // device eigenbasis (eig.hip).  workspace: device memory of at least

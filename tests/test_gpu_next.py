@@ -104,3 +104,94 @@ def test_warm_start_with_a_wider_basis_on_contact():
               flush=True)
         assert err <= 1e-5
     assert sg["n_constraints"] > 0
+
+
+def _shuffled(sc, seed):
+    """The same scene with its vertices renumbered at random: natural vertex
+    i becomes shuf[i]; returns the scene and inv (caller j = natural inv[j])."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    shuf = rng.permutation(sc.nv)
+    inv = np.argsort(shuf)
+    sc2 = dataclasses.replace(sc, tris=shuf[sc.tris].astype(np.int32), rest=sc.rest[inv], x0=sc.x0[inv],
+                              v0=sc.v0[inv], pinned=sc.pinned[inv])
+    return sc2, inv
+
+
+def test_reordered_scene_matches_the_natural_order():
+    """The small hanging cloth (corners pinned, no contact) with shuffled
+    vertex numbers, stepped with the vertex reorder on, gives in the
+    caller's numbering the natural-order scene's result to FP32 rounding
+    after 10 steps: positions, velocities, pins, the basis and H cross the
+    boundary in the caller's order.  With contact the two differ beyond
+    rounding once a near-threshold contact decision flips (summation orders
+    differ), so there only the outcome is checked.  The stage-level calls
+    refuse a reordered scene."""
+    import paper_2403_19272_amd as P
+    sc = scenegen.config(0)
+    o, U, rho = oracle_side(sc, "fp32")
+    sc2, inv = _shuffled(sc, 9)
+    assert sc2.pinned.sum() == 2 and not np.array_equal(sc2.pinned, sc.pinned)
+    a = gpu_side(sc, U, "fp32", rho)
+    b = gpu_side(sc2, U[inv], "fp32", rho, reorder=True)
+    Ha, Hb = a.system_matrix(), b.system_matrix()
+    assert abs(Hb - Ha[inv][:, inv]).max() <= 1e-12 * abs(Ha).max()
+    for s in range(sc.steps):
+        a.step(sc.gravity)
+        b.step(sc.gravity)
+    xa, va = a.get_state()
+    xb, vb = b.get_state()
+    diag = np.linalg.norm(xa.max(0) - xa.min(0))
+    err = np.linalg.norm(xb - xa[inv], axis=1).max() / diag
+    moved = np.linalg.norm(xa - sc.x0, axis=1).max() / diag
+    print(f"[reorder] err/diag={err:.2e} moved/diag={moved:.2e}", flush=True)
+    assert moved > 5e-3 and err <= 1e-5
+    assert np.array_equal(xb[sc2.pinned == 1], sc2.x0[sc2.pinned == 1])
+    with pytest.raises(P.ClothError) as e:
+        b.stage_partial_ccd(xb)
+    assert e.value.code == P.CLOTH_E_INVALID
+    # a contact scene: the reordered steps stay finite and in contact
+    cc = scenegen.drop_cloth(48, seed=31, obstacle="cylinder", r=16, steps=3, d_hat=1e-3, side=47 / 127.0)
+    oc, Uc, _ = oracle_side(cc, "mixed", rho=0.95, gamma=0.6)
+    cc2, inv2 = _shuffled(cc, 11)
+    g = gpu_side(cc2, Uc[inv2], "mixed", 0.95, gamma=0.6, reorder=True)
+    x0 = scenegen.draped_state(cc, seed=5)[inv2]
+    g.set_state(x0, np.zeros_like(x0))
+    st = g.step(cc.gravity, n=3)
+    x, v = g.get_state()
+    assert np.isfinite(x).all() and st["n_constraints"] > 0
+
+
+def test_reorder_restores_sweep_speed_on_a_shuffled_grid():
+    """Timing only (printed): a 256 x 256 grid with shuffled numbering,
+    stepped in free fall with and without the reorder, beside the natural
+    order; the reordered scene matches the natural one to FP32 rounding."""
+    import time
+
+    import paper_2403_19272_amd as P
+    sc = scenegen.drop_cloth(256, seed=1, obstacle="sphere", r=64, steps=3, d_hat=1e-3)
+    sc2, inv = _shuffled(sc, 10)
+
+    def make(s, **kw):
+        g = P.ClothScene(s.tris, s.rest, dt=s.dt, density=s.density, k_stretch=s.k_stretch, k_bend=s.k_bend,
+                         d_hat=s.d_hat, r=s.r, iters_inner=10, iters_outer=3, cheb_rho=0.99, cheb_gamma=0.6,
+                         precision=P.CLOTH_MIXED, self_contact=True, **kw)
+        return g
+
+    nat = make(sc)
+    U = nat.compute_basis(degree=200, max_passes=8, tol=5e-2, return_basis=True)["U"]
+    shuf, reo = make(sc2), make(sc2, reorder=True)
+    for g in (shuf, reo):
+        g.set_basis(U[inv])
+    times = {}
+    for name, g, x0 in (("natural", nat, sc.x0), ("shuffled", shuf, sc2.x0), ("reordered", reo, sc2.x0)):
+        g.set_state(x0, np.zeros_like(x0))
+        g.step(sc.gravity, n=2)   # (reading the statistics waits for the steps)
+        t0 = time.perf_counter()
+        g.step(sc.gravity, n=5)
+        times[name] = (time.perf_counter() - t0) / 5 * 1e3
+    print("[reorder timing] ms/step " + " ".join(f"{k} {v:.3f}" for k, v in times.items()), flush=True)
+    xn, _ = nat.get_state()
+    xr, _ = reo.get_state()
+    err = np.linalg.norm(xr - xn[inv], axis=1).max() / np.linalg.norm(xn.max(0) - xn.min(0))
+    assert err <= 1e-5

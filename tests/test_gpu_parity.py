@@ -140,10 +140,13 @@ def test_partial_ccd_life_spans_bit_exact():
     assert np.array_equal(got["ob_a"][0], ob)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "mixed"])
-def test_inner_iteration_with_contact(precision):
+@pytest.mark.parametrize("precision,uu", [("fp32", False), ("mixed", False), ("fp32", True), ("mixed", True)])
+def test_inner_iteration_with_contact(precision, uu):
+    """Inner iterations with VT, EE and obstacle constraints against the
+    oracle; uu: the contact matrix from the precomputed Eq. (uu) store
+    instead of the matrix-core Gram."""
     sc, o, U, blk = contact_block(precision=precision)
-    g = gpu_side(sc, U, precision, 0.95)
+    g = gpu_side(sc, U, precision, 0.95, uu_store=uu)
     g.stage_load_block(blk["xm"], blk["xk"], blk["xkm1"], blk["z"], blk["vt"], blk["a_vt"], blk["ee"],
                        blk["a_ee"], blk["ob_a"])
     k = 4
@@ -157,8 +160,32 @@ def test_inner_iteration_with_contact(precision):
     err = vertex_err(got["xk"], xk1) / diag
     upd = vertex_err(xk1, blk["xk"]) / diag
     qerr = np.abs(got["Q"] - o.trace["Q"]).max() / np.abs(o.trace["Q"]).max()
-    print(f"[inner {precision}] err/diag={err:.3e} update/diag={upd:.3e} Q rel={qerr:.2e}", flush=True)
+    print(f"[inner {precision} uu={uu}] err/diag={err:.3e} update/diag={upd:.3e} Q rel={qerr:.2e}", flush=True)
     assert upd > 1e-4
+    assert err <= 1e-5
+    assert qerr <= 1e-3
+
+
+def test_uu_store_steps_match_the_gram_steps():
+    """Whole steps with the contact matrix summed from the precomputed
+    Eq. (uu) store agree with the matrix-core Gram's steps to FP32
+    rounding (the two sum A in different orders)."""
+    sc = scenegen.drop_cloth(48, seed=31, obstacle="cylinder", r=16, steps=3, d_hat=1e-3, side=47 / 127.0)
+    o, U, rho = oracle_side(sc, "mixed", rho=0.95, gamma=0.6)
+    a = gpu_side(sc, U, "mixed", 0.95, gamma=0.6)
+    b = gpu_side(sc, U, "mixed", 0.95, gamma=0.6, uu_store=True)
+    x0 = scenegen.draped_state(sc, seed=5)   # the arc's vertices touch the cylinder
+    for g in (a, b):
+        g.set_state(x0, np.zeros_like(x0))
+    for s in range(sc.steps):
+        sa = a.step(sc.gravity)
+        sb = b.step(sc.gravity)
+    xa, _ = a.get_state()
+    xb, _ = b.get_state()
+    err = vertex_err(xb, xa) / bbox_diag(xa)
+    print(f"[uu steps] constraints {sa['n_constraints']}/{sb['n_constraints']} contact vertices "
+          f"{sb['n_contact_vertices']} err/diag={err:.2e}", flush=True)
+    assert sb["n_contact_vertices"] > 20 and b.footprint > a.footprint
     assert err <= 1e-5
 
 

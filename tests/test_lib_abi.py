@@ -41,6 +41,24 @@ def test_status_strings_and_footprint_on_host():
     assert P.lib.cloth_query_footprint(ctypes.byref(mesh2), ctypes.byref(prm), ctypes.byref(n)) == P.CLOTH_E_MESH
 
 
+def test_uu_store_adds_its_triangles_to_the_footprint_on_host():
+    """The precomputed Eq. (uu) store takes r (r + 1) / 2 FP32 per vertex of
+    the arena (plus at most one alignment pad)."""
+    import paper_2403_19272_amd as P
+    import scenegen
+    sc = scenegen.config(0)
+    tris = np.ascontiguousarray(sc.tris, np.int32)
+    mesh = P.Mesh(sc.nv, sc.nt, tris.ctypes.data, None)
+    got = []
+    for uu in (0, 1):
+        prm = P.SolverParams(r=16, iters_inner=20, iters_outer=1, cheb_delay=3, self_contact=1, uu_store=uu)
+        n = ctypes.c_size_t(0)
+        assert P.lib.cloth_query_footprint(ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(n)) == 0
+        got.append(n.value)
+    need = sc.nv * 16 * 17 // 2 * 4
+    assert need <= got[1] - got[0] <= need + 256
+
+
 def test_init_rejects_bad_budgets_tolerances_and_strain_limits_on_host():
     """Argument checks that run before any device call: a per-step budget
     beyond the norm slots, non-finite tolerances, strain limits outside
@@ -70,3 +88,34 @@ def test_init_rejects_bad_budgets_tolerances_and_strain_limits_on_host():
                          d_hat=1e-3, alpha=0.8)
         assert init(bad, ok) == P.CLOTH_E_INVALID, (smin, smax)
         assert "strain limits" in P.lib.cloth_last_error().decode()
+
+
+def test_vertex_order_restores_a_narrow_band_on_host():
+    """cloth_vertex_order (reverse Cuthill-McKee) is a permutation, and on a
+    grid whose vertex numbering was shuffled it brings the bandwidth of the
+    edge graph back near the natural row-major numbering's (n + 1), far
+    below the shuffled one; it is deterministic."""
+    import paper_2403_19272_amd as P
+    import scenegen
+    n = 40
+    tris = scenegen.grid_triangles(n)
+    rng = np.random.default_rng(3)
+    shuf = rng.permutation(n * n)            # new index of old vertex i is shuf[i]
+    t2 = shuf[tris].astype(np.int32)
+
+    def band(t, order=None):
+        pos = np.arange(n * n) if order is None else np.argsort(order)
+        e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+        return int(np.abs(pos[e[:, 0]] - pos[e[:, 1]]).max())
+
+    o = P.vertex_order(t2, n * n)
+    assert np.array_equal(np.sort(o), np.arange(n * n))
+    assert np.array_equal(o, P.vertex_order(t2, n * n))
+    assert band(tris) == n + 1
+    assert band(t2) > 10 * n
+    assert band(t2, o) <= 2 * (n + 1)
+    bad = np.array([[0, 1, 5]], np.int32)
+    mesh = P.Mesh(3, 1, bad.ctypes.data, None)
+    out = np.empty(3, np.int32)
+    assert P.lib.cloth_vertex_order(ctypes.byref(mesh), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == \
+        P.CLOTH_E_MESH
