@@ -349,7 +349,8 @@ def batch_main(args, P, torch):
             acc[f"scene{i}_nv{scs[i].nv}"] = oracle_error(scs[i], bases[i], *states[i], iters,
                                                           st0[i]["cheb_rho"], st0[i]["cheb_gamma"], P)
     bg.close()
-    best = forms["mixed_one_graph"]
+    best_name = max(("mixed_streams", "mixed_one_graph"), key=lambda k: forms[k]["value"])
+    best = forms[best_name]
     out = {
         "metric": METRIC, "value": best["value"], "unit": "vertex-iters/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
@@ -357,8 +358,8 @@ def batch_main(args, P, torch):
         "config": {"workload": f"64 uneven cloths, {min(s.nv for s in scs)}..{max(s.nv for s in scs)} "
                                f"vertices ({sum(s.nv for s in scs)} in all), each dropped onto its own "
                                f"sphere, self contact, dt=1/200 s, {iters} PD iterations/step, r=32 BF16 "
-                               f"basis; one graph launch per step for all; timed window of {K} steps "
-                               f"from step {preroll} (in contact)",
+                               f"basis; all scenes stepped together ({best_name.replace('mixed_', '')}); "
+                               f"timed window of {K} steps from step {preroll} (in contact)",
                    "scenes": len(scs), "vertices": sum(s.nv for s in scs), "iters_per_step": iters},
         "p50_step_ms": best["p50_step_ms"], "p99_step_ms": best["p99_step_ms"],
         "forms": forms,
