@@ -81,11 +81,26 @@ typedef struct {
  *   K_base     growth base K of Eq. (exp) (the paper uses 2)
  *   a_max      cap on the life span a
  *   d_hat      contact target distance (m)
- *   alpha      filter back-off, s = alpha * t_TOI (the paper uses 0.8) */
+ *   alpha      filter back-off, s = alpha * t_TOI (the paper uses 0.8)
+ *   friction   friction coefficient mu of obstacle contacts (0: frictionless).
+ *              Lagged friction (sec. 8.4 uses a lagged friction Hessian at
+ *              every local/global iteration): an obstacle constraint of
+ *              vertex v in the contact band, with unit normal n, normal
+ *              force lambda = w (R + d_hat - |radial|) of its barrier weight
+ *              w and tangential slip u_T of (x - x*) - h v_s over the step
+ *              (x* the step's start, v_s = omega R (axis x n) the surface
+ *              velocity of a spinning obstacle), adds the weight
+ *              mu lambda f1(|u_T|) / |u_T| with the target x - u_T, where
+ *              f1(y) = 2 y / eps - y^2 / eps^2 below eps = friction_eps_v h
+ *              and 1 above (a smoothed Coulomb law: the force is mu lambda
+ *              while slipping, proportional to the slip while sticking)
+ *   friction_eps_v
+ *              the sticking velocity threshold (m/s); <= 0: 1e-3 */
 typedef struct {
     double density, k_stretch, k_bend, sigma_min, sigma_max, k_contact, K_base;
     int32_t a_max;
     double d_hat, alpha;
+    double friction, friction_eps_v;
 } cloth_material;
 
 /* Solver settings.
@@ -440,7 +455,8 @@ cloth_status cloth_stage_toi(cloth_scene s, const float* xm, const float* xp, in
 /* Loads a block state: x- (start of block), x^k, x^{k-1}, the inertia target
  * z, and a constraint set (sorted VT and EE lists with life spans, and
  * per-vertex obstacle life spans ob_a[j*nv + v], -1 = not a member).  The
- * frozen constraint data are computed from xm. */
+ * frozen constraint data are computed from xm, which also stands for the
+ * step's start x* of the friction slip. */
 cloth_status cloth_stage_load_block(cloth_scene s, const float* xm, const float* xk,
                                     const float* xkm1, const float* z, int64_t n_vt,
                                     const int32_t* vt, const int32_t* a_vt, int64_t n_ee,

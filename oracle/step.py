@@ -54,6 +54,8 @@ class Params:
     warm_iters: int = 0        # modal warm-start iterations (0 = start from z)
     rf_iters: int = 0          # residual-forwarding iterations (0 = off)
     rf_toi: float = 0.5        # forward the residual when the exiting t_TOI is below this
+    friction: float = 0.0      # friction coefficient mu of obstacle contacts (0 = frictionless)
+    friction_eps_v: float = 1e-3   # sticking velocity threshold (m/s)
 
 
 @dataclass
@@ -62,6 +64,7 @@ class Obst:
     center: np.ndarray
     radius: float
     axis: np.ndarray
+    omega: float = 0.0   # spin about the axis (rad/s): the surface moves at omega R (axis x n)
 
 
 @dataclass
@@ -215,6 +218,39 @@ def obstacle_toi(ob: Obst, xm: np.ndarray, xp: np.ndarray) -> np.ndarray:
     return toi
 
 
+def obstacle_friction(ob: Obst, x: np.ndarray, xs: np.ndarray, w: np.ndarray, h: float, d_hat: float,
+                      mu: float, eps_v: float):
+    """Lagged friction of obstacle contacts (section 8.4: a lagged friction
+    Hessian at every local/global iteration), a smoothed Coulomb law.  For a
+    vertex in the contact band (signed distance below d_hat) with unit
+    normal n, normal force lambda = w (R + d_hat - |radial|) of its barrier
+    weight w, and tangential slip u_T: the tangential part of the motion over
+    the step (x - xs) relative to the surface, which moves by
+    h omega R (axis x n), the friction term is a weight
+        wf = mu lambda f1(|u_T|) / |u_T|,
+        f1(y) = 2 y / eps - y^2 / eps^2 for y < eps = eps_v h, 1 beyond,
+    pulling toward x - u_T, so its force wf |u_T| is mu lambda while
+    slipping and grows linearly from zero while sticking.  Returns (wf, u_T);
+    wf = 0 outside the band."""
+    phi, o, rad = obstacle_phi(ob, x)
+    band = (phi < d_hat) & (rad > 0)
+    wf = np.zeros(len(x))
+    uT = np.zeros_like(x)
+    if mu <= 0 or not band.any():
+        return wf, uT
+    n = o[band] / rad[band, None]
+    vs_h = h * ob.omega * ob.radius * np.cross(ob.axis, n)
+    u = (x[band] - xs[band]) - vs_h
+    ut = u - np.sum(u * n, axis=1)[:, None] * n
+    y = np.linalg.norm(ut, axis=1)
+    eps = eps_v * h
+    f = np.where(y < eps, 2.0 / eps - y / eps ** 2, 1.0 / np.where(y > 0, y, 1.0))
+    lam = w[band] * (ob.radius + d_hat - rad[band])
+    wf[band] = mu * lam * f
+    uT[band] = ut
+    return wf, uT
+
+
 class Oracle:
     """FP64 reference solver for one scene; state is (x, v)."""
 
@@ -253,11 +289,13 @@ class Oracle:
         return np.ldexp(self.m.k_contact, a.astype(np.int64)) if self.p.K_base == 2.0 else \
             self.m.k_contact * self.p.K_base ** a
 
-    def _collision_terms(self, C: Constraints, x: np.ndarray):
+    def _collision_terms(self, C: Constraints, x: np.ndarray, xs: Optional[np.ndarray] = None):
         """Per-vertex W = sum w_p and WY = sum w_p y_{p,v} over constraints.
         VT/EE: half-space projection with the normal and closest-point
         parameters frozen at x-; obstacles: projection onto the surface offset
-        by d_hat."""
+        by d_hat, plus the lagged friction term (`obstacle_friction`, slip
+        measured from the step's start xs) when the friction coefficient is
+        positive."""
         nv = self.m.nv
         W = np.zeros(nv)
         WY = np.zeros((nv, 3))
@@ -288,6 +326,11 @@ class Oracle:
                     o[inside] * ((ob.radius + dh) / rad[inside])[:, None]
                 np.add.at(W, v, w[sel])
                 np.add.at(WY, v, w[sel][:, None] * y)
+                if self.p.friction > 0:
+                    wf, uT = obstacle_friction(ob, x[v], (self.x if xs is None else xs)[v], w[sel], self.m.h,
+                                               dh, self.p.friction, self.p.friction_eps_v)
+                    np.add.at(W, v, wf)
+                    np.add.at(WY, v, wf[:, None] * (x[v] - uT))
         return W, WY
 
     @staticmethod
@@ -459,14 +502,15 @@ class Oracle:
         dx[~self.free] = 0
         return dx
 
-    def iterate(self, xk, xkm1, k, C, inertia, xm, frozen=None):
+    def iterate(self, xk, xkm1, k, C, inertia, xm, frozen=None, xs=None):
         """One inner PD iteration from x^k (history x^{k-1}) -> x^{k+1}.
         `frozen` = (b, W) replaces the local step by a fixed right-hand side
-        and diagonal (used to check the global solve on its own)."""
+        and diagonal (used to check the global solve on its own); xs: the
+        step's start for the friction slip (default: the current state)."""
         m, p = self.m, self.p
         free = self.free
         if frozen is None:
-            W, WY = self._collision_terms(C, xk)
+            W, WY = self._collision_terms(C, xk, xs)
             b = inertia + elastic_rhs(m, xk) + WY
         else:
             b, W = frozen

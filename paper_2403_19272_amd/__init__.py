@@ -51,7 +51,8 @@ class Material(C.Structure):
     _fields_ = [("density", C.c_double), ("k_stretch", C.c_double), ("k_bend", C.c_double),
                 ("sigma_min", C.c_double), ("sigma_max", C.c_double),
                 ("k_contact", C.c_double), ("K_base", C.c_double), ("a_max", C.c_int32),
-                ("d_hat", C.c_double), ("alpha", C.c_double)]
+                ("d_hat", C.c_double), ("alpha", C.c_double), ("friction", C.c_double),
+                ("friction_eps_v", C.c_double)]
 
 
 class SolverParams(C.Structure):
@@ -201,7 +202,8 @@ class ClothScene:
                  tol_outer=0.0, cheb_rho=0.0, cheb_gamma=0.0, cheb_delay=3,
                  precision=CLOTH_PLAIN_FP32, self_contact=False, pair_capacity=0,
                  debug_tangles=False, broad_margin=0.0, broad_margin_motion=0.0, r_warm=0,
-                 broad_reuse=False, uu_store=False, reorder=False, arena=None):
+                 broad_reuse=False, uu_store=False, reorder=False, friction=0.0, friction_eps_v=0.0,
+                 arena=None):
         self._tris = np.ascontiguousarray(tris, np.int32)
         rest = _f32(rest)
         nv = rest.shape[0]
@@ -210,7 +212,7 @@ class ClothScene:
         self.mesh = Mesh(nv, self._tris.shape[0], self._tris.ctypes.data, None if self._pinned is None
                          else self._pinned.ctypes.data)
         self.mat = Material(density, k_stretch, k_bend, sigma_min, sigma_max, k_contact, K_base, a_max,
-                            d_hat, alpha)
+                            d_hat, alpha, friction, friction_eps_v)
         self.params = SolverParams(r, iters_inner, iters_outer, tol_inner, tol_outer, cheb_rho,
                                    cheb_gamma, cheb_delay, precision, int(bool(self_contact)),
                                    pair_capacity, int(bool(debug_tangles)), broad_margin,

@@ -508,6 +508,8 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     }
     if (params->precision != CLOTH_PLAIN_FP32 && params->precision != CLOTH_MIXED)
         return fail(CLOTH_E_INVALID, "unknown precision");
+    if (!(mat->friction >= 0 && std::isfinite(mat->friction)) || !std::isfinite(mat->friction_eps_v))
+        return fail(CLOTH_E_INVALID, "friction must be finite and >= 0");
     std::unique_ptr<cloth_scene_s> sc(new (std::nothrow) cloth_scene_s());
     if (!sc) return fail(CLOTH_E_OOM, "host allocation");
     Scene& s = sc->s;
@@ -578,6 +580,8 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     d.edges = s.d_edges;
     d.U = s.d_U;
     d.smin = (float)s.smin;
+    d.mu = (float)s.mu;
+    d.feps = s.feps;
     d.smax = (float)s.smax;
 
     // static uploads
@@ -886,6 +890,7 @@ cloth_status cloth_add_obstacle(cloth_scene sc, const cloth_obstacle* ob) {
         o.a[i] = an > 0 ? ob->axis[i] / an : (i == 0 ? 1.0 : 0.0);
     }
     o.R = ob->radius;
+    o.wh = ob->omega * s.h;
     cloth_status rc = drop_graph(s);
     if (rc != CLOTH_OK) return rc;
     s.obst.push_back(o);
@@ -1319,6 +1324,8 @@ cloth_status cloth_stage_load_block(cloth_scene sc, const float* xm, const float
     aos_to_soa(xm, t, s.nv);
     HIPCHECK(hipMemcpy(d.xm, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(d.x, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
+    // the block's start stands for the step's start (the friction slip)
+    HIPCHECK(hipMemcpy(d.xstar, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
     aos_to_soa(xk, t, s.nv);
     HIPCHECK(hipMemcpy(d.xk, t.data(), 12 * (size_t)s.nv, hipMemcpyHostToDevice));
     s.x4_valid = false;

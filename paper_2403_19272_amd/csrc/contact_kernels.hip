@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "contact.hpp"
+#include "friction.hpp"
 #include "kernels.hpp"
 
 namespace cloth {
@@ -1854,7 +1855,19 @@ __device__ __forceinline__ float contact_weight(const Dev& d, int v, int force_k
         int a = d.ob_a[j * d.nv + v];
         if (a < 0) continue;
         if (force_k) a = 0;
-        Wv += (d.Kb == 2.0f) ? ldexpf(d.kc, a) : d.kc * powf(d.Kb, (float)a);
+        const float w = (d.Kb == 2.0f) ? ldexpf(d.kc, a) : d.kc * powf(d.Kb, (float)a);
+        Wv += w;
+        if (d.mu > 0.0f) {
+            // the friction weight, from the same iterate as the local step
+            const int n = d.nv;
+            const float x0 = d.xk[v], x1 = d.xk[n + v], x2 = d.xk[2 * n + v];
+            const ObstD& o = d.ob[j];
+            double ox, oy, oz;
+            const double rad = obstacle_radial(o, x0, x1, x2, ox, oy, oz);
+            double ux, uy, uz;
+            Wv += (float)obstacle_friction(d, o, w, ox, oy, oz, rad, x0, x1, x2, d.xstar[v], d.xstar[n + v],
+                                           d.xstar[2 * n + v], ux, uy, uz);
+        }
     }
     return Wv;
 }
@@ -2955,8 +2968,10 @@ cloth_status contact_build_uu(Scene& s) {
 cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t st) {
     Dev& d = s.d;
     int* wchg = c.cnt + CNT_WCHG;
-    // weights forced to k (residual forwarding) differ from the spans' ones
-    if (force_k) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, s.d.gate, wchg, 1, 1);
+    // weights forced to k (residual forwarding) differ from the spans' ones;
+    // friction weights follow the iterate, so they change every iteration
+    if (force_k || (s.mu > 0 && !s.obst.empty()))
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, s.d.gate, wchg, 1, 1);
     const int tot = s.r * (s.r + 1) / 2;
     double* gred = d.Amat;
     double* Arm = d.Amat + (size_t)GRAM_GROUPS * tot;

@@ -121,6 +121,8 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     s.amax = mat->a_max > 0 ? mat->a_max : 20;
     s.dhat = mat->d_hat;
     s.alpha = mat->alpha > 0 ? mat->alpha : 0.8;
+    s.mu = mat->friction > 0 ? mat->friction : 0.0;
+    s.feps = (mat->friction_eps_v > 0 ? mat->friction_eps_v : 1e-3) * dt;
     // strain limits: 0, 0 reads as the rotation projection (1, 1)
     s.smin = (mat->sigma_min == 0 && mat->sigma_max == 0) ? 1.0 : mat->sigma_min;
     s.smax = (mat->sigma_min == 0 && mat->sigma_max == 0) ? 1.0 : mat->sigma_max;

@@ -18,6 +18,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include "friction.hpp"
 #include "kernels.hpp"
 
 namespace cloth {
@@ -504,20 +505,24 @@ __global__ void __launch_bounds__(TPB) k_local_residual(Dev d, int flags) {
                 if (force_k) a = 0;
                 float w = (d.Kb == 2.0f) ? ldexpf(d.kc, a) : d.kc * powf(d.Kb, (float)a);
                 const ObstD& o = d.ob[j];
-                double ox = x0 - o.c[0], oy = x1 - o.c[1], oz = x2 - o.c[2];
-                if (o.kind == CLOTH_CYLINDER) {
-                    double ax = ox * o.a[0] + oy * o.a[1] + oz * o.a[2];
-                    ox -= ax * o.a[0];
-                    oy -= ax * o.a[1];
-                    oz -= ax * o.a[2];
-                }
-                double rad = sqrt(ox * ox + oy * oy + oz * oz);
+                double ox, oy, oz;
+                const double rad = obstacle_radial(o, x0, x1, x2, ox, oy, oz);
                 double sc = 0.0;   // y - x = (sc - 1) * radial
                 if (rad - o.R < d.dhat && rad > 0) sc = (o.R + d.dhat) / rad - 1.0;
                 Wv += w;
                 wx += w * (float)(sc * ox);
                 wy += w * (float)(sc * oy);
                 wz += w * (float)(sc * oz);
+                if (d.mu > 0.0f) {
+                    double ux, uy, uz;
+                    const double wf = obstacle_friction(d, o, w, ox, oy, oz, rad, x0, x1, x2, d.xstar[v],
+                                                        d.xstar[n + v], d.xstar[2 * n + v], ux, uy, uz);
+                    // weight wf toward the target x - u_T: w (y - x) = -wf u_T
+                    Wv += (float)wf;
+                    wx += (float)(-wf * ux);
+                    wy += (float)(-wf * uy);
+                    wz += (float)(-wf * uz);
+                }
             }
             d.W[v] = Wv;
             if (!linear) {

@@ -61,6 +61,7 @@ static_assert(sizeof(TriRec) == 32, "TriRec layout");
 struct ObstD {
     int kind;        // CLOTH_SPHERE / CLOTH_CYLINDER (axis a unit length)
     double c[3], a[3], R;
+    double wh;       // spin about the axis times the time step (rad per step)
 };
 
 // Device pointers and sizes handed to kernels by value.
@@ -107,6 +108,8 @@ struct Dev {
     float kc, Kb;             // initial weight k and growth base K of Eq. (exp)
     double dhat;
     float smin, smax;         // strain limits of the projection (1, 1: rotation)
+    float mu;                 // friction coefficient of obstacle contacts (0: none)
+    double feps;              // sticking slip threshold eps_v h (m)
     // Tolerance mode: while `gate` is set and *gate != 0 the kernel returns
     // at once (the Jacobi sweep copies x^k forward instead), so a converged
     // loop runs its remaining launches of the fixed step graph as no-ops.
@@ -124,6 +127,7 @@ struct Scene {
     double rho = 0, gamma = 0;
     double tol_in = 0, tol_out = 0;   // Algorithm 1 loop tolerances (<= 0: fixed budgets)
     double smin = 1, smax = 1;        // strain limits
+    double mu = 0, feps = 0;          // obstacle friction coefficient, sticking slip eps_v h
     int debug_tangles = 0;            // check the end state of every step for intersecting triangles
     double bp_mu0 = 0.0, bp_kappa = 1.0;   // reusable candidate superset: box growth margins
     int bp_reuse = 0;                      // ... and whether it is used

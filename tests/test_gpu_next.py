@@ -195,3 +195,49 @@ def test_reorder_restores_sweep_speed_on_a_shuffled_grid():
     xr, _ = reo.get_state()
     err = np.linalg.norm(xr - xn[inv], axis=1).max() / np.linalg.norm(xn.max(0) - xn.min(0))
     assert err <= 1e-5
+
+
+def test_spinning_cylinder_drags_the_cloth_with_friction():
+    """Lagged obstacle friction on the device against the oracle: a small
+    flat cloth laid half d_hat above the top line of a cylinder spinning at
+    2 rad/s (self contact off), 4 steps of 2 x 6 iterations.  With friction
+    the cloth picks up the surface's velocity along +z, and the positions
+    match the oracle's to FP32 rounding; without friction it does not move
+    along z."""
+    import paper_2403_19272_amd as P
+    from oracle import model as M
+    from oracle import step as S
+    sc = scenegen.drop_cloth(9, seed=2, obstacle="cylinder", r=8, steps=4, drop=0.0, d_hat=1e-3, side=0.05,
+                             iters_outer=2, iters_inner=6)
+    ob = sc.obstacles[0]
+    x0 = sc.rest.astype(np.float64).copy()
+    x0[:, 1] = ob.radius + 0.5e-3
+    x0 = x0.astype(np.float32)
+    m = M.build_model(sc.tris, x0, sc.pinned, sc.dt, sc.density, sc.k_stretch, sc.k_bend)
+    _, U = M.eigenbasis(m, sc.r)
+    out = {}
+    for mu in (0.0, 0.6):
+        p = S.Params(iters_outer=2, iters_inner=6, cheb_rho=0.9, cheb_gamma=0.6, d_hat=sc.d_hat,
+                     self_contact=False, friction=mu)
+        o = S.Oracle(m, M.stored_basis(U, "fp32"), p, sc.gravity,
+                     [S.Obst(ob.kind, np.array(ob.center, float), ob.radius, np.array(ob.axis, float), omega=2.0)])
+        o.set_state(x0, np.zeros_like(x0))
+        g = P.ClothScene(sc.tris, x0, dt=sc.dt, density=sc.density, k_stretch=sc.k_stretch, k_bend=sc.k_bend,
+                         k_contact=m.k_contact, d_hat=sc.d_hat, r=sc.r, iters_inner=6, iters_outer=2,
+                         cheb_rho=0.9, cheb_gamma=0.6, cheb_delay=3, precision=P.CLOTH_PLAIN_FP32,
+                         self_contact=False, friction=mu)
+        g.add_obstacle(ob.kind, ob.center, ob.radius, axis=ob.axis, half_length=ob.half_length, omega=2.0)
+        g.set_basis(U)
+        g.set_state(x0, np.zeros_like(x0))
+        for _ in range(sc.steps):
+            o.step()
+            g.step(sc.gravity)
+        x, v = g.get_state()
+        diag = bbox_diag(o.x)
+        err = float(np.linalg.norm(x - o.x, axis=1).max()) / diag
+        out[mu] = (float(v[:, 2].mean()), float(o.v[:, 2].mean()), err)
+        print(f"[friction mu={mu}] vz gpu {out[mu][0]:.5f} oracle {out[mu][1]:.5f} err/diag {err:.2e}", flush=True)
+        g.close()
+    assert abs(out[0.0][0]) < 1e-4 and out[0.6][0] > 0.01   # (v = dx / h carries FP32 noise x 200)
+    assert out[0.6][2] <= 1e-5 and out[0.0][2] <= 1e-5
+    assert abs(out[0.6][0] - out[0.6][1]) <= 0.02 * out[0.6][1]

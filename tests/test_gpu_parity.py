@@ -140,13 +140,28 @@ def test_partial_ccd_life_spans_bit_exact():
     assert np.array_equal(got["ob_a"][0], ob)
 
 
-@pytest.mark.parametrize("precision,uu", [("fp32", False), ("mixed", False), ("fp32", True), ("mixed", True)])
-def test_inner_iteration_with_contact(precision, uu):
+@pytest.mark.parametrize("precision,uu,mu", [("fp32", False, 0.0), ("mixed", False, 0.0), ("fp32", True, 0.0),
+                                           ("mixed", True, 0.0), ("fp32", False, 0.5), ("mixed", True, 0.5)])
+def test_inner_iteration_with_contact(precision, uu, mu):
     """Inner iterations with VT, EE and obstacle constraints against the
     oracle; uu: the contact matrix from the precomputed Eq. (uu) store
-    instead of the matrix-core Gram."""
+    instead of the matrix-core Gram; mu: lagged obstacle friction (the
+    block's start stands for the step's start)."""
     sc, o, U, blk = contact_block(precision=precision)
-    g = gpu_side(sc, U, precision, 0.95, uu_store=uu)
+    if mu > 0:
+        # the obstacle members moved into the sphere's contact band, each with
+        # a slip since the block's start from sticking to slipping sizes
+        rng = np.random.default_rng(5)
+        ob = sc.obstacles[0]
+        mem = np.flatnonzero(blk["ob_a"][0] >= 0)
+        c = np.array(ob.center)
+        d = blk["xk"][mem].astype(np.float64) - c
+        nrm = d / np.linalg.norm(d, axis=1)[:, None]
+        blk["xk"][mem] = c + nrm * (ob.radius + rng.uniform(-0.5, 0.9, len(mem)) * sc.d_hat)[:, None]
+        slip = rng.normal(size=(len(mem), 3)) * np.exp(rng.uniform(np.log(1e-7), np.log(1e-4), len(mem)))[:, None]
+        blk["xm"][mem] = blk["xk"][mem] - slip
+    o.p.friction = mu
+    g = gpu_side(sc, U, precision, 0.95, uu_store=uu, friction=mu)
     g.stage_load_block(blk["xm"], blk["xk"], blk["xkm1"], blk["z"], blk["vt"], blk["a_vt"], blk["ee"],
                        blk["a_ee"], blk["ob_a"])
     k = 4
@@ -155,12 +170,18 @@ def test_inner_iteration_with_contact(precision, uu):
     C = oracle_constraints(o, blk)
     inertia = (o.m.mass / o.m.h ** 2)[:, None] * blk["z"].astype(np.float64)
     xk1 = o.iterate(blk["xk"].astype(np.float64), blk["xkm1"].astype(np.float64), k, C, inertia,
-                    blk["xm"].astype(np.float64))
+                    blk["xm"].astype(np.float64), xs=blk["xm"].astype(np.float64))
+    if mu > 0:
+        v = C.ob[:, 0]
+        wf, _ = S.obstacle_friction(o.obs[0], blk["xk"][v].astype(np.float64), blk["xm"][v].astype(np.float64),
+                                    o._weights(C.a_ob), o.m.h, o.p.d_hat, mu, o.p.friction_eps_v)
+        print(f"[inner friction] {int((wf > 0).sum())} of {len(v)} obstacle members in the band", flush=True)
+        assert (wf > 0).sum() > 5
     diag = bbox_diag(xk1)
     err = vertex_err(got["xk"], xk1) / diag
     upd = vertex_err(xk1, blk["xk"]) / diag
     qerr = np.abs(got["Q"] - o.trace["Q"]).max() / np.abs(o.trace["Q"]).max()
-    print(f"[inner {precision} uu={uu}] err/diag={err:.3e} update/diag={upd:.3e} Q rel={qerr:.2e}", flush=True)
+    print(f"[inner {precision} uu={uu} mu={mu}] err/diag={err:.3e} update/diag={upd:.3e} Q rel={qerr:.2e}", flush=True)
     assert upd > 1e-4
     assert err <= 1e-5
     assert qerr <= 1e-3
