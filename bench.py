@@ -57,14 +57,14 @@ def log(*a):
 
 
 def make_gpu_scene(sc, precision, P, k_contact=0.0, iters_inner=None, iters_outer=None, rho=0.0, gamma=0.0,
-                   broad_reuse=False, pair_capacity=0, uu_store=False, friction=0.0):
+                   broad_reuse=False, pair_capacity=0, uu_store=False, friction=0.0, smoother=0):
     prec = P.CLOTH_MIXED if precision == "mixed" else P.CLOTH_PLAIN_FP32
     g = P.ClothScene(sc.tris, sc.rest, dt=sc.dt, density=sc.density, k_stretch=sc.k_stretch,
                      k_bend=sc.k_bend, k_contact=k_contact, d_hat=sc.d_hat, pinned=sc.pinned, r=sc.r,
                      iters_inner=iters_inner or sc.iters_inner, iters_outer=iters_outer or sc.iters_outer,
                      cheb_rho=rho, cheb_gamma=gamma, cheb_delay=3, precision=prec,
                      self_contact=sc.self_contact, broad_reuse=broad_reuse, pair_capacity=pair_capacity,
-                     uu_store=uu_store, friction=friction, arena="torch")
+                     uu_store=uu_store, friction=friction, smoother=smoother, arena="torch")
     for ob in sc.obstacles:
         g.add_obstacle(ob.kind, ob.center, ob.radius, axis=ob.axis, half_length=ob.half_length,
                        omega=ob.omega)
@@ -561,6 +561,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 window")
     ap.add_argument("--broad-reuse", action="store_true",
                     help="filter the candidate lists from the reusable superset (broad_reuse)")
+    ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "ajacobi2"],
+                    help="Chebyshev-accelerated Jacobi (default) or rank-2 A-Jacobi")
     ap.add_argument("--friction", type=float, default=0.0,
                     help="friction coefficient of the obstacle contacts (lagged friction; 0 = frictionless)")
     ap.add_argument("--uu-store", action="store_true",
@@ -608,7 +610,7 @@ def main():
         sc.precision = args.precision
     log(f"workload {sc.name}: nv={sc.nv} nt={sc.nt} r={sc.r} {sc.precision}")
     g = make_gpu_scene(sc, sc.precision, P, broad_reuse=args.broad_reuse, uu_store=args.uu_store,
-                       friction=args.friction)
+                       friction=args.friction, smoother=1 if args.smoother == "ajacobi2" else 0)
     if args.eager:
         g.set_graph(False)
     t0 = time.time()
@@ -782,6 +784,7 @@ def main():
         "launch": "eager" if args.eager else "graph replay",
         "contact_matrix": "precomputed U_j U_j^T store" if args.uu_store else "matrix-core Gram",
         "obstacle_friction": args.friction,
+        "smoother": args.smoother,
         "roofline": roof,
         "kernel_rooflines": rooflines or None,
         "step_roofline": step_roof,

@@ -168,7 +168,12 @@ typedef struct {
  *                       boundary keeps the caller's order: positions,
  *                       velocities, bases and the system matrix cross it in
  *                       the caller's numbering.  The stage-level calls need
- *                       the caller's order (CLOTH_E_INVALID when set) */
+ *                       the caller's order (CLOTH_E_INVALID when set)
+ *   smoother            0: Jacobi with Chebyshev acceleration (cheb_rho,
+ *                       cheb_gamma, cheb_delay); 1: rank-2 A-Jacobi (sec. 8.1):
+ *                       every inner iteration takes two damped Jacobi steps
+ *                       (damping cheb_gamma) after the subspace correction,
+ *                       with no Chebyshev blend */
 typedef struct {
     int32_t r, iters_inner, iters_outer;
     double tol_inner, tol_outer;
@@ -178,7 +183,7 @@ typedef struct {
     int32_t debug_tangles;
     double broad_margin, broad_margin_motion;
     int32_t r_warm, broad_reuse;
-    int32_t uu_store, reorder;
+    int32_t uu_store, reorder, smoother;
 } cloth_solver_params;
 
 typedef struct {

@@ -55,6 +55,7 @@ class Params:
     rf_iters: int = 0          # residual-forwarding iterations (0 = off)
     rf_toi: float = 0.5        # forward the residual when the exiting t_TOI is below this
     friction: float = 0.0      # friction coefficient mu of obstacle contacts (0 = frictionless)
+    smoother: str = "chebyshev"    # or "ajacobi2": rank-2 A-Jacobi, two damped Jacobi steps per iteration
     friction_eps_v: float = 1e-3   # sticking velocity threshold (m/s)
 
 
@@ -523,8 +524,15 @@ class Oracle:
         r1 = b - m.H @ xt - W[:, None] * xt
         r1[~free] = 0
         xhat = xt + r1 / (m.diagH + W)[:, None]
-        om = self.omega[min(k, len(self.omega) - 1)]
         self.trace = dict(r0=r0, g=g, A=A, Q=Q, xt=xt, r1=r1, xhat=xhat, b=b, W=W)
+        if p.smoother == "ajacobi2":
+            # rank-2 A-Jacobi (sec. 8.1): two Jacobi steps per iteration, each
+            # damped by gamma, the first from the subspace-corrected x~
+            y1 = xk + p.cheb_gamma * (xhat - xk)
+            r2 = b - m.H @ y1 - W[:, None] * y1
+            r2[~free] = 0
+            return y1 + p.cheb_gamma * r2 / (m.diagH + W)[:, None]
+        om = self.omega[min(k, len(self.omega) - 1)]
         return om * (p.cheb_gamma * (xhat - xk) + xk - xkm1) + xkm1
 
 

@@ -171,6 +171,7 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
     }
     d.x4 = cv<float4>(carve_fn, n);
     d.d4 = cv<float4>(carve_fn, n);
+    d.e4 = cv<float4>(carve_fn, n);
     d.W = cv<float>(carve_fn, n);
     d.mh2 = cv<float>(carve_fn, n);
     d.diag = cv<float>(carve_fn, n);
@@ -232,6 +233,7 @@ static size_t dry_footprint(const Scene& src) {
     s.r_warm = src.r_warm;
     s.bp_reuse = src.bp_reuse;
     s.uu_store = src.uu_store;
+    s.smoother = src.smoother;
     s.iters_in = src.iters_in;
     s.iters_out = src.iters_out;
     s.prec = src.prec;
@@ -350,8 +352,16 @@ static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStrea
     }
     TIMED(K_EXPAND, launch_expand(d, s.prec, 0, st));
     float om = omega_override > 0 ? omega_override : s.omega[std::min(k, (int)s.omega.size() - 1)];
-    TIMED(K_JACOBI, launch_jacobi_cheb(d, om, (float)s.gamma, has_contact, s.d.dxbits + slot,
-                                       prev_slot >= 0 ? s.d.dxbits + prev_slot : nullptr, st));
+    if (s.smoother == 1 && !linear) {
+        // rank-2 A-Jacobi: two damped Jacobi steps, no Chebyshev blend
+        TIMED(K_JACOBI, launch_jacobi_cheb(d, 1.0f, (float)s.gamma, has_contact, s.d.dxbits + slot,
+                                           prev_slot >= 0 ? s.d.dxbits + prev_slot : nullptr, st, 1));
+        TIMED(K_JACOBI, launch_jacobi_cheb(d, 1.0f, (float)s.gamma, has_contact, s.d.dxbits + slot,
+                                           prev_slot >= 0 ? s.d.dxbits + prev_slot : nullptr, st, 2));
+    } else {
+        TIMED(K_JACOBI, launch_jacobi_cheb(d, om, (float)s.gamma, has_contact, s.d.dxbits + slot,
+                                           prev_slot >= 0 ? s.d.dxbits + prev_slot : nullptr, st));
+    }
     float* t = d.xkm1;
     d.xkm1 = d.xk;
     d.xk = d.xk1;
@@ -473,6 +483,7 @@ cloth_status cloth_query_footprint(const cloth_mesh* mesh, const cloth_solver_pa
     ds.r = params->r;
     ds.r_warm = params->r_warm;
     ds.uu_store = params->uu_store ? 1 : 0;
+    ds.smoother = params->smoother;
     ds.bp_reuse = params->broad_reuse ? 1 : 0;
     ds.iters_in = std::max(1, params->iters_inner);
     ds.iters_out = std::max(1, params->iters_outer);
@@ -508,6 +519,7 @@ cloth_status cloth_init(const cloth_mesh* mesh, const float* rest_xyz, const clo
     }
     if (params->precision != CLOTH_PLAIN_FP32 && params->precision != CLOTH_MIXED)
         return fail(CLOTH_E_INVALID, "unknown precision");
+    if (params->smoother != 0 && params->smoother != 1) return fail(CLOTH_E_INVALID, "unknown smoother");
     if (!(mat->friction >= 0 && std::isfinite(mat->friction)) || !std::isfinite(mat->friction_eps_v))
         return fail(CLOTH_E_INVALID, "friction must be finite and >= 0");
     std::unique_ptr<cloth_scene_s> sc(new (std::nothrow) cloth_scene_s());

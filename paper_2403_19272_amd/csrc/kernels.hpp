@@ -44,7 +44,9 @@ hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpar
 // delta = U q into d.d4 (AoS); add: d.xt = x^k + U q (SoA)
 hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st);
 // dx_prev (may be null): the slot a gated sweep repeats
+// mode 0: Chebyshev blend; 1, 2: the two launches of a rank-2 A-Jacobi step
 hipError_t launch_jacobi_cheb(const Dev& d, float omega, float gamma, int has_contact,
-                              unsigned long long* dx_slot, const unsigned long long* dx_prev, hipStream_t st);
+                              unsigned long long* dx_slot, const unsigned long long* dx_prev, hipStream_t st,
+                              int mode = 0);
 
 }  // namespace cloth

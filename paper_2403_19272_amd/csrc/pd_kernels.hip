@@ -856,12 +856,17 @@ __global__ void __launch_bounds__(TPB) k_expand_mfma(Dev d, int add) {
 // and AoS to d.x4 (the next local step's gathers).  A non-finite change
 // flags the step as diverged.  Gated (a converged loop): x^{k+1} = x^k and
 // the slot repeats the previous iteration's norm (dx_prev).
+// Rank-2 A-Jacobi (sec. 8.1), two damped Jacobi steps per iteration, as two
+// launches: mode 1 writes e1 = gamma (x^ - x^k) to d.e4 (y1 = x^k + e1);
+// mode 2 repeats the sweep with e1 in place of delta, whose x^ - x^k is then
+// e1 + D^{-1} (b - A y1), and writes x^{k+1} = y1 + gamma D^{-1} (b - A y1).
 __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float gamma, int has_contact,
                                                     unsigned long long* dx_slot,
-                                                    const unsigned long long* __restrict__ dx_prev) {
+                                                    const unsigned long long* __restrict__ dx_prev, int mode) {
     const int n = d.nv;
     const int v = xcd_tile(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     if (gated(d.gate)) {
+        if (mode == 1) return;
         if (v < n)
             for (int c = 0; c < 3; ++c) d.xk1[c * n + v] = d.xk[c * n + v];
         if (blockIdx.x == 0 && threadIdx.x == 0 && dx_prev) *dx_slot = *dx_prev;
@@ -869,7 +874,7 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
     }
     double dxm = 0.0;
     if (v < n) {
-        const float4* DL = d.d4;
+        const float4* DL = mode == 2 ? d.e4 : d.d4;
         float xk[3] = {d.xk[v], d.xk[n + v], d.xk[2 * n + v]};
         float xkm1[3] = {d.xkm1[v], d.xkm1[n + v], d.xkm1[2 * n + v]};
         float dh[3] = {0.f, 0.f, 0.f};
@@ -890,10 +895,19 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
             dh[1] = (r01 - ay) * inv;
             dh[2] = (r02 - az) * inv;
         }
+        if (mode == 1) {
+            d.e4[v] = make_float4(gamma * dh[0], gamma * dh[1], gamma * dh[2], 0.f);
+            return;
+        }
         double s2 = 0.0;
         float nx[3];
+        const float4 e1 = mode == 2 ? d.e4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float e1c[3] = {e1.x, e1.y, e1.z};
         for (int c = 0; c < 3; ++c) {
-            nx[c] = xkm1[c] + omega * (gamma * dh[c] + (xk[c] - xkm1[c]));
+            if (mode == 2)
+                nx[c] = (xk[c] + e1c[c]) + gamma * (dh[c] - e1c[c]);
+            else
+                nx[c] = xkm1[c] + omega * (gamma * dh[c] + (xk[c] - xkm1[c]));
             d.xk1[c * n + v] = nx[c];
             double dd = (double)nx[c] - (double)xk[c];
             s2 += dd * dd;
@@ -1029,9 +1043,10 @@ hipError_t launch_expand(const Dev& d, int prec, int add, hipStream_t st) {
 }
 
 hipError_t launch_jacobi_cheb(const Dev& d, float omega, float gamma, int has_contact,
-                              unsigned long long* dx_slot, const unsigned long long* dx_prev, hipStream_t st) {
+                              unsigned long long* dx_slot, const unsigned long long* dx_prev, hipStream_t st,
+                              int mode) {
     launch_timed(k_jacobi_cheb, dim3(blocks_for(d.nv)), dim3(TPB), 0, st, d, omega, gamma, has_contact, dx_slot,
-                 dx_prev);
+                 dx_prev, mode);
     return hipGetLastError();
 }
 

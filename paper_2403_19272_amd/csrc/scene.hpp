@@ -71,6 +71,7 @@ struct Dev {
     float *x, *v, *xstar, *z, *xm, *xk, *xkm1, *xk1, *xt, *b, *WY;
     float4* x4;               // nv: AoS copy of x^k for the neighbour gathers
     float4* d4;               // nv: AoS delta = U q (gathered by the Jacobi sweep)
+    float4* e4;               // nv: AoS first step of a rank-2 A-Jacobi iteration
     float* W;                 // nv: diagonal collision weights
     float* mh2;               // nv: m / h^2
     float* diag;              // nv: diag(H)
@@ -133,6 +134,7 @@ struct Scene {
     int bp_reuse = 0;                      // ... and whether it is used
     int r_warm = 0;                   // width of the modal warm-start basis (0: the reuse basis)
     int uu_store = 0;                 // contact matrix from the precomputed U_j U_j^T store
+    int smoother = 0;                 // 0: Chebyshev-accelerated Jacobi, 1: rank-2 A-Jacobi
     std::vector<int> perm;            // internal vertex i is the caller's perm[i] (empty: the caller's order)
     void* d_Uw = nullptr;             // its stored values (nv * r_warm)
     double* d_Ainvw = nullptr;        // inverse of its Galerkin matrix (r_warm * r_warm)

@@ -40,6 +40,25 @@ def test_hanging_cloth_ten_steps(precision):
     assert np.abs(vg - o.v).max() <= 1e-5 * diag / sc.dt
 
 
+def test_hanging_cloth_with_rank2_a_jacobi():
+    """The rank-2 A-Jacobi smoother (two damped Jacobi steps per iteration,
+    sec. 8.1) on the small hanging cloth: 10 steps x 20 iterations against
+    the oracle with the same smoother, in FP32."""
+    sc = scenegen.config(0)
+    o, U, rho = oracle_side(sc, "fp32", gamma=0.6)
+    o.p.smoother = "ajacobi2"
+    g = gpu_side(sc, U, "fp32", rho, gamma=0.6, smoother=1)
+    for s in range(sc.steps):
+        o.step()
+        g.step(sc.gravity)
+    xg, vg = g.get_state()
+    diag = bbox_diag(o.x)
+    err = vertex_err(xg, o.x) / diag
+    print(f"[c0 rank-2] err/diag={err:.3e} moved={vertex_err(o.x, sc.x0):.3e}", flush=True)
+    assert err <= 1e-5
+    assert vertex_err(o.x, sc.x0) > 1e-3
+
+
 def crumpled(sc, seed, amp=0.02, step=0.01):
     rng = np.random.default_rng(seed)
     xm = (sc.x0 + rng.normal(0, amp, sc.x0.shape)).astype(np.float32)
@@ -140,9 +159,11 @@ def test_partial_ccd_life_spans_bit_exact():
     assert np.array_equal(got["ob_a"][0], ob)
 
 
-@pytest.mark.parametrize("precision,uu,mu", [("fp32", False, 0.0), ("mixed", False, 0.0), ("fp32", True, 0.0),
-                                           ("mixed", True, 0.0), ("fp32", False, 0.5), ("mixed", True, 0.5)])
-def test_inner_iteration_with_contact(precision, uu, mu):
+@pytest.mark.parametrize("precision,uu,mu,sm", [("fp32", False, 0.0, 0), ("mixed", False, 0.0, 0),
+                                              ("fp32", True, 0.0, 0), ("mixed", True, 0.0, 0),
+                                              ("fp32", False, 0.5, 0), ("mixed", True, 0.5, 0),
+                                              ("mixed", False, 0.0, 1)])
+def test_inner_iteration_with_contact(precision, uu, mu, sm):
     """Inner iterations with VT, EE and obstacle constraints against the
     oracle; uu: the contact matrix from the precomputed Eq. (uu) store
     instead of the matrix-core Gram; mu: lagged obstacle friction (the
@@ -161,7 +182,8 @@ def test_inner_iteration_with_contact(precision, uu, mu):
         slip = rng.normal(size=(len(mem), 3)) * np.exp(rng.uniform(np.log(1e-7), np.log(1e-4), len(mem)))[:, None]
         blk["xm"][mem] = blk["xk"][mem] - slip
     o.p.friction = mu
-    g = gpu_side(sc, U, precision, 0.95, uu_store=uu, friction=mu)
+    o.p.smoother = "ajacobi2" if sm else "chebyshev"
+    g = gpu_side(sc, U, precision, 0.95, uu_store=uu, friction=mu, smoother=sm)
     g.stage_load_block(blk["xm"], blk["xk"], blk["xkm1"], blk["z"], blk["vt"], blk["a_vt"], blk["ee"],
                        blk["a_ee"], blk["ob_a"])
     k = 4
@@ -181,7 +203,7 @@ def test_inner_iteration_with_contact(precision, uu, mu):
     err = vertex_err(got["xk"], xk1) / diag
     upd = vertex_err(xk1, blk["xk"]) / diag
     qerr = np.abs(got["Q"] - o.trace["Q"]).max() / np.abs(o.trace["Q"]).max()
-    print(f"[inner {precision} uu={uu} mu={mu}] err/diag={err:.3e} update/diag={upd:.3e} Q rel={qerr:.2e}", flush=True)
+    print(f"[inner {precision} uu={uu} mu={mu} smoother={sm}] err/diag={err:.3e} update/diag={upd:.3e} Q rel={qerr:.2e}", flush=True)
     assert upd > 1e-4
     assert err <= 1e-5
     assert qerr <= 1e-3
