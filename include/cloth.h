@@ -173,7 +173,18 @@ typedef struct {
  *                       cheb_gamma, cheb_delay); 1: rank-2 A-Jacobi (sec. 8.1):
  *                       every inner iteration takes two damped Jacobi steps
  *                       (damping cheb_gamma) after the subspace correction,
- *                       with no Chebyshev blend */
+ *                       with no Chebyshev blend
+ *   adaptive_samples    1: the partial CCD (Eq. (query)) of a pair whose
+ *                       threshold interval rho* (Eq. (sample_bound)) shrank
+ *                       over the iteration, by stretch or fast motion,
+ *                       samples it more densely (end of section 4.1): the
+ *                       ratio c of rho* at the iterate to rho* at x- gives
+ *                       the level m = min(8, floor(2 / c)); m > 2 replaces
+ *                       the three fixed samples by the centroids of the m^2
+ *                       sub-triangles of the barycentric triangle (VT) or
+ *                       the centres of the m x m cells of the parameter
+ *                       square (EE); the frozen closest point is always a
+ *                       sample */
 typedef struct {
     int32_t r, iters_inner, iters_outer;
     double tol_inner, tol_outer;
@@ -183,7 +194,7 @@ typedef struct {
     int32_t debug_tangles;
     double broad_margin, broad_margin_motion;
     int32_t r_warm, broad_reuse;
-    int32_t uu_store, reorder, smoother;
+    int32_t uu_store, reorder, smoother, adaptive_samples;
 } cloth_solver_params;
 
 typedef struct {

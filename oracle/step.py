@@ -56,6 +56,7 @@ class Params:
     rf_toi: float = 0.5        # forward the residual when the exiting t_TOI is below this
     friction: float = 0.0      # friction coefficient mu of obstacle contacts (0 = frictionless)
     smoother: str = "chebyshev"    # or "ajacobi2": rank-2 A-Jacobi, two damped Jacobi steps per iteration
+    adaptive_samples: bool = False   # partial-CCD sample density from the change of rho* (Eq. (sample_bound))
     friction_eps_v: float = 1e-3   # sticking velocity threshold (m/s)
 
 
@@ -186,6 +187,65 @@ def query_ee(xm, xp, e1, e2, lam):
         p2 = x[e2[:, 0]][:, None] + lam[..., 1:] * (x[e2[:, 1]] - x[e2[:, 0]])[:, None]
         return p2 - p1
     return np.einsum("psd,psd->ps", diff(xp), diff(xm))
+
+
+ADAPT_M0, ADAPT_MMAX = 2, 8
+
+
+def _norm3(d):
+    """|d| per row, summed in the order x, y, z."""
+    return np.sqrt((d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2])
+
+
+def rho_star_ratio(q0, q1, vt):
+    """Change ratio of the threshold sample interval rho* of Eq.
+    (sample_bound) over an inner iteration, for pairs with corner points q0
+    (at x-) and q1 (at the iterate), shape (P, 4, 3); VT: vertex 0 against
+    triangle (1, 2, 3); EE: edge (0, 1) against edge (2, 3).  rho* is
+    proportional to (H0)^2 / (L (H1 + 2 L)); H0 (the distance at t = 0) is
+    the same for both, L is the longest primitive edge and H1 the largest
+    distance between a point of one primitive and a point of the other over
+    the motion.  Both are convex in time along straight-line motion, so
+    their maxima over t are the larger of the two end values; the reference
+    takes them at x- alone (no motion).  The ratio is at most 1."""
+    if vt:
+        edges = [(1, 2), (2, 3), (3, 1)]
+        pairs = [(0, 1), (0, 2), (0, 3)]
+    else:
+        edges = [(0, 1), (2, 3)]
+        pairs = [(0, 2), (0, 3), (1, 2), (1, 3)]
+    L0 = np.max([_norm3(q0[:, i] - q0[:, j]) for i, j in edges], axis=0)
+    L1 = np.maximum(L0, np.max([_norm3(q1[:, i] - q1[:, j]) for i, j in edges], axis=0))
+    H0 = np.max([_norm3(q0[:, i] - q0[:, j]) for i, j in pairs], axis=0)
+    H1 = np.maximum(H0, np.max([_norm3(q1[:, i] - q1[:, j]) for i, j in pairs], axis=0))
+    return (L0 * (H0 + 2.0 * L0)) / (L1 * (H1 + 2.0 * L1))
+
+
+def adaptive_level(ratio):
+    """Subdivision level m of the refined sample set: the base interval
+    (level ADAPT_M0) scaled by the ratio, m = min(ADAPT_MMAX, floor(M0 /
+    ratio)); m <= M0 keeps the fixed base samples."""
+    with np.errstate(divide="ignore"):
+        m = np.floor(ADAPT_M0 / ratio)
+    return np.minimum(m, ADAPT_MMAX).astype(np.int64)
+
+
+def refined_samples(m, vt):
+    """The refined sample set of level m: VT, the centroids of the m^2
+    sub-triangles of the m-subdivision of the barycentric triangle; EE, the
+    centres of the m x m cells of the parameter square."""
+    out = []
+    if vt:
+        for i in range(m):
+            for j in range(m - i):
+                out.append(((i + 1.0 / 3) / m, (j + 1.0 / 3) / m))
+                if i + j <= m - 2:
+                    out.append(((i + 2.0 / 3) / m, (j + 2.0 / 3) / m))
+    else:
+        for i in range(m):
+            for j in range(m):
+                out.append(((i + 0.5) / m, (j + 0.5) / m))
+    return np.array(out)
 
 
 def obstacle_phi(ob: Obst, x: np.ndarray):
@@ -355,12 +415,21 @@ class Oracle:
                                   C.lam_vt[:, None, :]], axis=1)          # (P,4,2)
             Q = query_vt(xm, xp, C.vt[:, 0], self.m.tris[C.vt[:, 1]], lam)
             act = (Q <= 0).any(1)
+            if self.p.adaptive_samples:
+                ids = np.concatenate([C.vt[:, :1], self.m.tris[C.vt[:, 1]]], axis=1)
+                act = self._refine(act, xm, xp, ids, True, C.lam_vt,
+                                   lambda sel, lam: query_vt(xm, xp, C.vt[sel, 0], self.m.tris[C.vt[sel, 1]], lam))
             C.a_vt = np.where(act, np.minimum(C.a_vt + 1, amax), 0).astype(np.int32)
         if len(C.ee):
             lam = np.concatenate([np.broadcast_to(EE_SAMPLES, (len(C.ee), 3, 2)),
                                   C.lam_ee[:, None, :]], axis=1)
-            Q = query_ee(xm, xp, self.m.edges[C.ee[:, 0]], self.m.edges[C.ee[:, 1]], lam)
+            e1, e2 = self.m.edges[C.ee[:, 0]], self.m.edges[C.ee[:, 1]]
+            Q = query_ee(xm, xp, e1, e2, lam)
             act = (Q <= 0).any(1)
+            if self.p.adaptive_samples:
+                ids = np.concatenate([e1, e2], axis=1)
+                act = self._refine(act, xm, xp, ids, False, C.lam_ee,
+                                   lambda sel, lam: query_ee(xm, xp, e1[sel], e2[sel], lam))
             C.a_ee = np.where(act, np.minimum(C.a_ee + 1, amax), 0).astype(np.int32)
         if len(C.ob):
             act = np.zeros(len(C.ob), bool)
@@ -369,6 +438,22 @@ class Oracle:
                 phi, _, _ = obstacle_phi(ob, xp[C.ob[sel, 0]])
                 act[sel] = phi < self.p.d_hat
             C.a_ob = np.where(act, np.minimum(C.a_ob + 1, amax), 0).astype(np.int32)
+
+    @staticmethod
+    def _refine(act, xm, xp, ids, vt, lam_frozen, query):
+        """Adaptive density (end of section 4.1): pairs whose rho* shrank
+        (stretch or fast motion) are queried on the refined sample set of
+        their level instead of the fixed one (the frozen closest point is
+        always a sample)."""
+        level = adaptive_level(rho_star_ratio(xm[ids], xp[ids], vt))
+        out = act.copy()
+        for m in np.unique(level[level > ADAPT_M0]):
+            sel = np.flatnonzero(level == m)
+            smp = refined_samples(int(m), vt)
+            lam = np.concatenate([np.broadcast_to(smp, (len(sel),) + smp.shape), lam_frozen[sel][:, None, :]],
+                                 axis=1)
+            out[sel] = (query(sel, lam) <= 0).any(1)
+        return out
 
     def _outer_ccd(self, xm: np.ndarray, xp: np.ndarray, prev: Constraints, st: StepStats):
         """Broad phase + full CCD on (x-, x+): returns (s, new constraint set).

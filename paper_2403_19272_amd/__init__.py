@@ -62,7 +62,8 @@ class SolverParams(C.Structure):
                 ("precision", C.c_int32), ("self_contact", C.c_int32), ("pair_capacity", C.c_int64),
                 ("debug_tangles", C.c_int32), ("broad_margin", C.c_double),
                 ("broad_margin_motion", C.c_double), ("r_warm", C.c_int32), ("broad_reuse", C.c_int32),
-                ("uu_store", C.c_int32), ("reorder", C.c_int32), ("smoother", C.c_int32)]
+                ("uu_store", C.c_int32), ("reorder", C.c_int32), ("smoother", C.c_int32),
+                ("adaptive_samples", C.c_int32)]
 
 
 class Obstacle(C.Structure):
@@ -203,7 +204,7 @@ class ClothScene:
                  precision=CLOTH_PLAIN_FP32, self_contact=False, pair_capacity=0,
                  debug_tangles=False, broad_margin=0.0, broad_margin_motion=0.0, r_warm=0,
                  broad_reuse=False, uu_store=False, reorder=False, friction=0.0, friction_eps_v=0.0,
-                 smoother=0, arena=None):
+                 smoother=0, adaptive_samples=False, arena=None):
         self._tris = np.ascontiguousarray(tris, np.int32)
         rest = _f32(rest)
         nv = rest.shape[0]
@@ -217,7 +218,8 @@ class ClothScene:
                                    cheb_gamma, cheb_delay, precision, int(bool(self_contact)),
                                    pair_capacity, int(bool(debug_tangles)), broad_margin,
                                    broad_margin_motion, r_warm, int(bool(broad_reuse)),
-                                   int(bool(uu_store)), int(bool(reorder)), int(smoother))
+                                   int(bool(uu_store)), int(bool(reorder)), int(smoother),
+                                   int(bool(adaptive_samples)))
         self.r = r
         self.r_warm = r_warm
         nbytes = C.c_size_t(0)

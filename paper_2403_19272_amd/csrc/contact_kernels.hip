@@ -1724,12 +1724,61 @@ __global__ void __launch_bounds__(256) k_pair_targets(Dev d, const int* cnt, con
     }
 }
 
+// Q(lambda) of Eq. (query) at one sample of a pair with corners q0 (x-) and
+// q1 (the iterate): VT, vertex 0 against the point of triangle (1, 2, 3) at
+// barycentrics (l1, l2); EE, edge (0, 1) at l1 against edge (2, 3) at l2.
+__device__ __forceinline__ double pair_query(bool vt, const d3* q0, const d3* q1, double l1, double l2) {
+    d3 a0, a1;
+    if (vt) {
+        d3 p20 = q0[1] + (q0[2] - q0[1]) * l1 + (q0[3] - q0[1]) * l2;
+        d3 p21 = q1[1] + (q1[2] - q1[1]) * l1 + (q1[3] - q1[1]) * l2;
+        a0 = p20 - q0[0];
+        a1 = p21 - q1[0];
+    } else {
+        a0 = (q0[2] + (q0[3] - q0[2]) * l2) - (q0[0] + (q0[1] - q0[0]) * l1);
+        a1 = (q1[2] + (q1[3] - q1[2]) * l2) - (q1[0] + (q1[1] - q1[0]) * l1);
+    }
+    return dot(a1, a0);
+}
+
+constexpr int ADAPT_M0 = 2, ADAPT_MMAX = 8;
+
+// Adaptive density (end of section 4.1): the change ratio of rho* (Eq.
+// (sample_bound)) over the iteration, with rho* proportional to
+// H0^2 / (L (H1 + 2 L)), L the longest primitive edge and H1 the largest
+// distance between a point of one primitive and one of the other over the
+// motion (both convex in time, so the larger end value), against their
+// values at x- alone; then the refined level min(MMAX, floor(M0 / ratio)).
+__device__ __forceinline__ int adaptive_level(bool vt, const d3* q0, const d3* q1) {
+    auto len = [](d3 a) { return sqrt(dot(a, a)); };
+    double L0, L1, H0, H1;
+    if (vt) {
+        L0 = fmax(fmax(len(q0[1] - q0[2]), len(q0[2] - q0[3])), len(q0[3] - q0[1]));
+        L1 = fmax(L0, fmax(fmax(len(q1[1] - q1[2]), len(q1[2] - q1[3])), len(q1[3] - q1[1])));
+        H0 = fmax(fmax(len(q0[0] - q0[1]), len(q0[0] - q0[2])), len(q0[0] - q0[3]));
+        H1 = fmax(H0, fmax(fmax(len(q1[0] - q1[1]), len(q1[0] - q1[2])), len(q1[0] - q1[3])));
+    } else {
+        L0 = fmax(len(q0[0] - q0[1]), len(q0[2] - q0[3]));
+        L1 = fmax(L0, fmax(len(q1[0] - q1[1]), len(q1[2] - q1[3])));
+        H0 = fmax(fmax(len(q0[0] - q0[2]), len(q0[0] - q0[3])), fmax(len(q0[1] - q0[2]), len(q0[1] - q0[3])));
+        H1 = fmax(H0, fmax(fmax(len(q1[0] - q1[2]), len(q1[0] - q1[3])),
+                           fmax(len(q1[1] - q1[2]), len(q1[1] - q1[3]))));
+    }
+    const double ratio = (L0 * (H0 + 2.0 * L0)) / (L1 * (H1 + 2.0 * L1));
+    const double m = floor((double)ADAPT_M0 / ratio);
+    return m >= (double)ADAPT_MMAX ? ADAPT_MMAX : (int)m;
+}
+
 // Partial CCD on (x-, x^{k+1}): active when Q(lambda) <= 0 at a sample
-// (three fixed samples plus the frozen closest point); a <- active ?
-// min(a+1, a_max) : 0.  Obstacles: active when phi(x^{k+1}) < d_hat.
+// (three fixed samples plus the frozen closest point; with `adapt`, pairs
+// whose rho* shrank use the refined set of their level instead of the
+// fixed samples: the centroids of the m^2 sub-triangles of the barycentric
+// triangle (VT) or the centres of the m x m cells of the parameter square
+// (EE)); a <- active ? min(a+1, a_max) : 0.  Obstacles: active when
+// phi(x^{k+1}) < d_hat.
 __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cpair, int* ca,
                               const double2* __restrict__ clam, int amax, const float* __restrict__ xnew,
-                              int* wchg) {
+                              int* wchg, int adapt) {
     if (gated(d.gate)) return;
     bool changed = false;
     const int nob = d.nob;
@@ -1747,37 +1796,37 @@ __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, cons
             pair_points(d, vt, pr.x, pr.y, xnew, q1);
             bool act = false;
             const double2 lf = clam[p];
+            const int m = adapt ? adaptive_level(vt, q0, q1) : ADAPT_M0;
+            if (m <= ADAPT_M0) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                // samples: VT barycentrics (1/6, 1/6), (2/3, 1/6), (1/6, 2/3);
-                // EE parameters (1/4, 1/4), (1/2, 1/2), (3/4, 3/4); then the
-                // frozen closest point
-                double l1, l2;
-                if (s == 0) {
-                    l1 = vt ? 1.0 / 6 : 0.25;
-                    l2 = vt ? 1.0 / 6 : 0.25;
-                } else if (s == 1) {
-                    l1 = vt ? 2.0 / 3 : 0.5;
-                    l2 = vt ? 1.0 / 6 : 0.5;
-                } else if (s == 2) {
-                    l1 = vt ? 1.0 / 6 : 0.75;
-                    l2 = vt ? 2.0 / 3 : 0.75;
-                } else {
-                    l1 = lf.x;
-                    l2 = lf.y;
+                for (int s = 0; s < 3; ++s) {
+                    // samples: VT barycentrics (1/6, 1/6), (2/3, 1/6), (1/6, 2/3);
+                    // EE parameters (1/4, 1/4), (1/2, 1/2), (3/4, 3/4)
+                    double l1, l2;
+                    if (s == 0) {
+                        l1 = vt ? 1.0 / 6 : 0.25;
+                        l2 = vt ? 1.0 / 6 : 0.25;
+                    } else if (s == 1) {
+                        l1 = vt ? 2.0 / 3 : 0.5;
+                        l2 = vt ? 1.0 / 6 : 0.5;
+                    } else {
+                        l1 = vt ? 1.0 / 6 : 0.75;
+                        l2 = vt ? 2.0 / 3 : 0.75;
+                    }
+                    act |= pair_query(vt, q0, q1, l1, l2) <= 0.0;
                 }
-                d3 a0, a1;
-                if (vt) {
-                    d3 p20 = q0[1] + (q0[2] - q0[1]) * l1 + (q0[3] - q0[1]) * l2;
-                    d3 p21 = q1[1] + (q1[2] - q1[1]) * l1 + (q1[3] - q1[1]) * l2;
-                    a0 = p20 - q0[0];
-                    a1 = p21 - q1[0];
-                } else {
-                    a0 = (q0[2] + (q0[3] - q0[2]) * l2) - (q0[0] + (q0[1] - q0[0]) * l1);
-                    a1 = (q1[2] + (q1[3] - q1[2]) * l2) - (q1[0] + (q1[1] - q1[0]) * l1);
-                }
-                act |= dot(a1, a0) <= 0.0;
+            } else if (vt) {
+                for (int i = 0; i < m; ++i)
+                    for (int j = 0; j < m - i; ++j) {
+                        act |= pair_query(vt, q0, q1, (i + 1.0 / 3) / m, (j + 1.0 / 3) / m) <= 0.0;
+                        if (i + j <= m - 2) act |= pair_query(vt, q0, q1, (i + 2.0 / 3) / m, (j + 2.0 / 3) / m) <= 0.0;
+                    }
+            } else {
+                for (int i = 0; i < m; ++i)
+                    for (int j = 0; j < m; ++j) act |= pair_query(vt, q0, q1, (i + 0.5) / m, (j + 0.5) / m) <= 0.0;
             }
+            // the frozen closest point is always a sample
+            act |= pair_query(vt, q0, q1, lf.x, lf.y) <= 0.0;
             const int a = ca[p], na = act ? min(a + 1, amax) : 0;
             ca[p] = na;
             changed |= na != a;
@@ -3017,7 +3066,7 @@ cloth_status contact_solve(Scene& s, ContactState& c, int nseg, hipStream_t st) 
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st) {
     Dev& d = s.d;
     hipLaunchKernelGGL(k_partial_ccd, dim3(gblocks(2 * c.cap + s.nv)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca,
-                       c.clam, s.amax, d.xk, c.cnt + CNT_WCHG);
+                       c.clam, s.amax, d.xk, c.cnt + CNT_WCHG, s.adapt_samples);
     HC(hipGetLastError());
     return CLOTH_OK;
 }

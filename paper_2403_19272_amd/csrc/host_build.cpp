@@ -317,6 +317,7 @@ std::string build_scene(Scene& s, const cloth_mesh* mesh, const float* rest, dou
     s.r_warm = prm->r_warm;
     s.uu_store = prm->uu_store ? 1 : 0;
     s.smoother = prm->smoother;
+    s.adapt_samples = prm->adaptive_samples ? 1 : 0;
     s.iters_in = prm->iters_inner;
     s.iters_out = prm->iters_outer;
     s.rho = prm->cheb_rho;

@@ -135,6 +135,7 @@ struct Scene {
     int r_warm = 0;                   // width of the modal warm-start basis (0: the reuse basis)
     int uu_store = 0;                 // contact matrix from the precomputed U_j U_j^T store
     int smoother = 0;                 // 0: Chebyshev-accelerated Jacobi, 1: rank-2 A-Jacobi
+    int adapt_samples = 0;            // partial-CCD sample density from the change of rho*
     std::vector<int> perm;            // internal vertex i is the caller's perm[i] (empty: the caller's order)
     void* d_Uw = nullptr;             // its stored values (nv * r_warm)
     double* d_Ainvw = nullptr;        // inverse of its Galerkin matrix (r_warm * r_warm)

@@ -142,14 +142,25 @@ def oracle_constraints(o, blk):
     return C
 
 
-def test_partial_ccd_life_spans_bit_exact():
-    sc, o, U, blk = contact_block()
-    g = gpu_side(sc, U, "fp32", 0.95)
+@pytest.mark.parametrize("adapt", [False, True])
+def test_partial_ccd_life_spans_bit_exact(adapt):
+    """Life spans after the partial CCD, bit-exact against the oracle; adapt:
+    the sample density adapted to the change of rho* (a larger motion, so
+    that most pairs are refined, at levels 3 to 8)."""
+    sc, o, U, blk = contact_block(step=0.5 if adapt else 0.1)
+    o.p.adaptive_samples = adapt
+    g = gpu_side(sc, U, "fp32", 0.95, adaptive_samples=adapt)
     g.stage_load_block(blk["xm"], blk["xk"], blk["xkm1"], blk["z"], blk["vt"], blk["a_vt"], blk["ee"],
                        blk["a_ee"], blk["ob_a"])
     g.stage_partial_ccd(blk["xp"])
     got = g.stage_read_block(nob=1)
     C = oracle_constraints(o, blk)
+    if adapt:
+        xm, xp = blk["xm"].astype(np.float64), blk["xp"].astype(np.float64)
+        ids = np.concatenate([C.vt[:, :1], o.m.tris[C.vt[:, 1]]], 1)
+        lv = S.adaptive_level(S.rho_star_ratio(xm[ids], xp[ids], True))
+        print(f"[pccd adaptive] VT levels {np.bincount(lv).tolist()}", flush=True)
+        assert (lv > S.ADAPT_M0).sum() > 100 and (lv == S.ADAPT_MMAX).any()
     o._partial_ccd(C, blk["xm"].astype(np.float64), blk["xp"].astype(np.float64))
     print(f"[pccd] vt={len(C.vt)} ee={len(C.ee)} ob={len(C.ob)} active_vt={int((C.a_vt > 0).sum())}", flush=True)
     assert np.array_equal(got["a_vt"], C.a_vt)

@@ -1,6 +1,8 @@
-"""Pins of the oracle's lagged obstacle friction (section 8.4 drapes with a
-lagged friction Hessian; the model is the smoothed Coulomb law documented in
-oracle.step.obstacle_friction).  CPU only."""
+"""Pins of the oracle's variants of the method: the lagged obstacle friction
+(section 8.4 drapes with a lagged friction Hessian; the model is the
+smoothed Coulomb law documented in oracle.step.obstacle_friction) and the
+partial-CCD sample density adapted to the change of rho* (end of section
+4.1).  CPU only."""
 import numpy as np
 
 import scenegen
@@ -102,3 +104,59 @@ def test_friction_slows_a_sliding_cloth_and_a_spinning_cylinder_drags_one():
     drag = _cloth_on("cylinder", 2.0, (0.0, 0.0, 0.0), 0.6, 4)
     assert abs(still.v[:, 2].mean()) < 1e-6
     assert drag.v[:, 2].mean() > 0.01
+
+
+def _cover_radius(smp, vt, grid=120):
+    """Largest distance from a point of the parameter domain to its nearest
+    sample (the sample interval of the set), by brute force on a grid."""
+    g = (np.arange(grid) + 0.5) / grid
+    P = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    if vt:
+        P = P[P.sum(1) <= 1.0]
+    d = np.linalg.norm(P[:, None, :] - smp[None, :, :], axis=2).min(1)
+    return d.max()
+
+
+def test_refined_sample_sets_cover_the_domain_at_an_interval_shrinking_like_1_over_m():
+    """Adaptive partial-CCD density (end of section 4.1): the refined set of
+    level m has m^2 points inside the parameter domain (barycentric triangle
+    for VT, unit square for EE), and its sample interval scales like 1/m."""
+    for vt in (True, False):
+        base = S.refined_samples(S.ADAPT_M0, vt)
+        r0 = _cover_radius(base, vt)
+        for m in (3, 4, 6, 8):
+            smp = S.refined_samples(m, vt)
+            assert len(smp) == m * m and len(np.unique(np.round(smp, 12), axis=0)) == m * m
+            assert np.all(smp > 0) and np.all(smp < 1)
+            if vt:
+                assert np.all(smp.sum(1) < 1)
+            r = _cover_radius(smp, vt)
+            assert r <= r0 * S.ADAPT_M0 / m * 1.15 + 2e-2 and r >= r0 * S.ADAPT_M0 / m * 0.6
+
+
+def test_rho_star_ratio_is_one_at_rest_and_falls_with_stretch_and_motion():
+    """rho* of Eq. (sample_bound) changes with the longest edge L and the
+    largest point distance H1: the ratio is 1 without motion, at most 1 for
+    any motion, and falls monotonically as a triangle is stretched or the
+    vertex moves farther; the level rises as the ratio falls."""
+    rng = np.random.default_rng(1)
+    for vt in (True, False):
+        q0 = rng.normal(size=(300, 4, 3))
+        q1 = q0 + rng.normal(scale=0.3, size=q0.shape)
+        assert np.allclose(S.rho_star_ratio(q0, q0.copy(), vt), 1.0)
+        r = S.rho_star_ratio(q0, q1, vt)
+        assert np.all(r > 0) and np.all(r <= 1.0)
+    tri = np.array([[0.3, 0.3, 0.01], [0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    prev = 1.0
+    for s in (1.0, 1.5, 2.0, 4.0):                  # stretch the triangle about its corner
+        q1 = tri.copy()
+        q1[1:] = tri[1:] * s
+        r = S.rho_star_ratio(tri[None], q1[None], True)[0]
+        assert r <= prev
+        prev = r
+    levels = []
+    for dz in (0.0, 0.5, 2.0, 8.0, 40.0):          # move the vertex farther through the plane
+        q1 = tri.copy()
+        q1[0, 2] -= dz
+        levels.append(int(S.adaptive_level(S.rho_star_ratio(tri[None], q1[None], True))[0]))
+    assert levels[0] == S.ADAPT_M0 and levels == sorted(levels) and levels[-1] == S.ADAPT_MMAX
