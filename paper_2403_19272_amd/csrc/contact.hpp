@@ -48,6 +48,7 @@ struct ContactState {
     // (see k_sup_gate) and the growth margins
     float *svbox = nullptr, *stbox = nullptr, *sebox = nullptr;
     int2 *sup_vt = nullptr, *sup_ee = nullptr;
+    int* toi_sched = nullptr;   // TOI chunk counters, one per XCD range on its own line
     int* supw = nullptr;
     double sup_mu0 = 0.0, sup_kappa = 1.0;
     bool sup_on = false;   // candidate lists filtered from the superset (else queried per stage)

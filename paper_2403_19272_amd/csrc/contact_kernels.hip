@@ -1334,7 +1334,7 @@ __global__ void __launch_bounds__(256) k_query_rescan(Dev d, const float* __rest
 // root refinement and the inside tests run on full wavefronts.
 constexpr int TOI_CHUNK = 1024;
 constexpr int TOI_FB = 32;        // fallback pairs per chunk taken by whole wavefronts
-constexpr int TOI_SCHED = 16;   // cnt[16..23]: next chunk of each XCD's range, cnt[24]: workgroups done
+constexpr int TOI_LINE = 16;     // ints between the chunk counters (one 64-byte line each)
 
 __device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, double t, double* toi_vt, double* toi_ee,
                                            int* keep, int* cand_a, int do_merge) {
@@ -1349,7 +1349,7 @@ __device__ __forceinline__ void toi_finish(int i, bool vt, int nvt, double t, do
 __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restrict__ xm, const float4* __restrict__ xp,
                                                    const int2* __restrict__ cvt, const int2* __restrict__ cee,
                                                    int* cnt, double* toi_vt, double* toi_ee, int* keep,
-                                                   int* cand_a, double* tpart, int do_merge) {
+                                                   int* cand_a, double* tpart, int do_merge, int* sched) {
     if (gated(d.gate)) return;
     __shared__ double wmin[4];
     __shared__ int queue[TOI_CHUNK + 256];   // pairs waiting for root refinement
@@ -1358,7 +1358,9 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
     __shared__ int qn, fbn, s_ch;
     const int nvt = cnt[0], nee = cnt[1];
     const int total = nvt + nee;
-    int* next = cnt + TOI_SCHED;   // next chunk of each XCD's range
+    // next chunk of each XCD's range, one counter per 64-byte line (cleared
+    // before the launch)
+    int* next = sched;
     double tmin = NOHIT;
     // the chunks are split into 8 contiguous ranges, one per XCD (workgroups
     // are dealt round-robin over the XCDs), so that an XCD gathers the
@@ -1377,9 +1379,13 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
             int ch = -1;
             for (; range < 8; ++range) {
                 const int x = (xcd + range) & 7;
-                const int c = x * per_x + atomicAdd(&next[x], 1);
-                if (c < min(nchunk, (x + 1) * per_x)) {
-                    ch = c;
+                const int lim = min(nchunk, (x + 1) * per_x) - x * per_x;   // chunks of range x
+                // a range seen used up is skipped without an atomic (the
+                // counter only grows, so a stale read only costs the atomic)
+                if (*(volatile int*)&next[TOI_LINE * x] >= lim) continue;
+                const int c = atomicAdd(&next[TOI_LINE * x], 1);
+                if (c < lim) {
+                    ch = x * per_x + c;
                     break;
                 }
             }
@@ -1451,15 +1457,7 @@ __global__ void __launch_bounds__(256) k_toi_merge(Dev d, const float4* __restri
     tmin = warp_min(tmin);
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = tmin;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        tpart[blockIdx.x] = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
-        // the last workgroup out clears the claim counters for the next launch
-        // (every other workgroup has made its last claim before counting itself)
-        __threadfence();
-        if (atomicAdd(&next[8], 1) == (int)gridDim.x - 1) {
-            for (int x = 0; x < 9; ++x) atomicExch(&next[x], 0);
-        }
-    }
+    if (threadIdx.x == 0) tpart[blockIdx.x] = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
 }
 
 // Second half of the constraint-set update, C_o = {TOI <= 1} U (C_{o-1}
@@ -2579,6 +2577,10 @@ static inline int gblocks(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, GRID_LOOP));
 }
 
+// the heavy queries are few: one workgroup per CU takes them (each
+// workgroup also counts itself out once, for the list's reset)
+static inline int rescan_blocks(int64_t nq) { return std::min(gblocks(nq), 256); }
+
 #define HC(expr)                                                                                        \
     do {                                                                                                \
         hipError_t e_ = (expr);                                                                         \
@@ -2658,6 +2660,7 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     c.sup_vt = static_cast<int2*>(carve(sizeof(int2) * (sup ? 2 * pc : 1)));
     c.sup_ee = static_cast<int2*>(carve(sizeof(int2) * (sup ? 2 * pc : 1)));
     c.supw = I(16);
+    c.toi_sched = I(8 * TOI_LINE);
     c.sup_mu0 = s.bp_mu0;
     c.sup_kappa = s.bp_kappa;
     c.sup_on = s.bp_reuse != 0;
@@ -2683,7 +2686,8 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
         !c.bpart || !c.grid || !c.xm4 || !c.xp4 || !c.vcount || !c.ecount || !c.cand_vt || !c.cand_ee || !c.toi_vt ||
         !c.toi_ee || !c.keep || !c.keep_ofs || !c.cand_a || !c.cpair || !c.cpair_prev || !c.ca ||
         !c.ca_prev || !c.clam || !c.cnrm || !c.slot || !c.vslot_ptr || !c.vslot_fill || !c.vslot || !c.cvlist ||
-        !c.cvflag || !c.cvofs || !c.svbox || !c.stbox || !c.sebox || !c.sup_vt || !c.sup_ee || !c.supw)
+        !c.cvflag || !c.cvofs || !c.svbox || !c.stbox || !c.sebox || !c.sup_vt || !c.sup_ee || !c.supw ||
+        !c.toi_sched)
         return set_error(CLOTH_E_OOM, "arena exhausted (contact buffers)");
     d.vslot_ptr = c.vslot_ptr;
     d.vslot = c.vslot;
@@ -2812,11 +2816,11 @@ static cloth_status bp_pairs(Scene& s, ContactState& c, const float* vb, const f
         else
             query_passes<8>(s, c, vt, qb, g, cnts, outp, n_out, cap, true, st);
         if (vt)
-            hipLaunchKernelGGL(k_query_rescan<true>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
+            hipLaunchKernelGGL(k_query_rescan<true>, dim3(rescan_blocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
                                c.rec, P, (const int*)cnts, (const int*)c.keep, outp, cap, c.max_out, c.cnt + 7,
                                (const int*)c.heavy_q, c.cnt + HEAVY_SLOT);
         else
-            hipLaunchKernelGGL(k_query_rescan<false>, dim3(gblocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
+            hipLaunchKernelGGL(k_query_rescan<false>, dim3(rescan_blocks(nq)), dim3(TPB), 0, st, d, qb, g, c.bucket_ptr,
                                c.rec, P, (const int*)cnts, (const int*)c.keep, outp, cap, c.max_out, c.cnt + 7,
                                (const int*)c.heavy_q, c.cnt + HEAVY_SLOT);
     }
@@ -2900,10 +2904,11 @@ static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm,
     int npart = 0;
     if (s.self_contact) {
         const int nb = gblocks(2 * c.cap);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, s.d.gate, c.toi_sched, 0, 8 * TOI_LINE);
         timing_begin(s, K_TOI, st);
         launch_timed(k_toi_merge, dim3(nb), dim3(TPB), 0, st, d, (const float4*)c.xm4, (const float4*)c.xp4,
                      (const int2*)c.cand_vt, (const int2*)c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.keep,
-                     c.cand_a, c.tpart, 1);
+                     c.cand_a, c.tpart, 1, c.toi_sched);
         timing_end(s, st);
         timing_begin(s, K_OUTER, st);
         hipLaunchKernelGGL(k_prev_match, dim3(gblocks(c.ccap)), dim3(TPB), 0, st, s.d.gate, (const int*)c.cnt,
@@ -3169,9 +3174,10 @@ cloth_status contact_stage_toi(Scene& s, ContactState& c, const float* xm, const
     HC(hipMemcpy(c.cnt, h, sizeof(h), hipMemcpyHostToDevice));
     hipLaunchKernelGGL(k_aos4, dim3(gblocks(s.nv)), dim3(TPB), 0, nullptr, s.nv, (const float*)s.d.xm, c.xm4);
     hipLaunchKernelGGL(k_aos4, dim3(gblocks(s.nv)), dim3(TPB), 0, nullptr, s.nv, (const float*)s.d.xt, c.xp4);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, nullptr, s.d.gate, c.toi_sched, 0, 8 * TOI_LINE);
     hipLaunchKernelGGL(k_toi_merge, dim3(gblocks(n_vt + n_ee)), dim3(TPB), 0, nullptr, s.d, (const float4*)c.xm4,
                        (const float4*)c.xp4, c.cand_vt, c.cand_ee, c.cnt, c.toi_vt, c.toi_ee, c.keep, c.cand_a,
-                       c.tpart, 0);
+                       c.tpart, 0, c.toi_sched);
     HC(hipGetLastError());
     HC(hipDeviceSynchronize());
     if (n_vt) HC(hipMemcpy(toi_vt, c.toi_vt, sizeof(double) * n_vt, hipMemcpyDeviceToHost));
