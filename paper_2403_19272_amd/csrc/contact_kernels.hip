@@ -2580,6 +2580,16 @@ static inline int gblocks(int64_t n) {
 // the heavy queries are few: one workgroup per CU takes them (each
 // workgroup also counts itself out once, for the list's reset)
 static inline int rescan_blocks(int64_t nq) { return std::min(gblocks(nq), 256); }
+// grids of the grid-stride kernels over the constraint set (at most a few
+// per vertex in practice; sized for one pass at one constraint per vertex)
+// and over the candidate lists (one pass at four per vertex): capacity-sized
+// grids would launch thousands of idle workgroups on small scenes
+static inline int cgrid(const Scene& s, const ContactState& c) {
+    return std::min(gblocks(c.ccap), gblocks(s.nv));
+}
+static inline int candgrid(const Scene& s, const ContactState& c) {
+    return std::min(gblocks(2 * c.cap), gblocks(4 * (int64_t)s.nv));
+}
 
 #define HC(expr)                                                                                        \
     do {                                                                                                \
@@ -2692,7 +2702,10 @@ cloth_status contact_layout(Scene& s, ContactState& c, const Carver& carve) {
     d.vslot_ptr = c.vslot_ptr;
     d.vslot = c.vslot;
     d.slot = c.slot;
-    c.gram_chunks = GRAM_CHUNKS;
+    // chunks of at least GRAM_MIN_PER_CHUNK contact vertices: no more than
+    // the vertices can fill
+    c.gram_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_CHUNKS, (s.nv + GRAM_MIN_PER_CHUNK - 1) /
+                                                                              GRAM_MIN_PER_CHUNK));
     return CLOTH_OK;
 }
 
@@ -2929,7 +2942,7 @@ static cloth_status toi_merge_filter(Scene& s, ContactState& c, const float* xm,
     if (s.self_contact) {
         hipLaunchKernelGGL(k_sum2, dim3(1), dim3(64), 0, st, s.d.gate, c.cnt);
         HC(scan_exclusive(c.keep, c.keep_ofs, (int)(2 * c.cap), c.cnt + 9, c.scan_tiles, nullptr, s.d.gate, st));
-        hipLaunchKernelGGL(k_compact, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, s.d.gate, c.cand_vt, c.cand_ee, c.cnt, c.keep,
+        hipLaunchKernelGGL(k_compact, dim3(candgrid(s, c)), dim3(TPB), 0, st, s.d.gate, c.cand_vt, c.cand_ee, c.cnt, c.keep,
                            c.keep_ofs, c.cand_a, c.cpair, c.ca, c.ccap);
     }
     HC(launch_filter(d, xm, xp, c.s_dev, d.x, d.xm, dxo, st));
@@ -2942,12 +2955,12 @@ static cloth_status block_setup(Scene& s, ContactState& c, hipStream_t st) {
     Dev& d = s.d;
     const int n = s.nv;
     if (s.self_contact) {
-        hipLaunchKernelGGL(k_freeze, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.clam, c.cnrm);
+        hipLaunchKernelGGL(k_freeze, dim3(cgrid(s, c)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.clam, c.cnrm);
         hipLaunchKernelGGL(k_fill_i32, dim3(gblocks(n + 1)), dim3(TPB), 0, st, s.d.gate, c.vslot_fill, 0, n + 1);
-        hipLaunchKernelGGL(k_slot_count, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.vslot_fill);
+        hipLaunchKernelGGL(k_slot_count, dim3(cgrid(s, c)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.vslot_fill);
         HC(scan_exclusive(c.vslot_fill, c.vslot_ptr, n + 1, nullptr, c.scan_tiles, nullptr, s.d.gate, st));
         hipLaunchKernelGGL(k_copy_i32, dim3(gblocks(n + 1)), dim3(TPB), 0, st, s.d.gate, c.vslot_fill, c.vslot_ptr, n + 1);
-        hipLaunchKernelGGL(k_slot_fill, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.vslot_fill,
+        hipLaunchKernelGGL(k_slot_fill, dim3(cgrid(s, c)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.vslot_fill,
                            c.vslot);
     }
     hipLaunchKernelGGL(k_slot_sort, dim3(gblocks(n)), dim3(TPB), 0, st, d, c.vslot_ptr, c.vslot, c.ob_a, c.nob,
@@ -2968,7 +2981,7 @@ static cloth_status outer_stage(Scene& s, ContactState& c, const float* xm, cons
     timing_begin(s, K_BROAD, st);
     if (first) hipLaunchKernelGGL(k_fill_i32, dim3(gblocks((int64_t)MAX_OBST * s.nv)), dim3(TPB), 0, st, s.d.gate, c.ob_a, -1,
                                   MAX_OBST * s.nv);
-    hipLaunchKernelGGL(k_save_prev, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, s.d.gate, c.cnt, c.cpair, c.ca, c.cpair_prev,
+    hipLaunchKernelGGL(k_save_prev, dim3(cgrid(s, c)), dim3(TPB), 0, st, s.d.gate, c.cnt, c.cpair, c.ca, c.cpair_prev,
                        c.ca_prev, first ? 1 : 0);
     hipLaunchKernelGGL(k_stage_counters, dim3(1), dim3(64), 0, st, s.d.gate, c.cnt, first ? 1 : 0, c.tmin_bits);
     cloth_status rc = broad_phase(s, c, xm, xp, st);
@@ -2998,7 +3011,7 @@ cloth_status contact_block_end(Scene& s, ContactState& c, bool setup, unsigned l
 cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, hipStream_t st) {
     if (!s.self_contact) return CLOTH_OK;
     Dev& d = s.d;
-    hipLaunchKernelGGL(k_pair_targets, dim3(gblocks(2 * c.cap)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca, c.clam,
+    hipLaunchKernelGGL(k_pair_targets, dim3(cgrid(s, c)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca, c.clam,
                        c.cnrm, (float)s.kc, (float)s.Kb, (float)s.dhat, c.slot, force_k ? 1 : 0);
     HC(hipGetLastError());
     return CLOTH_OK;
@@ -3070,7 +3083,7 @@ cloth_status contact_solve(Scene& s, ContactState& c, int nseg, hipStream_t st) 
 
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st) {
     Dev& d = s.d;
-    hipLaunchKernelGGL(k_partial_ccd, dim3(gblocks(2 * c.cap + s.nv)), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca,
+    hipLaunchKernelGGL(k_partial_ccd, dim3(std::min(gblocks(2 * c.cap + s.nv), gblocks(2 * (int64_t)s.nv))), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca,
                        c.clam, s.amax, d.xk, c.cnt + CNT_WCHG, s.adapt_samples);
     HC(hipGetLastError());
     return CLOTH_OK;
