@@ -323,14 +323,16 @@ static cloth_status fail_any(cloth_status c, const char*) { return c; }
 // One inner iteration on the device state: x^k = d.xk, x^{k-1} = d.xkm1 ->
 // d.xk1; then buffers rotate so that d.xk holds x^{k+1}.
 static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStream_t st, bool linear,
-                                    float omega_override, bool force_k = false, int prev_slot = -1) {
+                                    float omega_override, bool force_k = false, int prev_slot = -1,
+                                    bool targets_ready = false) {
     Scene& s = sc->s;
     ContactState& c = sc->c;
     Dev& d = s.d;
     int has_contact = (c.active && !linear) ? 1 : 0;
     if (k == 0 || !s.x4_valid) TIMED(K_MISC, launch_aos4(d.xk, d.x4, s.nv, st));
     if (has_contact) {
-        TIMED(K_TARGETS, contact_prepare_iteration(s, c, force_k, st));
+        // (the previous iteration's partial CCD may have written them already)
+        if (!targets_ready) TIMED(K_TARGETS, contact_prepare_iteration(s, c, force_k, st));
         // fork: the contact matrix needs only the collision weights, fixed
         // once the targets are; it is formed and factored on the side stream
         // while the local step and U^T r0 run
@@ -989,6 +991,7 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
     for (int o = 0; o < s.iters_out; ++o) {
         TIMED(K_MISC, launch_copy3(d.xk, d.x, n, st));
         TIMED(K_MISC, launch_copy3(d.xkm1, d.x, n, st));
+        bool tready = false;   // the pair targets of iteration k are written
         for (int k = 0; k < s.iters_in; ++k) {
             const int slot = slot_inner(s, o, k);
             if (tol) {
@@ -996,8 +999,12 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
                                           o > 0 ? slot_outer(s, o - 1) : -1, s.tol_out, 1, c.cnt, st));
                 d.gate = s.d_gate;
             }
-            cloth_status rc = inner_iteration(sc, k, slot, st, false, 0.f, false, slot > 0 ? slot - 1 : -1);
-            if (rc == CLOTH_OK && contact) TIMED(K_PCCD, contact_partial_ccd(s, c, st));
+            cloth_status rc = inner_iteration(sc, k, slot, st, false, 0.f, false, slot > 0 ? slot - 1 : -1, tready);
+            // within a block the partial CCD also writes the next iteration's
+            // pair targets (one launch less per iteration)
+            const bool fuse = k + 1 < s.iters_in;
+            if (rc == CLOTH_OK && contact) TIMED(K_PCCD, contact_partial_ccd(s, c, st, fuse));
+            tready = contact && fuse && s.self_contact && c.active;
             d.gate = nullptr;
             if (rc != CLOTH_OK) return rc;
         }

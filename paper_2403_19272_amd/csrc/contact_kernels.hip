@@ -1684,20 +1684,18 @@ __global__ void k_cv_compact(const int* __restrict__ gate, int n, const int* __r
 // half-space projection with the
 // frozen normal and closest-point parameters (minimum-norm correction over
 // movable vertices), weight w = k * 2^a (Eq. (exp) with K = 2; other K use powf).
-__global__ void __launch_bounds__(256) k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ cpair, const int* __restrict__ ca,
-                               const double2* __restrict__ clam, const float4* __restrict__ cnrm, float kc, float Kb,
-                               float dhat, float4* slot, int force_k) {
-    if (gated(d.gate)) return;
-    const int nvt = cnt[2], nc = cnt[2] + cnt[3];
+// the four slots of pair constraint p (VT when vt) with life span a, from
+// the positions X
+__device__ __forceinline__ void pair_target(const Dev& d, int p, bool vt, int2 pr, const float* __restrict__ X,
+                                            const double2* __restrict__ clam, const float4* __restrict__ cnrm,
+                                            int a, float kc, float Kb, float dhat, float4* slot) {
     const int n = d.nv;
-    const float* X = d.xk;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
-        int2 pr = cpair[p];
+    {
         int id[4];
-        pair_ids(d, p < nvt, pr.x, pr.y, id);
+        pair_ids(d, vt, pr.x, pr.y, id);
         float l1 = (float)clam[p].x, l2 = (float)clam[p].y;
         float c[4];
-        if (p < nvt) {
+        if (vt) {
             c[0] = 1.f; c[1] = -(1.f - l1 - l2); c[2] = -l1; c[3] = -l2;
         } else {
             c[0] = -(1.f - l1); c[1] = -l1; c[2] = 1.f - l2; c[3] = l2;
@@ -1713,13 +1711,21 @@ __global__ void __launch_bounds__(256) k_pair_targets(Dev d, const int* cnt, con
             den += cm[k] * cm[k];
         }
         float delta = (gx < 0.f && den > 0.f) ? -gx / den : 0.f;
-        int a = force_k ? 0 : ca[p];
         float w = (Kb == 2.0f) ? ldexpf(kc, a) : kc * powf(Kb, (float)a);
         for (int k = 0; k < 4; ++k) {   // (w, w (y - x)) with y - x = c_k delta n
             float s = cm[k] * delta;
             slot[4 * (size_t)p + k] = make_float4(w, w * s * nr.x, w * s * nr.y, w * s * nr.z);
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_pair_targets(Dev d, const int* cnt, const int2* __restrict__ cpair, const int* __restrict__ ca,
+                               const double2* __restrict__ clam, const float4* __restrict__ cnrm, float kc, float Kb,
+                               float dhat, float4* slot, int force_k) {
+    if (gated(d.gate)) return;
+    const int nvt = cnt[2], nc = cnt[2] + cnt[3];
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x)
+        pair_target(d, p, p < nvt, cpair[p], d.xk, clam, cnrm, force_k ? 0 : ca[p], kc, Kb, dhat, slot);
 }
 
 // Q(lambda) of Eq. (query) at one sample of a pair with corners q0 (x-) and
@@ -1774,9 +1780,13 @@ __device__ __forceinline__ int adaptive_level(bool vt, const d3* q0, const d3* q
 // triangle (VT) or the centres of the m x m cells of the parameter square
 // (EE)); a <- active ? min(a+1, a_max) : 0.  Obstacles: active when
 // phi(x^{k+1}) < d_hat.
+// With `tg`, the pair constraints' targets of the next iteration follow at
+// once (what k_pair_targets would compute from the new life spans and
+// xnew, which is the next iteration's x^k).
 __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, const int2* __restrict__ cpair, int* ca,
                               const double2* __restrict__ clam, int amax, const float* __restrict__ xnew,
-                              int* wchg, int adapt) {
+                              int* wchg, int adapt, int tg, const float4* __restrict__ cnrm, float kc,
+                              float Kb, float dhat_f, float4* slot) {
     if (gated(d.gate)) return;
     bool changed = false;
     const int nob = d.nob;
@@ -1828,6 +1838,7 @@ __global__ void __launch_bounds__(256) k_partial_ccd(Dev d, const int* cnt, cons
             const int a = ca[p], na = act ? min(a + 1, amax) : 0;
             ca[p] = na;
             changed |= na != a;
+            if (tg) pair_target(d, p, vt, pr, xnew, clam, cnrm, na, kc, Kb, dhat_f, slot);
         } else {
             int v = p - nc;
             d3 x = ld3(xnew, n, v);
@@ -3081,10 +3092,12 @@ cloth_status contact_solve(Scene& s, ContactState& c, int nseg, hipStream_t st) 
     return CLOTH_OK;
 }
 
-cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st) {
+cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st, bool targets) {
     Dev& d = s.d;
+    const bool tg = targets && s.self_contact;
     hipLaunchKernelGGL(k_partial_ccd, dim3(std::min(gblocks(2 * c.cap + s.nv), gblocks(2 * (int64_t)s.nv))), dim3(TPB), 0, st, d, c.cnt, c.cpair, c.ca,
-                       c.clam, s.amax, d.xk, c.cnt + CNT_WCHG, s.adapt_samples);
+                       c.clam, s.amax, d.xk, c.cnt + CNT_WCHG, s.adapt_samples, tg ? 1 : 0, (const float4*)c.cnrm,
+                       (float)s.kc, (float)s.Kb, (float)s.dhat, c.slot);
     HC(hipGetLastError());
     return CLOTH_OK;
 }
