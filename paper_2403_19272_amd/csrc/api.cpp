@@ -151,6 +151,19 @@ int slot_inner(const Scene& s, int o, int k) { return o * s.iters_in + k; }
 int slot_rf(const Scene& s, int k) { return s.iters_out * s.iters_in + k; }
 int slot_outer(const Scene& s, int o) { return s.iters_out * s.iters_in + RF_MAX + o; }
 int slots_needed(const Scene& s) { return std::max(slot_outer(s, s.iters_out), CHEB_EST_SLOTS); }
+// the device address of norm slot i (DX_SUB sub-slots, see scene.hpp)
+unsigned long long* dx_slot(Scene& s, int i) { return s.d.dxbits + (size_t)i * DX_STRIDE; }
+// the values of the first n norm slots (the maximum over each slot's
+// sub-slots), read after the work on st
+std::vector<unsigned long long> read_slots(Scene& s, int n, hipStream_t st) {
+    std::vector<unsigned long long> raw((size_t)n * DX_STRIDE), out(n, 0ull);
+    if (hipMemcpyAsync(raw.data(), s.d.dxbits, 8 * raw.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return out;
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < DX_SUB; ++k) out[i] = std::max(out[i], raw[(size_t)i * DX_STRIDE + 8 * k]);
+    return out;
+}
 
 }  // namespace
 
@@ -211,7 +224,7 @@ static cloth_status layout_scene(Scene& s, ContactState& c, const Carver& carve_
         if (!d.UU) return fail(CLOTH_E_OOM, "arena exhausted (U_j U_j^T store)");
     }
     s.nslots_cap = slots_needed(s);
-    d.dxbits = cv<unsigned long long>(carve_fn, (size_t)s.nslots_cap);
+    d.dxbits = cv<unsigned long long>(carve_fn, (size_t)s.nslots_cap * DX_STRIDE);
     s.d_rfdx = cv<float>(carve_fn, 3 * (size_t)n);
     s.d_gate = cv<int>(carve_fn, 4);
     if (!d.x4 || !d.d4 || !d.W || !d.mh2 || !d.diag || !s.d_pinned || !s.d_rowptr || !s.d_col || !s.d_val || !s.d_tri ||
@@ -356,13 +369,13 @@ static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStrea
     float om = omega_override > 0 ? omega_override : s.omega[std::min(k, (int)s.omega.size() - 1)];
     if (s.smoother == 1 && !linear) {
         // rank-2 A-Jacobi: two damped Jacobi steps, no Chebyshev blend
-        TIMED(K_JACOBI, launch_jacobi_cheb(d, 1.0f, (float)s.gamma, has_contact, s.d.dxbits + slot,
-                                           prev_slot >= 0 ? s.d.dxbits + prev_slot : nullptr, st, 1));
-        TIMED(K_JACOBI, launch_jacobi_cheb(d, 1.0f, (float)s.gamma, has_contact, s.d.dxbits + slot,
-                                           prev_slot >= 0 ? s.d.dxbits + prev_slot : nullptr, st, 2));
+        TIMED(K_JACOBI, launch_jacobi_cheb(d, 1.0f, (float)s.gamma, has_contact, dx_slot(s, slot),
+                                           prev_slot >= 0 ? dx_slot(s, prev_slot) : nullptr, st, 1));
+        TIMED(K_JACOBI, launch_jacobi_cheb(d, 1.0f, (float)s.gamma, has_contact, dx_slot(s, slot),
+                                           prev_slot >= 0 ? dx_slot(s, prev_slot) : nullptr, st, 2));
     } else {
-        TIMED(K_JACOBI, launch_jacobi_cheb(d, om, (float)s.gamma, has_contact, s.d.dxbits + slot,
-                                           prev_slot >= 0 ? s.d.dxbits + prev_slot : nullptr, st));
+        TIMED(K_JACOBI, launch_jacobi_cheb(d, om, (float)s.gamma, has_contact, dx_slot(s, slot),
+                                           prev_slot >= 0 ? dx_slot(s, prev_slot) : nullptr, st));
     }
     float* t = d.xkm1;
     d.xkm1 = d.xk;
@@ -1010,7 +1023,7 @@ static cloth_status step_enqueue(cloth_scene sc, const float g[3], hipStream_t s
         }
         // the block's end (its gate: the outer condition of its first iteration)
         if (tol) d.gate = s.d_gate + 1;
-        unsigned long long* dxo = d.dxbits + slot_outer(s, o);
+        unsigned long long* dxo = dx_slot(s, slot_outer(s, o));
         if (contact) {
             bool last = o == s.iters_out - 1;
             cloth_status rc = contact_block_end(s, c, !last || rf, dxo, st);  // x+ = x^k -> x, x-
@@ -1108,9 +1121,7 @@ static cloth_status collect_stats(cloth_scene sc, hipStream_t st, cloth_step_sta
     const bool tol = s.tol_in > 0 || s.tol_out > 0;
     int h[CNT_TANGLES + 2];
     HIPCHECK(hipMemcpyAsync(h, c.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
-    std::vector<unsigned long long> bits((size_t)s.nslots_cap);
-    HIPCHECK(hipMemcpyAsync(bits.data(), s.d.dxbits, 8 * bits.size(), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
+    std::vector<unsigned long long> bits = read_slots(s, s.nslots_cap, st);
     auto as_d = [](unsigned long long b) {
         double v;
         std::memcpy(&v, &b, 8);
@@ -1303,14 +1314,12 @@ cloth_status cloth_estimate_chebyshev(cloth_scene sc, void* stream) {
         s.gamma = gm;
         HIPCHECK(hipMemcpyAsync(d.xk, e.data(), sizeof(float) * e.size(), hipMemcpyHostToDevice, st));
         HIPCHECK(launch_copy3(d.xkm1, d.xk, n, st));
-        HIPCHECK(launch_fill_u64(d.dxbits, 0ull, warm + meas + 1, st));
+        HIPCHECK(launch_fill_u64(d.dxbits, 0ull, (warm + meas + 1) * DX_STRIDE, st));
         for (int k = 0; k < warm + meas; ++k) {
             cloth_status rc = inner_iteration(sc, k, k, st, true, 1.0f);
             if (rc != CLOTH_OK) return rc;
         }
-        std::vector<unsigned long long> bits(warm + meas);
-        HIPCHECK(hipMemcpyAsync(bits.data(), d.dxbits, 8 * bits.size(), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
+        std::vector<unsigned long long> bits = read_slots(s, warm + meas, st);
         double a, b;
         std::memcpy(&a, &bits[warm - 1], 8);
         std::memcpy(&b, &bits[warm + meas - 1], 8);
@@ -1361,7 +1370,7 @@ cloth_status cloth_stage_load_block(cloth_scene sc, const float* xm, const float
 cloth_status cloth_stage_inner(cloth_scene sc, int32_t k) {
     if (!sc) return fail(CLOTH_E_INVALID, "null argument");
     if (!sc->s.basis_set) return fail(CLOTH_E_INVALID, "basis not set");
-    HIPCHECK(launch_fill_u64(sc->s.d.dxbits, 0ull, 1, nullptr));
+    HIPCHECK(launch_fill_u64(sc->s.d.dxbits, 0ull, DX_STRIDE, nullptr));
     cloth_status rc = inner_iteration(sc, k, 0, nullptr, false, 0.f);
     if (rc != CLOTH_OK) return rc;
     if (sc->c.active) {
@@ -1403,9 +1412,9 @@ cloth_status cloth_stage_read_block(cloth_scene sc, float* xk, int32_t* a_vt, in
     }
     if (Q) HIPCHECK(hipMemcpy(Q, d.Qd, sizeof(double) * 3 * s.r, hipMemcpyDeviceToHost));
     if (dx) {
-        unsigned long long bits;
-        HIPCHECK(hipMemcpy(&bits, d.dxbits, 8, hipMemcpyDeviceToHost));
-        std::memcpy(dx, &bits, 8);
+        HIPCHECK(hipDeviceSynchronize());
+        std::vector<unsigned long long> bits = read_slots(s, 1, nullptr);
+        std::memcpy(dx, &bits[0], 8);
     }
     return contact_read_constraints(s, sc->c, a_vt, a_ee, ob_a);
 }

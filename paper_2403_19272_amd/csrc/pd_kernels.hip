@@ -226,6 +226,12 @@ __device__ __forceinline__ double warp_max(double v) {
 __device__ __forceinline__ bool gated(const int* g) { return g && *g; }
 
 __device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+// the value of a norm slot: the maximum over its sub-slots
+__device__ __forceinline__ double slot_value(const unsigned long long* slot) {
+    unsigned long long m = 0ull;
+    for (int k = 0; k < DX_SUB; ++k) m = max(m, slot[8 * k]);
+    return bits_to_double(m);
+}
 
 // block maximum of a per-thread value folded into *slot (FP64 bits; the
 // values are non-negative, so their bit patterns order like the values)
@@ -237,7 +243,7 @@ __device__ __forceinline__ void block_max_to(double v, unsigned long long* slot)
     if (threadIdx.x == 0) {
         double m = wmax[0];
         for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, wmax[i]);
-        atomicMax(slot, (unsigned long long)__double_as_longlong(m));
+        atomicMax(&slot[8 * (blockIdx.x % DX_SUB)], (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -251,7 +257,7 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
 // Start of a step: the norm slots are cleared, the running step's status
 // and iteration counters reset, the gates opened.
 __global__ void k_step_open(unsigned long long* dxbits, int nslots, int* cnt, int* gate) {
-    for (int i = threadIdx.x; i < nslots; i += blockDim.x) dxbits[i] = 0ull;
+    for (int i = threadIdx.x; i < nslots * DX_STRIDE; i += blockDim.x) dxbits[i] = 0ull;
     if (threadIdx.x == 0) {
         cnt[CNT_STEP_FAIL] = 0;
         cnt[CNT_INNER_DONE] = 0;
@@ -273,12 +279,12 @@ __global__ void k_gate(int* gate, const unsigned long long* __restrict__ dxbits,
                        int prev_outer, double tol_out, int block, int* cnt) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (block && prev_inner < 0) {
-        const int stop = prev_outer >= 0 && tol_out > 0 && bits_to_double(dxbits[prev_outer]) < tol_out;
+        const int stop = prev_outer >= 0 && tol_out > 0 && slot_value(dxbits + (size_t)prev_outer * DX_STRIDE) < tol_out;
         gate[1] = stop;
         if (!stop) cnt[CNT_OUTER_DONE] += 1;
     }
     const int skip = (block && gate[1]) ||
-                     (prev_inner >= 0 && tol_in > 0 && bits_to_double(dxbits[prev_inner]) < tol_in);
+                     (prev_inner >= 0 && tol_in > 0 && slot_value(dxbits + (size_t)prev_inner * DX_STRIDE) < tol_in);
     gate[0] = skip;
     if (block && !skip) cnt[CNT_INNER_DONE] += 1;
 }
@@ -869,7 +875,7 @@ __global__ void __launch_bounds__(TPB) k_jacobi_cheb(Dev d, float omega, float g
         if (mode == 1) return;
         if (v < n)
             for (int c = 0; c < 3; ++c) d.xk1[c * n + v] = d.xk[c * n + v];
-        if (blockIdx.x == 0 && threadIdx.x == 0 && dx_prev) *dx_slot = *dx_prev;
+        if (blockIdx.x == 0 && threadIdx.x < DX_SUB && dx_prev) dx_slot[8 * threadIdx.x] = dx_prev[8 * threadIdx.x];
         return;
     }
     double dxm = 0.0;

@@ -15,7 +15,13 @@ constexpr int TPB = 256;          // threads per block of the vertex/pair kernel
 constexpr int MAX_OBST = 4;
 constexpr double NO_HIT = 2.0;
 constexpr int MAX_R = 192;        // widest basis: the packed FP64 Cholesky factor lives in LDS
-constexpr int GRAM_CHUNKS = 512;  // contact-vertex chunks of the Gram partials
+constexpr int GRAM_CHUNKS = 512;
+// A norm slot is DX_SUB sub-slots 64 bytes apart (DX_STRIDE u64 per slot):
+// workgroup b folds its maximum into sub-slot b % DX_SUB, so that the
+// atomics of a launch's workgroups do not queue on one address; the slot's
+// value is the maximum over its sub-slots.
+constexpr int DX_SUB = 16;
+constexpr int DX_STRIDE = 8 * DX_SUB;  // contact-vertex chunks of the Gram partials
 constexpr int RF_MAX = 64;        // residual-forwarding iterations per step at most
 constexpr int CHEB_EST_SLOTS = 201;  // per-iteration norms of the Chebyshev estimate
 constexpr int GRAM_GROUPS_MAX = 16;  // chunk groups of the first FP64 reduction level
