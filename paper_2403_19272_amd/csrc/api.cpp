@@ -363,7 +363,7 @@ static cloth_status inner_iteration(cloth_scene_s* sc, int k, int slot, hipStrea
     TIMED(K_REDUCE, launch_reduce_solve(d, s.nblk, has_contact, c.gpart2, st));
     if (has_contact) {
         HIPCHECK(hipStreamWaitEvent(st, s.ev_join, 0));   // join
-        TIMED(K_CHOL_TRI, contact_solve(s, c, (s.nblk + U_SEG - 1) / U_SEG, st));
+        TIMED(K_CHOL_TRI, contact_solve(s, c, st));
     }
     TIMED(K_EXPAND, launch_expand(d, s.prec, 0, st));
     float om = omega_override > 0 ? omega_override : s.omega[std::min(k, (int)s.omega.size() - 1)];

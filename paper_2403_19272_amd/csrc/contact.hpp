@@ -108,7 +108,7 @@ cloth_status contact_prepare_iteration(Scene& s, ContactState& c, bool force_k, 
 // the contact matrix and its factorization (needs only the weights: may
 // run beside the local step), then q = A^{-1} g on it
 cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t st);
-cloth_status contact_solve(Scene& s, ContactState& c, int nseg, hipStream_t st);
+cloth_status contact_solve(Scene& s, ContactState& c, hipStream_t st);
 // targets: also the pair constraints' targets of the next iteration (from
 // the new life spans and x^k), so that it needs no k_pair_targets launch
 cloth_status contact_partial_ccd(Scene& s, ContactState& c, hipStream_t st, bool targets = false);

@@ -2393,23 +2393,16 @@ __global__ void __launch_bounds__(FT) k_chol_factor(Dev d, const double* __restr
 // NS: row slots of the solve, 2 for r <= 128 and 3 up to MAX_R (chosen on
 // the host; one instantiation per kernel keeps it within 128 VGPRs).
 template <int NS>
-__global__ void __launch_bounds__(1024) k_chol_tri(Dev d, const double* __restrict__ g1, int nseg,
-                                                   const int* __restrict__ n_cv) {
+__global__ void __launch_bounds__(1024) k_chol_tri(Dev d, const int* __restrict__ n_cv) {
     if (gated(d.gate)) return;
     extern __shared__ double A[];
     const int r = d.r;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tot = r * (r + 1) / 2;
-    // g = U^T r0: the sum of the level-1 partials (FP64), kept in LDS after
-    // the factor (and in d.gvec)
+    // g = U^T r0 (summed into d.gvec before the factor was waited for),
+    // kept in LDS after the factor
     double* g = A + tot + r + 1;
-    for (int o = tid; o < 3 * r; o += 1024) {
-        double acc = 0.0;
-#pragma unroll 16
-        for (int sg = 0; sg < nseg; ++sg) acc += g1[(size_t)sg * 3 * r + o];
-        g[o] = acc;
-        d.gvec[o] = acc;
-    }
+    for (int o = tid; o < 3 * r; o += 1024) g[o] = d.gvec[o];
     if (*n_cv == 0) {
         __syncthreads();   // g complete
         // q = A^{-1} g: wavefront w takes rows w, w + 16, ..., lanes the
@@ -3077,17 +3070,14 @@ cloth_status contact_factor(Scene& s, ContactState& c, bool force_k, hipStream_t
     return CLOTH_OK;
 }
 
-// q = A^{-1} g on the factor of contact_factor; g = U^T r0 is the sum of the
-// nseg level-1 partials of the local step's product
-cloth_status contact_solve(Scene& s, ContactState& c, int nseg, hipStream_t st) {
+// q = A^{-1} g on the factor of contact_factor; g = U^T r0 is in d.gvec
+cloth_status contact_solve(Scene& s, ContactState& c, hipStream_t st) {
     Dev& d = s.d;
     const size_t lds = chol_lds_bytes(s.r) + sizeof(double) * 3 * s.r;
     if (s.r <= 128)
-        hipLaunchKernelGGL(k_chol_tri<2>, dim3(1), dim3(1024), lds, st, d, (const double*)c.gpart2, nseg,
-                           (const int*)(c.cnt + 6));
+        hipLaunchKernelGGL(k_chol_tri<2>, dim3(1), dim3(1024), lds, st, d, (const int*)(c.cnt + 6));
     else
-        hipLaunchKernelGGL(k_chol_tri<3>, dim3(1), dim3(1024), lds, st, d, (const double*)c.gpart2, nseg,
-                           (const int*)(c.cnt + 6));
+        hipLaunchKernelGGL(k_chol_tri<3>, dim3(1), dim3(1024), lds, st, d, (const int*)(c.cnt + 6));
     HC(hipGetLastError());
     return CLOTH_OK;
 }

@@ -1026,10 +1026,11 @@ hipError_t launch_reduce_solve(const Dev& d, int nblk, int contact, double* gpar
     const int m = d.r * 3;
     int nseg = (nblk + SEG - 1) / SEG;
     hipLaunchKernelGGL(k_reduce_g1, dim3(nseg), dim3(256), 0, st, d.gate, (const float*)d.gpart, nblk, m, gpart2);
-    // with contact the second level is summed by the solve on the contact factor
-    if (!contact)
-        hipLaunchKernelGGL(k_solve_reduced, dim3(1), dim3(1024), sizeof(double) * m, st, d,
-                           (const double*)gpart2, nseg, 1);
+    // the second level (g in d.gvec), and without contact the solve with the
+    // inverse of Lambda~; with contact the solve on the contact factor
+    // follows once it is ready, and g is summed here, before that wait
+    hipLaunchKernelGGL(k_solve_reduced, dim3(1), dim3(1024), sizeof(double) * m, st, d,
+                       (const double*)gpart2, nseg, contact ? 0 : 1);
     return hipGetLastError();
 }
 
