@@ -591,7 +591,7 @@ static hipError_t scan_exclusive(const int* in, int* out, int n_cap, const int* 
 // to its high corner on every axis: every overlapping target is seen exactly
 // once provided each target is narrower than a cell.  Two grids keep the
 // cells small when a few boxes are much wider than the rest (fast-moving
-// parts): grid 1 has cells of 1.5 x the mean target width per axis and holds
+// parts): grid 1 has cells of 3 x the mean target width per axis and holds
 // the targets narrower than that; grid 2 has cells as wide as the widest
 // target and holds the others (it is used only when such targets exist).
 // Cells are hashed into one bucket table; each bucket holds inline records
@@ -1014,7 +1014,7 @@ __global__ void __launch_bounds__(256) k_grid(const int* __restrict__ gate, cons
         g.use2 = 0;
         for (int c = 0; c < 3; ++c) {
             g.cs2[c] = (double)r[c] * CELL_MARGIN + 1e-30;
-            g.cs1[c] = fmin(g.cs2[c], 1.5 * ((double)r[9 + c] / count) * CELL_MARGIN + 1e-30);
+            g.cs1[c] = fmin(g.cs2[c], 3.0 * ((double)r[9 + c] / count) * CELL_MARGIN + 1e-30);
             double ext = (double)r[6 + c] - (double)r[3 + c];
             if (!isfinite(g.cs2[c]) || !isfinite(g.cs1[c]) || !isfinite(ext)) g.ok = 0;
             // targets wider than a grid-1 cell exist
