@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "contact.hpp"
@@ -2265,8 +2266,10 @@ __device__ __forceinline__ void chol_panel(double* A, double* dinv, int r, int p
 // by one wavefront on the factor in LDS (three wavefronts take the three
 // coordinates side by side).  NS = row slots in use (64 NS >= r): slot q of a
 // lane holds row lane + 64 q; the slot being worked on is a compile-time
-// index (the outer loops over it unroll), and the LDS entries of the next
-// four columns are loaded while the current four are applied.
+// index (the outer loops over it unroll).  The columns go in groups of 16
+// (8 for the last ones when r is not a multiple of 16; r is a multiple of
+// 8, so no group crosses a slot): a group's LDS entries are requested
+// together and their latency is paid once per group, not per column.
 template <int NS>
 __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* dinv, const double* __restrict__ g,
                                          int r, int lane, int c, int zs) {
@@ -2277,38 +2280,33 @@ __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* 
         di[q] = i < r ? dinv[i] : 0.0;
         y[q] = i < r ? g[i * 3 + c] : 0.0;
     }
-    // forward: step k applies column k (y(k) final) to the rows below it
-    double cur[4][NS], nxt[4][NS];
-    auto load_fwd = [&](int k0, double (&buf)[4][NS]) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                // entries outside the strict lower part read the zero at zs:
-                // the address is chosen, not the value, so that the loads
-                // are unconditional and their waits come only at the use
-                const int i = lane + 64 * q, k = k0 + kk;
-                buf[kk][q] = A[(i > k && i < r) ? rm(i, k) : zs];
-            }
-    };
+    // forward: step k applies column k (y(k) final) to the rows below it;
+    // entries outside the strict lower part read the zero at zs (the
+    // address is chosen, not the value, so that the loads are unconditional)
 #pragma unroll
     for (int qk = 0; qk < NS; ++qk) {
         const int kend = min(r, 64 * qk + 64);
-        load_fwd(64 * qk, cur);
-        for (int k0 = 64 * qk; k0 < kend; k0 += 4) {
-            load_fwd(k0 + 4, nxt);
+        auto fwd = [&](auto width, int k0) {
+            constexpr int GS = decltype(width)::value;
+            double cur[GS][NS];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
+            for (int kk = 0; kk < GS; ++kk)
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const int i = lane + 64 * q, k = k0 + kk;
+                    cur[kk][q] = A[(i > k && i < r) ? rm(i, k) : zs];
+                }
+#pragma unroll
+            for (int kk = 0; kk < GS; ++kk) {
                 const int src = (k0 + kk) & 63;
                 const double yk = bcast_f64(y[qk] * di[qk], src);
 #pragma unroll
                 for (int q = qk; q < NS; ++q) y[q] = fma(-cur[kk][q], yk, y[q]);
             }
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                for (int q = 0; q < NS; ++q) cur[kk][q] = nxt[kk][q];
-        }
+        };
+        int k0 = 64 * qk;
+        for (; k0 + 16 <= kend; k0 += 16) fwd(std::integral_constant<int, 16>(), k0);
+        if (k0 < kend) fwd(std::integral_constant<int, 8>(), k0);
     }
     // backward: with z = D^{-1} y, q(i) = z(i) - (1 / A(i, i)) sum_{k > i} A(k, i) q(k);
     // acc holds the sums, and row k's value is final when step k broadcasts it
@@ -2318,33 +2316,31 @@ __device__ __forceinline__ void chol_tri(Dev& d, const double* A, const double* 
         y[q] *= di[q];
         acc[q] = 0.0;
     }
-    auto load_bwd = [&](int k0, double (&buf)[4][NS]) {   // columns k0, k0 - 1, k0 - 2, k0 - 3
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                const int i = lane + 64 * q, k = k0 - kk;
-                buf[kk][q] = A[i < k ? rm(k, i) : zs];
-            }
-    };
 #pragma unroll
     for (int qk = NS - 1; qk >= 0; --qk) {
         const int ktop = min(r, 64 * qk + 64) - 1;   // r is a multiple of 8
-        load_bwd(ktop, cur);
-        for (int k0 = ktop; k0 >= 64 * qk; k0 -= 4) {
-            load_bwd(k0 - 4, nxt);
+        // columns k0, k0 - 1, ..., k0 - GS + 1
+        auto bwd = [&](auto width, int k0) {
+            constexpr int GS = decltype(width)::value;
+            double cur[GS][NS];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
+            for (int kk = 0; kk < GS; ++kk)
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const int i = lane + 64 * q, k = k0 - kk;
+                    cur[kk][q] = A[i < k ? rm(k, i) : zs];
+                }
+#pragma unroll
+            for (int kk = 0; kk < GS; ++kk) {
                 const int src = (k0 - kk) & 63;
                 const double qv = bcast_f64(fma(-di[qk], acc[qk], y[qk]), src);
 #pragma unroll
                 for (int q = 0; q <= qk; ++q) acc[q] = fma(cur[kk][q], qv, acc[q]);
             }
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                for (int q = 0; q < NS; ++q) cur[kk][q] = nxt[kk][q];
-        }
+        };
+        int k0 = ktop;
+        for (; k0 - 15 >= 64 * qk; k0 -= 16) bwd(std::integral_constant<int, 16>(), k0);
+        if (k0 >= 64 * qk) bwd(std::integral_constant<int, 8>(), k0);
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
