@@ -8,7 +8,8 @@
 //                      evaluated in difference form; per-block partial
 //                      products U^T r0 (r x 3)
 //   k_reduce_g1        first level of the deterministic sum of the partials
-//   k_solve_reduced    g = U^T r0 in FP64, q = A^{-1} g (A = Lambda~ + U^T W U)
+//   k_solve_reduced    g = U^T r0 in FP64; without contact also q = Lambda~^{-1} g
+//                      (with contact q = A^{-1} g follows on the contact factor)
 //   k_expand           delta = U q  (x~ = x^k + delta)
 //   k_jacobi_cheb      r1 = r0 - (H + diag W) delta, x^ = x~ + r1 / (diag H + W),
 //                      Chebyshev blend -> x^{k+1}; max |x^{k+1} - x^k| in FP64
